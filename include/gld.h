@@ -1,0 +1,192 @@
+/*
+ * gld.h -- C ABI of the MI355X (gfx950) generalized Langevin dynamics (GLD)
+ * time-step library, libgld.so.
+ *
+ * Method: G. Jung, M. Hanke, F. Schmid, "Generalized Langevin dynamics:
+ * construction and numerical integration of non-Markovian particle-based
+ * models", arXiv:1808.00270.  One call of gld_step advances N identical
+ * particles in a periodic box by the G-JF type integrator of eq.
+ * (GLD_integrator)/(aa-bb), with
+ *   - the conservative pair force F^C (WCA pair potential),
+ *   - the non-Markovian dissipative force F^D' of eq. (dissipative_force2):
+ *     a memory convolution over the last m_max-1 displacement steps with the
+ *     self kernel K^s_m and the pair kernel K^p_m(R_ij) evaluated at the
+ *     current distances,
+ *   - the colored random force F^R whose lag correlations obey the discrete
+ *     fluctuation-dissipation relation eq. (stochastic_force2), i.e. the
+ *     vector sum_s A_s W_{n+s} of eq. (noise_production) with the filter
+ *     matrices A_s the per-frequency square roots of Sec. II.C.
+ *
+ * Memory and streams.  The library never allocates device memory.  The caller
+ * provides one device workspace of at least gld_workspace_size() bytes and a
+ * HIP stream (hipStream_t passed as void*); both must outlive the system.
+ * All device work of a system is enqueued on that stream.
+ *
+ * Host arrays.  All host arrays are row-major, particle-major [n][3] doubles,
+ * owned by the caller, read (or written) only during the call.
+ *
+ * Errors.  Every entry point returns a gld_status.  Errors found on the device
+ * during gld_step (non-positive-definite noise correlation, non-finite state,
+ * neighbour-list overflow, spectrum outside the noise interval) are latched
+ * with their step index and returned by the next synchronising call
+ * (gld_sync, gld_read_state).  After such an error the system is poisoned:
+ * gld_step refuses to run until gld_write_state installs a new state.
+ * gld_last_error() gives a thread-local message for the last failing call.
+ */
+#ifndef GLD_H
+#define GLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GLD_OK = 0,
+    GLD_ERR_INVALID_ARG = -1, /* bad parameter, size or pointer                       */
+    GLD_ERR_NOT_PD = -2,      /* noise correlation matrix not positive definite        */
+    GLD_ERR_NO_CONV = -3,     /* noise approximation did not reach the tolerance       */
+    GLD_ERR_NONFINITE = -4,   /* NaN/Inf in positions or velocities                     */
+    GLD_ERR_OOM = -5,         /* workspace too small                                   */
+    GLD_ERR_DEVICE = -6,      /* HIP runtime error                                      */
+    GLD_ERR_BOX = -7,         /* box too small for the cutoff (r_cut >= L/2)            */
+    GLD_ERR_CAPACITY = -8,    /* more neighbours than max_neighbors                     */
+    GLD_ERR_INTERVAL = -9     /* pair-matrix spectrum left the noise interval           */
+} gld_status;
+
+typedef enum { GLD_FP64 = 0, GLD_FP32_MIXED = 1 } gld_precision;
+
+/* Tensor structure of the pair memory (Sec. II.A): isotropic K^p 1, or only
+ * the component parallel to the line of centres, K^p e e^T. */
+typedef enum { GLD_PAIR_ISOTROPIC = 0, GLD_PAIR_PARALLEL = 1 } gld_pair_tensor;
+
+/* System description.  Discrete kernels K_m are those of eq. (k-discrete);
+ * the pair kernel is separable, K^p_m(r) = w(r) g_m, with w tabulated on the
+ * uniform grid r_b = r0 + b dr (b = 0..n_r-1) and linearly interpolated, as
+ * the paper tabulates its kernels on a distance grid (Sec. III.A); below
+ * r_cut_min the kernel is frozen at its value at r_cut_min (Sec. III.B). */
+typedef struct {
+    int64_t n;                 /* particles, >= 1                                    */
+    double box[3];             /* periodic box edges; each > 2 r_cut                 */
+    double dt;                 /* time step                                          */
+    double mass;               /* particle mass M                                    */
+    double kT;                 /* k_B T (0 switches the random force off)             */
+    int32_t m_max;             /* memory length: lags m = 0..m_max-1, 1..4096        */
+    int32_t n_r;               /* distance grid points, >= 2                         */
+    const double *k_self;      /* [m_max]  K^s_m                                     */
+    const double *k_pair_g;    /* [m_max]  g_m (NULL: no pair memory)                */
+    const double *k_pair_w;    /* [n_r]    w(r_b) (NULL: no pair memory)             */
+    double r0, dr;             /* distance grid                                      */
+    double r_cut;              /* pair cutoff (memory and neighbour list)            */
+    double r_cut_min;          /* kernel frozen below this distance                  */
+    int32_t pair_tensor;       /* gld_pair_tensor                                    */
+    int32_t precision;         /* gld_precision                                      */
+    double wca_sigma;          /* WCA conservative pair force; wca_eps = 0 disables  */
+    double wca_eps;
+    uint64_t seed;             /* Philox4x32-10 key of the white noise W             */
+    double noise_tol;          /* relative rms accuracy of F^R (0: 1e-7 FP32_MIXED,
+                                  1e-13 FP64)                                        */
+    double lam_lo, lam_hi;     /* interval holding the spectrum of the pair-weight
+                                  matrix P = [w(R_ij) T_ij]; both 0: chosen at
+                                  create from the initial configuration              */
+    int32_t max_neighbors;     /* pair-list capacity per particle (0: automatic)     */
+    int32_t check_interval;    /* steps between spectrum (positive-definiteness)
+                                  checks by Lanczos on P (0: 100, < 0: never)        */
+} gld_params;
+
+/* Snapshot of a system.  On read, every non-NULL array is filled; on write,
+ * r and v are required, history is optional (NULL = zero history). */
+typedef struct {
+    double *r;        /* [n][3] positions, unwrapped                               */
+    double *v;        /* [n][3] velocities                                         */
+    double *f_c;      /* [n][3] F^C at the current positions (read only)           */
+    double *f_d;      /* [n][3] F^D' of the last completed step (read only)        */
+    double *f_r;      /* [n][3] F^R of the last completed step (read only)         */
+    double *history;  /* [m_max-1][n][3] displacements dR_{n-m}, m = 1..m_max-1    */
+    int64_t step;     /* time step index n of (r, v)                               */
+    int32_t flags;    /* latched gld_status of the device checks (read only)       */
+    int64_t flag_step;/* step at which the latched error occurred (read only)      */
+} gld_state;
+
+/* Parameters of the colored-noise construction chosen by the library. */
+typedef struct {
+    int32_t cheb_terms;     /* K: Chebyshev terms in the pair-weight matrix           */
+    int32_t rank;           /* r: filters in the white-noise filter bank              */
+    int32_t block;          /* steps of filter output produced per filter launch      */
+    double lam_lo, lam_hi;  /* interval of the expansion                              */
+    double lam_singular;    /* largest lambda where some frequency's K_hat is singular */
+    double err_estimate;    /* estimated relative rms error of F^R                    */
+} gld_noise_info;
+
+typedef struct gld_system gld_system;
+
+/* Device bytes a system with these parameters needs.  Host-only. */
+gld_status gld_workspace_size(const gld_params *params, size_t *bytes);
+
+/* Create a system at step 0 from r0, v0 ([n][3]) with zero history.  Runs the
+ * one-off FP64 construction of the noise filters (Sec. II.C: the Fourier
+ * transforms of the kernels are precomputed under time-scale separation),
+ * uploads the state, builds the neighbour list, computes F^C_0 and checks the
+ * noise correlation for positive definiteness at t = 0 (Sec. II.B).
+ * Synchronises the stream before returning.  *out receives the handle. */
+gld_status gld_create(const gld_params *params, const double *r0, const double *v0,
+                      void *d_workspace, size_t workspace_bytes, void *hip_stream,
+                      gld_system **out);
+
+/* Enqueue n_steps integrator steps on the system's stream; returns without
+ * waiting.  A latched device error from an earlier step is returned here
+ * only if it was already observed by a synchronising call. */
+gld_status gld_step(gld_system *sys, int64_t n_steps);
+
+/* Wait for the stream; return the latched device status. */
+gld_status gld_sync(gld_system *sys);
+
+/* Synchronise and copy the state to the host arrays of *out. */
+gld_status gld_read_state(gld_system *sys, gld_state *out);
+
+/* Install a state (r, v, step, optional history); recomputes the neighbour
+ * list and F^C, clears latched errors.  Synchronises. */
+gld_status gld_write_state(gld_system *sys, const gld_state *in);
+
+/* Noise-construction parameters of a system. */
+gld_status gld_noise_parameters(const gld_system *sys, gld_noise_info *out);
+
+/* Use HIP graph replay for gld_step (default on).  */
+gld_status gld_set_graph(gld_system *sys, int enable);
+
+/* Per-kernel timing.  While enabled, gld_step launches eagerly and records a
+ * HIP event pair around every kernel on the system's stream; gld_kernel_times
+ * synchronises and returns, for each kernel class, the summed duration in ms
+ * and the launch count since timing was enabled. */
+enum {
+    GLD_K_HISTORY = 0,  /* memory convolution over the displacement ring           */
+    GLD_K_DISSIPATIVE,  /* pair contraction of F^D'                                */
+    GLD_K_NOISE_FIR,    /* white-noise filter bank                                 */
+    GLD_K_NOISE_SPMV,   /* Chebyshev pair mat-vec chain of F^R                     */
+    GLD_K_UPDATE,       /* position and velocity updates                           */
+    GLD_K_NEIGHBOR,     /* cell list, pair list and F^C                            */
+    GLD_K_CHECK,        /* Lanczos spectrum check                                  */
+    GLD_K_COUNT
+};
+gld_status gld_set_timing(gld_system *sys, int enable);
+gld_status gld_kernel_times(gld_system *sys, double *ms_sum, int64_t *launches);
+
+/* Release the handle (the workspace stays the caller's). Synchronises. */
+gld_status gld_destroy(gld_system *sys);
+
+/* White noise exactly as the integrator draws it: out[t][i][c] = W_{i,c,t0+t}
+ * for t < n_t, i < n, c < 3, on the device (d_out: n_t*n*3 doubles), and the
+ * raw Philox4x32-10 words out4[t][i][4] (d_raw: n_t*n*4 uint32, may be NULL). */
+gld_status gld_white_noise(uint64_t seed, int64_t n, int64_t t0, int64_t n_t,
+                           double *d_out, uint32_t *d_raw, void *hip_stream);
+
+const char *gld_status_string(int status);
+const char *gld_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLD_H */

@@ -1,0 +1,117 @@
+"""Seeded synthetic GLD workloads: kernel tables, boxes and initial states.
+
+This module holds input generation only (no part of the integrator, the
+memory convolution or the noise construction).  Both the HIP path and the
+CPU oracle receive the arrays it produces.
+
+Kernel shapes (self and separable pair memory) follow the synthetic
+benchmark definitions; the paper's own kernels were reconstructed from
+molecular dynamics data that is not available, so these stand in for them.
+
+* self kernel      K^s(t)   = 10 exp(-t/0.5) cos(4 t)
+* pair kernel      K^p(r,t) = w(r) g(t),  w(r) = (1 - r/r_c)^2,
+                   g(t) = 3 exp(-t/0.3) cos(5 t)
+* discrete tables  K_0 = dt K(0) / 2, K_m = dt K(m dt) (trapezoid weights,
+                   so that kT a_m K_m / dt = kT K(m dt), the FDT target)
+* initial state    simple-cubic lattice (n_side = ceil(N^(1/3)), x fastest,
+                   first N sites) with uniform jitter +-0.1 per coordinate;
+                   Maxwell velocities N(0, kT/M) per component.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+def self_kernel(t):
+    return 10.0 * np.exp(-t / 0.5) * np.cos(4.0 * t)
+
+
+def pair_time_kernel(t):
+    return 3.0 * np.exp(-t / 0.3) * np.cos(5.0 * t)
+
+
+def pair_weight(r, r_cut):
+    r = np.asarray(r, dtype=np.float64)
+    return np.where(r < r_cut, (1.0 - r / r_cut) ** 2, 0.0)
+
+
+def discretize(kernel, dt, m_max):
+    """Trapezoid map of a continuous memory kernel onto the lags m = 0..m_max-1."""
+    t = np.arange(m_max) * dt
+    k = dt * kernel(t)
+    k[0] *= 0.5
+    return k
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    n: int
+    rho: float
+    m_max: int
+    steps: int
+    dt: float = 0.01
+    mass: float = 1.0
+    kT: float = 1.0
+    r_cut: float = 5.0
+    n_r: int = 501
+    wca_sigma: float = 1.0
+    wca_eps: float = 1.0
+    seed: int = 0
+    parallel: bool = False
+
+    @property
+    def box(self) -> float:
+        return (self.n / self.rho) ** (1.0 / 3.0)
+
+    def tables(self):
+        """(k_self[m_max], g[m_max], w[n_r], r0, dr): separable pair kernel."""
+        k_self = discretize(self_kernel, self.dt, self.m_max)
+        g = discretize(pair_time_kernel, self.dt, self.m_max)
+        dr = self.r_cut / (self.n_r - 1)
+        r = np.arange(self.n_r) * dr
+        w = pair_weight(r, self.r_cut)
+        w[-1] = 0.0
+        return k_self, g, w, 0.0, dr
+
+    def k_pair_table(self):
+        """General table K^p_m(r_b) = w_b g_m (outer product), shape [n_r, m_max]."""
+        _, g, w, _, _ = self.tables()
+        return np.outer(w, g)
+
+    def initial_state(self):
+        rng = np.random.default_rng(self.seed)
+        L = self.box
+        ns = int(math.ceil(self.n ** (1.0 / 3.0) - 1e-9))
+        a = L / ns
+        idx = np.arange(self.n)
+        lat = np.stack([idx % ns, (idx // ns) % ns, idx // (ns * ns)], axis=1).astype(np.float64)
+        R = lat * a + rng.uniform(-0.1, 0.1, size=(self.n, 3))
+        V = rng.normal(0.0, math.sqrt(self.kT / self.mass), size=(self.n, 3))
+        return R, V
+
+
+def config(k: int, **over) -> Workload:
+    """The synthetic configurations (1-based, as listed in the benchmark set).
+
+    1: N=64,     rho=0.05, m_max=200,  1000 steps   (parity, statistics)
+    2: N=10^4,   rho=0.05, m_max=500,  10^4 steps   (single GPU, cache resident)
+    3: N=2x10^5, rho=0.5,  m_max=1000, 10^3 steps   (headline, HBM bound)
+    """
+    table = {
+        1: dict(name="cfg1_n64_rho0.05_m200", n=64, rho=0.05, m_max=200, steps=1000),
+        2: dict(name="cfg2_n1e4_rho0.05_m500", n=10_000, rho=0.05, m_max=500, steps=10_000),
+        3: dict(name="cfg3_n2e5_rho0.5_m1000", n=200_000, rho=0.5, m_max=1000, steps=1000),
+    }
+    d = dict(table[k])
+    d["seed"] = 1000 + k
+    d.update(over)
+    return Workload(**d)
+
+
+def random_history(rng, m_max, n, scale=0.01):
+    """A seeded displacement history dR_{n-m}, m = 1..m_max-1, shape [m_max-1, n, 3]."""
+    return rng.normal(0.0, scale, size=(max(m_max - 1, 0), n, 3))
