@@ -86,7 +86,7 @@ typedef struct {
     double wca_sigma;          /* WCA conservative pair force; wca_eps = 0 disables  */
     double wca_eps;
     uint64_t seed;             /* Philox4x32-10 key of the white noise W             */
-    double noise_tol;          /* relative rms accuracy of F^R (0: 1e-7 FP32_MIXED,
+    double noise_tol;          /* relative rms accuracy of F^R (0: 1e-6 FP32_MIXED,
                                   1e-13 FP64)                                        */
     double lam_lo, lam_hi;     /* interval holding the spectrum of the pair-weight
                                   matrix P = [w(R_ij) T_ij]; both 0: chosen at
@@ -181,6 +181,19 @@ gld_status gld_destroy(gld_system *sys);
  * raw Philox4x32-10 words out4[t][i][4] (d_raw: n_t*n*4 uint32, may be NULL). */
 gld_status gld_white_noise(uint64_t seed, int64_t n, int64_t t0, int64_t n_t,
                            double *d_out, uint32_t *d_raw, void *hip_stream);
+
+/* Host only.  The one-off FP64 noise-filter construction (Sec. II.C, with the
+ * Fourier transforms of the kernels precomputed) for the interval
+ * [lam_lo, lam_hi] of the pair-weight matrix spectrum and relative rms
+ * tolerance tol (0: the precision's default).  On success, *info holds K and
+ * r, a_out[r][2 m_max - 1] the filter taps for lags -(m_max-1)..m_max-1 and
+ * b_out[K][r] the Chebyshev mixing weights, so that
+ *   F^R_n = sum_{k<K} T_k(alpha P + beta 1) sum_q b[k][q] sum_t a[q][t] W_{n+t},
+ * alpha = 2/(hi-lo), beta = -(hi+lo)/(hi-lo).  Capacities: a_cap >= r (2 m_max - 1)
+ * and b_cap >= K r doubles; too small -> GLD_ERR_INVALID_ARG. */
+gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, double lam_hi, double tol,
+                                   double *a_out, size_t a_cap, double *b_out, size_t b_cap,
+                                   gld_noise_info *info);
 
 const char *gld_status_string(int status);
 const char *gld_last_error(void);

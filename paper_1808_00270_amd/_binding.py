@@ -1,0 +1,128 @@
+"""ctypes declarations of the libgld C ABI (include/gld.h), same names.
+
+Argument marshalling only: every step of the integrator runs in the HIP
+kernels of libgld.so.  Importing this module fails loudly when the library
+has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgld.so")
+
+GLD_OK = 0
+GLD_ERR_INVALID_ARG = -1
+GLD_ERR_NOT_PD = -2
+GLD_ERR_NO_CONV = -3
+GLD_ERR_NONFINITE = -4
+GLD_ERR_OOM = -5
+GLD_ERR_DEVICE = -6
+GLD_ERR_BOX = -7
+GLD_ERR_CAPACITY = -8
+GLD_ERR_INTERVAL = -9
+
+GLD_FP64 = 0
+GLD_FP32_MIXED = 1
+GLD_PAIR_ISOTROPIC = 0
+GLD_PAIR_PARALLEL = 1
+
+(GLD_K_HISTORY, GLD_K_DISSIPATIVE, GLD_K_NOISE_FIR, GLD_K_NOISE_SPMV, GLD_K_UPDATE, GLD_K_NEIGHBOR,
+ GLD_K_CHECK, GLD_K_COUNT) = range(8)
+KERNEL_NAMES = ["history", "dissipative", "noise_fir", "noise_spmv", "update", "neighbor", "check"]
+
+_dp = C.POINTER(C.c_double)
+
+
+class gld_params(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("box", C.c_double * 3),
+        ("dt", C.c_double),
+        ("mass", C.c_double),
+        ("kT", C.c_double),
+        ("m_max", C.c_int32),
+        ("n_r", C.c_int32),
+        ("k_self", _dp),
+        ("k_pair_g", _dp),
+        ("k_pair_w", _dp),
+        ("r0", C.c_double),
+        ("dr", C.c_double),
+        ("r_cut", C.c_double),
+        ("r_cut_min", C.c_double),
+        ("pair_tensor", C.c_int32),
+        ("precision", C.c_int32),
+        ("wca_sigma", C.c_double),
+        ("wca_eps", C.c_double),
+        ("seed", C.c_uint64),
+        ("noise_tol", C.c_double),
+        ("lam_lo", C.c_double),
+        ("lam_hi", C.c_double),
+        ("max_neighbors", C.c_int32),
+        ("check_interval", C.c_int32),
+    ]
+
+
+class gld_state(C.Structure):
+    _fields_ = [
+        ("r", _dp),
+        ("v", _dp),
+        ("f_c", _dp),
+        ("f_d", _dp),
+        ("f_r", _dp),
+        ("history", _dp),
+        ("step", C.c_int64),
+        ("flags", C.c_int32),
+        ("flag_step", C.c_int64),
+    ]
+
+
+class gld_noise_info(C.Structure):
+    _fields_ = [
+        ("cheb_terms", C.c_int32),
+        ("rank", C.c_int32),
+        ("block", C.c_int32),
+        ("lam_lo", C.c_double),
+        ("lam_hi", C.c_double),
+        ("lam_singular", C.c_double),
+        ("err_estimate", C.c_double),
+    ]
+
+
+EXPORTED = [
+    "gld_workspace_size", "gld_create", "gld_step", "gld_sync", "gld_read_state", "gld_write_state",
+    "gld_noise_parameters", "gld_set_graph", "gld_set_timing", "gld_kernel_times", "gld_destroy",
+    "gld_white_noise", "gld_build_noise_filters", "gld_status_string", "gld_last_error",
+]
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libgld.so not built at {path}; run __graft_entry__.build() "
+                          "(there is no fallback implementation)")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    P = C.POINTER(gld_params)
+    S = C.POINTER(gld_state)
+    lib.gld_workspace_size.argtypes = [P, C.POINTER(C.c_size_t)]
+    lib.gld_create.argtypes = [P, _dp, _dp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.gld_step.argtypes = [vp, C.c_int64]
+    lib.gld_sync.argtypes = [vp]
+    lib.gld_read_state.argtypes = [vp, S]
+    lib.gld_write_state.argtypes = [vp, S]
+    lib.gld_noise_parameters.argtypes = [vp, C.POINTER(gld_noise_info)]
+    lib.gld_set_graph.argtypes = [vp, C.c_int]
+    lib.gld_set_timing.argtypes = [vp, C.c_int]
+    lib.gld_kernel_times.argtypes = [vp, _dp, C.POINTER(C.c_int64)]
+    lib.gld_destroy.argtypes = [vp]
+    lib.gld_white_noise.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, vp, vp, vp]
+    lib.gld_build_noise_filters.argtypes = [P, C.c_double, C.c_double, C.c_double, _dp, C.c_size_t, _dp,
+                                            C.c_size_t, C.POINTER(gld_noise_info)]
+    lib.gld_status_string.restype = C.c_char_p
+    lib.gld_status_string.argtypes = [C.c_int]
+    lib.gld_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("gld_status_string", "gld_last_error"):
+            getattr(lib, name).restype = C.c_int
+    return lib

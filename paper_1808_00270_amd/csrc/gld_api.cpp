@@ -1,0 +1,797 @@
+// C ABI of libgld (see include/gld.h): validation, workspace layout, the
+// one-off setup, the per-step launch sequence (replayed as a HIP graph) and
+// state transfer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "gld.h"
+#include "gld_internal.h"
+
+using gld::Dev;
+using gld::NoisePlan;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gld_status fail(gld_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(GLD_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+struct Layout {
+    size_t off = 0;
+    char *base = nullptr;
+    template <typename P>
+    void take(P *&ptr, size_t bytes)
+    {
+        off = (off + 255) & ~static_cast<size_t>(255);
+        ptr = base ? reinterpret_cast<P *>(base + off) : nullptr;
+        off += bytes;
+    }
+};
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+bool finite_all(const double *p, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+gld_status validate(const gld_params *p)
+{
+    if (!p) return fail(GLD_ERR_INVALID_ARG, "params is NULL");
+    if (p->n < 1 || p->n > (int64_t(1) << 30)) return fail(GLD_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+    if (p->m_max < 1 || p->m_max > 4096) return fail(GLD_ERR_INVALID_ARG, "m_max must be in [1, 4096]");
+    if (p->n_r < 2) return fail(GLD_ERR_INVALID_ARG, "n_r must be >= 2");
+    if (!(p->dt > 0) || !(p->mass > 0) || !(p->kT >= 0) || !std::isfinite(p->kT))
+        return fail(GLD_ERR_INVALID_ARG, "dt, mass must be > 0 and kT >= 0");
+    if (!p->k_self || !finite_all(p->k_self, p->m_max)) return fail(GLD_ERR_INVALID_ARG, "k_self missing or not finite");
+    if ((p->k_pair_g == nullptr) != (p->k_pair_w == nullptr))
+        return fail(GLD_ERR_INVALID_ARG, "k_pair_g and k_pair_w must both be given or both NULL");
+    if (p->k_pair_g && (!finite_all(p->k_pair_g, p->m_max) || !finite_all(p->k_pair_w, p->n_r)))
+        return fail(GLD_ERR_INVALID_ARG, "pair kernel tables not finite");
+    if (!(p->dr > 0) || !std::isfinite(p->r0)) return fail(GLD_ERR_INVALID_ARG, "dr must be > 0");
+    if (!(p->r_cut > 0)) return fail(GLD_ERR_INVALID_ARG, "r_cut must be > 0");
+    for (int c = 0; c < 3; ++c) {
+        if (!(p->box[c] > 0) || !std::isfinite(p->box[c])) return fail(GLD_ERR_INVALID_ARG, "box edges must be > 0");
+        if (!(p->r_cut < 0.5 * p->box[c]))
+            return fail(GLD_ERR_BOX, "r_cut must be smaller than half of every box edge (minimum image)");
+    }
+    if (p->pair_tensor != GLD_PAIR_ISOTROPIC && p->pair_tensor != GLD_PAIR_PARALLEL)
+        return fail(GLD_ERR_INVALID_ARG, "unknown pair_tensor");
+    if (p->precision != GLD_FP64 && p->precision != GLD_FP32_MIXED)
+        return fail(GLD_ERR_INVALID_ARG, "unknown precision");
+    if (p->wca_eps != 0.0 && !(std::pow(2.0, 1.0 / 6.0) * p->wca_sigma <= p->r_cut))
+        return fail(GLD_ERR_INVALID_ARG, "the WCA range 2^(1/6) sigma must not exceed r_cut");
+    if (p->noise_tol < 0 || p->noise_tol >= 1) return fail(GLD_ERR_INVALID_ARG, "noise_tol must be in [0, 1)");
+    if (p->max_neighbors < 0) return fail(GLD_ERR_INVALID_ARG, "max_neighbors must be >= 0");
+    return GLD_OK;
+}
+
+struct Geometry {
+    int64_t S = 0;
+    int cap = 0;
+    int nc[3] = {1, 1, 1};
+    int ncell = 1;
+    bool fp64 = false, parallel = false;
+    int firw = 64;
+};
+
+Geometry geometry(const gld_params *p)
+{
+    Geometry g;
+    g.S = round_up(p->n, 64);
+    g.fp64 = p->precision == GLD_FP64;
+    g.parallel = p->pair_tensor == GLD_PAIR_PARALLEL;
+    g.firw = g.fp64 ? 32 : 64;
+    const double vol = p->box[0] * p->box[1] * p->box[2];
+    if (p->max_neighbors > 0) {
+        g.cap = p->max_neighbors;
+    } else {
+        const double expect = static_cast<double>(p->n) / vol * (4.0 / 3.0) * M_PI * p->r_cut * p->r_cut * p->r_cut;
+        g.cap = static_cast<int>(round_up(static_cast<int64_t>(1.5 * expect + 32), 32));
+    }
+    g.cap = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g.cap, p->n - 1)));
+    int64_t cells = 1;
+    for (int c = 0; c < 3; ++c) {
+        g.nc[c] = std::max(1, static_cast<int>(std::floor(p->box[c] / p->r_cut)));
+        cells *= g.nc[c];
+    }
+    // keep the cell count proportional to n (larger cells are always valid)
+    const int64_t limit = std::max<int64_t>(4096, 8 * p->n);
+    while (cells > limit) {
+        cells = 1;
+        for (int c = 0; c < 3; ++c) {
+            g.nc[c] = std::max(1, g.nc[c] * 4 / 5);
+            cells *= g.nc[c];
+        }
+    }
+    g.ncell = static_cast<int>(cells);
+    return g;
+}
+
+// Carve the workspace.  With base == nullptr only the size is computed.
+size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
+{
+    Layout L;
+    L.base = base;
+    const size_t elt = g.fp64 ? 8 : 4;
+    const int64_t S = g.S, n = p->n, vec = 3 * S;
+    const int nslots = std::max(0, p->m_max - 1);
+    const int P = 2 * p->m_max - 1;
+    L.take(d.R, vec * 8);
+    L.take(d.V, vec * 8);
+    L.take(d.FC, vec * 8);
+    L.take(d.FCn, vec * 8);
+    L.take(d.Rw, vec * 8);
+    L.take(d.ring, static_cast<size_t>(nslots) * vec * elt);
+    L.take(d.Dneg, vec * elt);
+    L.take(d.Y, vec * elt);
+    L.take(d.FD, vec * elt);
+    L.take(d.FR, vec * elt);
+    for (auto &b : d.cb) L.take(b, vec * elt);
+    for (auto &b : d.lq) L.take(b, vec * elt);
+    L.take(d.lw, vec * elt);
+    L.take(d.U, static_cast<size_t>(g.firw) * vec * elt);
+    L.take(d.Afilt, static_cast<size_t>(gld::kMaxRank) * P * elt);
+    L.take(d.Bmix, static_cast<size_t>(gld::kMaxCheb) * gld::kMaxRank * elt);
+    L.take(d.ks, static_cast<size_t>(p->m_max) * elt);
+    L.take(d.gm, static_cast<size_t>(p->m_max) * elt);
+    L.take(d.wtab, static_cast<size_t>(p->n_r) * 8);
+    L.take(d.nbr, static_cast<size_t>(g.cap) * n * 4);
+    L.take(d.nbr_w, static_cast<size_t>(g.cap) * n * elt);
+    if (g.parallel) L.take(d.nbr_e, 3 * static_cast<size_t>(g.cap) * n * elt);
+    L.take(d.nnbr, n * 4);
+    L.take(d.cell_id, n * 4);
+    L.take(d.cell_slot, n * 4);
+    L.take(d.cell_tmp, n * 4);
+    L.take(d.cell_sorted, n * 4);
+    L.take(d.cell_count, static_cast<size_t>(g.ncell) * 4);
+    L.take(d.cell_start, static_cast<size_t>(g.ncell + 1) * 4);
+    L.take(d.partial, gld::kPartials * 8);
+    L.take(d.lab, (2 * gld::kCheckIters + 4) * 8);
+    L.take(d.d_step, 8);
+    L.take(d.d_flags, 8);
+    L.take(d.d_flag_step, 8);
+    L.take(d.d_rowmax, 8);
+    return L.off + 256;
+}
+
+}  // namespace
+
+struct gld_system {
+    gld_params p{};
+    std::vector<double> k_self, g, w;
+    Geometry geo;
+    Dev d;
+    NoisePlan plan;
+    hipStream_t st = nullptr;
+    int64_t step = 0;
+    int noise_on = 0;
+    int check_interval = 100;
+    bool graph_on = true;
+    bool graph_ready = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    std::vector<std::pair<int, size_t>> pending;  // (class, index of start event)
+    double ms[GLD_K_COUNT] = {0};
+    int64_t cnt[GLD_K_COUNT] = {0};
+    double theta[2] = {0, 0};
+    gld_status latched = GLD_OK;
+};
+
+namespace {
+
+// host [n][3] doubles -> device [3][S] of type T (staging through a host buffer)
+template <typename T>
+gld_status upload_vec(gld_system *s, void *dst, const double *src)
+{
+    const int64_t n = s->p.n, S = s->geo.S;
+    std::vector<T> h(3 * S, T(0));
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) h[c * S + i] = static_cast<T>(src[3 * i + c]);
+    HIP_TRY(hipMemcpyAsync(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    return GLD_OK;
+}
+
+template <typename T>
+gld_status download_vec(gld_system *s, double *dst, const void *src)
+{
+    const int64_t n = s->p.n, S = s->geo.S;
+    std::vector<T> h(3 * S);
+    HIP_TRY(hipMemcpyAsync(h.data(), src, h.size() * sizeof(T), hipMemcpyDeviceToHost, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) dst[3 * i + c] = static_cast<double>(h[c * S + i]);
+    return GLD_OK;
+}
+
+gld_status upload_work_vec(gld_system *s, void *dst, const double *src)
+{
+    return s->geo.fp64 ? upload_vec<double>(s, dst, src) : upload_vec<float>(s, dst, src);
+}
+
+gld_status download_work_vec(gld_system *s, double *dst, const void *src)
+{
+    return s->geo.fp64 ? download_vec<double>(s, dst, src) : download_vec<float>(s, dst, src);
+}
+
+template <typename T>
+gld_status upload_table(gld_system *s, void *dst, const double *src, size_t n)
+{
+    std::vector<T> h(src, src + n);
+    HIP_TRY(hipMemcpyAsync(dst, h.data(), n * sizeof(T), hipMemcpyHostToDevice, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    return GLD_OK;
+}
+
+gld_status upload_work_table(gld_system *s, void *dst, const double *src, size_t n)
+{
+    return s->geo.fp64 ? upload_table<double>(s, dst, src, n) : upload_table<float>(s, dst, src, n);
+}
+
+gld_status read_flags(gld_system *s)
+{
+    int flags[2] = {0, 0};
+    long long fstep = 0;
+    HIP_TRY(hipStreamSynchronize(s->st));
+    HIP_TRY(hipMemcpy(flags, s->d.d_flags, sizeof(flags), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&fstep, s->d.d_flag_step, sizeof(fstep), hipMemcpyDeviceToHost));
+    if (flags[0] != 0 && s->latched == GLD_OK) {
+        s->latched = static_cast<gld_status>(flags[0]);
+        g_last_error = std::string("device check failed at step ") + std::to_string(fstep) + ": " +
+                       gld_status_string(flags[0]);
+    }
+    return s->latched;
+}
+
+// -- timing helpers ----------------------------------------------------------
+gld_status ev_begin(gld_system *s, size_t &idx)
+{
+    if (!s->timing) return GLD_OK;
+    while (s->pool.size() < s->pool_used + 2) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        s->pool.push_back(e);
+    }
+    idx = s->pool_used;
+    s->pool_used += 2;
+    HIP_TRY(hipEventRecord(s->pool[idx], s->st));
+    return GLD_OK;
+}
+
+gld_status ev_end(gld_system *s, int cls, size_t idx)
+{
+    if (!s->timing) return GLD_OK;
+    HIP_TRY(hipEventRecord(s->pool[idx + 1], s->st));
+    s->pending.emplace_back(cls, idx);
+    return GLD_OK;
+}
+
+#define LAUNCH(cls, expr)                                  \
+    do {                                                   \
+        size_t ix_ = 0;                                    \
+        gld_status s_ = ev_begin(s, ix_);                  \
+        if (s_ != GLD_OK) return s_;                       \
+        HIP_TRY(expr);                                     \
+        if ((s_ = ev_end(s, cls, ix_)) != GLD_OK) return s_; \
+    } while (0)
+
+// One integrator step, eq. (GLD_integrator).  Every launch reads the step
+// index from device memory, so the same sequence is replayed for any step.
+gld_status enqueue_step(gld_system *s)
+{
+    const Dev &d = s->d;
+    hipStream_t st = s->st;
+    LAUNCH(GLD_K_HISTORY, gld::launch_history(d, st));
+    LAUNCH(GLD_K_DISSIPATIVE, gld::launch_dissipative(d, st));
+    if (s->noise_on) {
+        const NoisePlan &pl = s->plan;
+        const size_t elt = s->geo.fp64 ? 8 : 4;
+        const int rc = d.fir_rcap;
+        auto coef = [&](int k) {
+            return static_cast<const void *>(static_cast<const char *>(d.Bmix) + static_cast<size_t>(k) * rc * elt);
+        };
+        LAUNCH(GLD_K_NOISE_FIR, gld::launch_fir(d, 0, st));
+        // Clenshaw: b_k = v_k + 2 P~ b_{k+1} - b_{k+2};  F = v_0 + P~ b_1 - b_2
+        void *prev1 = nullptr, *prev2 = nullptr;
+        for (int k = pl.K - 1; k >= 1; --k) {
+            void *out = nullptr;
+            for (void *c : d.cb)
+                if (c != prev1 && c != prev2) { out = c; break; }
+            if (!prev1) {
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r, out));
+            } else {
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, prev1,
+                                                          prev2 ? -1.0 : 0.0, prev2, coef(k), pl.r, out));
+            }
+            prev2 = prev1;
+            prev1 = out;
+        }
+        if (prev1) {
+            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0, prev2,
+                                                      coef(0), pl.r, d.FR));
+        } else {
+            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r, d.FR));
+        }
+    }
+    LAUNCH(GLD_K_UPDATE, gld::launch_update_r(d, st));
+    LAUNCH(GLD_K_NEIGHBOR, gld::launch_neighbors(d, st, d.FCn));
+    LAUNCH(GLD_K_UPDATE, gld::launch_update_v(d, st));
+    HIP_TRY(gld::launch_step_advance(d, st));
+    return GLD_OK;
+}
+
+gld_status enqueue_check(gld_system *s)
+{
+    const NoisePlan &pl = s->plan;
+    LAUNCH(GLD_K_CHECK, gld::launch_spectrum_check(s->d, s->st, gld::kCheckIters, pl.lo, pl.hi, pl.sing_lo,
+                                                     pl.sing_hi, s->step + 0x5eed));
+    return GLD_OK;
+}
+
+void drop_graph(gld_system *s)
+{
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+    s->graph_ready = false;
+}
+
+gld_status build_graph(gld_system *s)
+{
+    drop_graph(s);
+    HIP_TRY(hipStreamBeginCapture(s->st, hipStreamCaptureModeRelaxed));
+    gld_status st = enqueue_step(s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->st, &g);
+    if (st != GLD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(GLD_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    s->graph = g;
+    HIP_TRY(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+    s->graph_ready = true;
+    return GLD_OK;
+}
+
+gld_status set_step(gld_system *s, int64_t step)
+{
+    long long v = step;
+    HIP_TRY(hipMemcpyAsync(s->d.d_step, &v, sizeof(v), hipMemcpyHostToDevice, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    s->step = step;
+    return GLD_OK;
+}
+
+gld_status clear_flags(gld_system *s)
+{
+    HIP_TRY(hipMemsetAsync(s->d.d_flags, 0, 8, s->st));
+    HIP_TRY(hipMemsetAsync(s->d.d_flag_step, 0, 8, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    s->latched = GLD_OK;
+    return GLD_OK;
+}
+
+gld_status run_check_now(gld_system *s, double lo, double hi, double slo, double shi, double theta[2],
+                         float *rowmax)
+{
+    HIP_TRY(gld::launch_spectrum_check(s->d, s->st, gld::kCheckIters, lo, hi, slo, shi, s->step + 0x5eed));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    double res[2];
+    HIP_TRY(hipMemcpy(res, s->d.lab + 2 * gld::kCheckIters, sizeof(res), hipMemcpyDeviceToHost));
+    theta[0] = res[0];
+    theta[1] = res[1];
+    if (rowmax) {
+        unsigned bits = 0;
+        HIP_TRY(hipMemcpy(&bits, s->d.d_rowmax, sizeof(bits), hipMemcpyDeviceToHost));
+        std::memcpy(rowmax, &bits, sizeof(float));
+    }
+    return GLD_OK;
+}
+
+gld_status setup_noise(gld_system *s)
+{
+    const gld_params &p = s->p;
+    Dev &d = s->d;
+    s->noise_on = p.kT > 0;
+    if (!s->noise_on) return GLD_OK;
+    std::string err;
+    gld_status st = gld::noise_spectra(p, s->plan, err);
+    if (st != GLD_OK) return fail(st, err);
+    const double tol = p.noise_tol > 0 ? p.noise_tol : (s->geo.fp64 ? 1e-13 : 1e-6);
+    double lo = p.lam_lo, hi = p.lam_hi;
+    const bool has_pair = d.has_pair;
+    if (!(hi > lo)) {
+        if (!has_pair) {
+            lo = -1.0;
+            hi = 1.0;
+        } else {
+            double th[2];
+            float gmax = 0;
+            const double inf = std::numeric_limits<double>::infinity();
+            if ((st = run_check_now(s, -inf, inf, -inf, inf, th, &gmax)) != GLD_OK) return st;
+            if (!(th[0] > s->plan.sing_lo) || !(th[1] < s->plan.sing_hi))
+                return fail(GLD_ERR_NOT_PD, "initial configuration: pair-matrix spectrum [" + std::to_string(th[0]) +
+                                                ", " + std::to_string(th[1]) + "] reaches a singular point of the "
+                                                "noise correlation (" + std::to_string(s->plan.sing_lo) + ", " +
+                                                std::to_string(s->plan.sing_hi) + "): not positive definite");
+            const double span = std::max(1.0, th[1] - th[0]);
+            lo = std::isfinite(s->plan.sing_lo) ? th[0] - 0.5 * (th[0] - s->plan.sing_lo) : th[0] - 0.5 * span;
+            hi = 1.2 * std::max(static_cast<double>(gmax), th[1]) + 0.1;
+            if (std::isfinite(s->plan.sing_hi)) hi = std::min(hi, th[1] + 0.5 * (s->plan.sing_hi - th[1]));
+        }
+    }
+    st = gld::noise_build(p, lo, hi, tol, s->plan, err);
+    if (st != GLD_OK) return fail(st, err);
+    const NoisePlan &pl = s->plan;
+    const int width = s->geo.firw;
+    d.fir_rcap = pl.r <= 8 ? 8 : (pl.r <= 16 ? 16 : 32);
+    d.fir_block = width / d.fir_rcap;
+    // padded filter taps [rcap][P] and mixing weights [K][rcap]
+    std::vector<double> A(static_cast<size_t>(d.fir_rcap) * pl.P, 0.0), B(static_cast<size_t>(pl.K) * d.fir_rcap, 0.0);
+    for (int q = 0; q < pl.r; ++q)
+        for (int t = 0; t < pl.P; ++t) A[static_cast<size_t>(q) * pl.P + t] = pl.Afilt[static_cast<size_t>(q) * pl.P + t];
+    for (int k = 0; k < pl.K; ++k)
+        for (int q = 0; q < pl.r; ++q) B[static_cast<size_t>(k) * d.fir_rcap + q] = pl.Bmix[static_cast<size_t>(k) * pl.r + q];
+    if ((st = upload_work_table(s, d.Afilt, A.data(), A.size())) != GLD_OK) return st;
+    if ((st = upload_work_table(s, d.Bmix, B.data(), B.size())) != GLD_OK) return st;
+    return GLD_OK;
+}
+
+gld_status refresh_forces(gld_system *s)
+{
+    HIP_TRY(gld::launch_neighbors(s->d, s->st, s->d.FC));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    return GLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gld_status_string(int status)
+{
+    switch (status) {
+    case GLD_OK: return "ok";
+    case GLD_ERR_INVALID_ARG: return "invalid argument";
+    case GLD_ERR_NOT_PD: return "noise correlation not positive definite";
+    case GLD_ERR_NO_CONV: return "noise approximation did not converge";
+    case GLD_ERR_NONFINITE: return "non-finite state";
+    case GLD_ERR_OOM: return "workspace too small";
+    case GLD_ERR_DEVICE: return "HIP runtime error";
+    case GLD_ERR_BOX: return "box too small for the cutoff";
+    case GLD_ERR_CAPACITY: return "neighbour list capacity exceeded";
+    case GLD_ERR_INTERVAL: return "pair-matrix spectrum outside the noise interval";
+    default: return "unknown status";
+    }
+}
+
+const char *gld_last_error(void) { return g_last_error.c_str(); }
+
+gld_status gld_workspace_size(const gld_params *params, size_t *bytes)
+{
+    gld_status st = validate(params);
+    if (st != GLD_OK) return st;
+    if (!bytes) return fail(GLD_ERR_INVALID_ARG, "bytes is NULL");
+    Dev d;
+    *bytes = carve(params, geometry(params), nullptr, d);
+    return GLD_OK;
+}
+
+gld_status gld_create(const gld_params *params, const double *r0, const double *v0, void *d_workspace,
+                      size_t workspace_bytes, void *hip_stream, gld_system **out)
+{
+    gld_status st = validate(params);
+    if (st != GLD_OK) return st;
+    if (!r0 || !v0 || !out || !d_workspace) return fail(GLD_ERR_INVALID_ARG, "NULL pointer argument");
+    if (!finite_all(r0, 3 * params->n) || !finite_all(v0, 3 * params->n))
+        return fail(GLD_ERR_NONFINITE, "initial state not finite");
+    *out = nullptr;
+    gld_system *s = new gld_system();
+    s->p = *params;
+    s->k_self.assign(params->k_self, params->k_self + params->m_max);
+    if (params->k_pair_g) {
+        s->g.assign(params->k_pair_g, params->k_pair_g + params->m_max);
+        s->w.assign(params->k_pair_w, params->k_pair_w + params->n_r);
+    }
+    s->p.k_self = s->k_self.data();
+    s->p.k_pair_g = params->k_pair_g ? s->g.data() : nullptr;
+    s->p.k_pair_w = params->k_pair_w ? s->w.data() : nullptr;
+    s->geo = geometry(&s->p);
+    s->st = static_cast<hipStream_t>(hip_stream);
+    s->check_interval = params->check_interval == 0 ? 100 : params->check_interval;
+    s->graph_on = s->st != nullptr;  // the legacy null stream cannot be captured
+    Dev &d = s->d;
+    const size_t need = carve(&s->p, s->geo, static_cast<char *>(d_workspace), d);
+    if (workspace_bytes < need) {
+        delete s;
+        return fail(GLD_ERR_OOM, "workspace has " + std::to_string(workspace_bytes) + " bytes, needs " + std::to_string(need));
+    }
+    if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) {
+        // re-carve from the next 256-byte boundary (the size includes that slack)
+        char *b = static_cast<char *>(d_workspace);
+        b += 256 - (reinterpret_cast<uintptr_t>(b) & 255);
+        carve(&s->p, s->geo, b, d);
+    }
+    const gld_params &p = s->p;
+    d.n = p.n;
+    d.S = s->geo.S;
+    d.nslots = std::max(0, p.m_max - 1);
+    d.M = p.m_max;
+    d.P = 2 * p.m_max - 1;
+    for (int c = 0; c < 3; ++c) d.box[c] = p.box[c];
+    d.dt = p.dt;
+    d.mass = p.mass;
+    d.kT = p.kT;
+    const double x = p.dt * p.k_self[0] / (2.0 * p.mass);  // eq. (aa-bb), isotropic K^s_0
+    d.b = 1.0 / (1.0 + x);
+    d.a = d.b * (1.0 - x);
+    d.r_cut = p.r_cut;
+    d.r_cut_min = p.r_cut_min;
+    d.r0 = p.r0;
+    d.dr = p.dr;
+    d.n_r = p.n_r;
+    d.parallel = s->geo.parallel;
+    d.fp64 = s->geo.fp64;
+    d.has_pair = p.k_pair_g != nullptr;
+    d.wca_sigma = p.wca_sigma;
+    d.wca_eps = p.wca_eps;
+    d.seed = p.seed;
+    d.cap = s->geo.cap;
+    d.ncell = s->geo.ncell;
+    for (int c = 0; c < 3; ++c) {
+        d.nc[c] = s->geo.nc[c];
+        if (d.nc[c] == 1) { d.noff[c] = 1; d.offs[c][0] = 0; }
+        else if (d.nc[c] == 2) { d.noff[c] = 2; d.offs[c][0] = 0; d.offs[c][1] = 1; }
+        else { d.noff[c] = 3; d.offs[c][0] = -1; d.offs[c][1] = 0; d.offs[c][2] = 1; }
+    }
+    d.g0 = d.has_pair ? p.k_pair_g[0] : 0.0;
+
+    auto bail = [&](gld_status e) {
+        if (s->st) (void)hipStreamSynchronize(s->st);
+        delete s;
+        return e;
+    };
+    if (hipMemsetAsync(d_workspace, 0, need, s->st) != hipSuccess) return bail(fail(GLD_ERR_DEVICE, "workspace clear failed"));
+    std::vector<double> zero_w(p.n_r, 0.0);
+    std::vector<double> zero_g(p.m_max, 0.0);
+    if (hipMemcpyAsync(d.wtab, d.has_pair ? p.k_pair_w : zero_w.data(), p.n_r * sizeof(double), hipMemcpyHostToDevice,
+                       s->st) != hipSuccess)
+        return bail(fail(GLD_ERR_DEVICE, "upload failed"));
+    if ((st = upload_work_table(s, d.ks, p.k_self, p.m_max)) != GLD_OK) return bail(st);
+    if ((st = upload_work_table(s, d.gm, d.has_pair ? p.k_pair_g : zero_g.data(), p.m_max)) != GLD_OK) return bail(st);
+    if ((st = upload_vec<double>(s, d.R, r0)) != GLD_OK) return bail(st);
+    if ((st = upload_vec<double>(s, d.V, v0)) != GLD_OK) return bail(st);
+    if ((st = set_step(s, 0)) != GLD_OK) return bail(st);
+    if ((st = refresh_forces(s)) != GLD_OK) return bail(st);
+    if ((st = read_flags(s)) != GLD_OK) return bail(st);
+    if ((st = setup_noise(s)) != GLD_OK) return bail(st);
+    if (s->noise_on && d.has_pair) {
+        // positive definiteness at t = 0 on the chosen interval (Sec. II.B)
+        float gm = 0;
+        if ((st = run_check_now(s, s->plan.lo, s->plan.hi, s->plan.sing_lo, s->plan.sing_hi, s->theta, &gm)) != GLD_OK)
+            return bail(st);
+        if ((st = read_flags(s)) != GLD_OK) return bail(st);
+    }
+    *out = s;
+    return GLD_OK;
+}
+
+gld_status gld_step(gld_system *s, int64_t n_steps)
+{
+    if (!s || n_steps < 0) return fail(GLD_ERR_INVALID_ARG, "bad system or step count");
+    if (s->latched != GLD_OK) return fail(s->latched, std::string("system is poisoned: ") + gld_status_string(s->latched));
+    gld_status st;
+    const bool use_graph = s->graph_on && !s->timing;
+    if (use_graph && !s->graph_ready && (st = build_graph(s)) != GLD_OK) return st;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        if (s->noise_on && s->d.has_pair && s->check_interval > 0 && s->step > 0 && s->step % s->check_interval == 0)
+            if ((st = enqueue_check(s)) != GLD_OK) return st;
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(s->gexec, s->st));
+        } else if ((st = enqueue_step(s)) != GLD_OK) {
+            return st;
+        }
+        ++s->step;
+    }
+    return GLD_OK;
+}
+
+gld_status gld_sync(gld_system *s)
+{
+    if (!s) return fail(GLD_ERR_INVALID_ARG, "NULL system");
+    return read_flags(s);
+}
+
+gld_status gld_read_state(gld_system *s, gld_state *o)
+{
+    if (!s || !o) return fail(GLD_ERR_INVALID_ARG, "NULL argument");
+    gld_status flag = read_flags(s);
+    if (flag == GLD_ERR_DEVICE) return flag;
+    gld_status st;
+    const Dev &d = s->d;
+    if (o->r && (st = download_vec<double>(s, o->r, d.R)) != GLD_OK) return st;
+    if (o->v && (st = download_vec<double>(s, o->v, d.V)) != GLD_OK) return st;
+    if (o->f_c && (st = download_vec<double>(s, o->f_c, d.FC)) != GLD_OK) return st;
+    if (o->f_d && (st = download_work_vec(s, o->f_d, d.FD)) != GLD_OK) return st;
+    if (o->f_r && (st = download_work_vec(s, o->f_r, d.FR)) != GLD_OK) return st;
+    if (o->history && d.nslots > 0) {
+        const size_t elt = s->geo.fp64 ? 8 : 4;
+        const int64_t n = s->p.n;
+        for (int m = 1; m <= d.nslots; ++m) {
+            int slot = static_cast<int>(((s->step - m) % d.nslots + d.nslots) % d.nslots);
+            const void *src = static_cast<const char *>(d.ring) + static_cast<size_t>(slot) * 3 * d.S * elt;
+            if ((st = download_work_vec(s, o->history + static_cast<size_t>(m - 1) * n * 3, src)) != GLD_OK) return st;
+        }
+    }
+    o->step = s->step;
+    int flags[2] = {0, 0};
+    long long fstep = 0;
+    HIP_TRY(hipMemcpy(flags, d.d_flags, sizeof(flags), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&fstep, d.d_flag_step, sizeof(fstep), hipMemcpyDeviceToHost));
+    o->flags = flags[0];
+    o->flag_step = fstep;
+    return flag;
+}
+
+gld_status gld_write_state(gld_system *s, const gld_state *in)
+{
+    if (!s || !in || !in->r || !in->v) return fail(GLD_ERR_INVALID_ARG, "NULL argument");
+    if (in->step < 0 || in->step > (int64_t(1) << 60)) return fail(GLD_ERR_INVALID_ARG, "step must be in [0, 2^60]");
+    if (!finite_all(in->r, 3 * s->p.n) || !finite_all(in->v, 3 * s->p.n))
+        return fail(GLD_ERR_NONFINITE, "state not finite");
+    HIP_TRY(hipStreamSynchronize(s->st));
+    gld_status st;
+    Dev &d = s->d;
+    if ((st = upload_vec<double>(s, d.R, in->r)) != GLD_OK) return st;
+    if ((st = upload_vec<double>(s, d.V, in->v)) != GLD_OK) return st;
+    if ((st = set_step(s, in->step)) != GLD_OK) return st;
+    const size_t elt = s->geo.fp64 ? 8 : 4;
+    if (d.nslots > 0) {
+        const int64_t n = s->p.n;
+        if (in->history) {
+            if (!finite_all(in->history, static_cast<int64_t>(d.nslots) * 3 * n))
+                return fail(GLD_ERR_NONFINITE, "history not finite");
+            for (int m = 1; m <= d.nslots; ++m) {
+                int slot = static_cast<int>(((in->step - m) % d.nslots + d.nslots) % d.nslots);
+                void *dst = static_cast<char *>(d.ring) + static_cast<size_t>(slot) * 3 * d.S * elt;
+                if ((st = upload_work_vec(s, dst, in->history + static_cast<size_t>(m - 1) * n * 3)) != GLD_OK) return st;
+            }
+        } else {
+            HIP_TRY(hipMemsetAsync(d.ring, 0, static_cast<size_t>(d.nslots) * 3 * d.S * elt, s->st));
+        }
+    }
+    HIP_TRY(hipMemsetAsync(d.FD, 0, 3 * d.S * elt, s->st));
+    HIP_TRY(hipMemsetAsync(d.FR, 0, 3 * d.S * elt, s->st));
+    if ((st = clear_flags(s)) != GLD_OK) return st;
+    if ((st = refresh_forces(s)) != GLD_OK) return st;
+    if (s->noise_on) HIP_TRY(gld::launch_fir(d, 1, s->st));  // filter outputs of the current block
+    return read_flags(s);
+}
+
+gld_status gld_noise_parameters(const gld_system *s, gld_noise_info *o)
+{
+    if (!s || !o) return fail(GLD_ERR_INVALID_ARG, "NULL argument");
+    o->cheb_terms = s->noise_on ? s->plan.K : 0;
+    o->rank = s->noise_on ? s->plan.r : 0;
+    o->block = s->d.fir_block;
+    o->lam_lo = s->plan.lo;
+    o->lam_hi = s->plan.hi;
+    o->lam_singular = s->plan.sing_lo;
+    o->err_estimate = s->plan.err_cheb + s->plan.err_rank;
+    return GLD_OK;
+}
+
+gld_status gld_set_graph(gld_system *s, int enable)
+{
+    if (!s) return fail(GLD_ERR_INVALID_ARG, "NULL system");
+    s->graph_on = enable && s->st != nullptr;
+    return GLD_OK;
+}
+
+gld_status gld_set_timing(gld_system *s, int enable)
+{
+    if (!s) return fail(GLD_ERR_INVALID_ARG, "NULL system");
+    HIP_TRY(hipStreamSynchronize(s->st));
+    s->timing = enable != 0;
+    s->pending.clear();
+    s->pool_used = 0;
+    for (int k = 0; k < GLD_K_COUNT; ++k) {
+        s->ms[k] = 0;
+        s->cnt[k] = 0;
+    }
+    return GLD_OK;
+}
+
+gld_status gld_kernel_times(gld_system *s, double *ms_sum, int64_t *launches)
+{
+    if (!s || !ms_sum || !launches) return fail(GLD_ERR_INVALID_ARG, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(s->st));
+    for (auto &pr : s->pending) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, s->pool[pr.second], s->pool[pr.second + 1]));
+        s->ms[pr.first] += ms;
+        s->cnt[pr.first] += 1;
+    }
+    s->pending.clear();
+    s->pool_used = 0;
+    for (int k = 0; k < GLD_K_COUNT; ++k) {
+        ms_sum[k] = s->ms[k];
+        launches[k] = s->cnt[k];
+    }
+    return GLD_OK;
+}
+
+gld_status gld_destroy(gld_system *s)
+{
+    if (!s) return GLD_OK;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    else (void)hipDeviceSynchronize();
+    drop_graph(s);
+    for (auto e : s->pool) (void)hipEventDestroy(e);
+    delete s;
+    return GLD_OK;
+}
+
+gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, double lam_hi, double tol, double *a_out,
+                                   size_t a_cap, double *b_out, size_t b_cap, gld_noise_info *info)
+{
+    gld_status st = validate(params);
+    if (st != GLD_OK) return st;
+    if (!a_out || !b_out || !info) return fail(GLD_ERR_INVALID_ARG, "NULL argument");
+    if (!(params->kT > 0)) return fail(GLD_ERR_INVALID_ARG, "kT must be > 0 for a noise construction");
+    if (tol <= 0) tol = params->precision == GLD_FP64 ? 1e-13 : 1e-6;
+    NoisePlan plan;
+    std::string err;
+    st = gld::noise_build(*params, lam_lo, lam_hi, tol, plan, err);
+    if (st != GLD_OK) return fail(st, err);
+    if (a_cap < plan.Afilt.size() || b_cap < plan.Bmix.size())
+        return fail(GLD_ERR_INVALID_ARG, "output capacity too small");
+    std::copy(plan.Afilt.begin(), plan.Afilt.end(), a_out);
+    std::copy(plan.Bmix.begin(), plan.Bmix.end(), b_out);
+    info->cheb_terms = plan.K;
+    info->rank = plan.r;
+    info->block = 0;
+    info->lam_lo = plan.lo;
+    info->lam_hi = plan.hi;
+    info->lam_singular = plan.sing_lo;
+    info->err_estimate = plan.err_cheb + plan.err_rank;
+    return GLD_OK;
+}
+
+gld_status gld_white_noise(uint64_t seed, int64_t n, int64_t t0, int64_t n_t, double *d_out, uint32_t *d_raw,
+                           void *hip_stream)
+{
+    if (n < 0 || n_t < 0 || n > (int64_t(1) << 32)) return fail(GLD_ERR_INVALID_ARG, "bad sizes");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(gld::launch_white_noise(seed, n, t0, n_t, d_out, d_raw, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GLD_OK;
+}
+
+}  // extern "C"

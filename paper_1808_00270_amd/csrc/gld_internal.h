@@ -1,0 +1,130 @@
+// Internal declarations of libgld: host-side noise construction, device
+// buffer layout and kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gld.h"
+
+namespace gld {
+
+constexpr int kMaxCheb = 512;     // Chebyshev terms of the noise expansion
+constexpr int kMaxRank = 32;      // filters in the white-noise filter bank
+constexpr int kCheckIters = 40;   // Lanczos iterations of a spectrum check
+
+// ---------------------------------------------------------------------------
+// One-off FP64 construction of the colored-noise filters.
+//
+// For a separable pair memory K^p_m(r) = w(r) g_m and no distance dependent
+// self memory, every per-frequency correlation matrix is
+//     K_hat_w = S_w 1 + G_w P,   P = [w(R_ij) T_ij]  (zero diagonal blocks),
+// with S_w, G_w the length-(2 m_max - 1) DFTs of kT a_m K^s_m / dt and
+// kT a_m g_m / dt.  The noise of eq. (noise_production) is then
+//     F_n = (1/P) sum_w' f_w(P) Re W_hat_w,   f_w(x) = sqrt(S_w + G_w x).
+// Expanding f_w in Chebyshev polynomials on an interval [lo, hi] holding the
+// spectrum of P and moving the frequency sum into the time domain gives
+//     F_n = sum_k T_k(P~) v_k(n),   v_k(n) = sum_t C[k][t] W_{n+t},
+// and the coefficient matrix C (K x (2 m_max - 1)) has a tiny numerical rank
+// r, so C = B A with r time filters A and mixing weights B.
+// ---------------------------------------------------------------------------
+struct NoisePlan {
+    int M = 0, P = 0;            // m_max, 2 m_max - 1
+    int K = 0;                   // Chebyshev terms
+    int r = 0;                   // filters
+    double lo = 0, hi = 0;       // expansion interval
+    double alpha = 0, beta = 0;  // P~ = alpha P + beta 1
+    double sing_lo = 0, sing_hi = 0;  // nearest singular points (-inf/+inf if none)
+    double err_cheb = 0, err_rank = 0;
+    std::vector<double> S, G;    // spectra [M]
+    std::vector<double> Bmix;    // [K][r]
+    std::vector<double> Afilt;   // [r][P], filter taps for lags t = -(M-1)..M-1
+};
+
+// Spectra and singular points only (no expansion).  Returns GLD_OK.
+gld_status noise_spectra(const gld_params &p, NoisePlan &plan, std::string &err);
+// Full construction on [lo, hi] with relative rms tolerance tol.
+gld_status noise_build(const gld_params &p, double lo, double hi, double tol, NoisePlan &plan,
+                       std::string &err);
+
+// ---------------------------------------------------------------------------
+// Device-side system description passed to the launchers.
+// ---------------------------------------------------------------------------
+struct Dev {
+    int64_t n = 0;
+    int64_t S = 0;          // component stride (>= n, multiple of 64); vectors are [3][S]
+    int nslots = 0;         // m_max - 1 ring slots
+    int M = 0, P = 0;
+    double box[3] = {0, 0, 0};
+    double dt = 0, mass = 0, kT = 0, a = 0, b = 0;
+    double r_cut = 0, r_cut_min = 0, r0 = 0, dr = 0;
+    int n_r = 0;
+    int parallel = 0;
+    int fp64 = 0;
+    int has_pair = 0;       // pair memory present
+    double wca_sigma = 0, wca_eps = 0;
+    uint64_t seed = 0;
+    int cap = 0;            // neighbours per particle
+    int nc[3] = {1, 1, 1};  // cell grid
+    int noff[3] = {1, 1, 1};
+    int offs[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    int ncell = 1;
+    int fir_block = 1, fir_rcap = 8;
+    double g0 = 0;
+
+    // state (double, [3][S])
+    double *R = nullptr, *V = nullptr, *FC = nullptr, *FCn = nullptr, *Rw = nullptr;
+    // work precision buffers (T = float or double), [3][S] unless noted
+    void *ring = nullptr;   // [nslots][3][S]
+    void *Dneg = nullptr, *Y = nullptr, *FD = nullptr, *FR = nullptr;
+    void *cb[3] = {nullptr, nullptr, nullptr};
+    void *U = nullptr;      // [fir_block][fir_rcap][3][S]
+    void *Afilt = nullptr;  // [fir_rcap][P]
+    void *Bmix = nullptr;   // [kMaxCheb][fir_rcap]
+    void *ks = nullptr, *gm = nullptr;  // [M]
+    double *wtab = nullptr;             // [n_r]
+    void *nbr_w = nullptr;              // [cap][n]
+    void *nbr_e = nullptr;              // [3][cap][n] (parallel tensor only)
+    int *nbr = nullptr;                 // [cap][n]
+    int *nnbr = nullptr;                // [n]
+    int *cell_id = nullptr, *cell_slot = nullptr, *cell_count = nullptr, *cell_start = nullptr;
+    int *cell_tmp = nullptr, *cell_sorted = nullptr;
+    // Lanczos check
+    void *lq[3] = {nullptr, nullptr, nullptr};
+    void *lw = nullptr;
+    double *partial = nullptr;  // [kPartials]
+    double *lab = nullptr;      // alpha[kCheckIters], beta[kCheckIters], result[4]
+    // scalars
+    long long *d_step = nullptr;
+    int *d_flags = nullptr;     // [0] status, [1] unused
+    long long *d_flag_step = nullptr;
+    unsigned *d_rowmax = nullptr;  // max row sum of |w| (float bits)
+};
+
+constexpr int kPartials = 1024;
+
+// Launchers (gld_kernels.hip).  All enqueue on `st` and return hipError_t.
+hipError_t launch_zero_int(int *p, int64_t n, hipStream_t st);
+hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out);
+hipError_t launch_history(const Dev &d, hipStream_t st);
+hipError_t launch_dissipative(const Dev &d, hipStream_t st);
+// filter bank; force = 1 produces the block holding the current step even mid-block
+hipError_t launch_fir(const Dev &d, int force, hipStream_t st);
+// out = a P x + b x + cz z + sum_q coef[q] u_q   (x, z may be null when a=b=0 / cz=0)
+hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
+                       const void *z, const void *coef, int r, void *out);
+hipError_t launch_update_r(const Dev &d, hipStream_t st);
+hipError_t launch_update_v(const Dev &d, hipStream_t st);
+hipError_t launch_step_advance(const Dev &d, hipStream_t st);
+hipError_t launch_fill_zero_work(const Dev &d, void *p, int64_t count, hipStream_t st);
+// Lanczos spectrum check on P; writes theta_min/max into d.lab[2*kCheckIters + 0/1]
+// and latches GLD_ERR_INTERVAL / GLD_ERR_NOT_PD against the given bounds.
+hipError_t launch_spectrum_check(const Dev &d, hipStream_t st, int iters, double lo, double hi,
+                                 double sing_lo, double sing_hi, long long salt);
+hipError_t launch_white_noise(uint64_t seed, int64_t n, int64_t t0, int64_t nt, double *out,
+                              uint32_t *raw, hipStream_t st);
+
+}  // namespace gld

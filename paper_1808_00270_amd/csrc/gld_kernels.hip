@@ -1,0 +1,1024 @@
+// Device kernels of the GLD time step for gfx950 (CDNA4, wave64).
+//
+// Paper: arXiv:1808.00270, Sec. II (eqs. GLD_integrator, aa-bb,
+// dissipative_force2, stochastic_force2, noise_production) and Algorithm 1.
+//
+// Data layout in HBM (all vectors structure-of-arrays, component-major):
+//   positions, velocities, F^C           double [3][S]
+//   displacement ring (history)          T      [m_max-1][3][S]   slot-major
+//   convolution outputs, F^D', F^R       T      [3][S]
+//   filter-bank outputs                  T      [block][rank][3][S]
+//   neighbour list                       int    [cap][n]  (row k = k-th nbr)
+//   neighbour weights w(R_ij)            T      [cap][n]
+// where the component stride S >= n is padded to a multiple of 64, so every
+// component and every ring slot starts on a 256-byte boundary and the history
+// stream is read with 16-byte (float4) or 32-byte (2 x double2) loads, a
+// whole wave covering 1 KiB (2 KiB) per lag.  Padding entries stay zero.
+//
+// T is float in the FP32-mixed mode and double in the FP64 mode; positions,
+// velocities and the conservative force are always double.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "gld_internal.h"
+
+namespace gld {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller.
+// Counter (particle, step lo, step hi, stream), key (seed lo, seed hi).
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        if (i) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        U4 o;
+        o.x = hi1 ^ c.y ^ k0;
+        o.y = lo1;
+        o.z = hi0 ^ c.w ^ k1;
+        o.w = lo0;
+        c = o;
+    }
+    return c;
+}
+
+__device__ __forceinline__ U4 philox_at(uint64_t seed, uint32_t pid, long long t, uint32_t stream)
+{
+    const unsigned long long tu = static_cast<unsigned long long>(t);
+    U4 c{pid, static_cast<uint32_t>(tu), static_cast<uint32_t>(tu >> 32), stream};
+    return philox10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+}
+
+template <typename T>
+struct BoxMuller;
+
+template <>
+struct BoxMuller<double> {
+    __device__ static void gauss3(U4 x, double z[3])
+    {
+        const double s = 1.0 / 4294967296.0;
+        const double u0 = (static_cast<double>(x.x) + 0.5) * s, u1 = (static_cast<double>(x.y) + 0.5) * s;
+        const double u2 = (static_cast<double>(x.z) + 0.5) * s, u3 = (static_cast<double>(x.w) + 0.5) * s;
+        const double ra = sqrt(-2.0 * log(u0)), rb = sqrt(-2.0 * log(u2));
+        double sa, ca, cb, sb;
+        sincos(6.283185307179586476925286766559 * u1, &sa, &ca);
+        sincos(6.283185307179586476925286766559 * u3, &sb, &cb);
+        z[0] = ra * ca;
+        z[1] = ra * sa;
+        z[2] = rb * cb;
+    }
+};
+
+template <>
+struct BoxMuller<float> {
+    __device__ static void gauss3(U4 x, float z[3])
+    {
+        // uniforms formed in double (exact), transcendental part in float
+        const double s = 1.0 / 4294967296.0;
+        const float u0 = static_cast<float>((static_cast<double>(x.x) + 0.5) * s);
+        const float u1 = static_cast<float>((static_cast<double>(x.y) + 0.5) * s);
+        const float u2 = static_cast<float>((static_cast<double>(x.z) + 0.5) * s);
+        const float u3 = static_cast<float>((static_cast<double>(x.w) + 0.5) * s);
+        const float ra = sqrtf(-2.0f * logf(u0)), rb = sqrtf(-2.0f * logf(u2));
+        float sa, ca, sb, cb;
+        sincosf(6.28318530717958647692f * u1, &sa, &ca);
+        sincosf(6.28318530717958647692f * u3, &sb, &cb);
+        z[0] = ra * ca;
+        z[1] = ra * sa;
+        z[2] = rb * cb;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void latch(int *flags, long long *flag_step, int code, long long step)
+{
+    if (atomicCAS(flags, 0, code) == 0) *flag_step = step;
+}
+
+__device__ __forceinline__ double wrap_coord(double x, double L)
+{
+    double y = x - L * floor(x / L);
+    if (y >= L) y -= L;
+    if (y < 0) y += L;
+    return y;
+}
+
+// linear interpolation on the distance grid; the bin index is clamped in
+// floating point first (NaN maps to bin 0), so every table access is in range
+__device__ __forceinline__ double interp_w(const double *wt, int n_r, double r0, double dr, double r, double rmin)
+{
+    if (r < rmin) r = rmin;
+    const double t = fmax((r - r0) / dr, 0.0);
+    const double tb = fmin(floor(t), static_cast<double>(n_r - 2));
+    const int b = static_cast<int>(fmax(tb, 0.0));
+    const double f = t - b;
+    return wt[b] * (1.0 - f) + wt[b + 1] * f;
+}
+
+// cell coordinate of a wrapped position, clamped to [0, nc-1] before the
+// integer conversion (NaN or huge values stay in range)
+__device__ __forceinline__ int cell_coord(double x, double L, int nc)
+{
+    const double q = fmin(fmax(floor(x / L * nc), 0.0), static_cast<double>(nc - 1));
+    return static_cast<int>(q);
+}
+
+__global__ void k_zero_int(int *p, int64_t n)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+template <typename T>
+__global__ void k_zero_work(T *p, int64_t n)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// H1: cell list (deterministic order: by cell, then by particle id)
+// ---------------------------------------------------------------------------
+struct CellGeom {
+    double L[3];
+    int nc[3];
+};
+
+__global__ void k_cell_assign(const double *__restrict__ R, int64_t S, int64_t n, CellGeom g, double *__restrict__ Rw,
+                              int *__restrict__ cell_id, int *__restrict__ cell_slot, int *__restrict__ cell_count)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int ci[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double x = wrap_coord(R[c * S + i], g.L[c]);
+        Rw[c * S + i] = x;
+        ci[c] = cell_coord(x, g.L[c], g.nc[c]);
+    }
+    const int cid = (ci[2] * g.nc[1] + ci[1]) * g.nc[0] + ci[0];
+    cell_id[i] = cid;
+    cell_slot[i] = atomicAdd(&cell_count[cid], 1);
+}
+
+// exclusive scan of the cell counts by one work-group (chunked)
+__global__ void k_cell_scan(const int *__restrict__ count, int *__restrict__ start, int ncell)
+{
+    __shared__ int part[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int chunk = (ncell + nt - 1) / nt;
+    const int b = tid * chunk, e = min(ncell, b + chunk);
+    int s = 0;
+    for (int k = b; k < e; ++k) s += count[k];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - s;
+    for (int k = b; k < e; ++k) {
+        start[k] = run;
+        run += count[k];
+    }
+    if (tid == nt - 1) start[ncell] = part[tid];
+}
+
+__global__ void k_cell_scatter(int64_t n, const int *__restrict__ cell_id, const int *__restrict__ cell_slot,
+                               const int *__restrict__ start, int *__restrict__ tmp)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    tmp[start[cell_id[i]] + cell_slot[i]] = static_cast<int>(i);
+}
+
+__global__ void k_cell_order(int64_t n, const int *__restrict__ cell_id, const int *__restrict__ start,
+                             const int *__restrict__ tmp, int *__restrict__ sorted)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell_id[i];
+    const int b = start[c], e = start[c + 1];
+    int rank = 0;
+    for (int k = b; k < e; ++k) rank += tmp[k] < i;
+    sorted[b + rank] = static_cast<int>(i);
+}
+
+// Pair list within r_cut (ordered pairs, all j != i), weights w(R_ij),
+// optional unit vectors, the WCA force F^C and the Gershgorin row sum.
+struct PairArgs {
+    const double *Rw;
+    int64_t S, n;
+    double L[3];
+    int nc[3], noff[3], offs[3][3];
+    const int *start, *sorted;
+    double rc2, r_cut_min, r0, dr;
+    const double *wtab;
+    int n_r;
+    int cap;
+    double wca_rc2, wca_s2, wca_eps;
+    int *nbr, *nnbr;
+    double *fc;
+    int *flags;
+    long long *flag_step;
+    const long long *d_step;
+    unsigned *rowmax;
+};
+
+template <typename T, bool PAR>
+__global__ void k_pairs(PairArgs a, T *__restrict__ nbr_w, T *__restrict__ nbr_e)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double xi = a.Rw[i], yi = a.Rw[a.S + i], zi = a.Rw[2 * a.S + i];
+    int ci[3];
+    const double xv[3] = {xi, yi, zi};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ci[c] = cell_coord(xv[c], a.L[c], a.nc[c]);
+    int cnt = 0;
+    double fx = 0, fy = 0, fz = 0, rowsum = 0;
+    for (int oz = 0; oz < a.noff[2]; ++oz) {
+        const int cz = (ci[2] + a.offs[2][oz] + a.nc[2]) % a.nc[2];
+        for (int oy = 0; oy < a.noff[1]; ++oy) {
+            const int cy = (ci[1] + a.offs[1][oy] + a.nc[1]) % a.nc[1];
+            for (int ox = 0; ox < a.noff[0]; ++ox) {
+                const int cx = (ci[0] + a.offs[0][ox] + a.nc[0]) % a.nc[0];
+                const int cid = (cz * a.nc[1] + cy) * a.nc[0] + cx;
+                const int b = a.start[cid], e = a.start[cid + 1];
+                for (int k = b; k < e; ++k) {
+                    const int j = a.sorted[k];
+                    if (j == i) continue;
+                    double dx = xi - a.Rw[j], dy = yi - a.Rw[a.S + j], dz = zi - a.Rw[2 * a.S + j];
+                    dx -= a.L[0] * rint(dx / a.L[0]);
+                    dy -= a.L[1] * rint(dy / a.L[1]);
+                    dz -= a.L[2] * rint(dz / a.L[2]);
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (!(r2 < a.rc2)) continue;
+                    if (r2 < a.wca_rc2) {
+                        const double s2 = a.wca_s2 / r2, s6 = s2 * s2 * s2;
+                        const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / r2;
+                        fx += fr * dx;
+                        fy += fr * dy;
+                        fz += fr * dz;
+                    }
+                    const double r = sqrt(r2);
+                    const double w = interp_w(a.wtab, a.n_r, a.r0, a.dr, r, a.r_cut_min);
+                    rowsum += fabs(w);
+                    if (cnt < a.cap) {
+                        const int64_t o = static_cast<int64_t>(cnt) * a.n + i;
+                        a.nbr[o] = j;
+                        nbr_w[o] = static_cast<T>(w);
+                        if (PAR) {
+                            const int64_t plane = static_cast<int64_t>(a.cap) * a.n;
+                            nbr_e[o] = static_cast<T>(dx / r);
+                            nbr_e[plane + o] = static_cast<T>(dy / r);
+                            nbr_e[2 * plane + o] = static_cast<T>(dz / r);
+                        }
+                    }
+                    ++cnt;
+                }
+            }
+        }
+    }
+    if (cnt > a.cap) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
+    a.nnbr[i] = cnt < a.cap ? cnt : a.cap;
+    a.fc[i] = fx;
+    a.fc[a.S + i] = fy;
+    a.fc[2 * a.S + i] = fz;
+    const float rs = static_cast<float>(rowsum);
+    atomicMax(a.rowmax, __float_as_uint(rs));
+}
+
+// ---------------------------------------------------------------------------
+// H3: memory convolution over the displacement ring (HBM stream)
+//   Dneg = -(1/dt) sum_{m=1}^{M-1} K^s_m dR_{n-m}
+//   Y    = g_0 V + (1/dt) sum_{m=1}^{M-1} g_m dR_{n-m}
+// One thread owns 4 consecutive elements of the [3][S] vector and one of CH
+// contiguous lag chunks; chunks are summed through LDS.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+template <>
+struct Vec4<double> {
+    using type = double4;
+};
+
+template <typename T>
+__device__ __forceinline__ typename Vec4<T>::type load4(const T *p);
+template <>
+__device__ __forceinline__ float4 load4<float>(const float *p)
+{
+    return *reinterpret_cast<const float4 *>(p);
+}
+template <>
+__device__ __forceinline__ double4 load4<double>(const double *p)
+{
+    const double2 a = reinterpret_cast<const double2 *>(p)[0];
+    const double2 b = reinterpret_cast<const double2 *>(p)[1];
+    return make_double4(a.x, a.y, b.x, b.y);
+}
+
+constexpr int kConvCols = 64;  // columns (4 elements each) per work-group
+constexpr int kConvCh = 4;     // lag chunks per work-group (block = 256)
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_history(const T *__restrict__ ring, int64_t S, int64_t n3, int nslots,
+                                                 const T *__restrict__ ks, const T *__restrict__ gm,
+                                                 const long long *__restrict__ d_step, const double *__restrict__ V,
+                                                 T g0, T inv_dt, T *__restrict__ Dneg, T *__restrict__ Y)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *sk = reinterpret_cast<T *>(smem_raw);  // [nslots + 1]
+    T *sg = sk + (nslots + 1);                // [nslots + 1]
+    T *red = sg + (nslots + 1);               // [kConvCh][kConvCols][8]
+    for (int m = threadIdx.x; m <= nslots; m += blockDim.x) {
+        sk[m] = ks[m];
+        sg[m] = gm[m];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % kConvCols;
+    const int ch = threadIdx.x / kConvCols;
+    const int64_t e0 = (static_cast<int64_t>(blockIdx.x) * kConvCols + lane) * 4;
+    const bool live = e0 < S;
+    T d0 = 0, d1 = 0, d2 = 0, d3 = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0;
+    if (live && nslots > 0) {
+        const long long step = *d_step;
+        const int head = static_cast<int>(step % nslots);
+        const int per = (nslots + kConvCh - 1) / kConvCh;
+        const int m0 = 1 + ch * per;
+        const int m1 = min(nslots + 1, m0 + per);
+        int slot = head - m0;
+        if (slot < 0) slot += nslots;
+        int m = m0;
+        // four lags per iteration: four independent 16/32-byte loads in flight
+        for (; m + 3 < m1; m += 4) {
+            int s1 = slot - 1, s2 = slot - 2, s3 = slot - 3;
+            if (s1 < 0) s1 += nslots;
+            if (s2 < 0) s2 += nslots;
+            if (s3 < 0) s3 += nslots;
+            const auto x0 = load4<T>(ring + static_cast<int64_t>(slot) * S + e0);
+            const auto x1 = load4<T>(ring + static_cast<int64_t>(s1) * S + e0);
+            const auto x2 = load4<T>(ring + static_cast<int64_t>(s2) * S + e0);
+            const auto x3 = load4<T>(ring + static_cast<int64_t>(s3) * S + e0);
+            const T k0 = sk[m], k1 = sk[m + 1], k2 = sk[m + 2], k3 = sk[m + 3];
+            const T q0 = sg[m], q1 = sg[m + 1], q2 = sg[m + 2], q3 = sg[m + 3];
+            d0 += k0 * x0.x + k1 * x1.x + k2 * x2.x + k3 * x3.x;
+            d1 += k0 * x0.y + k1 * x1.y + k2 * x2.y + k3 * x3.y;
+            d2 += k0 * x0.z + k1 * x1.z + k2 * x2.z + k3 * x3.z;
+            d3 += k0 * x0.w + k1 * x1.w + k2 * x2.w + k3 * x3.w;
+            h0 += q0 * x0.x + q1 * x1.x + q2 * x2.x + q3 * x3.x;
+            h1 += q0 * x0.y + q1 * x1.y + q2 * x2.y + q3 * x3.y;
+            h2 += q0 * x0.z + q1 * x1.z + q2 * x2.z + q3 * x3.z;
+            h3 += q0 * x0.w + q1 * x1.w + q2 * x2.w + q3 * x3.w;
+            slot = s3 - 1;
+            if (slot < 0) slot += nslots;
+        }
+        for (; m < m1; ++m) {
+            const auto x = load4<T>(ring + static_cast<int64_t>(slot) * S + e0);
+            const T k = sk[m], q = sg[m];
+            d0 += k * x.x;
+            d1 += k * x.y;
+            d2 += k * x.z;
+            d3 += k * x.w;
+            h0 += q * x.x;
+            h1 += q * x.y;
+            h2 += q * x.z;
+            h3 += q * x.w;
+            if (--slot < 0) slot += nslots;
+        }
+    }
+    T *my = red + (static_cast<int64_t>(ch) * kConvCols + lane) * 8;
+    my[0] = d0; my[1] = d1; my[2] = d2; my[3] = d3;
+    my[4] = h0; my[5] = h1; my[6] = h2; my[7] = h3;
+    __syncthreads();
+    if (ch != 0 || !live) return;
+    T acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0;
+    for (int c = 0; c < kConvCh; ++c) {
+        const T *o = red + (static_cast<int64_t>(c) * kConvCols + lane) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] += o[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t e = e0 + q;
+        if (e < n3) {
+            Dneg[e] = -acc[q] * inv_dt;
+            Y[e] = g0 * static_cast<T>(V[e]) + acc[4 + q] * inv_dt;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// H4/H5: pair mat-vec with fused combination
+//   out_i = a (P x)_i + b x_i + cz z_i + sum_q coef[q] u_q,i
+// P = [w(R_ij) T_ij], T = 1 (isotropic) or e e^T (parallel).  One thread per
+// particle, neighbours read column-wise (coalesced), x gathered from L2.
+// ---------------------------------------------------------------------------
+struct SpmvArgs {
+    int64_t n, S;
+    int cap;
+    const int *nbr, *nnbr;
+    double a, b, cz;
+    const void *x, *z;
+    const void *coef;   // [r] (device)
+    const void *U;      // filter outputs [block][rcap][S]
+    int r, rcap, block;
+    const long long *d_step;
+    void *out;
+};
+
+template <typename T, bool PAR>
+__global__ __launch_bounds__(256) void k_spmv(SpmvArgs A, const T *__restrict__ nbr_w, const T *__restrict__ nbr_e)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int64_t S = A.S;
+    const T *x = static_cast<const T *>(A.x);
+    T o0 = 0, o1 = 0, o2 = 0;
+    if (A.a != 0.0) {
+        T p0 = 0, p1 = 0, p2 = 0;
+        const int cnt = A.nnbr[i];
+        const int64_t plane = static_cast<int64_t>(A.cap) * A.n;
+        for (int k = 0; k < cnt; ++k) {
+            const int64_t o = static_cast<int64_t>(k) * A.n + i;
+            const int j = A.nbr[o];
+            const T w = nbr_w[o];
+            const T xj0 = x[j], xj1 = x[S + j], xj2 = x[2 * S + j];
+            if (PAR) {
+                const T ex = nbr_e[o], ey = nbr_e[plane + o], ez = nbr_e[2 * plane + o];
+                const T s = w * (ex * xj0 + ey * xj1 + ez * xj2);
+                p0 += s * ex;
+                p1 += s * ey;
+                p2 += s * ez;
+            } else {
+                p0 += w * xj0;
+                p1 += w * xj1;
+                p2 += w * xj2;
+            }
+        }
+        o0 = static_cast<T>(A.a) * p0;
+        o1 = static_cast<T>(A.a) * p1;
+        o2 = static_cast<T>(A.a) * p2;
+    }
+    if (A.b != 0.0) {
+        o0 += static_cast<T>(A.b) * x[i];
+        o1 += static_cast<T>(A.b) * x[S + i];
+        o2 += static_cast<T>(A.b) * x[2 * S + i];
+    }
+    if (A.cz != 0.0) {
+        const T *z = static_cast<const T *>(A.z);
+        o0 += static_cast<T>(A.cz) * z[i];
+        o1 += static_cast<T>(A.cz) * z[S + i];
+        o2 += static_cast<T>(A.cz) * z[2 * S + i];
+    }
+    if (A.r > 0) {
+        const T *coef = static_cast<const T *>(A.coef);
+        const long long step = *A.d_step;
+        const int bi = static_cast<int>(step % A.block);
+        const T *u = static_cast<const T *>(A.U) + static_cast<int64_t>(bi) * A.rcap * 3 * S;
+        for (int q = 0; q < A.r; ++q) {
+            const T c = coef[q];
+            const T *uq = u + static_cast<int64_t>(q) * 3 * S;
+            o0 += c * uq[i];
+            o1 += c * uq[S + i];
+            o2 += c * uq[2 * S + i];
+        }
+    }
+    T *out = static_cast<T *>(A.out);
+    out[i] = o0;
+    out[S + i] = o1;
+    out[2 * S + i] = o2;
+}
+
+// ---------------------------------------------------------------------------
+// H5: white-noise filter bank.  Every BF steps (when the device step counter
+// is a multiple of BF) each thread regenerates its particle's white noise
+// over the window t = n0-(M-1) .. n0+BF-1+(M-1) once and accumulates
+//   u_q(n0 + b) = sum_{t=-(M-1)}^{M-1} A_q[t] W_{n0+b+t},  b < BF, q < RC
+// (filter taps zero-padded to RC rows).  Output U[b][q][3][S].
+// ---------------------------------------------------------------------------
+template <typename T, int BF, int RC>
+__global__ __launch_bounds__(128) void k_fir(int64_t n, int64_t S, int M, uint64_t seed,
+                                             const T *__restrict__ A, const long long *__restrict__ d_step,
+                                             T *__restrict__ U, int force)
+{
+    // regular launches work only at block starts; a forced launch (after a
+    // state is installed mid-block) produces the block holding the step
+    const long long cur = *d_step;
+    if (!force && cur % BF != 0) return;
+    const long long n0 = cur - cur % BF;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int P = 2 * M - 1;
+    T acc[BF][RC][3];
+#pragma unroll
+    for (int b = 0; b < BF; ++b)
+#pragma unroll
+        for (int q = 0; q < RC; ++q) acc[b][q][0] = acc[b][q][1] = acc[b][q][2] = T(0);
+    const int span = P + BF - 1;
+    for (int k = 0; k < span; ++k) {
+        const long long t = n0 - (M - 1) + k;
+        T w[3];
+        BoxMuller<T>::gauss3(philox_at(seed, static_cast<uint32_t>(i), t, 0u), w);
+        // output b uses tap index k - b (lag t - (n0 + b) = k - b - (M-1))
+#pragma unroll
+        for (int b = 0; b < BF; ++b) {
+            const int ti = k - b;
+            if (ti >= 0 && ti < P) {
+#pragma unroll
+                for (int q = 0; q < RC; ++q) {
+                    const T c = A[static_cast<int64_t>(q) * P + ti];
+                    acc[b][q][0] += c * w[0];
+                    acc[b][q][1] += c * w[1];
+                    acc[b][q][2] += c * w[2];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < BF; ++b)
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+            T *u = U + (static_cast<int64_t>(b) * RC + q) * 3 * S;
+            u[i] = acc[b][q][0];
+            u[S + i] = acc[b][q][1];
+            u[2 * S + i] = acc[b][q][2];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// H6: G-JF type update, eq. (GLD_integrator) with the position coefficient b
+// (App. A):  R' = R + dt b V + dt^2/(2M) b (F^C + F^D' + F^R);  dR -> ring.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_update_r(int64_t n3, double *__restrict__ R, const double *__restrict__ V,
+                           const double *__restrict__ FC, const T *__restrict__ FD, const T *__restrict__ FR,
+                           T *__restrict__ ring, int64_t S, int nslots, const long long *__restrict__ d_step,
+                           double c_v, double c_f)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n3) return;
+    const double f = FC[e] + static_cast<double>(FD[e]) + static_cast<double>(FR[e]);
+    const double dR = c_v * V[e] + c_f * f;
+    R[e] += dR;
+    if (nslots > 0) {
+        const int head = static_cast<int>(*d_step % nslots);
+        ring[static_cast<int64_t>(head) * S + e] = static_cast<T>(dR);
+    }
+}
+
+//   V' = a V + dt/(2M) (a F^C_n + F^C_{n+1}) + dt/M b (F^D' + F^R)
+template <typename T>
+__global__ void k_update_v(int64_t n3, const double *__restrict__ R, double *__restrict__ V, double *__restrict__ FC,
+                           const double *__restrict__ FCn, const T *__restrict__ FD, const T *__restrict__ FR, double a,
+                           double half_dt_m, double dtb_m, int *flags, long long *flag_step,
+                           const long long *__restrict__ d_step)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n3) return;
+    const double fcn = FCn[e];
+    const double v = a * V[e] + half_dt_m * (a * FC[e] + fcn) +
+                     dtb_m * (static_cast<double>(FD[e]) + static_cast<double>(FR[e]));
+    V[e] = v;
+    FC[e] = fcn;
+    if (!isfinite(v) || !isfinite(R[e])) latch(flags, flag_step, GLD_ERR_NONFINITE, *d_step);
+}
+
+__global__ void k_step_advance(long long *d_step) { *d_step += 1; }
+
+// ---------------------------------------------------------------------------
+// Spectrum check: Lanczos on P (no reorthogonalisation, extreme Ritz values)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_lanczos_start(int64_t n, int64_t S, uint64_t seed, long long salt, T *__restrict__ q)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T z[3];
+    BoxMuller<T>::gauss3(philox_at(seed, static_cast<uint32_t>(i), salt, 1u), z);
+    q[i] = z[0];
+    q[S + i] = z[1];
+    q[2 * S + i] = z[2];
+}
+
+// partial[block] = sum x*y over the [3][S] vectors (first n of each component)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot(int64_t n, int64_t S, const T *__restrict__ x, const T *__restrict__ y,
+                                             double *__restrict__ partial)
+{
+    __shared__ double sh[256];
+    double s = 0;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < 3 * n;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t c = e / n, i = e - c * n;
+        s += static_cast<double>(x[c * S + i]) * static_cast<double>(y[c * S + i]);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// out = sum(partial) (mode 0) or sqrt(sum) (mode 1)
+__global__ __launch_bounds__(256) void k_dot_finish(const double *__restrict__ partial, int nb, double *out, int mode)
+{
+    __shared__ double sh[256];
+    double s = 0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) s += partial[k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = mode ? sqrt(sh[0]) : sh[0];
+}
+
+// w <- w - alpha q - beta_prev q_prev   (beta_prev = 0 for the first step)
+template <typename T>
+__global__ void k_lanczos_orth(int64_t n, int64_t S, T *__restrict__ w, const T *__restrict__ q,
+                               const T *__restrict__ qp, const double *__restrict__ alpha,
+                               const double *__restrict__ beta_prev)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= 3 * n) return;
+    const int64_t c = e / n, i = e - c * n, o = c * S + i;
+    T v = w[o] - static_cast<T>(*alpha) * q[o];
+    if (beta_prev) v -= static_cast<T>(*beta_prev) * qp[o];
+    w[o] = v;
+}
+
+// q_next = w / beta
+template <typename T>
+__global__ void k_lanczos_scale(int64_t n, int64_t S, const T *__restrict__ w, const double *__restrict__ beta,
+                                T *__restrict__ qn)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= 3 * n) return;
+    const int64_t c = e / n, i = e - c * n, o = c * S + i;
+    const double b = *beta;
+    qn[o] = b > 0 ? static_cast<T>(static_cast<double>(w[o]) / b) : T(0);
+}
+
+// q <- q / |q| using a precomputed norm
+template <typename T>
+__global__ void k_lanczos_normalize(int64_t n, int64_t S, T *__restrict__ q, const double *__restrict__ nrm)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= 3 * n) return;
+    const int64_t c = e / n, i = e - c * n, o = c * S + i;
+    q[o] = static_cast<T>(static_cast<double>(q[o]) / *nrm);
+}
+
+// Sturm count: number of eigenvalues of the tridiagonal (alpha, beta) below x
+__device__ int sturm_count(const double *al, const double *be, int k, double x)
+{
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < k; ++i) {
+        const double b2 = i > 0 ? be[i - 1] * be[i - 1] : 0.0;
+        d = al[i] - x - (i > 0 ? b2 / d : 0.0);
+        if (d == 0.0) d = 1e-300;
+        if (d < 0) ++cnt;
+    }
+    return cnt;
+}
+
+// Extreme Ritz values by bisection; checks them against the noise interval
+// and the singular points; result[0] = theta_min, result[1] = theta_max.
+__global__ void k_lanczos_judge(const double *al, const double *be, int k, double lo, double hi, double sing_lo,
+                                double sing_hi, double *result, int *flags, long long *flag_step,
+                                const long long *d_step)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // effective dimension: stop at the first (near) breakdown
+    int kk = k;
+    for (int i = 0; i < k - 1; ++i)
+        if (!(be[i] > 1e-300)) { kk = i + 1; break; }
+    double gl = 1e300, gh = -1e300;
+    for (int i = 0; i < kk; ++i) {
+        const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i < kk - 1 ? fabs(be[i]) : 0.0);
+        gl = fmin(gl, al[i] - r);
+        gh = fmax(gh, al[i] + r);
+    }
+    double a = gl, b = gh;
+    for (int it = 0; it < 200; ++it) {  // smallest eigenvalue
+        const double mid = 0.5 * (a + b);
+        if (sturm_count(al, be, kk, mid) >= 1) b = mid; else a = mid;
+    }
+    const double tmin = 0.5 * (a + b);
+    a = gl;
+    b = gh;
+    for (int it = 0; it < 200; ++it) {  // largest eigenvalue
+        const double mid = 0.5 * (a + b);
+        if (sturm_count(al, be, kk, mid) >= kk) b = mid; else a = mid;
+    }
+    const double tmax = 0.5 * (a + b);
+    result[0] = tmin;
+    result[1] = tmax;
+    if (!(tmin > sing_lo) || !(tmax < sing_hi)) latch(flags, flag_step, GLD_ERR_NOT_PD, *d_step);
+    else if (tmin < lo || tmax > hi) latch(flags, flag_step, GLD_ERR_INTERVAL, *d_step);
+}
+
+// ---------------------------------------------------------------------------
+// white noise export
+// ---------------------------------------------------------------------------
+__global__ void k_white(uint64_t seed, int64_t n, long long t0, int64_t nt, double *out, uint32_t *raw)
+{
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n * nt) return;
+    const int64_t t = g / n, i = g - t * n;
+    const U4 x = philox_at(seed, static_cast<uint32_t>(i), t0 + t, 0u);
+    if (raw) {
+        raw[4 * g] = x.x;
+        raw[4 * g + 1] = x.y;
+        raw[4 * g + 2] = x.z;
+        raw[4 * g + 3] = x.w;
+    }
+    if (out) {
+        double z[3];
+        BoxMuller<double>::gauss3(x, z);
+        out[3 * g] = z[0];
+        out[3 * g + 1] = z[1];
+        out[3 * g + 2] = z[2];
+    }
+}
+
+inline unsigned blocks(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+template <typename T>
+hipError_t spectrum_check_t(const Dev &d, hipStream_t st, int iters, double lo, double hi, double sing_lo,
+                            double sing_hi, long long salt);
+
+}  // namespace
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+hipError_t launch_zero_int(int *p, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_zero_int<<<blocks(n, 256), 256, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero_work(const Dev &d, void *p, int64_t count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (d.fp64) k_zero_work<double><<<blocks(count, 256), 256, 0, st>>>(static_cast<double *>(p), count);
+    else k_zero_work<float><<<blocks(count, 256), 256, 0, st>>>(static_cast<float *>(p), count);
+    return hipGetLastError();
+}
+
+hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
+{
+    hipError_t e;
+    if ((e = launch_zero_int(d.cell_count, d.ncell, st)) != hipSuccess) return e;
+    if ((e = launch_zero_int(reinterpret_cast<int *>(d.d_rowmax), 1, st)) != hipSuccess) return e;
+    CellGeom g;
+    for (int c = 0; c < 3; ++c) {
+        g.L[c] = d.box[c];
+        g.nc[c] = d.nc[c];
+    }
+    k_cell_assign<<<blocks(d.n, 256), 256, 0, st>>>(d.R, d.S, d.n, g, d.Rw, d.cell_id, d.cell_slot, d.cell_count);
+    k_cell_scan<<<1, 1024, 0, st>>>(d.cell_count, d.cell_start, d.ncell);
+    k_cell_scatter<<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.cell_id, d.cell_slot, d.cell_start, d.cell_tmp);
+    k_cell_order<<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.cell_id, d.cell_start, d.cell_tmp, d.cell_sorted);
+    PairArgs a{};
+    a.Rw = d.Rw;
+    a.S = d.S;
+    a.n = d.n;
+    for (int c = 0; c < 3; ++c) {
+        a.L[c] = d.box[c];
+        a.nc[c] = d.nc[c];
+        a.noff[c] = d.noff[c];
+        for (int k = 0; k < 3; ++k) a.offs[c][k] = d.offs[c][k];
+    }
+    a.start = d.cell_start;
+    a.sorted = d.cell_sorted;
+    a.rc2 = d.r_cut * d.r_cut;
+    a.r_cut_min = d.r_cut_min;
+    a.r0 = d.r0;
+    a.dr = d.dr;
+    a.wtab = d.wtab;
+    a.n_r = d.n_r;
+    a.cap = d.cap;
+    const double rw = std::pow(2.0, 1.0 / 6.0) * d.wca_sigma;
+    a.wca_rc2 = d.wca_eps != 0.0 ? rw * rw : 0.0;
+    a.wca_s2 = d.wca_sigma * d.wca_sigma;
+    a.wca_eps = d.wca_eps;
+    a.nbr = d.nbr;
+    a.nnbr = d.nnbr;
+    a.fc = fc_out;
+    a.flags = d.d_flags;
+    a.flag_step = d.d_flag_step;
+    a.d_step = d.d_step;
+    a.rowmax = d.d_rowmax;
+    if (d.fp64) {
+        if (d.parallel) k_pairs<double, true><<<blocks(d.n, 128), 128, 0, st>>>(a, (double *)d.nbr_w, (double *)d.nbr_e);
+        else k_pairs<double, false><<<blocks(d.n, 128), 128, 0, st>>>(a, (double *)d.nbr_w, (double *)d.nbr_e);
+    } else {
+        if (d.parallel) k_pairs<float, true><<<blocks(d.n, 128), 128, 0, st>>>(a, (float *)d.nbr_w, (float *)d.nbr_e);
+        else k_pairs<float, false><<<blocks(d.n, 128), 128, 0, st>>>(a, (float *)d.nbr_w, (float *)d.nbr_e);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t history_t(const Dev &d, hipStream_t st)
+{
+    const int64_t len = 3 * d.S;  // one slot; a multiple of 4 since S is a multiple of 64
+    const unsigned nb = blocks(len / 4, kConvCols);
+    const size_t shm = sizeof(T) * (2 * (d.nslots + 1) + kConvCh * kConvCols * 8);
+    if (shm > 65536) {  // long memories in FP64: allow up to the 160 KiB of LDS of a CDNA4 CU
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_history<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
+        if (e != hipSuccess) return e;
+    }
+    k_history<T><<<nb, kConvCols * kConvCh, shm, st>>>(
+        static_cast<const T *>(d.ring), len, len, d.nslots, static_cast<const T *>(d.ks),
+        static_cast<const T *>(d.gm), d.d_step, d.V, static_cast<T>(d.g0), static_cast<T>(1.0 / d.dt),
+        static_cast<T *>(d.Dneg), static_cast<T *>(d.Y));
+    return hipGetLastError();
+}
+
+hipError_t launch_history(const Dev &d, hipStream_t st)
+{
+    return d.fp64 ? history_t<double>(d, st) : history_t<float>(d, st);
+}
+
+hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz, const void *z,
+                       const void *coef, int r, void *out)
+{
+    SpmvArgs A{};
+    A.n = d.n;
+    A.S = d.S;
+    A.cap = d.cap;
+    A.nbr = d.nbr;
+    A.nnbr = d.nnbr;
+    A.a = a;
+    A.b = b;
+    A.cz = cz;
+    A.x = x;
+    A.z = z;
+    A.coef = coef;
+    A.U = d.U;
+    A.r = coef ? r : 0;
+    A.rcap = d.fir_rcap;
+    A.block = d.fir_block;
+    A.d_step = d.d_step;
+    A.out = out;
+    const unsigned nb = blocks(d.n, 256);
+    if (d.fp64) {
+        if (d.parallel) k_spmv<double, true><<<nb, 256, 0, st>>>(A, (const double *)d.nbr_w, (const double *)d.nbr_e);
+        else k_spmv<double, false><<<nb, 256, 0, st>>>(A, (const double *)d.nbr_w, nullptr);
+    } else {
+        if (d.parallel) k_spmv<float, true><<<nb, 256, 0, st>>>(A, (const float *)d.nbr_w, (const float *)d.nbr_e);
+        else k_spmv<float, false><<<nb, 256, 0, st>>>(A, (const float *)d.nbr_w, nullptr);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dissipative(const Dev &d, hipStream_t st)
+{
+    // F^D' = -(P Y) + Dneg
+    return launch_spmv(d, st, d.has_pair ? -1.0 : 0.0, 0.0, d.Y, 1.0, d.Dneg, nullptr, 0, d.FD);
+}
+
+template <typename T, int BF, int RC>
+static hipError_t fir_t(const Dev &d, hipStream_t st, int force)
+{
+    k_fir<T, BF, RC><<<blocks(d.n, 128), 128, 0, st>>>(d.n, d.S, d.M, d.seed, static_cast<const T *>(d.Afilt),
+                                                       d.d_step, static_cast<T *>(d.U), force);
+    return hipGetLastError();
+}
+
+hipError_t launch_fir(const Dev &d, int force, hipStream_t st)
+{
+    if (d.fp64) {
+        switch (d.fir_rcap) {
+        case 8: return fir_t<double, 4, 8>(d, st, force);
+        case 16: return fir_t<double, 2, 16>(d, st, force);
+        default: return fir_t<double, 1, 32>(d, st, force);
+        }
+    }
+    switch (d.fir_rcap) {
+    case 8: return fir_t<float, 8, 8>(d, st, force);
+    case 16: return fir_t<float, 4, 16>(d, st, force);
+    default: return fir_t<float, 2, 32>(d, st, force);
+    }
+}
+
+hipError_t launch_update_r(const Dev &d, hipStream_t st)
+{
+    const double c_v = d.dt * d.b, c_f = d.dt * d.dt / (2.0 * d.mass) * d.b;
+    // element-wise over the whole padded [3][S] vectors (padding stays zero)
+    const int64_t len = 3 * d.S;
+    if (d.fp64)
+        k_update_r<double><<<blocks(len, 256), 256, 0, st>>>(len, d.R, d.V, d.FC, (const double *)d.FD,
+                                                              (const double *)d.FR, (double *)d.ring, 3 * d.S,
+                                                              d.nslots, d.d_step, c_v, c_f);
+    else
+        k_update_r<float><<<blocks(len, 256), 256, 0, st>>>(len, d.R, d.V, d.FC, (const float *)d.FD,
+                                                             (const float *)d.FR, (float *)d.ring, 3 * d.S,
+                                                             d.nslots, d.d_step, c_v, c_f);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_v(const Dev &d, hipStream_t st)
+{
+    const int64_t len = 3 * d.S;
+    const double half = d.dt / (2.0 * d.mass), dtb = d.dt / d.mass * d.b;
+    if (d.fp64)
+        k_update_v<double><<<blocks(len, 256), 256, 0, st>>>(len, d.R, d.V, d.FC, d.FCn, (const double *)d.FD,
+                                                              (const double *)d.FR, d.a, half, dtb, d.d_flags,
+                                                              d.d_flag_step, d.d_step);
+    else
+        k_update_v<float><<<blocks(len, 256), 256, 0, st>>>(len, d.R, d.V, d.FC, d.FCn, (const float *)d.FD,
+                                                             (const float *)d.FR, d.a, half, dtb, d.d_flags,
+                                                             d.d_flag_step, d.d_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_advance(const Dev &d, hipStream_t st)
+{
+    k_step_advance<<<1, 1, 0, st>>>(d.d_step);
+    return hipGetLastError();
+}
+
+namespace {
+template <typename T>
+hipError_t spectrum_check_t(const Dev &d, hipStream_t st, int iters, double lo, double hi, double sing_lo,
+                            double sing_hi, long long salt)
+{
+    const int64_t n = d.n, S = d.S;
+    T *q[3] = {static_cast<T *>(d.lq[0]), static_cast<T *>(d.lq[1]), static_cast<T *>(d.lq[2])};
+    T *w = static_cast<T *>(d.lw);
+    double *al = d.lab, *be = d.lab + kCheckIters, *res = d.lab + 2 * kCheckIters;
+    const unsigned nbd = static_cast<unsigned>(std::min<int64_t>(kPartials, blocks(3 * n, 256)));
+    const unsigned ne = blocks(3 * n, 256);
+    k_lanczos_start<T><<<blocks(n, 256), 256, 0, st>>>(n, S, d.seed, salt, q[0]);
+    k_dot<T><<<nbd, 256, 0, st>>>(n, S, q[0], q[0], d.partial);
+    k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, res + 2, 1);
+    k_lanczos_normalize<T><<<ne, 256, 0, st>>>(n, S, q[0], res + 2);
+    iters = std::min(iters, kCheckIters);
+    for (int k = 0; k < iters; ++k) {
+        T *qc = q[k % 3], *qp = q[(k + 2) % 3], *qn = q[(k + 1) % 3];
+        hipError_t e = launch_spmv(d, st, 1.0, 0.0, qc, 0.0, nullptr, nullptr, 0, w);
+        if (e != hipSuccess) return e;
+        k_dot<T><<<nbd, 256, 0, st>>>(n, S, qc, w, d.partial);
+        k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, al + k, 0);
+        k_lanczos_orth<T><<<ne, 256, 0, st>>>(n, S, w, qc, qp, al + k, k > 0 ? be + k - 1 : nullptr);
+        k_dot<T><<<nbd, 256, 0, st>>>(n, S, w, w, d.partial);
+        k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, be + k, 1);
+        k_lanczos_scale<T><<<ne, 256, 0, st>>>(n, S, w, be + k, qn);
+    }
+    k_lanczos_judge<<<1, 1, 0, st>>>(al, be, iters, lo, hi, sing_lo, sing_hi, res, d.d_flags, d.d_flag_step,
+                                     d.d_step);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_spectrum_check(const Dev &d, hipStream_t st, int iters, double lo, double hi, double sing_lo,
+                                 double sing_hi, long long salt)
+{
+    return d.fp64 ? spectrum_check_t<double>(d, st, iters, lo, hi, sing_lo, sing_hi, salt)
+                  : spectrum_check_t<float>(d, st, iters, lo, hi, sing_lo, sing_hi, salt);
+}
+
+hipError_t launch_white_noise(uint64_t seed, int64_t n, int64_t t0, int64_t nt, double *out, uint32_t *raw,
+                              hipStream_t st)
+{
+    if (n * nt == 0) return hipSuccess;
+    k_white<<<blocks(n * nt, 256), 256, 0, st>>>(seed, n, t0, nt, out, raw);
+    return hipGetLastError();
+}
+
+}  // namespace gld

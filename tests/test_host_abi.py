@@ -1,0 +1,149 @@
+"""CPU tests of the library's host side: the C ABI loads and exports every
+declared entry point, parameter validation, and the one-off FP64 noise-filter
+construction checked against the oracle's dense colored noise (Sec. II.C)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_1808_00270_amd as p
+    if not os.path.exists(p._binding.LIB_PATH):
+        from paper_1808_00270_amd import _build
+        _build.build()
+    p.lib()
+    return p
+
+
+def test_every_declared_symbol_is_exported(pkg):
+    header = open(os.path.join(ROOT, "include", "gld.h")).read()
+    declared = set(re.findall(r"^\s*(?:gld_status|const char \*)\s*(gld_\w+)\s*\(", header, re.M))
+    assert len(declared) >= 14
+    lib = C.CDLL(pkg._binding.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(pkg._binding.EXPORTED)
+
+
+def _params(pkg, **over):
+    from paper_1808_00270_amd import workloads as wl
+    w = wl.config(1, m_max=over.pop("m_max", 30))
+    k_self, g, wt, r0, dr = w.tables()
+    keep = [k_self, g, wt]
+    B = pkg._binding
+    d = C.POINTER(C.c_double)
+    p = B.gld_params(n=w.n, box=(C.c_double * 3)(w.box, w.box, w.box), dt=w.dt, mass=1.0, kT=1.0, m_max=w.m_max,
+                     n_r=len(wt), k_self=k_self.ctypes.data_as(d), k_pair_g=g.ctypes.data_as(d),
+                     k_pair_w=wt.ctypes.data_as(d), r0=r0, dr=dr, r_cut=5.0, wca_sigma=1.0, wca_eps=1.0, seed=1)
+    for k, v in over.items():
+        if k == "box":
+            p.box = (C.c_double * 3)(v, v, v)
+        else:
+            setattr(p, k, v)
+    return p, keep
+
+
+def test_workspace_size_and_validation(pkg):
+    B = pkg._binding
+    lib = pkg.lib()
+    p, keep = _params(pkg)
+    nb = C.c_size_t()
+    assert lib.gld_workspace_size(C.byref(p), C.byref(nb)) == B.GLD_OK
+    # ring (m_max-1) * 3 * S floats is part of it
+    assert nb.value > 29 * 3 * 64 * 4
+    p2, k2 = _params(pkg, box=9.0)  # r_cut = 5 >= L/2
+    assert lib.gld_workspace_size(C.byref(p2), C.byref(nb)) == B.GLD_ERR_BOX
+    p3, k3 = _params(pkg)
+    p3.m_max = 0
+    assert lib.gld_workspace_size(C.byref(p3), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    p4, k4 = _params(pkg, dt=-1.0)
+    assert lib.gld_workspace_size(C.byref(p4), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    p5, k5 = _params(pkg, precision=7)
+    assert lib.gld_workspace_size(C.byref(p5), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    assert b"box" in lib.gld_last_error() or len(lib.gld_last_error()) > 0
+
+
+def _filters(pkg, p, lo, hi, tol):
+    B = pkg._binding
+    lib = pkg.lib()
+    P = 2 * p.m_max - 1
+    A = np.zeros(32 * P)
+    Bm = np.zeros(512 * 32)
+    info = B.gld_noise_info()
+    d = C.POINTER(C.c_double)
+    st = lib.gld_build_noise_filters(C.byref(p), lo, hi, tol, A.ctypes.data_as(d), A.size, Bm.ctypes.data_as(d),
+                                     Bm.size, C.byref(info))
+    return st, info, A, Bm
+
+
+@pytest.mark.parametrize("parallel,tol", [(False, 1e-6), (False, 1e-12), (True, 1e-10)])
+def test_noise_filters_reproduce_dense_colored_noise(pkg, oracle_mod, parallel, tol):
+    """F = sum_k T_k(P~) sum_q b[k][q] sum_t a[q][t] W_{n+t}, applied densely
+    here, equals the oracle's dense per-frequency square-root noise within the
+    requested tolerance (normwise, relative)."""
+    B = pkg._binding
+    from paper_1808_00270_amd import workloads as wl
+    n, L, M, dt = 10, 10.5, 24, 0.05  # memory window 1.2 covers the kernel decay
+    rng = np.random.default_rng(17)
+    R = rng.uniform(0, L, (n, 3))
+    k_self = wl.discretize(wl.self_kernel, dt, M)
+    g = wl.discretize(wl.pair_time_kernel, dt, M)
+    n_r, rc = 101, 5.0
+    dr = rc / (n_r - 1)
+    wt = wl.pair_weight(np.arange(n_r) * dr, rc)
+    d = C.POINTER(C.c_double)
+    p = B.gld_params(n=n, box=(C.c_double * 3)(L, L, L), dt=dt, mass=1.0, kT=1.0, m_max=M, n_r=n_r,
+                     k_self=k_self.ctypes.data_as(d), k_pair_g=g.ctypes.data_as(d), k_pair_w=wt.ctypes.data_as(d),
+                     r0=0.0, dr=dr, r_cut=rc, pair_tensor=int(parallel), precision=0, wca_sigma=1.0, wca_eps=1.0,
+                     seed=3)
+    o = oracle_mod.Oracle(n=n, box=L, dt=dt, mass=1.0, kT=1.0, k_self=k_self, k_pair=np.outer(wt, g), r0=0.0,
+                          dr=dr, r_cut=rc, parallel=parallel, seed=3)
+    # dense pair-weight matrix P from the oracle's pair list
+    ij, r = o.pairs(R)
+    Pm = np.zeros((3 * n, 3 * n))
+    for (i, j), rr in zip(ij, r):
+        w = np.interp(rr, np.arange(n_r) * dr, wt)
+        dvec = R[i] - R[j]
+        dvec -= L * np.round(dvec / L)
+        T = np.outer(dvec, dvec) / rr ** 2 if parallel else np.eye(3)
+        Pm[3 * i:3 * i + 3, 3 * j:3 * j + 3] = w * T
+    ev = np.linalg.eigvalsh(Pm)
+    lo, hi = ev.min() - 0.3, ev.max() + 0.5
+    st, info, A, Bm = _filters(pkg, p, lo, hi, tol)
+    assert st == B.GLD_OK, pkg.lib().gld_last_error()
+    K, rk = info.cheb_terms, info.rank
+    assert 1 <= rk <= 32 and K >= 2
+    Pp = 2 * M - 1
+    A = A[:rk * Pp].reshape(rk, Pp)
+    Bm = Bm[:K * rk].reshape(K, rk)
+    al, be = 2 / (hi - lo), -(hi + lo) / (hi - lo)
+    Pt = al * Pm + be * np.eye(3 * n)
+    for step in (0, 5):
+        W = np.array([[oracle_mod.gauss3(3, i, step + t) for i in range(n)] for t in range(-(M - 1), M)])
+        W = W.reshape(Pp, 3 * n)
+        u = A @ W                      # [r][3n]
+        v = Bm @ u                     # [K][3n]
+        # Clenshaw
+        b1 = np.zeros(3 * n)
+        b2 = np.zeros(3 * n)
+        for k in range(K - 1, 0, -1):
+            b1, b2 = v[k] + 2 * Pt @ b1 - b2, b1
+        F = v[0] + Pt @ b1 - b2
+        ref = o.noise_dense_freq(step, R).ravel()
+        err = np.linalg.norm(F - ref) / np.linalg.norm(ref)
+        assert err <= max(10 * tol, 1e-13), (err, info.err_estimate)
+    assert info.err_estimate <= tol
+
+
+def test_noise_filters_report_not_pd(pkg):
+    B = pkg._binding
+    p, keep = _params(pkg)
+    st, info, A, Bm = _filters(pkg, p, -3.0, 5.0, 1e-6)  # singular point near -1.8
+    assert st == B.GLD_ERR_NOT_PD
