@@ -423,7 +423,7 @@ gld_status setup_noise(gld_system *s)
     std::string err;
     gld_status st = gld::noise_spectra(p, s->plan, err);
     if (st != GLD_OK) return fail(st, err);
-    const double tol = p.noise_tol > 0 ? p.noise_tol : (s->geo.fp64 ? 1e-13 : 1e-6);
+    const double tol = p.noise_tol > 0 ? p.noise_tol : (s->geo.fp64 ? 1e-12 : 1e-6);
     double lo = p.lam_lo, hi = p.lam_hi;
     const bool has_pair = d.has_pair;
     if (!(hi > lo)) {
@@ -442,7 +442,9 @@ gld_status setup_noise(gld_system *s)
                                                 std::to_string(s->plan.sing_hi) + "): not positive definite");
             const double span = std::max(1.0, th[1] - th[0]);
             lo = std::isfinite(s->plan.sing_lo) ? th[0] - 0.5 * (th[0] - s->plan.sing_lo) : th[0] - 0.5 * span;
-            hi = 1.2 * std::max(static_cast<double>(gmax), th[1]) + 0.1;
+            // the largest row sum of |w| bounds lambda_max at every step; leave
+            // room for it to grow as the configuration evolves
+            hi = 2.0 * std::max(static_cast<double>(gmax), th[1]) + 1.0;
             if (std::isfinite(s->plan.sing_hi)) hi = std::min(hi, th[1] + 0.5 * (s->plan.sing_hi - th[1]));
         }
     }
@@ -460,6 +462,7 @@ gld_status setup_noise(gld_system *s)
         for (int q = 0; q < pl.r; ++q) B[static_cast<size_t>(k) * d.fir_rcap + q] = pl.Bmix[static_cast<size_t>(k) * pl.r + q];
     if ((st = upload_work_table(s, d.Afilt, A.data(), A.size())) != GLD_OK) return st;
     if ((st = upload_work_table(s, d.Bmix, B.data(), B.size())) != GLD_OK) return st;
+    if (has_pair) d.lam_hi = pl.hi;  // from now on every pair build checks the bound
     return GLD_OK;
 }
 
@@ -765,7 +768,7 @@ gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, doub
     if (st != GLD_OK) return st;
     if (!a_out || !b_out || !info) return fail(GLD_ERR_INVALID_ARG, "NULL argument");
     if (!(params->kT > 0)) return fail(GLD_ERR_INVALID_ARG, "kT must be > 0 for a noise construction");
-    if (tol <= 0) tol = params->precision == GLD_FP64 ? 1e-13 : 1e-6;
+    if (tol <= 0) tol = params->precision == GLD_FP64 ? 1e-12 : 1e-6;
     NoisePlan plan;
     std::string err;
     st = gld::noise_build(*params, lam_lo, lam_hi, tol, plan, err);

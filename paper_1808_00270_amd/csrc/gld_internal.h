@@ -74,6 +74,7 @@ struct Dev {
     int ncell = 1;
     int fir_block = 1, fir_rcap = 8;
     double g0 = 0;
+    double lam_hi = __builtin_huge_val();  // noise interval top, checked every step
 
     // state (double, [3][S])
     double *R = nullptr, *V = nullptr, *FC = nullptr, *FCn = nullptr, *Rw = nullptr;

@@ -241,6 +241,7 @@ struct PairArgs {
     long long *flag_step;
     const long long *d_step;
     unsigned *rowmax;
+    double lam_hi;  // upper end of the noise interval (Gershgorin check), +inf: none
 };
 
 template <typename T, bool PAR>
@@ -303,6 +304,9 @@ __global__ void k_pairs(PairArgs a, T *__restrict__ nbr_w, T *__restrict__ nbr_e
     a.fc[i] = fx;
     a.fc[a.S + i] = fy;
     a.fc[2 * a.S + i] = fz;
+    // block Gershgorin: the spectral norm of P is at most the largest row sum
+    // of |w| (||T_ij|| = 1 for both tensor forms), a rigorous bound on lambda_max
+    if (rowsum > a.lam_hi) latch(a.flags, a.flag_step, GLD_ERR_INTERVAL, *a.d_step);
     const float rs = static_cast<float>(rowsum);
     atomicMax(a.rowmax, __float_as_uint(rs));
 }
@@ -841,6 +845,7 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     a.flag_step = d.d_flag_step;
     a.d_step = d.d_step;
     a.rowmax = d.d_rowmax;
+    a.lam_hi = d.lam_hi;
     if (d.fp64) {
         if (d.parallel) k_pairs<double, true><<<blocks(d.n, 128), 128, 0, st>>>(a, (double *)d.nbr_w, (double *)d.nbr_e);
         else k_pairs<double, false><<<blocks(d.n, 128), 128, 0, st>>>(a, (double *)d.nbr_w, (double *)d.nbr_e);

@@ -150,12 +150,20 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
     std::vector<double> c(static_cast<size_t>(Kc) * M);  // c[k][w]
     std::vector<double> fv(nq);
     for (int w = 0; w < M; ++w) {
-        for (int j = 0; j < nq; ++j) fv[j] = std::sqrt(plan.S[w] + plan.G[w] * lam[j]);
+        double fmax = 0;
+        for (int j = 0; j < nq; ++j) {
+            fv[j] = std::sqrt(plan.S[w] + plan.G[w] * lam[j]);
+            fmax = std::max(fmax, std::fabs(fv[j]));
+        }
+        // coefficients below the round-off floor of the quadrature sum carry
+        // no information (the true ones decay geometrically below it)
+        const double floor_w = 64.0 * std::numeric_limits<double>::epsilon() * fmax;
         for (int k = 0; k < Kc; ++k) {
             const double *ct = &costab[static_cast<size_t>(k) * nq];
             double s = 0;
             for (int j = 0; j < nq; ++j) s += fv[j] * ct[j];
-            c[static_cast<size_t>(k) * M + w] = (k == 0 ? 1.0 : 2.0) * s / nq;
+            s = (k == 0 ? 1.0 : 2.0) * s / nq;
+            c[static_cast<size_t>(k) * M + w] = std::fabs(s) < floor_w ? 0.0 : s;
         }
     }
     // relative rms error of truncating after K terms:
@@ -213,16 +221,19 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
         order[q] = q;
     }
     std::sort(order.begin(), order.end(), [&](int a, int b) { return sv[a] > sv[b]; });
-    // smallest r with sqrt(K sum_{dropped} sigma^2 / c0) <= tol/2,  c0 = sig / P
+    // Truncation error of the rank-r filter bank.  Along an eigenvector of P
+    // with eigenvalue x the error is sum_t (dC^T tau)_t xi_t, xi_t iid N(0,1),
+    // tau_k = T_k(x~), |tau|^2 <= K; hence its rms relative to the signal
+    // (variance c0 = sig / P per component) is at most
+    //     sqrt(K) sigma_{r+1} / sqrt(c0).
+    // Smallest r with that bound within tol/2:
     const double c0 = sig / P;
-    double dropped = 0;
     int r = K;
     for (int q = K - 1; q >= 1; --q) {
-        const double s = sv[order[q]];
-        if (std::sqrt(K * (dropped + s * s) / c0) > 0.5 * tol) break;
-        dropped += s * s;
+        if (std::sqrt(static_cast<double>(K) / c0) * sv[order[q]] > 0.5 * tol) break;  // keep order[q]
         r = q;
     }
+    const double dropped_max = r < K ? sv[order[r]] : 0.0;
     if (r > kMaxRank) {
         err = "noise filter bank needs rank " + std::to_string(r) + " > " + std::to_string(kMaxRank);
         return GLD_ERR_NO_CONV;
@@ -230,7 +241,7 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
     plan.K = K;
     plan.r = r;
     plan.err_cheb = err_cheb;
-    plan.err_rank = std::sqrt(K * dropped / c0);
+    plan.err_rank = std::sqrt(static_cast<double>(K) / c0) * dropped_max;
     plan.Bmix.assign(static_cast<size_t>(K) * r, 0.0);
     plan.Afilt.assign(static_cast<size_t>(r) * P, 0.0);
     for (int qq = 0; qq < r; ++qq) {
