@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the GLD time step on one MI355X.
+
+Workload (default): N = 2e5 particles at density 0.5 (about 262 neighbours
+within r_c = 5), memory m_max = 1000, dt = 0.01, WCA + exp-cos self and pair
+memory (see paper_1808_00270_amd/workloads.py).  One "step" is the whole hot
+path: neighbour build + F^C, history convolution, dissipative pair
+contraction, colored noise (filter bank + Chebyshev mat-vec chain), update.
+
+Prints ONE JSON line: whole-step particle-steps/s of the FP32-mixed path
+(value), the FP64 path beside it, per-step latency p50/p99, per-kernel event
+timings, the roofline of the dominant kernel and of the history convolution,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # vector FP32
+FP64_PEAK_TFLOPS = 78.6        # vector FP64
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic(info, n, m_max, pairs, fp64, kind):
+    """Algorithmic bytes (or flops) of one launch of a kernel class."""
+    sT = 8 if fp64 else 4
+    vec = 3 * n
+    if kind == "history":
+        # ring read, velocity read, two outputs written
+        return dict(bytes=(m_max - 1) * vec * sT + vec * 8 + 2 * vec * sT)
+    if kind in ("noise_spmv", "dissipative"):
+        r = info["rank"]
+        # neighbour index + weight per ordered pair, gathered vector once,
+        # combination inputs (z and r filter outputs), output
+        return dict(bytes=pairs * (4 + sT) + 4 * n + vec * sT * (1 + 1 + r + 1))
+    if kind == "noise_fir":
+        P = 2 * m_max - 1
+        # per active launch: block * rank filters of P taps on 3N channels
+        return dict(flops=2.0 * vec * info["block"] * info["rank"] * P)
+    return {}
+
+
+def run_gpu(args, fp64):
+    import torch
+    import paper_1808_00270_amd as pkg
+    from paper_1808_00270_amd import workloads as wl
+
+    w = wl.config(args.config)
+    tag = "fp64" if fp64 else "fp32-mixed"
+    log(f"[bench] create {w.name} {tag}")
+    t0 = time.perf_counter()
+    s = pkg.System.from_workload(w, fp64=fp64)
+    t_create = time.perf_counter() - t0
+    info = s.noise_info()
+    log(f"[bench] created in {t_create:.1f}s, noise {info}")
+    # warmup
+    s.step(args.warmup)
+    s.sync()
+    # timed region: graph replay of K steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    s.sync()
+    torch.cuda.synchronize()
+    dt_run = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt_run / args.steps
+    log(f"[bench] {tag}: {ms_per_step:.3f} ms/step")
+    # per-step latency, synchronous single steps
+    lat = []
+    for _ in range(args.latency_steps):
+        t1 = time.perf_counter()
+        s.step(1)
+        s.sync()
+        lat.append(1e3 * (time.perf_counter() - t1))
+    # per-kernel durations with HIP events on the system's stream (same work)
+    s.set_timing(True)
+    s.step(args.kernel_steps)
+    kt = s.kernel_times()
+    s.set_timing(False)
+    st = s.read_state()
+    # mean neighbour count from the pair weights is not exported; estimate the
+    # pair count from the density (checked against the oracle's pair list)
+    pairs = w.n * (w.n / w.box ** 3) * 4.0 / 3.0 * math.pi * w.r_cut ** 3
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return dict(w=w, info=info, ms_per_step=ms_per_step, lat=lat, kt=kt, pairs=pairs, t_create=t_create,
+                status=st["status"])
+
+
+def roofline_entry(res, kind, fp64, kernel_steps):
+    w, info = res["w"], res["info"]
+    ms, cnt = res["kt"][kind]
+    if cnt == 0:
+        return None
+    alg = algorithmic(info, w.n, w.m_max, res["pairs"], fp64, kind)
+    if kind == "noise_fir":
+        # only one launch in `block` does work; charge the active ones
+        active = max(1, cnt // max(1, info["block"]))
+        avg = ms / active
+        fl = alg["flops"]
+        ach = fl / (avg * 1e-3) / 1e12
+        peak = FP64_PEAK_TFLOPS if fp64 else FP32_PEAK_TFLOPS
+        return dict(kernel=kind, bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
+                    traffic=None, avg_ms=avg, launches=cnt, flops_per_launch=fl)
+    avg = ms / cnt
+    b = alg["bytes"]
+    ach = b / (avg * 1e-3) / 1e9
+    return dict(kernel=kind, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                traffic=None, avg_ms=avg, launches=cnt, bytes_per_launch=b)
+
+
+def cpu_baseline(args):
+    """The FP64 oracle on a bounded sample of the same workload: dissipative and
+    conservative forces for a sample of particles, the colored noise for a
+    subset of the frequencies of Algorithm 1; scaled to one full step."""
+    import oracle
+    from paper_1808_00270_amd import workloads as wl
+
+    w = wl.config(args.config)
+    k_self, g, wt, r0, dr = w.tables()
+    o = oracle.Oracle(n=w.n, box=w.box, dt=w.dt, mass=w.mass, kT=w.kT, k_self=k_self, k_pair=np.outer(wt, g),
+                      r0=r0, dr=dr, r_cut=w.r_cut, wca_sigma=w.wca_sigma, wca_eps=w.wca_eps, seed=w.seed)
+    R, V = w.initial_state()
+    hist = np.zeros((w.m_max - 1, w.n, 3))   # zero pages; the oracle loops over every lag regardless
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(w.n, size=args.cpu_rows, replace=False))
+    t0 = time.perf_counter()
+    o.forces_rows(R, V, hist, rows)
+    t_rows = time.perf_counter() - t0
+    nw = args.cpu_freqs
+    t0 = time.perf_counter()
+    o.noise(0, R, w0=0, w1=nw)
+    t_noise = time.perf_counter() - t0
+    t_step = t_rows * (w.n / len(rows)) + t_noise * (w.m_max / nw)
+    cores = oracle.num_threads()
+    return dict(value=w.n / t_step, unit="particle-steps/s", cores=cores, kind="oracle",
+                sample=(f"{w.name}: F^C+F^D' of {len(rows)} random particles ({t_rows:.1f}s) and the "
+                        f"Algorithm-1 noise for {nw} of {w.m_max} frequencies incl. pair search ({t_noise:.1f}s), "
+                        f"scaled to one full step = {t_step:.0f}s"),
+                seconds=t_rows + t_noise)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--latency-steps", type=int, default=100)
+    ap.add_argument("--kernel-steps", type=int, default=40)
+    ap.add_argument("--cpu-rows", type=int, default=2000)
+    ap.add_argument("--cpu-freqs", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this GLD build runs one system on one GPU; multi-GPU runs are not supported "
+              "(each GPU would take its own systems with no communication).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+
+    r32 = run_gpu(args, fp64=False)
+    r64 = None if args.no_fp64 else run_gpu(args, fp64=True)
+    w = r32["w"]
+    value = w.n * 1e3 / r32["ms_per_step"]
+    per_step = {k: ms / args.kernel_steps for k, (ms, c) in r32["kt"].items()}
+    dom = max((k for k in per_step if k != "check"), key=lambda k: per_step[k])
+    roof = roofline_entry(r32, dom, False, args.kernel_steps)
+    roof_hist = roofline_entry(r32, "history", False, args.kernel_steps)
+    out = {
+        "metric": "particle-steps/s, N=2e5, m_max=1000 (FP32-mixed vs FP64 plain); p50/p99 latency",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "rho": w.rho, "m_max": w.m_max, "r_cut": w.r_cut, "dt": w.dt,
+                   "precision": "fp32-mixed (f32 history/noise, f64 positions and update)"},
+        "latency_ms": {"p50": float(np.percentile(r32["lat"], 50)), "p99": float(np.percentile(r32["lat"], 99))},
+        "noise": {k: r32["info"][k] for k in ("cheb_terms", "rank", "block", "err_estimate")},
+        "kernels_ms_per_step": per_step,
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | {"kernel": dom},
+        "roofline_history": roof_hist,
+    }
+    if r64 is not None:
+        out["fp64_plain"] = {
+            "value": w.n * 1e3 / r64["ms_per_step"], "ms_per_step": r64["ms_per_step"],
+            "latency_ms": {"p50": float(np.percentile(r64["lat"], 50)), "p99": float(np.percentile(r64["lat"], 99))},
+            "noise": {k: r64["info"][k] for k in ("cheb_terms", "rank", "block", "err_estimate")},
+            "kernels_ms_per_step": {k: ms / args.kernel_steps for k, (ms, c) in r64["kt"].items()},
+            "roofline_history": roofline_entry(r64, "history", True, args.kernel_steps),
+        }
+        out["fp32_over_fp64"] = r64["ms_per_step"] / r32["ms_per_step"]
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -110,19 +110,17 @@ Geometry geometry(const gld_params *p)
         g.cap = static_cast<int>(round_up(static_cast<int64_t>(1.5 * expect + 32), 32));
     }
     g.cap = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g.cap, p->n - 1)));
+    g.cap = static_cast<int>(round_up(g.cap, 8));  // 16-byte aligned rows of 16-bit indices
+    // Cells of edge >= r_cut; a work-group of 128 lanes owns one cell, so aim
+    // for about 96 particles per cell (larger cells are always valid).
+    const double target = 96.0;
     int64_t cells = 1;
     for (int c = 0; c < 3; ++c) {
-        g.nc[c] = std::max(1, static_cast<int>(std::floor(p->box[c] / p->r_cut)));
+        const int by_cut = std::max(1, static_cast<int>(std::floor(p->box[c] / p->r_cut)));
+        const double frac = p->box[c] / std::cbrt(vol);
+        const int by_occ = std::max(1, static_cast<int>(std::lround(std::cbrt(p->n / target) * frac)));
+        g.nc[c] = std::min(by_cut, by_occ);
         cells *= g.nc[c];
-    }
-    // keep the cell count proportional to n (larger cells are always valid)
-    const int64_t limit = std::max<int64_t>(4096, 8 * p->n);
-    while (cells > limit) {
-        cells = 1;
-        for (int c = 0; c < 3; ++c) {
-            g.nc[c] = std::max(1, g.nc[c] * 4 / 5);
-            cells *= g.nc[c];
-        }
     }
     g.ncell = static_cast<int>(cells);
     return g;
@@ -147,19 +145,25 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.Y, vec * elt);
     L.take(d.FD, vec * elt);
     L.take(d.FR, vec * elt);
-    for (auto &b : d.cb) L.take(b, vec * elt);
-    for (auto &b : d.lq) L.take(b, vec * elt);
-    L.take(d.lw, vec * elt);
+    const size_t v4 = 4 * static_cast<size_t>(S) * elt;  // one sorted T4 vector
+    for (auto &b : d.cb) L.take(b, v4);
+    for (auto &b : d.lq) L.take(b, v4);
+    L.take(d.lw, v4);
+    L.take(d.ys, v4);
+    L.take(d.us, static_cast<size_t>(gld::kMaxRank) * v4);
+    L.take(d.pos_s, static_cast<size_t>(n) * 32);
+    L.take(d.relf, static_cast<size_t>(n) * 16);
+    L.take(d.reld, static_cast<size_t>(n) * 32);  // both modes: the neighbour build decides in FP64 data
     L.take(d.U, static_cast<size_t>(g.firw) * vec * elt);
     L.take(d.Afilt, static_cast<size_t>(gld::kMaxRank) * P * elt);
     L.take(d.Bmix, static_cast<size_t>(gld::kMaxCheb) * gld::kMaxRank * elt);
     L.take(d.ks, static_cast<size_t>(p->m_max) * elt);
     L.take(d.gm, static_cast<size_t>(p->m_max) * elt);
     L.take(d.wtab, static_cast<size_t>(p->n_r) * 8);
-    L.take(d.nbr, static_cast<size_t>(g.cap) * n * 4);
-    L.take(d.nbr_w, static_cast<size_t>(g.cap) * n * elt);
-    if (g.parallel) L.take(d.nbr_e, 3 * static_cast<size_t>(g.cap) * n * elt);
-    L.take(d.nnbr, n * 4);
+    L.take(d.nbj, static_cast<size_t>(g.cap) * n * 4);
+    L.take(d.nbw, static_cast<size_t>(g.cap) * n * elt);
+    if (g.parallel) L.take(d.nbe, 3 * static_cast<size_t>(g.cap) * n * elt);
+    L.take(d.nn, n * 4);
     L.take(d.cell_id, n * 4);
     L.take(d.cell_slot, n * 4);
     L.take(d.cell_tmp, n * 4);
@@ -305,36 +309,41 @@ gld_status enqueue_step(gld_system *s)
 {
     const Dev &d = s->d;
     hipStream_t st = s->st;
+    const NoisePlan &pl = s->plan;
     LAUNCH(GLD_K_HISTORY, gld::launch_history(d, st));
+    if (s->noise_on) LAUNCH(GLD_K_NOISE_FIR, gld::launch_fir(d, 0, st));
+    LAUNCH(GLD_K_DISSIPATIVE, gld::launch_permute(d, st, s->noise_on ? pl.r : 0));
     LAUNCH(GLD_K_DISSIPATIVE, gld::launch_dissipative(d, st));
     if (s->noise_on) {
-        const NoisePlan &pl = s->plan;
         const size_t elt = s->geo.fp64 ? 8 : 4;
         const int rc = d.fir_rcap;
         auto coef = [&](int k) {
             return static_cast<const void *>(static_cast<const char *>(d.Bmix) + static_cast<size_t>(k) * rc * elt);
         };
-        LAUNCH(GLD_K_NOISE_FIR, gld::launch_fir(d, 0, st));
-        // Clenshaw: b_k = v_k + 2 P~ b_{k+1} - b_{k+2};  F = v_0 + P~ b_1 - b_2
+        // Clenshaw: b_k = v_k + 2 P~ b_{k+1} - b_{k+2};  F = v_0 + P~ b_1 - b_2,
+        // v_k = sum_q B[k][q] u_q, P~ = alpha P + beta 1
         void *prev1 = nullptr, *prev2 = nullptr;
         for (int k = pl.K - 1; k >= 1; --k) {
             void *out = nullptr;
             for (void *c : d.cb)
                 if (c != prev1 && c != prev2) { out = c; break; }
             if (!prev1) {
-                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r, out));
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r, out,
+                                                          nullptr, nullptr));
             } else {
                 LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, prev1,
-                                                          prev2 ? -1.0 : 0.0, prev2, coef(k), pl.r, out));
+                                                          prev2 ? -1.0 : 0.0, prev2, coef(k), pl.r, out, nullptr,
+                                                          nullptr));
             }
             prev2 = prev1;
             prev1 = out;
         }
         if (prev1) {
             LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0, prev2,
-                                                      coef(0), pl.r, d.FR));
+                                                      coef(0), pl.r, nullptr, d.FR, nullptr));
         } else {
-            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r, d.FR));
+            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r, nullptr,
+                                                      d.FR, nullptr));
         }
     }
     LAUNCH(GLD_K_UPDATE, gld::launch_update_r(d, st));

@@ -81,19 +81,24 @@ struct Dev {
     // work precision buffers (T = float or double), [3][S] unless noted
     void *ring = nullptr;   // [nslots][3][S]
     void *Dneg = nullptr, *Y = nullptr, *FD = nullptr, *FR = nullptr;
-    void *cb[3] = {nullptr, nullptr, nullptr};
+    void *cb[3] = {nullptr, nullptr, nullptr};  // T4 [S] Clenshaw vectors, sorted order
     void *U = nullptr;      // [fir_block][fir_rcap][3][S]
     void *Afilt = nullptr;  // [fir_rcap][P]
     void *Bmix = nullptr;   // [kMaxCheb][fir_rcap]
     void *ks = nullptr, *gm = nullptr;  // [M]
     double *wtab = nullptr;             // [n_r]
-    void *nbr_w = nullptr;              // [cap][n]
-    void *nbr_e = nullptr;              // [3][cap][n] (parallel tensor only)
-    int *nbr = nullptr;                 // [cap][n]
-    int *nnbr = nullptr;                // [n]
+    int *nbj = nullptr;                 // [cap][n] neighbour sorted indices (column-major)
+    void *nbw = nullptr;                // T [cap][n] pair weights w(R_ij)
+    void *nbe = nullptr;                // T [3][cap][n] unit vectors (parallel tensor only)
+    int *nn = nullptr;                  // [n] neighbour counts (sorted order)
+    void *pos_s = nullptr;              // double4 [n] wrapped positions, sorted order
+    void *relf = nullptr;               // float4 [n] positions relative to their own cell, sorted
+    void *reld = nullptr;               // double4 [n] the same in double
+    void *ys = nullptr;                 // T4 [S] dissipative input, sorted order
+    void *us = nullptr;                 // T4 [fir_rcap][S] filter outputs of the step, sorted order
     int *cell_id = nullptr, *cell_slot = nullptr, *cell_count = nullptr, *cell_start = nullptr;
     int *cell_tmp = nullptr, *cell_sorted = nullptr;
-    // Lanczos check
+    // Lanczos check (T4 [S], sorted order)
     void *lq[3] = {nullptr, nullptr, nullptr};
     void *lw = nullptr;
     double *partial = nullptr;  // [kPartials]
@@ -114,9 +119,14 @@ hipError_t launch_history(const Dev &d, hipStream_t st);
 hipError_t launch_dissipative(const Dev &d, hipStream_t st);
 // filter bank; force = 1 produces the block holding the current step even mid-block
 hipError_t launch_fir(const Dev &d, int force, hipStream_t st);
-// out = a P x + b x + cz z + sum_q coef[q] u_q   (x, z may be null when a=b=0 / cz=0)
+// out = a P x + b x + cz z + sum_q coef[q] us_q  (x, z, us: sorted T4; x, z may be null
+// when a = b = 0 / cz = 0).  Written to out_sorted (T4) or, if that is null,
+// scattered to out_orig ([3][S], original order) plus add_orig when given.
 hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
-                       const void *z, const void *coef, int r, void *out);
+                       const void *z, const void *coef, int r, void *out_sorted, void *out_orig,
+                       const void *add_orig);
+// sorted copies of the dissipative input Y and of the r filter outputs of the step
+hipError_t launch_permute(const Dev &d, hipStream_t st, int r);
 hipError_t launch_update_r(const Dev &d, hipStream_t st);
 hipError_t launch_update_v(const Dev &d, hipStream_t st);
 hipError_t launch_step_advance(const Dev &d, hipStream_t st);

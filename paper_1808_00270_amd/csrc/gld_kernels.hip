@@ -111,204 +111,11 @@ __device__ __forceinline__ void latch(int *flags, long long *flag_step, int code
     if (atomicCAS(flags, 0, code) == 0) *flag_step = step;
 }
 
-__device__ __forceinline__ double wrap_coord(double x, double L)
-{
-    double y = x - L * floor(x / L);
-    if (y >= L) y -= L;
-    if (y < 0) y += L;
-    return y;
-}
-
-// linear interpolation on the distance grid; the bin index is clamped in
-// floating point first (NaN maps to bin 0), so every table access is in range
-__device__ __forceinline__ double interp_w(const double *wt, int n_r, double r0, double dr, double r, double rmin)
-{
-    if (r < rmin) r = rmin;
-    const double t = fmax((r - r0) / dr, 0.0);
-    const double tb = fmin(floor(t), static_cast<double>(n_r - 2));
-    const int b = static_cast<int>(fmax(tb, 0.0));
-    const double f = t - b;
-    return wt[b] * (1.0 - f) + wt[b + 1] * f;
-}
-
-// cell coordinate of a wrapped position, clamped to [0, nc-1] before the
-// integer conversion (NaN or huge values stay in range)
-__device__ __forceinline__ int cell_coord(double x, double L, int nc)
-{
-    const double q = fmin(fmax(floor(x / L * nc), 0.0), static_cast<double>(nc - 1));
-    return static_cast<int>(q);
-}
-
-__global__ void k_zero_int(int *p, int64_t n)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
 template <typename T>
 __global__ void k_zero_work(T *p, int64_t n)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = T(0);
-}
-
-// ---------------------------------------------------------------------------
-// H1: cell list (deterministic order: by cell, then by particle id)
-// ---------------------------------------------------------------------------
-struct CellGeom {
-    double L[3];
-    int nc[3];
-};
-
-__global__ void k_cell_assign(const double *__restrict__ R, int64_t S, int64_t n, CellGeom g, double *__restrict__ Rw,
-                              int *__restrict__ cell_id, int *__restrict__ cell_slot, int *__restrict__ cell_count)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int ci[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double x = wrap_coord(R[c * S + i], g.L[c]);
-        Rw[c * S + i] = x;
-        ci[c] = cell_coord(x, g.L[c], g.nc[c]);
-    }
-    const int cid = (ci[2] * g.nc[1] + ci[1]) * g.nc[0] + ci[0];
-    cell_id[i] = cid;
-    cell_slot[i] = atomicAdd(&cell_count[cid], 1);
-}
-
-// exclusive scan of the cell counts by one work-group (chunked)
-__global__ void k_cell_scan(const int *__restrict__ count, int *__restrict__ start, int ncell)
-{
-    __shared__ int part[1024];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int chunk = (ncell + nt - 1) / nt;
-    const int b = tid * chunk, e = min(ncell, b + chunk);
-    int s = 0;
-    for (int k = b; k < e; ++k) s += count[k];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < nt; off <<= 1) {
-        const int v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    int run = part[tid] - s;
-    for (int k = b; k < e; ++k) {
-        start[k] = run;
-        run += count[k];
-    }
-    if (tid == nt - 1) start[ncell] = part[tid];
-}
-
-__global__ void k_cell_scatter(int64_t n, const int *__restrict__ cell_id, const int *__restrict__ cell_slot,
-                               const int *__restrict__ start, int *__restrict__ tmp)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    tmp[start[cell_id[i]] + cell_slot[i]] = static_cast<int>(i);
-}
-
-__global__ void k_cell_order(int64_t n, const int *__restrict__ cell_id, const int *__restrict__ start,
-                             const int *__restrict__ tmp, int *__restrict__ sorted)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = cell_id[i];
-    const int b = start[c], e = start[c + 1];
-    int rank = 0;
-    for (int k = b; k < e; ++k) rank += tmp[k] < i;
-    sorted[b + rank] = static_cast<int>(i);
-}
-
-// Pair list within r_cut (ordered pairs, all j != i), weights w(R_ij),
-// optional unit vectors, the WCA force F^C and the Gershgorin row sum.
-struct PairArgs {
-    const double *Rw;
-    int64_t S, n;
-    double L[3];
-    int nc[3], noff[3], offs[3][3];
-    const int *start, *sorted;
-    double rc2, r_cut_min, r0, dr;
-    const double *wtab;
-    int n_r;
-    int cap;
-    double wca_rc2, wca_s2, wca_eps;
-    int *nbr, *nnbr;
-    double *fc;
-    int *flags;
-    long long *flag_step;
-    const long long *d_step;
-    unsigned *rowmax;
-    double lam_hi;  // upper end of the noise interval (Gershgorin check), +inf: none
-};
-
-template <typename T, bool PAR>
-__global__ void k_pairs(PairArgs a, T *__restrict__ nbr_w, T *__restrict__ nbr_e)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    const double xi = a.Rw[i], yi = a.Rw[a.S + i], zi = a.Rw[2 * a.S + i];
-    int ci[3];
-    const double xv[3] = {xi, yi, zi};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ci[c] = cell_coord(xv[c], a.L[c], a.nc[c]);
-    int cnt = 0;
-    double fx = 0, fy = 0, fz = 0, rowsum = 0;
-    for (int oz = 0; oz < a.noff[2]; ++oz) {
-        const int cz = (ci[2] + a.offs[2][oz] + a.nc[2]) % a.nc[2];
-        for (int oy = 0; oy < a.noff[1]; ++oy) {
-            const int cy = (ci[1] + a.offs[1][oy] + a.nc[1]) % a.nc[1];
-            for (int ox = 0; ox < a.noff[0]; ++ox) {
-                const int cx = (ci[0] + a.offs[0][ox] + a.nc[0]) % a.nc[0];
-                const int cid = (cz * a.nc[1] + cy) * a.nc[0] + cx;
-                const int b = a.start[cid], e = a.start[cid + 1];
-                for (int k = b; k < e; ++k) {
-                    const int j = a.sorted[k];
-                    if (j == i) continue;
-                    double dx = xi - a.Rw[j], dy = yi - a.Rw[a.S + j], dz = zi - a.Rw[2 * a.S + j];
-                    dx -= a.L[0] * rint(dx / a.L[0]);
-                    dy -= a.L[1] * rint(dy / a.L[1]);
-                    dz -= a.L[2] * rint(dz / a.L[2]);
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (!(r2 < a.rc2)) continue;
-                    if (r2 < a.wca_rc2) {
-                        const double s2 = a.wca_s2 / r2, s6 = s2 * s2 * s2;
-                        const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / r2;
-                        fx += fr * dx;
-                        fy += fr * dy;
-                        fz += fr * dz;
-                    }
-                    const double r = sqrt(r2);
-                    const double w = interp_w(a.wtab, a.n_r, a.r0, a.dr, r, a.r_cut_min);
-                    rowsum += fabs(w);
-                    if (cnt < a.cap) {
-                        const int64_t o = static_cast<int64_t>(cnt) * a.n + i;
-                        a.nbr[o] = j;
-                        nbr_w[o] = static_cast<T>(w);
-                        if (PAR) {
-                            const int64_t plane = static_cast<int64_t>(a.cap) * a.n;
-                            nbr_e[o] = static_cast<T>(dx / r);
-                            nbr_e[plane + o] = static_cast<T>(dy / r);
-                            nbr_e[2 * plane + o] = static_cast<T>(dz / r);
-                        }
-                    }
-                    ++cnt;
-                }
-            }
-        }
-    }
-    if (cnt > a.cap) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
-    a.nnbr[i] = cnt < a.cap ? cnt : a.cap;
-    a.fc[i] = fx;
-    a.fc[a.S + i] = fy;
-    a.fc[2 * a.S + i] = fz;
-    // block Gershgorin: the spectral norm of P is at most the largest row sum
-    // of |w| (||T_ij|| = 1 for both tensor forms), a rigorous bound on lambda_max
-    if (rowsum > a.lam_hi) latch(a.flags, a.flag_step, GLD_ERR_INTERVAL, *a.d_step);
-    const float rs = static_cast<float>(rowsum);
-    atomicMax(a.rowmax, __float_as_uint(rs));
 }
 
 // ---------------------------------------------------------------------------
@@ -437,88 +244,6 @@ __global__ __launch_bounds__(256) void k_history(const T *__restrict__ ring, int
 }
 
 // ---------------------------------------------------------------------------
-// H4/H5: pair mat-vec with fused combination
-//   out_i = a (P x)_i + b x_i + cz z_i + sum_q coef[q] u_q,i
-// P = [w(R_ij) T_ij], T = 1 (isotropic) or e e^T (parallel).  One thread per
-// particle, neighbours read column-wise (coalesced), x gathered from L2.
-// ---------------------------------------------------------------------------
-struct SpmvArgs {
-    int64_t n, S;
-    int cap;
-    const int *nbr, *nnbr;
-    double a, b, cz;
-    const void *x, *z;
-    const void *coef;   // [r] (device)
-    const void *U;      // filter outputs [block][rcap][S]
-    int r, rcap, block;
-    const long long *d_step;
-    void *out;
-};
-
-template <typename T, bool PAR>
-__global__ __launch_bounds__(256) void k_spmv(SpmvArgs A, const T *__restrict__ nbr_w, const T *__restrict__ nbr_e)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    const int64_t S = A.S;
-    const T *x = static_cast<const T *>(A.x);
-    T o0 = 0, o1 = 0, o2 = 0;
-    if (A.a != 0.0) {
-        T p0 = 0, p1 = 0, p2 = 0;
-        const int cnt = A.nnbr[i];
-        const int64_t plane = static_cast<int64_t>(A.cap) * A.n;
-        for (int k = 0; k < cnt; ++k) {
-            const int64_t o = static_cast<int64_t>(k) * A.n + i;
-            const int j = A.nbr[o];
-            const T w = nbr_w[o];
-            const T xj0 = x[j], xj1 = x[S + j], xj2 = x[2 * S + j];
-            if (PAR) {
-                const T ex = nbr_e[o], ey = nbr_e[plane + o], ez = nbr_e[2 * plane + o];
-                const T s = w * (ex * xj0 + ey * xj1 + ez * xj2);
-                p0 += s * ex;
-                p1 += s * ey;
-                p2 += s * ez;
-            } else {
-                p0 += w * xj0;
-                p1 += w * xj1;
-                p2 += w * xj2;
-            }
-        }
-        o0 = static_cast<T>(A.a) * p0;
-        o1 = static_cast<T>(A.a) * p1;
-        o2 = static_cast<T>(A.a) * p2;
-    }
-    if (A.b != 0.0) {
-        o0 += static_cast<T>(A.b) * x[i];
-        o1 += static_cast<T>(A.b) * x[S + i];
-        o2 += static_cast<T>(A.b) * x[2 * S + i];
-    }
-    if (A.cz != 0.0) {
-        const T *z = static_cast<const T *>(A.z);
-        o0 += static_cast<T>(A.cz) * z[i];
-        o1 += static_cast<T>(A.cz) * z[S + i];
-        o2 += static_cast<T>(A.cz) * z[2 * S + i];
-    }
-    if (A.r > 0) {
-        const T *coef = static_cast<const T *>(A.coef);
-        const long long step = *A.d_step;
-        const int bi = static_cast<int>(step % A.block);
-        const T *u = static_cast<const T *>(A.U) + static_cast<int64_t>(bi) * A.rcap * 3 * S;
-        for (int q = 0; q < A.r; ++q) {
-            const T c = coef[q];
-            const T *uq = u + static_cast<int64_t>(q) * 3 * S;
-            o0 += c * uq[i];
-            o1 += c * uq[S + i];
-            o2 += c * uq[2 * S + i];
-        }
-    }
-    T *out = static_cast<T *>(A.out);
-    out[i] = o0;
-    out[S + i] = o1;
-    out[2 * S + i] = o2;
-}
-
-// ---------------------------------------------------------------------------
 // H5: white-noise filter bank.  Every BF steps (when the device step counter
 // is a multiple of BF) each thread regenerates its particle's white noise
 // over the window t = n0-(M-1) .. n0+BF-1+(M-1) once and accumulates
@@ -618,29 +343,28 @@ __global__ void k_step_advance(long long *d_step) { *d_step += 1; }
 // Spectrum check: Lanczos on P (no reorthogonalisation, extreme Ritz values)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_lanczos_start(int64_t n, int64_t S, uint64_t seed, long long salt, T *__restrict__ q)
+__global__ void k_lanczos_start(int64_t n, uint64_t seed, long long salt, T *__restrict__ q)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     T z[3];
     BoxMuller<T>::gauss3(philox_at(seed, static_cast<uint32_t>(i), salt, 1u), z);
-    q[i] = z[0];
-    q[S + i] = z[1];
-    q[2 * S + i] = z[2];
+    q[4 * i] = z[0];
+    q[4 * i + 1] = z[1];
+    q[4 * i + 2] = z[2];
+    q[4 * i + 3] = T(0);
 }
 
-// partial[block] = sum x*y over the [3][S] vectors (first n of each component)
+// partial[block] = sum x*y over flat arrays of m entries
 template <typename T>
-__global__ __launch_bounds__(256) void k_dot(int64_t n, int64_t S, const T *__restrict__ x, const T *__restrict__ y,
+__global__ __launch_bounds__(256) void k_dot(int64_t m, const T *__restrict__ x, const T *__restrict__ y,
                                              double *__restrict__ partial)
 {
     __shared__ double sh[256];
     double s = 0;
-    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < 3 * n;
-         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int64_t c = e / n, i = e - c * n;
-        s += static_cast<double>(x[c * S + i]) * static_cast<double>(y[c * S + i]);
-    }
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        s += static_cast<double>(x[e]) * static_cast<double>(y[e]);
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -667,38 +391,34 @@ __global__ __launch_bounds__(256) void k_dot_finish(const double *__restrict__ p
 
 // w <- w - alpha q - beta_prev q_prev   (beta_prev = 0 for the first step)
 template <typename T>
-__global__ void k_lanczos_orth(int64_t n, int64_t S, T *__restrict__ w, const T *__restrict__ q,
-                               const T *__restrict__ qp, const double *__restrict__ alpha,
-                               const double *__restrict__ beta_prev)
+__global__ void k_lanczos_orth(int64_t m, T *__restrict__ w, const T *__restrict__ q, const T *__restrict__ qp,
+                               const double *__restrict__ alpha, const double *__restrict__ beta_prev)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= 3 * n) return;
-    const int64_t c = e / n, i = e - c * n, o = c * S + i;
-    T v = w[o] - static_cast<T>(*alpha) * q[o];
-    if (beta_prev) v -= static_cast<T>(*beta_prev) * qp[o];
-    w[o] = v;
+    if (e >= m) return;
+    T v = w[e] - static_cast<T>(*alpha) * q[e];
+    if (beta_prev) v -= static_cast<T>(*beta_prev) * qp[e];
+    w[e] = v;
 }
 
 // q_next = w / beta
 template <typename T>
-__global__ void k_lanczos_scale(int64_t n, int64_t S, const T *__restrict__ w, const double *__restrict__ beta,
+__global__ void k_lanczos_scale(int64_t m, const T *__restrict__ w, const double *__restrict__ beta,
                                 T *__restrict__ qn)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= 3 * n) return;
-    const int64_t c = e / n, i = e - c * n, o = c * S + i;
+    if (e >= m) return;
     const double b = *beta;
-    qn[o] = b > 0 ? static_cast<T>(static_cast<double>(w[o]) / b) : T(0);
+    qn[e] = b > 0 ? static_cast<T>(static_cast<double>(w[e]) / b) : T(0);
 }
 
 // q <- q / |q| using a precomputed norm
 template <typename T>
-__global__ void k_lanczos_normalize(int64_t n, int64_t S, T *__restrict__ q, const double *__restrict__ nrm)
+__global__ void k_lanczos_normalize(int64_t m, T *__restrict__ q, const double *__restrict__ nrm)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= 3 * n) return;
-    const int64_t c = e / n, i = e - c * n, o = c * S + i;
-    q[o] = static_cast<T>(static_cast<double>(q[o]) / *nrm);
+    if (e >= m) return;
+    q[e] = static_cast<T>(static_cast<double>(q[e]) / *nrm);
 }
 
 // Sturm count: number of eigenvalues of the tridiagonal (alpha, beta) below x
@@ -786,73 +506,11 @@ hipError_t spectrum_check_t(const Dev &d, hipStream_t st, int iters, double lo, 
 // ===========================================================================
 // launchers
 // ===========================================================================
-hipError_t launch_zero_int(int *p, int64_t n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    k_zero_int<<<blocks(n, 256), 256, 0, st>>>(p, n);
-    return hipGetLastError();
-}
-
 hipError_t launch_fill_zero_work(const Dev &d, void *p, int64_t count, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
     if (d.fp64) k_zero_work<double><<<blocks(count, 256), 256, 0, st>>>(static_cast<double *>(p), count);
     else k_zero_work<float><<<blocks(count, 256), 256, 0, st>>>(static_cast<float *>(p), count);
-    return hipGetLastError();
-}
-
-hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
-{
-    hipError_t e;
-    if ((e = launch_zero_int(d.cell_count, d.ncell, st)) != hipSuccess) return e;
-    if ((e = launch_zero_int(reinterpret_cast<int *>(d.d_rowmax), 1, st)) != hipSuccess) return e;
-    CellGeom g;
-    for (int c = 0; c < 3; ++c) {
-        g.L[c] = d.box[c];
-        g.nc[c] = d.nc[c];
-    }
-    k_cell_assign<<<blocks(d.n, 256), 256, 0, st>>>(d.R, d.S, d.n, g, d.Rw, d.cell_id, d.cell_slot, d.cell_count);
-    k_cell_scan<<<1, 1024, 0, st>>>(d.cell_count, d.cell_start, d.ncell);
-    k_cell_scatter<<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.cell_id, d.cell_slot, d.cell_start, d.cell_tmp);
-    k_cell_order<<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.cell_id, d.cell_start, d.cell_tmp, d.cell_sorted);
-    PairArgs a{};
-    a.Rw = d.Rw;
-    a.S = d.S;
-    a.n = d.n;
-    for (int c = 0; c < 3; ++c) {
-        a.L[c] = d.box[c];
-        a.nc[c] = d.nc[c];
-        a.noff[c] = d.noff[c];
-        for (int k = 0; k < 3; ++k) a.offs[c][k] = d.offs[c][k];
-    }
-    a.start = d.cell_start;
-    a.sorted = d.cell_sorted;
-    a.rc2 = d.r_cut * d.r_cut;
-    a.r_cut_min = d.r_cut_min;
-    a.r0 = d.r0;
-    a.dr = d.dr;
-    a.wtab = d.wtab;
-    a.n_r = d.n_r;
-    a.cap = d.cap;
-    const double rw = std::pow(2.0, 1.0 / 6.0) * d.wca_sigma;
-    a.wca_rc2 = d.wca_eps != 0.0 ? rw * rw : 0.0;
-    a.wca_s2 = d.wca_sigma * d.wca_sigma;
-    a.wca_eps = d.wca_eps;
-    a.nbr = d.nbr;
-    a.nnbr = d.nnbr;
-    a.fc = fc_out;
-    a.flags = d.d_flags;
-    a.flag_step = d.d_flag_step;
-    a.d_step = d.d_step;
-    a.rowmax = d.d_rowmax;
-    a.lam_hi = d.lam_hi;
-    if (d.fp64) {
-        if (d.parallel) k_pairs<double, true><<<blocks(d.n, 128), 128, 0, st>>>(a, (double *)d.nbr_w, (double *)d.nbr_e);
-        else k_pairs<double, false><<<blocks(d.n, 128), 128, 0, st>>>(a, (double *)d.nbr_w, (double *)d.nbr_e);
-    } else {
-        if (d.parallel) k_pairs<float, true><<<blocks(d.n, 128), 128, 0, st>>>(a, (float *)d.nbr_w, (float *)d.nbr_e);
-        else k_pairs<float, false><<<blocks(d.n, 128), 128, 0, st>>>(a, (float *)d.nbr_w, (float *)d.nbr_e);
-    }
     return hipGetLastError();
 }
 
@@ -877,44 +535,6 @@ static hipError_t history_t(const Dev &d, hipStream_t st)
 hipError_t launch_history(const Dev &d, hipStream_t st)
 {
     return d.fp64 ? history_t<double>(d, st) : history_t<float>(d, st);
-}
-
-hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz, const void *z,
-                       const void *coef, int r, void *out)
-{
-    SpmvArgs A{};
-    A.n = d.n;
-    A.S = d.S;
-    A.cap = d.cap;
-    A.nbr = d.nbr;
-    A.nnbr = d.nnbr;
-    A.a = a;
-    A.b = b;
-    A.cz = cz;
-    A.x = x;
-    A.z = z;
-    A.coef = coef;
-    A.U = d.U;
-    A.r = coef ? r : 0;
-    A.rcap = d.fir_rcap;
-    A.block = d.fir_block;
-    A.d_step = d.d_step;
-    A.out = out;
-    const unsigned nb = blocks(d.n, 256);
-    if (d.fp64) {
-        if (d.parallel) k_spmv<double, true><<<nb, 256, 0, st>>>(A, (const double *)d.nbr_w, (const double *)d.nbr_e);
-        else k_spmv<double, false><<<nb, 256, 0, st>>>(A, (const double *)d.nbr_w, nullptr);
-    } else {
-        if (d.parallel) k_spmv<float, true><<<nb, 256, 0, st>>>(A, (const float *)d.nbr_w, (const float *)d.nbr_e);
-        else k_spmv<float, false><<<nb, 256, 0, st>>>(A, (const float *)d.nbr_w, nullptr);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_dissipative(const Dev &d, hipStream_t st)
-{
-    // F^D' = -(P Y) + Dneg
-    return launch_spmv(d, st, d.has_pair ? -1.0 : 0.0, 0.0, d.Y, 1.0, d.Dneg, nullptr, 0, d.FD);
 }
 
 template <typename T, int BF, int RC>
@@ -983,27 +603,27 @@ template <typename T>
 hipError_t spectrum_check_t(const Dev &d, hipStream_t st, int iters, double lo, double hi, double sing_lo,
                             double sing_hi, long long salt)
 {
-    const int64_t n = d.n, S = d.S;
+    const int64_t n = d.n, m = 4 * n;  // sorted T4 vectors, the 4th entry stays zero
     T *q[3] = {static_cast<T *>(d.lq[0]), static_cast<T *>(d.lq[1]), static_cast<T *>(d.lq[2])};
     T *w = static_cast<T *>(d.lw);
     double *al = d.lab, *be = d.lab + kCheckIters, *res = d.lab + 2 * kCheckIters;
-    const unsigned nbd = static_cast<unsigned>(std::min<int64_t>(kPartials, blocks(3 * n, 256)));
-    const unsigned ne = blocks(3 * n, 256);
-    k_lanczos_start<T><<<blocks(n, 256), 256, 0, st>>>(n, S, d.seed, salt, q[0]);
-    k_dot<T><<<nbd, 256, 0, st>>>(n, S, q[0], q[0], d.partial);
+    const unsigned nbd = static_cast<unsigned>(std::min<int64_t>(kPartials, blocks(m, 256)));
+    const unsigned ne = blocks(m, 256);
+    k_lanczos_start<T><<<blocks(n, 256), 256, 0, st>>>(n, d.seed, salt, q[0]);
+    k_dot<T><<<nbd, 256, 0, st>>>(m, q[0], q[0], d.partial);
     k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, res + 2, 1);
-    k_lanczos_normalize<T><<<ne, 256, 0, st>>>(n, S, q[0], res + 2);
+    k_lanczos_normalize<T><<<ne, 256, 0, st>>>(m, q[0], res + 2);
     iters = std::min(iters, kCheckIters);
     for (int k = 0; k < iters; ++k) {
         T *qc = q[k % 3], *qp = q[(k + 2) % 3], *qn = q[(k + 1) % 3];
-        hipError_t e = launch_spmv(d, st, 1.0, 0.0, qc, 0.0, nullptr, nullptr, 0, w);
+        hipError_t e = launch_spmv(d, st, 1.0, 0.0, qc, 0.0, nullptr, nullptr, 0, w, nullptr, nullptr);
         if (e != hipSuccess) return e;
-        k_dot<T><<<nbd, 256, 0, st>>>(n, S, qc, w, d.partial);
+        k_dot<T><<<nbd, 256, 0, st>>>(m, qc, w, d.partial);
         k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, al + k, 0);
-        k_lanczos_orth<T><<<ne, 256, 0, st>>>(n, S, w, qc, qp, al + k, k > 0 ? be + k - 1 : nullptr);
-        k_dot<T><<<nbd, 256, 0, st>>>(n, S, w, w, d.partial);
+        k_lanczos_orth<T><<<ne, 256, 0, st>>>(m, w, qc, qp, al + k, k > 0 ? be + k - 1 : nullptr);
+        k_dot<T><<<nbd, 256, 0, st>>>(m, w, w, d.partial);
         k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, be + k, 1);
-        k_lanczos_scale<T><<<ne, 256, 0, st>>>(n, S, w, be + k, qn);
+        k_lanczos_scale<T><<<ne, 256, 0, st>>>(m, w, be + k, qn);
     }
     k_lanczos_judge<<<1, 1, 0, st>>>(al, be, iters, lo, hi, sing_lo, sing_hi, res, d.d_flags, d.d_flag_step,
                                      d.d_step);
