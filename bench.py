@@ -42,9 +42,9 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
         return dict(bytes=(m_max - 1) * vec * sT + vec * 8 + 2 * vec * sT)
     if kind in ("noise_spmv", "dissipative"):
         r = info["rank"]
-        # neighbour index + weight per ordered pair, gathered vector once,
-        # combination inputs (z and r filter outputs), output
-        return dict(bytes=pairs * (4 + sT) + 4 * n + vec * sT * (1 + 1 + r + 1))
+        # 16-bit staged index + weight per ordered pair, the input vector
+        # once, combination inputs (z and r filter outputs), output
+        return dict(bytes=pairs * (2 + sT) + 4 * n + vec * sT * (1 + 1 + r + 1))
     if kind == "noise_fir":
         P = 2 * m_max - 1
         # per active launch: block * rank filters of P taps on 3N channels

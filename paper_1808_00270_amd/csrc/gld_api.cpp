@@ -93,6 +93,7 @@ struct Geometry {
     int ncell = 1;
     bool fp64 = false, parallel = false;
     int firw = 64;
+    int maxc = 1;  // candidates the mat-vec stages per round
 };
 
 Geometry geometry(const gld_params *p)
@@ -110,7 +111,7 @@ Geometry geometry(const gld_params *p)
         g.cap = static_cast<int>(round_up(static_cast<int64_t>(1.5 * expect + 32), 32));
     }
     g.cap = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g.cap, p->n - 1)));
-    g.cap = static_cast<int>(round_up(g.cap, 8));  // 16-byte aligned rows of 16-bit indices
+    g.cap = static_cast<int>(round_up(g.cap, 8));  // lists are stored in chunks of 8 entries
     // Cells of edge >= r_cut; a work-group of 128 lanes owns one cell, so aim
     // for about 96 particles per cell (larger cells are always valid).
     const double target = 96.0;
@@ -123,6 +124,15 @@ Geometry geometry(const gld_params *p)
         cells *= g.nc[c];
     }
     g.ncell = static_cast<int>(cells);
+    // The mat-vec stages the candidates of a cell's stencil in LDS: room for
+    // 15 % over the mean (larger stencils are staged in rounds), at most what
+    // one work-group's LDS holds.
+    int nst = 1;
+    for (int c = 0; c < 3; ++c) nst *= std::min(g.nc[c], 3);
+    const double occ = static_cast<double>(p->n) / cells;
+    int64_t want = round_up(static_cast<int64_t>(1.15 * nst * occ + 64), 64);
+    want = std::min<int64_t>(want, p->n);
+    g.maxc = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, gld::mv_max_staging(g.fp64, g.parallel))));
     return g;
 }
 
@@ -160,9 +170,9 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.ks, static_cast<size_t>(p->m_max) * elt);
     L.take(d.gm, static_cast<size_t>(p->m_max) * elt);
     L.take(d.wtab, static_cast<size_t>(p->n_r) * 8);
-    L.take(d.nbj, static_cast<size_t>(g.cap) * n * 4);
+    L.take(d.nbl, static_cast<size_t>(g.cap) * n * 2);
     L.take(d.nbw, static_cast<size_t>(g.cap) * n * elt);
-    if (g.parallel) L.take(d.nbe, 3 * static_cast<size_t>(g.cap) * n * elt);
+    L.take(d.stab, static_cast<size_t>(g.ncell) * 28 * 8);
     L.take(d.nn, n * 4);
     L.take(d.cell_id, n * 4);
     L.take(d.cell_slot, n * 4);
@@ -575,6 +585,7 @@ gld_status gld_create(const gld_params *params, const double *r0, const double *
     d.wca_eps = p.wca_eps;
     d.seed = p.seed;
     d.cap = s->geo.cap;
+    d.maxc = s->geo.maxc;
     d.ncell = s->geo.ncell;
     for (int c = 0; c < 3; ++c) {
         d.nc[c] = s->geo.nc[c];

@@ -87,9 +87,10 @@ struct Dev {
     void *Bmix = nullptr;   // [kMaxCheb][fir_rcap]
     void *ks = nullptr, *gm = nullptr;  // [M]
     double *wtab = nullptr;             // [n_r]
-    int *nbj = nullptr;                 // [cap][n] neighbour sorted indices (column-major)
-    void *nbw = nullptr;                // T [cap][n] pair weights w(R_ij)
-    void *nbe = nullptr;                // T [3][cap][n] unit vectors (parallel tensor only)
+    void *nbl = nullptr;                // uint16 [cap/8][n][8] staged-stencil indices of the neighbours
+    void *nbw = nullptr;                // T [cap/4][n][4] pair weights (w, or w / R^2 for the parallel tensor)
+    void *stab = nullptr;               // int2 [ncell][28] stencil of each cell (first index, base)
+    int maxc = 0;                       // candidates staged per round by the mat-vec
     int *nn = nullptr;                  // [n] neighbour counts (sorted order)
     void *pos_s = nullptr;              // double4 [n] wrapped positions, sorted order
     void *relf = nullptr;               // float4 [n] positions relative to their own cell, sorted
@@ -127,6 +128,8 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
                        const void *add_orig);
 // sorted copies of the dissipative input Y and of the r filter outputs of the step
 hipError_t launch_permute(const Dev &d, hipStream_t st, int r);
+// largest mat-vec staging capacity (candidates) that fits the LDS of one work-group
+int mv_max_staging(int fp64, int parallel);
 hipError_t launch_update_r(const Dev &d, hipStream_t st);
 hipError_t launch_update_v(const Dev &d, hipStream_t st);
 hipError_t launch_step_advance(const Dev &d, hipStream_t st);

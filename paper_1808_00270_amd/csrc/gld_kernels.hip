@@ -8,8 +8,8 @@
 //   displacement ring (history)          T      [m_max-1][3][S]   slot-major
 //   convolution outputs, F^D', F^R       T      [3][S]
 //   filter-bank outputs                  T      [block][rank][3][S]
-//   neighbour list                       int    [cap][n]  (row k = k-th nbr)
-//   neighbour weights w(R_ij)            T      [cap][n]
+//   neighbour lists (cell-sorted order)  uint16 [cap/8][n][8] staged-stencil indices
+//                                        T      [cap/4][n][4] pair weights
 // where the component stride S >= n is padded to a multiple of 64, so every
 // component and every ring slot starts on a 256-byte boundary and the history
 // stream is read with 16-byte (float4) or 32-byte (2 x double2) loads, a

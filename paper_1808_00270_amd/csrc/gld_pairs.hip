@@ -4,15 +4,18 @@
 // noise, Sec. II.C).
 //
 // Design.  Particles are ordered by cell every step (cells of edge >= r_c,
-// chosen so that a cell holds about one 128-lane work-group of particles).
-// One work-group owns one cell and stages the input vector of the up to 27
-// neighbour cells in LDS, chunk by chunk, so the ~260 neighbour gathers per
-// particle hit LDS instead of L2.  Once per step the neighbour build stores,
-// per particle, the 16-bit indices of its neighbours in that staged
-// neighbourhood and the pair weights w(R_ij) (2 + 4 bytes per pair in FP32,
-// read as 16-byte vectors, prefetched one group ahead); every mat-vec of the
-// step then streams them once.  The parallel tensor form, which also needs
-// the unit vectors, recomputes them from staged positions instead.
+// about a hundred particles each).  The neighbour build, once per step, gives
+// every particle its list of neighbours as 16-bit indices into the
+// concatenated candidate list of its cell's stencil (the up to 27 cells
+// around it) together with the final pair weights, in 8-entry chunks; it also
+// computes the WCA force and the Gershgorin bound of the noise interval.
+// Every mat-vec of the step (about fifty per step: the dissipative force and
+// the Chebyshev chain of the noise) then runs one work-group per cell: it
+// stages the input vector of the stencil in LDS, and four lanes per particle
+// stream the chunks (one 16-byte load brings 8 indices, another 4 weights;
+// a wave's loads are one contiguous kilobyte) and gather from LDS.  The lists
+// are 6 bytes per pair in FP32, so a mat-vec is bound by streaming them from
+// HBM.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,7 +27,7 @@ namespace gld {
 
 namespace {
 
-constexpr int kPairThreads = 128;  // lanes per work-group (one cell)
+constexpr int kPairThreads = 128;  // lanes per work-group of the neighbour build (one cell)
 constexpr int kBuildChunk = 1024;  // staged candidates per round, neighbour build
 constexpr int kMaxStencil = 27;
 
@@ -60,19 +63,6 @@ __device__ __forceinline__ int cell_coord(double x, double L, int nc)
 {
     const double q = fmin(fmax(floor(x / L * nc), 0.0), static_cast<double>(nc - 1));
     return static_cast<int>(q);
-}
-
-// linear interpolation on the distance grid; bin index clamped in floating
-// point first (NaN maps to bin 0), so every table access is in range
-template <typename T>
-__device__ __forceinline__ T interp_w(const T *wt, int n_r, T r0, T inv_dr, T r, T rmin)
-{
-    if (r < rmin) r = rmin;
-    const T t = fmax((r - r0) * inv_dr, T(0));
-    const T tb = fmin(floor(t), static_cast<T>(n_r - 2));
-    const int b = static_cast<int>(fmax(tb, T(0)));
-    const T f = t - static_cast<T>(b);
-    return wt[b] + f * (wt[b + 1] - wt[b]);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,64 +215,124 @@ __device__ void make_stencil(const Geo &g, const int *__restrict__ cstart, int c
     st.base[k] = base;
 }
 
+
 // ---------------------------------------------------------------------------
-// neighbour build: one work-group per cell.  Candidates are staged in LDS
-// (positions relative to the home cell, periodic images applied, as float and
-// double); the wave walks them in lockstep (broadcast reads, no memory
-// traffic in the loop).  Per particle s (sorted order) it writes, column-major
-// so that a wave's 64 consecutive particles touch one contiguous segment,
-//   nbj[k][s]  sorted index of the k-th neighbour
-//   nbw[k][s]  squared distance (turned into w(R_ij) by k_weights)
-//   nbe[c][k][s]  separation vector (parallel tensor form only)
-//   nn[s]      neighbour count,  fc[p] WCA force (FP64, original order)
-// The pair decision is taken in FP64 in the FP64 mode and in FP32 otherwise
-// (a pair within rounding of r_c has w ~ 0 either way); the force is FP64.
+// Neighbour lists.  Particle s (sorted order) with n_s neighbours holds in
+// entry k the neighbour's position in the concatenated candidate list of the
+// home cell's stencil (16 bits; the order in which the mat-vec stages them)
+// and the pair weight, in chunks of 8 entries:
+//   nbl  uint16 [cap/8][n][8]   entry (k, s) at ((k>>3) n + s) 8 + (k&7)
+//   nbw  T      [cap/4][n][4]   entry (k, s) at ((k>>2) n + s) 4 + (k&3)
+// so that one lane fetches 8 indices, or 4 weights, with one 16-byte load
+// (two for FP64 weights) and a wave's 64 consecutive particles read one
+// contiguous segment.  The weight is w(R_ij) for the isotropic tensor and
+// w(R_ij) / R_ij^2 for the parallel one, whose mat-vec rebuilds the
+// separation d from staged positions (w e e^T x = (w / R^2) d (d . x)).
+// Lists are padded to a multiple of 8 with zero weights (index of the
+// particle itself).  The stencil of each cell is stored as well:
+//   stab int2 [ncell][28]      (first sorted index, concatenation base) of
+//                               each entry; entry nst holds (0, total)
 // ---------------------------------------------------------------------------
+constexpr int kStab = kMaxStencil + 1;
+
+__device__ __forceinline__ int64_t nbl_at(int k, int64_t s, int64_t n) { return ((k >> 3) * n + s) * 8 + (k & 7); }
+__device__ __forceinline__ int64_t nbw_at(int k, int64_t s, int64_t n) { return ((k >> 2) * n + s) * 4 + (k & 3); }
+
 struct BuildArgs {
     Geo g;
     int64_t n, S;
+    int ncell;
     const int *cstart, *sorted;
     const double4 *reld_src;  // positions relative to their own cell, double
-    int exact64, parallel;
+    const double4 *pos_s;     // wrapped positions (WCA force in FP64)
     double rc2;
     int cap;
+    const double *wtab;       // w(r) on the distance grid
+    int n_r;
+    double r0, dr, r_cut_min, lam_hi;
     double wca_rc2, wca_s2, wca_eps;
-    int *nbj;
-    void *nbw, *nbe;
+    uint16_t *nbl;
+    void *nbw;
     int *nn;
-    double *fc;
+    int2 *stab;
+    double *fc;               // WCA force, [3][S] original order
+    unsigned *rowmax;
     int *flags;
     long long *flag_step;
     const long long *d_step;
 };
 
+__device__ __forceinline__ double interp_wd(const double *wt, int n_r, double r0, double dr, double r, double rmin)
+{
+    if (r < rmin) r = rmin;
+    const double t = fmax((r - r0) / dr, 0.0);
+    const double tb = fmin(floor(t), static_cast<double>(n_r - 2));
+    const int b = static_cast<int>(fmax(tb, 0.0));
+    const double f = t - b;
+    return wt[b] * (1.0 - f) + wt[b + 1] * f;
+}
+
+// w(r): linear interpolation on the distance grid, frozen below r_cut_min
 template <typename T>
+__device__ __forceinline__ T weight_of(const BuildArgs &a, T r)
+{
+    if (sizeof(T) == 8) return static_cast<T>(interp_wd(a.wtab, a.n_r, a.r0, a.dr, static_cast<double>(r), a.r_cut_min));
+    const T rmin = static_cast<T>(a.r_cut_min);
+    const T rr = r < rmin ? rmin : r;
+    const T t = fmax((rr - static_cast<T>(a.r0)) * static_cast<T>(1.0 / a.dr), T(0));
+    const T tb = fmin(floor(t), static_cast<T>(a.n_r - 2));
+    const int b = static_cast<int>(fmax(tb, T(0)));
+    const T f = t - static_cast<T>(b);
+    const T w0 = static_cast<T>(a.wtab[b]), w1 = static_cast<T>(a.wtab[b + 1]);
+    return w0 + f * (w1 - w0);
+}
+
+// ---------------------------------------------------------------------------
+// neighbour build: one work-group per cell.  Candidates are staged in LDS
+// (positions relative to the home cell, periodic images applied, as float or
+// double); the wave walks them in lockstep (broadcast reads, no memory
+// traffic in the loop).  The pair decision is taken in FP64 in the FP64 mode
+// and in FP32 otherwise (a pair within rounding of r_c has w ~ 0 either way);
+// the WCA force is FP64 from the wrapped positions.  Per particle it writes
+// the lists above, nn[s], fc[p], and checks the row sum of |w| (a bound on
+// the spectral norm of P, ||T_ij|| = 1 for both tensor forms) against the
+// top of the noise interval.
+// ---------------------------------------------------------------------------
+template <typename T, bool EXACT64, bool PAR>
 __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
 {
-    constexpr int CH = 1024;
+    constexpr int CH = kBuildChunk;
     __shared__ Stencil st;
-    __shared__ float4 relf[CH];
-    __shared__ double4 reld[CH];
+    __shared__ float4 relf[EXACT64 ? 1 : CH];
+    __shared__ double4 reld[EXACT64 ? CH : 1];
     __shared__ int sid[CH];
     const int cid = blockIdx.x;
-    if (threadIdx.x == 0) make_stencil(a.g, a.cstart, cid, st);
+    if (threadIdx.x == 0) {
+        make_stencil(a.g, a.cstart, cid, st);
+        int2 *row = a.stab + static_cast<int64_t>(cid) * kStab;
+        for (int k = 0; k < st.n; ++k) row[k] = make_int2(st.start[k], st.base[k]);
+        row[st.n] = make_int2(0, st.base[st.n]);
+    }
     __syncthreads();
     const int h0 = a.cstart[cid], h1 = a.cstart[cid + 1];
     const int total = st.base[st.n];
+    const bool store = total <= 65536;  // staged positions must fit 16 bits
     const float Lxf = static_cast<float>(a.g.L[0]), Lyf = static_cast<float>(a.g.L[1]), Lzf = static_cast<float>(a.g.L[2]);
     const bool mi0 = a.g.nc[0] < 3, mi1 = a.g.nc[1] < 3, mi2 = a.g.nc[2] < 3;
     const float rc2f = static_cast<float>(a.rc2);
-    const int64_t plane = static_cast<int64_t>(a.cap) * a.n;
+    const int64_t n = a.n;
+    const double wca_pre = a.wca_rc2 * 1.0001;
     T *nbw = static_cast<T *>(a.nbw);
-    T *nbe = static_cast<T *>(a.nbe);
+    uint16_t *nbl = a.nbl;
     for (int g0 = h0; g0 < h1; g0 += kPairThreads) {
         const int s = g0 + threadIdx.x;
         const bool live = s < h1;
         const int self_l = st.base[st.home] + (s - h0);
         const double4 xd = live ? a.reld_src[s] : make_double4(0, 0, 0, 0);
+        const double4 xi = live ? a.pos_s[s] : make_double4(0, 0, 0, 0);
         const float xf0 = static_cast<float>(xd.x), xf1 = static_cast<float>(xd.y), xf2 = static_cast<float>(xd.z);
         int cnt = 0;
-        double fx = 0, fy = 0, fz = 0;
+        double rowsum = 0, fx = 0, fy = 0, fz = 0;
         for (int c0 = 0; c0 < total; c0 += CH) {
             const int c1 = min(total, c0 + CH);
             __syncthreads();
@@ -305,139 +355,93 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
             for (int j = 0; j < per; ++j) {
                 const int l = static_cast<int>(threadIdx.x) + j * kPairThreads;
                 if (c0 + l < c1) {
-                    reld[l] = v[j];
-                    relf[l] = make_float4(static_cast<float>(v[j].x), static_cast<float>(v[j].y),
-                                          static_cast<float>(v[j].z), 0.f);
+                    if (EXACT64) reld[l] = v[j];
+                    else
+                        relf[l] = make_float4(static_cast<float>(v[j].x), static_cast<float>(v[j].y),
+                                              static_cast<float>(v[j].z), 0.f);
                     sid[l] = sj[j];
                 }
             }
             __syncthreads();
             if (!live) continue;
-            for (int l = c0; l < c1; ++l) {
-                bool in;
-                double r2, ex, ey, ez;
-                if (a.exact64) {
-                    const double4 q = reld[l - c0];
-                    ex = xd.x - q.x;
-                    ey = xd.y - q.y;
-                    ez = xd.z - q.z;
-                    if (mi0) ex -= a.g.L[0] * rint(ex / a.g.L[0]);
-                    if (mi1) ey -= a.g.L[1] * rint(ey / a.g.L[1]);
-                    if (mi2) ez -= a.g.L[2] * rint(ez / a.g.L[2]);
-                    r2 = ex * ex + ey * ey + ez * ez;
-                    in = r2 < a.rc2;
-                } else {
-                    const float4 q = relf[l - c0];
-                    float dx = xf0 - q.x, dy = xf1 - q.y, dz = xf2 - q.z;
-                    if (mi0) dx -= Lxf * rintf(dx / Lxf);
-                    if (mi1) dy -= Lyf * rintf(dy / Lyf);
-                    if (mi2) dz -= Lzf * rintf(dz / Lzf);
-                    const float r2f = dx * dx + dy * dy + dz * dz;
-                    in = r2f < rc2f;
-                    r2 = r2f;
-                    ex = dx;
-                    ey = dy;
-                    ez = dz;
+            // wave-uniform candidates, four per round: broadcast LDS reads
+            // issued together, then branch-light appends
+            for (int l0 = c0; l0 < c1; l0 += 4) {
+                T r2[4];
+                bool hit[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int l = l0 + u;
+                    const int li = min(l, c1 - 1) - c0;
+                    if (EXACT64) {
+                        const double4 q = reld[li];
+                        double dx = xd.x - q.x, dy = xd.y - q.y, dz = xd.z - q.z;
+                        if (mi0) dx -= a.g.L[0] * rint(dx / a.g.L[0]);
+                        if (mi1) dy -= a.g.L[1] * rint(dy / a.g.L[1]);
+                        if (mi2) dz -= a.g.L[2] * rint(dz / a.g.L[2]);
+                        r2[u] = dx * dx + dy * dy + dz * dz;
+                        hit[u] = r2[u] < a.rc2;
+                    } else {
+                        const float4 q = relf[li];
+                        float dx = xf0 - q.x, dy = xf1 - q.y, dz = xf2 - q.z;
+                        if (mi0) dx -= Lxf * rintf(dx / Lxf);
+                        if (mi1) dy -= Lyf * rintf(dy / Lyf);
+                        if (mi2) dz -= Lzf * rintf(dz / Lzf);
+                        const float r2f = dx * dx + dy * dy + dz * dz;
+                        r2[u] = r2f;
+                        hit[u] = r2f < rc2f;
+                    }
+                    hit[u] = hit[u] && l < c1 && l != self_l;
                 }
-                if (!in || l == self_l) continue;
-                if (r2 < a.wca_rc2 * 1.0001) {
-                    // WCA force in FP64 from the staged double positions
-                    const double4 q = reld[l - c0];
-                    double gx = xd.x - q.x, gy = xd.y - q.y, gz = xd.z - q.z;
-                    if (mi0) gx -= a.g.L[0] * rint(gx / a.g.L[0]);
-                    if (mi1) gy -= a.g.L[1] * rint(gy / a.g.L[1]);
-                    if (mi2) gz -= a.g.L[2] * rint(gz / a.g.L[2]);
-                    const double rd2 = gx * gx + gy * gy + gz * gz;
-                    if (rd2 < a.wca_rc2) {
-                        const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
-                        const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
-                        fx += fr * gx;
-                        fy += fr * gy;
-                        fz += fr * gz;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!hit[u]) continue;
+                    const T r = sqrt(r2[u]);
+                    const T w = weight_of<T>(a, r);
+                    rowsum += fabs(static_cast<double>(w));
+                    if (store && cnt < a.cap) {
+                        nbl[nbl_at(cnt, s, n)] = static_cast<uint16_t>(l0 + u);
+                        nbw[nbw_at(cnt, s, n)] = PAR ? w / r2[u] : w;
+                    }
+                    ++cnt;
+                    if (static_cast<double>(r2[u]) < wca_pre) {
+                        // conservative WCA force in FP64 from the wrapped positions
+                        const double4 xj = a.pos_s[sid[l0 + u - c0]];
+                        double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
+                        gx -= a.g.L[0] * rint(gx / a.g.L[0]);
+                        gy -= a.g.L[1] * rint(gy / a.g.L[1]);
+                        gz -= a.g.L[2] * rint(gz / a.g.L[2]);
+                        const double rd2 = gx * gx + gy * gy + gz * gz;
+                        if (rd2 < a.wca_rc2) {
+                            const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
+                            const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
+                            fx += fr * gx;
+                            fy += fr * gy;
+                            fz += fr * gz;
+                        }
                     }
                 }
-                if (cnt < a.cap) {
-                    const int64_t o = static_cast<int64_t>(cnt) * a.n + s;
-                    a.nbj[o] = sid[l - c0];
-                    nbw[o] = static_cast<T>(r2);
-                    if (a.parallel) {
-                        nbe[o] = static_cast<T>(ex);
-                        nbe[plane + o] = static_cast<T>(ey);
-                        nbe[2 * plane + o] = static_cast<T>(ez);
-                    }
-                }
-                ++cnt;
             }
         }
         if (live) {
+            const int kept = store ? min(cnt, a.cap) : 0;
+            for (int k = kept; k < ((kept + 7) & ~7); ++k) {
+                nbl[nbl_at(k, s, n)] = static_cast<uint16_t>(self_l);
+                nbw[nbw_at(k, s, n)] = T(0);
+            }
+            if (cnt > a.cap || !store) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
+            a.nn[s] = kept;
             const int p = a.sorted[s];
-            if (cnt > a.cap) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
-            a.nn[s] = min(cnt, a.cap);
             a.fc[p] = fx;
             a.fc[a.S + p] = fy;
             a.fc[2 * a.S + p] = fz;
+            if (rowsum > a.lam_hi) latch(a.flags, a.flag_step, GLD_ERR_INTERVAL, *a.d_step);
         }
+        // largest row sum: wave maximum, one atomic per wave
+        float rm = static_cast<float>(rowsum);
+        for (int off = 32; off > 0; off >>= 1) rm = fmaxf(rm, __shfl_xor(rm, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(a.rowmax, __float_as_uint(rm));
     }
-}
-
-__device__ __forceinline__ double interp_wd(const double *wt, int n_r, double r0, double dr, double r, double rmin)
-{
-    if (r < rmin) r = rmin;
-    const double t = fmax((r - r0) / dr, 0.0);
-    const double tb = fmin(floor(t), static_cast<double>(n_r - 2));
-    const int b = static_cast<int>(fmax(tb, 0.0));
-    const double f = t - b;
-    return wt[b] * (1.0 - f) + wt[b + 1] * f;
-}
-
-// ---------------------------------------------------------------------------
-// pair weights, lane-parallel over each particle's own list (lockstep k,
-// coalesced): nbw <- w(sqrt(nbw)) (linear interpolation on the distance grid,
-// frozen below r_cut_min), unit vectors for the parallel form, and the block
-// Gershgorin check of the largest row sum of |w| (a bound on the spectral norm
-// of P, ||T_ij|| = 1 for both tensor forms) against the noise interval.
-// ---------------------------------------------------------------------------
-template <typename T, bool PAR>
-__global__ __launch_bounds__(256) void k_weights(int64_t n, int cap, const int *__restrict__ nn, T *__restrict__ nbw,
-                                                 T *__restrict__ nbe, const double *__restrict__ wtab, int n_r,
-                                                 double r0, double dr, double r_cut_min, double lam_hi,
-                                                 unsigned *rowmax, int *flags, long long *flag_step,
-                                                 const long long *d_step)
-{
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int cnt = nn[s];
-    const int64_t plane = static_cast<int64_t>(cap) * n;
-    const T tr0 = static_cast<T>(r0), inv_dr = static_cast<T>(1.0 / dr), rmin = static_cast<T>(r_cut_min);
-    double rowsum = 0;
-    for (int k = 0; k < cnt; ++k) {
-        const int64_t o = static_cast<int64_t>(k) * n + s;
-        const T r = sqrt(nbw[o]);
-        T w;
-        if (sizeof(T) == 8) {
-            w = static_cast<T>(interp_wd(wtab, n_r, r0, dr, static_cast<double>(r), r_cut_min));
-        } else {
-            const T rr = r < rmin ? rmin : r;
-            const T t = fmax((rr - tr0) * inv_dr, T(0));
-            const T tb = fmin(floor(t), static_cast<T>(n_r - 2));
-            const int b = static_cast<int>(fmax(tb, T(0)));
-            const T f = t - static_cast<T>(b);
-            const T w0 = static_cast<T>(wtab[b]), w1 = static_cast<T>(wtab[b + 1]);
-            w = w0 + f * (w1 - w0);
-        }
-        nbw[o] = w;
-        rowsum += fabs(static_cast<double>(w));
-        if (PAR) {
-            const T inv = T(1) / r;
-            nbe[o] *= inv;
-            nbe[plane + o] *= inv;
-            nbe[2 * plane + o] *= inv;
-        }
-    }
-    if (rowsum > lam_hi) {
-        if (atomicCAS(flags, 0, GLD_ERR_INTERVAL) == 0) *flag_step = *d_step;
-    }
-    atomicMax(rowmax, __float_as_uint(static_cast<float>(rowsum)));
 }
 
 // ---------------------------------------------------------------------------
@@ -474,133 +478,281 @@ __global__ void k_permute(int64_t n, int64_t S, const int *__restrict__ sorted, 
     }
 }
 
+
 // ---------------------------------------------------------------------------
-// pair mat-vec with fused combination, one thread per particle (sorted order):
+// pair mat-vec with fused combination, one work-group per cell:
 //   out_s = a (P x)_s + b x_s + cz z_s + sum_q coef[q] us_q,s   (+ add[p])
-// The k-th neighbour index and weight of 64 consecutive particles are one
-// contiguous segment (column-major lists); x_j is gathered (cell order keeps
-// a wave's neighbourhood in a few tens of KiB, i.e. in L1/L2).  x, z, us are
-// sorted T4; out is sorted T4 or scattered to the original order [3][S]
-// (out_orig), optionally plus add_orig[p].
+// x is staged in LDS for the whole stencil (for the parallel tensor with the
+// positions relative to the home cell, built exactly as in the neighbour
+// build); L lanes per particle walk its chunks sub, sub + L, ... with the
+// next chunk's loads in flight, and the L partial sums meet in LDS.  A
+// stencil larger than the staging capacity is done in rounds, each lane
+// taking the entries that fall into the staged range (the entries of a list
+// ascend, so the summation order is the same).  x, z, us are sorted T4; out
+// is sorted T4 or scattered to the original order [3][S] (out_orig),
+// optionally plus add_orig[p].
 // ---------------------------------------------------------------------------
+template <typename T>
+struct V2;
+template <>
+struct V2<float> {
+    using t = float2;
+};
+template <>
+struct V2<double> {
+    using t = double2;
+};
+
 struct MvArgs {
     int64_t n, S;
-    const int *sorted;
-    const int *nbj;
-    const void *nbw, *nbe;
+    const int *sorted, *cstart;
+    const int2 *stab;
+    int nst;    // stencil entries per cell
+    int maxc;   // staged candidates per round
+    const uint4 *nbl;
+    const void *nbw;
     const int *nn;
-    int cap;
+    const double4 *reld;  // parallel tensor: positions relative to their own cell
+    Geo g;
     double a, b, cz;
     const void *x, *z, *coef, *us, *add_orig;
     int r;
     void *out_sorted, *out_orig;
 };
 
-template <typename T, bool PAR>
-__global__ __launch_bounds__(256) void k_mv(MvArgs A)
+// LDS bytes of one work-group
+template <typename T, bool PAR, int BS>
+constexpr size_t mv_lds_bytes(int maxc)
 {
     using T4 = typename V4<T>::t;
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= A.n) return;
-    const T4 *__restrict__ x = static_cast<const T4 *>(A.x);
-    const int *__restrict__ nbj = A.nbj;
-    const T *__restrict__ nbw = static_cast<const T *>(A.nbw);
-    const T *__restrict__ nbe = static_cast<const T *>(A.nbe);
-    const int64_t n = A.n;
-    T p0 = 0, p1 = 0, p2 = 0;
-    if (A.a != 0.0) {
-        const int cnt = A.nn[s];
-        const int64_t plane = static_cast<int64_t>(A.cap) * n;
-        int k = 0;
-        // four independent gathers in flight per iteration
-        for (; k + 3 < cnt; k += 4) {
-            int j[4];
-            T w[4];
-            T4 v[4];
+    using T2 = typename V2<T>::t;
+    return static_cast<size_t>(maxc > BS ? maxc : BS) * sizeof(T4) + (PAR ? static_cast<size_t>(maxc) * sizeof(T2) : 0);
+}
+
+// one chunk of 8 entries; CHECK: only entries with staged index in [c0, c0 + cn)
+template <typename T, bool PAR, bool CHECK>
+__device__ __forceinline__ void mv_chunk(const typename V4<T>::t *xs, const typename V2<T>::t *pyz, uint4 id,
+                                         const typename V4<T>::t &wa, const typename V4<T>::t &wb, const T (&own)[3],
+                                         const T (&Lb)[3], const bool (&mi)[3], unsigned c0, unsigned cn, T &p0, T &p1,
+                                         T &p2)
+{
+    using T4 = typename V4<T>::t;
+    const unsigned li[8] = {id.x & 0xffffu, id.x >> 16, id.y & 0xffffu, id.y >> 16,
+                            id.z & 0xffffu, id.z >> 16, id.w & 0xffffu, id.w >> 16};
+    const T w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+    if (!CHECK) {
+        T4 v[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t o = static_cast<int64_t>(k + u) * n + s;
-                j[u] = nbj[o];
-                w[u] = nbw[o];
+        for (int u = 0; u < 8; ++u) v[u] = xs[li[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (PAR) {
+                const typename V2<T>::t q = pyz[li[u]];
+                T dx = own[0] - v[u].w, dy = own[1] - q.x, dz = own[2] - q.y;
+                if (mi[0]) dx -= Lb[0] * rint(dx / Lb[0]);
+                if (mi[1]) dy -= Lb[1] * rint(dy / Lb[1]);
+                if (mi[2]) dz -= Lb[2] * rint(dz / Lb[2]);
+                const T sc = w[u] * (dx * v[u].x + dy * v[u].y + dz * v[u].z);
+                p0 += sc * dx;
+                p1 += sc * dy;
+                p2 += sc * dz;
+            } else {
+                p0 += w[u] * v[u].x;
+                p1 += w[u] * v[u].y;
+                p2 += w[u] * v[u].z;
             }
+        }
+    } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = x[j[u]];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (PAR) {
-                    const int64_t o = static_cast<int64_t>(k + u) * n + s;
-                    const T ex = nbe[o], ey = nbe[plane + o], ez = nbe[2 * plane + o];
-                    const T sc = w[u] * (ex * v[u].x + ey * v[u].y + ez * v[u].z);
-                    p0 += sc * ex;
-                    p1 += sc * ey;
-                    p2 += sc * ez;
-                } else {
-                    p0 += w[u] * v[u].x;
-                    p1 += w[u] * v[u].y;
-                    p2 += w[u] * v[u].z;
+        for (int u = 0; u < 8; ++u) {
+            const unsigned l = li[u] - c0;
+            if (l >= cn) continue;
+            const T4 v = xs[l];
+            if (PAR) {
+                const typename V2<T>::t q = pyz[l];
+                T dx = own[0] - v.w, dy = own[1] - q.x, dz = own[2] - q.y;
+                if (mi[0]) dx -= Lb[0] * rint(dx / Lb[0]);
+                if (mi[1]) dy -= Lb[1] * rint(dy / Lb[1]);
+                if (mi[2]) dz -= Lb[2] * rint(dz / Lb[2]);
+                const T sc = w[u] * (dx * v.x + dy * v.y + dz * v.z);
+                p0 += sc * dx;
+                p1 += sc * dy;
+                p2 += sc * dz;
+            } else {
+                p0 += w[u] * v.x;
+                p1 += w[u] * v.y;
+                p2 += w[u] * v.z;
+            }
+        }
+    }
+}
+
+template <typename T, bool PAR, int BS, int L>
+__global__ __launch_bounds__(BS) void k_mv(MvArgs A)
+{
+    using T4 = typename V4<T>::t;
+    using T2 = typename V2<T>::t;
+    constexpr int PG = BS / L;  // particles per round
+    extern __shared__ __align__(32) unsigned char mv_lds[];
+    __shared__ int sst[kStab], sbase[kStab];
+    const int cid = blockIdx.x;
+    const int h0 = A.cstart[cid], occ = A.cstart[cid + 1] - h0;
+    if (occ <= 0) return;
+    const int tid = threadIdx.x;
+    const int nst = A.nst;
+    if (tid <= nst) {
+        const int2 e = A.stab[static_cast<int64_t>(cid) * kStab + tid];
+        sst[tid] = e.x;
+        sbase[tid] = e.y;
+    }
+    T4 *xs = reinterpret_cast<T4 *>(mv_lds);
+    T2 *pyz = reinterpret_cast<T2 *>(mv_lds + static_cast<size_t>(A.maxc > BS ? A.maxc : BS) * sizeof(T4));
+    T4 *part = xs;  // reused once the gathers of a round are done
+    const T4 *__restrict__ x = static_cast<const T4 *>(A.x);
+    const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw);
+    const uint4 *__restrict__ nbl = A.nbl;
+    const int64_t n = A.n;
+    const bool pair = A.a != 0.0;
+    const T Lb[3] = {static_cast<T>(A.g.L[0]), static_cast<T>(A.g.L[1]), static_cast<T>(A.g.L[2])};
+    const bool mi[3] = {A.g.nc[0] < 3, A.g.nc[1] < 3, A.g.nc[2] < 3};
+    __syncthreads();
+    const int total = sbase[nst];
+    bool staged_all = false;
+    for (int g0 = 0; g0 < occ; g0 += PG) {
+        const int m = min(PG, occ - g0);
+        const bool active = tid < m * L;
+        const int sub = active ? tid / m : 0;
+        const int pi = active ? tid - sub * m : 0;
+        const int64_t s = h0 + g0 + pi;
+        const int nch = (active && pair) ? (A.nn[s] + 7) >> 3 : 0;
+        T own[3] = {T(0), T(0), T(0)};
+        if (PAR && active) {
+            const double4 q = A.reld[s];
+            own[0] = static_cast<T>(q.x);
+            own[1] = static_cast<T>(q.y);
+            own[2] = static_cast<T>(q.z);
+        }
+        T p0 = 0, p1 = 0, p2 = 0;
+        if (pair) {
+            for (int c0 = 0; c0 < total; c0 += A.maxc) {
+                const int c1 = min(total, c0 + A.maxc);
+                const bool single = c0 == 0 && c1 == total;
+                if (!(single && staged_all)) {
+                    __syncthreads();
+                    for (int l = c0 + tid; l < c1; l += BS) {
+                        int lo = 0, hi = nst - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (sbase[mid] <= l) lo = mid; else hi = mid - 1;
+                        }
+                        const int t = sst[lo] + (l - sbase[lo]);
+                        T4 v = x[t];
+                        if (PAR) {
+                            const int e0 = lo % A.g.noff[0], e1 = (lo / A.g.noff[0]) % A.g.noff[1];
+                            const int e2 = lo / (A.g.noff[0] * A.g.noff[1]);
+                            const double4 q = A.reld[t];
+                            v.w = static_cast<T>(q.x + A.g.offs[0][e0] * A.g.edge[0]);
+                            T2 yz;
+                            yz.x = static_cast<T>(q.y + A.g.offs[1][e1] * A.g.edge[1]);
+                            yz.y = static_cast<T>(q.z + A.g.offs[2][e2] * A.g.edge[2]);
+                            pyz[l - c0] = yz;
+                        }
+                        xs[l - c0] = v;
+                    }
+                    __syncthreads();
+                    staged_all = single;
+                }
+                // this lane's chunks, the next one's loads in flight
+                uint4 id = make_uint4(0, 0, 0, 0);
+                T4 wa{}, wb{};
+                if (sub < nch) {
+                    id = nbl[sub * n + s];
+                    wa = nbw4[(2 * sub) * n + s];
+                    wb = nbw4[(2 * sub + 1) * n + s];
+                }
+                for (int ch = sub; ch < nch; ch += L) {
+                    const uint4 cid8 = id;
+                    const T4 cwa = wa, cwb = wb;
+                    if (ch + L < nch) {
+                        const int nx = ch + L;
+                        id = nbl[nx * n + s];
+                        wa = nbw4[(2 * nx) * n + s];
+                        wb = nbw4[(2 * nx + 1) * n + s];
+                    }
+                    if (single) mv_chunk<T, PAR, false>(xs, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1, p2);
+                    else
+                        mv_chunk<T, PAR, true>(xs, pyz, cid8, cwa, cwb, own, Lb, mi, static_cast<unsigned>(c0),
+                                               static_cast<unsigned>(c1 - c0), p0, p1, p2);
                 }
             }
         }
-        for (; k < cnt; ++k) {
-            const int64_t o = static_cast<int64_t>(k) * n + s;
-            const T w = nbw[o];
-            const T4 v = x[nbj[o]];
-            if (PAR) {
-                const T ex = nbe[o], ey = nbe[plane + o], ez = nbe[2 * plane + o];
-                const T sc = w * (ex * v.x + ey * v.y + ez * v.z);
-                p0 += sc * ex;
-                p1 += sc * ey;
-                p2 += sc * ez;
+        // the L partial sums of each particle meet in LDS
+        __syncthreads();
+        if (active) {
+            T4 q;
+            q.x = p0;
+            q.y = p1;
+            q.z = p2;
+            q.w = T(0);
+            part[sub * PG + pi] = q;
+        }
+        __syncthreads();
+        staged_all = false;
+        if (tid < m) {
+            T q0 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+            for (int u = 0; u < L; ++u) {
+                const T4 q = part[u * PG + tid];
+                q0 += q.x;
+                q1 += q.y;
+                q2 += q.z;
+            }
+            const int64_t so = h0 + g0 + tid;
+            T o0 = static_cast<T>(A.a) * q0, o1 = static_cast<T>(A.a) * q1, o2 = static_cast<T>(A.a) * q2;
+            if (A.b != 0.0) {
+                const T4 xv = x[so];
+                o0 += static_cast<T>(A.b) * xv.x;
+                o1 += static_cast<T>(A.b) * xv.y;
+                o2 += static_cast<T>(A.b) * xv.z;
+            }
+            if (A.cz != 0.0) {
+                const T4 zs = static_cast<const T4 *>(A.z)[so];
+                o0 += static_cast<T>(A.cz) * zs.x;
+                o1 += static_cast<T>(A.cz) * zs.y;
+                o2 += static_cast<T>(A.cz) * zs.z;
+            }
+            if (A.r > 0) {
+                const T *coef = static_cast<const T *>(A.coef);
+                const T4 *us = static_cast<const T4 *>(A.us);
+                for (int qi = 0; qi < A.r; ++qi) {
+                    const T c = coef[qi];
+                    const T4 u = us[static_cast<int64_t>(qi) * A.S + so];
+                    o0 += c * u.x;
+                    o1 += c * u.y;
+                    o2 += c * u.z;
+                }
+            }
+            if (A.out_sorted) {
+                T4 o;
+                o.x = o0;
+                o.y = o1;
+                o.z = o2;
+                o.w = T(0);
+                static_cast<T4 *>(A.out_sorted)[so] = o;
             } else {
-                p0 += w * v.x;
-                p1 += w * v.y;
-                p2 += w * v.z;
+                const int p = A.sorted[so];
+                T *out = static_cast<T *>(A.out_orig);
+                if (A.add_orig) {
+                    const T *ad = static_cast<const T *>(A.add_orig);
+                    o0 += ad[p];
+                    o1 += ad[A.S + p];
+                    o2 += ad[2 * A.S + p];
+                }
+                out[p] = o0;
+                out[A.S + p] = o1;
+                out[2 * A.S + p] = o2;
             }
         }
-    }
-    T o0 = static_cast<T>(A.a) * p0, o1 = static_cast<T>(A.a) * p1, o2 = static_cast<T>(A.a) * p2;
-    if (A.b != 0.0) {
-        const T4 xs = x[s];
-        o0 += static_cast<T>(A.b) * xs.x;
-        o1 += static_cast<T>(A.b) * xs.y;
-        o2 += static_cast<T>(A.b) * xs.z;
-    }
-    if (A.cz != 0.0) {
-        const T4 zs = static_cast<const T4 *>(A.z)[s];
-        o0 += static_cast<T>(A.cz) * zs.x;
-        o1 += static_cast<T>(A.cz) * zs.y;
-        o2 += static_cast<T>(A.cz) * zs.z;
-    }
-    if (A.r > 0) {
-        const T *coef = static_cast<const T *>(A.coef);
-        const T4 *us = static_cast<const T4 *>(A.us);
-        for (int q = 0; q < A.r; ++q) {
-            const T c = coef[q];
-            const T4 u = us[static_cast<int64_t>(q) * A.S + s];
-            o0 += c * u.x;
-            o1 += c * u.y;
-            o2 += c * u.z;
-        }
-    }
-    if (A.out_sorted) {
-        T4 o;
-        o.x = o0;
-        o.y = o1;
-        o.z = o2;
-        o.w = T(0);
-        static_cast<T4 *>(A.out_sorted)[s] = o;
-    } else {
-        const int p = A.sorted[s];
-        T *out = static_cast<T *>(A.out_orig);
-        if (A.add_orig) {
-            const T *ad = static_cast<const T *>(A.add_orig);
-            o0 += ad[p];
-            o1 += ad[A.S + p];
-            o2 += ad[2 * A.S + p];
-        }
-        out[p] = o0;
-        out[A.S + p] = o1;
-        out[2 * A.S + p] = o2;
     }
 }
 
@@ -617,7 +769,34 @@ Geo make_geo(const Dev &d)
     return g;
 }
 
+// launch shapes of the mat-vec: lanes per work-group, lanes per particle
+constexpr int kMvThreads32 = 512, kMvLanes32 = 4;
+constexpr int kMvThreads64 = 512, kMvLanes64 = 4;
+
+template <typename T, bool PAR, int BS, int L>
+hipError_t launch_mv_t(const Dev &d, const MvArgs &A, hipStream_t st)
+{
+    const size_t shm = mv_lds_bytes<T, PAR, BS>(d.maxc);
+    if (shm > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mv<T, PAR, BS, L>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
+        if (e != hipSuccess) return e;
+    }
+    k_mv<T, PAR, BS, L><<<d.ncell, BS, shm, st>>>(A);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+// largest staging capacity (candidates) that fits one work-group's LDS
+int mv_max_staging(int fp64, int parallel)
+{
+    const size_t budget = 160 * 1024 - 1024;
+    size_t per;
+    if (fp64) per = parallel ? sizeof(double4) + sizeof(double2) : sizeof(double4);
+    else per = parallel ? sizeof(float4) + sizeof(float2) : sizeof(float4);
+    return static_cast<int>(budget / per);
+}
 
 // ===========================================================================
 // launchers
@@ -643,48 +822,40 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
                                                    static_cast<float4 *>(d.relf), static_cast<double4 *>(d.reld));
     BuildArgs a{};
     a.g = g;
+    a.ncell = d.ncell;
     a.n = d.n;
     a.S = d.S;
     a.cstart = d.cell_start;
     a.sorted = d.cell_sorted;
     a.reld_src = static_cast<const double4 *>(d.reld);
-    a.exact64 = d.fp64;
-    a.parallel = d.parallel;
+    a.pos_s = static_cast<const double4 *>(d.pos_s);
     a.rc2 = d.r_cut * d.r_cut;
     a.cap = d.cap;
+    a.wtab = d.wtab;
+    a.n_r = d.n_r;
+    a.r0 = d.r0;
+    a.dr = d.dr;
+    a.r_cut_min = d.r_cut_min;
+    a.lam_hi = d.lam_hi;
     const double rw = std::pow(2.0, 1.0 / 6.0) * d.wca_sigma;
     a.wca_rc2 = d.wca_eps != 0.0 ? rw * rw : 0.0;
     a.wca_s2 = d.wca_sigma * d.wca_sigma;
     a.wca_eps = d.wca_eps;
-    a.nbj = d.nbj;
+    a.nbl = static_cast<uint16_t *>(d.nbl);
     a.nbw = d.nbw;
-    a.nbe = d.nbe;
     a.nn = d.nn;
+    a.stab = static_cast<int2 *>(d.stab);
     a.fc = fc_out;
+    a.rowmax = d.d_rowmax;
     a.flags = d.d_flags;
     a.flag_step = d.d_flag_step;
     a.d_step = d.d_step;
-    if (d.fp64) k_build<double><<<d.ncell, kPairThreads, 0, st>>>(a);
-    else k_build<float><<<d.ncell, kPairThreads, 0, st>>>(a);
-    const unsigned nb = blocks(d.n, 256);
     if (d.fp64) {
-        if (d.parallel)
-            k_weights<double, true><<<nb, 256, 0, st>>>(d.n, d.cap, d.nn, (double *)d.nbw, (double *)d.nbe, d.wtab,
-                                                        d.n_r, d.r0, d.dr, d.r_cut_min, d.lam_hi, d.d_rowmax,
-                                                        d.d_flags, d.d_flag_step, d.d_step);
-        else
-            k_weights<double, false><<<nb, 256, 0, st>>>(d.n, d.cap, d.nn, (double *)d.nbw, nullptr, d.wtab, d.n_r,
-                                                         d.r0, d.dr, d.r_cut_min, d.lam_hi, d.d_rowmax, d.d_flags,
-                                                         d.d_flag_step, d.d_step);
+        if (d.parallel) k_build<double, true, true><<<d.ncell, kPairThreads, 0, st>>>(a);
+        else k_build<double, true, false><<<d.ncell, kPairThreads, 0, st>>>(a);
     } else {
-        if (d.parallel)
-            k_weights<float, true><<<nb, 256, 0, st>>>(d.n, d.cap, d.nn, (float *)d.nbw, (float *)d.nbe, d.wtab,
-                                                       d.n_r, d.r0, d.dr, d.r_cut_min, d.lam_hi, d.d_rowmax,
-                                                       d.d_flags, d.d_flag_step, d.d_step);
-        else
-            k_weights<float, false><<<nb, 256, 0, st>>>(d.n, d.cap, d.nn, (float *)d.nbw, nullptr, d.wtab, d.n_r,
-                                                        d.r0, d.dr, d.r_cut_min, d.lam_hi, d.d_rowmax, d.d_flags,
-                                                        d.d_flag_step, d.d_step);
+        if (d.parallel) k_build<float, false, true><<<d.ncell, kPairThreads, 0, st>>>(a);
+        else k_build<float, false, false><<<d.ncell, kPairThreads, 0, st>>>(a);
     }
     return hipGetLastError();
 }
@@ -711,11 +882,15 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
     A.n = d.n;
     A.S = d.S;
     A.sorted = d.cell_sorted;
-    A.nbj = d.nbj;
+    A.cstart = d.cell_start;
+    A.stab = static_cast<const int2 *>(d.stab);
+    A.nst = d.noff[0] * d.noff[1] * d.noff[2];
+    A.maxc = d.maxc;
+    A.nbl = static_cast<const uint4 *>(d.nbl);
     A.nbw = d.nbw;
-    A.nbe = d.nbe;
     A.nn = d.nn;
-    A.cap = d.cap;
+    A.reld = static_cast<const double4 *>(d.reld);
+    A.g = make_geo(d);
     A.a = d.has_pair ? a : 0.0;
     A.b = b;
     A.cz = cz;
@@ -727,15 +902,12 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
     A.r = coef ? r : 0;
     A.out_sorted = out_sorted;
     A.out_orig = out_orig;
-    const unsigned nb = blocks(d.n, 256);
     if (d.fp64) {
-        if (d.parallel) k_mv<double, true><<<nb, 256, 0, st>>>(A);
-        else k_mv<double, false><<<nb, 256, 0, st>>>(A);
-    } else {
-        if (d.parallel) k_mv<float, true><<<nb, 256, 0, st>>>(A);
-        else k_mv<float, false><<<nb, 256, 0, st>>>(A);
+        if (d.parallel) return launch_mv_t<double, true, kMvThreads64, kMvLanes64>(d, A, st);
+        return launch_mv_t<double, false, kMvThreads64, kMvLanes64>(d, A, st);
     }
-    return hipGetLastError();
+    if (d.parallel) return launch_mv_t<float, true, kMvThreads32, kMvLanes32>(d, A, st);
+    return launch_mv_t<float, false, kMvThreads32, kMvLanes32>(d, A, st);
 }
 
 hipError_t launch_dissipative(const Dev &d, hipStream_t st)

@@ -94,6 +94,22 @@ class Workload:
         return R, V
 
 
+def slab_state(w: Workload, frac: float):
+    """All particles in the slab z < frac L (density rho / frac there, empty
+    elsewhere): a simple lattice of n_xy x n_xy x n_z sites filled in order,
+    jittered +-0.1; Maxwell velocities as in Workload.initial_state."""
+    rng = np.random.default_rng(w.seed + 7)
+    L = w.box
+    nxy = int(math.ceil((w.n / frac) ** (1.0 / 3.0) - 1e-9))
+    nz = int(math.ceil(w.n / (nxy * nxy)))
+    idx = np.arange(w.n)
+    R = np.stack([(idx % nxy) * (L / nxy), ((idx // nxy) % nxy) * (L / nxy),
+                  (idx // (nxy * nxy)) * (frac * L / nz)], axis=1)
+    R += rng.uniform(-0.1, 0.1, size=(w.n, 3))
+    V = rng.normal(0.0, math.sqrt(w.kT / w.mass), size=(w.n, 3))
+    return R, V
+
+
 def config(k: int, **over) -> Workload:
     """The synthetic configurations (1-based, as listed in the benchmark set).
 

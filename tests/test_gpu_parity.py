@@ -64,14 +64,16 @@ def assert_close(name, a, b, tol, atol=0.0):
     assert np.all(d <= 10 * tol * rms + atol), f"{name}: element error {emax:.3e} > {10 * tol:.1e} (x rms)"
 
 
-def one_step(pkg, oracle_mod, w, fp64, step=5, hist_scale=0.01, seed=11, check_fc=True, **kw):
+def one_step(pkg, oracle_mod, w, fp64, step=5, hist_scale=0.01, seed=11, check_fc=True, state=None, **kw):
     tables = kw.pop("tables", None)
     rng = np.random.default_rng(seed)
-    R, V = w.initial_state()
+    R, V = w.initial_state() if state is None else state
     hist = wl.random_history(rng, w.m_max, w.n, scale=hist_scale)
     if fp64:
         kw.setdefault("noise_tol", 1e-13)
     log(f"  one_step {w.name} n={w.n} m_max={w.m_max} fp64={fp64} parallel={w.parallel} kw={kw}")
+    if state is not None:
+        kw.update(r=R, v=V)  # the noise interval is set up for this configuration
     s = pkg.System.from_workload(w, fp64=fp64, **kw)
     s.write_state(R, V, step=step, history=hist)
     FC0 = s.read_state()["f_c"]
@@ -152,6 +154,16 @@ def test_one_step_dense_small_box(pkg, oracle_mod, fp64):
     # large benchmark at a size the oracle's Algorithm 1 finishes quickly
     w = wl.config(3, n=1200, m_max=60)
     one_step(pkg, oracle_mod, w, fp64, step=9)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("parallel", [False, True])
+def test_one_step_crowded_cells(pkg, oracle_mod, fp64, parallel):
+    # every particle in half of the box: the occupied cells hold about 1.6x
+    # the mean, so the mat-vec stages their stencils in two rounds and takes
+    # their particles in two groups
+    w = wl.config(2, n=5000, rho=0.05, m_max=60, parallel=parallel)
+    one_step(pkg, oracle_mod, w, fp64, step=4, state=wl.slab_state(w, 0.5))
 
 
 @pytest.mark.parametrize("fp64", [True, False])
