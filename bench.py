@@ -65,6 +65,8 @@ def run_gpu(args, fp64):
     t_create = time.perf_counter() - t0
     info = s.noise_info()
     log(f"[bench] created in {t_create:.1f}s, noise {info}")
+    if args.no_graph:
+        s.set_graph(False)
     # warmup
     s.step(args.warmup)
     s.sync()
@@ -100,6 +102,34 @@ def run_gpu(args, fp64):
                 status=st["status"])
 
 
+def measured_traffic(workload, kind, fp64):
+    """Calibrated HBM bytes per launch of a kernel class from the committed
+    rocprofv3 counter summary of this workload (profiles/*_traffic.json), or
+    None when there is none or the kernel sources changed since it was taken."""
+    import glob
+    from paper_1808_00270_amd.profile_summary import source_hash
+    cls = {"neighbor": "neighbor_build"}.get(kind, kind)
+    tag = "fp64" if fp64 else "fp32"
+    h = source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json"))):
+        with open(path) as f:
+            d = json.load(f)
+        if workload not in d.get("name", "") or not d["name"].endswith(tag):
+            continue
+        if d.get("source_sha256") != h:
+            continue
+        k = d.get("kernels", {}).get(cls)
+        if k:
+            return k["traffic_bytes"]
+    return None
+
+
+def pct(lat):
+    if not lat:
+        return None
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+
+
 def roofline_entry(res, kind, fp64, kernel_steps):
     w, info = res["w"], res["info"]
     ms, cnt = res["kt"][kind]
@@ -119,7 +149,7 @@ def roofline_entry(res, kind, fp64, kernel_steps):
     b = alg["bytes"]
     ach = b / (avg * 1e-3) / 1e9
     return dict(kernel=kind, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                traffic=None, avg_ms=avg, launches=cnt, bytes_per_launch=b)
+                traffic=measured_traffic(w.name, kind, fp64), avg_ms=avg, launches=cnt, bytes_per_launch=b)
 
 
 def cpu_baseline(args):
@@ -165,6 +195,10 @@ def main():
     ap.add_argument("--cpu-freqs", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly (counter runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the runs, negate this many MiB of float32 once: a kernel of known HBM "
+                         "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this GLD build runs one system on one GPU; multi-GPU runs are not supported "
@@ -178,6 +212,15 @@ def main():
 
     r32 = run_gpu(args, fp64=False)
     r64 = None if args.no_fp64 else run_gpu(args, fp64=True)
+    if args.calib_copy_mib > 0:
+        nf = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(nf, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration: negated {nf * 4} bytes (read {nf * 4}, write {nf * 4})")
+        del a, b
     w = r32["w"]
     value = w.n * 1e3 / r32["ms_per_step"]
     per_step = {k: ms / args.kernel_steps for k, (ms, c) in r32["kt"].items()}
@@ -199,7 +242,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "rho": w.rho, "m_max": w.m_max, "r_cut": w.r_cut, "dt": w.dt,
                    "precision": "fp32-mixed (f32 history/noise, f64 positions and update)"},
-        "latency_ms": {"p50": float(np.percentile(r32["lat"], 50)), "p99": float(np.percentile(r32["lat"], 99))},
+        "latency_ms": pct(r32["lat"]),
         "noise": {k: r32["info"][k] for k in ("cheb_terms", "rank", "block", "err_estimate")},
         "kernels_ms_per_step": per_step,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | {"kernel": dom},
@@ -208,7 +251,7 @@ def main():
     if r64 is not None:
         out["fp64_plain"] = {
             "value": w.n * 1e3 / r64["ms_per_step"], "ms_per_step": r64["ms_per_step"],
-            "latency_ms": {"p50": float(np.percentile(r64["lat"], 50)), "p99": float(np.percentile(r64["lat"], 99))},
+            "latency_ms": pct(r64["lat"]),
             "noise": {k: r64["info"][k] for k in ("cheb_terms", "rank", "block", "err_estimate")},
             "kernels_ms_per_step": {k: ms / args.kernel_steps for k, (ms, c) in r64["kt"].items()},
             "roofline_history": roofline_entry(r64, "history", True, args.kernel_steps),

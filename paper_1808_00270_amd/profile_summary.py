@@ -1,0 +1,164 @@
+"""Text summaries of rocprofv3 runs of bench.py, for the profiles/ folder.
+
+Inputs are the rocpd databases rocprofv3 writes: one kernel-trace run with
+--stats, and one --pmc run per HBM counter (FETCH_SIZE, then WRITE_SIZE), each
+of a bench.py run that ends with the calibration kernel (--calib-copy-mib):
+an elementwise negation that reads and writes a float32 buffer of known size
+once.  The counters of that kernel against its true bytes give the scale of
+each counter on the device; the kernels of the GLD step are then reported in
+calibrated HBM bytes per launch.
+
+Writes
+  profiles/<name>.md            the kernel table and the traffic table, with
+                                the commands that produced them
+  profiles/<name>_traffic.json  per kernel class: calibrated bytes read and
+                                written per launch, and the hash of the kernel
+                                sources they were measured on (bench.py
+                                reports the traffic only while it matches)
+
+usage: python -m paper_1808_00270_amd.profile_summary --name NAME --kt DIR
+       [--fetch DIR --write DIR --calib-bytes B] --cmd-kt "..." [--cmd-fetch
+       "..." --cmd-write "..."] [--note "..."]
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import glob
+import hashlib
+import json
+import os
+import re
+import sqlite3
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SOURCES = ["gld_api.cpp", "gld_noise_plan.cpp", "gld_kernels.hip", "gld_pairs.hip", "gld_internal.h"]
+
+# kernel classes of the step (the names bench.py uses) -> kernel symbol
+CLASSES = {
+    "noise_spmv": r"k_mv<",
+    "history": r"k_history<",
+    "noise_fir": r"k_fir<",
+    "neighbor_build": r"k_build<",
+    "update": r"k_update_[rv]",
+}
+CALIB = r"neg"
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for s in SOURCES:
+        with open(os.path.join(HERE, "csrc", s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def short(name: str) -> str:
+    m = re.search(r"(k_\w+)(<[^>(]*>)?", name)
+    if m:
+        return m.group(1) + (m.group(2) or "")
+    return name if len(name) <= 60 else name[:57] + "..."
+
+
+def db(path: str) -> sqlite3.Connection:
+    files = glob.glob(os.path.join(path, "**", "*_results.db"), recursive=True)
+    if not files:
+        raise SystemExit(f"no rocpd database under {path}")
+    return sqlite3.connect(files[0])
+
+
+def kernel_table(path: str):
+    c = db(path)
+    return c.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+
+
+def counter_means(path: str, counter: str):
+    """Mean counter value (KiB) per dispatch, by kernel name."""
+    c = db(path)
+    rows = c.execute("select dispatch_id, kernel_name, sum(value) from counters_collection "
+                     "where counter_name = ? group by dispatch_id", (counter,)).fetchall()
+    acc = collections.defaultdict(list)
+    for _, name, v in rows:
+        acc[name].append(v)
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def pick(table: dict, pattern: str):
+    hits = [(k, v) for k, v in table.items() if re.search(pattern, k)]
+    if not hits:
+        return None
+    if len(hits) == 1:
+        return hits[0][1]
+    # several instantiations: dispatch-weighted mean
+    tot = sum(v[1] for _, v in hits)
+    return (sum(v[0] * v[1] for _, v in hits) / tot, tot)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--kt", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--calib-bytes", type=float, default=0.0)
+    ap.add_argument("--cmd-kt", required=True)
+    ap.add_argument("--cmd-fetch", default="")
+    ap.add_argument("--cmd-write", default="")
+    ap.add_argument("--note", default="")
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    a = ap.parse_args()
+
+    lines = [f"# {a.name}", ""]
+    if a.note:
+        lines += [a.note, ""]
+    lines += ["Kernel trace:", "", "    " + a.cmd_kt, "",
+              "| kernel | calls | avg (us) | total (ms) | % |", "|---|---:|---:|---:|---:|"]
+    kt = kernel_table(a.kt)
+    for name, calls, total, avg, pctg in kt[:16]:
+        lines.append(f"| `{short(name)}` | {calls} | {avg:.1f} | {total / 1e3:.2f} | {pctg:.1f} |")
+    avg_by_class = {}
+    for cls, pat in CLASSES.items():
+        sel = [(calls, total) for name, calls, total, _, _ in kt if re.search(pat, name)]
+        if sel:
+            calls = sum(c for c, _ in sel)
+            avg_by_class[cls] = sum(t for _, t in sel) / calls
+    out = {"name": a.name, "source_sha256": source_hash(), "avg_us": avg_by_class, "kernels": {}}
+
+    if a.fetch and a.write and a.calib_bytes > 0:
+        fe = counter_means(a.fetch, "FETCH_SIZE")
+        wr = counter_means(a.write, "WRITE_SIZE")
+        cf, cw = pick(fe, CALIB), pick(wr, CALIB)
+        if cf is None or cw is None:
+            raise SystemExit("calibration kernel not found in the counter runs")
+        sf = cf[0] * 1024.0 / a.calib_bytes  # counter bytes per true byte
+        sw = cw[0] * 1024.0 / a.calib_bytes
+        out["calibration"] = {"bytes": a.calib_bytes, "fetch_kib": cf[0], "write_kib": cw[0],
+                              "fetch_scale": sf, "write_scale": sw}
+        lines += ["", "HBM traffic per launch (FETCH_SIZE and WRITE_SIZE, one counter per run):", "",
+                  "    " + a.cmd_fetch, "    " + a.cmd_write, "",
+                  f"Calibration: negation of {a.calib_bytes / 2**20:.0f} MiB float32 (reads and writes "
+                  f"{a.calib_bytes:.0f} B): FETCH_SIZE {cf[0]:.0f} KiB (scale {sf:.4f}), "
+                  f"WRITE_SIZE {cw[0]:.0f} KiB (scale {sw:.4f}).", "",
+                  "| kernel | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | read (MB) | written (MB) |",
+                  "|---|---:|---:|---:|---:|---:|"]
+        for cls, pat in CLASSES.items():
+            f, w = pick(fe, pat), pick(wr, pat)
+            if f is None or w is None:
+                continue
+            rb, wb = f[0] * 1024.0 / sf, w[0] * 1024.0 / sw
+            out["kernels"][cls] = {"read_bytes": rb, "write_bytes": wb, "traffic_bytes": rb + wb,
+                                   "dispatches": f[1]}
+            lines.append(f"| {cls} (`{pat.rstrip('<')}`) | {f[1]} | {f[0]:.0f} | {w[0]:.0f} | {rb / 1e6:.1f} | "
+                         f"{wb / 1e6:.1f} |")
+    lines += ["", f"Kernel sources (sha256 over csrc): `{out['source_sha256'][:16]}`", ""]
+    os.makedirs(a.out, exist_ok=True)
+    with open(os.path.join(a.out, a.name + ".md"), "w") as f:
+        f.write("\n".join(lines))
+    with open(os.path.join(a.out, a.name + "_traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
