@@ -58,6 +58,10 @@ typedef enum {
 
 typedef enum { GLD_FP64 = 0, GLD_FP32_MIXED = 1 } gld_precision;
 
+/* Largest distance grid of the pair weight w(r): the neighbour build keeps
+ * the whole table in LDS. */
+#define GLD_MAX_DISTANCE_BINS 1024
+
 /* Tensor structure of the pair memory (Sec. II.A): isotropic K^p 1, or only
  * the component parallel to the line of centres, K^p e e^T. */
 typedef enum { GLD_PAIR_ISOTROPIC = 0, GLD_PAIR_PARALLEL = 1 } gld_pair_tensor;
@@ -74,7 +78,7 @@ typedef struct {
     double mass;               /* particle mass M                                    */
     double kT;                 /* k_B T (0 switches the random force off)             */
     int32_t m_max;             /* memory length: lags m = 0..m_max-1, 1..4096        */
-    int32_t n_r;               /* distance grid points, >= 2                         */
+    int32_t n_r;               /* distance grid points, 2..GLD_MAX_DISTANCE_BINS     */
     const double *k_self;      /* [m_max]  K^s_m                                     */
     const double *k_pair_g;    /* [m_max]  g_m (NULL: no pair memory)                */
     const double *k_pair_w;    /* [n_r]    w(r_b) (NULL: no pair memory)             */

@@ -60,7 +60,8 @@ gld_status validate(const gld_params *p)
     if (!p) return fail(GLD_ERR_INVALID_ARG, "params is NULL");
     if (p->n < 1 || p->n > (int64_t(1) << 30)) return fail(GLD_ERR_INVALID_ARG, "n must be in [1, 2^30]");
     if (p->m_max < 1 || p->m_max > 4096) return fail(GLD_ERR_INVALID_ARG, "m_max must be in [1, 4096]");
-    if (p->n_r < 2) return fail(GLD_ERR_INVALID_ARG, "n_r must be >= 2");
+    if (p->n_r < 2 || p->n_r > GLD_MAX_DISTANCE_BINS)
+        return fail(GLD_ERR_INVALID_ARG, "n_r must be in [2, GLD_MAX_DISTANCE_BINS]");
     if (!(p->dt > 0) || !(p->mass > 0) || !(p->kT >= 0) || !std::isfinite(p->kT))
         return fail(GLD_ERR_INVALID_ARG, "dt, mass must be > 0 and kT >= 0");
     if (!p->k_self || !finite_all(p->k_self, p->m_max)) return fail(GLD_ERR_INVALID_ARG, "k_self missing or not finite");

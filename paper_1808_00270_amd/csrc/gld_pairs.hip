@@ -262,52 +262,140 @@ struct BuildArgs {
     const long long *d_step;
 };
 
-__device__ __forceinline__ double interp_wd(const double *wt, int n_r, double r0, double dr, double r, double rmin)
-{
-    if (r < rmin) r = rmin;
-    const double t = fmax((r - r0) / dr, 0.0);
-    const double tb = fmin(floor(t), static_cast<double>(n_r - 2));
-    const int b = static_cast<int>(fmax(tb, 0.0));
-    const double f = t - b;
-    return wt[b] * (1.0 - f) + wt[b + 1] * f;
-}
-
-// w(r): linear interpolation on the distance grid, frozen below r_cut_min
+// w(r): linear interpolation on the distance grid, frozen below r_cut_min;
+// tab is the table in the work precision (FP32 entries are the FP64 ones
+// rounded), staged in LDS
 template <typename T>
-__device__ __forceinline__ T weight_of(const BuildArgs &a, T r)
+__device__ __forceinline__ T weight_of(const BuildArgs &a, const T *tab, T r)
 {
-    if (sizeof(T) == 8) return static_cast<T>(interp_wd(a.wtab, a.n_r, a.r0, a.dr, static_cast<double>(r), a.r_cut_min));
+    if (sizeof(T) == 8) {
+        double rr = static_cast<double>(r);
+        if (rr < a.r_cut_min) rr = a.r_cut_min;
+        const double t = fmax((rr - a.r0) / a.dr, 0.0);
+        const double tb = fmin(floor(t), static_cast<double>(a.n_r - 2));
+        const int b = static_cast<int>(fmax(tb, 0.0));
+        const double f = t - b;
+        return static_cast<T>(static_cast<double>(tab[b]) * (1.0 - f) + static_cast<double>(tab[b + 1]) * f);
+    }
     const T rmin = static_cast<T>(a.r_cut_min);
     const T rr = r < rmin ? rmin : r;
     const T t = fmax((rr - static_cast<T>(a.r0)) * static_cast<T>(1.0 / a.dr), T(0));
     const T tb = fmin(floor(t), static_cast<T>(a.n_r - 2));
     const int b = static_cast<int>(fmax(tb, T(0)));
     const T f = t - static_cast<T>(b);
-    const T w0 = static_cast<T>(a.wtab[b]), w1 = static_cast<T>(a.wtab[b + 1]);
+    const T w0 = tab[b], w1 = tab[b + 1];
     return w0 + f * (w1 - w0);
 }
 
 // ---------------------------------------------------------------------------
-// neighbour build: one work-group per cell.  Candidates are staged in LDS
-// (positions relative to the home cell, periodic images applied, as float or
-// double); the wave walks them in lockstep (broadcast reads, no memory
-// traffic in the loop).  The pair decision is taken in FP64 in the FP64 mode
+// neighbour build: one work-group per cell, one lane per particle.
+// Candidates are staged in LDS in chunks (positions relative to the home
+// cell, periodic images applied, as float or double).  The wave walks them in
+// lockstep with broadcast reads and only tests the distance, appending the
+// staged index of each hit to the lane's queue in LDS; the queues are then
+// drained with every lane busy (weight, row sum, WCA force, list entry), and
+// list entries leave in whole 8-entry chunks from registers, so every store
+// is a 16-byte vector.  The pair decision is taken in FP64 in the FP64 mode
 // and in FP32 otherwise (a pair within rounding of r_c has w ~ 0 either way);
 // the WCA force is FP64 from the wrapped positions.  Per particle it writes
-// the lists above, nn[s], fc[p], and checks the row sum of |w| (a bound on
-// the spectral norm of P, ||T_ij|| = 1 for both tensor forms) against the
-// top of the noise interval.
+// the lists above, nn[s], fc[p], and checks the row sum of |w| (a bound on the
+// spectral norm of P, ||T_ij|| = 1 for both tensor forms) against the top of
+// the noise interval.
 // ---------------------------------------------------------------------------
-template <typename T, bool EXACT64, bool PAR>
+constexpr int kQueue = 48;                     // queued hits per lane
+constexpr int kCheckBlock = 16;                // candidates tested between queue checks
+constexpr int kDrainAt = kQueue - kCheckBlock;  // a queue this long is drained
+
+// one list chunk being filled: 8 staged indices (16 bits each) and 8 weights,
+// kept in scalars so that it stays in registers
+template <typename T>
+struct Chunk {
+    uint32_t i0 = 0, i1 = 0, i2 = 0, i3 = 0;
+    T w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, w6 = 0, w7 = 0;
+    __device__ static __forceinline__ uint32_t ins(uint32_t word, int pos, int k, uint32_t l)
+    {
+        if ((pos >> 1) != k) return word;
+        return (pos & 1) ? ((word & 0xffffu) | (l << 16)) : ((word & 0xffff0000u) | l);
+    }
+    __device__ __forceinline__ void put(int pos, uint32_t l, T w)
+    {
+        i0 = ins(i0, pos, 0, l);
+        i1 = ins(i1, pos, 1, l);
+        i2 = ins(i2, pos, 2, l);
+        i3 = ins(i3, pos, 3, l);
+        w0 = pos == 0 ? w : w0;
+        w1 = pos == 1 ? w : w1;
+        w2 = pos == 2 ? w : w2;
+        w3 = pos == 3 ? w : w3;
+        w4 = pos == 4 ? w : w4;
+        w5 = pos == 5 ? w : w5;
+        w6 = pos == 6 ? w : w6;
+        w7 = pos == 7 ? w : w7;
+    }
+    __device__ __forceinline__ void store(uint16_t *nbl, void *nbw, int chunk, int64_t s, int64_t n) const
+    {
+        using T4 = typename V4<T>::t;
+        reinterpret_cast<uint4 *>(nbl)[chunk * n + s] = make_uint4(i0, i1, i2, i3);
+        T4 a, b;
+        a.x = w0;
+        a.y = w1;
+        a.z = w2;
+        a.w = w3;
+        b.x = w4;
+        b.y = w5;
+        b.z = w6;
+        b.w = w7;
+        T4 *nbw4 = static_cast<T4 *>(nbw);
+        nbw4[(2 * chunk) * n + s] = a;
+        nbw4[(2 * chunk + 1) * n + s] = b;
+    }
+};
+
+// squared distance from the home particle to the staged candidate li, in the
+// precision of the pair decision (FP64 data in the FP64 mode, FP32 otherwise);
+// MI: some axis has fewer than 3 cells, so the minimum image is taken there
+template <typename T, bool EXACT64, bool MI>
+__device__ __forceinline__ T staged_r2(const double4 *reld, const float4 *relf, int li, const double4 &xd,
+                                       const float (&xf)[3], const Geo &g, const bool (&mi)[3], const float (&Lf)[3])
+{
+    if (EXACT64) {
+        const double4 q = reld[li];
+        double ux = xd.x - q.x, uy = xd.y - q.y, uz = xd.z - q.z;
+        if (MI && mi[0]) ux -= g.L[0] * rint(ux / g.L[0]);
+        if (MI && mi[1]) uy -= g.L[1] * rint(uy / g.L[1]);
+        if (MI && mi[2]) uz -= g.L[2] * rint(uz / g.L[2]);
+        return static_cast<T>(ux * ux + uy * uy + uz * uz);
+    } else {
+        const float4 q = relf[li];
+        float ux = xf[0] - q.x, uy = xf[1] - q.y, uz = xf[2] - q.z;
+        if (MI && mi[0]) ux -= Lf[0] * rintf(ux / Lf[0]);
+        if (MI && mi[1]) uy -= Lf[1] * rintf(uy / Lf[1]);
+        if (MI && mi[2]) uz -= Lf[2] * rintf(uz / Lf[2]);
+        return static_cast<T>(ux * ux + uy * uy + uz * uz);
+    }
+}
+
+template <typename T, bool EXACT64, bool PAR, bool MI>
 __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
 {
-    constexpr int CH = kBuildChunk;
+    constexpr int CH = EXACT64 ? kBuildChunk / 2 : kBuildChunk;
     __shared__ Stencil st;
-    __shared__ float4 relf[EXACT64 ? 1 : CH];
-    __shared__ double4 reld[EXACT64 ? CH : 1];
+    // staged candidates; entries past the end of the stencil hold NaN
+    // positions, which never pass the distance test
+    __shared__ float4 relf[EXACT64 ? 1 : CH + 4];
+    __shared__ double4 reld[EXACT64 ? CH + 4 : 1];
     __shared__ int sid[CH];
+    __shared__ uint16_t queue[kQueue][kPairThreads];
+    __shared__ T tab[GLD_MAX_DISTANCE_BINS];
     const int cid = blockIdx.x;
-    if (threadIdx.x == 0) {
+    const int tid = threadIdx.x;
+    for (int b = tid; b < a.n_r; b += kPairThreads) tab[b] = static_cast<T>(a.wtab[b]);
+    const double qnan = __builtin_nan("");
+    if (tid < 4) {
+        if (EXACT64) reld[CH + tid] = make_double4(qnan, qnan, qnan, 0.0);
+        else relf[CH + tid] = make_float4(qnan, qnan, qnan, 0.f);
+    }
+    if (tid == 0) {
         make_stencil(a.g, a.cstart, cid, st);
         int2 *row = a.stab + static_cast<int64_t>(cid) * kStab;
         for (int k = 0; k < st.n; ++k) row[k] = make_int2(st.start[k], st.base[k]);
@@ -317,22 +405,21 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
     const int h0 = a.cstart[cid], h1 = a.cstart[cid + 1];
     const int total = st.base[st.n];
     const bool store = total <= 65536;  // staged positions must fit 16 bits
-    const float Lxf = static_cast<float>(a.g.L[0]), Lyf = static_cast<float>(a.g.L[1]), Lzf = static_cast<float>(a.g.L[2]);
-    const bool mi0 = a.g.nc[0] < 3, mi1 = a.g.nc[1] < 3, mi2 = a.g.nc[2] < 3;
-    const float rc2f = static_cast<float>(a.rc2);
+    const float Lf[3] = {static_cast<float>(a.g.L[0]), static_cast<float>(a.g.L[1]), static_cast<float>(a.g.L[2])};
+    const bool mi[3] = {a.g.nc[0] < 3, a.g.nc[1] < 3, a.g.nc[2] < 3};
+    const T rc2 = static_cast<T>(a.rc2);
     const int64_t n = a.n;
     const double wca_pre = a.wca_rc2 * 1.0001;
-    T *nbw = static_cast<T *>(a.nbw);
-    uint16_t *nbl = a.nbl;
     for (int g0 = h0; g0 < h1; g0 += kPairThreads) {
-        const int s = g0 + threadIdx.x;
+        const int s = g0 + tid;
         const bool live = s < h1;
         const int self_l = st.base[st.home] + (s - h0);
         const double4 xd = live ? a.reld_src[s] : make_double4(0, 0, 0, 0);
         const double4 xi = live ? a.pos_s[s] : make_double4(0, 0, 0, 0);
-        const float xf0 = static_cast<float>(xd.x), xf1 = static_cast<float>(xd.y), xf2 = static_cast<float>(xd.z);
-        int cnt = 0;
+        const float xf[3] = {static_cast<float>(xd.x), static_cast<float>(xd.y), static_cast<float>(xd.z)};
+        int cnt = 0, nq = 0;
         double rowsum = 0, fx = 0, fy = 0, fz = 0;
+        Chunk<T> ck;
         for (int c0 = 0; c0 < total; c0 += CH) {
             const int c1 = min(total, c0 + CH);
             __syncthreads();
@@ -341,7 +428,7 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
             int sj[per];
 #pragma unroll
             for (int j = 0; j < per; ++j) {
-                const int l = c0 + static_cast<int>(threadIdx.x) + j * kPairThreads;
+                const int l = c0 + tid + j * kPairThreads;
                 if (l < c1) {
                     const int t = stencil_entry(st, l);
                     sj[j] = st.start[t] + (l - st.base[t]);
@@ -353,81 +440,92 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
             }
 #pragma unroll
             for (int j = 0; j < per; ++j) {
-                const int l = static_cast<int>(threadIdx.x) + j * kPairThreads;
+                const int l = tid + j * kPairThreads;
                 if (c0 + l < c1) {
                     if (EXACT64) reld[l] = v[j];
                     else
                         relf[l] = make_float4(static_cast<float>(v[j].x), static_cast<float>(v[j].y),
                                               static_cast<float>(v[j].z), 0.f);
                     sid[l] = sj[j];
+                } else if (EXACT64) {
+                    reld[l] = make_double4(qnan, qnan, qnan, 0.0);
+                } else {
+                    relf[l] = make_float4(qnan, qnan, qnan, 0.f);
                 }
             }
             __syncthreads();
             if (!live) continue;
-            // wave-uniform candidates, four per round: broadcast LDS reads
-            // issued together, then branch-light appends
-            for (int l0 = c0; l0 < c1; l0 += 4) {
-                T r2[4];
-                bool hit[4];
+            // lockstep distance test, four broadcast candidates per round,
+            // appended without branches (a miss writes the next free slot and
+            // does not advance); a queue is drained (all lanes busy on list
+            // entries) once one in the wave could overflow in the next block,
+            // and at the end of the staged chunk.  Blocks start at multiples of
+            // 4 from c0, so a round only runs past c1 into the NaN padding.
+            const int self_li = self_l - c0;
+            for (int b0 = c0;; b0 += kCheckBlock) {
+                const int b1 = min(c1, b0 + kCheckBlock);
+                for (int l0 = b0 - c0; l0 < b1 - c0; l0 += 4) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int l = l0 + u;
-                    const int li = min(l, c1 - 1) - c0;
-                    if (EXACT64) {
-                        const double4 q = reld[li];
-                        double dx = xd.x - q.x, dy = xd.y - q.y, dz = xd.z - q.z;
-                        if (mi0) dx -= a.g.L[0] * rint(dx / a.g.L[0]);
-                        if (mi1) dy -= a.g.L[1] * rint(dy / a.g.L[1]);
-                        if (mi2) dz -= a.g.L[2] * rint(dz / a.g.L[2]);
-                        r2[u] = dx * dx + dy * dy + dz * dz;
-                        hit[u] = r2[u] < a.rc2;
-                    } else {
-                        const float4 q = relf[li];
-                        float dx = xf0 - q.x, dy = xf1 - q.y, dz = xf2 - q.z;
-                        if (mi0) dx -= Lxf * rintf(dx / Lxf);
-                        if (mi1) dy -= Lyf * rintf(dy / Lyf);
-                        if (mi2) dz -= Lzf * rintf(dz / Lzf);
-                        const float r2f = dx * dx + dy * dy + dz * dz;
-                        r2[u] = r2f;
-                        hit[u] = r2f < rc2f;
+                    for (int u = 0; u < 4; ++u) {
+                        const int li = l0 + u;
+                        const T r2 = staged_r2<T, EXACT64, MI>(reld, relf, li, xd, xf, a.g, mi, Lf);
+                        const bool hit = r2 < rc2 && li != self_li;
+                        queue[nq][tid] = static_cast<uint16_t>(li);
+                        nq += hit ? 1 : 0;
                     }
-                    hit[u] = hit[u] && l < c1 && l != self_l;
                 }
+                const bool last = b1 >= c1;
+                if (last || __any(nq >= kDrainAt)) {
+                    for (int e = 0; e < nq; e += 2) {
+                        // two entries per round: their LDS reads and square
+                        // roots overlap
+                        const bool two = e + 1 < nq;
+                        const int lq[2] = {queue[e][tid], two ? queue[e + 1][tid] : queue[e][tid]};
+                        T r2[2], w[2];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (!hit[u]) continue;
-                    const T r = sqrt(r2[u]);
-                    const T w = weight_of<T>(a, r);
-                    rowsum += fabs(static_cast<double>(w));
-                    if (store && cnt < a.cap) {
-                        nbl[nbl_at(cnt, s, n)] = static_cast<uint16_t>(l0 + u);
-                        nbw[nbw_at(cnt, s, n)] = PAR ? w / r2[u] : w;
-                    }
-                    ++cnt;
-                    if (static_cast<double>(r2[u]) < wca_pre) {
-                        // conservative WCA force in FP64 from the wrapped positions
-                        const double4 xj = a.pos_s[sid[l0 + u - c0]];
-                        double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
-                        gx -= a.g.L[0] * rint(gx / a.g.L[0]);
-                        gy -= a.g.L[1] * rint(gy / a.g.L[1]);
-                        gz -= a.g.L[2] * rint(gz / a.g.L[2]);
-                        const double rd2 = gx * gx + gy * gy + gz * gz;
-                        if (rd2 < a.wca_rc2) {
-                            const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
-                            const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
-                            fx += fr * gx;
-                            fy += fr * gy;
-                            fz += fr * gz;
+                        for (int u = 0; u < 2; ++u) {
+                            r2[u] = staged_r2<T, EXACT64, MI>(reld, relf, lq[u], xd, xf, a.g, mi, Lf);
+                            w[u] = weight_of<T>(a, tab, static_cast<T>(sqrt(r2[u])));
+                        }
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            if (u == 1 && !two) break;
+                            rowsum += fabs(static_cast<double>(w[u]));
+                            if (store && cnt < a.cap) {
+                                const int pos = cnt & 7;
+                                ck.put(pos, static_cast<uint32_t>(c0 + lq[u]), PAR ? w[u] / r2[u] : w[u]);
+                                if (pos == 7) ck.store(a.nbl, a.nbw, cnt >> 3, s, n);
+                            }
+                            ++cnt;
+                            if (static_cast<double>(r2[u]) < wca_pre) {
+                                // conservative WCA force in FP64 from the wrapped positions
+                                const double4 xj = a.pos_s[sid[lq[u]]];
+                                double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
+                                gx -= a.g.L[0] * rint(gx / a.g.L[0]);
+                                gy -= a.g.L[1] * rint(gy / a.g.L[1]);
+                                gz -= a.g.L[2] * rint(gz / a.g.L[2]);
+                                const double rd2 = gx * gx + gy * gy + gz * gz;
+                                if (rd2 < a.wca_rc2) {
+                                    const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
+                                    const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
+                                    fx += fr * gx;
+                                    fy += fr * gy;
+                                    fz += fr * gz;
+                                }
+                            }
                         }
                     }
+                    nq = 0;
                 }
+                if (last) break;
             }
         }
         if (live) {
             const int kept = store ? min(cnt, a.cap) : 0;
-            for (int k = kept; k < ((kept + 7) & ~7); ++k) {
-                nbl[nbl_at(k, s, n)] = static_cast<uint16_t>(self_l);
-                nbw[nbw_at(k, s, n)] = T(0);
+            if (kept & 7) {
+                // pad the last chunk: zero weight, the particle itself
+                for (int pos = kept & 7; pos < 8; ++pos) ck.put(pos, static_cast<uint32_t>(self_l), T(0));
+                ck.store(a.nbl, a.nbw, kept >> 3, s, n);
             }
             if (cnt > a.cap || !store) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
             a.nn[s] = kept;
@@ -440,7 +538,7 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
         // largest row sum: wave maximum, one atomic per wave
         float rm = static_cast<float>(rowsum);
         for (int off = 32; off > 0; off >>= 1) rm = fmaxf(rm, __shfl_xor(rm, off));
-        if ((threadIdx.x & 63) == 0) atomicMax(a.rowmax, __float_as_uint(rm));
+        if ((tid & 63) == 0) atomicMax(a.rowmax, __float_as_uint(rm));
     }
 }
 
@@ -530,7 +628,7 @@ constexpr size_t mv_lds_bytes(int maxc)
 }
 
 // one chunk of 8 entries; CHECK: only entries with staged index in [c0, c0 + cn)
-template <typename T, bool PAR, bool CHECK>
+template <typename T, bool PAR, bool CHECK, bool MI>
 __device__ __forceinline__ void mv_chunk(const typename V4<T>::t *xs, const typename V2<T>::t *pyz, uint4 id,
                                          const typename V4<T>::t &wa, const typename V4<T>::t &wb, const T (&own)[3],
                                          const T (&Lb)[3], const bool (&mi)[3], unsigned c0, unsigned cn, T &p0, T &p1,
@@ -549,9 +647,9 @@ __device__ __forceinline__ void mv_chunk(const typename V4<T>::t *xs, const type
             if (PAR) {
                 const typename V2<T>::t q = pyz[li[u]];
                 T dx = own[0] - v[u].w, dy = own[1] - q.x, dz = own[2] - q.y;
-                if (mi[0]) dx -= Lb[0] * rint(dx / Lb[0]);
-                if (mi[1]) dy -= Lb[1] * rint(dy / Lb[1]);
-                if (mi[2]) dz -= Lb[2] * rint(dz / Lb[2]);
+                if (MI && mi[0]) dx -= Lb[0] * rint(dx / Lb[0]);
+                if (MI && mi[1]) dy -= Lb[1] * rint(dy / Lb[1]);
+                if (MI && mi[2]) dz -= Lb[2] * rint(dz / Lb[2]);
                 const T sc = w[u] * (dx * v[u].x + dy * v[u].y + dz * v[u].z);
                 p0 += sc * dx;
                 p1 += sc * dy;
@@ -571,9 +669,9 @@ __device__ __forceinline__ void mv_chunk(const typename V4<T>::t *xs, const type
             if (PAR) {
                 const typename V2<T>::t q = pyz[l];
                 T dx = own[0] - v.w, dy = own[1] - q.x, dz = own[2] - q.y;
-                if (mi[0]) dx -= Lb[0] * rint(dx / Lb[0]);
-                if (mi[1]) dy -= Lb[1] * rint(dy / Lb[1]);
-                if (mi[2]) dz -= Lb[2] * rint(dz / Lb[2]);
+                if (MI && mi[0]) dx -= Lb[0] * rint(dx / Lb[0]);
+                if (MI && mi[1]) dy -= Lb[1] * rint(dy / Lb[1]);
+                if (MI && mi[2]) dz -= Lb[2] * rint(dz / Lb[2]);
                 const T sc = w[u] * (dx * v.x + dy * v.y + dz * v.z);
                 p0 += sc * dx;
                 p1 += sc * dy;
@@ -587,7 +685,7 @@ __device__ __forceinline__ void mv_chunk(const typename V4<T>::t *xs, const type
     }
 }
 
-template <typename T, bool PAR, int BS, int L>
+template <typename T, bool PAR, bool MI, int BS, int L>
 __global__ __launch_bounds__(BS) void k_mv(MvArgs A)
 {
     using T4 = typename V4<T>::t;
@@ -679,9 +777,9 @@ __global__ __launch_bounds__(BS) void k_mv(MvArgs A)
                         wa = nbw4[(2 * nx) * n + s];
                         wb = nbw4[(2 * nx + 1) * n + s];
                     }
-                    if (single) mv_chunk<T, PAR, false>(xs, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1, p2);
+                    if (single) mv_chunk<T, PAR, false, MI>(xs, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1, p2);
                     else
-                        mv_chunk<T, PAR, true>(xs, pyz, cid8, cwa, cwb, own, Lb, mi, static_cast<unsigned>(c0),
+                        mv_chunk<T, PAR, true, MI>(xs, pyz, cid8, cwa, cwb, own, Lb, mi, static_cast<unsigned>(c0),
                                                static_cast<unsigned>(c1 - c0), p0, p1, p2);
                 }
             }
@@ -773,17 +871,29 @@ Geo make_geo(const Dev &d)
 constexpr int kMvThreads32 = 512, kMvLanes32 = 4;
 constexpr int kMvThreads64 = 512, kMvLanes64 = 4;
 
-template <typename T, bool PAR, int BS, int L>
+template <typename T, bool PAR, bool MI, int BS, int L>
 hipError_t launch_mv_t(const Dev &d, const MvArgs &A, hipStream_t st)
 {
     const size_t shm = mv_lds_bytes<T, PAR, BS>(d.maxc);
     if (shm > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mv<T, PAR, BS, L>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mv<T, PAR, MI, BS, L>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
         if (e != hipSuccess) return e;
     }
-    k_mv<T, PAR, BS, L><<<d.ncell, BS, shm, st>>>(A);
+    k_mv<T, PAR, MI, BS, L><<<d.ncell, BS, shm, st>>>(A);
     return hipGetLastError();
+}
+
+template <typename T, bool EX>
+void launch_build_t(const Dev &d, const BuildArgs &a, bool mi, hipStream_t st)
+{
+    if (d.parallel) {
+        if (mi) k_build<T, EX, true, true><<<d.ncell, kPairThreads, 0, st>>>(a);
+        else k_build<T, EX, true, false><<<d.ncell, kPairThreads, 0, st>>>(a);
+    } else {
+        if (mi) k_build<T, EX, false, true><<<d.ncell, kPairThreads, 0, st>>>(a);
+        else k_build<T, EX, false, false><<<d.ncell, kPairThreads, 0, st>>>(a);
+    }
 }
 
 }  // namespace
@@ -850,13 +960,9 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     a.flags = d.d_flags;
     a.flag_step = d.d_flag_step;
     a.d_step = d.d_step;
-    if (d.fp64) {
-        if (d.parallel) k_build<double, true, true><<<d.ncell, kPairThreads, 0, st>>>(a);
-        else k_build<double, true, false><<<d.ncell, kPairThreads, 0, st>>>(a);
-    } else {
-        if (d.parallel) k_build<float, false, true><<<d.ncell, kPairThreads, 0, st>>>(a);
-        else k_build<float, false, false><<<d.ncell, kPairThreads, 0, st>>>(a);
-    }
+    const bool mi = d.nc[0] < 3 || d.nc[1] < 3 || d.nc[2] < 3;
+    if (d.fp64) launch_build_t<double, true>(d, a, mi, st);
+    else launch_build_t<float, false>(d, a, mi, st);
     return hipGetLastError();
 }
 
@@ -902,12 +1008,19 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
     A.r = coef ? r : 0;
     A.out_sorted = out_sorted;
     A.out_orig = out_orig;
+    const bool mi = d.nc[0] < 3 || d.nc[1] < 3 || d.nc[2] < 3;
     if (d.fp64) {
-        if (d.parallel) return launch_mv_t<double, true, kMvThreads64, kMvLanes64>(d, A, st);
-        return launch_mv_t<double, false, kMvThreads64, kMvLanes64>(d, A, st);
+        if (d.parallel) {
+            if (mi) return launch_mv_t<double, true, true, kMvThreads64, kMvLanes64>(d, A, st);
+            return launch_mv_t<double, true, false, kMvThreads64, kMvLanes64>(d, A, st);
+        }
+        return launch_mv_t<double, false, false, kMvThreads64, kMvLanes64>(d, A, st);
     }
-    if (d.parallel) return launch_mv_t<float, true, kMvThreads32, kMvLanes32>(d, A, st);
-    return launch_mv_t<float, false, kMvThreads32, kMvLanes32>(d, A, st);
+    if (d.parallel) {
+        if (mi) return launch_mv_t<float, true, true, kMvThreads32, kMvLanes32>(d, A, st);
+        return launch_mv_t<float, true, false, kMvThreads32, kMvLanes32>(d, A, st);
+    }
+    return launch_mv_t<float, false, false, kMvThreads32, kMvLanes32>(d, A, st);
 }
 
 hipError_t launch_dissipative(const Dev &d, hipStream_t st)
