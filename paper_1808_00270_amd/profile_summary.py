@@ -35,13 +35,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["gld_api.cpp", "gld_noise_plan.cpp", "gld_kernels.hip", "gld_pairs.hip", "gld_internal.h"]
 
-# kernel classes of the step (the names bench.py uses) -> kernel symbol
+# kernel classes of the step (the names bench.py uses) -> kernel symbol, for
+# the work type T of the precision
 CLASSES = {
-    "noise_spmv": r"k_mv<",
-    "history": r"k_history<",
-    "noise_fir": r"k_fir<",
-    "neighbor_build": r"k_build<",
-    "update": r"k_update_[rv]",
+    "noise_spmv": r"k_mv<{T}",
+    "history": r"k_history<{T}",
+    "noise_fir": r"k_fir<{T}",
+    "neighbor_build": r"k_build<{T}",
+    "update": r"k_update_[rv]<{T}",
 }
 CALIB = r"neg"
 
@@ -106,8 +107,11 @@ def main():
     ap.add_argument("--cmd-fetch", default="")
     ap.add_argument("--cmd-write", default="")
     ap.add_argument("--note", default="")
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
+                    help="kernel classes of this path (work type float or double)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
+    classes = {k: v.format(T="float" if a.precision == "fp32" else "double") for k, v in CLASSES.items()}
 
     lines = [f"# {a.name}", ""]
     if a.note:
@@ -117,13 +121,16 @@ def main():
     kt = kernel_table(a.kt)
     for name, calls, total, avg, pctg in kt[:16]:
         lines.append(f"| `{short(name)}` | {calls} | {avg:.1f} | {total / 1e3:.2f} | {pctg:.1f} |")
+    lines += ["", "Average duration per launch by kernel class (" + a.precision + " path):", ""]
     avg_by_class = {}
-    for cls, pat in CLASSES.items():
+    for cls, pat in classes.items():
         sel = [(calls, total) for name, calls, total, _, _ in kt if re.search(pat, name)]
         if sel:
             calls = sum(c for c, _ in sel)
             avg_by_class[cls] = sum(t for _, t in sel) / calls
-    out = {"name": a.name, "source_sha256": source_hash(), "avg_us": avg_by_class, "kernels": {}}
+            lines.append(f"- {cls} (`{pat}`): {avg_by_class[cls]:.1f} us over {calls} launches")
+    out = {"name": a.name, "precision": a.precision, "source_sha256": source_hash(), "avg_us": avg_by_class,
+           "kernels": {}}
 
     if a.fetch and a.write and a.calib_bytes > 0:
         fe = counter_means(a.fetch, "FETCH_SIZE")
@@ -142,14 +149,14 @@ def main():
                   f"WRITE_SIZE {cw[0]:.0f} KiB (scale {sw:.4f}).", "",
                   "| kernel | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | read (MB) | written (MB) |",
                   "|---|---:|---:|---:|---:|---:|"]
-        for cls, pat in CLASSES.items():
+        for cls, pat in classes.items():
             f, w = pick(fe, pat), pick(wr, pat)
             if f is None or w is None:
                 continue
             rb, wb = f[0] * 1024.0 / sf, w[0] * 1024.0 / sw
             out["kernels"][cls] = {"read_bytes": rb, "write_bytes": wb, "traffic_bytes": rb + wb,
                                    "dispatches": f[1]}
-            lines.append(f"| {cls} (`{pat.rstrip('<')}`) | {f[1]} | {f[0]:.0f} | {w[0]:.0f} | {rb / 1e6:.1f} | "
+            lines.append(f"| {cls} (`{pat}`) | {f[1]} | {f[0]:.0f} | {w[0]:.0f} | {rb / 1e6:.1f} | "
                          f"{wb / 1e6:.1f} |")
     lines += ["", f"Kernel sources (sha256 over csrc): `{out['source_sha256'][:16]}`", ""]
     os.makedirs(a.out, exist_ok=True)
