@@ -463,8 +463,23 @@ gld_status setup_noise(gld_system *s)
             const double span = std::max(1.0, th[1] - th[0]);
             lo = std::isfinite(s->plan.sing_lo) ? th[0] - 0.5 * (th[0] - s->plan.sing_lo) : th[0] - 0.5 * span;
             // the largest row sum of |w| bounds lambda_max at every step; leave
-            // room for it to grow as the configuration evolves
-            hi = 2.0 * std::max(static_cast<double>(gmax), th[1]) + 1.0;
+            // room for it to grow as the configuration evolves: twice the
+            // initial bound, and at least 8 standard deviations above the
+            // mean row sum of an ideal gas at this density (mean rho int w dV,
+            // variance rho int w^2 dV), which the lattice start understates
+            double mu = 0, var = 0;
+            const double rho = static_cast<double>(p.n) / (p.box[0] * p.box[1] * p.box[2]);
+            for (int b = 0; b + 1 < p.n_r; ++b) {
+                // trapezoid over the grid, inside the cutoff
+                const double ra = p.r0 + b * p.dr, rb = ra + p.dr;
+                if (ra >= p.r_cut) break;
+                const double wa = std::fabs(p.k_pair_w[b]), wb = std::fabs(p.k_pair_w[b + 1]);
+                mu += 0.5 * p.dr * (ra * ra * wa + rb * rb * wb);
+                var += 0.5 * p.dr * (ra * ra * wa * wa + rb * rb * wb * wb);
+            }
+            mu *= 4.0 * M_PI * rho;
+            var *= 4.0 * M_PI * rho;
+            hi = std::max(2.0 * std::max(static_cast<double>(gmax), th[1]) + 1.0, mu + 8.0 * std::sqrt(var));
             if (std::isfinite(s->plan.sing_hi)) hi = std::min(hi, th[1] + 0.5 * (s->plan.sing_hi - th[1]));
         }
     }

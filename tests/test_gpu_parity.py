@@ -64,11 +64,13 @@ def assert_close(name, a, b, tol, atol=0.0):
     assert np.all(d <= 10 * tol * rms + atol), f"{name}: element error {emax:.3e} > {10 * tol:.1e} (x rms)"
 
 
-def one_step(pkg, oracle_mod, w, fp64, step=5, hist_scale=0.01, seed=11, check_fc=True, state=None, **kw):
+def one_step(pkg, oracle_mod, w, fp64, step=5, hist_scale=0.01, seed=11, check_fc=True, state=None, hist=None,
+             **kw):
     tables = kw.pop("tables", None)
     rng = np.random.default_rng(seed)
     R, V = w.initial_state() if state is None else state
-    hist = wl.random_history(rng, w.m_max, w.n, scale=hist_scale)
+    if hist is None:
+        hist = wl.random_history(rng, w.m_max, w.n, scale=hist_scale)
     if fp64:
         kw.setdefault("noise_tol", 1e-13)
     log(f"  one_step {w.name} n={w.n} m_max={w.m_max} fp64={fp64} parallel={w.parallel} kw={kw}")
