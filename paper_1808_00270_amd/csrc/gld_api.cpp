@@ -460,13 +460,20 @@ gld_status setup_noise(gld_system *s)
                                                 ", " + std::to_string(th[1]) + "] reaches a singular point of the "
                                                 "noise correlation (" + std::to_string(s->plan.sing_lo) + ", " +
                                                 std::to_string(s->plan.sing_hi) + "): not positive definite");
+            // lower end a quarter of the way from the smallest Ritz value to the
+            // singular point: the expansion's cost grows as that gap closes,
+            // while the smallest eigenvalue of P is set by the short-range
+            // structure and moves by a few percent of the gap as a lattice
+            // start melts (cfg3: -0.810 -> -0.797 over 1000 steps, gap 1.05);
+            // the periodic Lanczos check latches GLD_ERR_INTERVAL if it ever
+            // crosses
             const double span = std::max(1.0, th[1] - th[0]);
-            lo = std::isfinite(s->plan.sing_lo) ? th[0] - 0.5 * (th[0] - s->plan.sing_lo) : th[0] - 0.5 * span;
+            lo = std::isfinite(s->plan.sing_lo) ? th[0] - 0.25 * (th[0] - s->plan.sing_lo) : th[0] - 0.5 * span;
             // the largest row sum of |w| bounds lambda_max at every step; leave
-            // room for it to grow as the configuration evolves: twice the
-            // initial bound, and at least 8 standard deviations above the
-            // mean row sum of an ideal gas at this density (mean rho int w dV,
-            // variance rho int w^2 dV), which the lattice start understates
+            // room for it to grow as the configuration evolves: 8 standard
+            // deviations above the mean row sum of an ideal gas at this density
+            // (mean rho int w dV, variance rho int w^2 dV; a liquid fluctuates
+            // less), and at least 1.25 times the initial bound
             double mu = 0, var = 0;
             const double rho = static_cast<double>(p.n) / (p.box[0] * p.box[1] * p.box[2]);
             for (int b = 0; b + 1 < p.n_r; ++b) {
@@ -479,7 +486,7 @@ gld_status setup_noise(gld_system *s)
             }
             mu *= 4.0 * M_PI * rho;
             var *= 4.0 * M_PI * rho;
-            hi = std::max(2.0 * std::max(static_cast<double>(gmax), th[1]) + 1.0, mu + 8.0 * std::sqrt(var));
+            hi = std::max(1.25 * std::max(static_cast<double>(gmax), th[1]) + 1.0, mu + 8.0 * std::sqrt(var));
             if (std::isfinite(s->plan.sing_hi)) hi = std::min(hi, th[1] + 0.5 * (s->plan.sing_hi - th[1]));
         }
     }

@@ -33,7 +33,8 @@ import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["gld_api.cpp", "gld_noise_plan.cpp", "gld_kernels.hip", "gld_pairs.hip", "gld_internal.h"]
+# the kernels and their launchers (the traffic of a launch depends on these only)
+SOURCES = ["gld_kernels.hip", "gld_pairs.hip", "gld_internal.h"]
 
 # kernel classes of the step (the names bench.py uses) -> kernel symbol, for
 # the work type T of the precision
