@@ -166,6 +166,9 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.relf, static_cast<size_t>(n) * 16);
     L.take(d.reld, static_cast<size_t>(n) * 32);  // both modes: the neighbour build decides in FP64 data
     L.take(d.U, static_cast<size_t>(g.firw) * vec * elt);
+    // white-noise ring: at most the full filter window plus the largest block
+    if (p->kT > 0)
+        L.take(d.wring, static_cast<size_t>(std::max(0, 2 * (p->m_max - 1)) + gld::kMaxFirBlock) * vec * elt);
     L.take(d.Afilt, static_cast<size_t>(gld::kMaxRank) * P * elt);
     L.take(d.Bmix, static_cast<size_t>(gld::kMaxCheb) * gld::kMaxRank * elt);
     L.take(d.ks, static_cast<size_t>(p->m_max) * elt);
@@ -322,7 +325,10 @@ gld_status enqueue_step(gld_system *s)
     hipStream_t st = s->st;
     const NoisePlan &pl = s->plan;
     LAUNCH(GLD_K_HISTORY, gld::launch_history(d, st));
-    if (s->noise_on) LAUNCH(GLD_K_NOISE_FIR, gld::launch_fir(d, 0, st));
+    if (s->noise_on) {
+        LAUNCH(GLD_K_NOISE_FIR, gld::launch_white_ring(d, 0, st));
+        LAUNCH(GLD_K_NOISE_FIR, gld::launch_fir(d, 0, st));
+    }
     LAUNCH(GLD_K_DISSIPATIVE, gld::launch_permute(d, st, s->noise_on ? pl.r : 0));
     LAUNCH(GLD_K_DISSIPATIVE, gld::launch_dissipative(d, st));
     if (s->noise_on) {
@@ -493,18 +499,34 @@ gld_status setup_noise(gld_system *s)
     st = gld::noise_build(p, lo, hi, tol, s->plan, err);
     if (st != GLD_OK) return fail(st, err);
     const NoisePlan &pl = s->plan;
-    const int width = s->geo.firw;
-    d.fir_rcap = pl.r <= 8 ? 8 : (pl.r <= 16 ? 16 : 32);
-    d.fir_block = width / d.fir_rcap;
-    // padded filter taps [rcap][P] and mixing weights [K][rcap]
-    std::vector<double> A(static_cast<size_t>(d.fir_rcap) * pl.P, 0.0), B(static_cast<size_t>(pl.K) * d.fir_rcap, 0.0);
+    d.fir_rcap = gld::fir_rcap_for(pl.r);
+    d.fir_block = gld::fir_block_for(s->geo.fp64, d.fir_rcap);
+    d.fir_half = pl.half;
+    d.wring_len = 2 * pl.half + d.fir_block;
+    // filter taps of the window, tap-major [2 half + 1][rcap] (columns beyond
+    // r zero), and mixing weights [K][rcap]
+    const int Pw = 2 * pl.half + 1;
+    std::vector<double> A(static_cast<size_t>(d.fir_rcap) * Pw, 0.0), B(static_cast<size_t>(pl.K) * d.fir_rcap, 0.0);
     for (int q = 0; q < pl.r; ++q)
-        for (int t = 0; t < pl.P; ++t) A[static_cast<size_t>(q) * pl.P + t] = pl.Afilt[static_cast<size_t>(q) * pl.P + t];
+        for (int t = 0; t < Pw; ++t)
+            A[static_cast<size_t>(t) * d.fir_rcap + q] = pl.Afilt[static_cast<size_t>(q) * pl.P + (pl.M - 1 - pl.half) + t];
     for (int k = 0; k < pl.K; ++k)
         for (int q = 0; q < pl.r; ++q) B[static_cast<size_t>(k) * d.fir_rcap + q] = pl.Bmix[static_cast<size_t>(k) * pl.r + q];
     if ((st = upload_work_table(s, d.Afilt, A.data(), A.size())) != GLD_OK) return st;
     if ((st = upload_work_table(s, d.Bmix, B.data(), B.size())) != GLD_OK) return st;
     if (has_pair) d.lam_hi = pl.hi;  // from now on every pair build checks the bound
+    return GLD_OK;
+}
+
+// white-noise ring and filter outputs for the current step (at creation and
+// after a state is installed): the window of the current block, its filter
+// outputs, then the slices the block's earlier steps would have added
+gld_status prime_noise(gld_system *s)
+{
+    if (!s->noise_on) return GLD_OK;
+    HIP_TRY(gld::launch_white_ring(s->d, 1, s->st));
+    HIP_TRY(gld::launch_fir(s->d, 1, s->st));
+    HIP_TRY(gld::launch_white_ring(s->d, 2, s->st));
     return GLD_OK;
 }
 
@@ -637,6 +659,7 @@ gld_status gld_create(const gld_params *params, const double *r0, const double *
     if ((st = refresh_forces(s)) != GLD_OK) return bail(st);
     if ((st = read_flags(s)) != GLD_OK) return bail(st);
     if ((st = setup_noise(s)) != GLD_OK) return bail(st);
+    if ((st = prime_noise(s)) != GLD_OK) return bail(st);
     if (s->noise_on && d.has_pair) {
         // positive definiteness at t = 0 on the chosen interval (Sec. II.B)
         float gm = 0;
@@ -736,7 +759,7 @@ gld_status gld_write_state(gld_system *s, const gld_state *in)
     HIP_TRY(hipMemsetAsync(d.FR, 0, 3 * d.S * elt, s->st));
     if ((st = clear_flags(s)) != GLD_OK) return st;
     if ((st = refresh_forces(s)) != GLD_OK) return st;
-    if (s->noise_on) HIP_TRY(gld::launch_fir(d, 1, s->st));  // filter outputs of the current block
+    if ((st = prime_noise(s)) != GLD_OK) return st;
     return read_flags(s);
 }
 
@@ -749,7 +772,7 @@ gld_status gld_noise_parameters(const gld_system *s, gld_noise_info *o)
     o->lam_lo = s->plan.lo;
     o->lam_hi = s->plan.hi;
     o->lam_singular = s->plan.sing_lo;
-    o->err_estimate = s->plan.err_cheb + s->plan.err_rank;
+    o->err_estimate = s->plan.err_cheb + s->plan.err_rank + s->plan.err_window;
     return GLD_OK;
 }
 
@@ -826,7 +849,7 @@ gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, doub
     info->lam_lo = plan.lo;
     info->lam_hi = plan.hi;
     info->lam_singular = plan.sing_lo;
-    info->err_estimate = plan.err_cheb + plan.err_rank;
+    info->err_estimate = plan.err_cheb + plan.err_rank + plan.err_window;
     return GLD_OK;
 }
 

@@ -38,10 +38,11 @@ struct NoisePlan {
     double lo = 0, hi = 0;       // expansion interval
     double alpha = 0, beta = 0;  // P~ = alpha P + beta 1
     double sing_lo = 0, sing_hi = 0;  // nearest singular points (-inf/+inf if none)
-    double err_cheb = 0, err_rank = 0;
+    double err_cheb = 0, err_rank = 0, err_window = 0;
+    int half = 0;                // filter window: lags |t| <= half
     std::vector<double> S, G;    // spectra [M]
     std::vector<double> Bmix;    // [K][r]
-    std::vector<double> Afilt;   // [r][P], filter taps for lags t = -(M-1)..M-1
+    std::vector<double> Afilt;   // [r][P], filter taps for lags t = -(M-1)..M-1 (zero beyond half)
 };
 
 // Spectra and singular points only (no expansion).  Returns GLD_OK.
@@ -73,6 +74,8 @@ struct Dev {
     int offs[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     int ncell = 1;
     int fir_block = 1, fir_rcap = 8;
+    int fir_half = 0;       // filter window half-width (lags |t| <= fir_half)
+    int wring_len = 1;      // slots of the white-noise ring
     double g0 = 0;
     double lam_hi = __builtin_huge_val();  // noise interval top, checked every step
 
@@ -83,7 +86,8 @@ struct Dev {
     void *Dneg = nullptr, *Y = nullptr, *FD = nullptr, *FR = nullptr;
     void *cb[3] = {nullptr, nullptr, nullptr};  // T4 [S] Clenshaw vectors, sorted order
     void *U = nullptr;      // [fir_block][fir_rcap][3][S]
-    void *Afilt = nullptr;  // [fir_rcap][P]
+    void *wring = nullptr;  // [wring_len][3][S] white noise W_t, slot t mod wring_len
+    void *Afilt = nullptr;  // [2 fir_half + 1][fir_rcap], tap-major
     void *Bmix = nullptr;   // [kMaxCheb][fir_rcap]
     void *ks = nullptr, *gm = nullptr;  // [M]
     double *wtab = nullptr;             // [n_r]
@@ -120,6 +124,14 @@ hipError_t launch_history(const Dev &d, hipStream_t st);
 hipError_t launch_dissipative(const Dev &d, hipStream_t st);
 // filter bank; force = 1 produces the block holding the current step even mid-block
 hipError_t launch_fir(const Dev &d, int force, hipStream_t st);
+// white-noise ring: mode 0 writes the slice the step adds (t = step + half +
+// block - 1); mode 1 fills the window of the current block; mode 2 the slices
+// steps n0 .. step-1 of the block would have added (after a resume mid-block)
+hipError_t launch_white_ring(const Dev &d, int mode, hipStream_t st);
+// filter block sizes for a padded rank (work precision), and the largest one
+int fir_block_for(int fp64, int rcap);
+int fir_rcap_for(int rank);
+constexpr int kMaxFirBlock = 16;
 // out = a P x + b x + cz z + sum_q coef[q] us_q  (x, z, us: sorted T4; x, z may be null
 // when a = b = 0 / cz = 0).  Written to out_sorted (T4) or, if that is null,
 // scattered to out_orig ([3][S], original order) plus add_orig when given.

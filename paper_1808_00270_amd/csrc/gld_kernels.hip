@@ -244,17 +244,63 @@ __global__ __launch_bounds__(256) void k_history(const T *__restrict__ ring, int
 }
 
 // ---------------------------------------------------------------------------
-// H5: white-noise filter bank.  Every BF steps (when the device step counter
-// is a multiple of BF) each thread regenerates its particle's white noise
-// over the window t = n0-(M-1) .. n0+BF-1+(M-1) once and accumulates
-//   u_q(n0 + b) = sum_{t=-(M-1)}^{M-1} A_q[t] W_{n0+b+t},  b < BF, q < RC
-// (filter taps zero-padded to RC rows).  Output U[b][q][3][S].
+// H5: white noise and the filter bank of eq. (noise_production).
+//
+// The white noise W_t of every particle is drawn once (Philox, Box-Muller)
+// into a ring of the L = 2 half + BF most recent and upcoming steps, slot
+// t mod L, [L][3][S]; each step adds the slice t = step + half + BF - 1.
+// Every BF steps (when the device step counter is a multiple of BF) the
+// filter bank streams the window t = n0-half .. n0+BF-1+half once and
+// accumulates
+//   u_q(n0 + b) = sum_{t=-half}^{half} A_q[t] W_{n0+b+t},  b < BF, q < RC
+// (taps zero-padded to RC rows, window cut where the taps fall below the
+// noise tolerance).  Output U[b][q][3][S].
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int ring_slot(long long t, int len)
+{
+    long long m = t % len;
+    return static_cast<int>(m < 0 ? m + len : m);
+}
+
+template <typename T>
+__global__ void k_white_ring(int64_t n, int64_t S, uint64_t seed, const long long *__restrict__ d_step, int mode,
+                             int bf, int half, int len, T *__restrict__ W)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long cur = *d_step;
+    const long long n0 = cur - cur % bf;
+    const int y = blockIdx.y;
+    long long t;
+    if (mode == 0) {
+        t = cur + half + bf - 1;
+    } else if (mode == 1) {
+        if (y >= len) return;
+        t = n0 - half + y;
+    } else {
+        if (y >= cur - n0) return;
+        t = n0 + half + bf + y;
+    }
+    T w[3];
+    BoxMuller<T>::gauss3(philox_at(seed, static_cast<uint32_t>(i), t, 0u), w);
+    T *dst = W + static_cast<int64_t>(ring_slot(t, len)) * 3 * S;
+    dst[i] = w[0];
+    dst[S + i] = w[1];
+    dst[2 * S + i] = w[2];
+}
+
+// The loop runs over the taps ti (outer) with a register window holding
+// W at steps n0-half+ti .. n0-half+ti+WIN-1: tap ti feeds output b from the
+// window entry ti+b, so one tap row A[ti][0..RC) (a scalar load, the same
+// for the whole wave) meets BF window entries; each tap adds one entry,
+// loaded PF taps ahead.  Unrolled by WIN so the window indices are static.
 template <typename T, int BF, int RC>
-__global__ __launch_bounds__(128) void k_fir(int64_t n, int64_t S, int M, uint64_t seed,
-                                             const T *__restrict__ A, const long long *__restrict__ d_step,
+__global__ __launch_bounds__(128) void k_fir(int64_t n, int64_t S, int half, int len, const T *__restrict__ A,
+                                             const T *__restrict__ W, const long long *__restrict__ d_step,
                                              T *__restrict__ U, int force)
 {
+    constexpr int PF = 2;          // prefetch distance (taps)
+    constexpr int WIN = BF + PF;   // window entries
     // regular launches work only at block starts; a forced launch (after a
     // state is installed mid-block) produces the block holding the step
     const long long cur = *d_step;
@@ -262,28 +308,50 @@ __global__ __launch_bounds__(128) void k_fir(int64_t n, int64_t S, int M, uint64
     const long long n0 = cur - cur % BF;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int P = 2 * M - 1;
+    const int P = 2 * half + 1;
+    const int span = P + BF - 1;  // window steps read
     T acc[BF][RC][3];
 #pragma unroll
     for (int b = 0; b < BF; ++b)
 #pragma unroll
         for (int q = 0; q < RC; ++q) acc[b][q][0] = acc[b][q][1] = acc[b][q][2] = T(0);
-    const int span = P + BF - 1;
-    for (int k = 0; k < span; ++k) {
-        const long long t = n0 - (M - 1) + k;
-        T w[3];
-        BoxMuller<T>::gauss3(philox_at(seed, static_cast<uint32_t>(i), t, 0u), w);
-        // output b uses tap index k - b (lag t - (n0 + b) = k - b - (M-1))
+    T win[WIN][3];
+    const int slot0 = ring_slot(n0 - half, len);
+    auto load = [&](int k, T (&dst)[3]) {
+        // window step k (0 <= k < span); beyond it zeros (never used)
+        if (k < span) {
+            int sl = slot0 + k;
+            sl -= sl >= len ? len : 0;
+            const T *src = W + static_cast<int64_t>(sl) * 3 * S + i;
+            dst[0] = src[0];
+            dst[1] = src[S];
+            dst[2] = src[2 * S];
+        } else {
+            dst[0] = dst[1] = dst[2] = T(0);
+        }
+    };
 #pragma unroll
-        for (int b = 0; b < BF; ++b) {
-            const int ti = k - b;
-            if (ti >= 0 && ti < P) {
+    for (int e = 0; e < WIN - 1; ++e) load(e, win[e]);
+    for (int t0 = 0; t0 < P; t0 += WIN) {
 #pragma unroll
-                for (int q = 0; q < RC; ++q) {
-                    const T c = A[static_cast<int64_t>(q) * P + ti];
-                    acc[b][q][0] += c * w[0];
-                    acc[b][q][1] += c * w[1];
-                    acc[b][q][2] += c * w[2];
+        for (int u = 0; u < WIN; ++u) {
+            const int ti = t0 + u;
+            if (ti < P) {
+                // entry ti + WIN - 1 goes where entry ti - 1 was
+                load(ti + WIN - 1, win[(u + WIN - 1) % WIN]);
+                const T *a = A + static_cast<int64_t>(ti) * RC;
+                T c[RC];
+#pragma unroll
+                for (int q = 0; q < RC; ++q) c[q] = a[q];
+#pragma unroll
+                for (int b = 0; b < BF; ++b) {
+                    const T *wv = win[(u + b) % WIN];
+#pragma unroll
+                    for (int q = 0; q < RC; ++q) {
+                        acc[b][q][0] += c[q] * wv[0];
+                        acc[b][q][1] += c[q] * wv[1];
+                        acc[b][q][2] += c[q] * wv[2];
+                    }
                 }
             }
         }
@@ -540,8 +608,46 @@ hipError_t launch_history(const Dev &d, hipStream_t st)
 template <typename T, int BF, int RC>
 static hipError_t fir_t(const Dev &d, hipStream_t st, int force)
 {
-    k_fir<T, BF, RC><<<blocks(d.n, 128), 128, 0, st>>>(d.n, d.S, d.M, d.seed, static_cast<const T *>(d.Afilt),
-                                                       d.d_step, static_cast<T *>(d.U), force);
+    k_fir<T, BF, RC><<<blocks(d.n, 128), 128, 0, st>>>(d.n, d.S, d.fir_half, d.wring_len,
+                                                       static_cast<const T *>(d.Afilt),
+                                                       static_cast<const T *>(d.wring), d.d_step,
+                                                       static_cast<T *>(d.U), force);
+    return hipGetLastError();
+}
+
+// padded ranks and, per work precision, the steps of one filter block: the
+// accumulators BF * RC * 3 fill about 192 registers (FP64 values take two)
+int fir_rcap_for(int rank)
+{
+    static const int caps[] = {4, 6, 8, 12, 16, 24, 32};
+    for (int c : caps)
+        if (rank <= c) return c;
+    return 32;
+}
+
+int fir_block_for(int fp64, int rcap)
+{
+    switch (rcap) {
+    case 4: return fp64 ? 8 : 16;
+    case 6: return fp64 ? 5 : 10;
+    case 8: return fp64 ? 4 : 8;
+    case 12: return fp64 ? 2 : 5;
+    case 16: return fp64 ? 2 : 4;
+    case 24: return fp64 ? 1 : 2;
+    default: return fp64 ? 1 : 2;
+    }
+}
+
+hipError_t launch_white_ring(const Dev &d, int mode, hipStream_t st)
+{
+    const unsigned gy = mode == 0 ? 1u : (mode == 1 ? static_cast<unsigned>(d.wring_len) : static_cast<unsigned>(d.fir_block));
+    const dim3 grid(blocks(d.n, 256), gy);
+    if (d.fp64)
+        k_white_ring<double><<<grid, 256, 0, st>>>(d.n, d.S, d.seed, d.d_step, mode, d.fir_block, d.fir_half,
+                                                    d.wring_len, static_cast<double *>(d.wring));
+    else
+        k_white_ring<float><<<grid, 256, 0, st>>>(d.n, d.S, d.seed, d.d_step, mode, d.fir_block, d.fir_half,
+                                                   d.wring_len, static_cast<float *>(d.wring));
     return hipGetLastError();
 }
 
@@ -549,14 +655,22 @@ hipError_t launch_fir(const Dev &d, int force, hipStream_t st)
 {
     if (d.fp64) {
         switch (d.fir_rcap) {
+        case 4: return fir_t<double, 8, 4>(d, st, force);
+        case 6: return fir_t<double, 5, 6>(d, st, force);
         case 8: return fir_t<double, 4, 8>(d, st, force);
+        case 12: return fir_t<double, 2, 12>(d, st, force);
         case 16: return fir_t<double, 2, 16>(d, st, force);
+        case 24: return fir_t<double, 1, 24>(d, st, force);
         default: return fir_t<double, 1, 32>(d, st, force);
         }
     }
     switch (d.fir_rcap) {
+    case 4: return fir_t<float, 16, 4>(d, st, force);
+    case 6: return fir_t<float, 10, 6>(d, st, force);
     case 8: return fir_t<float, 8, 8>(d, st, force);
+    case 12: return fir_t<float, 5, 12>(d, st, force);
     case 16: return fir_t<float, 4, 16>(d, st, force);
+    case 24: return fir_t<float, 2, 24>(d, st, force);
     default: return fir_t<float, 2, 32>(d, st, force);
     }
 }

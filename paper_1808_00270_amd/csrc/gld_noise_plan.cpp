@@ -225,12 +225,13 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
     // with eigenvalue x the error is sum_t (dC^T tau)_t xi_t, xi_t iid N(0,1),
     // tau_k = T_k(x~), |tau|^2 <= K; hence its rms relative to the signal
     // (variance c0 = sig / P per component) is at most
-    //     sqrt(K) sigma_{r+1} / sqrt(c0).
-    // Smallest r with that bound within tol/2:
+    //     sqrt(K) ||dC||_2 / sqrt(c0),  ||dC||_2 = sigma_{r+1}.
+    // Error budget: Chebyshev tail tol/2, rank tol/4, filter window tol/4.
+    // Smallest r with the rank bound within tol/4:
     const double c0 = sig / P;
     int r = K;
     for (int q = K - 1; q >= 1; --q) {
-        if (std::sqrt(static_cast<double>(K) / c0) * sv[order[q]] > 0.5 * tol) break;  // keep order[q]
+        if (std::sqrt(static_cast<double>(K) / c0) * sv[order[q]] > 0.25 * tol) break;  // keep order[q]
         r = q;
     }
     const double dropped_max = r < K ? sv[order[r]] : 0.0;
@@ -251,6 +252,33 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
         for (int t = 0; t < P; ++t)
             plan.Afilt[static_cast<size_t>(qq) * P + t] = (s > 0) ? X[static_cast<size_t>(q) * P + t] / s : 0.0;
     }
+    // Filter window.  The taps decay with the memory; dropping the lags
+    // |t| > h changes C = B A by dC (its columns |t| > h), with the same
+    // bound as above: sqrt(K) ||dC||_F / sqrt(c0) <= tol/4.  Smallest h:
+    std::vector<double> col2(P, 0.0);  // squared column norms of B A
+    for (int t = 0; t < P; ++t) {
+        double acc = 0;
+        for (int k = 0; k < K; ++k) {
+            double v = 0;
+            for (int q = 0; q < r; ++q)
+                v += plan.Bmix[static_cast<size_t>(k) * r + q] * plan.Afilt[static_cast<size_t>(q) * P + t];
+            acc += v * v;
+        }
+        col2[t] = acc;
+    }
+    int h = M - 1;
+    double dropped2 = 0;
+    while (h > 0) {
+        const double add = col2[(M - 1) - h] + col2[(M - 1) + h];
+        if (std::sqrt(static_cast<double>(K) * (dropped2 + add) / c0) > 0.25 * tol) break;
+        dropped2 += add;
+        --h;
+    }
+    plan.half = h;
+    plan.err_window = std::sqrt(static_cast<double>(K) * dropped2 / c0);
+    for (int q = 0; q < r; ++q)
+        for (int t = 0; t < P; ++t)
+            if (std::abs(t - (M - 1)) > h) plan.Afilt[static_cast<size_t>(q) * P + t] = 0.0;
     return GLD_OK;
 }
 
