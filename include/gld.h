@@ -98,6 +98,15 @@ typedef struct {
     int32_t max_neighbors;     /* pair-list capacity per particle (0: automatic)     */
     int32_t check_interval;    /* steps between spectrum (positive-definiteness)
                                   checks by Lanczos on P (0: 100, < 0: never)        */
+    double verlet_skin;        /* >= 0.  0: the neighbour lists are rebuilt every
+                                  step.  > 0: a list of candidates within
+                                  r_cut + verlet_skin is rebuilt only once some
+                                  particle has moved more than verlet_skin / 2 since
+                                  the last build, and each step takes the pairs
+                                  within r_cut from it (the same pairs; the order of
+                                  the neighbour sums then depends on when the list
+                                  was built, so a resumed run agrees with an
+                                  uninterrupted one to rounding, not bit for bit) */
 } gld_params;
 
 /* Snapshot of a system.  On read, every non-NULL array is filled; on write,

@@ -61,6 +61,7 @@ class gld_params(C.Structure):
         ("lam_hi", C.c_double),
         ("max_neighbors", C.c_int32),
         ("check_interval", C.c_int32),
+        ("verlet_skin", C.c_double),
     ]
 
 

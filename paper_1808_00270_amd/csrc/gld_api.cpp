@@ -84,12 +84,15 @@ gld_status validate(const gld_params *p)
         return fail(GLD_ERR_INVALID_ARG, "the WCA range 2^(1/6) sigma must not exceed r_cut");
     if (p->noise_tol < 0 || p->noise_tol >= 1) return fail(GLD_ERR_INVALID_ARG, "noise_tol must be in [0, 1)");
     if (p->max_neighbors < 0) return fail(GLD_ERR_INVALID_ARG, "max_neighbors must be >= 0");
+    if (!(p->verlet_skin >= 0) || !std::isfinite(p->verlet_skin))
+        return fail(GLD_ERR_INVALID_ARG, "verlet_skin must be finite and >= 0");
     return GLD_OK;
 }
 
 struct Geometry {
     int64_t S = 0;
     int cap = 0;
+    int capS = 0;  // candidates within r_cut + skin
     int nc[3] = {1, 1, 1};
     int ncell = 1;
     bool fp64 = false, parallel = false;
@@ -113,12 +116,16 @@ Geometry geometry(const gld_params *p)
     }
     g.cap = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g.cap, p->n - 1)));
     g.cap = static_cast<int>(round_up(g.cap, 8));  // lists are stored in chunks of 8 entries
+    // candidate lists within r_cut + skin: the pair capacity scaled by volume
+    const double grow = std::pow((p->r_cut + p->verlet_skin) / p->r_cut, 3.0);
+    g.capS = static_cast<int>(round_up(static_cast<int64_t>(std::ceil(g.cap * grow)), 8));
     // Cells of edge >= r_cut; a work-group of 128 lanes owns one cell, so aim
     // for about 96 particles per cell (larger cells are always valid).
     const double target = 96.0;
     int64_t cells = 1;
     for (int c = 0; c < 3; ++c) {
-        const int by_cut = std::max(1, static_cast<int>(std::floor(p->box[c] / p->r_cut)));
+        // cells of edge >= r_cut + skin hold every candidate in the 27-cell stencil
+        const int by_cut = std::max(1, static_cast<int>(std::floor(p->box[c] / (p->r_cut + p->verlet_skin))));
         const double frac = p->box[c] / std::cbrt(vol);
         const int by_occ = std::max(1, static_cast<int>(std::lround(std::cbrt(p->n / target) * frac)));
         g.nc[c] = std::min(by_cut, by_occ);
@@ -163,8 +170,12 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.ys, v4);
     L.take(d.us, static_cast<size_t>(gld::kMaxRank) * v4);
     L.take(d.pos_s, static_cast<size_t>(n) * 32);
-    L.take(d.relf, static_cast<size_t>(n) * 16);
     L.take(d.reld, static_cast<size_t>(n) * 32);  // both modes: the neighbour build decides in FP64 data
+    L.take(d.relf, static_cast<size_t>(n) * 16);
+    L.take(d.rb_s, static_cast<size_t>(n) * 32);
+    L.take(d.relb, static_cast<size_t>(n) * 32);
+    L.take(d.snl, static_cast<size_t>(g.capS) * n * 4);
+    L.take(d.snn, n * 4);
     L.take(d.U, static_cast<size_t>(g.firw) * vec * elt);
     // white-noise ring: at most the full filter window plus the largest block
     if (p->kT > 0)
@@ -190,6 +201,7 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.d_flags, 8);
     L.take(d.d_flag_step, 8);
     L.take(d.d_rowmax, 8);
+    L.take(d.d_rebuild, 8);
     return L.off + 256;
 }
 
@@ -532,6 +544,9 @@ gld_status prime_noise(gld_system *s)
 
 gld_status refresh_forces(gld_system *s)
 {
+    // a new configuration: rebuild the cell order and candidate lists
+    static const int one = 1;
+    HIP_TRY(hipMemcpyAsync(s->d.d_rebuild, &one, sizeof(int), hipMemcpyHostToDevice, s->st));
     HIP_TRY(gld::launch_neighbors(s->d, s->st, s->d.FC));
     HIP_TRY(hipStreamSynchronize(s->st));
     return GLD_OK;
@@ -631,6 +646,8 @@ gld_status gld_create(const gld_params *params, const double *r0, const double *
     d.seed = p.seed;
     d.cap = s->geo.cap;
     d.maxc = s->geo.maxc;
+    d.capS = s->geo.capS;
+    d.skin = p.verlet_skin;
     d.ncell = s->geo.ncell;
     for (int c = 0; c < 3; ++c) {
         d.nc[c] = s->geo.nc[c];

@@ -69,6 +69,8 @@ struct Dev {
     double wca_sigma = 0, wca_eps = 0;
     uint64_t seed = 0;
     int cap = 0;            // neighbours per particle
+    int capS = 0;           // candidates per particle (within r_cut + skin)
+    double skin = 0;        // Verlet skin (0: rebuild every step)
     int nc[3] = {1, 1, 1};  // cell grid
     int noff[3] = {1, 1, 1};
     int offs[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -95,10 +97,14 @@ struct Dev {
     void *nbw = nullptr;                // T [cap/4][n][4] pair weights (w, or w / R^2 for the parallel tensor)
     void *stab = nullptr;               // int2 [ncell][28] stencil of each cell (first index, base)
     int maxc = 0;                       // candidates staged per round by the mat-vec
+    void *snl = nullptr;                // int [capS/4][n][4] candidate lists (cell-order indices, within r_cut + skin)
+    int *snn = nullptr;                 // [n] candidate counts
+    void *rb_s = nullptr;               // double4 [n] unwrapped positions at the last build, cell order
+    void *relb = nullptr;               // double4 [n] positions relative to own cell at the last build
     int *nn = nullptr;                  // [n] neighbour counts (sorted order)
-    void *pos_s = nullptr;              // double4 [n] wrapped positions, sorted order
-    void *relf = nullptr;               // float4 [n] positions relative to their own cell, sorted
-    void *reld = nullptr;               // double4 [n] the same in double
+    void *pos_s = nullptr;              // double4 [n] wrapped positions, cell order
+    void *reld = nullptr;               // double4 [n] current positions relative to the build-time cell, sorted
+    void *relf = nullptr;               // float4 [n] the same rounded to float
     void *ys = nullptr;                 // T4 [S] dissipative input, sorted order
     void *us = nullptr;                 // T4 [fir_rcap][S] filter outputs of the step, sorted order
     int *cell_id = nullptr, *cell_slot = nullptr, *cell_count = nullptr, *cell_start = nullptr;
@@ -113,6 +119,7 @@ struct Dev {
     int *d_flags = nullptr;     // [0] status, [1] unused
     long long *d_flag_step = nullptr;
     unsigned *d_rowmax = nullptr;  // max row sum of |w| (float bits)
+    int *d_rebuild = nullptr;      // rebuild the cell order and candidate lists this step
 };
 
 constexpr int kPartials = 1024;

@@ -76,15 +76,21 @@ struct Geo {
     double edge[3];  // L / nc
 };
 
-__global__ void k_zero(int *p, int64_t n)
+// The cell list and the candidate lists are rebuilt only when the device
+// flag *gate is set (see k_disp_check); every kernel of the rebuild checks it
+// first, so the same launch sequence serves every step of a graph.
+__global__ void k_zero(int *p, int64_t n, const int *gate)
 {
+    if (gate && *gate == 0) return;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
 }
 
 __global__ void k_cell_assign(const double *__restrict__ R, int64_t S, int64_t n, Geo g, double *__restrict__ Rw,
-                              int *__restrict__ cell_id, int *__restrict__ cell_slot, int *__restrict__ cell_count)
+                              int *__restrict__ cell_id, int *__restrict__ cell_slot, int *__restrict__ cell_count,
+                              const int *gate)
 {
+    if (*gate == 0) return;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int ci[3];
@@ -100,8 +106,9 @@ __global__ void k_cell_assign(const double *__restrict__ R, int64_t S, int64_t n
 }
 
 // exclusive scan of the cell counts by one work-group (chunked)
-__global__ void k_cell_scan(const int *__restrict__ count, int *__restrict__ start, int ncell)
+__global__ void k_cell_scan(const int *__restrict__ count, int *__restrict__ start, int ncell, const int *gate)
 {
+    if (*gate == 0) return;
     __shared__ int part[1024];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int chunk = (ncell + nt - 1) / nt;
@@ -125,21 +132,23 @@ __global__ void k_cell_scan(const int *__restrict__ count, int *__restrict__ sta
 }
 
 __global__ void k_cell_scatter(int64_t n, const int *__restrict__ cell_id, const int *__restrict__ cell_slot,
-                               const int *__restrict__ start, int *__restrict__ tmp)
+                               const int *__restrict__ start, int *__restrict__ tmp, const int *gate)
 {
+    if (*gate == 0) return;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     tmp[start[cell_id[i]] + cell_slot[i]] = static_cast<int>(i);
 }
 
-// rank within the cell by particle id; also the sorted copies of the wrapped
-// positions: absolute (double4) and relative to the particle's own cell
-// origin (float4 and double4, for staging)
+// rank within the cell by particle id; at the build, the sorted copies of
+// the unwrapped positions (rb) and of the wrapped positions relative to the
+// particle's own cell origin (relb); k_rel_update moves both every step
 __global__ void k_cell_order(int64_t n, int64_t S, Geo g, const int *__restrict__ cell_id,
                              const int *__restrict__ start, const int *__restrict__ tmp, int *__restrict__ sorted,
-                             const double *__restrict__ Rw, double4 *__restrict__ pos_s,
-                             float4 *__restrict__ relf, double4 *__restrict__ reld)
+                             const double *__restrict__ R, const double *__restrict__ Rw, double4 *__restrict__ rb,
+                             double4 *__restrict__ relb, const int *gate)
 {
+    if (*gate == 0) return;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int c = cell_id[i];
@@ -148,12 +157,48 @@ __global__ void k_cell_order(int64_t n, int64_t S, Geo g, const int *__restrict_
     for (int k = b; k < e; ++k) rank += tmp[k] < i;
     const int s = b + rank;
     sorted[s] = static_cast<int>(i);
+    rb[s] = make_double4(R[i], R[S + i], R[2 * S + i], 0.0);
     const double x = Rw[i], y = Rw[S + i], z = Rw[2 * S + i];
-    pos_s[s] = make_double4(x, y, z, 0.0);
     const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
-    const double rx = x - cx * g.edge[0], ry = y - cy * g.edge[1], rz = z - cz * g.edge[2];
-    relf[s] = make_float4(static_cast<float>(rx), static_cast<float>(ry), static_cast<float>(rz), 0.f);
-    reld[s] = make_double4(rx, ry, rz, 0.0);
+    relb[s] = make_double4(x - cx * g.edge[0], y - cy * g.edge[1], z - cz * g.edge[2], 0.0);
+}
+
+// Every step, before the rebuild kernels: does some particle lie more than
+// skin/2 from where it was at the last build?  Then the pairs within r_c may
+// include one missing from the candidate list, and the lists are rebuilt.
+__global__ void k_disp_check(int64_t n, int64_t S, const int *__restrict__ sorted, const double *__restrict__ R,
+                             const double4 *__restrict__ rb, double thr2, int *gate)
+{
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool far = false;
+    if (s < n) {
+        const int p = sorted[s];
+        const double4 b = rb[s];
+        const double dx = R[p] - b.x, dy = R[S + p] - b.y, dz = R[2 * S + p] - b.z;
+        far = !(dx * dx + dy * dy + dz * dz <= thr2);  // NaN counts as far
+    }
+    if (__any(far) && (threadIdx.x & 63) == 0) atomicOr(gate, 1);
+}
+
+// Every step, after the rebuild kernels: current positions in the cell order
+// of the last build, relative to the build-time cell (relb + R - rb, from the
+// unwrapped displacement, so crossing the box edge needs no care), as double
+// and float, and wrapped absolute (WCA).  Clears the rebuild flag.
+__global__ void k_rel_update(int64_t n, int64_t S, Geo g, const int *__restrict__ sorted,
+                             const double *__restrict__ R, const double4 *__restrict__ rb,
+                             const double4 *__restrict__ relb, double4 *__restrict__ reld, float4 *__restrict__ relf,
+                             double4 *__restrict__ pos_s, int *gate)
+{
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s == 0) *gate = 0;
+    if (s >= n) return;
+    const int p = sorted[s];
+    const double x = R[p], y = R[S + p], z = R[2 * S + p];
+    const double4 b = rb[s], q = relb[s];
+    const double4 rel = make_double4(q.x + (x - b.x), q.y + (y - b.y), q.z + (z - b.z), 0.0);
+    reld[s] = rel;
+    relf[s] = make_float4(static_cast<float>(rel.x), static_cast<float>(rel.y), static_cast<float>(rel.z), 0.f);
+    pos_s[s] = make_double4(wrap_coord(x, g.L[0]), wrap_coord(y, g.L[1]), wrap_coord(z, g.L[2]), 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,10 +288,17 @@ struct BuildArgs {
     int64_t n, S;
     int ncell;
     const int *cstart, *sorted;
-    const double4 *reld_src;  // positions relative to their own cell, double
+    const double4 *reld_src;  // positions relative to their own (build-time) cell, double
+    const float4 *relf_src;   // the same rounded to float (FP32 refresh)
     const double4 *pos_s;     // wrapped positions (WCA force in FP64)
-    double rc2;
-    int cap;
+    double rc2;               // r_cut^2
+    double rcs2;              // (r_cut + skin)^2: candidate lists
+    int cap, capS;            // pair list / candidate list capacity
+    int *snl;                 // candidate lists [capS/4][n][4] (cell-order indices)
+    int *snn;                 // candidate counts
+    int nst;                  // stencil entries per cell
+    const int *cell_id;       // cell of each particle (original order)
+    const int *gate;          // rebuild flag
     const double *wtab;       // w(r) on the distance grid
     int n_r;
     double r0, dr, r_cut_min, lam_hi;
@@ -255,6 +307,7 @@ struct BuildArgs {
     void *nbw;
     int *nn;
     int2 *stab;
+    const int2 *stab_c;
     double *fc;               // WCA force, [3][S] original order
     unsigned *rowmax;
     int *flags;
@@ -288,66 +341,43 @@ __device__ __forceinline__ T weight_of(const BuildArgs &a, const T *tab, T r)
 }
 
 // ---------------------------------------------------------------------------
-// neighbour build: one work-group per cell, one lane per particle.
-// Candidates are staged in LDS in chunks (positions relative to the home
-// cell, periodic images applied, as float or double).  The wave walks them in
-// lockstep with broadcast reads and only tests the distance, appending the
-// staged index of each hit to the lane's queue in LDS; the queues are then
-// drained with every lane busy (weight, row sum, WCA force, list entry), and
-// list entries leave in whole 8-entry chunks from registers, so every store
-// is a 16-byte vector.  The pair decision is taken in FP64 in the FP64 mode
-// and in FP32 otherwise (a pair within rounding of r_c has w ~ 0 either way);
-// the WCA force is FP64 from the wrapped positions.  Per particle it writes
-// the lists above, nn[s], fc[p], and checks the row sum of |w| (a bound on the
-// spectral norm of P, ||T_ij|| = 1 for both tensor forms) against the top of
-// the noise interval.
+// Neighbour lists in two stages.
+//
+// Build (only when the rebuild flag is set): one work-group per cell, one lane
+// per particle.  Candidates are staged in LDS in chunks (positions relative to
+// the home cell, periodic images applied, as float or double).  The wave walks
+// them in lockstep with broadcast reads and only tests the distance against
+// r_c + skin, appending the staged index of each hit to the lane's queue in
+// LDS; the queues are drained with every lane busy into the candidate list
+// (8-index chunks, one 16-byte store each).
+//
+// Refresh (every step): one work-group per cell stages the current positions
+// of the stencil; each lane walks its particle's candidate list and keeps the
+// pairs within r_c: the pair list with weights (the lists above), the WCA
+// force, and the row sum of |w| (a bound on the spectral norm of P, ||T_ij|| =
+// 1 for both tensor forms) against the top of the noise interval.  The
+// distance is formed exactly as in the build, so with skin 0 the two agree
+// pair for pair.  The pair decision is taken in FP64 in the FP64 mode and in
+// FP32 otherwise (a pair within rounding of r_c has w ~ 0 either way); the WCA
+// force is FP64 from the wrapped positions.
 // ---------------------------------------------------------------------------
 constexpr int kQueue = 48;                     // queued hits per lane
 constexpr int kCheckBlock = 16;                // candidates tested between queue checks
 constexpr int kDrainAt = kQueue - kCheckBlock;  // a queue this long is drained
 
-// one list chunk being filled: 8 staged indices (16 bits each) and 8 weights,
-// kept in scalars so that it stays in registers
-template <typename T>
-struct Chunk {
+// one candidate chunk being filled: 4 cell-order indices
+struct IdxChunk {
     uint32_t i0 = 0, i1 = 0, i2 = 0, i3 = 0;
-    T w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, w6 = 0, w7 = 0;
-    __device__ static __forceinline__ uint32_t ins(uint32_t word, int pos, int k, uint32_t l)
+    __device__ __forceinline__ void put(int pos, uint32_t g)
     {
-        if ((pos >> 1) != k) return word;
-        return (pos & 1) ? ((word & 0xffffu) | (l << 16)) : ((word & 0xffff0000u) | l);
+        i0 = pos == 0 ? g : i0;
+        i1 = pos == 1 ? g : i1;
+        i2 = pos == 2 ? g : i2;
+        i3 = pos == 3 ? g : i3;
     }
-    __device__ __forceinline__ void put(int pos, uint32_t l, T w)
+    __device__ __forceinline__ void store(int *dst, int chunk, int64_t s, int64_t n) const
     {
-        i0 = ins(i0, pos, 0, l);
-        i1 = ins(i1, pos, 1, l);
-        i2 = ins(i2, pos, 2, l);
-        i3 = ins(i3, pos, 3, l);
-        w0 = pos == 0 ? w : w0;
-        w1 = pos == 1 ? w : w1;
-        w2 = pos == 2 ? w : w2;
-        w3 = pos == 3 ? w : w3;
-        w4 = pos == 4 ? w : w4;
-        w5 = pos == 5 ? w : w5;
-        w6 = pos == 6 ? w : w6;
-        w7 = pos == 7 ? w : w7;
-    }
-    __device__ __forceinline__ void store(uint16_t *nbl, void *nbw, int chunk, int64_t s, int64_t n) const
-    {
-        using T4 = typename V4<T>::t;
-        reinterpret_cast<uint4 *>(nbl)[chunk * n + s] = make_uint4(i0, i1, i2, i3);
-        T4 a, b;
-        a.x = w0;
-        a.y = w1;
-        a.z = w2;
-        a.w = w3;
-        b.x = w4;
-        b.y = w5;
-        b.z = w6;
-        b.w = w7;
-        T4 *nbw4 = static_cast<T4 *>(nbw);
-        nbw4[(2 * chunk) * n + s] = a;
-        nbw4[(2 * chunk + 1) * n + s] = b;
+        reinterpret_cast<uint4 *>(dst)[chunk * n + s] = make_uint4(i0, i1, i2, i3);
     }
 };
 
@@ -375,9 +405,10 @@ __device__ __forceinline__ T staged_r2(const double4 *reld, const float4 *relf, 
     }
 }
 
-template <typename T, bool EXACT64, bool PAR, bool MI>
+template <typename T, bool EXACT64, bool MI>
 __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
 {
+    if (*a.gate == 0) return;
     constexpr int CH = EXACT64 ? kBuildChunk / 2 : kBuildChunk;
     __shared__ Stencil st;
     // staged candidates; entries past the end of the stencil hold NaN
@@ -386,10 +417,8 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
     __shared__ double4 reld[EXACT64 ? CH + 4 : 1];
     __shared__ int sid[CH];
     __shared__ uint16_t queue[kQueue][kPairThreads];
-    __shared__ T tab[GLD_MAX_DISTANCE_BINS];
     const int cid = blockIdx.x;
     const int tid = threadIdx.x;
-    for (int b = tid; b < a.n_r; b += kPairThreads) tab[b] = static_cast<T>(a.wtab[b]);
     const double qnan = __builtin_nan("");
     if (tid < 4) {
         if (EXACT64) reld[CH + tid] = make_double4(qnan, qnan, qnan, 0.0);
@@ -407,19 +436,16 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
     const bool store = total <= 65536;  // staged positions must fit 16 bits
     const float Lf[3] = {static_cast<float>(a.g.L[0]), static_cast<float>(a.g.L[1]), static_cast<float>(a.g.L[2])};
     const bool mi[3] = {a.g.nc[0] < 3, a.g.nc[1] < 3, a.g.nc[2] < 3};
-    const T rc2 = static_cast<T>(a.rc2);
+    const T rcs2 = static_cast<T>(a.rcs2);
     const int64_t n = a.n;
-    const double wca_pre = a.wca_rc2 * 1.0001;
     for (int g0 = h0; g0 < h1; g0 += kPairThreads) {
         const int s = g0 + tid;
         const bool live = s < h1;
         const int self_l = st.base[st.home] + (s - h0);
         const double4 xd = live ? a.reld_src[s] : make_double4(0, 0, 0, 0);
-        const double4 xi = live ? a.pos_s[s] : make_double4(0, 0, 0, 0);
         const float xf[3] = {static_cast<float>(xd.x), static_cast<float>(xd.y), static_cast<float>(xd.z)};
         int cnt = 0, nq = 0;
-        double rowsum = 0, fx = 0, fy = 0, fz = 0;
-        Chunk<T> ck;
+        IdxChunk ck;
         for (int c0 = 0; c0 < total; c0 += CH) {
             const int c1 = min(total, c0 + CH);
             __syncthreads();
@@ -433,9 +459,16 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
                     const int t = stencil_entry(st, l);
                     sj[j] = st.start[t] + (l - st.base[t]);
                     v[j] = a.reld_src[sj[j]];
-                    v[j].x += st.offd[t][0];
-                    v[j].y += st.offd[t][1];
-                    v[j].z += st.offd[t][2];
+                    if (EXACT64) {
+                        v[j].x += st.offd[t][0];
+                        v[j].y += st.offd[t][1];
+                        v[j].z += st.offd[t][2];
+                    } else {
+                        // position and image offset each rounded, then added
+                        v[j].x = static_cast<float>(v[j].x) + st.offf[t][0];
+                        v[j].y = static_cast<float>(v[j].y) + st.offf[t][1];
+                        v[j].z = static_cast<float>(v[j].z) + st.offf[t][2];
+                    }
                 }
             }
 #pragma unroll
@@ -457,10 +490,10 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
             if (!live) continue;
             // lockstep distance test, four broadcast candidates per round,
             // appended without branches (a miss writes the next free slot and
-            // does not advance); a queue is drained (all lanes busy on list
-            // entries) once one in the wave could overflow in the next block,
-            // and at the end of the staged chunk.  Blocks start at multiples of
-            // 4 from c0, so a round only runs past c1 into the NaN padding.
+            // does not advance); a queue is drained once one in the wave could
+            // overflow in the next block, and at the end of the staged chunk.
+            // Blocks start at multiples of 4 from c0, so a round only runs
+            // past c1 into the NaN padding.
             const int self_li = self_l - c0;
             for (int b0 = c0;; b0 += kCheckBlock) {
                 const int b1 = min(c1, b0 + kCheckBlock);
@@ -469,51 +502,20 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
                     for (int u = 0; u < 4; ++u) {
                         const int li = l0 + u;
                         const T r2 = staged_r2<T, EXACT64, MI>(reld, relf, li, xd, xf, a.g, mi, Lf);
-                        const bool hit = r2 < rc2 && li != self_li;
+                        const bool hit = r2 < rcs2 && li != self_li;
                         queue[nq][tid] = static_cast<uint16_t>(li);
                         nq += hit ? 1 : 0;
                     }
                 }
                 const bool last = b1 >= c1;
                 if (last || __any(nq >= kDrainAt)) {
-                    for (int e = 0; e < nq; e += 2) {
-                        // two entries per round: their LDS reads and square
-                        // roots overlap
-                        const bool two = e + 1 < nq;
-                        const int lq[2] = {queue[e][tid], two ? queue[e + 1][tid] : queue[e][tid]};
-                        T r2[2], w[2];
-#pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            r2[u] = staged_r2<T, EXACT64, MI>(reld, relf, lq[u], xd, xf, a.g, mi, Lf);
-                            w[u] = weight_of<T>(a, tab, static_cast<T>(sqrt(r2[u])));
+                    for (int e = 0; e < nq; ++e) {
+                        if (store && cnt < a.capS) {
+                            const int pos = cnt & 3;
+                            ck.put(pos, static_cast<uint32_t>(sid[queue[e][tid]]));
+                            if (pos == 3) ck.store(a.snl, cnt >> 2, s, n);
                         }
-#pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            if (u == 1 && !two) break;
-                            rowsum += fabs(static_cast<double>(w[u]));
-                            if (store && cnt < a.cap) {
-                                const int pos = cnt & 7;
-                                ck.put(pos, static_cast<uint32_t>(c0 + lq[u]), PAR ? w[u] / r2[u] : w[u]);
-                                if (pos == 7) ck.store(a.nbl, a.nbw, cnt >> 3, s, n);
-                            }
-                            ++cnt;
-                            if (static_cast<double>(r2[u]) < wca_pre) {
-                                // conservative WCA force in FP64 from the wrapped positions
-                                const double4 xj = a.pos_s[sid[lq[u]]];
-                                double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
-                                gx -= a.g.L[0] * rint(gx / a.g.L[0]);
-                                gy -= a.g.L[1] * rint(gy / a.g.L[1]);
-                                gz -= a.g.L[2] * rint(gz / a.g.L[2]);
-                                const double rd2 = gx * gx + gy * gy + gz * gz;
-                                if (rd2 < a.wca_rc2) {
-                                    const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
-                                    const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
-                                    fx += fr * gx;
-                                    fy += fr * gy;
-                                    fz += fr * gz;
-                                }
-                            }
-                        }
+                        ++cnt;
                     }
                     nq = 0;
                 }
@@ -521,25 +523,201 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
             }
         }
         if (live) {
-            const int kept = store ? min(cnt, a.cap) : 0;
-            if (kept & 7) {
-                // pad the last chunk: zero weight, the particle itself
-                for (int pos = kept & 7; pos < 8; ++pos) ck.put(pos, static_cast<uint32_t>(self_l), T(0));
-                ck.store(a.nbl, a.nbw, kept >> 3, s, n);
+            const int kept = store ? min(cnt, a.capS) : 0;
+            if (kept & 3) {
+                // pad the last chunk with the particle itself (never a pair)
+                for (int pos = kept & 3; pos < 4; ++pos) ck.put(pos, static_cast<uint32_t>(s));
+                ck.store(a.snl, kept >> 2, s, n);
             }
-            if (cnt > a.cap || !store) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
-            a.nn[s] = kept;
-            const int p = a.sorted[s];
-            a.fc[p] = fx;
-            a.fc[a.S + p] = fy;
-            a.fc[2 * a.S + p] = fz;
-            if (rowsum > a.lam_hi) latch(a.flags, a.flag_step, GLD_ERR_INTERVAL, *a.d_step);
+            if (cnt > a.capS || !store) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
+            a.snn[s] = kept;
         }
-        // largest row sum: wave maximum, one atomic per wave
-        float rm = static_cast<float>(rowsum);
-        for (int off = 32; off > 0; off >>= 1) rm = fmaxf(rm, __shfl_xor(rm, off));
-        if ((tid & 63) == 0) atomicMax(a.rowmax, __float_as_uint(rm));
     }
+}
+
+// Refresh, four lanes per particle (cell order), no staging.  The quad walks
+// its particle's candidate list four entries per round, lane q taking entry
+// 4 it + q; the candidate list holds cell-order indices ascending in stencil
+// order, so each lane tracks the stencil entry of its candidates by moving
+// forward (it gives the image offset and the 16-bit staged index of the pair
+// list).  Positions are formed as in the build (FP32: position and image
+// offset each rounded, then added), so with skin 0 the two agree pair for
+// pair.  The pairs of a round get consecutive list positions in entry order
+// (ballot prefix), so the list is the one a single lane would write; entries
+// gather in a 16-slot LDS ring per particle and leave as whole chunks.
+constexpr int kRefreshThreads = 256;
+constexpr int kRefreshParticles = kRefreshThreads / 4;
+constexpr int kXcds = 8;
+
+template <typename T, bool EXACT64, bool PAR, bool MI>
+__global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
+{
+    __shared__ T tab[GLD_MAX_DISTANCE_BINS];
+    __shared__ uint16_t ob_i[16][kRefreshParticles];
+    __shared__ T ob_w[16][kRefreshParticles];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < a.n_r; b += kRefreshThreads) tab[b] = static_cast<T>(a.wtab[b]);
+    __syncthreads();
+    const int pl = tid >> 2, q = tid & 3;  // particle of the block, lane of the quad
+    // work-groups are dealt round-robin to the 8 XCDs: renumber them so that
+    // each XCD takes one contiguous range of the cell order, whose candidates
+    // (that range and its halo) then stay in that XCD's L2
+    const unsigned nblk = static_cast<unsigned>((a.n + kRefreshParticles - 1) / kRefreshParticles);
+    const unsigned per = (nblk + kXcds - 1) / kXcds;
+    const unsigned lb = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int64_t s = static_cast<int64_t>(lb) * kRefreshParticles + pl;
+    if (lb >= nblk || s >= a.n) return;  // whole quads leave together
+    const int64_t n = a.n;
+    const float Lf[3] = {static_cast<float>(a.g.L[0]), static_cast<float>(a.g.L[1]), static_cast<float>(a.g.L[2])};
+    const bool mi[3] = {a.g.nc[0] < 3, a.g.nc[1] < 3, a.g.nc[2] < 3};
+    const T rc2 = static_cast<T>(a.rc2);
+    const T wca_pre = static_cast<T>(a.wca_rc2 * 1.0001);
+    using T4 = typename V4<T>::t;
+    T4 *nbw4 = static_cast<T4 *>(a.nbw);
+    uint4 *nbl4 = reinterpret_cast<uint4 *>(a.nbl);
+    const int p = a.sorted[s];
+    const int2 *row = a.stab_c + static_cast<int64_t>(a.cell_id[p]) * kStab;
+    const int nst = a.nst;
+    const double4 xd = a.reld_src[s];
+    const double4 xi = a.pos_s[s];
+    const float4 xfv = a.relf_src[s];
+    // stencil entry k of this lane's candidates: [start, end) of the cell
+    // order, its base in the staged concatenation, the image offset
+    int k = 0;
+    int2 ek = row[0], ek1 = row[1];
+    int end = ek.x + (ek1.y - ek.y);
+    double ox = 0, oy = 0, oz = 0;
+    auto set_offset = [&]() {
+        const int e0 = k % a.g.noff[0], e1 = (k / a.g.noff[0]) % a.g.noff[1], e2 = k / (a.g.noff[0] * a.g.noff[1]);
+        ox = a.g.offs[0][e0] * a.g.edge[0];
+        oy = a.g.offs[1][e1] * a.g.edge[1];
+        oz = a.g.offs[2][e2] * a.g.edge[2];
+    };
+    set_offset();
+    const int ns = a.snn[s];
+    const int nit = (ns + 3) >> 2;
+    const int *snl = a.snl;
+    const unsigned quad_shift = static_cast<unsigned>(threadIdx.x & 60);  // first lane of the quad in the wave
+    int cnt = 0;  // pairs so far (the same in the four lanes)
+    T rowsum = 0;  // a bound checked with ample margin: work precision suffices
+    double fx = 0, fy = 0, fz = 0;
+    auto flush = [&](int chunk, int half) {
+        uint32_t w32[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            w32[u] = static_cast<uint32_t>(ob_i[half + 2 * u][pl]) |
+                     (static_cast<uint32_t>(ob_i[half + 2 * u + 1][pl]) << 16);
+        nbl4[chunk * n + s] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
+        T4 x, y;
+        x.x = ob_w[half + 0][pl];
+        x.y = ob_w[half + 1][pl];
+        x.z = ob_w[half + 2][pl];
+        x.w = ob_w[half + 3][pl];
+        y.x = ob_w[half + 4][pl];
+        y.y = ob_w[half + 5][pl];
+        y.z = ob_w[half + 6][pl];
+        y.w = ob_w[half + 7][pl];
+        nbw4[(2 * chunk) * n + s] = x;
+        nbw4[(2 * chunk + 1) * n + s] = y;
+    };
+    int gnext = nit > 0 ? snl[s * 4 + q] : 0;
+    for (int it = 0; it < nit; ++it) {
+        const int gg = gnext;
+        if (it + 1 < nit) gnext = snl[((it + 1) * n + s) * 4 + q];
+        bool hit = false;
+        T r2 = 0;
+        if (it * 4 + q < ns) {
+            while ((gg < ek.x || gg >= end) && k + 1 < nst) {  // next stencil entry (the list ascends)
+                ++k;
+                ek = ek1;
+                ek1 = row[k + 1];
+                end = ek.x + (ek1.y - ek.y);
+                set_offset();
+            }
+            if (gg >= ek.x && gg < end) {  // always, for a built list
+                if (EXACT64) {
+                    const double4 v = a.reld_src[gg];
+                    double ux = xd.x - (v.x + ox), uy = xd.y - (v.y + oy), uz = xd.z - (v.z + oz);
+                    if (MI && mi[0]) ux -= a.g.L[0] * rint(ux / a.g.L[0]);
+                    if (MI && mi[1]) uy -= a.g.L[1] * rint(uy / a.g.L[1]);
+                    if (MI && mi[2]) uz -= a.g.L[2] * rint(uz / a.g.L[2]);
+                    r2 = static_cast<T>(ux * ux + uy * uy + uz * uz);
+                } else {
+                    const float4 v = a.relf_src[gg];
+                    float ux = xfv.x - (v.x + static_cast<float>(ox));
+                    float uy = xfv.y - (v.y + static_cast<float>(oy));
+                    float uz = xfv.z - (v.z + static_cast<float>(oz));
+                    if (MI && mi[0]) ux -= Lf[0] * rintf(ux / Lf[0]);
+                    if (MI && mi[1]) uy -= Lf[1] * rintf(uy / Lf[1]);
+                    if (MI && mi[2]) uz -= Lf[2] * rintf(uz / Lf[2]);
+                    r2 = static_cast<T>(ux * ux + uy * uy + uz * uz);
+                }
+                hit = r2 < rc2;
+            }
+        }
+        const unsigned quad = static_cast<unsigned>((__ballot(hit) >> quad_shift) & 0xfull);
+        if (hit) {
+            const int pos = cnt + __popc(quad & ((1u << q) - 1u));
+            const T r = sqrt(r2);
+            const T w = weight_of<T>(a, tab, r);
+            rowsum += fabs(w);
+            if (pos < a.cap) {
+                ob_i[pos & 15][pl] = static_cast<uint16_t>(ek.y + (gg - ek.x));
+                ob_w[pos & 15][pl] = PAR ? w / r2 : w;
+            }
+            if (r2 < wca_pre) {
+                // conservative WCA force in FP64 from the wrapped positions
+                const double4 xj = a.pos_s[gg];
+                double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
+                gx -= a.g.L[0] * rint(gx / a.g.L[0]);
+                gy -= a.g.L[1] * rint(gy / a.g.L[1]);
+                gz -= a.g.L[2] * rint(gz / a.g.L[2]);
+                const double rd2 = gx * gx + gy * gy + gz * gz;
+                if (rd2 < a.wca_rc2) {
+                    const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
+                    const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
+                    fx += fr * gx;
+                    fy += fr * gy;
+                    fz += fr * gz;
+                }
+            }
+        }
+        const int cnt1 = cnt + __popc(quad);
+        // a chunk completed this round: lane 0 of the quad stores it (the
+        // ring's writes above come first in the wave's LDS order)
+        if ((cnt1 >> 3) != (cnt >> 3) && q == 0 && (cnt >> 3) < (a.cap >> 3)) flush(cnt >> 3, ((cnt >> 3) & 1) * 8);
+        cnt = cnt1;
+    }
+    // quad sums (WCA force components in the order of the lanes' entries)
+    for (int off = 1; off < 4; off <<= 1) {
+        rowsum += __shfl_xor(rowsum, off);
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+    }
+    if (q != 0) return;
+    const int kept = min(cnt, a.cap);
+    if (kept & 7) {
+        // pad the last chunk: zero weight, the particle itself (the home cell
+        // is the stencil entry with zero offset on each axis)
+        const int home = ((a.g.noff[2] == 3 ? 1 : 0) * a.g.noff[1] + (a.g.noff[1] == 3 ? 1 : 0)) * a.g.noff[0] +
+                         (a.g.noff[0] == 3 ? 1 : 0);
+        const int2 eh = row[home];
+        const uint16_t self_l = static_cast<uint16_t>(eh.y + (static_cast<int>(s) - eh.x));
+        const int half = ((kept >> 3) & 1) * 8;
+        for (int pos = kept & 7; pos < 8; ++pos) {
+            ob_i[half + pos][pl] = self_l;
+            ob_w[half + pos][pl] = T(0);
+        }
+        flush(kept >> 3, half);
+    }
+    if (cnt > a.cap) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
+    a.nn[s] = kept;
+    a.fc[p] = fx;
+    a.fc[a.S + p] = fy;
+    a.fc[2 * a.S + p] = fz;
+    if (static_cast<double>(rowsum) > a.lam_hi) latch(a.flags, a.flag_step, GLD_ERR_INTERVAL, *a.d_step);
+    atomicMax(a.rowmax, __float_as_uint(static_cast<float>(rowsum)));
 }
 
 // ---------------------------------------------------------------------------
@@ -749,10 +927,12 @@ __global__ __launch_bounds__(BS) void k_mv(MvArgs A)
                             const int e0 = lo % A.g.noff[0], e1 = (lo / A.g.noff[0]) % A.g.noff[1];
                             const int e2 = lo / (A.g.noff[0] * A.g.noff[1]);
                             const double4 q = A.reld[t];
-                            v.w = static_cast<T>(q.x + A.g.offs[0][e0] * A.g.edge[0]);
+                            // as in the neighbour lists: position and image offset
+                            // each in the work precision, then added
+                            v.w = static_cast<T>(q.x) + static_cast<T>(A.g.offs[0][e0] * A.g.edge[0]);
                             T2 yz;
-                            yz.x = static_cast<T>(q.y + A.g.offs[1][e1] * A.g.edge[1]);
-                            yz.y = static_cast<T>(q.z + A.g.offs[2][e2] * A.g.edge[2]);
+                            yz.x = static_cast<T>(q.y) + static_cast<T>(A.g.offs[1][e1] * A.g.edge[1]);
+                            yz.y = static_cast<T>(q.z) + static_cast<T>(A.g.offs[2][e2] * A.g.edge[2]);
                             pyz[l - c0] = yz;
                         }
                         xs[l - c0] = v;
@@ -885,15 +1065,26 @@ hipError_t launch_mv_t(const Dev &d, const MvArgs &A, hipStream_t st)
 }
 
 template <typename T, bool EX>
-void launch_build_t(const Dev &d, const BuildArgs &a, bool mi, hipStream_t st)
+hipError_t launch_build_t(const Dev &d, const BuildArgs &a, bool mi, hipStream_t st)
 {
-    if (d.parallel) {
-        if (mi) k_build<T, EX, true, true><<<d.ncell, kPairThreads, 0, st>>>(a);
-        else k_build<T, EX, true, false><<<d.ncell, kPairThreads, 0, st>>>(a);
-    } else {
-        if (mi) k_build<T, EX, false, true><<<d.ncell, kPairThreads, 0, st>>>(a);
-        else k_build<T, EX, false, false><<<d.ncell, kPairThreads, 0, st>>>(a);
-    }
+    if (mi) k_build<T, EX, true><<<d.ncell, kPairThreads, 0, st>>>(a);
+    else k_build<T, EX, false><<<d.ncell, kPairThreads, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T, bool EX, bool PAR, bool MI>
+hipError_t refresh_k(const BuildArgs &a, hipStream_t st)
+{
+    const unsigned nb = blocks(a.n, kRefreshParticles);
+    k_refresh<T, EX, PAR, MI><<<(nb + kXcds - 1) / kXcds * kXcds, kRefreshThreads, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T, bool EX>
+hipError_t launch_refresh_t(const Dev &d, const BuildArgs &a, bool mi, hipStream_t st)
+{
+    if (d.parallel) return mi ? refresh_k<T, EX, true, true>(a, st) : refresh_k<T, EX, true, false>(a, st);
+    return mi ? refresh_k<T, EX, false, true>(a, st) : refresh_k<T, EX, false, false>(a, st);
 }
 
 }  // namespace
@@ -914,22 +1105,25 @@ int mv_max_staging(int fp64, int parallel)
 hipError_t launch_zero_int(int *p, int64_t n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    k_zero<<<blocks(n, 256), 256, 0, st>>>(p, n);
+    k_zero<<<blocks(n, 256), 256, 0, st>>>(p, n, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
 {
-    hipError_t e;
-    if ((e = launch_zero_int(d.cell_count, d.ncell, st)) != hipSuccess) return e;
-    if ((e = launch_zero_int(reinterpret_cast<int *>(d.d_rowmax), 1, st)) != hipSuccess) return e;
     const Geo g = make_geo(d);
-    k_cell_assign<<<blocks(d.n, 256), 256, 0, st>>>(d.R, d.S, d.n, g, d.Rw, d.cell_id, d.cell_slot, d.cell_count);
-    k_cell_scan<<<1, 1024, 0, st>>>(d.cell_count, d.cell_start, d.ncell);
-    k_cell_scatter<<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.cell_id, d.cell_slot, d.cell_start, d.cell_tmp);
-    k_cell_order<<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.S, g, d.cell_id, d.cell_start, d.cell_tmp, d.cell_sorted,
-                                                   d.Rw, static_cast<double4 *>(d.pos_s),
-                                                   static_cast<float4 *>(d.relf), static_cast<double4 *>(d.reld));
+    const unsigned nb = blocks(d.n, 256);
+    // rebuild the cell order and the candidate lists if some particle moved
+    // more than skin/2 since the last build (or the host asked for it)
+    const double half = 0.5 * d.skin;
+    k_disp_check<<<nb, 256, 0, st>>>(d.n, d.S, d.cell_sorted, d.R, static_cast<const double4 *>(d.rb_s), half * half,
+                                     d.d_rebuild);
+    k_zero<<<blocks(d.ncell, 256), 256, 0, st>>>(d.cell_count, d.ncell, d.d_rebuild);
+    k_cell_assign<<<nb, 256, 0, st>>>(d.R, d.S, d.n, g, d.Rw, d.cell_id, d.cell_slot, d.cell_count, d.d_rebuild);
+    k_cell_scan<<<1, 1024, 0, st>>>(d.cell_count, d.cell_start, d.ncell, d.d_rebuild);
+    k_cell_scatter<<<nb, 256, 0, st>>>(d.n, d.cell_id, d.cell_slot, d.cell_start, d.cell_tmp, d.d_rebuild);
+    k_cell_order<<<nb, 256, 0, st>>>(d.n, d.S, g, d.cell_id, d.cell_start, d.cell_tmp, d.cell_sorted, d.R, d.Rw,
+                                     static_cast<double4 *>(d.rb_s), static_cast<double4 *>(d.relb), d.d_rebuild);
     BuildArgs a{};
     a.g = g;
     a.ncell = d.ncell;
@@ -938,9 +1132,17 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     a.cstart = d.cell_start;
     a.sorted = d.cell_sorted;
     a.reld_src = static_cast<const double4 *>(d.reld);
+    a.relf_src = static_cast<const float4 *>(d.relf);
     a.pos_s = static_cast<const double4 *>(d.pos_s);
     a.rc2 = d.r_cut * d.r_cut;
+    a.rcs2 = (d.r_cut + d.skin) * (d.r_cut + d.skin);
     a.cap = d.cap;
+    a.capS = d.capS;
+    a.snl = static_cast<int *>(d.snl);
+    a.snn = d.snn;
+    a.nst = d.noff[0] * d.noff[1] * d.noff[2];
+    a.cell_id = d.cell_id;
+    a.gate = d.d_rebuild;
     a.wtab = d.wtab;
     a.n_r = d.n_r;
     a.r0 = d.r0;
@@ -955,15 +1157,26 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     a.nbw = d.nbw;
     a.nn = d.nn;
     a.stab = static_cast<int2 *>(d.stab);
+    a.stab_c = static_cast<const int2 *>(d.stab);
     a.fc = fc_out;
     a.rowmax = d.d_rowmax;
     a.flags = d.d_flags;
     a.flag_step = d.d_flag_step;
     a.d_step = d.d_step;
     const bool mi = d.nc[0] < 3 || d.nc[1] < 3 || d.nc[2] < 3;
-    if (d.fp64) launch_build_t<double, true>(d, a, mi, st);
-    else launch_build_t<float, false>(d, a, mi, st);
-    return hipGetLastError();
+    hipError_t e;
+    // the build stages the positions of the build itself (relb)
+    BuildArgs ab = a;
+    ab.reld_src = static_cast<const double4 *>(d.relb);
+    if ((e = d.fp64 ? launch_build_t<double, true>(d, ab, mi, st) : launch_build_t<float, false>(d, ab, mi, st)) !=
+        hipSuccess)
+        return e;
+    // current positions in the build's cell order; clears the rebuild flag
+    k_rel_update<<<nb, 256, 0, st>>>(d.n, d.S, g, d.cell_sorted, d.R, static_cast<const double4 *>(d.rb_s),
+                                     static_cast<const double4 *>(d.relb), static_cast<double4 *>(d.reld),
+                                     static_cast<float4 *>(d.relf), static_cast<double4 *>(d.pos_s), d.d_rebuild);
+    if ((e = launch_zero_int(reinterpret_cast<int *>(d.d_rowmax), 1, st)) != hipSuccess) return e;
+    return d.fp64 ? launch_refresh_t<double, true>(d, a, mi, st) : launch_refresh_t<float, false>(d, a, mi, st);
 }
 
 hipError_t launch_permute(const Dev &d, hipStream_t st, int r)

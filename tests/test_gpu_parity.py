@@ -203,23 +203,59 @@ def test_trajectory_fp64_cfg1(pkg, oracle_mod):
 
 @pytest.mark.parametrize("fp64", [True, False])
 def test_resume_and_graph_replay_are_bitwise(pkg, fp64):
+    # lists rebuilt every step (skin 0): a resumed run is the uninterrupted one
     w = wl.config(1)
-    a = pkg.System.from_workload(w, fp64=fp64)
+    a = pkg.System.from_workload(w, fp64=fp64, verlet_skin=0.0)
     a.step(37)
     ga = a.read_state(history=True)
     a.close()
-    b = pkg.System.from_workload(w, fp64=fp64)
+    b = pkg.System.from_workload(w, fp64=fp64, verlet_skin=0.0)
     b.set_graph(False)
     b.step(20)
     mid = b.read_state(history=True)
     b.close()
-    c = pkg.System.from_workload(w, fp64=fp64)
+    c = pkg.System.from_workload(w, fp64=fp64, verlet_skin=0.0)
     c.write_state(mid["r"], mid["v"], step=mid["step"], history=mid["history"])
     c.step(17)
     gc = c.read_state(history=True)
     c.close()
     for k in ("r", "v", "f_d", "f_r", "history"):
         assert np.array_equal(ga[k], gc[k]), k
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_graph_replay_is_bitwise_with_skin(pkg, fp64):
+    # with a Verlet skin the rebuild decisions are taken on the device, the
+    # same in a replayed graph and in eager launches
+    w = wl.config(2, n=3000, m_max=60)
+    runs = []
+    for graph in (True, False):
+        s = pkg.System.from_workload(w, fp64=fp64)
+        s.set_graph(graph)
+        s.step(60)
+        runs.append(s.read_state(history=True))
+        s.close()
+    for k in ("r", "v", "f_d", "f_r", "history"):
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+
+
+def test_verlet_skin_matches_rebuild_every_step(pkg):
+    # 27 cells, particles moving several skins: the candidate lists must hold
+    # every pair within r_c at every step (a missed pair would change the
+    # forces at the percent level); only the order of the sums differs
+    w = wl.config(2, n=3000, m_max=60)
+    out = {}
+    for skin in (0.0, 0.5):
+        s = pkg.System.from_workload(w, fp64=True, verlet_skin=skin)
+        s.step(150)
+        out[skin] = s.read_state()
+        s.close()
+    R0 = wl.config(2, n=3000, m_max=60).initial_state()[0]
+    moved = np.abs(out[0.0]["r"] - R0).max()
+    log(f"    largest displacement over the run {moved:.3f} (skin 0.5)")
+    assert moved > 0.5
+    for k in ("r", "v", "f_c", "f_d", "f_r"):
+        assert_close(k, out[0.5][k], out[0.0][k], 1e-9, 1e-12)
 
 
 def test_fp32_mixed_tracks_fp64_over_steps(pkg):
