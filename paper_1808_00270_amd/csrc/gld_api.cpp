@@ -174,7 +174,7 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.relf, static_cast<size_t>(n) * 16);
     L.take(d.rb_s, static_cast<size_t>(n) * 32);
     L.take(d.relb, static_cast<size_t>(n) * 32);
-    L.take(d.snl, static_cast<size_t>(g.capS) * n * 4);
+    L.take(d.snl, static_cast<size_t>(g.capS) * n * 2);
     L.take(d.snn, n * 4);
     L.take(d.U, static_cast<size_t>(g.firw) * vec * elt);
     // white-noise ring: at most the full filter window plus the largest block

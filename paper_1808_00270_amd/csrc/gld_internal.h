@@ -97,7 +97,7 @@ struct Dev {
     void *nbw = nullptr;                // T [cap/4][n][4] pair weights (w, or w / R^2 for the parallel tensor)
     void *stab = nullptr;               // int2 [ncell][28] stencil of each cell (first index, base)
     int maxc = 0;                       // candidates staged per round by the mat-vec
-    void *snl = nullptr;                // int [capS/4][n][4] candidate lists (cell-order indices, within r_cut + skin)
+    void *snl = nullptr;                // uint16 [capS/8][n][8] candidate lists (staged indices, within r_cut + skin)
     int *snn = nullptr;                 // [n] candidate counts
     void *rb_s = nullptr;               // double4 [n] unwrapped positions at the last build, cell order
     void *relb = nullptr;               // double4 [n] positions relative to own cell at the last build

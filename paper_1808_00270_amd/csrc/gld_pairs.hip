@@ -18,6 +18,7 @@
 // HBM.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -294,9 +295,10 @@ struct BuildArgs {
     double rc2;               // r_cut^2
     double rcs2;              // (r_cut + skin)^2: candidate lists
     int cap, capS;            // pair list / candidate list capacity
-    int *snl;                 // candidate lists [capS/4][n][4] (cell-order indices)
+    uint4 *snl;               // candidate lists uint16 [capS/8][n][8] (staged indices)
     int *snn;                 // candidate counts
     int nst;                  // stencil entries per cell
+    int stage_n;              // stencil positions the refresh stages in LDS
     const int *cell_id;       // cell of each particle (original order)
     const int *gate;          // rebuild flag
     const double *wtab;       // w(r) on the distance grid
@@ -365,19 +367,22 @@ constexpr int kQueue = 48;                     // queued hits per lane
 constexpr int kCheckBlock = 16;                // candidates tested between queue checks
 constexpr int kDrainAt = kQueue - kCheckBlock;  // a queue this long is drained
 
-// one candidate chunk being filled: 4 cell-order indices
+// one candidate chunk being filled: 8 staged indices of 16 bits
 struct IdxChunk {
     uint32_t i0 = 0, i1 = 0, i2 = 0, i3 = 0;
-    __device__ __forceinline__ void put(int pos, uint32_t g)
+    __device__ __forceinline__ void put(int pos, uint32_t l)
     {
-        i0 = pos == 0 ? g : i0;
-        i1 = pos == 1 ? g : i1;
-        i2 = pos == 2 ? g : i2;
-        i3 = pos == 3 ? g : i3;
+        const int sh = (pos & 1) * 16;
+        const uint32_t keep = ~(0xffffu << sh), v = l << sh;
+        const int w = pos >> 1;
+        i0 = w == 0 ? (i0 & keep) | v : i0;
+        i1 = w == 1 ? (i1 & keep) | v : i1;
+        i2 = w == 2 ? (i2 & keep) | v : i2;
+        i3 = w == 3 ? (i3 & keep) | v : i3;
     }
-    __device__ __forceinline__ void store(int *dst, int chunk, int64_t s, int64_t n) const
+    __device__ __forceinline__ void store(uint4 *dst, int chunk, int64_t s, int64_t n) const
     {
-        reinterpret_cast<uint4 *>(dst)[chunk * n + s] = make_uint4(i0, i1, i2, i3);
+        dst[chunk * n + s] = make_uint4(i0, i1, i2, i3);
     }
 };
 
@@ -415,7 +420,6 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
     // positions, which never pass the distance test
     __shared__ float4 relf[EXACT64 ? 1 : CH + 4];
     __shared__ double4 reld[EXACT64 ? CH + 4 : 1];
-    __shared__ int sid[CH];
     __shared__ uint16_t queue[kQueue][kPairThreads];
     const int cid = blockIdx.x;
     const int tid = threadIdx.x;
@@ -433,7 +437,7 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
     __syncthreads();
     const int h0 = a.cstart[cid], h1 = a.cstart[cid + 1];
     const int total = st.base[st.n];
-    const bool store = total <= 65536;  // staged positions must fit 16 bits
+    const bool store = total < 65536;  // staged indices and the end marker fit 16 bits
     const float Lf[3] = {static_cast<float>(a.g.L[0]), static_cast<float>(a.g.L[1]), static_cast<float>(a.g.L[2])};
     const bool mi[3] = {a.g.nc[0] < 3, a.g.nc[1] < 3, a.g.nc[2] < 3};
     const T rcs2 = static_cast<T>(a.rcs2);
@@ -479,7 +483,6 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
                     else
                         relf[l] = make_float4(static_cast<float>(v[j].x), static_cast<float>(v[j].y),
                                               static_cast<float>(v[j].z), 0.f);
-                    sid[l] = sj[j];
                 } else if (EXACT64) {
                     reld[l] = make_double4(qnan, qnan, qnan, 0.0);
                 } else {
@@ -511,9 +514,9 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
                 if (last || __any(nq >= kDrainAt)) {
                     for (int e = 0; e < nq; ++e) {
                         if (store && cnt < a.capS) {
-                            const int pos = cnt & 3;
-                            ck.put(pos, static_cast<uint32_t>(sid[queue[e][tid]]));
-                            if (pos == 3) ck.store(a.snl, cnt >> 2, s, n);
+                            const int pos = cnt & 7;
+                            ck.put(pos, static_cast<uint32_t>(c0 + queue[e][tid]));
+                            if (pos == 7) ck.store(a.snl, cnt >> 3, s, n);
                         }
                         ++cnt;
                     }
@@ -524,10 +527,11 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
         }
         if (live) {
             const int kept = store ? min(cnt, a.capS) : 0;
-            if (kept & 3) {
-                // pad the last chunk with the particle itself (never a pair)
-                for (int pos = kept & 3; pos < 4; ++pos) ck.put(pos, static_cast<uint32_t>(s));
-                ck.store(a.snl, kept >> 2, s, n);
+            if (kept & 7) {
+                // pad the last chunk with the end marker (index total: no
+                // candidate)
+                for (int pos = kept & 7; pos < 8; ++pos) ck.put(pos, static_cast<uint32_t>(total));
+                ck.store(a.snl, kept >> 3, s, n);
             }
             if (cnt > a.capS || !store) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
             a.snn[s] = kept;
@@ -535,189 +539,323 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
     }
 }
 
-// Refresh, four lanes per particle (cell order), no staging.  The quad walks
-// its particle's candidate list four entries per round, lane q taking entry
-// 4 it + q; the candidate list holds cell-order indices ascending in stencil
-// order, so each lane tracks the stencil entry of its candidates by moving
-// forward (it gives the image offset and the 16-bit staged index of the pair
-// list).  Positions are formed as in the build (FP32: position and image
-// offset each rounded, then added), so with skin 0 the two agree pair for
-// pair.  The pairs of a round get consecutive list positions in entry order
-// (ballot prefix), so the list is the one a single lane would write; entries
-// gather in a 16-slot LDS ring per particle and leave as whole chunks.
+// Refresh, one work-group per cell (the cell order and stencils of the last
+// build).  The current positions of the stencil's particles are staged in LDS
+// with the image offset of their stencil entry, formed as in the build (FP32:
+// position and offset each rounded, then added; FP64 exact), up to stage_n of
+// them; a candidate past those is read from global memory.  Four lanes serve
+// one particle: in round k lane q takes the k-th group of kPerLane candidates
+// of its share (FP32: chunk 4k + q of 8 entries; FP64: half chunks of 4, which
+// keeps the ring below small) and tests them against r_c.  The hits of a round
+// get consecutive list positions in candidate order (a prefix sum over the
+// quad), pass through a ring of kRing entries per particle in LDS and leave as
+// whole 8-entry chunks, one per lane.  The pair list is thus the candidate
+// list filtered in order, and with skin 0 the list a build at r_c would make.
+// (The ring is written and read by the lanes of one wave, whose LDS accesses
+// complete in issue order.)
 constexpr int kRefreshThreads = 256;
-constexpr int kRefreshParticles = kRefreshThreads / 4;
-constexpr int kXcds = 8;
+constexpr int kRefreshGroup = kRefreshThreads / 4;  // particles per round of a work-group
+constexpr size_t kRefreshLds = 80 * 1024;           // per work-group: two per CU
+
+template <typename T>
+struct RefreshShape;
+template <>
+struct RefreshShape<float> {
+    static constexpr int kPerLane = 8;  // candidates per lane and round
+    static constexpr int kRing = 64;    // ring entries per particle, >= 7 + 4 kPerLane
+};
+template <>
+struct RefreshShape<double> {
+    static constexpr int kPerLane = 4;
+    static constexpr int kRing = 32;
+};
+
+// ring rows: 16-byte aligned, consecutive particles on different LDS banks
+template <typename T>
+constexpr int ring_idx_stride() { return RefreshShape<T>::kRing + 8; }
+template <typename T>
+constexpr int ring_w_stride() { return RefreshShape<T>::kRing + 4; }
+
+// LDS of the refresh besides the staged positions (bytes, with slack)
+template <typename T>
+constexpr size_t refresh_fixed_lds()
+{
+    return sizeof(T) * GLD_MAX_DISTANCE_BINS + sizeof(uint16_t) * kRefreshGroup * ring_idx_stride<T>() +
+           sizeof(T) * kRefreshGroup * ring_w_stride<T>() + sizeof(int) * 2 * kStab + sizeof(T) * 3 * kMaxStencil + 512;
+}
+
+// whole-chunk reads of the ring, which is written entry by entry: these
+// types may alias the entries' types, so the compiler keeps the reads after
+// the writes
+typedef uint4 __attribute__((__may_alias__)) uint4_ring;
+typedef float4 __attribute__((__may_alias__)) float4_ring;
+typedef double4 __attribute__((__may_alias__)) double4_ring;
+template <typename T>
+struct RingV4;
+template <>
+struct RingV4<float> {
+    using t = float4_ring;
+};
+template <>
+struct RingV4<double> {
+    using t = double4_ring;
+};
+
+// stencil entry holding staged index l (sb ascending over nst entries)
+__device__ __forceinline__ int entry_of(const int *sb, int nst, int l)
+{
+    int lo = 0, hi = nst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sb[mid] <= l) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// current position of staged candidate l (stencil entry e) relative to the
+// home cell, in the precision of the pair decision
+template <typename T, bool EXACT64>
+__device__ __forceinline__ typename V4<T>::t stencil_pos(const BuildArgs &a, const int *sst, const int *sb,
+                                                         const T (*off)[3], int l, int e)
+{
+    const int t = sst[e] + (l - sb[e]);
+    typename V4<T>::t p;
+    if (EXACT64) {
+        const double4 v = a.reld_src[t];
+        p.x = static_cast<T>(v.x + static_cast<double>(off[e][0]));
+        p.y = static_cast<T>(v.y + static_cast<double>(off[e][1]));
+        p.z = static_cast<T>(v.z + static_cast<double>(off[e][2]));
+    } else {
+        const float4 v = a.relf_src[t];
+        p.x = static_cast<T>(v.x + static_cast<float>(off[e][0]));
+        p.y = static_cast<T>(v.y + static_cast<float>(off[e][1]));
+        p.z = static_cast<T>(v.z + static_cast<float>(off[e][2]));
+    }
+    p.w = T(0);
+    return p;
+}
+
+// the candidate indices of lane q in round k: kPerLane 16-bit entries in
+// kPerLane/2 words; past the list, the end marker
+template <typename T>
+__device__ __forceinline__ void load_candidates(const BuildArgs &a, int64_t s, int k, int q, int nch, uint32_t fill,
+                                                uint32_t (&w)[RefreshShape<T>::kPerLane / 2])
+{
+    if constexpr (RefreshShape<T>::kPerLane == 8) {
+        const int c = 4 * k + q;
+        uint4 v = make_uint4(fill, fill, fill, fill);
+        if (c < nch) v = a.snl[c * a.n + s];
+        w[0] = v.x;
+        w[1] = v.y;
+        w[2] = v.z;
+        w[3] = v.w;
+    } else {
+        const int h = 4 * k + q, c = h >> 1;
+        uint2 v = make_uint2(fill, fill);
+        if (c < nch) v = reinterpret_cast<const uint2 *>(a.snl)[(c * a.n + s) * 2 + (h & 1)];
+        w[0] = v.x;
+        w[1] = v.y;
+    }
+}
 
 template <typename T, bool EXACT64, bool PAR, bool MI>
 __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
 {
+    using T4 = typename V4<T>::t;
+    using RV4 = typename RingV4<T>::t;
+    constexpr int PL = RefreshShape<T>::kPerLane, RING = RefreshShape<T>::kRing;
+    constexpr int RI = ring_idx_stride<T>(), RW = ring_w_stride<T>();
+    extern __shared__ __align__(32) unsigned char rf_lds[];
+    T4 *pos = reinterpret_cast<T4 *>(rf_lds);
     __shared__ T tab[GLD_MAX_DISTANCE_BINS];
-    __shared__ uint16_t ob_i[16][kRefreshParticles];
-    __shared__ T ob_w[16][kRefreshParticles];
+    __shared__ __align__(16) uint16_t ring_i[kRefreshGroup * RI];
+    __shared__ __align__(32) T ring_w[kRefreshGroup * RW];
+    __shared__ int sst[kStab], sb[kStab];
+    __shared__ T off[kMaxStencil][3];
+    __shared__ unsigned blk_max;
+    const int cid = blockIdx.x;
+    const int h0 = a.cstart[cid], occ = a.cstart[cid + 1] - h0;
+    if (occ <= 0) return;  // the whole work-group
     const int tid = threadIdx.x;
+    const int nst = a.nst;
     for (int b = tid; b < a.n_r; b += kRefreshThreads) tab[b] = static_cast<T>(a.wtab[b]);
+    if (tid <= nst) {
+        const int2 e = a.stab_c[static_cast<int64_t>(cid) * kStab + tid];
+        sst[tid] = e.x;
+        sb[tid] = e.y;
+    }
+    if (tid < nst) {
+        const int e0 = tid % a.g.noff[0], e1 = (tid / a.g.noff[0]) % a.g.noff[1];
+        const int e2 = tid / (a.g.noff[0] * a.g.noff[1]);
+        off[tid][0] = static_cast<T>(a.g.offs[0][e0] * a.g.edge[0]);
+        off[tid][1] = static_cast<T>(a.g.offs[1][e1] * a.g.edge[1]);
+        off[tid][2] = static_cast<T>(a.g.offs[2][e2] * a.g.edge[2]);
+    }
+    if (tid == 0) blk_max = 0u;
     __syncthreads();
-    const int pl = tid >> 2, q = tid & 3;  // particle of the block, lane of the quad
-    // work-groups are dealt round-robin to the 8 XCDs: renumber them so that
-    // each XCD takes one contiguous range of the cell order, whose candidates
-    // (that range and its halo) then stay in that XCD's L2
-    const unsigned nblk = static_cast<unsigned>((a.n + kRefreshParticles - 1) / kRefreshParticles);
-    const unsigned per = (nblk + kXcds - 1) / kXcds;
-    const unsigned lb = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
-    const int64_t s = static_cast<int64_t>(lb) * kRefreshParticles + pl;
-    if (lb >= nblk || s >= a.n) return;  // whole quads leave together
+    const int total = sb[nst];
+    const int nstage = min(total, a.stage_n);
+    for (int l = tid; l < nstage; l += kRefreshThreads)
+        pos[l] = stencil_pos<T, EXACT64>(a, sst, sb, off, l, entry_of(sb, nst, l));
+    __syncthreads();
+
+    const int pl = tid >> 2, q = tid & 3;  // particle of the round, lane of the quad
     const int64_t n = a.n;
-    const float Lf[3] = {static_cast<float>(a.g.L[0]), static_cast<float>(a.g.L[1]), static_cast<float>(a.g.L[2])};
-    const bool mi[3] = {a.g.nc[0] < 3, a.g.nc[1] < 3, a.g.nc[2] < 3};
     const T rc2 = static_cast<T>(a.rc2);
     const T wca_pre = static_cast<T>(a.wca_rc2 * 1.0001);
-    using T4 = typename V4<T>::t;
-    T4 *nbw4 = static_cast<T4 *>(a.nbw);
+    const T Lw[3] = {static_cast<T>(a.g.L[0]), static_cast<T>(a.g.L[1]), static_cast<T>(a.g.L[2])};
+    const bool mi[3] = {a.g.nc[0] < 3, a.g.nc[1] < 3, a.g.nc[2] < 3};
+    const int capc = a.cap >> 3;
+    const uint32_t fill = static_cast<uint32_t>(total) * 0x10001u;
+    // the home cell is the stencil entry with zero offset on each axis
+    const int home = ((a.g.noff[2] == 3 ? 1 : 0) * a.g.noff[1] + (a.g.noff[1] == 3 ? 1 : 0)) * a.g.noff[0] +
+                     (a.g.noff[0] == 3 ? 1 : 0);
+    uint16_t *ri = ring_i + pl * RI;
+    T *rw = ring_w + pl * RW;
     uint4 *nbl4 = reinterpret_cast<uint4 *>(a.nbl);
-    const int p = a.sorted[s];
-    const int2 *row = a.stab_c + static_cast<int64_t>(a.cell_id[p]) * kStab;
-    const int nst = a.nst;
-    const double4 xd = a.reld_src[s];
-    const double4 xi = a.pos_s[s];
-    const float4 xfv = a.relf_src[s];
-    // stencil entry k of this lane's candidates: [start, end) of the cell
-    // order, its base in the staged concatenation, the image offset
-    int k = 0;
-    int2 ek = row[0], ek1 = row[1];
-    int end = ek.x + (ek1.y - ek.y);
-    double ox = 0, oy = 0, oz = 0;
-    auto set_offset = [&]() {
-        const int e0 = k % a.g.noff[0], e1 = (k / a.g.noff[0]) % a.g.noff[1], e2 = k / (a.g.noff[0] * a.g.noff[1]);
-        ox = a.g.offs[0][e0] * a.g.edge[0];
-        oy = a.g.offs[1][e1] * a.g.edge[1];
-        oz = a.g.offs[2][e2] * a.g.edge[2];
-    };
-    set_offset();
-    const int ns = a.snn[s];
-    const int nit = (ns + 3) >> 2;
-    const int *snl = a.snl;
-    const unsigned quad_shift = static_cast<unsigned>(threadIdx.x & 60);  // first lane of the quad in the wave
-    int cnt = 0;  // pairs so far (the same in the four lanes)
-    T rowsum = 0;  // a bound checked with ample margin: work precision suffices
-    double fx = 0, fy = 0, fz = 0;
-    auto flush = [&](int chunk, int half) {
-        uint32_t w32[4];
+    T4 *nbw4 = static_cast<T4 *>(a.nbw);
+    for (int g0 = 0; g0 < occ; g0 += kRefreshGroup) {
+        const bool live = g0 + pl < occ;
+        const int64_t s = h0 + g0 + pl;
+        T ox = 0, oy = 0, oz = 0;
+        int ns = 0;
+        if (live) {
+            if (EXACT64) {
+                const double4 v = a.reld_src[s];
+                ox = static_cast<T>(v.x);
+                oy = static_cast<T>(v.y);
+                oz = static_cast<T>(v.z);
+            } else {
+                const float4 v = a.relf_src[s];
+                ox = static_cast<T>(v.x);
+                oy = static_cast<T>(v.y);
+                oz = static_cast<T>(v.z);
+            }
+            ns = a.snn[s];
+        }
+        const int nch = (ns + 7) >> 3;
+        const int nround = (ns + 4 * PL - 1) / (4 * PL);
+        int cnt = 0;  // pairs so far (the same in the four lanes)
+        T rowsum = 0;  // a bound checked with ample margin: work precision suffices
+        double fx = 0, fy = 0, fz = 0;
+        uint32_t nxt[PL / 2];
+        load_candidates<T>(a, s, 0, q, nch, fill, nxt);
+        for (int k = 0; k < nround; ++k) {
+            uint32_t cur[PL / 2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            w32[u] = static_cast<uint32_t>(ob_i[half + 2 * u][pl]) |
-                     (static_cast<uint32_t>(ob_i[half + 2 * u + 1][pl]) << 16);
-        nbl4[chunk * n + s] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
-        T4 x, y;
-        x.x = ob_w[half + 0][pl];
-        x.y = ob_w[half + 1][pl];
-        x.z = ob_w[half + 2][pl];
-        x.w = ob_w[half + 3][pl];
-        y.x = ob_w[half + 4][pl];
-        y.y = ob_w[half + 5][pl];
-        y.z = ob_w[half + 6][pl];
-        y.w = ob_w[half + 7][pl];
-        nbw4[(2 * chunk) * n + s] = x;
-        nbw4[(2 * chunk + 1) * n + s] = y;
-    };
-    int gnext = nit > 0 ? snl[s * 4 + q] : 0;
-    for (int it = 0; it < nit; ++it) {
-        const int gg = gnext;
-        if (it + 1 < nit) gnext = snl[((it + 1) * n + s) * 4 + q];
-        bool hit = false;
-        T r2 = 0;
-        if (it * 4 + q < ns) {
-            while ((gg < ek.x || gg >= end) && k + 1 < nst) {  // next stencil entry (the list ascends)
-                ++k;
-                ek = ek1;
-                ek1 = row[k + 1];
-                end = ek.x + (ek1.y - ek.y);
-                set_offset();
-            }
-            if (gg >= ek.x && gg < end) {  // always, for a built list
-                if (EXACT64) {
-                    const double4 v = a.reld_src[gg];
-                    double ux = xd.x - (v.x + ox), uy = xd.y - (v.y + oy), uz = xd.z - (v.z + oz);
-                    if (MI && mi[0]) ux -= a.g.L[0] * rint(ux / a.g.L[0]);
-                    if (MI && mi[1]) uy -= a.g.L[1] * rint(uy / a.g.L[1]);
-                    if (MI && mi[2]) uz -= a.g.L[2] * rint(uz / a.g.L[2]);
-                    r2 = static_cast<T>(ux * ux + uy * uy + uz * uz);
+            for (int u = 0; u < PL / 2; ++u) cur[u] = nxt[u];
+            if (k + 1 < nround) load_candidates<T>(a, s, k + 1, q, nch, fill, nxt);
+            int lv[PL];
+            T r2v[PL];
+            unsigned mask = 0;
+#pragma unroll
+            for (int u = 0; u < PL; ++u) {
+                const int l = static_cast<int>((cur[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
+                lv[u] = l;
+                T4 p;
+                if (l < nstage) {
+                    p = pos[l];
+                } else if (l < total) {
+                    p = stencil_pos<T, EXACT64>(a, sst, sb, off, l, entry_of(sb, nst, l));
                 } else {
-                    const float4 v = a.relf_src[gg];
-                    float ux = xfv.x - (v.x + static_cast<float>(ox));
-                    float uy = xfv.y - (v.y + static_cast<float>(oy));
-                    float uz = xfv.z - (v.z + static_cast<float>(oz));
-                    if (MI && mi[0]) ux -= Lf[0] * rintf(ux / Lf[0]);
-                    if (MI && mi[1]) uy -= Lf[1] * rintf(uy / Lf[1]);
-                    if (MI && mi[2]) uz -= Lf[2] * rintf(uz / Lf[2]);
-                    r2 = static_cast<T>(ux * ux + uy * uy + uz * uz);
+                    p.x = ox;
+                    p.y = oy;
+                    p.z = oz;
                 }
-                hit = r2 < rc2;
+                T ux = ox - p.x, uy = oy - p.y, uz = oz - p.z;
+                if (MI && mi[0]) ux -= Lw[0] * rint(ux / Lw[0]);
+                if (MI && mi[1]) uy -= Lw[1] * rint(uy / Lw[1]);
+                if (MI && mi[2]) uz -= Lw[2] * rint(uz / Lw[2]);
+                const T r2 = ux * ux + uy * uy + uz * uz;
+                r2v[u] = r2;
+                mask |= (l < total && r2 < rc2) ? (1u << u) : 0u;
             }
-        }
-        const unsigned quad = static_cast<unsigned>((__ballot(hit) >> quad_shift) & 0xfull);
-        if (hit) {
-            const int pos = cnt + __popc(quad & ((1u << q) - 1u));
-            const T r = sqrt(r2);
-            const T w = weight_of<T>(a, tab, r);
-            rowsum += fabs(w);
-            if (pos < a.cap) {
-                ob_i[pos & 15][pl] = static_cast<uint16_t>(ek.y + (gg - ek.x));
-                ob_w[pos & 15][pl] = PAR ? w / r2 : w;
-            }
-            if (r2 < wca_pre) {
-                // conservative WCA force in FP64 from the wrapped positions
-                const double4 xj = a.pos_s[gg];
-                double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
-                gx -= a.g.L[0] * rint(gx / a.g.L[0]);
-                gy -= a.g.L[1] * rint(gy / a.g.L[1]);
-                gz -= a.g.L[2] * rint(gz / a.g.L[2]);
-                const double rd2 = gx * gx + gy * gy + gz * gz;
-                if (rd2 < a.wca_rc2) {
-                    const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
-                    const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
-                    fx += fr * gx;
-                    fy += fr * gy;
-                    fz += fr * gz;
+            // list positions of this lane's hits: after those of the lanes
+            // before it in the quad
+            const int c = __popc(mask);
+            int inc = c;
+            int t = __shfl_up(inc, 1, 4);
+            if (q >= 1) inc += t;
+            t = __shfl_up(inc, 2, 4);
+            if (q >= 2) inc += t;
+            const int tot = __shfl(inc, 3, 4);
+            int at = cnt + inc - c;
+#pragma unroll
+            for (int u = 0; u < PL; ++u) {
+                if ((mask >> u) & 1u) {
+                    const T r2 = r2v[u];
+                    const T w = weight_of<T>(a, tab, sqrt(r2));
+                    rowsum += fabs(w);
+                    const int slot = at & (RING - 1);
+                    ri[slot] = static_cast<uint16_t>(lv[u]);
+                    rw[slot] = PAR ? w / r2 : w;
+                    ++at;
+                    if (r2 < wca_pre) {
+                        // conservative WCA force in FP64 from the wrapped positions
+                        const int e = entry_of(sb, nst, lv[u]);
+                        const double4 xi = a.pos_s[s];
+                        const double4 xj = a.pos_s[sst[e] + (lv[u] - sb[e])];
+                        double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
+                        gx -= a.g.L[0] * rint(gx / a.g.L[0]);
+                        gy -= a.g.L[1] * rint(gy / a.g.L[1]);
+                        gz -= a.g.L[2] * rint(gz / a.g.L[2]);
+                        const double rd2 = gx * gx + gy * gy + gz * gz;
+                        if (rd2 < a.wca_rc2) {
+                            const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
+                            const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
+                            fx += fr * gx;
+                            fy += fr * gy;
+                            fz += fr * gz;
+                        }
+                    }
                 }
             }
+            // chunks completed this round, one per lane
+            const int cnt1 = cnt + tot;
+            const int fc = (cnt >> 3) + q;
+            if (fc < (cnt1 >> 3) && fc < capc) {
+                const int base = (fc * 8) & (RING - 1);
+                nbl4[fc * n + s] = *reinterpret_cast<const uint4_ring *>(ri + base);
+                nbw4[(2 * fc) * n + s] = *reinterpret_cast<const RV4 *>(rw + base);
+                nbw4[(2 * fc + 1) * n + s] = *reinterpret_cast<const RV4 *>(rw + base + 4);
+            }
+            cnt = cnt1;
         }
-        const int cnt1 = cnt + __popc(quad);
-        // a chunk completed this round: lane 0 of the quad stores it (the
-        // ring's writes above come first in the wave's LDS order)
-        if ((cnt1 >> 3) != (cnt >> 3) && q == 0 && (cnt >> 3) < (a.cap >> 3)) flush(cnt >> 3, ((cnt >> 3) & 1) * 8);
-        cnt = cnt1;
-    }
-    // quad sums (WCA force components in the order of the lanes' entries)
-    for (int off = 1; off < 4; off <<= 1) {
-        rowsum += __shfl_xor(rowsum, off);
-        fx += __shfl_xor(fx, off);
-        fy += __shfl_xor(fy, off);
-        fz += __shfl_xor(fz, off);
-    }
-    if (q != 0) return;
-    const int kept = min(cnt, a.cap);
-    if (kept & 7) {
-        // pad the last chunk: zero weight, the particle itself (the home cell
-        // is the stencil entry with zero offset on each axis)
-        const int home = ((a.g.noff[2] == 3 ? 1 : 0) * a.g.noff[1] + (a.g.noff[1] == 3 ? 1 : 0)) * a.g.noff[0] +
-                         (a.g.noff[0] == 3 ? 1 : 0);
-        const int2 eh = row[home];
-        const uint16_t self_l = static_cast<uint16_t>(eh.y + (static_cast<int>(s) - eh.x));
-        const int half = ((kept >> 3) & 1) * 8;
-        for (int pos = kept & 7; pos < 8; ++pos) {
-            ob_i[half + pos][pl] = self_l;
-            ob_w[half + pos][pl] = T(0);
+        // quad sums (WCA force components in the order of the lanes' entries)
+        for (int o = 1; o < 4; o <<= 1) {
+            rowsum += __shfl_xor(rowsum, o);
+            fx += __shfl_xor(fx, o);
+            fy += __shfl_xor(fy, o);
+            fz += __shfl_xor(fz, o);
         }
-        flush(kept >> 3, half);
+        if (live && q == 0) {
+            const int kept = min(cnt, a.cap);
+            if (kept & 7) {
+                // pad the last chunk: zero weight, the particle itself
+                const uint16_t self_l = static_cast<uint16_t>(sb[home] + (static_cast<int>(s) - sst[home]));
+                for (int p = kept; p < ((kept + 7) & ~7); ++p) {
+                    ri[p & (RING - 1)] = self_l;
+                    rw[p & (RING - 1)] = T(0);
+                }
+                const int fl = kept >> 3, base = (fl * 8) & (RING - 1);
+                nbl4[fl * n + s] = *reinterpret_cast<const uint4_ring *>(ri + base);
+                nbw4[(2 * fl) * n + s] = *reinterpret_cast<const RV4 *>(rw + base);
+                nbw4[(2 * fl + 1) * n + s] = *reinterpret_cast<const RV4 *>(rw + base + 4);
+            }
+            if (cnt > a.cap) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
+            a.nn[s] = kept;
+            const int p = a.sorted[s];
+            a.fc[p] = fx;
+            a.fc[a.S + p] = fy;
+            a.fc[2 * a.S + p] = fz;
+            if (static_cast<double>(rowsum) > a.lam_hi) latch(a.flags, a.flag_step, GLD_ERR_INTERVAL, *a.d_step);
+            // row sums are >= 0, so their float bits order as unsigned
+            // integers; one global atomic per work-group
+            atomicMax(&blk_max, __float_as_uint(static_cast<float>(rowsum)));
+        }
     }
-    if (cnt > a.cap) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
-    a.nn[s] = kept;
-    a.fc[p] = fx;
-    a.fc[a.S + p] = fy;
-    a.fc[2 * a.S + p] = fz;
-    if (static_cast<double>(rowsum) > a.lam_hi) latch(a.flags, a.flag_step, GLD_ERR_INTERVAL, *a.d_step);
-    atomicMax(a.rowmax, __float_as_uint(static_cast<float>(rowsum)));
+    __syncthreads();
+    if (tid == 0) atomicMax(a.rowmax, blk_max);
 }
 
 // ---------------------------------------------------------------------------
@@ -1073,18 +1211,23 @@ hipError_t launch_build_t(const Dev &d, const BuildArgs &a, bool mi, hipStream_t
 }
 
 template <typename T, bool EX, bool PAR, bool MI>
-hipError_t refresh_k(const BuildArgs &a, hipStream_t st)
+hipError_t refresh_k(const Dev &d, const BuildArgs &a, hipStream_t st)
 {
-    const unsigned nb = blocks(a.n, kRefreshParticles);
-    k_refresh<T, EX, PAR, MI><<<(nb + kXcds - 1) / kXcds * kXcds, kRefreshThreads, 0, st>>>(a);
+    const size_t shm = static_cast<size_t>(a.stage_n) * sizeof(typename V4<T>::t);
+    k_refresh<T, EX, PAR, MI><<<d.ncell, kRefreshThreads, shm, st>>>(a);
     return hipGetLastError();
 }
 
 template <typename T, bool EX>
-hipError_t launch_refresh_t(const Dev &d, const BuildArgs &a, bool mi, hipStream_t st)
+hipError_t launch_refresh_t(const Dev &d, BuildArgs a, bool mi, hipStream_t st)
 {
-    if (d.parallel) return mi ? refresh_k<T, EX, true, true>(a, st) : refresh_k<T, EX, true, false>(a, st);
-    return mi ? refresh_k<T, EX, false, true>(a, st) : refresh_k<T, EX, false, false>(a, st);
+    // stage the expected stencil (the mat-vec's estimate) as far as the LDS
+    // budget of two work-groups per CU allows
+    constexpr size_t per = sizeof(typename V4<T>::t);
+    const int room = static_cast<int>((kRefreshLds - refresh_fixed_lds<T>()) / per);
+    a.stage_n = std::max(0, std::min(d.maxc, room));
+    if (d.parallel) return mi ? refresh_k<T, EX, true, true>(d, a, st) : refresh_k<T, EX, true, false>(d, a, st);
+    return mi ? refresh_k<T, EX, false, true>(d, a, st) : refresh_k<T, EX, false, false>(d, a, st);
 }
 
 }  // namespace
@@ -1138,7 +1281,7 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     a.rcs2 = (d.r_cut + d.skin) * (d.r_cut + d.skin);
     a.cap = d.cap;
     a.capS = d.capS;
-    a.snl = static_cast<int *>(d.snl);
+    a.snl = static_cast<uint4 *>(d.snl);
     a.snn = d.snn;
     a.nst = d.noff[0] * d.noff[1] * d.noff[2];
     a.cell_id = d.cell_id;
