@@ -45,6 +45,17 @@ struct V4<double> {
     using t = double4;
 };
 
+template <typename T>
+struct V2;
+template <>
+struct V2<float> {
+    using t = float2;
+};
+template <>
+struct V2<double> {
+    using t = double2;
+};
+
 __device__ __forceinline__ void latch(int *flags, long long *flag_step, int code, long long step)
 {
     if (atomicCAS(flags, 0, code) == 0) *flag_step = step;
@@ -342,6 +353,30 @@ __device__ __forceinline__ T weight_of(const BuildArgs &a, const T *tab, T r)
     return w0 + f * (w1 - w0);
 }
 
+// the same from a table of pairs (w_b, w_{b+1}): one LDS read per weight
+template <typename T>
+__device__ __forceinline__ T weight_of2(const BuildArgs &a, const typename V2<T>::t *tab2, T r)
+{
+    if (sizeof(T) == 8) {
+        double rr = static_cast<double>(r);
+        if (rr < a.r_cut_min) rr = a.r_cut_min;
+        const double t = fmax((rr - a.r0) / a.dr, 0.0);
+        const double tb = fmin(floor(t), static_cast<double>(a.n_r - 2));
+        const int b = static_cast<int>(fmax(tb, 0.0));
+        const double f = t - b;
+        const typename V2<T>::t e = tab2[b];
+        return static_cast<T>(static_cast<double>(e.x) * (1.0 - f) + static_cast<double>(e.y) * f);
+    }
+    const T rmin = static_cast<T>(a.r_cut_min);
+    const T rr = r < rmin ? rmin : r;
+    const T t = fmax((rr - static_cast<T>(a.r0)) * static_cast<T>(1.0 / a.dr), T(0));
+    const T tb = fmin(floor(t), static_cast<T>(a.n_r - 2));
+    const int b = static_cast<int>(fmax(tb, T(0)));
+    const T f = t - static_cast<T>(b);
+    const typename V2<T>::t e = tab2[b];
+    return e.x + f * (e.y - e.x);
+}
+
 // ---------------------------------------------------------------------------
 // Neighbour lists in two stages.
 //
@@ -580,7 +615,7 @@ constexpr int ring_w_stride() { return RefreshShape<T>::kRing + 4; }
 template <typename T>
 constexpr size_t refresh_fixed_lds()
 {
-    return sizeof(T) * GLD_MAX_DISTANCE_BINS + sizeof(uint16_t) * kRefreshGroup * ring_idx_stride<T>() +
+    return 2 * sizeof(T) * GLD_MAX_DISTANCE_BINS + sizeof(uint16_t) * kRefreshGroup * ring_idx_stride<T>() +
            sizeof(T) * kRefreshGroup * ring_w_stride<T>() + sizeof(int) * 2 * kStab + sizeof(T) * 3 * kMaxStencil + 512;
 }
 
@@ -658,6 +693,34 @@ __device__ __forceinline__ void load_candidates(const BuildArgs &a, int64_t s, i
     }
 }
 
+// entry u (not a compile-time constant) of a lane's candidate words, by
+// shifts of 64-bit halves (an indexed read would place the words in scratch)
+template <int NW>
+__device__ __forceinline__ int cand_at(const uint32_t (&w)[NW], int u)
+{
+    static_assert(NW == 2 || NW == 4, "two or four candidate words");
+    const uint64_t lo = (static_cast<uint64_t>(w[1]) << 32) | w[0];
+    uint64_t x = lo;
+    if constexpr (NW == 4) {
+        const uint64_t hi = (static_cast<uint64_t>(w[3]) << 32) | w[2];
+        x = u < 4 ? lo : hi;
+    }
+    return static_cast<int>((x >> ((u & 3) * 16)) & 0xffffu);
+}
+
+// exclusive prefix sum of c over the four lanes of a quad (DPP quad
+// permutes: lane q reads lane q-1, then lane q-2), and the quad's total
+__device__ __forceinline__ int quad_scan(int c, int q, int &tot)
+{
+    int inc = c;
+    int t = __builtin_amdgcn_update_dpp(0, inc, 0x90, 0xf, 0xf, false);  // quad_perm [0,0,1,2]
+    inc += q >= 1 ? t : 0;
+    t = __builtin_amdgcn_update_dpp(0, inc, 0x40, 0xf, 0xf, false);  // quad_perm [0,0,0,1]
+    inc += q >= 2 ? t : 0;
+    tot = __builtin_amdgcn_update_dpp(0, inc, 0xff, 0xf, 0xf, false);  // quad_perm [3,3,3,3]
+    return inc - c;
+}
+
 template <typename T, bool EXACT64, bool PAR, bool MI>
 __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
 {
@@ -667,7 +730,8 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
     constexpr int RI = ring_idx_stride<T>(), RW = ring_w_stride<T>();
     extern __shared__ __align__(32) unsigned char rf_lds[];
     T4 *pos = reinterpret_cast<T4 *>(rf_lds);
-    __shared__ T tab[GLD_MAX_DISTANCE_BINS];
+    using T2 = typename V2<T>::t;
+    __shared__ T2 tab2[GLD_MAX_DISTANCE_BINS];
     __shared__ __align__(16) uint16_t ring_i[kRefreshGroup * RI];
     __shared__ __align__(32) T ring_w[kRefreshGroup * RW];
     __shared__ int sst[kStab], sb[kStab];
@@ -678,7 +742,12 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
     if (occ <= 0) return;  // the whole work-group
     const int tid = threadIdx.x;
     const int nst = a.nst;
-    for (int b = tid; b < a.n_r; b += kRefreshThreads) tab[b] = static_cast<T>(a.wtab[b]);
+    for (int b = tid; b < a.n_r; b += kRefreshThreads) {
+        T2 e;
+        e.x = static_cast<T>(a.wtab[b]);
+        e.y = static_cast<T>(a.wtab[min(b + 1, a.n_r - 1)]);
+        tab2[b] = e;
+    }
     if (tid <= nst) {
         const int2 e = a.stab_c[static_cast<int64_t>(cid) * kStab + tid];
         sst[tid] = e.x;
@@ -695,8 +764,11 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
     __syncthreads();
     const int total = sb[nst];
     const int nstage = min(total, a.stage_n);
+    // all candidates staged (one slot more holds the end marker's read)
+    const bool full = nstage == total;
     for (int l = tid; l < nstage; l += kRefreshThreads)
         pos[l] = stencil_pos<T, EXACT64>(a, sst, sb, off, l, entry_of(sb, nst, l));
+    if (tid == 0) pos[nstage] = T4{};
     __syncthreads();
 
     const int pl = tid >> 2, q = tid & 3;  // particle of the round, lane of the quad
@@ -745,69 +817,80 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
 #pragma unroll
             for (int u = 0; u < PL / 2; ++u) cur[u] = nxt[u];
             if (k + 1 < nround) load_candidates<T>(a, s, k + 1, q, nch, fill, nxt);
+            // the round runs in phases of straight-line code (positions,
+            // distances, weights, ring writes), so that the LDS reads of its
+            // candidates are in flight together
             int lv[PL];
-            T r2v[PL];
-            unsigned mask = 0;
+            T4 pv[PL];
+            unsigned gmask = 0;  // candidates past the staged part of the stencil
 #pragma unroll
             for (int u = 0; u < PL; ++u) {
                 const int l = static_cast<int>((cur[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
                 lv[u] = l;
-                T4 p;
-                if (l < nstage) {
-                    p = pos[l];
-                } else if (l < total) {
-                    p = stencil_pos<T, EXACT64>(a, sst, sb, off, l, entry_of(sb, nst, l));
-                } else {
-                    p.x = ox;
-                    p.y = oy;
-                    p.z = oz;
-                }
-                T ux = ox - p.x, uy = oy - p.y, uz = oz - p.z;
+                pv[u] = pos[min(l, nstage)];
+                gmask |= (l >= nstage && l < total) ? (1u << u) : 0u;
+            }
+            if (gmask) {
+#pragma unroll
+                for (int u = 0; u < PL; ++u)
+                    if ((gmask >> u) & 1u)
+                        pv[u] = stencil_pos<T, EXACT64>(a, sst, sb, off, lv[u], entry_of(sb, nst, lv[u]));
+            }
+            T r2v[PL];
+            unsigned mask = 0;
+#pragma unroll
+            for (int u = 0; u < PL; ++u) {
+                T ux = ox - pv[u].x, uy = oy - pv[u].y, uz = oz - pv[u].z;
                 if (MI && mi[0]) ux -= Lw[0] * rint(ux / Lw[0]);
                 if (MI && mi[1]) uy -= Lw[1] * rint(uy / Lw[1]);
                 if (MI && mi[2]) uz -= Lw[2] * rint(uz / Lw[2]);
                 const T r2 = ux * ux + uy * uy + uz * uz;
                 r2v[u] = r2;
-                mask |= (l < total && r2 < rc2) ? (1u << u) : 0u;
+                mask |= (lv[u] < total && r2 < rc2) ? (1u << u) : 0u;
             }
             // list positions of this lane's hits: after those of the lanes
             // before it in the quad
-            const int c = __popc(mask);
-            int inc = c;
-            int t = __shfl_up(inc, 1, 4);
-            if (q >= 1) inc += t;
-            t = __shfl_up(inc, 2, 4);
-            if (q >= 2) inc += t;
-            const int tot = __shfl(inc, 3, 4);
-            int at = cnt + inc - c;
+            int tot;
+            int at = cnt + quad_scan(__popc(mask), q, tot);
+            // every candidate is weighed and written: a hit to its ring slot,
+            // a miss to the lane's spare slot past the ring (FP32: hardware
+            // square root, within one ulp)
+            T wv[PL];
 #pragma unroll
             for (int u = 0; u < PL; ++u) {
-                if ((mask >> u) & 1u) {
-                    const T r2 = r2v[u];
-                    const T w = weight_of<T>(a, tab, sqrt(r2));
-                    rowsum += fabs(w);
-                    const int slot = at & (RING - 1);
-                    ri[slot] = static_cast<uint16_t>(lv[u]);
-                    rw[slot] = PAR ? w / r2 : w;
-                    ++at;
-                    if (r2 < wca_pre) {
-                        // conservative WCA force in FP64 from the wrapped positions
-                        const int e = entry_of(sb, nst, lv[u]);
-                        const double4 xi = a.pos_s[s];
-                        const double4 xj = a.pos_s[sst[e] + (lv[u] - sb[e])];
-                        double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
-                        gx -= a.g.L[0] * rint(gx / a.g.L[0]);
-                        gy -= a.g.L[1] * rint(gy / a.g.L[1]);
-                        gz -= a.g.L[2] * rint(gz / a.g.L[2]);
-                        const double rd2 = gx * gx + gy * gy + gz * gz;
-                        if (rd2 < a.wca_rc2) {
-                            const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
-                            const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
-                            fx += fr * gx;
-                            fy += fr * gy;
-                            fz += fr * gz;
-                        }
-                    }
+                const T r = sizeof(T) == 4 ? static_cast<T>(__builtin_amdgcn_sqrtf(static_cast<float>(r2v[u])))
+                                           : sqrt(r2v[u]);
+                wv[u] = weight_of2<T>(a, tab2, r);
+            }
+            unsigned wmask = 0;  // hits within the WCA range
+#pragma unroll
+            for (int u = 0; u < PL; ++u) {
+                const bool h = (mask >> u) & 1u;
+                rowsum += h ? fabs(wv[u]) : T(0);
+                const int slot = h ? (at & (RING - 1)) : RING + q;
+                ri[slot] = static_cast<uint16_t>(lv[u]);
+                rw[slot] = PAR ? wv[u] / r2v[u] : wv[u];
+                at += h ? 1 : 0;
+                wmask |= (h && r2v[u] < wca_pre) ? (1u << u) : 0u;
+            }
+            while (wmask) {
+                // conservative WCA force in FP64 from the wrapped positions
+                const int l = cand_at(cur, __ffs(wmask) - 1);
+                wmask &= wmask - 1;
+                const int e = entry_of(sb, nst, l);
+                const double4 xi = a.pos_s[s];
+                const double4 xj = a.pos_s[sst[e] + (l - sb[e])];
+                double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
+                gx -= a.g.L[0] * rint(gx / a.g.L[0]);
+                gy -= a.g.L[1] * rint(gy / a.g.L[1]);
+                gz -= a.g.L[2] * rint(gz / a.g.L[2]);
+                const double rd2 = gx * gx + gy * gy + gz * gz;
+                if (rd2 < a.wca_rc2) {
+                    const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
+                    const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
+                    fx += fr * gx;
+                    fy += fr * gy;
+                    fz += fr * gz;
                 }
             }
             // chunks completed this round, one per lane
@@ -906,17 +989,6 @@ __global__ void k_permute(int64_t n, int64_t S, const int *__restrict__ sorted, 
 // is sorted T4 or scattered to the original order [3][S] (out_orig),
 // optionally plus add_orig[p].
 // ---------------------------------------------------------------------------
-template <typename T>
-struct V2;
-template <>
-struct V2<float> {
-    using t = float2;
-};
-template <>
-struct V2<double> {
-    using t = double2;
-};
-
 struct MvArgs {
     int64_t n, S;
     const int *sorted, *cstart;
@@ -1213,7 +1285,7 @@ hipError_t launch_build_t(const Dev &d, const BuildArgs &a, bool mi, hipStream_t
 template <typename T, bool EX, bool PAR, bool MI>
 hipError_t refresh_k(const Dev &d, const BuildArgs &a, hipStream_t st)
 {
-    const size_t shm = static_cast<size_t>(a.stage_n) * sizeof(typename V4<T>::t);
+    const size_t shm = static_cast<size_t>(a.stage_n + 1) * sizeof(typename V4<T>::t);
     k_refresh<T, EX, PAR, MI><<<d.ncell, kRefreshThreads, shm, st>>>(a);
     return hipGetLastError();
 }
@@ -1224,7 +1296,7 @@ hipError_t launch_refresh_t(const Dev &d, BuildArgs a, bool mi, hipStream_t st)
     // stage the expected stencil (the mat-vec's estimate) as far as the LDS
     // budget of two work-groups per CU allows
     constexpr size_t per = sizeof(typename V4<T>::t);
-    const int room = static_cast<int>((kRefreshLds - refresh_fixed_lds<T>()) / per);
+    const int room = static_cast<int>((kRefreshLds - refresh_fixed_lds<T>()) / per) - 1;
     a.stage_n = std::max(0, std::min(d.maxc, room));
     if (d.parallel) return mi ? refresh_k<T, EX, true, true>(d, a, st) : refresh_k<T, EX, true, false>(d, a, st);
     return mi ? refresh_k<T, EX, false, true>(d, a, st) : refresh_k<T, EX, false, false>(d, a, st);
