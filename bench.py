@@ -46,8 +46,9 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
         # once, combination inputs (z and r filter outputs), output
         return dict(bytes=pairs * (2 + sT) + 4 * n + vec * sT * (1 + 1 + r + 1))
     if kind == "noise_fir":
-        P = 2 * m_max - 1
-        # per active launch: block * rank filters of P taps on 3N channels
+        P = 2 * info["window_half"] + 1
+        # per active launch: block * rank filters of P taps (the window kept
+        # by the noise plan) on 3N channels
         return dict(flops=2.0 * vec * info["block"] * info["rank"] * P)
     return {}
 
@@ -243,7 +244,7 @@ def main():
         "config": {"workload": w.name, "n": w.n, "rho": w.rho, "m_max": w.m_max, "r_cut": w.r_cut, "dt": w.dt,
                    "precision": "fp32-mixed (f32 history/noise, f64 positions and update)"},
         "latency_ms": pct(r32["lat"]),
-        "noise": {k: r32["info"][k] for k in ("cheb_terms", "rank", "block", "err_estimate")},
+        "noise": {k: r32["info"][k] for k in ("cheb_terms", "rank", "block", "window_half", "err_estimate")},
         "kernels_ms_per_step": per_step,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | {"kernel": dom},
         "roofline_history": roof_hist,
@@ -252,7 +253,7 @@ def main():
         out["fp64_plain"] = {
             "value": w.n * 1e3 / r64["ms_per_step"], "ms_per_step": r64["ms_per_step"],
             "latency_ms": pct(r64["lat"]),
-            "noise": {k: r64["info"][k] for k in ("cheb_terms", "rank", "block", "err_estimate")},
+            "noise": {k: r64["info"][k] for k in ("cheb_terms", "rank", "block", "window_half", "err_estimate")},
             "kernels_ms_per_step": {k: ms / args.kernel_steps for k, (ms, c) in r64["kt"].items()},
             "roofline_history": roofline_entry(r64, "history", True, args.kernel_steps),
         }

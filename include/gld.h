@@ -131,6 +131,7 @@ typedef struct {
     double lam_lo, lam_hi;  /* interval of the expansion                              */
     double lam_singular;    /* largest lambda where some frequency's K_hat is singular */
     double err_estimate;    /* estimated relative rms error of F^R                    */
+    int32_t window_half;    /* h: the filters use the white noise at lags |t| <= h    */
 } gld_noise_info;
 
 typedef struct gld_system gld_system;

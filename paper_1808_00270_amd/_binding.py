@@ -88,6 +88,7 @@ class gld_noise_info(C.Structure):
         ("lam_hi", C.c_double),
         ("lam_singular", C.c_double),
         ("err_estimate", C.c_double),
+        ("window_half", C.c_int32),
     ]
 
 

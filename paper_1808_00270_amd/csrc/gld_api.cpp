@@ -790,6 +790,7 @@ gld_status gld_noise_parameters(const gld_system *s, gld_noise_info *o)
     o->lam_hi = s->plan.hi;
     o->lam_singular = s->plan.sing_lo;
     o->err_estimate = s->plan.err_cheb + s->plan.err_rank + s->plan.err_window;
+    o->window_half = s->noise_on ? s->plan.half : 0;
     return GLD_OK;
 }
 
@@ -867,6 +868,7 @@ gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, doub
     info->lam_hi = plan.hi;
     info->lam_singular = plan.sing_lo;
     info->err_estimate = plan.err_cheb + plan.err_rank + plan.err_window;
+    info->window_half = plan.half;
     return GLD_OK;
 }
 

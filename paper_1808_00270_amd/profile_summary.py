@@ -42,8 +42,10 @@ CLASSES = {
     "noise_spmv": r"k_mv<{T}",
     "history": r"k_history<{T}",
     "noise_fir": r"k_fir<{T}",
+    "noise_white": r"k_white_ring<{T}",
+    "neighbor_refresh": r"k_refresh<{T}",
     "neighbor_build": r"k_build<{T}",
-    "update": r"k_update_[rv]<{T}",
+    "update": r"k_update_[rv]\b",  # FP64 in both paths
 }
 CALIB = r"neg"
 

@@ -123,6 +123,12 @@ def test_noise_filters_reproduce_dense_colored_noise(pkg, oracle_mod, parallel, 
     Pp = 2 * M - 1
     A = A[:rk * Pp].reshape(rk, Pp)
     Bm = Bm[:K * rk].reshape(K, rk)
+    # the reported window: taps vanish beyond lag h, and lag h itself is kept
+    h = info.window_half
+    assert 0 <= h <= M - 1
+    lags = np.abs(np.arange(Pp) - (M - 1))
+    assert not np.any(A[:, lags > h])
+    assert np.any(A[:, lags == h])
     al, be = 2 / (hi - lo), -(hi + lo) / (hi - lo)
     Pt = al * Pm + be * np.eye(3 * n)
     for step in (0, 5):
