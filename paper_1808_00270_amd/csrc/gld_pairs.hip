@@ -1006,18 +1006,51 @@ struct MvArgs {
     void *out_sorted, *out_orig;
 };
 
-// LDS bytes of one work-group
+// The staged input vector: (x, y, z, pad) per candidate, or, for the FP64
+// isotropic mat-vec, three arrays x[], y[], z[] of stride maxc (24 instead of
+// 32 bytes per candidate, so that two work-groups fit in a CU's LDS)
+template <typename T, bool PAR>
+constexpr bool mv_soa()
+{
+    return sizeof(T) == 8 && !PAR;
+}
+
+template <typename T, bool SOA>
+struct StageView {
+    const typename V4<T>::t *aos;
+    const T *soa;
+    unsigned stride;
+    __device__ __forceinline__ typename V4<T>::t get(unsigned l) const
+    {
+        if constexpr (SOA) {
+            typename V4<T>::t v;
+            v.x = soa[l];
+            v.y = soa[stride + l];
+            v.z = soa[2 * stride + l];
+            v.w = T(0);
+            return v;
+        } else {
+            return aos[l];
+        }
+    }
+};
+
+// LDS bytes of one work-group (the staging area is reused for the partial
+// sums of BS lanes)
 template <typename T, bool PAR, int BS>
 constexpr size_t mv_lds_bytes(int maxc)
 {
     using T4 = typename V4<T>::t;
     using T2 = typename V2<T>::t;
-    return static_cast<size_t>(maxc > BS ? maxc : BS) * sizeof(T4) + (PAR ? static_cast<size_t>(maxc) * sizeof(T2) : 0);
+    const size_t stage = mv_soa<T, PAR>() ? static_cast<size_t>(maxc) * 3 * sizeof(T)
+                                          : static_cast<size_t>(maxc) * sizeof(T4);
+    const size_t part = static_cast<size_t>(BS) * sizeof(T4);
+    return (stage > part ? stage : part) + (PAR ? static_cast<size_t>(maxc) * sizeof(T2) : 0);
 }
 
 // one chunk of 8 entries; CHECK: only entries with staged index in [c0, c0 + cn)
-template <typename T, bool PAR, bool CHECK, bool MI>
-__device__ __forceinline__ void mv_chunk(const typename V4<T>::t *xs, const typename V2<T>::t *pyz, uint4 id,
+template <typename T, bool PAR, bool CHECK, bool MI, bool SOA>
+__device__ __forceinline__ void mv_chunk(const StageView<T, SOA> &xs, const typename V2<T>::t *pyz, uint4 id,
                                          const typename V4<T>::t &wa, const typename V4<T>::t &wb, const T (&own)[3],
                                          const T (&Lb)[3], const bool (&mi)[3], unsigned c0, unsigned cn, T &p0, T &p1,
                                          T &p2)
@@ -1029,7 +1062,7 @@ __device__ __forceinline__ void mv_chunk(const typename V4<T>::t *xs, const type
     if (!CHECK) {
         T4 v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = xs[li[u]];
+        for (int u = 0; u < 8; ++u) v[u] = xs.get(li[u]);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (PAR) {
@@ -1053,7 +1086,7 @@ __device__ __forceinline__ void mv_chunk(const typename V4<T>::t *xs, const type
         for (int u = 0; u < 8; ++u) {
             const unsigned l = li[u] - c0;
             if (l >= cn) continue;
-            const T4 v = xs[l];
+            const T4 v = xs.get(l);
             if (PAR) {
                 const typename V2<T>::t q = pyz[l];
                 T dx = own[0] - v.w, dy = own[1] - q.x, dz = own[2] - q.y;
@@ -1091,7 +1124,11 @@ __global__ __launch_bounds__(BS) void k_mv(MvArgs A)
         sst[tid] = e.x;
         sbase[tid] = e.y;
     }
+    constexpr bool SOA = mv_soa<T, PAR>();
     T4 *xs = reinterpret_cast<T4 *>(mv_lds);
+    T *xsoa = reinterpret_cast<T *>(mv_lds);
+    const unsigned sstride = static_cast<unsigned>(A.maxc);
+    const StageView<T, SOA> view{xs, xsoa, sstride};
     T2 *pyz = reinterpret_cast<T2 *>(mv_lds + static_cast<size_t>(A.maxc > BS ? A.maxc : BS) * sizeof(T4));
     T4 *part = xs;  // reused once the gathers of a round are done
     const T4 *__restrict__ x = static_cast<const T4 *>(A.x);
@@ -1145,7 +1182,13 @@ __global__ __launch_bounds__(BS) void k_mv(MvArgs A)
                             yz.y = static_cast<T>(q.z) + static_cast<T>(A.g.offs[2][e2] * A.g.edge[2]);
                             pyz[l - c0] = yz;
                         }
-                        xs[l - c0] = v;
+                        if constexpr (SOA) {
+                            xsoa[l - c0] = v.x;
+                            xsoa[sstride + (l - c0)] = v.y;
+                            xsoa[2 * sstride + (l - c0)] = v.z;
+                        } else {
+                            xs[l - c0] = v;
+                        }
                     }
                     __syncthreads();
                     staged_all = single;
@@ -1167,9 +1210,9 @@ __global__ __launch_bounds__(BS) void k_mv(MvArgs A)
                         wa = nbw4[(2 * nx) * n + s];
                         wb = nbw4[(2 * nx + 1) * n + s];
                     }
-                    if (single) mv_chunk<T, PAR, false, MI>(xs, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1, p2);
+                    if (single) mv_chunk<T, PAR, false, MI>(view, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1, p2);
                     else
-                        mv_chunk<T, PAR, true, MI>(xs, pyz, cid8, cwa, cwb, own, Lb, mi, static_cast<unsigned>(c0),
+                        mv_chunk<T, PAR, true, MI>(view, pyz, cid8, cwa, cwb, own, Lb, mi, static_cast<unsigned>(c0),
                                                static_cast<unsigned>(c1 - c0), p0, p1, p2);
                 }
             }
@@ -1309,7 +1352,7 @@ int mv_max_staging(int fp64, int parallel)
 {
     const size_t budget = 160 * 1024 - 1024;
     size_t per;
-    if (fp64) per = parallel ? sizeof(double4) + sizeof(double2) : sizeof(double4);
+    if (fp64) per = parallel ? sizeof(double4) + sizeof(double2) : 3 * sizeof(double);
     else per = parallel ? sizeof(float4) + sizeof(float2) : sizeof(float4);
     return static_cast<int>(budget / per);
 }
