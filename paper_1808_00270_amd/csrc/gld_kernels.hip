@@ -367,6 +367,120 @@ __global__ __launch_bounds__(128) void k_fir(int64_t n, int64_t S, int half, int
         }
 }
 
+// FP32 filter bank on the matrix cores.  For the block of steps starting at
+// n0 the outputs are a product of two matrices:
+//   U[b][q][m] = sum_k Ash[k][(b,q)] X[k][m],
+//   X[k][m]    = W at window step k (ring slot of n0 - half + k), channel m
+//                (m = component * S + particle), k < span = P + BF - 1,
+//   Ash[k][(b,q)] = A[k - b][q] for 0 <= k - b < P, else 0.
+// Each wave owns 64 channels and all BF*RC <= 64 rows (b,q): four 32x32
+// accumulator tiles of v_mfma_f32_32x32x2f32, which takes two k per
+// instruction (lanes 0-31 the first, 32-63 the second).  The channel operand
+// is a 128-byte segment of one ring slice per half-wave; the tap operand
+// comes from the taps staged in LDS in chunks of kFirChunk window steps.  The
+// ring loads run a batch of kFirUnroll steps ahead; past the window they read
+// other (finite) ring slices, which meet zero taps.
+typedef float fir_v16f __attribute__((ext_vector_type(16)));
+constexpr int kFirMfmaThreads = 256;  // four waves, 256 channels
+constexpr int kFirChunk = 128;        // window steps per staged tap chunk
+constexpr int kFirUnroll = 8;         // MFMA k-pairs per batch
+
+__global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t S, int bf, int rc, int half, int len,
+                                                              const float *__restrict__ A,
+                                                              const float *__restrict__ W,
+                                                              const long long *__restrict__ d_step,
+                                                              float *__restrict__ U, int force)
+{
+    __shared__ float taps[(kFirChunk + 32) * 32];
+    const long long cur = *d_step;
+    if (!force && cur % bf != 0) return;
+    const long long n0 = cur - cur % bf;
+    const int P = 2 * half + 1;
+    const int span = P + bf - 1;
+    const int64_t M = 3 * S;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t m0 = (static_cast<int64_t>(blockIdx.x) * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
+    const bool wlive = m0 < M;  // a wave past the channels only joins the staging
+    const int hi = lane >> 5, lo = lane & 31;
+    // this lane's tap rows i = 32 rt + lo, i.e. (b, q) = (i / rc, i % rc)
+    int trow[2];
+    bool tval[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const int i = 32 * rt + lo;
+        tval[rt] = i < bf * rc;
+        trow[rt] = (bf - 1 - (tval[rt] ? i / rc : 0)) * rc + (tval[rt] ? i % rc : 0);
+    }
+    // channel columns of this lane (clamped for a dead wave: never stored)
+    const int64_t c0 = wlive ? m0 + lo : lo, c1 = c0 + 32;
+    fir_v16f acc[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = fir_v16f{};
+    // ring slot of this lane's window step k = 2 j + hi
+    int sl = ring_slot(n0 - half + hi, len);
+    float xa[kFirUnroll][2], xn[kFirUnroll][2];
+    auto load_batch = [&](float (&dst)[kFirUnroll][2]) {
+#pragma unroll
+        for (int u = 0; u < kFirUnroll; ++u) {
+            const float *src = W + static_cast<int64_t>(sl) * M;
+            dst[u][0] = src[c0];
+            dst[u][1] = src[c1];
+            sl += 2;
+            sl -= sl >= len ? len : 0;
+        }
+    };
+    load_batch(xa);
+    for (int k0 = 0; k0 < span; k0 += kFirChunk) {
+        // taps of window steps [k0, k0 + kFirChunk) for every b: rows
+        // t = k0 - (bf - 1) .. k0 + kFirChunk - 1, zero outside [0, P)
+        __syncthreads();
+        const int rows = kFirChunk + bf - 1;
+        for (int e = tid; e < rows * rc; e += kFirMfmaThreads) {
+            const int t = k0 - (bf - 1) + e / rc;
+            taps[e] = (t >= 0 && t < P) ? A[static_cast<int64_t>(t) * rc + e % rc] : 0.f;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kFirChunk; kk += 2 * kFirUnroll) {
+            load_batch(xn);
+#pragma unroll
+            for (int u = 0; u < kFirUnroll; ++u) {
+                const int kl = kk + 2 * u + hi;  // window step k0 + kl of this lane
+                float av[2];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) av[rt] = tval[rt] ? taps[kl * rc + trow[rt]] : 0.f;
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rt], xa[u][ct], acc[rt][ct], 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kFirUnroll; ++u) {
+                xa[u][0] = xn[u][0];
+                xa[u][1] = xn[u][1];
+            }
+        }
+    }
+    if (!wlive) return;
+    // accumulator element v of tile (rt, ct): row i = 32 rt + (v % 4) + 4 hi
+    // + 8 (v / 4), channel m0 + 32 ct + lo
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        const int64_t m = m0 + 32 * ct + lo;
+        const int64_t p = m - (m >= S ? S : 0) - (m >= 2 * S ? S : 0);  // particle of channel m
+        if (p >= n) continue;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = 32 * rt + (v % 4) + 4 * hi + 8 * (v / 4);
+                if (i < bf * rc) U[static_cast<int64_t>(i) * M + m] = acc[rt][ct][v];
+            }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // H6: G-JF type update, eq. (GLD_integrator) with the position coefficient b
 // (App. A):  R' = R + dt b V + dt^2/(2M) b (F^C + F^D' + F^R);  dR -> ring.
@@ -664,15 +778,13 @@ hipError_t launch_fir(const Dev &d, int force, hipStream_t st)
         default: return fir_t<double, 1, 32>(d, st, force);
         }
     }
-    switch (d.fir_rcap) {
-    case 4: return fir_t<float, 16, 4>(d, st, force);
-    case 6: return fir_t<float, 10, 6>(d, st, force);
-    case 8: return fir_t<float, 8, 8>(d, st, force);
-    case 12: return fir_t<float, 5, 12>(d, st, force);
-    case 16: return fir_t<float, 4, 16>(d, st, force);
-    case 24: return fir_t<float, 2, 24>(d, st, force);
-    default: return fir_t<float, 2, 32>(d, st, force);
-    }
+    // FP32: block * rcap <= 64 for every padded rank, the rows of one pair
+    // of MFMA tiles
+    const int64_t M = 3 * d.S;
+    k_fir_mfma<<<static_cast<unsigned>((M + kFirMfmaThreads - 1) / kFirMfmaThreads), kFirMfmaThreads, 0, st>>>(
+        d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, d.wring_len, static_cast<const float *>(d.Afilt),
+        static_cast<const float *>(d.wring), d.d_step, static_cast<float *>(d.U), force);
+    return hipGetLastError();
 }
 
 hipError_t launch_update_r(const Dev &d, hipStream_t st)
