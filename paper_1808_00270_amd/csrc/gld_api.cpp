@@ -180,7 +180,7 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     // white-noise ring: at most the full filter window plus the largest block
     if (p->kT > 0)
         L.take(d.wring, static_cast<size_t>(std::max(0, 2 * (p->m_max - 1)) + gld::kMaxFirBlock) * vec * elt);
-    L.take(d.Afilt, static_cast<size_t>(gld::kMaxRank) * P * elt);
+    L.take(d.Afilt, static_cast<size_t>(gld::kMaxRank) * gld::fir_padded_rows(p->m_max - 1, gld::kMaxFirBlock) * elt);
     L.take(d.Bmix, static_cast<size_t>(gld::kMaxCheb) * gld::kMaxRank * elt);
     L.take(d.ks, static_cast<size_t>(p->m_max) * elt);
     L.take(d.gm, static_cast<size_t>(p->m_max) * elt);
@@ -516,12 +516,16 @@ gld_status setup_noise(gld_system *s)
     d.fir_half = pl.half;
     d.wring_len = 2 * pl.half + d.fir_block;
     // filter taps of the window, tap-major [2 half + 1][rcap] (columns beyond
-    // r zero), and mixing weights [K][rcap]
+    // r zero); FP32 (matrix-core filter bank) with block - 1 zero rows before
+    // and kFirChunk + block - 1 after; and mixing weights [K][rcap]
     const int Pw = 2 * pl.half + 1;
-    std::vector<double> A(static_cast<size_t>(d.fir_rcap) * Pw, 0.0), B(static_cast<size_t>(pl.K) * d.fir_rcap, 0.0);
+    const int front = s->geo.fp64 ? 0 : d.fir_block - 1;
+    const size_t rows = s->geo.fp64 ? static_cast<size_t>(Pw) : gld::fir_padded_rows(pl.half, d.fir_block);
+    std::vector<double> A(static_cast<size_t>(d.fir_rcap) * rows, 0.0), B(static_cast<size_t>(pl.K) * d.fir_rcap, 0.0);
     for (int q = 0; q < pl.r; ++q)
         for (int t = 0; t < Pw; ++t)
-            A[static_cast<size_t>(t) * d.fir_rcap + q] = pl.Afilt[static_cast<size_t>(q) * pl.P + (pl.M - 1 - pl.half) + t];
+            A[static_cast<size_t>(t + front) * d.fir_rcap + q] =
+                pl.Afilt[static_cast<size_t>(q) * pl.P + (pl.M - 1 - pl.half) + t];
     for (int k = 0; k < pl.K; ++k)
         for (int q = 0; q < pl.r; ++q) B[static_cast<size_t>(k) * d.fir_rcap + q] = pl.Bmix[static_cast<size_t>(k) * pl.r + q];
     if ((st = upload_work_table(s, d.Afilt, A.data(), A.size())) != GLD_OK) return st;

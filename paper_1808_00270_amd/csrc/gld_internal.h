@@ -139,6 +139,10 @@ hipError_t launch_white_ring(const Dev &d, int mode, hipStream_t st);
 int fir_block_for(int fp64, int rcap);
 int fir_rcap_for(int rank);
 constexpr int kMaxFirBlock = 16;
+// FP32 filter bank on the matrix cores: window steps per staged tap chunk; its
+// taps are stored zero-padded, [bf - 1 + (2 half + 1) + kFirChunk + bf - 1][rcap]
+constexpr int kFirChunk = 128;
+inline size_t fir_padded_rows(int half, int bf) { return static_cast<size_t>(2 * half + 1 + kFirChunk + 2 * (bf - 1)); }
 // out = a P x + b x + cz z + sum_q coef[q] us_q  (x, z, us: sorted T4; x, z may be null
 // when a = b = 0 / cz = 0).  Written to out_sorted (T4) or, if that is null,
 // scattered to out_orig ([3][S], original order) plus add_orig when given.

@@ -378,12 +378,14 @@ __global__ __launch_bounds__(128) void k_fir(int64_t n, int64_t S, int half, int
 // instruction (lanes 0-31 the first, 32-63 the second).  The channel operand
 // is a 128-byte segment of one ring slice per half-wave; the tap operand
 // comes from the taps staged in LDS in chunks of kFirChunk window steps.  The
-// ring loads run a batch of kFirUnroll steps ahead; past the window they read
-// other (finite) ring slices, which meet zero taps.
+// ring loads run two batches of kFirUnroll k-pairs ahead; past the window they
+// read other (finite) ring slices, which meet zero taps.
+// The taps come zero-padded (see kFirChunk): row t + bf - 1 holds A[t], so
+// a chunk's rows are one contiguous copy.
 typedef float fir_v16f __attribute__((ext_vector_type(16)));
 constexpr int kFirMfmaThreads = 256;  // four waves, 256 channels
-constexpr int kFirChunk = 128;        // window steps per staged tap chunk
 constexpr int kFirUnroll = 8;         // MFMA k-pairs per batch
+constexpr int kFirStageIt = ((kFirChunk + kMaxFirBlock - 1) * kMaxRank / 2 + kFirMfmaThreads - 1) / kFirMfmaThreads;
 
 __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t S, int bf, int rc, int half, int len,
                                                               const float *__restrict__ A,
@@ -391,65 +393,84 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t
                                                               const long long *__restrict__ d_step,
                                                               float *__restrict__ U, int force)
 {
-    __shared__ float taps[(kFirChunk + 32) * 32];
+    __shared__ __align__(16) float taps[(kFirChunk + kMaxFirBlock - 1) * kMaxRank];
     const long long cur = *d_step;
     if (!force && cur % bf != 0) return;
     const long long n0 = cur - cur % bf;
-    const int P = 2 * half + 1;
-    const int span = P + bf - 1;
+    const int span = 2 * half + bf;  // window steps: 2 half + 1 taps, bf outputs
     const int64_t M = 3 * S;
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t m0 = (static_cast<int64_t>(blockIdx.x) * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
     const bool wlive = m0 < M;  // a wave past the channels only joins the staging
     const int hi = lane >> 5, lo = lane & 31;
     // this lane's tap rows i = 32 rt + lo, i.e. (b, q) = (i / rc, i % rc)
+    // (rows past bf * rc read a valid tap and multiply it by 0, so the LDS
+    // reads carry no branch)
     int trow[2];
-    bool tval[2];
+    float tmul[2];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
         const int i = 32 * rt + lo;
-        tval[rt] = i < bf * rc;
-        trow[rt] = (bf - 1 - (tval[rt] ? i / rc : 0)) * rc + (tval[rt] ? i % rc : 0);
+        const bool valid = i < bf * rc;
+        tmul[rt] = valid ? 1.f : 0.f;
+        trow[rt] = (bf - 1 - (valid ? i / rc : 0)) * rc + (valid ? i % rc : 0);
     }
     // channel columns of this lane (clamped for a dead wave: never stored)
-    const int64_t c0 = wlive ? m0 + lo : lo, c1 = c0 + 32;
+    const int64_t c0 = wlive ? m0 + lo : lo;
     fir_v16f acc[2][2];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = fir_v16f{};
-    // ring slot of this lane's window step k = 2 j + hi
+    // ring slot of this lane's window step k = 2 j + hi, and its channel c0
+    // there (c1 = c0 + 32 follows at a fixed offset)
     int sl = ring_slot(n0 - half + hi, len);
-    float xa[kFirUnroll][2], xn[kFirUnroll][2];
+    const float *src = W + static_cast<int64_t>(sl) * M + c0;
+    const int64_t wrap = static_cast<int64_t>(len) * M;
+    float xa[kFirUnroll][2], xn[kFirUnroll][2], xm[kFirUnroll][2];
     auto load_batch = [&](float (&dst)[kFirUnroll][2]) {
 #pragma unroll
         for (int u = 0; u < kFirUnroll; ++u) {
-            const float *src = W + static_cast<int64_t>(sl) * M;
-            dst[u][0] = src[c0];
-            dst[u][1] = src[c1];
+            dst[u][0] = src[0];
+            dst[u][1] = src[32];
             sl += 2;
-            sl -= sl >= len ? len : 0;
+            src += 2 * M;
+            if (sl >= len) {
+                sl -= len;
+                src -= wrap;
+            }
         }
     };
     load_batch(xa);
+    load_batch(xn);
     for (int k0 = 0; k0 < span; k0 += kFirChunk) {
-        // taps of window steps [k0, k0 + kFirChunk) for every b: rows
-        // t = k0 - (bf - 1) .. k0 + kFirChunk - 1, zero outside [0, P)
-        __syncthreads();
-        const int rows = kFirChunk + bf - 1;
-        for (int e = tid; e < rows * rc; e += kFirMfmaThreads) {
-            const int t = k0 - (bf - 1) + e / rc;
-            taps[e] = (t >= 0 && t < P) ? A[static_cast<int64_t>(t) * rc + e % rc] : 0.f;
+        // taps of window steps [k0, k0 + kFirChunk) for every b: padded rows
+        // k0 .. k0 + kFirChunk + bf - 2 (t = k0 - (bf - 1) ..), loaded before
+        // the barrier that retires the previous chunk
+        const int nel = (kFirChunk + bf - 1) * rc / 2;  // float2 (rc is even)
+        const float2 *srcA = reinterpret_cast<const float2 *>(A + static_cast<int64_t>(k0) * rc);
+        float2 tv[kFirStageIt];
+#pragma unroll
+        for (int j = 0; j < kFirStageIt; ++j) {
+            const int e = tid + j * kFirMfmaThreads;
+            tv[j] = e < nel ? srcA[e] : make_float2(0.f, 0.f);
         }
         __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kFirStageIt; ++j) {
+            const int e = tid + j * kFirMfmaThreads;
+            if (e < nel) reinterpret_cast<float2 *>(taps)[e] = tv[j];
+        }
+        __syncthreads();
+#pragma unroll 1
         for (int kk = 0; kk < kFirChunk; kk += 2 * kFirUnroll) {
-            load_batch(xn);
+            load_batch(xm);  // two batches ahead
 #pragma unroll
             for (int u = 0; u < kFirUnroll; ++u) {
                 const int kl = kk + 2 * u + hi;  // window step k0 + kl of this lane
                 float av[2];
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt) av[rt] = tval[rt] ? taps[kl * rc + trow[rt]] : 0.f;
+                for (int rt = 0; rt < 2; ++rt) av[rt] = taps[kl * rc + trow[rt]] * tmul[rt];
 #pragma unroll
                 for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -460,6 +481,8 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t
             for (int u = 0; u < kFirUnroll; ++u) {
                 xa[u][0] = xn[u][0];
                 xa[u][1] = xn[u][1];
+                xn[u][0] = xm[u][0];
+                xn[u][1] = xm[u][1];
             }
         }
     }
