@@ -516,11 +516,12 @@ gld_status setup_noise(gld_system *s)
     d.fir_half = pl.half;
     d.wring_len = 2 * pl.half + d.fir_block;
     // filter taps of the window, tap-major [2 half + 1][rcap] (columns beyond
-    // r zero); FP32 (matrix-core filter bank) with block - 1 zero rows before
-    // and kFirChunk + block - 1 after; and mixing weights [K][rcap]
+    // r zero) with block - 1 zero rows before and kFirChunk + block - 1 after
+    // (the matrix-core filter bank copies whole chunks of rows); and mixing
+    // weights [K][rcap]
     const int Pw = 2 * pl.half + 1;
-    const int front = s->geo.fp64 ? 0 : d.fir_block - 1;
-    const size_t rows = s->geo.fp64 ? static_cast<size_t>(Pw) : gld::fir_padded_rows(pl.half, d.fir_block);
+    const int front = d.fir_block - 1;
+    const size_t rows = gld::fir_padded_rows(pl.half, d.fir_block);
     std::vector<double> A(static_cast<size_t>(d.fir_rcap) * rows, 0.0), B(static_cast<size_t>(pl.K) * d.fir_rcap, 0.0);
     for (int q = 0; q < pl.r; ++q)
         for (int t = 0; t < Pw; ++t)

@@ -7,6 +7,7 @@
 //   positions, velocities, F^C           double [3][S]
 //   displacement ring (history)          T      [m_max-1][3][S]   slot-major
 //   convolution outputs, F^D', F^R       T      [3][S]
+//   white-noise ring                     T      [2 half + block][3][S]  slice t at t mod len
 //   filter-bank outputs                  T      [block][rank][3][S]
 //   neighbour lists (cell-sorted order)  uint16 [cap/8][n][8] staged-stencil indices
 //                                        T      [cap/4][n][4] pair weights
@@ -138,10 +139,15 @@ struct Vec4<double> {
 
 template <typename T>
 __device__ __forceinline__ typename Vec4<T>::type load4(const T *p);
+// (the displacement ring is read once per step: FP32 loads are non-temporal,
+// which measured 462 -> 395 us at cfg3; for FP64 the hint measured slightly
+// slower and is left out)
+typedef float ring_f4 __attribute__((ext_vector_type(4)));
 template <>
 __device__ __forceinline__ float4 load4<float>(const float *p)
 {
-    return *reinterpret_cast<const float4 *>(p);
+    const ring_f4 v = __builtin_nontemporal_load(reinterpret_cast<const ring_f4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
 }
 template <>
 __device__ __forceinline__ double4 load4<double>(const double *p)
@@ -289,84 +295,6 @@ __global__ void k_white_ring(int64_t n, int64_t S, uint64_t seed, const long lon
     dst[2 * S + i] = w[2];
 }
 
-// The loop runs over the taps ti (outer) with a register window holding
-// W at steps n0-half+ti .. n0-half+ti+WIN-1: tap ti feeds output b from the
-// window entry ti+b, so one tap row A[ti][0..RC) (a scalar load, the same
-// for the whole wave) meets BF window entries; each tap adds one entry,
-// loaded PF taps ahead.  Unrolled by WIN so the window indices are static.
-template <typename T, int BF, int RC>
-__global__ __launch_bounds__(128) void k_fir(int64_t n, int64_t S, int half, int len, const T *__restrict__ A,
-                                             const T *__restrict__ W, const long long *__restrict__ d_step,
-                                             T *__restrict__ U, int force)
-{
-    constexpr int PF = 2;          // prefetch distance (taps)
-    constexpr int WIN = BF + PF;   // window entries
-    // regular launches work only at block starts; a forced launch (after a
-    // state is installed mid-block) produces the block holding the step
-    const long long cur = *d_step;
-    if (!force && cur % BF != 0) return;
-    const long long n0 = cur - cur % BF;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int P = 2 * half + 1;
-    const int span = P + BF - 1;  // window steps read
-    T acc[BF][RC][3];
-#pragma unroll
-    for (int b = 0; b < BF; ++b)
-#pragma unroll
-        for (int q = 0; q < RC; ++q) acc[b][q][0] = acc[b][q][1] = acc[b][q][2] = T(0);
-    T win[WIN][3];
-    const int slot0 = ring_slot(n0 - half, len);
-    auto load = [&](int k, T (&dst)[3]) {
-        // window step k (0 <= k < span); beyond it zeros (never used)
-        if (k < span) {
-            int sl = slot0 + k;
-            sl -= sl >= len ? len : 0;
-            const T *src = W + static_cast<int64_t>(sl) * 3 * S + i;
-            dst[0] = src[0];
-            dst[1] = src[S];
-            dst[2] = src[2 * S];
-        } else {
-            dst[0] = dst[1] = dst[2] = T(0);
-        }
-    };
-#pragma unroll
-    for (int e = 0; e < WIN - 1; ++e) load(e, win[e]);
-    for (int t0 = 0; t0 < P; t0 += WIN) {
-#pragma unroll
-        for (int u = 0; u < WIN; ++u) {
-            const int ti = t0 + u;
-            if (ti < P) {
-                // entry ti + WIN - 1 goes where entry ti - 1 was
-                load(ti + WIN - 1, win[(u + WIN - 1) % WIN]);
-                const T *a = A + static_cast<int64_t>(ti) * RC;
-                T c[RC];
-#pragma unroll
-                for (int q = 0; q < RC; ++q) c[q] = a[q];
-#pragma unroll
-                for (int b = 0; b < BF; ++b) {
-                    const T *wv = win[(u + b) % WIN];
-#pragma unroll
-                    for (int q = 0; q < RC; ++q) {
-                        acc[b][q][0] += c[q] * wv[0];
-                        acc[b][q][1] += c[q] * wv[1];
-                        acc[b][q][2] += c[q] * wv[2];
-                    }
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < BF; ++b)
-#pragma unroll
-        for (int q = 0; q < RC; ++q) {
-            T *u = U + (static_cast<int64_t>(b) * RC + q) * 3 * S;
-            u[i] = acc[b][q][0];
-            u[S + i] = acc[b][q][1];
-            u[2 * S + i] = acc[b][q][2];
-        }
-}
-
 // FP32 filter bank on the matrix cores.  For the block of steps starting at
 // n0 the outputs are a product of two matrices:
 //   U[b][q][m] = sum_k Ash[k][(b,q)] X[k][m],
@@ -431,8 +359,8 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t
     auto load_batch = [&](float (&dst)[kFirUnroll][2]) {
 #pragma unroll
         for (int u = 0; u < kFirUnroll; ++u) {
-            dst[u][0] = src[0];
-            dst[u][1] = src[32];
+            dst[u][0] = __builtin_nontemporal_load(src);
+            dst[u][1] = __builtin_nontemporal_load(src + 32);
             sl += 2;
             src += 2 * M;
             if (sl >= len) {
@@ -499,6 +427,121 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int i = 32 * rt + (v % 4) + 4 * hi + 8 * (v / 4);
+                if (i < bf * rc) U[static_cast<int64_t>(i) * M + m] = acc[rt][ct][v];
+            }
+    }
+}
+
+// FP64 filter bank on the matrix cores, the same product with
+// v_mfma_f64_16x16x4f64 (four k per instruction, lanes 16 g .. 16 g + 15
+// taking k = g): each wave owns 64 channels (four 16-wide column tiles) and
+// the bf * rc <= 32 rows (two 16-row tiles); accumulator element v of a tile
+// is row 4 v + g, column lane % 16.  Taps are staged in chunks of
+// kFirChunk64 window steps.
+typedef double fir_v4d __attribute__((ext_vector_type(4)));
+constexpr int kFirChunk64 = 64;
+constexpr int kFirUnroll64 = 4;  // MFMA k-quads per batch
+constexpr int kFirStageIt64 =
+    ((kFirChunk64 + kMaxFirBlock - 1) * kMaxRank / 2 + kFirMfmaThreads - 1) / kFirMfmaThreads;
+
+__global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma64(int64_t n, int64_t S, int bf, int rc, int half,
+                                                                int len, const double *__restrict__ A,
+                                                                const double *__restrict__ W,
+                                                                const long long *__restrict__ d_step,
+                                                                double *__restrict__ U, int force)
+{
+    __shared__ __align__(16) double taps[(kFirChunk64 + kMaxFirBlock - 1) * kMaxRank];
+    const long long cur = *d_step;
+    if (!force && cur % bf != 0) return;
+    const long long n0 = cur - cur % bf;
+    const int span = 2 * half + bf;
+    const int64_t M = 3 * S;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t m0 = (static_cast<int64_t>(blockIdx.x) * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
+    const bool wlive = m0 < M;
+    const int g = lane >> 4, lo = lane & 15;
+    int trow[2];
+    double tmul[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const int i = 16 * rt + lo;
+        const bool valid = i < bf * rc;
+        tmul[rt] = valid ? 1.0 : 0.0;
+        trow[rt] = (bf - 1 - (valid ? i / rc : 0)) * rc + (valid ? i % rc : 0);
+    }
+    const int64_t c0 = wlive ? m0 + lo : lo;
+    fir_v4d acc[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = fir_v4d{};
+    // ring slot of this lane's window step k = 4 j + g
+    int sl = ring_slot(n0 - half + g, len);
+    const double *src = W + static_cast<int64_t>(sl) * M + c0;
+    const int64_t wrap = static_cast<int64_t>(len) * M;
+    double xa[kFirUnroll64][4], xn[kFirUnroll64][4];
+    auto load_batch = [&](double (&dst)[kFirUnroll64][4]) {
+#pragma unroll
+        for (int u = 0; u < kFirUnroll64; ++u) {
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) dst[u][ct] = __builtin_nontemporal_load(src + 16 * ct);
+            sl += 4;
+            src += 4 * M;
+            if (sl >= len) {
+                sl -= len;
+                src -= wrap;
+            }
+        }
+    };
+    load_batch(xa);
+    for (int k0 = 0; k0 < span; k0 += kFirChunk64) {
+        const int nel = (kFirChunk64 + bf - 1) * rc / 2;  // double2 (rc is even)
+        const double2 *srcA = reinterpret_cast<const double2 *>(A + static_cast<int64_t>(k0) * rc);
+        double2 tv[kFirStageIt64];
+#pragma unroll
+        for (int j = 0; j < kFirStageIt64; ++j) {
+            const int e = tid + j * kFirMfmaThreads;
+            tv[j] = e < nel ? srcA[e] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kFirStageIt64; ++j) {
+            const int e = tid + j * kFirMfmaThreads;
+            if (e < nel) reinterpret_cast<double2 *>(taps)[e] = tv[j];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int kk = 0; kk < kFirChunk64; kk += 4 * kFirUnroll64) {
+            load_batch(xn);
+#pragma unroll
+            for (int u = 0; u < kFirUnroll64; ++u) {
+                const int kl = kk + 4 * u + g;
+                double av[2];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) av[rt] = taps[kl * rc + trow[rt]] * tmul[rt];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct < 4; ++ct)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], xa[u][ct], acc[rt][ct], 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kFirUnroll64; ++u)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) xa[u][ct] = xn[u][ct];
+        }
+    }
+    if (!wlive) return;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int64_t m = m0 + 16 * ct + lo;
+        const int64_t p = m - (m >= S ? S : 0) - (m >= 2 * S ? S : 0);
+        if (p >= n) continue;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * rt + 4 * v + g;
                 if (i < bf * rc) U[static_cast<int64_t>(i) * M + m] = acc[rt][ct][v];
             }
     }
@@ -742,18 +785,9 @@ hipError_t launch_history(const Dev &d, hipStream_t st)
     return d.fp64 ? history_t<double>(d, st) : history_t<float>(d, st);
 }
 
-template <typename T, int BF, int RC>
-static hipError_t fir_t(const Dev &d, hipStream_t st, int force)
-{
-    k_fir<T, BF, RC><<<blocks(d.n, 128), 128, 0, st>>>(d.n, d.S, d.fir_half, d.wring_len,
-                                                       static_cast<const T *>(d.Afilt),
-                                                       static_cast<const T *>(d.wring), d.d_step,
-                                                       static_cast<T *>(d.U), force);
-    return hipGetLastError();
-}
-
-// padded ranks and, per work precision, the steps of one filter block: the
-// accumulators BF * RC * 3 fill about 192 registers (FP64 values take two)
+// padded ranks and, per work precision, the steps of one filter block:
+// block * rcap <= 64 (FP32) or <= 32 (FP64), the accumulator rows of the
+// filter bank's MFMA tiles
 int fir_rcap_for(int rank)
 {
     static const int caps[] = {4, 6, 8, 12, 16, 24, 32};
@@ -790,23 +824,20 @@ hipError_t launch_white_ring(const Dev &d, int mode, hipStream_t st)
 
 hipError_t launch_fir(const Dev &d, int force, hipStream_t st)
 {
-    if (d.fp64) {
-        switch (d.fir_rcap) {
-        case 4: return fir_t<double, 8, 4>(d, st, force);
-        case 6: return fir_t<double, 5, 6>(d, st, force);
-        case 8: return fir_t<double, 4, 8>(d, st, force);
-        case 12: return fir_t<double, 2, 12>(d, st, force);
-        case 16: return fir_t<double, 2, 16>(d, st, force);
-        case 24: return fir_t<double, 1, 24>(d, st, force);
-        default: return fir_t<double, 1, 32>(d, st, force);
-        }
-    }
-    // FP32: block * rcap <= 64 for every padded rank, the rows of one pair
-    // of MFMA tiles
+    // block * rcap <= 64 (FP32) or <= 32 (FP64) for every padded rank: the
+    // rows of one pair of MFMA tiles
     const int64_t M = 3 * d.S;
-    k_fir_mfma<<<static_cast<unsigned>((M + kFirMfmaThreads - 1) / kFirMfmaThreads), kFirMfmaThreads, 0, st>>>(
-        d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, d.wring_len, static_cast<const float *>(d.Afilt),
-        static_cast<const float *>(d.wring), d.d_step, static_cast<float *>(d.U), force);
+    const unsigned grid = static_cast<unsigned>((M + kFirMfmaThreads - 1) / kFirMfmaThreads);
+    if (d.fp64)
+        k_fir_mfma64<<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, d.wring_len,
+                                                       static_cast<const double *>(d.Afilt),
+                                                       static_cast<const double *>(d.wring), d.d_step,
+                                                       static_cast<double *>(d.U), force);
+    else
+        k_fir_mfma<<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, d.wring_len,
+                                                     static_cast<const float *>(d.Afilt),
+                                                     static_cast<const float *>(d.wring), d.d_step,
+                                                     static_cast<float *>(d.U), force);
     return hipGetLastError();
 }
 

@@ -3,19 +3,21 @@
 // (the pair part of eq. dissipative_force2 and the matrix of the colored
 // noise, Sec. II.C).
 //
-// Design.  Particles are ordered by cell every step (cells of edge >= r_c,
-// about a hundred particles each).  The neighbour build, once per step, gives
-// every particle its list of neighbours as 16-bit indices into the
-// concatenated candidate list of its cell's stencil (the up to 27 cells
-// around it) together with the final pair weights, in 8-entry chunks; it also
-// computes the WCA force and the Gershgorin bound of the noise interval.
-// Every mat-vec of the step (about fifty per step: the dissipative force and
-// the Chebyshev chain of the noise) then runs one work-group per cell: it
-// stages the input vector of the stencil in LDS, and four lanes per particle
-// stream the chunks (one 16-byte load brings 8 indices, another 4 weights;
-// a wave's loads are one contiguous kilobyte) and gather from LDS.  The lists
-// are 6 bytes per pair in FP32, so a mat-vec is bound by streaming them from
-// HBM.
+// Design.  Particles are ordered by cell (cells of edge >= r_c + skin, about
+// ninety particles each at the benchmark density).  The lists come in two
+// stages.  Candidate lists hold, for every particle, the particles within
+// r_c + skin as 16-bit indices into the concatenated candidate list of its
+// cell's stencil (the up to 27 cells around it); they and the cell order are
+// rebuilt only when some particle has moved more than skin/2 since the last
+// build.  Every step the refresh filters the candidates to the pairs within
+// r_c, in candidate order, with their final weights, and computes the WCA
+// force and the Gershgorin bound of the noise interval.  Every mat-vec of the
+// step (about forty: the dissipative force and the Chebyshev chain of the
+// noise) then runs one work-group per cell: it stages the input vector of the
+// stencil in LDS, and four lanes per particle stream the pair chunks (one
+// 16-byte load brings 8 indices, another 4 weights; a wave's loads are one
+// contiguous kilobyte) and gather from LDS.  The lists are 6 bytes per pair
+// in FP32, so a mat-vec is bound by streaming them from HBM.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,6 +58,37 @@ struct V2<double> {
     using t = double2;
 };
 
+// 16-byte loads marked non-temporal, for the lists that stream through L2
+// once per kernel (candidate lists, pair lists): the hint keeps them from
+// evicting the positions and vectors that the 27 work-groups of a cell's
+// neighbourhood each stage.  (The refresh's pair-list stores stay ordinary:
+// their 16-byte pieces of a line arrive at different times and are merged
+// in L2.)
+template <typename V>
+struct NtVec;
+template <>
+struct NtVec<uint4> {
+    typedef unsigned t __attribute__((ext_vector_type(4)));
+};
+template <>
+struct NtVec<float4> {
+    typedef float t __attribute__((ext_vector_type(4)));
+};
+template <>
+struct NtVec<double4> {
+    typedef double t __attribute__((ext_vector_type(4)));
+};
+template <typename V>
+__device__ __forceinline__ V stream_load(const V *p)
+{
+    const typename NtVec<V>::t v = __builtin_nontemporal_load(reinterpret_cast<const typename NtVec<V>::t *>(p));
+    V r;
+    r.x = v.x;
+    r.y = v.y;
+    r.z = v.z;
+    r.w = v.w;
+    return r;
+}
 __device__ __forceinline__ void latch(int *flags, long long *flag_step, int code, long long step)
 {
     if (atomicCAS(flags, 0, code) == 0) *flag_step = step;
@@ -328,34 +361,11 @@ struct BuildArgs {
     const long long *d_step;
 };
 
-// w(r): linear interpolation on the distance grid, frozen below r_cut_min;
-// tab is the table in the work precision (FP32 entries are the FP64 ones
-// rounded), staged in LDS
+// w(r): linear interpolation on the distance grid, frozen below r_cut_min.
+// tab2[b] = (w_b, w_{b+1}) in the work precision (FP32 entries are the FP64
+// ones rounded), staged in LDS: one read per weight
 template <typename T>
-__device__ __forceinline__ T weight_of(const BuildArgs &a, const T *tab, T r)
-{
-    if (sizeof(T) == 8) {
-        double rr = static_cast<double>(r);
-        if (rr < a.r_cut_min) rr = a.r_cut_min;
-        const double t = fmax((rr - a.r0) / a.dr, 0.0);
-        const double tb = fmin(floor(t), static_cast<double>(a.n_r - 2));
-        const int b = static_cast<int>(fmax(tb, 0.0));
-        const double f = t - b;
-        return static_cast<T>(static_cast<double>(tab[b]) * (1.0 - f) + static_cast<double>(tab[b + 1]) * f);
-    }
-    const T rmin = static_cast<T>(a.r_cut_min);
-    const T rr = r < rmin ? rmin : r;
-    const T t = fmax((rr - static_cast<T>(a.r0)) * static_cast<T>(1.0 / a.dr), T(0));
-    const T tb = fmin(floor(t), static_cast<T>(a.n_r - 2));
-    const int b = static_cast<int>(fmax(tb, T(0)));
-    const T f = t - static_cast<T>(b);
-    const T w0 = tab[b], w1 = tab[b + 1];
-    return w0 + f * (w1 - w0);
-}
-
-// the same from a table of pairs (w_b, w_{b+1}): one LDS read per weight
-template <typename T>
-__device__ __forceinline__ T weight_of2(const BuildArgs &a, const typename V2<T>::t *tab2, T r)
+__device__ __forceinline__ T weight_of(const BuildArgs &a, const typename V2<T>::t *tab2, T r)
 {
     if (sizeof(T) == 8) {
         double rr = static_cast<double>(r);
@@ -679,7 +689,7 @@ __device__ __forceinline__ void load_candidates(const BuildArgs &a, int64_t s, i
     if constexpr (RefreshShape<T>::kPerLane == 8) {
         const int c = 4 * k + q;
         uint4 v = make_uint4(fill, fill, fill, fill);
-        if (c < nch) v = a.snl[c * a.n + s];
+        if (c < nch) v = stream_load(&a.snl[c * a.n + s]);
         w[0] = v.x;
         w[1] = v.y;
         w[2] = v.z;
@@ -860,7 +870,7 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
             for (int u = 0; u < PL; ++u) {
                 const T r = sizeof(T) == 4 ? static_cast<T>(__builtin_amdgcn_sqrtf(static_cast<float>(r2v[u])))
                                            : sqrt(r2v[u]);
-                wv[u] = weight_of2<T>(a, tab2, r);
+                wv[u] = weight_of<T>(a, tab2, r);
             }
             unsigned wmask = 0;  // hits within the WCA range
 #pragma unroll
@@ -1197,18 +1207,18 @@ __global__ __launch_bounds__(BS) void k_mv(MvArgs A)
                 uint4 id = make_uint4(0, 0, 0, 0);
                 T4 wa{}, wb{};
                 if (sub < nch) {
-                    id = nbl[sub * n + s];
-                    wa = nbw4[(2 * sub) * n + s];
-                    wb = nbw4[(2 * sub + 1) * n + s];
+                    id = stream_load(&nbl[sub * n + s]);
+                    wa = stream_load(&nbw4[(2 * sub) * n + s]);
+                    wb = stream_load(&nbw4[(2 * sub + 1) * n + s]);
                 }
                 for (int ch = sub; ch < nch; ch += L) {
                     const uint4 cid8 = id;
                     const T4 cwa = wa, cwb = wb;
                     if (ch + L < nch) {
                         const int nx = ch + L;
-                        id = nbl[nx * n + s];
-                        wa = nbw4[(2 * nx) * n + s];
-                        wb = nbw4[(2 * nx + 1) * n + s];
+                        id = stream_load(&nbl[nx * n + s]);
+                        wa = stream_load(&nbw4[(2 * nx) * n + s]);
+                        wb = stream_load(&nbw4[(2 * nx + 1) * n + s]);
                     }
                     if (single) mv_chunk<T, PAR, false, MI>(view, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1, p2);
                     else
