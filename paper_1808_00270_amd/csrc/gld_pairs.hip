@@ -1116,8 +1116,16 @@ __device__ __forceinline__ void mv_chunk(const StageView<T, SOA> &xs, const type
     }
 }
 
+// FP32 isotropic: at most 80 registers, so that six waves per SIMD (three
+// work-groups of 512, as the LDS allows) are resident
+template <typename T, bool PAR>
+constexpr int mv_min_waves()
+{
+    return (sizeof(T) == 4 && !PAR) ? 6 : 1;
+}
+
 template <typename T, bool PAR, bool MI, int BS, int L>
-__global__ __launch_bounds__(BS) void k_mv(MvArgs A)
+__global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
 {
     using T4 = typename V4<T>::t;
     using T2 = typename V2<T>::t;
@@ -1167,6 +1175,15 @@ __global__ __launch_bounds__(BS) void k_mv(MvArgs A)
         }
         T p0 = 0, p1 = 0, p2 = 0;
         if (pair) {
+            // this lane's first chunk: its loads are in flight during the
+            // staging below (a later staging round loads it again)
+            uint4 id = make_uint4(0, 0, 0, 0);
+            T4 wa{}, wb{};
+            if (sub < nch) {
+                id = stream_load(&nbl[sub * n + s]);
+                wa = stream_load(&nbw4[(2 * sub) * n + s]);
+                wb = stream_load(&nbw4[(2 * sub + 1) * n + s]);
+            }
             for (int c0 = 0; c0 < total; c0 += A.maxc) {
                 const int c1 = min(total, c0 + A.maxc);
                 const bool single = c0 == 0 && c1 == total;
@@ -1204,9 +1221,7 @@ __global__ __launch_bounds__(BS) void k_mv(MvArgs A)
                     staged_all = single;
                 }
                 // this lane's chunks, the next one's loads in flight
-                uint4 id = make_uint4(0, 0, 0, 0);
-                T4 wa{}, wb{};
-                if (sub < nch) {
+                if (c0 > 0 && sub < nch) {
                     id = stream_load(&nbl[sub * n + s]);
                     wa = stream_load(&nbw4[(2 * sub) * n + s]);
                     wb = stream_load(&nbw4[(2 * sub + 1) * n + s]);
