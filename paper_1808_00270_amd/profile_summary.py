@@ -37,11 +37,11 @@ ROOT = os.path.dirname(HERE)
 SOURCES = ["gld_kernels.hip", "gld_pairs.hip", "gld_internal.h"]
 
 # kernel classes of the step (the names bench.py uses) -> kernel symbol, for
-# the work type T of the precision
+# the work type T of the precision (F: suffix of the FP64 filter-bank kernel)
 CLASSES = {
     "noise_spmv": r"k_mv<{T}",
     "history": r"k_history<{T}",
-    "noise_fir": r"k_fir<{T}",
+    "noise_fir": r"k_fir_mfma{F}\(",
     "noise_white": r"k_white_ring<{T}",
     "neighbor_refresh": r"k_refresh<{T}",
     "neighbor_build": r"k_build<{T}",
@@ -114,7 +114,8 @@ def main():
                     help="kernel classes of this path (work type float or double)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
-    classes = {k: v.format(T="float" if a.precision == "fp32" else "double") for k, v in CLASSES.items()}
+    classes = {k: v.format(T="float" if a.precision == "fp32" else "double", F="" if a.precision == "fp32" else "64")
+               for k, v in CLASSES.items()}
 
     lines = [f"# {a.name}", ""]
     if a.note:
