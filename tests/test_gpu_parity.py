@@ -158,6 +158,23 @@ def test_one_step_dense_small_box(pkg, oracle_mod, fp64):
     one_step(pkg, oracle_mod, w, fp64, step=9)
 
 
+@pytest.mark.parametrize("fp64,noise_tol", [(False, 1e-6), (False, 1e-8), (True, 1e-13)])
+def test_one_step_four_mode_pair_memory(pkg, oracle_mod, fp64, noise_tol):
+    """A pair memory of four damped oscillators, unlike the self memory, so
+    that the filter bank needs more filters (padded ranks 8 and 12 in FP32,
+    16 in FP64, with partly used matrix-core accumulator rows); amplitudes
+    kept small enough for the correlation to stay positive definite."""
+    w = wl.config(1)
+    k_self, _, wt, r0, dr = w.tables()
+    t = np.arange(w.m_max) * w.dt
+    modes = [(0.105, 0.3, 11.0), (0.09, 1.0, 2.0), (0.09, 0.7, 17.0), (0.06, 0.4, 25.0)]
+    g = w.dt * sum(a * np.exp(-t / tau) * np.cos(om * t) for a, tau, om in modes)
+    g[0] *= 0.5  # trapezoid weight of the lag-0 term
+    info = one_step(pkg, oracle_mod, w, fp64, tables=(k_self, g, wt, r0, dr), k_pair_g=g, noise_tol=noise_tol)
+    log(f"    filters {info['rank']}, Chebyshev terms {info['cheb_terms']}")
+    assert info["rank"] >= 7
+
+
 @pytest.mark.parametrize("fp64", [True, False])
 @pytest.mark.parametrize("parallel", [False, True])
 def test_one_step_crowded_cells(pkg, oracle_mod, fp64, parallel):
