@@ -1116,6 +1116,34 @@ __device__ __forceinline__ void mv_chunk(const StageView<T, SOA> &xs, const type
     }
 }
 
+// output of particle so (cell order): to the sorted vector, or to the
+// original order with an optional addend
+template <typename T>
+__device__ __forceinline__ void mv_store(const MvArgs &A, int64_t so, T o0, T o1, T o2)
+{
+    using T4 = typename V4<T>::t;
+    if (A.out_sorted) {
+        T4 o;
+        o.x = o0;
+        o.y = o1;
+        o.z = o2;
+        o.w = T(0);
+        static_cast<T4 *>(A.out_sorted)[so] = o;
+    } else {
+        const int p = A.sorted[so];
+        T *out = static_cast<T *>(A.out_orig);
+        if (A.add_orig) {
+            const T *ad = static_cast<const T *>(A.add_orig);
+            o0 += ad[p];
+            o1 += ad[A.S + p];
+            o2 += ad[2 * A.S + p];
+        }
+        out[p] = o0;
+        out[A.S + p] = o1;
+        out[2 * A.S + p] = o2;
+    }
+}
+
 // FP32 isotropic: at most 80 registers, so that six waves per SIMD (three
 // work-groups of 512, as the LDS allows) are resident
 template <typename T, bool PAR>
@@ -1242,71 +1270,114 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                 }
             }
         }
-        // the L partial sums of each particle meet in LDS
-        __syncthreads();
-        if (active) {
-            T4 q;
-            q.x = p0;
-            q.y = p1;
-            q.z = p2;
-            q.w = T(0);
-            part[sub * PG + pi] = q;
-        }
-        __syncthreads();
-        staged_all = false;
-        if (tid < m) {
-            T q0 = 0, q1 = 0, q2 = 0;
-#pragma unroll
-            for (int u = 0; u < L; ++u) {
-                const T4 q = part[u * PG + tid];
-                q0 += q.x;
-                q1 += q.y;
-                q2 += q.z;
-            }
-            const int64_t so = h0 + g0 + tid;
-            T o0 = static_cast<T>(A.a) * q0, o1 = static_cast<T>(A.a) * q1, o2 = static_cast<T>(A.a) * q2;
-            if (A.b != 0.0) {
-                const T4 xv = x[so];
-                o0 += static_cast<T>(A.b) * xv.x;
-                o1 += static_cast<T>(A.b) * xv.y;
-                o2 += static_cast<T>(A.b) * xv.z;
-            }
-            if (A.cz != 0.0) {
-                const T4 zs = static_cast<const T4 *>(A.z)[so];
-                o0 += static_cast<T>(A.cz) * zs.x;
-                o1 += static_cast<T>(A.cz) * zs.y;
-                o2 += static_cast<T>(A.cz) * zs.z;
-            }
-            if (A.r > 0) {
+        // the terms besides the pair sum, b x + cz z + sum_q c_q u_q: in FP64
+        // they are spread over the L lanes of each particle (lane sub takes
+        // terms sub, sub + L, ...: 0 is x, 1 is z, 2 + q is u_q), loaded right
+        // after the pair loop and added to the lane's partial sum; in FP32 the
+        // first lane of each particle adds them after the reduction (measured
+        // at cfg3: FP64 138 -> 128 us per mat-vec with the spread, FP32 71 ->
+        // 73 us)
+        if constexpr (sizeof(T) == 8) {
+            T e0 = 0, e1 = 0, e2 = 0;
+            if (active) {
+                const int nterm = 2 + A.r;
                 const T *coef = static_cast<const T *>(A.coef);
                 const T4 *us = static_cast<const T4 *>(A.us);
-                for (int qi = 0; qi < A.r; ++qi) {
-                    const T c = coef[qi];
-                    const T4 u = us[static_cast<int64_t>(qi) * A.S + so];
-                    o0 += c * u.x;
-                    o1 += c * u.y;
-                    o2 += c * u.z;
+                const T4 *zv = static_cast<const T4 *>(A.z);
+                for (int tt = sub; tt < nterm; tt += L) {
+                    T cf = T(0);
+                    T4 v{};
+                    if (tt == 0) {
+                        if (A.b != 0.0) {
+                            cf = static_cast<T>(A.b);
+                            v = x[s];
+                        }
+                    } else if (tt == 1) {
+                        if (A.cz != 0.0) {
+                            cf = static_cast<T>(A.cz);
+                            v = zv[s];
+                        }
+                    } else {
+                        cf = coef[tt - 2];
+                        v = us[static_cast<int64_t>(tt - 2) * A.S + s];
+                    }
+                    e0 += cf * v.x;
+                    e1 += cf * v.y;
+                    e2 += cf * v.z;
                 }
             }
-            if (A.out_sorted) {
-                T4 o;
-                o.x = o0;
-                o.y = o1;
-                o.z = o2;
-                o.w = T(0);
-                static_cast<T4 *>(A.out_sorted)[so] = o;
-            } else {
-                const int p = A.sorted[so];
-                T *out = static_cast<T *>(A.out_orig);
-                if (A.add_orig) {
-                    const T *ad = static_cast<const T *>(A.add_orig);
-                    o0 += ad[p];
-                    o1 += ad[A.S + p];
-                    o2 += ad[2 * A.S + p];
+            // the L partial sums of each particle meet in LDS
+            __syncthreads();
+            if (active) {
+                const T a = static_cast<T>(A.a);
+                T4 q;
+                q.x = a * p0 + e0;
+                q.y = a * p1 + e1;
+                q.z = a * p2 + e2;
+                q.w = T(0);
+                part[sub * PG + pi] = q;
+            }
+            __syncthreads();
+            staged_all = false;
+            if (tid < m) {
+                T o0 = 0, o1 = 0, o2 = 0;
+#pragma unroll
+                for (int u = 0; u < L; ++u) {
+                    const T4 q = part[u * PG + tid];
+                    o0 += q.x;
+                    o1 += q.y;
+                    o2 += q.z;
                 }
-                out[p] = o0;
-                out[A.S + p] = o1;
-                out[2 * A.S + p] = o2;
+                mv_store<T>(A, h0 + g0 + tid, o0, o1, o2);
+            }
+        } else {
+            // the L partial sums of each particle meet in LDS
+            __syncthreads();
+            if (active) {
+                T4 q;
+                q.x = p0;
+                q.y = p1;
+                q.z = p2;
+                q.w = T(0);
+                part[sub * PG + pi] = q;
+            }
+            __syncthreads();
+            staged_all = false;
+            if (tid < m) {
+                T q0 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+                for (int u = 0; u < L; ++u) {
+                    const T4 q = part[u * PG + tid];
+                    q0 += q.x;
+                    q1 += q.y;
+                    q2 += q.z;
+                }
+                const int64_t so = h0 + g0 + tid;
+                T o0 = static_cast<T>(A.a) * q0, o1 = static_cast<T>(A.a) * q1, o2 = static_cast<T>(A.a) * q2;
+                if (A.b != 0.0) {
+                    const T4 xv = x[so];
+                    o0 += static_cast<T>(A.b) * xv.x;
+                    o1 += static_cast<T>(A.b) * xv.y;
+                    o2 += static_cast<T>(A.b) * xv.z;
+                }
+                if (A.cz != 0.0) {
+                    const T4 zs = static_cast<const T4 *>(A.z)[so];
+                    o0 += static_cast<T>(A.cz) * zs.x;
+                    o1 += static_cast<T>(A.cz) * zs.y;
+                    o2 += static_cast<T>(A.cz) * zs.z;
+                }
+                if (A.r > 0) {
+                    const T *coef = static_cast<const T *>(A.coef);
+                    const T4 *us = static_cast<const T4 *>(A.us);
+                    for (int qi = 0; qi < A.r; ++qi) {
+                        const T c = coef[qi];
+                        const T4 u = us[static_cast<int64_t>(qi) * A.S + so];
+                        o0 += c * u.x;
+                        o1 += c * u.y;
+                        o2 += c * u.z;
+                    }
+                }
+                mv_store<T>(A, so, o0, o1, o2);
             }
         }
     }
