@@ -93,8 +93,10 @@ struct Dev {
     void *Bmix = nullptr;   // [kMaxCheb][fir_rcap]
     void *ks = nullptr, *gm = nullptr;  // [M]
     double *wtab = nullptr;             // [n_r]
-    void *nbl = nullptr;                // uint16 [cap/8][n][8] staged-stencil indices of the neighbours
-    void *nbw = nullptr;                // T [cap/4][n][4] pair weights (w, or w / R^2 for the parallel tensor)
+    void *nbl = nullptr;                // uint16 chunks of 8 staged-stencil indices, cell-blocked: cell at h0 with occ
+                                        // particles holds [cap/8][occ][8] from chunk h0 cap/8
+    void *nbw = nullptr;                // T pair weights (w, or w / R^2 for the parallel tensor), cell-blocked
+                                        // [cap/4][occ][4] from row h0 cap/4
     void *stab = nullptr;               // int2 [ncell][28] stencil of each cell (first index, base)
     int maxc = 0;                       // candidates staged per round by the mat-vec
     void *snl = nullptr;                // uint16 [capS/8][n][8] candidate lists (staged indices, within r_cut + skin)

@@ -9,8 +9,9 @@
 //   convolution outputs, F^D', F^R       T      [3][S]
 //   white-noise ring                     T      [2 half + block][3][S]  slice t at t mod len
 //   filter-bank outputs                  T      [block][rank][3][S]
-//   neighbour lists (cell-sorted order)  uint16 [cap/8][n][8] staged-stencil indices
-//                                        T      [cap/4][n][4] pair weights
+//   neighbour lists (cell-sorted order)  uint16 [cap/8][occ][8] staged-stencil indices
+//                                        T      [cap/4][occ][4] pair weights
+//                                        (blocked by cell: occ particles of one cell)
 // where the component stride S >= n is padded to a multiple of 64, so every
 // component and every ring slot starts on a 256-byte boundary and the history
 // stream is read with 16-byte (float4) or 32-byte (2 x double2) loads, a

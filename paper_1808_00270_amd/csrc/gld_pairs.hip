@@ -310,12 +310,14 @@ __device__ void make_stencil(const Geo &g, const int *__restrict__ cstart, int c
 // Neighbour lists.  Particle s (sorted order) with n_s neighbours holds in
 // entry k the neighbour's position in the concatenated candidate list of the
 // home cell's stencil (16 bits; the order in which the mat-vec stages them)
-// and the pair weight, in chunks of 8 entries:
-//   nbl  uint16 [cap/8][n][8]   entry (k, s) at ((k>>3) n + s) 8 + (k&7)
-//   nbw  T      [cap/4][n][4]   entry (k, s) at ((k>>2) n + s) 4 + (k&3)
+// and the pair weight, in chunks of 8 entries, blocked by cell: for the cell
+// starting at sorted index h0 with occ particles, particle j = s - h0,
+// C = cap/8,
+//   nbl  uint16  entry (k, s) at ((h0 C + (k>>3) occ + j) 8 + (k&7)
+//   nbw  T       entry (k, s) at ((2 h0 C + (k>>2) occ + j) 4 + (k&3)
 // so that one lane fetches 8 indices, or 4 weights, with one 16-byte load
-// (two for FP64 weights) and a wave's 64 consecutive particles read one
-// contiguous segment.  The weight is w(R_ij) for the isotropic tensor and
+// (two for FP64 weights), a wave's consecutive particles read one
+// contiguous segment, and a cell's lists are one contiguous stretch.  The weight is w(R_ij) for the isotropic tensor and
 // w(R_ij) / R_ij^2 for the parallel one, whose mat-vec rebuilds the
 // separation d from staged positions (w e e^T x = (w / R^2) d (d . x)).
 // Lists are padded to a multiple of 8 with zero weights (index of the
@@ -774,15 +776,14 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
     __syncthreads();
     const int total = sb[nst];
     const int nstage = min(total, a.stage_n);
-    // all candidates staged (one slot more holds the end marker's read)
-    const bool full = nstage == total;
+    // (one slot past the staged ones is read for candidates that are not
+    // staged, and for the end marker)
     for (int l = tid; l < nstage; l += kRefreshThreads)
         pos[l] = stencil_pos<T, EXACT64>(a, sst, sb, off, l, entry_of(sb, nst, l));
     if (tid == 0) pos[nstage] = T4{};
     __syncthreads();
 
     const int pl = tid >> 2, q = tid & 3;  // particle of the round, lane of the quad
-    const int64_t n = a.n;
     const T rc2 = static_cast<T>(a.rc2);
     const T wca_pre = static_cast<T>(a.wca_rc2 * 1.0001);
     const T Lw[3] = {static_cast<T>(a.g.L[0]), static_cast<T>(a.g.L[1]), static_cast<T>(a.g.L[2])};
@@ -794,8 +795,10 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
                      (a.g.noff[0] == 3 ? 1 : 0);
     uint16_t *ri = ring_i + pl * RI;
     T *rw = ring_w + pl * RW;
-    uint4 *nbl4 = reinterpret_cast<uint4 *>(a.nbl);
-    T4 *nbw4 = static_cast<T4 *>(a.nbw);
+    // this cell's lists (cell-blocked: chunk c of the cell's particle j at
+    // c occ + j, weight rows likewise)
+    uint4 *nbl4 = reinterpret_cast<uint4 *>(a.nbl) + static_cast<int64_t>(h0) * capc;
+    T4 *nbw4 = static_cast<T4 *>(a.nbw) + static_cast<int64_t>(h0) * 2 * capc;
     for (int g0 = 0; g0 < occ; g0 += kRefreshGroup) {
         const bool live = g0 + pl < occ;
         const int64_t s = h0 + g0 + pl;
@@ -908,9 +911,9 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
             const int fc = (cnt >> 3) + q;
             if (fc < (cnt1 >> 3) && fc < capc) {
                 const int base = (fc * 8) & (RING - 1);
-                nbl4[fc * n + s] = *reinterpret_cast<const uint4_ring *>(ri + base);
-                nbw4[(2 * fc) * n + s] = *reinterpret_cast<const RV4 *>(rw + base);
-                nbw4[(2 * fc + 1) * n + s] = *reinterpret_cast<const RV4 *>(rw + base + 4);
+                nbl4[fc * occ + (g0 + pl)] = *reinterpret_cast<const uint4_ring *>(ri + base);
+                nbw4[(2 * fc) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base);
+                nbw4[(2 * fc + 1) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base + 4);
             }
             cnt = cnt1;
         }
@@ -931,9 +934,9 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
                     rw[p & (RING - 1)] = T(0);
                 }
                 const int fl = kept >> 3, base = (fl * 8) & (RING - 1);
-                nbl4[fl * n + s] = *reinterpret_cast<const uint4_ring *>(ri + base);
-                nbw4[(2 * fl) * n + s] = *reinterpret_cast<const RV4 *>(rw + base);
-                nbw4[(2 * fl + 1) * n + s] = *reinterpret_cast<const RV4 *>(rw + base + 4);
+                nbl4[fl * occ + (g0 + pl)] = *reinterpret_cast<const uint4_ring *>(ri + base);
+                nbw4[(2 * fl) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base);
+                nbw4[(2 * fl + 1) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base + 4);
             }
             if (cnt > a.cap) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
             a.nn[s] = kept;
@@ -1005,6 +1008,7 @@ struct MvArgs {
     const int2 *stab;
     int nst;    // stencil entries per cell
     int maxc;   // staged candidates per round
+    int cap8;   // list chunks per particle (cap / 8)
     const uint4 *nbl;
     const void *nbw;
     const int *nn;
@@ -1178,9 +1182,10 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
     T2 *pyz = reinterpret_cast<T2 *>(mv_lds + static_cast<size_t>(A.maxc > BS ? A.maxc : BS) * sizeof(T4));
     T4 *part = xs;  // reused once the gathers of a round are done
     const T4 *__restrict__ x = static_cast<const T4 *>(A.x);
-    const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw);
-    const uint4 *__restrict__ nbl = A.nbl;
-    const int64_t n = A.n;
+    // this cell's lists (cell-blocked: chunk c of the cell's particle j at
+    // c occ + j, weight rows likewise)
+    const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw) + static_cast<int64_t>(h0) * 2 * A.cap8;
+    const uint4 *__restrict__ nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;
     const bool pair = A.a != 0.0;
     const T Lb[3] = {static_cast<T>(A.g.L[0]), static_cast<T>(A.g.L[1]), static_cast<T>(A.g.L[2])};
     const bool mi[3] = {A.g.nc[0] < 3, A.g.nc[1] < 3, A.g.nc[2] < 3};
@@ -1193,6 +1198,7 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
         const int sub = active ? tid / m : 0;
         const int pi = active ? tid - sub * m : 0;
         const int64_t s = h0 + g0 + pi;
+        const int j = g0 + pi;  // particle of the cell
         const int nch = (active && pair) ? (A.nn[s] + 7) >> 3 : 0;
         T own[3] = {T(0), T(0), T(0)};
         if (PAR && active) {
@@ -1208,9 +1214,9 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
             uint4 id = make_uint4(0, 0, 0, 0);
             T4 wa{}, wb{};
             if (sub < nch) {
-                id = stream_load(&nbl[sub * n + s]);
-                wa = stream_load(&nbw4[(2 * sub) * n + s]);
-                wb = stream_load(&nbw4[(2 * sub + 1) * n + s]);
+                id = stream_load(&nbl[sub * occ + j]);
+                wa = stream_load(&nbw4[(2 * sub) * occ + j]);
+                wb = stream_load(&nbw4[(2 * sub + 1) * occ + j]);
             }
             for (int c0 = 0; c0 < total; c0 += A.maxc) {
                 const int c1 = min(total, c0 + A.maxc);
@@ -1250,18 +1256,18 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                 }
                 // this lane's chunks, the next one's loads in flight
                 if (c0 > 0 && sub < nch) {
-                    id = stream_load(&nbl[sub * n + s]);
-                    wa = stream_load(&nbw4[(2 * sub) * n + s]);
-                    wb = stream_load(&nbw4[(2 * sub + 1) * n + s]);
+                    id = stream_load(&nbl[sub * occ + j]);
+                    wa = stream_load(&nbw4[(2 * sub) * occ + j]);
+                    wb = stream_load(&nbw4[(2 * sub + 1) * occ + j]);
                 }
                 for (int ch = sub; ch < nch; ch += L) {
                     const uint4 cid8 = id;
                     const T4 cwa = wa, cwb = wb;
                     if (ch + L < nch) {
                         const int nx = ch + L;
-                        id = stream_load(&nbl[nx * n + s]);
-                        wa = stream_load(&nbw4[(2 * nx) * n + s]);
-                        wb = stream_load(&nbw4[(2 * nx + 1) * n + s]);
+                        id = stream_load(&nbl[nx * occ + j]);
+                        wa = stream_load(&nbw4[(2 * nx) * occ + j]);
+                        wb = stream_load(&nbw4[(2 * nx + 1) * occ + j]);
                     }
                     if (single) mv_chunk<T, PAR, false, MI>(view, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1, p2);
                     else
@@ -1559,6 +1565,7 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
     A.stab = static_cast<const int2 *>(d.stab);
     A.nst = d.noff[0] * d.noff[1] * d.noff[2];
     A.maxc = d.maxc;
+    A.cap8 = d.cap >> 3;
     A.nbl = static_cast<const uint4 *>(d.nbl);
     A.nbw = d.nbw;
     A.nn = d.nn;
