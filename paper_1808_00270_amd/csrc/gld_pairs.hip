@@ -341,7 +341,8 @@ struct BuildArgs {
     double rc2;               // r_cut^2
     double rcs2;              // (r_cut + skin)^2: candidate lists
     int cap, capS;            // pair list / candidate list capacity
-    uint4 *snl;               // candidate lists uint16 [capS/8][n][8] (staged indices)
+    uint4 *snl;               // candidate lists: uint16 chunks of 8 staged indices, blocked by
+                              // cell (the cell at h0 holds [capS/8][occ][8] from chunk h0 capS/8)
     int *snn;                 // candidate counts
     int nst;                  // stencil entries per cell
     int stage_n;              // stencil positions the refresh stages in LDS
@@ -427,9 +428,10 @@ struct IdxChunk {
         i2 = w == 2 ? (i2 & keep) | v : i2;
         i3 = w == 3 ? (i3 & keep) | v : i3;
     }
-    __device__ __forceinline__ void store(uint4 *dst, int chunk, int64_t s, int64_t n) const
+    // dst: the cell's candidate lists, chunk c of its particle j at c occ + j
+    __device__ __forceinline__ void store(uint4 *dst, int chunk, int j, int occ) const
     {
-        dst[chunk * n + s] = make_uint4(i0, i1, i2, i3);
+        dst[static_cast<int64_t>(chunk) * occ + j] = make_uint4(i0, i1, i2, i3);
     }
 };
 
@@ -483,12 +485,12 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
     }
     __syncthreads();
     const int h0 = a.cstart[cid], h1 = a.cstart[cid + 1];
+    uint4 *cl = a.snl + static_cast<int64_t>(h0) * (a.capS >> 3);  // this cell's candidate lists
     const int total = st.base[st.n];
     const bool store = total < 65536;  // staged indices and the end marker fit 16 bits
     const float Lf[3] = {static_cast<float>(a.g.L[0]), static_cast<float>(a.g.L[1]), static_cast<float>(a.g.L[2])};
     const bool mi[3] = {a.g.nc[0] < 3, a.g.nc[1] < 3, a.g.nc[2] < 3};
     const T rcs2 = static_cast<T>(a.rcs2);
-    const int64_t n = a.n;
     for (int g0 = h0; g0 < h1; g0 += kPairThreads) {
         const int s = g0 + tid;
         const bool live = s < h1;
@@ -563,7 +565,7 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
                         if (store && cnt < a.capS) {
                             const int pos = cnt & 7;
                             ck.put(pos, static_cast<uint32_t>(c0 + queue[e][tid]));
-                            if (pos == 7) ck.store(a.snl, cnt >> 3, s, n);
+                            if (pos == 7) ck.store(cl, cnt >> 3, s - h0, h1 - h0);
                         }
                         ++cnt;
                     }
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
                 // pad the last chunk with the end marker (index total: no
                 // candidate)
                 for (int pos = kept & 7; pos < 8; ++pos) ck.put(pos, static_cast<uint32_t>(total));
-                ck.store(a.snl, kept >> 3, s, n);
+                ck.store(cl, kept >> 3, s - h0, h1 - h0);
             }
             if (cnt > a.capS || !store) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
             a.snn[s] = kept;
@@ -685,13 +687,13 @@ __device__ __forceinline__ typename V4<T>::t stencil_pos(const BuildArgs &a, con
 // the candidate indices of lane q in round k: kPerLane 16-bit entries in
 // kPerLane/2 words; past the list, the end marker
 template <typename T>
-__device__ __forceinline__ void load_candidates(const BuildArgs &a, int64_t s, int k, int q, int nch, uint32_t fill,
+__device__ __forceinline__ void load_candidates(const uint4 *cl, int j, int occ, int k, int q, int nch, uint32_t fill,
                                                 uint32_t (&w)[RefreshShape<T>::kPerLane / 2])
 {
     if constexpr (RefreshShape<T>::kPerLane == 8) {
         const int c = 4 * k + q;
         uint4 v = make_uint4(fill, fill, fill, fill);
-        if (c < nch) v = stream_load(&a.snl[c * a.n + s]);
+        if (c < nch) v = stream_load(&cl[static_cast<int64_t>(c) * occ + j]);
         w[0] = v.x;
         w[1] = v.y;
         w[2] = v.z;
@@ -699,7 +701,7 @@ __device__ __forceinline__ void load_candidates(const BuildArgs &a, int64_t s, i
     } else {
         const int h = 4 * k + q, c = h >> 1;
         uint2 v = make_uint2(fill, fill);
-        if (c < nch) v = reinterpret_cast<const uint2 *>(a.snl)[(c * a.n + s) * 2 + (h & 1)];
+        if (c < nch) v = reinterpret_cast<const uint2 *>(cl)[(static_cast<int64_t>(c) * occ + j) * 2 + (h & 1)];
         w[0] = v.x;
         w[1] = v.y;
     }
@@ -798,6 +800,7 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
     // this cell's lists (cell-blocked: chunk c of the cell's particle j at
     // c occ + j, weight rows likewise)
     uint4 *nbl4 = reinterpret_cast<uint4 *>(a.nbl) + static_cast<int64_t>(h0) * capc;
+    const uint4 *cl = a.snl + static_cast<int64_t>(h0) * (a.capS >> 3);  // candidate lists, likewise
     T4 *nbw4 = static_cast<T4 *>(a.nbw) + static_cast<int64_t>(h0) * 2 * capc;
     for (int g0 = 0; g0 < occ; g0 += kRefreshGroup) {
         const bool live = g0 + pl < occ;
@@ -824,12 +827,12 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
         T rowsum = 0;  // a bound checked with ample margin: work precision suffices
         double fx = 0, fy = 0, fz = 0;
         uint32_t nxt[PL / 2];
-        load_candidates<T>(a, s, 0, q, nch, fill, nxt);
+        load_candidates<T>(cl, g0 + pl, occ, 0, q, nch, fill, nxt);
         for (int k = 0; k < nround; ++k) {
             uint32_t cur[PL / 2];
 #pragma unroll
             for (int u = 0; u < PL / 2; ++u) cur[u] = nxt[u];
-            if (k + 1 < nround) load_candidates<T>(a, s, k + 1, q, nch, fill, nxt);
+            if (k + 1 < nround) load_candidates<T>(cl, g0 + pl, occ, k + 1, q, nch, fill, nxt);
             // the round runs in phases of straight-line code (positions,
             // distances, weights, ring writes), so that the LDS reads of its
             // candidates are in flight together
