@@ -40,11 +40,19 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
     if kind == "history":
         # ring read, velocity read, two outputs written
         return dict(bytes=(m_max - 1) * vec * sT + vec * 8 + 2 * vec * sT)
-    if kind in ("noise_spmv", "dissipative"):
-        r = info["rank"]
+    if kind == "dissipative":
         # 16-bit staged index + weight per ordered pair, the input vector
-        # once, combination inputs (z and r filter outputs), output
-        return dict(bytes=pairs * (2 + sT) + 4 * n + vec * sT * (1 + 1 + r + 1))
+        # once, the self-memory term added, the output
+        return dict(bytes=pairs * (2 + sT) + 4 * n + vec * sT * 3)
+    if kind == "noise_spmv":
+        r, K = info["rank"], info["cheb_terms"]
+        # K launches per step, averaged: K - 1 stream the pair lists (index +
+        # weight per ordered pair, the input vector once, the combination
+        # inputs z and the r filter outputs, the output); the first has no
+        # pair term and reads only the r filter outputs and writes the output
+        full = pairs * (2 + sT) + 4 * n + vec * sT * (1 + 1 + r + 1)
+        first = vec * sT * (r + 1)
+        return dict(bytes=((K - 1) * full + first) / K)
     if kind == "noise_fir":
         P = 2 * info["window_half"] + 1
         # per active launch: block * rank filters of P taps (the window kept

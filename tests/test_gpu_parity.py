@@ -333,3 +333,27 @@ def test_parallel_tensor_at_high_density_is_not_pd(pkg, oracle_mod):
     with pytest.raises(pkg.GLDError) as e:
         pkg.System.from_workload(w)
     assert e.value.status == pkg._binding.GLD_ERR_NOT_PD
+
+
+def test_kernel_timing_counts(pkg):
+    """Per-kernel timing: an event pair per launch, except the Chebyshev chain,
+    timed as a whole and counted as its K launches."""
+    w = wl.config(1)
+    s = pkg.System.from_workload(w)
+    K = s.noise_info()["cheb_terms"]
+    s.set_timing(True)
+    s.step(3)
+    kt = s.kernel_times()
+    s.set_timing(False)
+    s.step(1)
+    s.sync()
+    s.close()
+    log(f"    K={K} {kt}")
+    assert kt["history"][1] == 3
+    assert kt["noise_spmv"][1] == 3 * K
+    assert kt["noise_fir"][1] == 6      # white ring and filter bank
+    assert kt["dissipative"][1] == 6    # permute and the pair contraction
+    assert kt["update"][1] == 6
+    assert kt["neighbor"][1] == 3
+    for k in ("history", "noise_spmv", "noise_fir", "dissipative", "update", "neighbor"):
+        assert kt[k][0] > 0, k
