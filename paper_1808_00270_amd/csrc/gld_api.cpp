@@ -344,7 +344,10 @@ gld_status enqueue_step(gld_system *s)
         LAUNCH(GLD_K_NOISE_FIR, gld::launch_fir(d, 0, st));
     }
     LAUNCH(GLD_K_DISSIPATIVE, gld::launch_permute(d, st, s->noise_on ? pl.r : 0));
-    LAUNCH(GLD_K_DISSIPATIVE, gld::launch_dissipative(d, st));
+    // the refresh of the step before wrote the pair lists in ascending cell
+    // order; the mat-vecs that stream them alternate the order from here on
+    bool rev = true;
+    LAUNCH(GLD_K_DISSIPATIVE, gld::launch_dissipative(d, st, rev));
     if (s->noise_on) {
         const size_t elt = s->geo.fp64 ? 8 : 4;
         const int rc = d.fir_rcap;
@@ -370,16 +373,17 @@ gld_status enqueue_step(gld_system *s)
                 LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r, out,
                                                           nullptr, nullptr));
             } else {
+                rev = !rev;
                 LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, prev1,
                                                           prev2 ? -1.0 : 0.0, prev2, coef(k), pl.r, out, nullptr,
-                                                          nullptr));
+                                                          nullptr, rev));
             }
             prev2 = prev1;
             prev1 = out;
         }
         if (prev1) {
             LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0, prev2,
-                                                      coef(0), pl.r, nullptr, d.FR, nullptr));
+                                                      coef(0), pl.r, nullptr, d.FR, nullptr, !rev));
         } else {
             LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r, nullptr,
                                                       d.FR, nullptr));

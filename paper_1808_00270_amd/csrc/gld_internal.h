@@ -130,7 +130,7 @@ constexpr int kPartials = 1024;
 hipError_t launch_zero_int(int *p, int64_t n, hipStream_t st);
 hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out);
 hipError_t launch_history(const Dev &d, hipStream_t st);
-hipError_t launch_dissipative(const Dev &d, hipStream_t st);
+hipError_t launch_dissipative(const Dev &d, hipStream_t st, bool reverse);
 // filter bank; force = 1 produces the block holding the current step even mid-block
 hipError_t launch_fir(const Dev &d, int force, hipStream_t st);
 // white-noise ring: mode 0 writes the slice the step adds (t = step + half +
@@ -148,9 +148,12 @@ inline size_t fir_padded_rows(int half, int bf) { return static_cast<size_t>(2 *
 // out = a P x + b x + cz z + sum_q coef[q] us_q  (x, z, us: sorted T4; x, z may be null
 // when a = b = 0 / cz = 0).  Written to out_sorted (T4) or, if that is null,
 // scattered to out_orig ([3][S], original order) plus add_orig when given.
+// reverse: the cells are taken in descending order.  The launches that stream
+// the pair lists alternate the order, so that each starts on the lists the one
+// before finished on, which are still in the caches.
 hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
                        const void *z, const void *coef, int r, void *out_sorted, void *out_orig,
-                       const void *add_orig);
+                       const void *add_orig, bool reverse = false);
 // sorted copies of the dissipative input Y and of the r filter outputs of the step
 hipError_t launch_permute(const Dev &d, hipStream_t st, int r);
 // largest mat-vec staging capacity (candidates) that fits the LDS of one work-group

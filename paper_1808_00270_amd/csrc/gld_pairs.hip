@@ -58,12 +58,14 @@ struct V2<double> {
     using t = double2;
 };
 
-// 16-byte loads marked non-temporal, for the lists that stream through L2
-// once per kernel (candidate lists, pair lists): the hint keeps them from
-// evicting the positions and vectors that the 27 work-groups of a cell's
-// neighbourhood each stage.  (The refresh's pair-list stores stay ordinary:
-// their 16-byte pieces of a line arrive at different times and are merged
-// in L2.)
+// 16-byte loads marked non-temporal, for the candidate lists, which stream
+// through L2 once per refresh: the hint keeps them from evicting the
+// positions that the 27 work-groups of a cell's neighbourhood each stage.
+// (The refresh's pair-list stores stay ordinary: their 16-byte pieces of a
+// line arrive at different times and are merged in L2.  The mat-vec's loads
+// of the pair lists stay ordinary too: its launches alternate the cell order
+// so that each starts on the lists the one before read last, and with the
+// hint that alternation measured no gain, without it 5% in FP64.)
 template <typename V>
 struct NtVec;
 template <>
@@ -1021,6 +1023,7 @@ struct MvArgs {
     const void *x, *z, *coef, *us, *add_orig;
     int r;
     void *out_sorted, *out_orig;
+    int rev;  // cells in descending order
 };
 
 // The staged input vector: (x, y, z, pad) per candidate, or, for the FP64
@@ -1167,7 +1170,7 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
     constexpr int PG = BS / L;  // particles per round
     extern __shared__ __align__(32) unsigned char mv_lds[];
     __shared__ int sst[kStab], sbase[kStab];
-    const int cid = blockIdx.x;
+    const int cid = A.rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
     const int h0 = A.cstart[cid], occ = A.cstart[cid + 1] - h0;
     if (occ <= 0) return;
     const int tid = threadIdx.x;
@@ -1217,9 +1220,9 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
             uint4 id = make_uint4(0, 0, 0, 0);
             T4 wa{}, wb{};
             if (sub < nch) {
-                id = stream_load(&nbl[sub * occ + j]);
-                wa = stream_load(&nbw4[(2 * sub) * occ + j]);
-                wb = stream_load(&nbw4[(2 * sub + 1) * occ + j]);
+                id = nbl[sub * occ + j];
+                wa = nbw4[(2 * sub) * occ + j];
+                wb = nbw4[(2 * sub + 1) * occ + j];
             }
             for (int c0 = 0; c0 < total; c0 += A.maxc) {
                 const int c1 = min(total, c0 + A.maxc);
@@ -1259,18 +1262,18 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                 }
                 // this lane's chunks, the next one's loads in flight
                 if (c0 > 0 && sub < nch) {
-                    id = stream_load(&nbl[sub * occ + j]);
-                    wa = stream_load(&nbw4[(2 * sub) * occ + j]);
-                    wb = stream_load(&nbw4[(2 * sub + 1) * occ + j]);
+                    id = nbl[sub * occ + j];
+                    wa = nbw4[(2 * sub) * occ + j];
+                    wb = nbw4[(2 * sub + 1) * occ + j];
                 }
                 for (int ch = sub; ch < nch; ch += L) {
                     const uint4 cid8 = id;
                     const T4 cwa = wa, cwb = wb;
                     if (ch + L < nch) {
                         const int nx = ch + L;
-                        id = stream_load(&nbl[nx * occ + j]);
-                        wa = stream_load(&nbw4[(2 * nx) * occ + j]);
-                        wb = stream_load(&nbw4[(2 * nx + 1) * occ + j]);
+                        id = nbl[nx * occ + j];
+                        wa = nbw4[(2 * nx) * occ + j];
+                        wb = nbw4[(2 * nx + 1) * occ + j];
                     }
                     if (single) mv_chunk<T, PAR, false, MI>(view, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1, p2);
                     else
@@ -1558,9 +1561,10 @@ hipError_t launch_permute(const Dev &d, hipStream_t st, int r)
 }
 
 hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz, const void *z,
-                       const void *coef, int r, void *out_sorted, void *out_orig, const void *add_orig)
+                       const void *coef, int r, void *out_sorted, void *out_orig, const void *add_orig, bool reverse)
 {
     MvArgs A{};
+    A.rev = reverse ? 1 : 0;
     A.n = d.n;
     A.S = d.S;
     A.sorted = d.cell_sorted;
@@ -1600,10 +1604,10 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
     return launch_mv_t<float, false, false, kMvThreads32, kMvLanes32>(d, A, st);
 }
 
-hipError_t launch_dissipative(const Dev &d, hipStream_t st)
+hipError_t launch_dissipative(const Dev &d, hipStream_t st, bool reverse)
 {
     // F^D' = -(P Y) + Dneg, scattered to the original order
-    return launch_spmv(d, st, -1.0, 0.0, d.ys, 0.0, nullptr, nullptr, 0, nullptr, d.FD, d.Dneg);
+    return launch_spmv(d, st, -1.0, 0.0, d.ys, 0.0, nullptr, nullptr, 0, nullptr, d.FD, d.Dneg, reverse);
 }
 
 }  // namespace gld
