@@ -1026,13 +1026,14 @@ struct MvArgs {
     int rev;  // cells in descending order
 };
 
-// The staged input vector: (x, y, z, pad) per candidate, or, for the FP64
-// isotropic mat-vec, three arrays x[], y[], z[] of stride maxc (24 instead of
-// 32 bytes per candidate, so that two work-groups fit in a CU's LDS)
+// The staged input vector: for the isotropic mat-vec three planes x[], y[],
+// z[] of stride maxc (3 values per candidate instead of 4: at cfg3 four FP32
+// or two FP64 work-groups fit in a CU's LDS); for the parallel tensor
+// (x, y, z, own x) per candidate
 template <typename T, bool PAR>
 constexpr bool mv_soa()
 {
-    return sizeof(T) == 8 && !PAR;
+    return !PAR;
 }
 
 template <typename T, bool SOA>
@@ -1079,7 +1080,22 @@ __device__ __forceinline__ void mv_chunk(const StageView<T, SOA> &xs, const type
     const unsigned li[8] = {id.x & 0xffffu, id.x >> 16, id.y & 0xffffu, id.y >> 16,
                             id.z & 0xffffu, id.z >> 16, id.w & 0xffffu, id.w >> 16};
     const T w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-    if (!CHECK) {
+    if constexpr (!CHECK && SOA && !PAR) {
+        // one plane at a time: eight staged values live instead of 24 (the
+        // FP32 kernel then needs about 62 registers: eight waves per SIMD)
+        T acc[3] = {p0, p1, p2};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = xs.soa[q * xs.stride + li[u]];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[q] += w[u] * v[u];
+        }
+        p0 = acc[0];
+        p1 = acc[1];
+        p2 = acc[2];
+    } else if (!CHECK) {
         T4 v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) v[u] = xs.get(li[u]);
@@ -1154,8 +1170,9 @@ __device__ __forceinline__ void mv_store(const MvArgs &A, int64_t so, T o0, T o1
     }
 }
 
-// FP32 isotropic: at most 80 registers, so that six waves per SIMD (three
-// work-groups of 512, as the LDS allows) are resident
+// FP32 isotropic: at most 80 registers, so that at least six waves per SIMD
+// are resident (the kernel needs about 62: eight waves, four work-groups of
+// 512, as the LDS of the planar staging allows at cfg3)
 template <typename T, bool PAR>
 constexpr int mv_min_waves()
 {
@@ -1282,14 +1299,13 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                 }
             }
         }
-        // the terms besides the pair sum, b x + cz z + sum_q c_q u_q: in FP64
-        // they are spread over the L lanes of each particle (lane sub takes
-        // terms sub, sub + L, ...: 0 is x, 1 is z, 2 + q is u_q), loaded right
-        // after the pair loop and added to the lane's partial sum; in FP32 the
-        // first lane of each particle adds them after the reduction (measured
-        // at cfg3: FP64 138 -> 128 us per mat-vec with the spread, FP32 71 ->
-        // 73 us)
-        if constexpr (sizeof(T) == 8) {
+        // the terms besides the pair sum, b x + cz z + sum_q c_q u_q, spread
+        // over the L lanes of each particle (lane sub takes terms sub, sub + L,
+        // ...: 0 is x, 1 is z, 2 + q is u_q), loaded right after the pair
+        // loop and added to the lane's partial sum, so that their loads are
+        // not left to the end of the work-group (measured at cfg3: FP64 138 ->
+        // 128 us per mat-vec, FP32 68 -> 64 us with the planar staging)
+        {
             T e0 = 0, e1 = 0, e2 = 0;
             if (active) {
                 const int nterm = 2 + A.r;
@@ -1341,55 +1357,6 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                     o2 += q.z;
                 }
                 mv_store<T>(A, h0 + g0 + tid, o0, o1, o2);
-            }
-        } else {
-            // the L partial sums of each particle meet in LDS
-            __syncthreads();
-            if (active) {
-                T4 q;
-                q.x = p0;
-                q.y = p1;
-                q.z = p2;
-                q.w = T(0);
-                part[sub * PG + pi] = q;
-            }
-            __syncthreads();
-            staged_all = false;
-            if (tid < m) {
-                T q0 = 0, q1 = 0, q2 = 0;
-#pragma unroll
-                for (int u = 0; u < L; ++u) {
-                    const T4 q = part[u * PG + tid];
-                    q0 += q.x;
-                    q1 += q.y;
-                    q2 += q.z;
-                }
-                const int64_t so = h0 + g0 + tid;
-                T o0 = static_cast<T>(A.a) * q0, o1 = static_cast<T>(A.a) * q1, o2 = static_cast<T>(A.a) * q2;
-                if (A.b != 0.0) {
-                    const T4 xv = x[so];
-                    o0 += static_cast<T>(A.b) * xv.x;
-                    o1 += static_cast<T>(A.b) * xv.y;
-                    o2 += static_cast<T>(A.b) * xv.z;
-                }
-                if (A.cz != 0.0) {
-                    const T4 zs = static_cast<const T4 *>(A.z)[so];
-                    o0 += static_cast<T>(A.cz) * zs.x;
-                    o1 += static_cast<T>(A.cz) * zs.y;
-                    o2 += static_cast<T>(A.cz) * zs.z;
-                }
-                if (A.r > 0) {
-                    const T *coef = static_cast<const T *>(A.coef);
-                    const T4 *us = static_cast<const T4 *>(A.us);
-                    for (int qi = 0; qi < A.r; ++qi) {
-                        const T c = coef[qi];
-                        const T4 u = us[static_cast<int64_t>(qi) * A.S + so];
-                        o0 += c * u.x;
-                        o1 += c * u.y;
-                        o2 += c * u.z;
-                    }
-                }
-                mv_store<T>(A, so, o0, o1, o2);
             }
         }
     }
@@ -1461,7 +1428,7 @@ int mv_max_staging(int fp64, int parallel)
     const size_t budget = 160 * 1024 - 1024;
     size_t per;
     if (fp64) per = parallel ? sizeof(double4) + sizeof(double2) : 3 * sizeof(double);
-    else per = parallel ? sizeof(float4) + sizeof(float2) : sizeof(float4);
+    else per = parallel ? sizeof(float4) + sizeof(float2) : 3 * sizeof(float);
     return static_cast<int>(budget / per);
 }
 
