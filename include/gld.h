@@ -107,6 +107,22 @@ typedef struct {
                                   the neighbour sums then depends on when the list
                                   was built, so a resumed run agrees with an
                                   uninterrupted one to rounding, not bit for bit) */
+    int32_t noise_window;      /* W in [0, 16]; 0 and 1: the random force of every
+                                  step at that step's positions (eq. stochastic_force2).
+                                  W > 1: the variant Sec. II.C proposes (remarks after
+                                  Algorithm 1) for positions that barely move over W
+                                  steps: the random forces of W consecutive steps are
+                                  computed together, all at the positions of the
+                                  window's first step.  Windows start at the steps that
+                                  are multiples of W; after gld_write_state at a step
+                                  inside a window, the rest of that window uses the
+                                  written positions.  The filter block of the noise
+                                  plan (gld_noise_info.block) becomes the largest
+                                  multiple of W it allows; W larger than the block the
+                                  plan allows (64 / padded rank steps in FP32_MIXED,
+                                  32 / padded rank in FP64, so 8 and 2 for ranks 8 and
+                                  16) makes gld_create return GLD_ERR_INVALID_ARG.
+                                  Ignored when kT = 0. */
 } gld_params;
 
 /* Snapshot of a system.  On read, every non-NULL array is filled; on write,
@@ -132,6 +148,7 @@ typedef struct {
     double lam_singular;    /* largest lambda where some frequency's K_hat is singular */
     double err_estimate;    /* estimated relative rms error of F^R                    */
     int32_t window_half;    /* h: the filters use the white noise at lags |t| <= h    */
+    int32_t noise_window;   /* W: steps whose random forces are computed together    */
 } gld_noise_info;
 
 typedef struct gld_system gld_system;

@@ -52,12 +52,16 @@ class System:
     Tables are the discrete kernels: ``k_self[m] = K^s_m``, pair memory
     ``K^p_m(r) = w(r) g_m`` with ``w`` on the grid ``r0 + b dr``.
     ``verlet_skin`` defaults to 0.1 r_cut (0: rebuild the lists every step).
+    ``noise_window`` W > 1 computes the random forces of W consecutive steps
+    together at the positions of the window's first step (the variant of
+    Sec. II.C for positions that barely move over W steps); W must divide
+    the filter block of the noise plan.
     """
 
     def __init__(self, *, n, box, dt, mass, kT, k_self, r, v, k_pair_g=None, k_pair_w=None, r0=0.0, dr=0.01,
                  r_cut=5.0, r_cut_min=0.0, parallel=False, fp64=False, wca_sigma=1.0, wca_eps=1.0, seed=0,
                  noise_tol=0.0, lam_lo=0.0, lam_hi=0.0, max_neighbors=0, check_interval=0, verlet_skin=None,
-                 device=None, stream=None):
+                 noise_window=1, device=None, stream=None):
         import torch
 
         self._keep = []
@@ -78,7 +82,7 @@ class System:
             precision=B.GLD_FP64 if fp64 else B.GLD_FP32_MIXED, wca_sigma=wca_sigma, wca_eps=wca_eps,
             seed=int(seed) & 0xFFFFFFFFFFFFFFFF, noise_tol=noise_tol, lam_lo=lam_lo, lam_hi=lam_hi,
             max_neighbors=max_neighbors, check_interval=check_interval,
-            verlet_skin=0.1 * r_cut if verlet_skin is None else float(verlet_skin))
+            verlet_skin=0.1 * r_cut if verlet_skin is None else float(verlet_skin), noise_window=int(noise_window))
         self.n, self.m_max, self.fp64 = int(n), m_max, fp64
         nbytes = C.c_size_t()
         _check(lib().gld_workspace_size(C.byref(self.params), C.byref(nbytes)), "gld_workspace_size")

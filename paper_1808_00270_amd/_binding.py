@@ -62,6 +62,7 @@ class gld_params(C.Structure):
         ("max_neighbors", C.c_int32),
         ("check_interval", C.c_int32),
         ("verlet_skin", C.c_double),
+        ("noise_window", C.c_int32),
     ]
 
 
@@ -89,6 +90,7 @@ class gld_noise_info(C.Structure):
         ("lam_singular", C.c_double),
         ("err_estimate", C.c_double),
         ("window_half", C.c_int32),
+        ("noise_window", C.c_int32),
     ]
 
 

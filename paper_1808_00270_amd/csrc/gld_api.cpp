@@ -87,6 +87,8 @@ gld_status validate(const gld_params *p)
     if (p->max_neighbors < 0) return fail(GLD_ERR_INVALID_ARG, "max_neighbors must be >= 0");
     if (!(p->verlet_skin >= 0) || !std::isfinite(p->verlet_skin))
         return fail(GLD_ERR_INVALID_ARG, "verlet_skin must be finite and >= 0");
+    if (p->noise_window < 0 || p->noise_window > gld::kMaxFirBlock)
+        return fail(GLD_ERR_INVALID_ARG, "noise_window must be in [0, " + std::to_string(gld::kMaxFirBlock) + "]");
     return GLD_OK;
 }
 
@@ -99,6 +101,7 @@ struct Geometry {
     bool fp64 = false, parallel = false;
     int firw = 64;
     int maxc = 1;  // candidates the mat-vec stages per round
+    int win = 1;   // noise window W
 };
 
 Geometry geometry(const gld_params *p)
@@ -108,6 +111,7 @@ Geometry geometry(const gld_params *p)
     g.fp64 = p->precision == GLD_FP64;
     g.parallel = p->pair_tensor == GLD_PAIR_PARALLEL;
     g.firw = g.fp64 ? 32 : 64;
+    g.win = p->kT > 0 ? std::max(1, p->noise_window) : 1;
     const double vol = p->box[0] * p->box[1] * p->box[2];
     if (p->max_neighbors > 0) {
         g.cap = p->max_neighbors;
@@ -170,6 +174,12 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.lw, v4);
     L.take(d.ys, v4);
     L.take(d.us, static_cast<size_t>(gld::kMaxRank) * v4);
+    if (g.win > 1) {
+        // W r <= block rcap <= firw vectors of filter outputs
+        L.take(d.usw, static_cast<size_t>(g.firw) * v4);
+        for (auto &b : d.cbw) L.take(b, static_cast<size_t>(g.win) * v4);
+        L.take(d.FRw, static_cast<size_t>(g.win) * vec * elt);
+    }
     L.take(d.pos_s, static_cast<size_t>(n) * 32);
     L.take(d.reld, static_cast<size_t>(n) * 32);  // both modes: the neighbour build decides in FP64 data
     L.take(d.relf, static_cast<size_t>(n) * 16);
@@ -219,9 +229,11 @@ struct gld_system {
     int noise_on = 0;
     int check_interval = 100;
     bool graph_on = true;
-    bool graph_ready = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    // one graph per step of the noise window (one in all unless W > 1)
+    bool graph_ready[gld::kMaxFirBlock] = {};
+    hipGraph_t graph[gld::kMaxFirBlock] = {};
+    hipGraphExec_t gexec[gld::kMaxFirBlock] = {};
+    bool win_valid = false;  // the window buffers hold the current window
     bool timing = false;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
@@ -331,9 +343,75 @@ gld_status ev_end(gld_system *s, int cls, size_t idx, int launches = 1)
         if ((s_ = ev_end(s, cls, ix_)) != GLD_OK) return s_; \
     } while (0)
 
+// Noise window of W > 1 steps (the variant the remarks after Algorithm 1 of
+// Sec. II.C propose when the positions barely move over W steps): the random
+// forces of the W steps of the window holding the current step, all at the
+// current positions, into FRw.  One Clenshaw chain per step of the window;
+// the chains of two steps share each stream of the pair lists.
+gld_status enqueue_window(gld_system *s)
+{
+    const Dev &d = s->d;
+    hipStream_t st = s->st;
+    const NoisePlan &pl = s->plan;
+    const int W = d.win;
+    const size_t elt = s->geo.fp64 ? 8 : 4;
+    const size_t v4 = 4 * elt * static_cast<size_t>(d.S);
+    const int rc = d.fir_rcap;
+    auto coef = [&](int k) {
+        return static_cast<const void *>(static_cast<const char *>(d.Bmix) + static_cast<size_t>(k) * rc * elt);
+    };
+    LAUNCH(GLD_K_NOISE_SPMV, gld::launch_permute_window(d, st, pl.r));
+    // the chains are timed as a whole, as in the single-step chain
+    size_t ix_chain = 0;
+    gld_status ts = ev_begin(s, ix_chain);
+    if (ts != GLD_OK) return ts;
+    const bool timing = s->timing;
+    s->timing = false;
+    int launches = 0;
+    bool rev = true;  // the cell order alternates from launch to launch
+    for (int m0 = 0; m0 < W; m0 += 2) {
+        const int nv = std::min(2, W - m0);
+        const void *us = static_cast<const char *>(d.usw) + static_cast<size_t>(m0) * pl.r * v4;
+        auto buf = [&](int i) -> void * { return i < 0 ? nullptr : static_cast<char *>(d.cbw[i]) + m0 * v4; };
+        void *fr = static_cast<char *>(d.FRw) + static_cast<size_t>(m0) * 3 * d.S * elt;
+        int prev1 = -1, prev2 = -1;
+        for (int k = pl.K - 1; k >= 1; --k) {
+            int out = 0;
+            while (out == prev1 || out == prev2) ++out;
+            if (prev1 < 0) {
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k),
+                                                                 pl.r, us, buf(out), nullptr, nv, false));
+            } else {
+                rev = !rev;
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, buf(prev1),
+                                                                 prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(k), pl.r,
+                                                                 us, buf(out), nullptr, nv, rev));
+            }
+            ++launches;
+            prev2 = prev1;
+            prev1 = out;
+        }
+        if (prev1 >= 0) {
+            rev = !rev;
+            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, pl.alpha, pl.beta, buf(prev1),
+                                                             prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(0), pl.r, us,
+                                                             nullptr, fr, nv, rev));
+        } else {
+            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r,
+                                                             us, nullptr, fr, nv, false));
+        }
+        ++launches;
+    }
+    s->timing = timing;
+    if ((ts = ev_end(s, GLD_K_NOISE_SPMV, ix_chain, launches)) != GLD_OK) return ts;
+    return GLD_OK;
+}
+
 // One integrator step, eq. (GLD_integrator).  Every launch reads the step
-// index from device memory, so the same sequence is replayed for any step.
-gld_status enqueue_step(gld_system *s)
+// index from device memory, so the same sequence is replayed for any step;
+// with a noise window the sequence of the window's first step (slot 0) also
+// computes the window's random forces.
+gld_status enqueue_step(gld_system *s, int slot)
 {
     const Dev &d = s->d;
     hipStream_t st = s->st;
@@ -343,12 +421,18 @@ gld_status enqueue_step(gld_system *s)
         LAUNCH(GLD_K_NOISE_FIR, gld::launch_white_ring(d, 0, st));
         LAUNCH(GLD_K_NOISE_FIR, gld::launch_fir(d, 0, st));
     }
-    LAUNCH(GLD_K_DISSIPATIVE, gld::launch_permute(d, st, s->noise_on ? pl.r : 0));
+    LAUNCH(GLD_K_DISSIPATIVE, gld::launch_permute(d, st, (s->noise_on && d.win == 1) ? pl.r : 0));
     // the refresh of the step before wrote the pair lists in ascending cell
     // order; the mat-vecs that stream them alternate the order from here on
     bool rev = true;
     LAUNCH(GLD_K_DISSIPATIVE, gld::launch_dissipative(d, st, rev));
-    if (s->noise_on) {
+    if (s->noise_on && d.win > 1) {
+        if (slot == 0) {
+            gld_status ws = enqueue_window(s);
+            if (ws != GLD_OK) return ws;
+        }
+        LAUNCH(GLD_K_NOISE_SPMV, gld::launch_take_window(d, st));
+    } else if (s->noise_on) {
         const size_t elt = s->geo.fp64 ? 8 : 4;
         const int rc = d.fir_rcap;
         auto coef = [&](int k) {
@@ -408,18 +492,19 @@ gld_status enqueue_check(gld_system *s)
 
 void drop_graph(gld_system *s)
 {
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
-    s->gexec = nullptr;
-    s->graph = nullptr;
-    s->graph_ready = false;
+    for (int k = 0; k < gld::kMaxFirBlock; ++k) {
+        if (s->gexec[k]) (void)hipGraphExecDestroy(s->gexec[k]);
+        if (s->graph[k]) (void)hipGraphDestroy(s->graph[k]);
+        s->gexec[k] = nullptr;
+        s->graph[k] = nullptr;
+        s->graph_ready[k] = false;
+    }
 }
 
-gld_status build_graph(gld_system *s)
+gld_status build_graph(gld_system *s, int slot)
 {
-    drop_graph(s);
     HIP_TRY(hipStreamBeginCapture(s->st, hipStreamCaptureModeRelaxed));
-    gld_status st = enqueue_step(s);
+    gld_status st = enqueue_step(s, slot);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s->st, &g);
     if (st != GLD_OK) {
@@ -427,9 +512,9 @@ gld_status build_graph(gld_system *s)
         return st;
     }
     if (e != hipSuccess) return fail(GLD_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    s->graph = g;
-    HIP_TRY(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
-    s->graph_ready = true;
+    s->graph[slot] = g;
+    HIP_TRY(hipGraphInstantiate(&s->gexec[slot], g, nullptr, nullptr, 0));
+    s->graph_ready[slot] = true;
     return GLD_OK;
 }
 
@@ -530,6 +615,13 @@ gld_status setup_noise(gld_system *s)
     d.fir_rcap = gld::fir_rcap_for(pl.r);
     d.fir_block = gld::fir_block_for(s->geo.fp64, d.fir_rcap);
     d.fir_half = pl.half;
+    // a noise window lies inside one filter block: the block becomes the
+    // largest multiple of W that the filter bank allows
+    d.win = s->geo.win;
+    if (d.win > d.fir_block)
+        return fail(GLD_ERR_INVALID_ARG, "noise_window " + std::to_string(d.win) + " exceeds the filter block " +
+                                             std::to_string(d.fir_block) + " that this noise plan allows");
+    d.fir_block -= d.fir_block % d.win;
     d.wring_len = 2 * pl.half + d.fir_block;
     // filter taps of the window, tap-major [2 half + 1][rcap] (columns beyond
     // r zero) with block - 1 zero rows before and kFirChunk + block - 1 after
@@ -556,6 +648,7 @@ gld_status setup_noise(gld_system *s)
 // outputs, then the slices the block's earlier steps would have added
 gld_status prime_noise(gld_system *s)
 {
+    s->win_valid = false;
     if (!s->noise_on) return GLD_OK;
     HIP_TRY(gld::launch_white_ring(s->d, 1, s->st));
     HIP_TRY(gld::launch_fir(s->d, 1, s->st));
@@ -715,15 +808,25 @@ gld_status gld_step(gld_system *s, int64_t n_steps)
     if (s->latched != GLD_OK) return fail(s->latched, std::string("system is poisoned: ") + gld_status_string(s->latched));
     gld_status st;
     const bool use_graph = s->graph_on && !s->timing;
-    if (use_graph && !s->graph_ready && (st = build_graph(s)) != GLD_OK) return st;
+    const int W = s->d.win;
+    if (use_graph)
+        for (int64_t k = 0; k < std::min<int64_t>(n_steps, W); ++k) {
+            const int sl = static_cast<int>((s->step + k) % W);
+            if (!s->graph_ready[sl] && (st = build_graph(s, sl)) != GLD_OK) return st;
+        }
     for (int64_t k = 0; k < n_steps; ++k) {
         if (s->noise_on && s->d.has_pair && s->check_interval > 0 && s->step > 0 && s->step % s->check_interval == 0)
             if ((st = enqueue_check(s)) != GLD_OK) return st;
+        const int slot = static_cast<int>(s->step % W);
+        // a state installed mid-window: the rest of that window at the
+        // installed positions
+        if (slot != 0 && !s->win_valid && (st = enqueue_window(s)) != GLD_OK) return st;
         if (use_graph) {
-            HIP_TRY(hipGraphLaunch(s->gexec, s->st));
-        } else if ((st = enqueue_step(s)) != GLD_OK) {
+            HIP_TRY(hipGraphLaunch(s->gexec[slot], s->st));
+        } else if ((st = enqueue_step(s, slot)) != GLD_OK) {
             return st;
         }
+        s->win_valid = true;
         ++s->step;
     }
     return GLD_OK;
@@ -812,6 +915,7 @@ gld_status gld_noise_parameters(const gld_system *s, gld_noise_info *o)
     o->lam_singular = s->plan.sing_lo;
     o->err_estimate = s->plan.err_cheb + s->plan.err_rank + s->plan.err_window;
     o->window_half = s->noise_on ? s->plan.half : 0;
+    o->noise_window = s->d.win;
     return GLD_OK;
 }
 
@@ -890,6 +994,7 @@ gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, doub
     info->lam_singular = plan.sing_lo;
     info->err_estimate = plan.err_cheb + plan.err_rank + plan.err_window;
     info->window_half = plan.half;
+    info->noise_window = std::max(1, params->noise_window);
     return GLD_OK;
 }
 

@@ -109,6 +109,11 @@ struct Dev {
     void *relf = nullptr;               // float4 [n] the same rounded to float
     void *ys = nullptr;                 // T4 [S] dissipative input, sorted order
     void *us = nullptr;                 // T4 [fir_rcap][S] filter outputs of the step, sorted order
+    // noise window (W > 1: the random forces of W steps computed together)
+    int win = 1;
+    void *usw = nullptr;                // T4 [W][r][S] filter outputs of the window's steps, sorted order
+    void *cbw[3] = {nullptr, nullptr, nullptr};  // T4 [W][S] Clenshaw vectors of the window's chains
+    void *FRw = nullptr;                // [W][3][S] random forces of the window's steps
     int *cell_id = nullptr, *cell_slot = nullptr, *cell_count = nullptr, *cell_start = nullptr;
     int *cell_tmp = nullptr, *cell_sorted = nullptr;
     // Lanczos check (T4 [S], sorted order)
@@ -156,6 +161,17 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
                        const void *add_orig, bool reverse = false);
 // sorted copies of the dissipative input Y and of the r filter outputs of the step
 hipError_t launch_permute(const Dev &d, hipStream_t st, int r);
+// noise window: sorted copies of the r filter outputs of the W steps of the
+// window holding the current step (into usw)
+hipError_t launch_permute_window(const Dev &d, hipStream_t st, int r);
+// noise window: launch_spmv over nv consecutive vectors (x, z, out_sorted: T4
+// [nv][S]; us: T4 [nv][r][S]; out_orig: [nv][3][S]), the pair lists streamed
+// once for every two vectors (isotropic tensor) or once per vector
+hipError_t launch_spmv_window(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
+                              const void *z, const void *coef, int r, const void *us, void *out_sorted,
+                              void *out_orig, int nv, bool reverse);
+// noise window: FR = FRw[step mod W]
+hipError_t launch_take_window(const Dev &d, hipStream_t st);
 // largest mat-vec staging capacity (candidates) that fits the LDS of one work-group
 int mv_max_staging(int fp64, int parallel);
 hipError_t launch_update_r(const Dev &d, hipStream_t st);

@@ -842,6 +842,30 @@ hipError_t launch_fir(const Dev &d, int force, hipStream_t st)
     return hipGetLastError();
 }
 
+// noise window: the random force of the step is slot (step mod W) of the
+// forces the window computed
+template <typename T>
+__global__ void k_take_window(int64_t len, const T *__restrict__ FRw, T *__restrict__ FR, int W,
+                              const long long *__restrict__ d_step)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    const int64_t slot = *d_step % W;
+    FR[i] = FRw[slot * len + i];
+}
+
+hipError_t launch_take_window(const Dev &d, hipStream_t st)
+{
+    const int64_t len = 3 * d.S;
+    if (d.fp64)
+        k_take_window<double><<<blocks(len, 256), 256, 0, st>>>(len, static_cast<const double *>(d.FRw),
+                                                                static_cast<double *>(d.FR), d.win, d.d_step);
+    else
+        k_take_window<float><<<blocks(len, 256), 256, 0, st>>>(len, static_cast<const float *>(d.FRw),
+                                                               static_cast<float *>(d.FR), d.win, d.d_step);
+    return hipGetLastError();
+}
+
 hipError_t launch_update_r(const Dev &d, hipStream_t st)
 {
     const double c_v = d.dt * d.b, c_f = d.dt * d.dt / (2.0 * d.mass) * d.b;

@@ -1362,6 +1362,231 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Noise window (the variant of Sec. II.C that computes the random forces of
+// W consecutive steps together, at the positions of the window's first step).
+// Filter outputs of the W steps of the window holding the current step, in
+// cell order: usw[(m r + q) S + s] = u_q(n0 + m) of the particle sorted[s],
+// n0 = step - step mod W (W divides the filter block, so the W steps lie in
+// the block whose outputs U holds).
+template <typename T>
+__global__ void k_permute_window(int64_t n, int64_t S, const int *__restrict__ sorted, const T *__restrict__ U,
+                                 int r, int rcap, int block, int W, const long long *__restrict__ d_step,
+                                 typename V4<T>::t *__restrict__ usw)
+{
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int p = sorted[s];
+    const long long n0 = *d_step - *d_step % W;
+    for (int m = 0; m < W; ++m) {
+        const int bi = static_cast<int>((n0 + m) % block);
+        for (int q = 0; q < r; ++q) {
+            const T *uq = U + (static_cast<int64_t>(bi) * rcap + q) * 3 * S;
+            typename V4<T>::t o;
+            o.x = uq[p];
+            o.y = uq[S + p];
+            o.z = uq[2 * S + p];
+            o.w = T(0);
+            usw[(static_cast<int64_t>(m) * r + q) * S + s] = o;
+        }
+    }
+}
+
+// NV right-hand sides through one stream of the pair lists (isotropic pair
+// tensor): for v < NV,
+//   out_v = a P x_v + b x_v + cz z_v + sum_q coef[q] us_{v,q},
+// with x_v = x + v S, z_v = z + v S, us_{v,q} = us + (v r + q) S (sorted T4),
+// out_v = out_sorted + v S (sorted T4) or out_orig + v 3 S ([3][S], original
+// order).  The staging holds NV x 3 planes of maxc values; rounds, lanes and
+// the spread epilogue are those of k_mv.  Each list chunk is read once for
+// the NV vectors, so the list traffic per vector falls by NV.
+template <typename T, int BS, int L, int NV>
+__global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
+{
+    using T4 = typename V4<T>::t;
+    constexpr int PG = BS / L;
+    extern __shared__ __align__(32) unsigned char mv_lds[];
+    __shared__ int sst[kStab], sbase[kStab];
+    const int cid = A.rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
+    const int h0 = A.cstart[cid], occ = A.cstart[cid + 1] - h0;
+    if (occ <= 0) return;
+    const int tid = threadIdx.x;
+    const int nst = A.nst;
+    if (tid <= nst) {
+        const int2 e = A.stab[static_cast<int64_t>(cid) * kStab + tid];
+        sst[tid] = e.x;
+        sbase[tid] = e.y;
+    }
+    T *xsoa = reinterpret_cast<T *>(mv_lds);   // [NV][3][maxc]
+    T4 *part = reinterpret_cast<T4 *>(mv_lds);  // [NV][BS], once the gathers of a round are done
+    const unsigned ss = static_cast<unsigned>(A.maxc);
+    const T4 *__restrict__ x = static_cast<const T4 *>(A.x);
+    const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw) + static_cast<int64_t>(h0) * 2 * A.cap8;
+    const uint4 *__restrict__ nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;
+    const bool pair = A.a != 0.0;
+    __syncthreads();
+    const int total = sbase[nst];
+    bool staged_all = false;
+    for (int g0 = 0; g0 < occ; g0 += PG) {
+        const int m = min(PG, occ - g0);
+        const bool active = tid < m * L;
+        const int sub = active ? tid / m : 0;
+        const int pi = active ? tid - sub * m : 0;
+        const int64_t s = h0 + g0 + pi;
+        const int j = g0 + pi;
+        const int nch = (active && pair) ? (A.nn[s] + 7) >> 3 : 0;
+        T p[NV][3];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) p[v][0] = p[v][1] = p[v][2] = T(0);
+        if (pair) {
+            for (int c0 = 0; c0 < total; c0 += A.maxc) {
+                const int c1 = min(total, c0 + A.maxc);
+                const bool single = c0 == 0 && c1 == total;
+                if (!(single && staged_all)) {
+                    __syncthreads();
+                    for (int l = c0 + tid; l < c1; l += BS) {
+                        int lo = 0, hi = nst - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (sbase[mid] <= l) lo = mid; else hi = mid - 1;
+                        }
+                        const int t = sst[lo] + (l - sbase[lo]);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            const T4 q = x[static_cast<int64_t>(v) * A.S + t];
+                            xsoa[(3 * v + 0) * ss + (l - c0)] = q.x;
+                            xsoa[(3 * v + 1) * ss + (l - c0)] = q.y;
+                            xsoa[(3 * v + 2) * ss + (l - c0)] = q.z;
+                        }
+                    }
+                    __syncthreads();
+                    staged_all = single;
+                }
+                uint4 id = make_uint4(0, 0, 0, 0);
+                T4 wa{}, wb{};
+                if (sub < nch) {
+                    id = nbl[sub * occ + j];
+                    wa = nbw4[(2 * sub) * occ + j];
+                    wb = nbw4[(2 * sub + 1) * occ + j];
+                }
+                const unsigned cn = static_cast<unsigned>(c1 - c0);
+                for (int ch = sub; ch < nch; ch += L) {
+                    const uint4 cid8 = id;
+                    const T4 cwa = wa, cwb = wb;
+                    if (ch + L < nch) {
+                        const int nx = ch + L;
+                        id = nbl[nx * occ + j];
+                        wa = nbw4[(2 * nx) * occ + j];
+                        wb = nbw4[(2 * nx + 1) * occ + j];
+                    }
+                    const unsigned li[8] = {cid8.x & 0xffffu, cid8.x >> 16, cid8.y & 0xffffu, cid8.y >> 16,
+                                            cid8.z & 0xffffu, cid8.z >> 16, cid8.w & 0xffffu, cid8.w >> 16};
+                    T w[8] = {cwa.x, cwa.y, cwa.z, cwa.w, cwb.x, cwb.y, cwb.z, cwb.w};
+                    unsigned lo8[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        // a later round: entries outside the staged range count zero
+                        lo8[u] = li[u] - static_cast<unsigned>(c0);
+                        if (!single && lo8[u] >= cn) {
+                            lo8[u] = 0;
+                            w[u] = T(0);
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            T val[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) val[u] = xsoa[(3 * v + q) * ss + lo8[u]];
+                            T acc = p[v][q];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) acc += w[u] * val[u];
+                            p[v][q] = acc;
+                        }
+                    }
+                }
+            }
+        }
+        // b x_v + cz z_v + sum_q c_q u_{v,q}, spread over the L lanes of each
+        // particle as in k_mv
+        T e[NV][3];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) e[v][0] = e[v][1] = e[v][2] = T(0);
+        if (active) {
+            const int nterm = 2 + A.r;
+            const T *coef = static_cast<const T *>(A.coef);
+            const T4 *us = static_cast<const T4 *>(A.us);
+            const T4 *zv = static_cast<const T4 *>(A.z);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                for (int tt = sub; tt < nterm; tt += L) {
+                    T cf = T(0);
+                    T4 q{};
+                    if (tt == 0) {
+                        if (A.b != 0.0) {
+                            cf = static_cast<T>(A.b);
+                            q = x[static_cast<int64_t>(v) * A.S + s];
+                        }
+                    } else if (tt == 1) {
+                        if (A.cz != 0.0) {
+                            cf = static_cast<T>(A.cz);
+                            q = zv[static_cast<int64_t>(v) * A.S + s];
+                        }
+                    } else {
+                        cf = coef[tt - 2];
+                        q = us[(static_cast<int64_t>(v) * A.r + (tt - 2)) * A.S + s];
+                    }
+                    e[v][0] += cf * q.x;
+                    e[v][1] += cf * q.y;
+                    e[v][2] += cf * q.z;
+                }
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const T a = static_cast<T>(A.a);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T4 q;
+                q.x = a * p[v][0] + e[v][0];
+                q.y = a * p[v][1] + e[v][1];
+                q.z = a * p[v][2] + e[v][2];
+                q.w = T(0);
+                part[v * BS + sub * PG + pi] = q;
+            }
+        }
+        __syncthreads();
+        staged_all = false;
+        for (int k = tid; k < NV * m; k += BS) {
+            const int v = k / m, i = k - v * m;
+            T o0 = 0, o1 = 0, o2 = 0;
+#pragma unroll
+            for (int u = 0; u < L; ++u) {
+                const T4 q = part[v * BS + u * PG + i];
+                o0 += q.x;
+                o1 += q.y;
+                o2 += q.z;
+            }
+            const int64_t so = h0 + g0 + i;
+            if (A.out_sorted) {
+                T4 o;
+                o.x = o0;
+                o.y = o1;
+                o.z = o2;
+                o.w = T(0);
+                static_cast<T4 *>(A.out_sorted)[static_cast<int64_t>(v) * A.S + so] = o;
+            } else {
+                const int pp = A.sorted[so];
+                T *out = static_cast<T *>(A.out_orig) + static_cast<int64_t>(v) * 3 * A.S;
+                out[pp] = o0;
+                out[A.S + pp] = o1;
+                out[2 * A.S + pp] = o2;
+            }
+        }
+    }
+}
+
 Geo make_geo(const Dev &d)
 {
     Geo g{};
@@ -1527,8 +1752,8 @@ hipError_t launch_permute(const Dev &d, hipStream_t st, int r)
     return hipGetLastError();
 }
 
-hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz, const void *z,
-                       const void *coef, int r, void *out_sorted, void *out_orig, const void *add_orig, bool reverse)
+MvArgs mv_args(const Dev &d, double a, double b, const void *x, double cz, const void *z, const void *coef, int r,
+               const void *us, void *out_sorted, void *out_orig, const void *add_orig, bool reverse)
 {
     MvArgs A{};
     A.rev = reverse ? 1 : 0;
@@ -1551,11 +1776,18 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
     A.x = x;
     A.z = z;
     A.coef = coef;
-    A.us = d.us;
+    A.us = us;
     A.add_orig = add_orig;
     A.r = coef ? r : 0;
     A.out_sorted = out_sorted;
     A.out_orig = out_orig;
+    return A;
+}
+
+hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz, const void *z,
+                       const void *coef, int r, void *out_sorted, void *out_orig, const void *add_orig, bool reverse)
+{
+    const MvArgs A = mv_args(d, a, b, x, cz, z, coef, r, d.us, out_sorted, out_orig, add_orig, reverse);
     const bool mi = d.nc[0] < 3 || d.nc[1] < 3 || d.nc[2] < 3;
     if (d.fp64) {
         if (d.parallel) {
@@ -1569,6 +1801,73 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
         return launch_mv_t<float, true, false, kMvThreads32, kMvLanes32>(d, A, st);
     }
     return launch_mv_t<float, false, false, kMvThreads32, kMvLanes32>(d, A, st);
+}
+
+// the staging capacity of the NV-vector mat-vec: what d.maxc asks for, at
+// most what one work-group's LDS holds
+template <typename T, int NV>
+int mvw_staging(const Dev &d)
+{
+    const size_t budget = 160 * 1024 - 1024;
+    return static_cast<int>(std::min<size_t>(static_cast<size_t>(d.maxc), budget / (NV * 3 * sizeof(T))));
+}
+
+template <typename T, int NV>
+hipError_t launch_mvw_t(const Dev &d, MvArgs A, hipStream_t st)
+{
+    constexpr int BS = sizeof(T) == 8 ? kMvThreads64 : kMvThreads32;
+    constexpr int L = sizeof(T) == 8 ? kMvLanes64 : kMvLanes32;
+    A.maxc = mvw_staging<T, NV>(d);
+    const size_t stage = static_cast<size_t>(NV) * 3 * A.maxc * sizeof(T);
+    const size_t part = static_cast<size_t>(NV) * BS * sizeof(typename V4<T>::t);
+    const size_t shm = stage > part ? stage : part;
+    if (shm > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mvw<T, BS, L, NV>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
+        if (e != hipSuccess) return e;
+    }
+    k_mvw<T, BS, L, NV><<<d.ncell, BS, shm, st>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_window(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
+                              const void *z, const void *coef, int r, const void *us, void *out_sorted,
+                              void *out_orig, int nv, bool reverse)
+{
+    const size_t elt = d.fp64 ? 8 : 4;
+    const size_t v4 = 4 * elt * static_cast<size_t>(d.S);  // one sorted T4 vector
+    if (!d.parallel && nv == 2) {
+        const MvArgs A = mv_args(d, a, b, x, cz, z, coef, r, us, out_sorted, out_orig, nullptr, reverse);
+        return d.fp64 ? launch_mvw_t<double, 2>(d, A, st) : launch_mvw_t<float, 2>(d, A, st);
+    }
+    // the parallel tensor (or a single vector): one mat-vec per vector
+    auto at = [](const void *p, size_t off) -> const void * {
+        return p ? static_cast<const void *>(static_cast<const char *>(p) + off) : nullptr;
+    };
+    for (int v = 0; v < nv; ++v) {
+        Dev dv = d;
+        dv.us = const_cast<void *>(at(us, static_cast<size_t>(v) * r * v4));
+        void *os = out_sorted ? static_cast<char *>(out_sorted) + v * v4 : nullptr;
+        void *oo = out_orig ? static_cast<char *>(out_orig) + static_cast<size_t>(v) * 3 * d.S * elt : nullptr;
+        hipError_t e = launch_spmv(dv, st, a, b, at(x, v * v4), cz, at(z, v * v4), coef, r, os, oo, nullptr, reverse);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_permute_window(const Dev &d, hipStream_t st, int r)
+{
+    if (d.fp64)
+        k_permute_window<double><<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.S, d.cell_sorted,
+                                                                   static_cast<const double *>(d.U), r, d.fir_rcap,
+                                                                   d.fir_block, d.win, d.d_step,
+                                                                   static_cast<double4 *>(d.usw));
+    else
+        k_permute_window<float><<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.S, d.cell_sorted,
+                                                                  static_cast<const float *>(d.U), r, d.fir_rcap,
+                                                                  d.fir_block, d.win, d.d_step,
+                                                                  static_cast<float4 *>(d.usw));
+    return hipGetLastError();
 }
 
 hipError_t launch_dissipative(const Dev &d, hipStream_t st, bool reverse)

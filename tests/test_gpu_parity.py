@@ -357,3 +357,67 @@ def test_kernel_timing_counts(pkg):
     assert kt["neighbor"][1] == 3
     for k in ("history", "noise_spmv", "noise_fir", "dissipative", "update", "neighbor"):
         assert kt[k][0] > 0, k
+
+
+# --------------------------------------------------------------------------
+# noise window: the random forces of W steps computed together at the
+# positions of the window's first step (the variant of Sec. II.C, remarks
+# after Algorithm 1); the oracle evaluates each step's noise at those
+# positions
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fp64,W,parallel,graph,crowded", [
+    (False, 2, False, True, False),
+    (False, 8, False, True, False),
+    (False, 4, False, False, False),   # eager launches, no graph
+    (False, 4, True, True, False),     # parallel tensor: one mat-vec per vector
+    (True, 2, False, True, False),
+    (False, 4, False, True, True),     # two staging rounds, two particle groups
+    (True, 2, False, True, True),
+])
+def test_noise_window_matches_oracle(pkg, oracle_mod, fp64, W, parallel, graph, crowded):
+    w = wl.config(2, n=5000, rho=0.05, m_max=60, parallel=parallel)
+    R, V = wl.slab_state(w, 0.5) if crowded else w.initial_state()
+    kw = {"noise_tol": 1e-13} if fp64 else {}
+    if crowded:
+        kw.update(r=R, v=V)
+    log(f"  noise window W={W} fp64={fp64} parallel={parallel} graph={graph} crowded={crowded}")
+    s = pkg.System.from_workload(w, fp64=fp64, noise_window=W, **kw)
+    info = s.noise_info()
+    assert info["noise_window"] == W and info["block"] % W == 0
+    log(f"    filter block {info['block']}, rank {info['rank']}, Chebyshev terms {info['cheb_terms']}")
+    if not graph:
+        s.set_graph(False)
+    hist = wl.random_history(np.random.default_rng(5), w.m_max, w.n, scale=0.01)
+    o = oracle_for(oracle_mod, w)
+    tol = TOL[fp64]
+    n0 = 3 * W
+    s.write_state(R, V, step=n0, history=hist)
+    for m in range(W):
+        s.step(1)
+        assert_close(f"F^R step {n0 + m}", s.read_state()["f_r"], o.noise(n0 + m, R), tol)
+    # the next window starts from the positions reached
+    g = s.read_state()
+    s.step(1)
+    assert_close(f"F^R step {n0 + W} (next window)", s.read_state()["f_r"], o.noise(n0 + W, g["r"]), tol)
+    # a state written inside a window: the rest of that window at the written
+    # positions
+    s.write_state(g["r"], g["v"], step=n0 + 1, history=hist)
+    for m in range(1, W):
+        s.step(1)
+        assert_close(f"F^R step {n0 + m} after a write inside the window", s.read_state()["f_r"],
+                     o.noise(n0 + m, g["r"]), tol)
+    assert s.read_state()["step"] == n0 + W
+    s.close()
+
+
+def test_noise_window_beyond_the_filter_block_is_rejected(pkg):
+    w = wl.config(2, n=2000, rho=0.05, m_max=60)
+    with pytest.raises(pkg.GLDError) as e:
+        pkg.System.from_workload(w, fp64=True, noise_window=16)  # FP64 filter blocks are at most 8 steps
+    assert e.value.status == pkg._binding.GLD_ERR_INVALID_ARG
+    s = pkg.System.from_workload(w, noise_window=3)  # an odd window: one chain alone in its last pair
+    assert s.noise_info()["block"] % 3 == 0
+    s.step(7)
+    s.sync()
+    s.close()

@@ -68,6 +68,15 @@ def test_workspace_size_and_validation(pkg):
     p5, k5 = _params(pkg, precision=7)
     assert lib.gld_workspace_size(C.byref(p5), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
     assert b"box" in lib.gld_last_error() or len(lib.gld_last_error()) > 0
+    # the noise window: 0..16, and its buffers are part of the workspace
+    base = nb.value
+    for W, ok in ((-1, False), (17, False), (0, True), (1, True), (8, True)):
+        pw, kw = _params(pkg)
+        pw.noise_window = W
+        st = lib.gld_workspace_size(C.byref(pw), C.byref(nb))
+        assert st == (B.GLD_OK if ok else B.GLD_ERR_INVALID_ARG), W
+        if ok:
+            assert (nb.value > base) == (W > 1), W
 
 
 def _filters(pkg, p, lo, hi, tol):
