@@ -61,16 +61,16 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
     return {}
 
 
-def run_gpu(args, fp64):
+def run_gpu(args, fp64, window=1):
     import torch
     import paper_1808_00270_amd as pkg
     from paper_1808_00270_amd import workloads as wl
 
     w = wl.config(args.config)
-    tag = "fp64" if fp64 else "fp32-mixed"
+    tag = ("fp64" if fp64 else "fp32-mixed") + (f", noise window {window}" if window > 1 else "")
     log(f"[bench] create {w.name} {tag}")
     t0 = time.perf_counter()
-    s = pkg.System.from_workload(w, fp64=fp64)
+    s = pkg.System.from_workload(w, fp64=fp64, noise_window=window)
     t_create = time.perf_counter() - t0
     info = s.noise_info()
     log(f"[bench] created in {t_create:.1f}s, noise {info}")
@@ -205,6 +205,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly (counter runs)")
+    ap.add_argument("--window", type=int, default=8,
+                    help="also time the FP32-mixed step with this noise window (the random forces of W steps "
+                         "at the positions of the window's first step; 0 or 1: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the runs, negate this many MiB of float32 once: a kernel of known HBM "
                          "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -221,6 +224,7 @@ def main():
 
     r32 = run_gpu(args, fp64=False)
     r64 = None if args.no_fp64 else run_gpu(args, fp64=True)
+    rw = run_gpu(args, fp64=False, window=args.window) if args.window > 1 else None
     if args.calib_copy_mib > 0:
         nf = args.calib_copy_mib * (1 << 20) // 4
         a = torch.ones(nf, dtype=torch.float32, device="cuda")
@@ -266,6 +270,17 @@ def main():
             "roofline_history": roofline_entry(r64, "history", True, args.kernel_steps),
         }
         out["fp32_over_fp64"] = r64["ms_per_step"] / r32["ms_per_step"]
+    if rw is not None:
+        # a variant, not the headline: the exact method computes every step's
+        # random force at that step's positions
+        out["fp32_noise_window"] = {
+            "window": args.window, "value": w.n * 1e3 / rw["ms_per_step"], "ms_per_step": rw["ms_per_step"],
+            "speedup": r32["ms_per_step"] / rw["ms_per_step"],
+            "noise": {k: rw["info"][k] for k in ("cheb_terms", "rank", "block", "noise_window")},
+            "kernels_ms_per_step": {k: ms / args.kernel_steps for k, (ms, c) in rw["kt"].items()},
+            "note": "random forces of W consecutive steps computed together at the positions of the window's "
+                    "first step (the variant proposed for time-scale separation); not the per-step method",
+        }
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(args)
