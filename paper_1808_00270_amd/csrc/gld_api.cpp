@@ -334,6 +334,15 @@ gld_status ev_end(gld_system *s, int cls, size_t idx, int launches = 1)
     return GLD_OK;
 }
 
+// per-launch events off for a stretch timed as a whole (restored on every
+// way out of the scope)
+struct TimingPause {
+    gld_system *s;
+    bool was;
+    explicit TimingPause(gld_system *sys) : s(sys), was(sys->timing) { s->timing = false; }
+    ~TimingPause() { s->timing = was; }
+};
+
 #define LAUNCH(cls, expr)                                  \
     do {                                                   \
         size_t ix_ = 0;                                    \
@@ -365,44 +374,44 @@ gld_status enqueue_window(gld_system *s)
     size_t ix_chain = 0;
     gld_status ts = ev_begin(s, ix_chain);
     if (ts != GLD_OK) return ts;
-    const bool timing = s->timing;
-    s->timing = false;
     int launches = 0;
-    bool rev = true;  // the cell order alternates from launch to launch
-    for (int m0 = 0; m0 < W; m0 += 2) {
-        const int nv = std::min(2, W - m0);
-        const void *us = static_cast<const char *>(d.usw) + static_cast<size_t>(m0) * pl.r * v4;
-        auto buf = [&](int i) -> void * { return i < 0 ? nullptr : static_cast<char *>(d.cbw[i]) + m0 * v4; };
-        void *fr = static_cast<char *>(d.FRw) + static_cast<size_t>(m0) * 3 * d.S * elt;
-        int prev1 = -1, prev2 = -1;
-        for (int k = pl.K - 1; k >= 1; --k) {
-            int out = 0;
-            while (out == prev1 || out == prev2) ++out;
-            if (prev1 < 0) {
-                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k),
-                                                                 pl.r, us, buf(out), nullptr, nv, false));
-            } else {
+    {
+        const TimingPause pause(s);
+        bool rev = true;  // the cell order alternates from launch to launch
+        for (int m0 = 0; m0 < W; m0 += 2) {
+            const int nv = std::min(2, W - m0);
+            const void *us = static_cast<const char *>(d.usw) + static_cast<size_t>(m0) * pl.r * v4;
+            auto buf = [&](int i) -> void * { return i < 0 ? nullptr : static_cast<char *>(d.cbw[i]) + m0 * v4; };
+            void *fr = static_cast<char *>(d.FRw) + static_cast<size_t>(m0) * 3 * d.S * elt;
+            int prev1 = -1, prev2 = -1;
+            for (int k = pl.K - 1; k >= 1; --k) {
+                int out = 0;
+                while (out == prev1 || out == prev2) ++out;
+                if (prev1 < 0) {
+                    LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k),
+                                                                     pl.r, us, buf(out), nullptr, nv, false));
+                } else {
+                    rev = !rev;
+                    LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, buf(prev1),
+                                                                     prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(k), pl.r,
+                                                                     us, buf(out), nullptr, nv, rev));
+                }
+                ++launches;
+                prev2 = prev1;
+                prev1 = out;
+            }
+            if (prev1 >= 0) {
                 rev = !rev;
-                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, buf(prev1),
-                                                                 prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(k), pl.r,
-                                                                 us, buf(out), nullptr, nv, rev));
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, pl.alpha, pl.beta, buf(prev1),
+                                                                 prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(0), pl.r, us,
+                                                                 nullptr, fr, nv, rev));
+            } else {
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r,
+                                                                 us, nullptr, fr, nv, false));
             }
             ++launches;
-            prev2 = prev1;
-            prev1 = out;
-        }
-        if (prev1 >= 0) {
-            rev = !rev;
-            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, pl.alpha, pl.beta, buf(prev1),
-                                                             prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(0), pl.r, us,
-                                                             nullptr, fr, nv, rev));
-        } else {
-            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r,
-                                                             us, nullptr, fr, nv, false));
-        }
-        ++launches;
     }
-    s->timing = timing;
+    }
     if ((ts = ev_end(s, GLD_K_NOISE_SPMV, ix_chain, launches)) != GLD_OK) return ts;
     return GLD_OK;
 }
@@ -446,24 +455,24 @@ gld_status enqueue_step(gld_system *s, int slot)
         size_t ix_chain = 0;
         gld_status ts = ev_begin(s, ix_chain);
         if (ts != GLD_OK) return ts;
-        const bool timing = s->timing;
-        s->timing = false;
-        void *prev1 = nullptr, *prev2 = nullptr;
-        for (int k = pl.K - 1; k >= 1; --k) {
-            void *out = nullptr;
-            for (void *c : d.cb)
-                if (c != prev1 && c != prev2) { out = c; break; }
-            if (!prev1) {
-                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r, out,
-                                                          nullptr, nullptr));
-            } else {
-                rev = !rev;
-                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, prev1,
-                                                          prev2 ? -1.0 : 0.0, prev2, coef(k), pl.r, out, nullptr,
-                                                          nullptr, rev));
-            }
-            prev2 = prev1;
-            prev1 = out;
+        {
+            const TimingPause pause(s);
+            void *prev1 = nullptr, *prev2 = nullptr;
+            for (int k = pl.K - 1; k >= 1; --k) {
+                void *out = nullptr;
+                for (void *c : d.cb)
+                    if (c != prev1 && c != prev2) { out = c; break; }
+                if (!prev1) {
+                    LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r, out,
+                                                              nullptr, nullptr));
+                } else {
+                    rev = !rev;
+                    LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, prev1,
+                                                              prev2 ? -1.0 : 0.0, prev2, coef(k), pl.r, out, nullptr,
+                                                              nullptr, rev));
+                }
+                prev2 = prev1;
+                prev1 = out;
         }
         if (prev1) {
             LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0, prev2,
@@ -472,7 +481,7 @@ gld_status enqueue_step(gld_system *s, int slot)
             LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r, nullptr,
                                                       d.FR, nullptr));
         }
-        s->timing = timing;
+        }
         if ((ts = ev_end(s, GLD_K_NOISE_SPMV, ix_chain, pl.K)) != GLD_OK) return ts;
     }
     LAUNCH(GLD_K_UPDATE, gld::launch_update_r(d, st));
