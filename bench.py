@@ -45,14 +45,14 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
         # once, the self-memory term added, the output
         return dict(bytes=pairs * (2 + sT) + 4 * n + vec * sT * 3)
     if kind == "noise_spmv":
-        r, K = info["rank"], info["cheb_terms"]
-        # K launches per step, averaged: K - 1 stream the pair lists (index +
-        # weight per ordered pair, the input vector once, the combination
-        # inputs z and the r filter outputs, the output); the first has no
-        # pair term and reads only the r filter outputs and writes the output
+        r = info["rank"]
+        # a term that streams the pair lists: index + weight per ordered pair,
+        # the input vector once, the combination inputs z and the r filter
+        # outputs, the output; the chain's first term has no pair term and
+        # reads only the r filter outputs and writes the output
         full = pairs * (2 + sT) + 4 * n + vec * sT * (1 + 1 + r + 1)
         first = vec * sT * (r + 1)
-        return dict(bytes=((K - 1) * full + first) / K)
+        return dict(full=full, first=first)
     if kind == "noise_fir":
         P = 2 * info["window_half"] + 1
         # per active launch: block * rank filters of P taps (the window kept
@@ -95,11 +95,14 @@ def run_gpu(args, fp64, window=1):
         s.step(1)
         s.sync()
         lat.append(1e3 * (time.perf_counter() - t1))
-    # per-kernel durations with HIP events on the system's stream (same work)
+    # per-kernel durations with HIP events on the system's stream (same work),
+    # and how many of those steps' chains used the tight noise plan
+    tight0 = s.noise_info()["tight_steps"]
     s.set_timing(True)
     s.step(args.kernel_steps)
     kt = s.kernel_times()
     s.set_timing(False)
+    kt_tight = s.noise_info()["tight_steps"] - tight0
     st = s.read_state()
     # mean neighbour count from the pair weights is not exported; estimate the
     # pair count from the density (checked against the oracle's pair list)
@@ -107,8 +110,8 @@ def run_gpu(args, fp64, window=1):
     s.close()
     del s
     torch.cuda.empty_cache()
-    return dict(w=w, info=info, ms_per_step=ms_per_step, lat=lat, kt=kt, pairs=pairs, t_create=t_create,
-                status=st["status"])
+    return dict(w=w, info=info, ms_per_step=ms_per_step, lat=lat, kt=kt, kt_tight=kt_tight, pairs=pairs,
+                t_create=t_create, status=st["status"])
 
 
 def measured_traffic(workload, kind, fp64):
@@ -154,8 +157,21 @@ def roofline_entry(res, kind, fp64, kernel_steps):
         peak = FP64_PEAK_TFLOPS if fp64 else FP32_PEAK_TFLOPS
         return dict(kernel=kind, bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
                     traffic=None, avg_ms=avg, launches=cnt, flops_per_launch=fl)
-    avg = ms / cnt
-    b = alg["bytes"]
+    if kind == "noise_spmv":
+        # the chain is timed as a whole; per launch that streams the pair
+        # lists: Ka - 1 of them per step, Ka the K of the step's plan (the
+        # first term and the skipped ones take a few microseconds, counted
+        # in with the rest)
+        K, Kt, nt = info["cheb_terms"], info["cheb_terms_tight"], res["kt_tight"]
+        steps = kernel_steps
+        launches = nt * (Kt - 1) + (steps - nt) * (K - 1)
+        total = launches * alg["full"] + steps * alg["first"]
+        avg = ms / launches
+        b = total / launches
+        cnt = launches
+    else:
+        avg = ms / cnt
+        b = alg["bytes"]
     ach = b / (avg * 1e-3) / 1e9
     return dict(kernel=kind, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                 traffic=measured_traffic(w.name, kind, fp64), avg_ms=avg, launches=cnt, bytes_per_launch=b)
@@ -256,7 +272,9 @@ def main():
         "config": {"workload": w.name, "n": w.n, "rho": w.rho, "m_max": w.m_max, "r_cut": w.r_cut, "dt": w.dt,
                    "precision": "fp32-mixed (f32 history/noise, f64 positions and update)"},
         "latency_ms": pct(r32["lat"]),
-        "noise": {k: r32["info"][k] for k in ("cheb_terms", "rank", "block", "window_half", "err_estimate")},
+        "noise": {k: r32["info"][k] for k in ("cheb_terms", "cheb_terms_tight", "lam_hi", "lam_hi_tight", "rank",
+                                              "block", "window_half", "err_estimate")}
+                 | {"tight_fraction_kernel_steps": r32["kt_tight"] / args.kernel_steps},
         "kernels_ms_per_step": per_step,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | {"kernel": dom},
         "roofline_history": roof_hist,
@@ -265,7 +283,9 @@ def main():
         out["fp64_plain"] = {
             "value": w.n * 1e3 / r64["ms_per_step"], "ms_per_step": r64["ms_per_step"],
             "latency_ms": pct(r64["lat"]),
-            "noise": {k: r64["info"][k] for k in ("cheb_terms", "rank", "block", "window_half", "err_estimate")},
+            "noise": {k: r64["info"][k] for k in ("cheb_terms", "cheb_terms_tight", "rank", "block", "window_half",
+                                                  "err_estimate")}
+                     | {"tight_fraction_kernel_steps": r64["kt_tight"] / args.kernel_steps},
             "kernels_ms_per_step": {k: ms / args.kernel_steps for k, (ms, c) in r64["kt"].items()},
             "roofline_history": roofline_entry(r64, "history", True, args.kernel_steps),
         }

@@ -149,6 +149,13 @@ typedef struct {
     double err_estimate;    /* estimated relative rms error of F^R                    */
     int32_t window_half;    /* h: the filters use the white noise at lags |t| <= h    */
     int32_t noise_window;   /* W: steps whose random forces are computed together    */
+    int32_t cheb_terms_tight; /* K of the tight plan on [lam_lo, lam_hi_tight] (0: none).
+                                 A step whose largest row sum of |w| (a bound on the
+                                 spectrum of P) is at most lam_hi_tight uses it; the
+                                 noise interval chosen at create only               */
+    double lam_hi_tight;
+    int64_t tight_steps;    /* steps since create whose chain used the tight plan
+                               (synchronises with the system's stream)               */
 } gld_noise_info;
 
 typedef struct gld_system gld_system;

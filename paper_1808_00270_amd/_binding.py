@@ -91,6 +91,9 @@ class gld_noise_info(C.Structure):
         ("err_estimate", C.c_double),
         ("window_half", C.c_int32),
         ("noise_window", C.c_int32),
+        ("cheb_terms_tight", C.c_int32),
+        ("lam_hi_tight", C.c_double),
+        ("tight_steps", C.c_int64),
     ]
 
 

@@ -213,6 +213,8 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.d_flag_step, 8);
     L.take(d.d_rowmax, 8);
     L.take(d.d_rebuild, 8);
+    L.take(d.chain, static_cast<size_t>(gld::kMaxCheb) * 32);  // ChainStep
+    L.take(d.d_tight, 8);
     return L.off + 256;
 }
 
@@ -457,30 +459,34 @@ gld_status enqueue_step(gld_system *s, int slot)
         if (ts != GLD_OK) return ts;
         {
             const TimingPause pause(s);
+            if (d.cheb_kt > 0) LAUNCH(GLD_K_NOISE_SPMV, gld::launch_cheb_select(d, st));
+            // term k of the chain passes its index: with a tight plan the
+            // step's plan (k_cheb_select) sets its combination, and the terms
+            // beyond the tight plan's K return at once
             void *prev1 = nullptr, *prev2 = nullptr;
             for (int k = pl.K - 1; k >= 1; --k) {
                 void *out = nullptr;
                 for (void *c : d.cb)
                     if (c != prev1 && c != prev2) { out = c; break; }
                 if (!prev1) {
-                    LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r, out,
-                                                              nullptr, nullptr));
+                    LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r,
+                                                              out, nullptr, nullptr, false, k));
                 } else {
                     rev = !rev;
                     LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, prev1,
                                                               prev2 ? -1.0 : 0.0, prev2, coef(k), pl.r, out, nullptr,
-                                                              nullptr, rev));
+                                                              nullptr, rev, k));
                 }
                 prev2 = prev1;
                 prev1 = out;
-        }
-        if (prev1) {
-            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0, prev2,
-                                                      coef(0), pl.r, nullptr, d.FR, nullptr, !rev));
-        } else {
-            LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r, nullptr,
-                                                      d.FR, nullptr));
-        }
+            }
+            if (prev1) {
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0, prev2,
+                                                          coef(0), pl.r, nullptr, d.FR, nullptr, !rev, 0));
+            } else {
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r,
+                                                          nullptr, d.FR, nullptr, false, 0));
+            }
         }
         if ((ts = ev_end(s, GLD_K_NOISE_SPMV, ix_chain, pl.K)) != GLD_OK) return ts;
     }
@@ -573,6 +579,7 @@ gld_status setup_noise(gld_system *s)
     if (st != GLD_OK) return fail(st, err);
     const double tol = p.noise_tol > 0 ? p.noise_tol : (s->geo.fp64 ? 1e-12 : 1e-6);
     double lo = p.lam_lo, hi = p.lam_hi;
+    double hi_t = 0;  // tight plan (automatic interval only)
     const bool has_pair = d.has_pair;
     if (!(hi > lo)) {
         if (!has_pair) {
@@ -614,12 +621,20 @@ gld_status setup_noise(gld_system *s)
             }
             mu *= 4.0 * M_PI * rho;
             var *= 4.0 * M_PI * rho;
-            hi = std::max(1.25 * std::max(static_cast<double>(gmax), th[1]) + 1.0, mu + 8.0 * std::sqrt(var));
+            const double observed = 1.25 * std::max(static_cast<double>(gmax), th[1]) + 1.0;
+            hi = std::max(observed, mu + 8.0 * std::sqrt(var));
             if (std::isfinite(s->plan.sing_hi)) hi = std::min(hi, th[1] + 0.5 * (s->plan.sing_hi - th[1]));
+            // A second, tight plan on [lo, observed] for the steps whose
+            // row-sum bound stays below it (the liquid's bound settles well
+            // below the ideal-gas margin: cfg3 near 30 against 48); the
+            // device picks the plan at every step, so the tight one is used
+            // only where its interval provably holds the spectrum.
+            if (observed < hi) hi_t = observed;
         }
     }
-    st = gld::noise_build(p, lo, hi, tol, s->plan, err);
+    st = gld::noise_build(p, lo, hi, tol, s->plan, err, hi_t);
     if (st != GLD_OK) return fail(st, err);
+    if (s->plan.K + s->plan.Kt > gld::kMaxCheb) s->plan.Kt = 0;  // the mixing table holds both plans' rows
     const NoisePlan &pl = s->plan;
     d.fir_rcap = gld::fir_rcap_for(pl.r);
     d.fir_block = gld::fir_block_for(s->geo.fp64, d.fir_rcap);
@@ -644,8 +659,21 @@ gld_status setup_noise(gld_system *s)
         for (int t = 0; t < Pw; ++t)
             A[static_cast<size_t>(t + front) * d.fir_rcap + q] =
                 pl.Afilt[static_cast<size_t>(q) * pl.P + (pl.M - 1 - pl.half) + t];
+    B.resize(static_cast<size_t>(pl.K + pl.Kt) * d.fir_rcap, 0.0);  // the tight plan's rows follow
     for (int k = 0; k < pl.K; ++k)
         for (int q = 0; q < pl.r; ++q) B[static_cast<size_t>(k) * d.fir_rcap + q] = pl.Bmix[static_cast<size_t>(k) * pl.r + q];
+    for (int k = 0; k < pl.Kt; ++k)
+        for (int q = 0; q < pl.r; ++q)
+            B[static_cast<size_t>(pl.K + k) * d.fir_rcap + q] = pl.Bmix_t[static_cast<size_t>(k) * pl.r + q];
+    d.cheb_kw = pl.K;
+    d.cheb_kt = pl.Kt;
+    // a margin for the rounding of the row sums (float)
+    d.lam_tight = pl.Kt > 0 ? static_cast<float>(pl.hi_t * (1.0 - 1e-5)) : 0.0f;
+    d.cheb_ab[0] = pl.alpha;
+    d.cheb_ab[1] = pl.beta;
+    d.cheb_ab[2] = pl.alpha_t;
+    d.cheb_ab[3] = pl.beta_t;
+    HIP_TRY(hipMemsetAsync(d.d_tight, 0, 8, s->st));
     if ((st = upload_work_table(s, d.Afilt, A.data(), A.size())) != GLD_OK) return st;
     if ((st = upload_work_table(s, d.Bmix, B.data(), B.size())) != GLD_OK) return st;
     if (has_pair) d.lam_hi = pl.hi;  // from now on every pair build checks the bound
@@ -925,6 +953,15 @@ gld_status gld_noise_parameters(const gld_system *s, gld_noise_info *o)
     o->err_estimate = s->plan.err_cheb + s->plan.err_rank + s->plan.err_window;
     o->window_half = s->noise_on ? s->plan.half : 0;
     o->noise_window = s->d.win;
+    o->cheb_terms_tight = s->noise_on ? s->plan.Kt : 0;
+    o->lam_hi_tight = s->noise_on ? s->plan.hi_t : 0.0;
+    o->tight_steps = 0;
+    if (s->noise_on && s->d.d_tight) {
+        unsigned long long n = 0;
+        HIP_TRY(hipStreamSynchronize(s->st));
+        HIP_TRY(hipMemcpy(&n, s->d.d_tight, sizeof(n), hipMemcpyDeviceToHost));
+        o->tight_steps = static_cast<int64_t>(n);
+    }
     return GLD_OK;
 }
 
@@ -1004,6 +1041,9 @@ gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, doub
     info->err_estimate = plan.err_cheb + plan.err_rank + plan.err_window;
     info->window_half = plan.half;
     info->noise_window = std::max(1, params->noise_window);
+    info->cheb_terms_tight = 0;
+    info->lam_hi_tight = 0.0;
+    info->tight_steps = 0;
     return GLD_OK;
 }
 

@@ -43,13 +43,20 @@ struct NoisePlan {
     std::vector<double> S, G;    // spectra [M]
     std::vector<double> Bmix;    // [K][r]
     std::vector<double> Afilt;   // [r][P], filter taps for lags t = -(M-1)..M-1 (zero beyond half)
+    // Tight plan (Kt > 0): the expansion on [lo, hi_t], hi_t < hi, with the
+    // same filters; a step whose row-sum bound of P stays below hi_t uses it
+    int Kt = 0;
+    double hi_t = 0, alpha_t = 0, beta_t = 0, err_cheb_t = 0;
+    std::vector<double> Bmix_t;  // [Kt][r]
 };
 
 // Spectra and singular points only (no expansion).  Returns GLD_OK.
 gld_status noise_spectra(const gld_params &p, NoisePlan &plan, std::string &err);
-// Full construction on [lo, hi] with relative rms tolerance tol.
+// Full construction on [lo, hi] with relative rms tolerance tol; with
+// lo < hi_tight < hi also the tight plan on [lo, hi_tight] (one filter bank
+// for both).
 gld_status noise_build(const gld_params &p, double lo, double hi, double tol, NoisePlan &plan,
-                       std::string &err);
+                       std::string &err, double hi_tight = 0.0);
 
 // ---------------------------------------------------------------------------
 // Device-side system description passed to the launchers.
@@ -80,6 +87,12 @@ struct Dev {
     int wring_len = 1;      // slots of the white-noise ring
     double g0 = 0;
     double lam_hi = __builtin_huge_val();  // noise interval top, checked every step
+    // Chebyshev chain with a tight plan (cheb_kt > 0): terms of the wide and
+    // the tight plan, the row-sum bound below which the tight plan is used,
+    // (alpha, beta) of the wide then the tight plan
+    int cheb_kw = 0, cheb_kt = 0;
+    float lam_tight = 0;
+    double cheb_ab[4] = {0, 0, 0, 0};
 
     // state (double, [3][S])
     double *R = nullptr, *V = nullptr, *FC = nullptr, *FCn = nullptr, *Rw = nullptr;
@@ -127,6 +140,8 @@ struct Dev {
     long long *d_flag_step = nullptr;
     unsigned *d_rowmax = nullptr;  // max row sum of |w| (float bits)
     int *d_rebuild = nullptr;      // rebuild the cell order and candidate lists this step
+    void *chain = nullptr;         // ChainStep [kMaxCheb]: the chain's terms as this step's plan sets them
+    unsigned long long *d_tight = nullptr;  // steps whose chain used the tight plan
 };
 
 constexpr int kPartials = 1024;
@@ -158,7 +173,11 @@ inline size_t fir_padded_rows(int half, int bf) { return static_cast<size_t>(2 *
 // before finished on, which are still in the caches.
 hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
                        const void *z, const void *coef, int r, void *out_sorted, void *out_orig,
-                       const void *add_orig, bool reverse = false);
+                       const void *add_orig, bool reverse = false, int cheb_k = -1);
+// the plan of this step's Chebyshev chain (tight or wide, from the row-sum
+// bound the refresh left): the combination of each term, for the terms of
+// launch_spmv that pass their index cheb_k
+hipError_t launch_cheb_select(const Dev &d, hipStream_t st);
 // sorted copies of the dissipative input Y and of the r filter outputs of the step
 hipError_t launch_permute(const Dev &d, hipStream_t st, int r);
 // noise window: sorted copies of the r filter outputs of the W steps of the

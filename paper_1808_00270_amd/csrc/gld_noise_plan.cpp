@@ -114,31 +114,16 @@ gld_status noise_spectra(const gld_params &p, NoisePlan &plan, std::string &err)
     return GLD_OK;
 }
 
-gld_status noise_build(const gld_params &p, double lo, double hi, double tol, NoisePlan &plan,
-                       std::string &err)
+namespace {
+
+// Chebyshev coefficients c_k(w) of f_w(x) = sqrt(S_w + G_w x) on [lo, hi],
+// truncated after the smallest K whose tail error is within tol/2, and the
+// time-domain rows X[k][t] = (1/P) sum_{w=-(M-1)}^{M-1} c_k(|w|) cos(2 pi w t / P),
+// t = -(M-1)..M-1 (P entries per row).
+gld_status cheb_rows(const NoisePlan &plan, double lo, double hi, double tol, double sig, int &K, double &err_cheb,
+                     std::vector<double> &X, std::string &err)
 {
-    gld_status st = noise_spectra(p, plan, err);
-    if (st != GLD_OK) return st;
     const int M = plan.M, P = plan.P;
-    if (!(hi > lo)) {
-        err = "noise interval must satisfy lam_hi > lam_lo";
-        return GLD_ERR_INVALID_ARG;
-    }
-    plan.lo = lo;
-    plan.hi = hi;
-    plan.alpha = 2.0 / (hi - lo);
-    plan.beta = -(hi + lo) / (hi - lo);
-    // positive definiteness of every K_hat_w on the interval (linear in lambda)
-    for (int w = 0; w < M; ++w) {
-        const double a = plan.S[w] + plan.G[w] * lo, b = plan.S[w] + plan.G[w] * hi;
-        if (!(a > 0) || !(b > 0)) {
-            err = "noise correlation not positive definite on [" + std::to_string(lo) + ", " +
-                  std::to_string(hi) + "] at frequency " + std::to_string(w) +
-                  " (singular points " + std::to_string(plan.sing_lo) + ", " + std::to_string(plan.sing_hi) + ")";
-            return GLD_ERR_NOT_PD;
-        }
-    }
-    // Chebyshev coefficients c_k(w) of f_w(x) = sqrt(S_w + G_w x) on [lo, hi]
     const int Kc = kMaxCheb;
     const int nq = 2 * Kc;
     std::vector<double> costab(static_cast<size_t>(Kc) * nq), lam(nq);
@@ -168,15 +153,9 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
     }
     // relative rms error of truncating after K terms:
     //   sum_w wt_w (sum_{k>=K} |c_k(w)|)^2 / sum_w wt_w S_w,  wt = 1 (w=0), 2
-    double sig = 0;
-    for (int w = 0; w < M; ++w) sig += (w == 0 ? 1.0 : 2.0) * plan.S[w];
-    if (!(sig > 0)) {
-        err = "zero self noise power";
-        return GLD_ERR_NOT_PD;
-    }
     std::vector<double> tail(M, 0.0);
-    int K = Kc;
-    double err_cheb = 0;
+    K = Kc;
+    err_cheb = 0;
     for (int k = Kc - 1; k >= 0; --k) {
         double e2 = 0;
         for (int w = 0; w < M; ++w) e2 += (w == 0 ? 1.0 : 2.0) * tail[w] * tail[w];
@@ -190,16 +169,14 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
     // even the last coefficient is too large: the interval is too close to a
     // singular point for this tolerance.
     if (K >= Kc - 8) {
-        err = "Chebyshev expansion of the noise does not reach the tolerance within " +
-              std::to_string(Kc) + " terms (interval too close to a singular point)";
+        err = "Chebyshev expansion of the noise does not reach the tolerance within " + std::to_string(Kc) +
+              " terms (interval too close to a singular point)";
         return GLD_ERR_NO_CONV;
     }
-    // time-domain coefficients C[k][t] = (1/P) sum_{w=-(M-1)}^{M-1} c_k(|w|) cos(2 pi w t / P)
     std::vector<double> cosm(static_cast<size_t>(M) * M);
     for (int w = 0; w < M; ++w)
         for (int t = 0; t < M; ++t) cosm[static_cast<size_t>(w) * M + t] = cos_phase(w, t, P);
-    // X = C^T as K columns of length P (t = -(M-1)..M-1, C symmetric in t)
-    std::vector<double> X(static_cast<size_t>(K) * P);
+    X.assign(static_cast<size_t>(K) * P, 0.0);
     for (int k = 0; k < K; ++k) {
         const double *ck = &c[static_cast<size_t>(k) * M];
         for (int t = 0; t < M; ++t) {
@@ -210,11 +187,61 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
             X[static_cast<size_t>(k) * P + (M - 1) - t] = s;
         }
     }
+    return GLD_OK;
+}
+
+}  // namespace
+
+gld_status noise_build(const gld_params &p, double lo, double hi, double tol, NoisePlan &plan,
+                       std::string &err, double hi_tight)
+{
+    gld_status st = noise_spectra(p, plan, err);
+    if (st != GLD_OK) return st;
+    const int M = plan.M, P = plan.P;
+    if (!(hi > lo)) {
+        err = "noise interval must satisfy lam_hi > lam_lo";
+        return GLD_ERR_INVALID_ARG;
+    }
+    plan.lo = lo;
+    plan.hi = hi;
+    plan.alpha = 2.0 / (hi - lo);
+    plan.beta = -(hi + lo) / (hi - lo);
+    // positive definiteness of every K_hat_w on the interval (linear in lambda)
+    for (int w = 0; w < M; ++w) {
+        const double a = plan.S[w] + plan.G[w] * lo, b = plan.S[w] + plan.G[w] * hi;
+        if (!(a > 0) || !(b > 0)) {
+            err = "noise correlation not positive definite on [" + std::to_string(lo) + ", " +
+                  std::to_string(hi) + "] at frequency " + std::to_string(w) +
+                  " (singular points " + std::to_string(plan.sing_lo) + ", " + std::to_string(plan.sing_hi) + ")";
+            return GLD_ERR_NOT_PD;
+        }
+    }
+    double sig = 0;
+    for (int w = 0; w < M; ++w) sig += (w == 0 ? 1.0 : 2.0) * plan.S[w];
+    if (!(sig > 0)) {
+        err = "zero self noise power";
+        return GLD_ERR_NOT_PD;
+    }
+    int K = 0;
+    double err_cheb = 0;
+    std::vector<double> X;  // rows of the plan on [lo, hi], then those of the tight plan
+    if ((st = cheb_rows(plan, lo, hi, tol, sig, K, err_cheb, X, err)) != GLD_OK) return st;
+    int Kt = 0;
+    double err_t = 0;
+    if (hi_tight > lo && hi_tight < hi) {
+        std::vector<double> Xt;
+        if ((st = cheb_rows(plan, lo, hi_tight, tol, sig, Kt, err_t, Xt, err)) != GLD_OK) return st;
+        if (Kt < K) X.insert(X.end(), Xt.begin(), Xt.end());
+        else Kt = 0;  // no saving
+    }
+    const int Ka = K + Kt;
+    // one filter bank for both plans: the leading singular vectors of the
+    // stacked rows; X = C^T as Ka columns of length P
     std::vector<double> Vr;
-    hestenes_svd(P, K, X, Vr);
-    std::vector<int> order(K);
-    std::vector<double> sv(K);
-    for (int q = 0; q < K; ++q) {
+    hestenes_svd(P, Ka, X, Vr);
+    std::vector<int> order(Ka);
+    std::vector<double> sv(Ka);
+    for (int q = 0; q < Ka; ++q) {
         double s = 0;
         for (int i = 0; i < P; ++i) s += X[static_cast<size_t>(q) * P + i] * X[static_cast<size_t>(q) * P + i];
         sv[q] = std::sqrt(s);
@@ -225,16 +252,17 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
     // with eigenvalue x the error is sum_t (dC^T tau)_t xi_t, xi_t iid N(0,1),
     // tau_k = T_k(x~), |tau|^2 <= K; hence its rms relative to the signal
     // (variance c0 = sig / P per component) is at most
-    //     sqrt(K) ||dC||_2 / sqrt(c0),  ||dC||_2 = sigma_{r+1}.
+    //     sqrt(K) ||dC||_2 / sqrt(c0),  ||dC||_2 = sigma_{r+1}
+    // (for either plan: its rows are part of the stacked matrix, and K >= Kt).
     // Error budget: Chebyshev tail tol/2, rank tol/4, filter window tol/4.
     // Smallest r with the rank bound within tol/4:
     const double c0 = sig / P;
-    int r = K;
-    for (int q = K - 1; q >= 1; --q) {
+    int r = Ka;
+    for (int q = Ka - 1; q >= 1; --q) {
         if (std::sqrt(static_cast<double>(K) / c0) * sv[order[q]] > 0.25 * tol) break;  // keep order[q]
         r = q;
     }
-    const double dropped_max = r < K ? sv[order[r]] : 0.0;
+    const double dropped_max = r < Ka ? sv[order[r]] : 0.0;
     if (r > kMaxRank) {
         err = "noise filter bank needs rank " + std::to_string(r) + " > " + std::to_string(kMaxRank);
         return GLD_ERR_NO_CONV;
@@ -243,25 +271,34 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
     plan.r = r;
     plan.err_cheb = err_cheb;
     plan.err_rank = std::sqrt(static_cast<double>(K) / c0) * dropped_max;
+    plan.Kt = Kt;
+    plan.hi_t = Kt > 0 ? hi_tight : 0.0;
+    plan.alpha_t = Kt > 0 ? 2.0 / (hi_tight - lo) : 0.0;
+    plan.beta_t = Kt > 0 ? -(hi_tight + lo) / (hi_tight - lo) : 0.0;
+    plan.err_cheb_t = err_t;
     plan.Bmix.assign(static_cast<size_t>(K) * r, 0.0);
+    plan.Bmix_t.assign(static_cast<size_t>(Kt) * r, 0.0);
     plan.Afilt.assign(static_cast<size_t>(r) * P, 0.0);
     for (int qq = 0; qq < r; ++qq) {
         const int q = order[qq];
         const double s = sv[q];
-        for (int k = 0; k < K; ++k) plan.Bmix[static_cast<size_t>(k) * r + qq] = Vr[static_cast<size_t>(k) * K + q] * s;
+        for (int k = 0; k < K; ++k) plan.Bmix[static_cast<size_t>(k) * r + qq] = Vr[static_cast<size_t>(k) * Ka + q] * s;
+        for (int k = 0; k < Kt; ++k)
+            plan.Bmix_t[static_cast<size_t>(k) * r + qq] = Vr[static_cast<size_t>(K + k) * Ka + q] * s;
         for (int t = 0; t < P; ++t)
             plan.Afilt[static_cast<size_t>(qq) * P + t] = (s > 0) ? X[static_cast<size_t>(q) * P + t] / s : 0.0;
     }
     // Filter window.  The taps decay with the memory; dropping the lags
     // |t| > h changes C = B A by dC (its columns |t| > h), with the same
-    // bound as above: sqrt(K) ||dC||_F / sqrt(c0) <= tol/4.  Smallest h:
+    // bound as above: sqrt(K) ||dC||_F / sqrt(c0) <= tol/4, the columns of
+    // both plans counted together.  Smallest h:
     std::vector<double> col2(P, 0.0);  // squared column norms of B A
     for (int t = 0; t < P; ++t) {
         double acc = 0;
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < Ka; ++k) {
+            const double *brow = k < K ? &plan.Bmix[static_cast<size_t>(k) * r] : &plan.Bmix_t[static_cast<size_t>(k - K) * r];
             double v = 0;
-            for (int q = 0; q < r; ++q)
-                v += plan.Bmix[static_cast<size_t>(k) * r + q] * plan.Afilt[static_cast<size_t>(q) * P + t];
+            for (int q = 0; q < r; ++q) v += brow[q] * plan.Afilt[static_cast<size_t>(q) * P + t];
             acc += v * v;
         }
         col2[t] = acc;
@@ -281,5 +318,4 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
             if (std::abs(t - (M - 1)) > h) plan.Afilt[static_cast<size_t>(q) * P + t] = 0.0;
     return GLD_OK;
 }
-
 }  // namespace gld

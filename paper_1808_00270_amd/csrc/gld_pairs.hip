@@ -1007,6 +1007,15 @@ __global__ void k_permute(int64_t n, int64_t S, const int *__restrict__ sorted, 
 // is sorted T4 or scattered to the original order [3][S] (out_orig),
 // optionally plus add_orig[p].
 // ---------------------------------------------------------------------------
+// One term of the Chebyshev chain as the plan of the step sets it: the
+// combination out = a P x + b x + cz z + sum_q B[row][q] u_q, or nothing
+// (skip) for the terms beyond the chosen plan's K
+struct ChainStep {
+    double a, b, cz;
+    int row;   // row of the mixing table (the tight plan's rows follow the wide plan's)
+    int skip;
+};
+
 struct MvArgs {
     int64_t n, S;
     const int *sorted, *cstart;
@@ -1024,6 +1033,11 @@ struct MvArgs {
     int r;
     void *out_sorted, *out_orig;
     int rev;  // cells in descending order
+    // a term of the Chebyshev chain whose plan is chosen on the device:
+    // chain[cheb_k] holds a, b, cz and the row of coef (the mixing table,
+    // rcap per row); null for every other mat-vec
+    const ChainStep *chain;
+    int cheb_k, rcap;
 };
 
 // The staged input vector: for the isotropic mat-vec three planes x[], y[],
@@ -1187,6 +1201,17 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
     constexpr int PG = BS / L;  // particles per round
     extern __shared__ __align__(32) unsigned char mv_lds[];
     __shared__ int sst[kStab], sbase[kStab];
+    double ca = A.a, cb = A.b, ccz = A.cz;
+    const T *coefp = static_cast<const T *>(A.coef);
+    if (A.chain) {
+        // a term of the Chebyshev chain: its coefficients follow this step's plan
+        const ChainStep cs = A.chain[A.cheb_k];
+        if (cs.skip) return;
+        ca = cs.a;
+        cb = cs.b;
+        ccz = cs.cz;
+        coefp += static_cast<int64_t>(cs.row) * A.rcap;
+    }
     const int cid = A.rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
     const int h0 = A.cstart[cid], occ = A.cstart[cid + 1] - h0;
     if (occ <= 0) return;
@@ -1209,7 +1234,7 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
     // c occ + j, weight rows likewise)
     const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw) + static_cast<int64_t>(h0) * 2 * A.cap8;
     const uint4 *__restrict__ nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;
-    const bool pair = A.a != 0.0;
+    const bool pair = ca != 0.0;
     const T Lb[3] = {static_cast<T>(A.g.L[0]), static_cast<T>(A.g.L[1]), static_cast<T>(A.g.L[2])};
     const bool mi[3] = {A.g.nc[0] < 3, A.g.nc[1] < 3, A.g.nc[2] < 3};
     __syncthreads();
@@ -1309,20 +1334,20 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
             T e0 = 0, e1 = 0, e2 = 0;
             if (active) {
                 const int nterm = 2 + A.r;
-                const T *coef = static_cast<const T *>(A.coef);
+                const T *coef = coefp;
                 const T4 *us = static_cast<const T4 *>(A.us);
                 const T4 *zv = static_cast<const T4 *>(A.z);
                 for (int tt = sub; tt < nterm; tt += L) {
                     T cf = T(0);
                     T4 v{};
                     if (tt == 0) {
-                        if (A.b != 0.0) {
-                            cf = static_cast<T>(A.b);
+                        if (cb != 0.0) {
+                            cf = static_cast<T>(cb);
                             v = x[s];
                         }
                     } else if (tt == 1) {
-                        if (A.cz != 0.0) {
-                            cf = static_cast<T>(A.cz);
+                        if (ccz != 0.0) {
+                            cf = static_cast<T>(ccz);
                             v = zv[s];
                         }
                     } else {
@@ -1337,7 +1362,7 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
             // the L partial sums of each particle meet in LDS
             __syncthreads();
             if (active) {
-                const T a = static_cast<T>(A.a);
+                const T a = static_cast<T>(ca);
                 T4 q;
                 q.x = a * p0 + e0;
                 q.y = a * p1 + e1;
@@ -1587,6 +1612,49 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
     }
 }
 
+// The plan of this step's Chebyshev chain.  The refresh of the step before
+// left the largest row sum of |w| (a Gershgorin bound on the spectrum of P,
+// ||T_ij|| = 1) in rowmax; at most lam_t, the tight plan's interval holds the
+// spectrum and its shorter expansion is used.  Term k of the chain (launched
+// in the order k = Kw-1 .. 0) then gets its Clenshaw combination:
+//   b_{Ka-1} = v_{Ka-1};  b_k = v_k + 2 P~ b_{k+1} - b_{k+2};  F = v_0 + P~ b_1 - b_2,
+// with b_{Ka} = b_{Ka+1} = 0, P~ = alpha P + beta and Ka the chosen plan's K;
+// the terms k >= Ka are skipped.
+struct ChainSel {
+    int Kw, Kt;           // terms of the wide and the tight plan
+    float lam_t;          // largest row-sum bound for the tight plan
+    double aw, bw, at, bt;
+};
+
+__global__ void k_cheb_select(ChainSel c, const unsigned *__restrict__ rowmax, ChainStep *__restrict__ out,
+                              unsigned long long *__restrict__ tight_steps)
+{
+    const float g = __uint_as_float(*rowmax);
+    const bool tight = c.Kt > 0 && g <= c.lam_t;
+    const int Ka = tight ? c.Kt : c.Kw;
+    const double al = tight ? c.at : c.aw, be = tight ? c.bt : c.bw;
+    for (int k = threadIdx.x; k < c.Kw; k += blockDim.x) {
+        ChainStep e;
+        e.row = (tight ? c.Kw : 0) + k;
+        e.skip = k >= Ka ? 1 : 0;
+        if (k >= Ka - 1) {
+            e.a = 0.0;
+            e.b = 0.0;
+            e.cz = 0.0;
+        } else if (k >= 1) {
+            e.a = 2.0 * al;
+            e.b = 2.0 * be;
+            e.cz = k == Ka - 2 ? 0.0 : -1.0;
+        } else {
+            e.a = al;
+            e.b = be;
+            e.cz = Ka == 2 ? 0.0 : -1.0;
+        }
+        out[k] = e;
+    }
+    if (threadIdx.x == 0 && tight) atomicAdd(tight_steps, 1ull);
+}
+
 Geo make_geo(const Dev &d)
 {
     Geo g{};
@@ -1785,9 +1853,17 @@ MvArgs mv_args(const Dev &d, double a, double b, const void *x, double cz, const
 }
 
 hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz, const void *z,
-                       const void *coef, int r, void *out_sorted, void *out_orig, const void *add_orig, bool reverse)
+                       const void *coef, int r, void *out_sorted, void *out_orig, const void *add_orig, bool reverse,
+                       int cheb_k)
 {
-    const MvArgs A = mv_args(d, a, b, x, cz, z, coef, r, d.us, out_sorted, out_orig, add_orig, reverse);
+    MvArgs A = mv_args(d, a, b, x, cz, z, coef, r, d.us, out_sorted, out_orig, add_orig, reverse);
+    if (cheb_k >= 0 && d.cheb_kt > 0) {
+        // the step's plan decides (k_cheb_select): coef is the whole mixing table
+        A.chain = static_cast<const ChainStep *>(d.chain);
+        A.cheb_k = cheb_k;
+        A.rcap = d.fir_rcap;
+        A.coef = d.Bmix;
+    }
     const bool mi = d.nc[0] < 3 || d.nc[1] < 3 || d.nc[2] < 3;
     if (d.fp64) {
         if (d.parallel) {
@@ -1853,6 +1929,20 @@ hipError_t launch_spmv_window(const Dev &d, hipStream_t st, double a, double b, 
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_cheb_select(const Dev &d, hipStream_t st)
+{
+    ChainSel c{};
+    c.Kw = d.cheb_kw;
+    c.Kt = d.cheb_kt;
+    c.lam_t = d.lam_tight;
+    c.aw = d.cheb_ab[0];
+    c.bw = d.cheb_ab[1];
+    c.at = d.cheb_ab[2];
+    c.bt = d.cheb_ab[3];
+    k_cheb_select<<<1, 64, 0, st>>>(c, d.d_rowmax, static_cast<ChainStep *>(d.chain), d.d_tight);
+    return hipGetLastError();
 }
 
 hipError_t launch_permute_window(const Dev &d, hipStream_t st, int r)

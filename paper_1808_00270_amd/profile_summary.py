@@ -77,26 +77,46 @@ def kernel_table(path: str):
     return c.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
 
 
-def counter_means(path: str, counter: str):
-    """Mean counter value (KiB) per dispatch, by kernel name."""
+def kernel_durations(path: str):
+    """Per-dispatch durations (us), by kernel name."""
+    c = db(path)
+    acc = collections.defaultdict(list)
+    for name, start, end in c.execute("select name, start, end from kernels"):
+        acc[name].append((end - start) / 1e3)
+    return acc
+
+
+def counter_values(path: str, counter: str):
+    """Counter value (KiB) of every dispatch, by kernel name."""
     c = db(path)
     rows = c.execute("select dispatch_id, kernel_name, sum(value) from counters_collection "
                      "where counter_name = ? group by dispatch_id", (counter,)).fetchall()
     acc = collections.defaultdict(list)
     for _, name, v in rows:
         acc[name].append(v)
-    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+    return acc
+
+
+def working(values):
+    """The dispatches that did the class's work, and the number of the
+    others: a launch below a quarter of the class median did next to nothing
+    (the Chebyshev chain's first term, which has no pair term, and the terms
+    beyond the K of the step's plan, which return at once).  The rebuild
+    kernels and the filter bank work one launch in several; their median
+    launch is the empty one, so they keep every launch."""
+    v = sorted(values)
+    med = v[len(v) // 2]
+    keep = [x for x in values if x >= 0.25 * med]
+    return keep, len(values) - len(keep)
 
 
 def pick(table: dict, pattern: str):
-    hits = [(k, v) for k, v in table.items() if re.search(pattern, k)]
-    if not hits:
+    """(mean over the working dispatches, their count, launches that returned at once)."""
+    vals = [x for k, v in table.items() if re.search(pattern, k) for x in v]
+    if not vals:
         return None
-    if len(hits) == 1:
-        return hits[0][1]
-    # several instantiations: dispatch-weighted mean
-    tot = sum(v[1] for _, v in hits)
-    return (sum(v[0] * v[1] for _, v in hits) / tot, tot)
+    keep, skipped = working(vals)
+    return (sum(keep) / len(keep), len(keep), skipped)
 
 
 def main():
@@ -125,20 +145,23 @@ def main():
     kt = kernel_table(a.kt)
     for name, calls, total, avg, pctg in kt[:16]:
         lines.append(f"| `{short(name)}` | {calls} | {avg:.1f} | {total / 1e3:.2f} | {pctg:.1f} |")
-    lines += ["", "Average duration per launch by kernel class (" + a.precision + " path):", ""]
+    lines += ["", "Average duration per launch by kernel class (" + a.precision + " path; launches below a "
+              "quarter of the class median did next to nothing and are counted apart: the chain's first term "
+              "and the terms beyond the K of the step's noise plan):", ""]
     avg_by_class = {}
+    durs = kernel_durations(a.kt)
     for cls, pat in classes.items():
-        sel = [(calls, total) for name, calls, total, _, _ in kt if re.search(pat, name)]
-        if sel:
-            calls = sum(c for c, _ in sel)
-            avg_by_class[cls] = sum(t for _, t in sel) / calls
-            lines.append(f"- {cls} (`{pat}`): {avg_by_class[cls]:.1f} us over {calls} launches")
+        d = pick(durs, pat)
+        if d:
+            avg_by_class[cls] = d[0]
+            extra = f" (+ {d[2]} that did next to nothing)" if d[2] else ""
+            lines.append(f"- {cls} (`{pat}`): {d[0]:.1f} us over {d[1]} launches{extra}")
     out = {"name": a.name, "precision": a.precision, "source_sha256": source_hash(), "avg_us": avg_by_class,
            "kernels": {}}
 
     if a.fetch and a.write and a.calib_bytes > 0:
-        fe = counter_means(a.fetch, "FETCH_SIZE")
-        wr = counter_means(a.write, "WRITE_SIZE")
+        fe = counter_values(a.fetch, "FETCH_SIZE")
+        wr = counter_values(a.write, "WRITE_SIZE")
         cf, cw = pick(fe, CALIB), pick(wr, CALIB)
         if cf is None or cw is None:
             raise SystemExit("calibration kernel not found in the counter runs")

@@ -421,3 +421,64 @@ def test_noise_window_beyond_the_filter_block_is_rejected(pkg):
     s.step(7)
     s.sync()
     s.close()
+
+
+# --------------------------------------------------------------------------
+# tight and wide noise plans: the chain of a step uses the shorter expansion
+# on [lam_lo, lam_hi_tight] when the largest row sum of |w| (a bound on the
+# spectrum of P) is at most lam_hi_tight, else the one on [lam_lo, lam_hi]
+# --------------------------------------------------------------------------
+
+def row_sum_bound(w, R):
+    """max_i sum_j |w(R_ij)| over pairs within r_cut (minimum image)."""
+    from scipy.spatial import cKDTree
+    _, _, wt, r0, dr = w.tables()
+    L = w.box
+    X = np.mod(R, L)
+    X[X >= L] = 0.0
+    pairs = cKDTree(X, boxsize=L).query_pairs(w.r_cut, output_type="ndarray")
+    d = X[pairs[:, 0]] - X[pairs[:, 1]]
+    d -= L * np.round(d / L)
+    wv = np.abs(np.interp(np.linalg.norm(d, axis=1), r0 + dr * np.arange(len(wt)), wt))
+    rows = np.zeros(w.n)
+    np.add.at(rows, pairs[:, 0], wv)
+    np.add.at(rows, pairs[:, 1], wv)
+    return rows.max()
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_tight_and_wide_noise_plans_match_oracle(pkg, oracle_mod, fp64):
+    w = wl.config(2, n=5000, rho=0.05, m_max=60)
+    s = pkg.System.from_workload(w, fp64=fp64, **({"noise_tol": 1e-13} if fp64 else {}))
+    info = s.noise_info()
+    log(f"    K {info['cheb_terms']} on [{info['lam_lo']:.3f}, {info['lam_hi']:.3f}], tight K "
+        f"{info['cheb_terms_tight']} up to {info['lam_hi_tight']:.3f}")
+    assert 0 < info["cheb_terms_tight"] < info["cheb_terms"]
+    hist = wl.random_history(np.random.default_rng(3), w.m_max, w.n, scale=0.01)
+    o = oracle_for(oracle_mod, w)
+    tol = TOL[fp64]
+    R, V = w.initial_state()
+    g0 = row_sum_bound(w, R)
+    log(f"    initial row-sum bound {g0:.3f}")
+    assert g0 <= info["lam_hi_tight"]
+    s.write_state(R, V, step=4, history=hist)
+    t0 = s.noise_info()["tight_steps"]
+    s.step(1)
+    assert s.noise_info()["tight_steps"] == t0 + 1
+    assert_close("F^R (tight plan)", s.read_state()["f_r"], o.noise(4, R), tol)
+    # a denser arrangement whose bound lies between the two: the wide plan
+    # (its smallest eigenvalue hardly moves: -0.672 against -0.670 at 0.55)
+    for frac in (0.6, 0.55, 0.5):
+        Rs, Vs = wl.slab_state(w, frac)
+        gs = row_sum_bound(w, Rs)
+        log(f"    slab {frac}: row-sum bound {gs:.3f}")
+        if info["lam_hi_tight"] < gs < info["lam_hi"]:
+            break
+    else:
+        pytest.fail("no slab with a row-sum bound between the two plans")
+    s.write_state(Rs, Vs, step=9, history=hist)
+    t1 = s.noise_info()["tight_steps"]
+    s.step(1)
+    assert s.noise_info()["tight_steps"] == t1
+    assert_close("F^R (wide plan)", s.read_state()["f_r"], o.noise(9, Rs), tol)
+    s.close()
