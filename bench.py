@@ -158,17 +158,11 @@ def roofline_entry(res, kind, fp64, kernel_steps):
         return dict(kernel=kind, bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
                     traffic=None, avg_ms=avg, launches=cnt, flops_per_launch=fl)
     if kind == "noise_spmv":
-        # the chain is timed as a whole; per launch that streams the pair
-        # lists: Ka - 1 of them per step, Ka the K of the step's plan (the
-        # first term and the skipped ones take a few microseconds, counted
-        # in with the rest)
-        K, Kt, nt = info["cheb_terms"], info["cheb_terms_tight"], res["kt_tight"]
-        steps = kernel_steps
-        launches = nt * (Kt - 1) + (steps - nt) * (K - 1)
-        total = launches * alg["full"] + steps * alg["first"]
-        avg = ms / launches
-        b = total / launches
-        cnt = launches
+        # the library times the chain's terms that stream the pair lists
+        # between one event pair and counts them (the plan choice, skipped
+        # terms and first term go to noise_setup)
+        avg = ms / cnt
+        b = alg["full"]
     else:
         avg = ms / cnt
         b = alg["bytes"]

@@ -29,8 +29,8 @@ GLD_PAIR_ISOTROPIC = 0
 GLD_PAIR_PARALLEL = 1
 
 (GLD_K_HISTORY, GLD_K_DISSIPATIVE, GLD_K_NOISE_FIR, GLD_K_NOISE_SPMV, GLD_K_UPDATE, GLD_K_NEIGHBOR,
- GLD_K_CHECK, GLD_K_COUNT) = range(8)
-KERNEL_NAMES = ["history", "dissipative", "noise_fir", "noise_spmv", "update", "neighbor", "check"]
+ GLD_K_CHECK, GLD_K_NOISE_SETUP, GLD_K_COUNT) = range(9)
+KERNEL_NAMES = ["history", "dissipative", "noise_fir", "noise_spmv", "update", "neighbor", "check", "noise_setup"]
 
 _dp = C.POINTER(C.c_double)
 

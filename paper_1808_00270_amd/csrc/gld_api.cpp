@@ -314,9 +314,10 @@ gld_status read_flags(gld_system *s)
 }
 
 // -- timing helpers ----------------------------------------------------------
-gld_status ev_begin(gld_system *s, size_t &idx)
+// force: record even while per-launch events are paused
+gld_status ev_begin(gld_system *s, size_t &idx, bool force = false)
 {
-    if (!s->timing) return GLD_OK;
+    if (!s->timing && !force) return GLD_OK;
     while (s->pool.size() < s->pool_used + 2) {
         hipEvent_t e;
         HIP_TRY(hipEventCreate(&e));
@@ -328,9 +329,9 @@ gld_status ev_begin(gld_system *s, size_t &idx)
     return GLD_OK;
 }
 
-gld_status ev_end(gld_system *s, int cls, size_t idx, int launches = 1)
+gld_status ev_end(gld_system *s, int cls, size_t idx, int launches = 1, bool force = false)
 {
-    if (!s->timing) return GLD_OK;
+    if (!s->timing && !force) return GLD_OK;
     HIP_TRY(hipEventRecord(s->pool[idx + 1], s->st));
     s->pending.emplace_back(cls, idx, launches);
     return GLD_OK;
@@ -379,6 +380,8 @@ gld_status enqueue_window(gld_system *s)
     int launches = 0;
     {
         const TimingPause pause(s);
+        // the plan of the window's positions (tight or wide), as for one step
+        if (d.cheb_kt > 0) LAUNCH(GLD_K_NOISE_SPMV, gld::launch_cheb_select(d, st));
         bool rev = true;  // the cell order alternates from launch to launch
         for (int m0 = 0; m0 < W; m0 += 2) {
             const int nv = std::min(2, W - m0);
@@ -391,12 +394,13 @@ gld_status enqueue_window(gld_system *s)
                 while (out == prev1 || out == prev2) ++out;
                 if (prev1 < 0) {
                     LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k),
-                                                                     pl.r, us, buf(out), nullptr, nv, false));
+                                                                     pl.r, us, buf(out), nullptr, nv, false, k));
                 } else {
                     rev = !rev;
-                    LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, buf(prev1),
-                                                                     prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(k), pl.r,
-                                                                     us, buf(out), nullptr, nv, rev));
+                    LAUNCH(GLD_K_NOISE_SPMV,
+                           gld::launch_spmv_window(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, buf(prev1),
+                                                   prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(k), pl.r, us, buf(out),
+                                                   nullptr, nv, rev, k));
                 }
                 ++launches;
                 prev2 = prev1;
@@ -405,14 +409,14 @@ gld_status enqueue_window(gld_system *s)
             if (prev1 >= 0) {
                 rev = !rev;
                 LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, pl.alpha, pl.beta, buf(prev1),
-                                                                 prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(0), pl.r, us,
-                                                                 nullptr, fr, nv, rev));
+                                                                 prev2 >= 0 ? -1.0 : 0.0, buf(prev2), coef(0), pl.r,
+                                                                 us, nullptr, fr, nv, rev, 0));
             } else {
-                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r,
-                                                                 us, nullptr, fr, nv, false));
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_window(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0),
+                                                                 pl.r, us, nullptr, fr, nv, false, 0));
             }
             ++launches;
-    }
+        }
     }
     if ((ts = ev_end(s, GLD_K_NOISE_SPMV, ix_chain, launches)) != GLD_OK) return ts;
     return GLD_OK;
@@ -451,20 +455,46 @@ gld_status enqueue_step(gld_system *s, int slot)
         };
         // Clenshaw: b_k = v_k + 2 P~ b_{k+1} - b_{k+2};  F = v_0 + P~ b_1 - b_2,
         // v_k = sum_q B[k][q] u_q, P~ = alpha P + beta 1
-        // the chain is timed as a whole: its launches follow each other with
-        // nothing in between, and an event pair per launch would add the
-        // event gaps to every one of them
-        size_t ix_chain = 0;
-        gld_status ts = ev_begin(s, ix_chain);
+        // Timing: the terms that stream the pair lists (k <= Ka - 2, Ka the K
+        // of the step's plan) run back to back between one event pair (an
+        // event pair per launch would add the event gaps to each of them);
+        // the plan choice, the skipped terms and the first term between
+        // another (noise_setup).  The host knows the step's plan only once
+        // the step before has run: timing mode synchronises here to read it.
+        const bool timing_on = s->timing;
+        int Ka = pl.K;
+        if (timing_on && d.cheb_kt > 0) {
+            HIP_TRY(hipStreamSynchronize(st));
+            unsigned bits = 0;
+            HIP_TRY(hipMemcpy(&bits, d.d_rowmax, sizeof(bits), hipMemcpyDeviceToHost));
+            float g = 0;
+            std::memcpy(&g, &bits, sizeof(g));
+            if (g <= d.lam_tight) Ka = pl.Kt;
+        }
+        size_t ix = 0;
+        gld_status ts = ev_begin(s, ix);
         if (ts != GLD_OK) return ts;
+        int setup = 0;
+        bool in_pairs = false;
+        auto to_pairs = [&](int k) -> gld_status {
+            // before term k: the first term that streams the lists opens the second event pair
+            if (!timing_on || in_pairs || k > Ka - 2) return GLD_OK;
+            in_pairs = true;
+            gld_status e = ev_end(s, GLD_K_NOISE_SETUP, ix, setup, true);
+            return e != GLD_OK ? e : ev_begin(s, ix, true);
+        };
         {
             const TimingPause pause(s);
-            if (d.cheb_kt > 0) LAUNCH(GLD_K_NOISE_SPMV, gld::launch_cheb_select(d, st));
+            if (d.cheb_kt > 0) {
+                LAUNCH(GLD_K_NOISE_SETUP, gld::launch_cheb_select(d, st));
+                ++setup;
+            }
             // term k of the chain passes its index: with a tight plan the
             // step's plan (k_cheb_select) sets its combination, and the terms
             // beyond the tight plan's K return at once
             void *prev1 = nullptr, *prev2 = nullptr;
             for (int k = pl.K - 1; k >= 1; --k) {
+                if ((ts = to_pairs(k)) != GLD_OK) return ts;
                 void *out = nullptr;
                 for (void *c : d.cb)
                     if (c != prev1 && c != prev2) { out = c; break; }
@@ -477,9 +507,11 @@ gld_status enqueue_step(gld_system *s, int slot)
                                                               prev2 ? -1.0 : 0.0, prev2, coef(k), pl.r, out, nullptr,
                                                               nullptr, rev, k));
                 }
+                if (!in_pairs) ++setup;
                 prev2 = prev1;
                 prev1 = out;
             }
+            if ((ts = to_pairs(0)) != GLD_OK) return ts;
             if (prev1) {
                 LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0, prev2,
                                                           coef(0), pl.r, nullptr, d.FR, nullptr, !rev, 0));
@@ -487,8 +519,11 @@ gld_status enqueue_step(gld_system *s, int slot)
                 LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r,
                                                           nullptr, d.FR, nullptr, false, 0));
             }
+            if (!in_pairs) ++setup;
         }
-        if ((ts = ev_end(s, GLD_K_NOISE_SPMV, ix_chain, pl.K)) != GLD_OK) return ts;
+        if ((ts = ev_end(s, in_pairs ? GLD_K_NOISE_SPMV : GLD_K_NOISE_SETUP, ix, in_pairs ? Ka - 1 : setup)) !=
+            GLD_OK)
+            return ts;
     }
     LAUNCH(GLD_K_UPDATE, gld::launch_update_r(d, st));
     LAUNCH(GLD_K_NEIGHBOR, gld::launch_neighbors(d, st, d.FCn));

@@ -188,7 +188,7 @@ hipError_t launch_permute_window(const Dev &d, hipStream_t st, int r);
 // once for every two vectors (isotropic tensor) or once per vector
 hipError_t launch_spmv_window(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
                               const void *z, const void *coef, int r, const void *us, void *out_sorted,
-                              void *out_orig, int nv, bool reverse);
+                              void *out_orig, int nv, bool reverse, int cheb_k = -1);
 // noise window: FR = FRw[step mod W]
 hipError_t launch_take_window(const Dev &d, hipStream_t st);
 // largest mat-vec staging capacity (candidates) that fits the LDS of one work-group

@@ -1432,6 +1432,17 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
     constexpr int PG = BS / L;
     extern __shared__ __align__(32) unsigned char mv_lds[];
     __shared__ int sst[kStab], sbase[kStab];
+    double ca = A.a, cb = A.b, ccz = A.cz;
+    const T *coefp = static_cast<const T *>(A.coef);
+    if (A.chain) {
+        // a term of the Chebyshev chains: its coefficients follow this step's plan
+        const ChainStep cs = A.chain[A.cheb_k];
+        if (cs.skip) return;
+        ca = cs.a;
+        cb = cs.b;
+        ccz = cs.cz;
+        coefp += static_cast<int64_t>(cs.row) * A.rcap;
+    }
     const int cid = A.rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
     const int h0 = A.cstart[cid], occ = A.cstart[cid + 1] - h0;
     if (occ <= 0) return;
@@ -1448,7 +1459,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
     const T4 *__restrict__ x = static_cast<const T4 *>(A.x);
     const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw) + static_cast<int64_t>(h0) * 2 * A.cap8;
     const uint4 *__restrict__ nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;
-    const bool pair = A.a != 0.0;
+    const bool pair = ca != 0.0;
     __syncthreads();
     const int total = sbase[nst];
     bool staged_all = false;
@@ -1540,7 +1551,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
         for (int v = 0; v < NV; ++v) e[v][0] = e[v][1] = e[v][2] = T(0);
         if (active) {
             const int nterm = 2 + A.r;
-            const T *coef = static_cast<const T *>(A.coef);
+            const T *coef = coefp;
             const T4 *us = static_cast<const T4 *>(A.us);
             const T4 *zv = static_cast<const T4 *>(A.z);
 #pragma unroll
@@ -1549,13 +1560,13 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                     T cf = T(0);
                     T4 q{};
                     if (tt == 0) {
-                        if (A.b != 0.0) {
-                            cf = static_cast<T>(A.b);
+                        if (cb != 0.0) {
+                            cf = static_cast<T>(cb);
                             q = x[static_cast<int64_t>(v) * A.S + s];
                         }
                     } else if (tt == 1) {
-                        if (A.cz != 0.0) {
-                            cf = static_cast<T>(A.cz);
+                        if (ccz != 0.0) {
+                            cf = static_cast<T>(ccz);
                             q = zv[static_cast<int64_t>(v) * A.S + s];
                         }
                     } else {
@@ -1570,7 +1581,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
         }
         __syncthreads();
         if (active) {
-            const T a = static_cast<T>(A.a);
+            const T a = static_cast<T>(ca);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 T4 q;
@@ -1908,12 +1919,18 @@ hipError_t launch_mvw_t(const Dev &d, MvArgs A, hipStream_t st)
 
 hipError_t launch_spmv_window(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
                               const void *z, const void *coef, int r, const void *us, void *out_sorted,
-                              void *out_orig, int nv, bool reverse)
+                              void *out_orig, int nv, bool reverse, int cheb_k)
 {
     const size_t elt = d.fp64 ? 8 : 4;
     const size_t v4 = 4 * elt * static_cast<size_t>(d.S);  // one sorted T4 vector
     if (!d.parallel && nv == 2) {
-        const MvArgs A = mv_args(d, a, b, x, cz, z, coef, r, us, out_sorted, out_orig, nullptr, reverse);
+        MvArgs A = mv_args(d, a, b, x, cz, z, coef, r, us, out_sorted, out_orig, nullptr, reverse);
+        if (cheb_k >= 0 && d.cheb_kt > 0) {
+            A.chain = static_cast<const ChainStep *>(d.chain);
+            A.cheb_k = cheb_k;
+            A.rcap = d.fir_rcap;
+            A.coef = d.Bmix;
+        }
         return d.fp64 ? launch_mvw_t<double, 2>(d, A, st) : launch_mvw_t<float, 2>(d, A, st);
     }
     // the parallel tensor (or a single vector): one mat-vec per vector
@@ -1925,7 +1942,8 @@ hipError_t launch_spmv_window(const Dev &d, hipStream_t st, double a, double b, 
         dv.us = const_cast<void *>(at(us, static_cast<size_t>(v) * r * v4));
         void *os = out_sorted ? static_cast<char *>(out_sorted) + v * v4 : nullptr;
         void *oo = out_orig ? static_cast<char *>(out_orig) + static_cast<size_t>(v) * 3 * d.S * elt : nullptr;
-        hipError_t e = launch_spmv(dv, st, a, b, at(x, v * v4), cz, at(z, v * v4), coef, r, os, oo, nullptr, reverse);
+        hipError_t e =
+            launch_spmv(dv, st, a, b, at(x, v * v4), cz, at(z, v * v4), coef, r, os, oo, nullptr, reverse, cheb_k);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -336,26 +336,33 @@ def test_parallel_tensor_at_high_density_is_not_pd(pkg, oracle_mod):
 
 
 def test_kernel_timing_counts(pkg):
-    """Per-kernel timing: an event pair per launch, except the Chebyshev chain,
-    timed as a whole and counted as its K launches."""
+    """Per-kernel timing: an event pair per launch, except the Chebyshev chain:
+    its terms that stream the pair lists (Ka - 1 of them, Ka the K of the
+    step's noise plan) count under noise_spmv, its plan choice, skipped terms
+    and first term under noise_setup."""
     w = wl.config(1)
     s = pkg.System.from_workload(w)
-    K = s.noise_info()["cheb_terms"]
+    info = s.noise_info()
+    K, Kt = info["cheb_terms"], info["cheb_terms_tight"]
     s.set_timing(True)
     s.step(3)
     kt = s.kernel_times()
     s.set_timing(False)
+    nt = s.noise_info()["tight_steps"] - info["tight_steps"]
     s.step(1)
     s.sync()
     s.close()
-    log(f"    K={K} {kt}")
+    log(f"    K={K} Kt={Kt} tight steps {nt} {kt}")
+    pair = nt * (Kt - 1) + (3 - nt) * (K - 1)
+    setup = 3 * (1 if Kt > 0 else 0) + nt * (K - Kt + 1) + (3 - nt)
     assert kt["history"][1] == 3
-    assert kt["noise_spmv"][1] == 3 * K
+    assert kt["noise_spmv"][1] == pair
+    assert kt["noise_setup"][1] == setup
     assert kt["noise_fir"][1] == 6      # white ring and filter bank
     assert kt["dissipative"][1] == 6    # permute and the pair contraction
     assert kt["update"][1] == 6
     assert kt["neighbor"][1] == 3
-    for k in ("history", "noise_spmv", "noise_fir", "dissipative", "update", "neighbor"):
+    for k in ("history", "noise_spmv", "noise_setup", "noise_fir", "dissipative", "update", "neighbor"):
         assert kt[k][0] > 0, k
 
 
@@ -446,10 +453,12 @@ def row_sum_bound(w, R):
     return rows.max()
 
 
-@pytest.mark.parametrize("fp64", [False, True])
-def test_tight_and_wide_noise_plans_match_oracle(pkg, oracle_mod, fp64):
+@pytest.mark.parametrize("fp64,W", [(False, 1), (True, 1), (False, 2)])
+def test_tight_and_wide_noise_plans_match_oracle(pkg, oracle_mod, fp64, W):
+    # W = 2: the window's chains follow the plan of the window's positions;
+    # the write at step 9 lands inside a window
     w = wl.config(2, n=5000, rho=0.05, m_max=60)
-    s = pkg.System.from_workload(w, fp64=fp64, **({"noise_tol": 1e-13} if fp64 else {}))
+    s = pkg.System.from_workload(w, fp64=fp64, noise_window=W, **({"noise_tol": 1e-13} if fp64 else {}))
     info = s.noise_info()
     log(f"    K {info['cheb_terms']} on [{info['lam_lo']:.3f}, {info['lam_hi']:.3f}], tight K "
         f"{info['cheb_terms_tight']} up to {info['lam_hi_tight']:.3f}")
