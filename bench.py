@@ -38,7 +38,9 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
     sT = 8 if fp64 else 4
     vec = 3 * n
     if kind == "history":
-        # ring read, velocity read, two outputs written
+        # what the convolution of the definition streams per step: the ring,
+        # the velocity, two outputs (the blocked form reads the ring once per
+        # block instead)
         return dict(bytes=(m_max - 1) * vec * sT + vec * 8 + 2 * vec * sT)
     if kind == "dissipative":
         # 16-bit staged index + weight per ordered pair, the input vector
@@ -147,6 +149,15 @@ def roofline_entry(res, kind, fp64, kernel_steps):
     ms, cnt = res["kt"][kind]
     if cnt == 0:
         return None
+    if kind == "history":
+        # blocked: the matrix-core product over the lags before the block at
+        # block starts, the block's own lags every step; per step against the
+        # bytes the per-step streaming convolution would read
+        per = ms / kernel_steps
+        b = algorithmic(info, w.n, w.m_max, res["pairs"], fp64, kind)["bytes"]
+        return dict(kernel=kind, method="blocked: matrix-core product every block of steps + the block's own lags",
+                    block_steps=16 if fp64 else 32, ms_per_step=per, definition_bytes_per_step=b,
+                    equivalent_GBps=b / (per * 1e-3) / 1e9, hbm_peak_GBps=HBM_PEAK_GBS)
     alg = algorithmic(info, w.n, w.m_max, res["pairs"], fp64, kind)
     if kind == "noise_fir":
         # only one launch in `block` does work; charge the active ones

@@ -194,6 +194,11 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.Afilt, static_cast<size_t>(gld::kMaxRank) * gld::fir_padded_rows(p->m_max - 1, gld::kMaxFirBlock) * elt);
     L.take(d.Bmix, static_cast<size_t>(gld::kMaxCheb) * gld::kMaxRank * elt);
     L.take(d.ks, static_cast<size_t>(p->m_max) * elt);
+    if (nslots > 0) {
+        const int hb = g.fp64 ? gld::kHistBlock64 : gld::kHistBlock32;
+        L.take(d.hist_taps, gld::hist_tap_rows(nslots, hb) * 2 * elt);
+        L.take(d.Uh, static_cast<size_t>(hb) * 2 * vec * elt);
+    }
     L.take(d.gm, static_cast<size_t>(p->m_max) * elt);
     L.take(d.wtab, static_cast<size_t>(p->n_r) * 8);
     L.take(d.nbl, static_cast<size_t>(g.cap) * n * 2);
@@ -431,6 +436,7 @@ gld_status enqueue_step(gld_system *s, int slot)
     const Dev &d = s->d;
     hipStream_t st = s->st;
     const NoisePlan &pl = s->plan;
+    LAUNCH(GLD_K_HISTORY, gld::launch_history_block(d, 0, st));
     LAUNCH(GLD_K_HISTORY, gld::launch_history(d, st));
     if (s->noise_on) {
         LAUNCH(GLD_K_NOISE_FIR, gld::launch_white_ring(d, 0, st));
@@ -856,6 +862,19 @@ gld_status gld_create(const gld_params *params, const double *r0, const double *
         return bail(fail(GLD_ERR_DEVICE, "upload failed"));
     if ((st = upload_work_table(s, d.ks, p.k_self, p.m_max)) != GLD_OK) return bail(st);
     if ((st = upload_work_table(s, d.gm, d.has_pair ? p.k_pair_g : zero_g.data(), p.m_max)) != GLD_OK) return bail(st);
+    d.hist_block = s->geo.fp64 ? gld::kHistBlock64 : gld::kHistBlock32;
+    if (d.nslots > 0) {
+        // taps of the blocked history convolution: row t + hb - 1 holds
+        // (K^s_m, g_m) for the lag m = M - 1 - t
+        const int hb = d.hist_block;
+        std::vector<double> A(gld::hist_tap_rows(d.nslots, hb) * 2, 0.0);
+        for (int t = 0; t < d.nslots; ++t) {
+            const int m = d.nslots - t;
+            A[static_cast<size_t>(t + hb - 1) * 2] = p.k_self[m];
+            A[static_cast<size_t>(t + hb - 1) * 2 + 1] = d.has_pair ? p.k_pair_g[m] : 0.0;
+        }
+        if ((st = upload_work_table(s, d.hist_taps, A.data(), A.size())) != GLD_OK) return bail(st);
+    }
     if ((st = upload_vec<double>(s, d.R, r0)) != GLD_OK) return bail(st);
     if ((st = upload_vec<double>(s, d.V, v0)) != GLD_OK) return bail(st);
     if ((st = set_step(s, 0)) != GLD_OK) return bail(st);
@@ -973,6 +992,8 @@ gld_status gld_write_state(gld_system *s, const gld_state *in)
     if ((st = clear_flags(s)) != GLD_OK) return st;
     if ((st = refresh_forces(s)) != GLD_OK) return st;
     if ((st = prime_noise(s)) != GLD_OK) return st;
+    // the history sums over the lags before the block holding this step
+    HIP_TRY(gld::launch_history_block(s->d, 1, s->st));
     return read_flags(s);
 }
 

@@ -84,6 +84,7 @@ struct Dev {
     int ncell = 1;
     int fir_block = 1, fir_rcap = 8;
     int fir_half = 0;       // filter window half-width (lags |t| <= fir_half)
+    int hist_block = 1;     // steps per block of the history convolution
     int wring_len = 1;      // slots of the white-noise ring
     double g0 = 0;
     double lam_hi = __builtin_huge_val();  // noise interval top, checked every step
@@ -105,6 +106,8 @@ struct Dev {
     void *Afilt = nullptr;  // [2 fir_half + 1][fir_rcap], tap-major
     void *Bmix = nullptr;   // [kMaxCheb][fir_rcap]
     void *ks = nullptr, *gm = nullptr;  // [M]
+    void *hist_taps = nullptr;          // [hist_tap_rows][2]: (K^s_m, g_m), m = M-1 .. 1, zero-padded
+    void *Uh = nullptr;                 // [hist_block][2][3][S]: the block's sums over the lags before it
     double *wtab = nullptr;             // [n_r]
     void *nbl = nullptr;                // uint16 chunks of 8 staged-stencil indices, cell-blocked: cell at h0 with occ
                                         // particles holds [cap/8][occ][8] from chunk h0 cap/8
@@ -149,7 +152,13 @@ constexpr int kPartials = 1024;
 // Launchers (gld_kernels.hip).  All enqueue on `st` and return hipError_t.
 hipError_t launch_zero_int(int *p, int64_t n, hipStream_t st);
 hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out);
+// history convolution of the step: the block's product (launch_history_block)
+// plus the step's own lags
 hipError_t launch_history(const Dev &d, hipStream_t st);
+// the lags that reach before the block, for all hist_block steps of the block
+// holding the current step: runs at block starts, or (force) at any step
+hipError_t launch_history_block(const Dev &d, int force, hipStream_t st);
+
 hipError_t launch_dissipative(const Dev &d, hipStream_t st, bool reverse);
 // filter bank; force = 1 produces the block holding the current step even mid-block
 hipError_t launch_fir(const Dev &d, int force, hipStream_t st);
@@ -165,6 +174,11 @@ constexpr int kMaxFirBlock = 16;
 // taps are stored zero-padded, [bf - 1 + (2 half + 1) + kFirChunk + bf - 1][rcap]
 constexpr int kFirChunk = 128;
 inline size_t fir_padded_rows(int half, int bf) { return static_cast<size_t>(2 * half + 1 + kFirChunk + 2 * (bf - 1)); }
+// steps per block of the history convolution: two filters (K^s, g) fill the
+// 64 (FP32) or 32 (FP64) accumulator rows of the matrix-core product
+constexpr int kHistBlock32 = 32, kHistBlock64 = 16;
+// rows of its zero-padded taps (the filter bank's layout, nslots taps)
+inline size_t hist_tap_rows(int nslots, int hb) { return static_cast<size_t>(hb - 1 + nslots + kFirChunk + hb - 1); }
 // out = a P x + b x + cz z + sum_q coef[q] us_q  (x, z, us: sorted T4; x, z may be null
 // when a = b = 0 / cz = 0).  Written to out_sorted (T4) or, if that is null,
 // scattered to out_orig ([3][S], original order) plus add_orig when given.

@@ -121,11 +121,17 @@ __global__ void k_zero_work(T *p, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
-// H3: memory convolution over the displacement ring (HBM stream)
+// H3: memory convolution over the displacement ring
 //   Dneg = -(1/dt) sum_{m=1}^{M-1} K^s_m dR_{n-m}
 //   Y    = g_0 V + (1/dt) sum_{m=1}^{M-1} g_m dR_{n-m}
-// One thread owns 4 consecutive elements of the [3][S] vector and one of CH
-// contiguous lag chunks; chunks are summed through LDS.
+// in blocks of HB steps.  For step n = n0 + j of the block starting at n0,
+// the lags m > j reach only displacements from before n0, which the ring
+// already holds when the block starts; for all j at once these sums are one
+// product (the filter bank's kernel on the matrix cores, ROLE 1):
+//   Uh[j][0] = sum_{m=j+1}^{M-1} K^s_m dR_{n0+j-m},  Uh[j][1] likewise with g_m,
+// which reads the ring once per block instead of once per step.  Each step
+// then adds its lags m <= j (the block's own displacements) directly.  The
+// sums are those of the definition, taken in another order.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Vec4;
@@ -139,115 +145,69 @@ struct Vec4<double> {
 };
 
 template <typename T>
-__device__ __forceinline__ typename Vec4<T>::type load4(const T *p);
-// (the displacement ring is read once per step: FP32 loads are non-temporal,
-// which measured 462 -> 395 us at cfg3; for FP64 the hint measured slightly
-// slower and is left out)
-typedef float ring_f4 __attribute__((ext_vector_type(4)));
-template <>
-__device__ __forceinline__ float4 load4<float>(const float *p)
+__device__ __forceinline__ typename Vec4<T>::type load4(const T *p)
 {
-    const ring_f4 v = __builtin_nontemporal_load(reinterpret_cast<const ring_f4 *>(p));
-    return make_float4(v.x, v.y, v.z, v.w);
-}
-template <>
-__device__ __forceinline__ double4 load4<double>(const double *p)
-{
-    const double2 a = reinterpret_cast<const double2 *>(p)[0];
-    const double2 b = reinterpret_cast<const double2 *>(p)[1];
-    return make_double4(a.x, a.y, b.x, b.y);
+    return *reinterpret_cast<const typename Vec4<T>::type *>(p);
 }
 
-constexpr int kConvCols = 64;  // columns (4 elements each) per work-group
-constexpr int kConvCh = 4;     // lag chunks per work-group (block = 256)
+// the step's part: 4 consecutive elements of the [3][S] vectors per thread
+template <typename T>
+__global__ __launch_bounds__(256) void k_history_step(const T *__restrict__ ring, const T *__restrict__ Uh,
+                                                      int64_t n3, int nslots, int hb, const T *__restrict__ ks,
+                                                      const T *__restrict__ gm,
+                                                      const long long *__restrict__ d_step,
+                                                      const double *__restrict__ V, T g0, T inv_dt,
+                                                      T *__restrict__ Dneg, T *__restrict__ Y)
+{
+    const int64_t e0 = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
+    if (e0 >= n3) return;
+    const long long step = *d_step;
+    const int j = static_cast<int>(step % hb);
+    T d[4] = {T(0), T(0), T(0), T(0)}, h[4] = {T(0), T(0), T(0), T(0)};
+    if (nslots > 0) {  // no history (m_max = 1): no block sums either
+        const auto ud = load4<T>(Uh + (2 * static_cast<int64_t>(j)) * n3 + e0);
+        const auto uh = load4<T>(Uh + (2 * static_cast<int64_t>(j) + 1) * n3 + e0);
+        d[0] = ud.x;
+        d[1] = ud.y;
+        d[2] = ud.z;
+        d[3] = ud.w;
+        h[0] = uh.x;
+        h[1] = uh.y;
+        h[2] = uh.z;
+        h[3] = uh.w;
+    }
+    const int mm = min(j, nslots);
+    for (int m = 1; m <= mm; ++m) {
+        long long t = (step - m) % nslots;
+        if (t < 0) t += nslots;
+        const auto x = load4<T>(ring + t * n3 + e0);
+        const T k = ks[m], q = gm[m];
+        d[0] += k * x.x;
+        d[1] += k * x.y;
+        d[2] += k * x.z;
+        d[3] += k * x.w;
+        h[0] += q * x.x;
+        h[1] += q * x.y;
+        h[2] += q * x.z;
+        h[3] += q * x.w;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t e = e0 + u;
+        Dneg[e] = -d[u] * inv_dt;
+        Y[e] = g0 * static_cast<T>(V[e]) + h[u] * inv_dt;
+    }
+}
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_history(const T *__restrict__ ring, int64_t S, int64_t n3, int nslots,
-                                                 const T *__restrict__ ks, const T *__restrict__ gm,
-                                                 const long long *__restrict__ d_step, const double *__restrict__ V,
-                                                 T g0, T inv_dt, T *__restrict__ Dneg, T *__restrict__ Y)
+static hipError_t history_t(const Dev &d, hipStream_t st)
 {
-    extern __shared__ unsigned char smem_raw[];
-    T *sk = reinterpret_cast<T *>(smem_raw);  // [nslots + 1]
-    T *sg = sk + (nslots + 1);                // [nslots + 1]
-    T *red = sg + (nslots + 1);               // [kConvCh][kConvCols][8]
-    for (int m = threadIdx.x; m <= nslots; m += blockDim.x) {
-        sk[m] = ks[m];
-        sg[m] = gm[m];
-    }
-    __syncthreads();
-    const int lane = threadIdx.x % kConvCols;
-    const int ch = threadIdx.x / kConvCols;
-    const int64_t e0 = (static_cast<int64_t>(blockIdx.x) * kConvCols + lane) * 4;
-    const bool live = e0 < S;
-    T d0 = 0, d1 = 0, d2 = 0, d3 = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0;
-    if (live && nslots > 0) {
-        const long long step = *d_step;
-        const int head = static_cast<int>(step % nslots);
-        const int per = (nslots + kConvCh - 1) / kConvCh;
-        const int m0 = 1 + ch * per;
-        const int m1 = min(nslots + 1, m0 + per);
-        int slot = head - m0;
-        if (slot < 0) slot += nslots;
-        int m = m0;
-        // four lags per iteration: four independent 16/32-byte loads in flight
-        for (; m + 3 < m1; m += 4) {
-            int s1 = slot - 1, s2 = slot - 2, s3 = slot - 3;
-            if (s1 < 0) s1 += nslots;
-            if (s2 < 0) s2 += nslots;
-            if (s3 < 0) s3 += nslots;
-            const auto x0 = load4<T>(ring + static_cast<int64_t>(slot) * S + e0);
-            const auto x1 = load4<T>(ring + static_cast<int64_t>(s1) * S + e0);
-            const auto x2 = load4<T>(ring + static_cast<int64_t>(s2) * S + e0);
-            const auto x3 = load4<T>(ring + static_cast<int64_t>(s3) * S + e0);
-            const T k0 = sk[m], k1 = sk[m + 1], k2 = sk[m + 2], k3 = sk[m + 3];
-            const T q0 = sg[m], q1 = sg[m + 1], q2 = sg[m + 2], q3 = sg[m + 3];
-            d0 += k0 * x0.x + k1 * x1.x + k2 * x2.x + k3 * x3.x;
-            d1 += k0 * x0.y + k1 * x1.y + k2 * x2.y + k3 * x3.y;
-            d2 += k0 * x0.z + k1 * x1.z + k2 * x2.z + k3 * x3.z;
-            d3 += k0 * x0.w + k1 * x1.w + k2 * x2.w + k3 * x3.w;
-            h0 += q0 * x0.x + q1 * x1.x + q2 * x2.x + q3 * x3.x;
-            h1 += q0 * x0.y + q1 * x1.y + q2 * x2.y + q3 * x3.y;
-            h2 += q0 * x0.z + q1 * x1.z + q2 * x2.z + q3 * x3.z;
-            h3 += q0 * x0.w + q1 * x1.w + q2 * x2.w + q3 * x3.w;
-            slot = s3 - 1;
-            if (slot < 0) slot += nslots;
-        }
-        for (; m < m1; ++m) {
-            const auto x = load4<T>(ring + static_cast<int64_t>(slot) * S + e0);
-            const T k = sk[m], q = sg[m];
-            d0 += k * x.x;
-            d1 += k * x.y;
-            d2 += k * x.z;
-            d3 += k * x.w;
-            h0 += q * x.x;
-            h1 += q * x.y;
-            h2 += q * x.z;
-            h3 += q * x.w;
-            if (--slot < 0) slot += nslots;
-        }
-    }
-    T *my = red + (static_cast<int64_t>(ch) * kConvCols + lane) * 8;
-    my[0] = d0; my[1] = d1; my[2] = d2; my[3] = d3;
-    my[4] = h0; my[5] = h1; my[6] = h2; my[7] = h3;
-    __syncthreads();
-    if (ch != 0 || !live) return;
-    T acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0;
-    for (int c = 0; c < kConvCh; ++c) {
-        const T *o = red + (static_cast<int64_t>(c) * kConvCols + lane) * 8;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] += o[q];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t e = e0 + q;
-        if (e < n3) {
-            Dneg[e] = -acc[q] * inv_dt;
-            Y[e] = g0 * static_cast<T>(V[e]) + acc[4 + q] * inv_dt;
-        }
-    }
+    const int64_t len = 3 * d.S;  // one slot; a multiple of 4 since S is a multiple of 64
+    k_history_step<T><<<static_cast<unsigned>((len / 4 + 255) / 256), 256, 0, st>>>(
+        static_cast<const T *>(d.ring), static_cast<const T *>(d.Uh), len, d.nslots, d.hist_block,
+        static_cast<const T *>(d.ks), static_cast<const T *>(d.gm), d.d_step, d.V, static_cast<T>(d.g0),
+        static_cast<T>(1.0 / d.dt), static_cast<T *>(d.Dneg), static_cast<T *>(d.Y));
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -316,8 +276,9 @@ constexpr int kFirMfmaThreads = 256;  // four waves, 256 channels
 constexpr int kFirUnroll = 8;         // MFMA k-pairs per batch
 constexpr int kFirStageIt = ((kFirChunk + kMaxFirBlock - 1) * kMaxRank / 2 + kFirMfmaThreads - 1) / kFirMfmaThreads;
 
-__global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t S, int bf, int rc, int half, int len,
-                                                              const float *__restrict__ A,
+template <int ROLE>
+__global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t S, int bf, int rc, int offset,
+                                                              int span, int len, const float *__restrict__ A,
                                                               const float *__restrict__ W,
                                                               const long long *__restrict__ d_step,
                                                               float *__restrict__ U, int force)
@@ -326,7 +287,6 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t
     const long long cur = *d_step;
     if (!force && cur % bf != 0) return;
     const long long n0 = cur - cur % bf;
-    const int span = 2 * half + bf;  // window steps: 2 half + 1 taps, bf outputs
     const int64_t M = 3 * S;
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t m0 = (static_cast<int64_t>(blockIdx.x) * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
@@ -353,15 +313,18 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t
         for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = fir_v16f{};
     // ring slot of this lane's window step k = 2 j + hi, and its channel c0
     // there (c1 = c0 + 32 follows at a fixed offset)
-    int sl = ring_slot(n0 - half + hi, len);
+    int sl = ring_slot(n0 - offset + hi, len);
     const float *src = W + static_cast<int64_t>(sl) * M + c0;
     const int64_t wrap = static_cast<int64_t>(len) * M;
+    int kw = hi;  // window step of the next load (steps past the span read as 0)
     float xa[kFirUnroll][2], xn[kFirUnroll][2], xm[kFirUnroll][2];
     auto load_batch = [&](float (&dst)[kFirUnroll][2]) {
 #pragma unroll
         for (int u = 0; u < kFirUnroll; ++u) {
-            dst[u][0] = __builtin_nontemporal_load(src);
-            dst[u][1] = __builtin_nontemporal_load(src + 32);
+            const bool in = kw < span;
+            dst[u][0] = in ? __builtin_nontemporal_load(src) : 0.f;
+            dst[u][1] = in ? __builtin_nontemporal_load(src + 32) : 0.f;
+            kw += 2;
             sl += 2;
             src += 2 * M;
             if (sl >= len) {
@@ -445,8 +408,9 @@ constexpr int kFirUnroll64 = 4;  // MFMA k-quads per batch
 constexpr int kFirStageIt64 =
     ((kFirChunk64 + kMaxFirBlock - 1) * kMaxRank / 2 + kFirMfmaThreads - 1) / kFirMfmaThreads;
 
-__global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma64(int64_t n, int64_t S, int bf, int rc, int half,
-                                                                int len, const double *__restrict__ A,
+template <int ROLE>
+__global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma64(int64_t n, int64_t S, int bf, int rc, int offset,
+                                                                int span, int len, const double *__restrict__ A,
                                                                 const double *__restrict__ W,
                                                                 const long long *__restrict__ d_step,
                                                                 double *__restrict__ U, int force)
@@ -455,7 +419,6 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma64(int64_t n, int64
     const long long cur = *d_step;
     if (!force && cur % bf != 0) return;
     const long long n0 = cur - cur % bf;
-    const int span = 2 * half + bf;
     const int64_t M = 3 * S;
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t m0 = (static_cast<int64_t>(blockIdx.x) * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
@@ -477,15 +440,18 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma64(int64_t n, int64
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = fir_v4d{};
     // ring slot of this lane's window step k = 4 j + g
-    int sl = ring_slot(n0 - half + g, len);
+    int sl = ring_slot(n0 - offset + g, len);
     const double *src = W + static_cast<int64_t>(sl) * M + c0;
     const int64_t wrap = static_cast<int64_t>(len) * M;
+    int kw = g;  // window step of the next load (steps past the span read as 0)
     double xa[kFirUnroll64][4], xn[kFirUnroll64][4];
     auto load_batch = [&](double (&dst)[kFirUnroll64][4]) {
 #pragma unroll
         for (int u = 0; u < kFirUnroll64; ++u) {
+            const bool in = kw < span;
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) dst[u][ct] = __builtin_nontemporal_load(src + 16 * ct);
+            for (int ct = 0; ct < 4; ++ct) dst[u][ct] = in ? __builtin_nontemporal_load(src + 16 * ct) : 0.0;
+            kw += 4;
             sl += 4;
             src += 4 * M;
             if (sl >= len) {
@@ -763,23 +729,6 @@ hipError_t launch_fill_zero_work(const Dev &d, void *p, int64_t count, hipStream
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t history_t(const Dev &d, hipStream_t st)
-{
-    const int64_t len = 3 * d.S;  // one slot; a multiple of 4 since S is a multiple of 64
-    const unsigned nb = blocks(len / 4, kConvCols);
-    const size_t shm = sizeof(T) * (2 * (d.nslots + 1) + kConvCh * kConvCols * 8);
-    if (shm > 65536) {  // long memories in FP64: allow up to the 160 KiB of LDS of a CDNA4 CU
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_history<T>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
-        if (e != hipSuccess) return e;
-    }
-    k_history<T><<<nb, kConvCols * kConvCh, shm, st>>>(
-        static_cast<const T *>(d.ring), len, len, d.nslots, static_cast<const T *>(d.ks),
-        static_cast<const T *>(d.gm), d.d_step, d.V, static_cast<T>(d.g0), static_cast<T>(1.0 / d.dt),
-        static_cast<T *>(d.Dneg), static_cast<T *>(d.Y));
-    return hipGetLastError();
-}
 
 hipError_t launch_history(const Dev &d, hipStream_t st)
 {
@@ -829,16 +778,18 @@ hipError_t launch_fir(const Dev &d, int force, hipStream_t st)
     // rows of one pair of MFMA tiles
     const int64_t M = 3 * d.S;
     const unsigned grid = static_cast<unsigned>((M + kFirMfmaThreads - 1) / kFirMfmaThreads);
+    // window: t = n0 - half .. n0 + bf - 1 + half (2 half + 1 taps, bf outputs)
+    const int span = 2 * d.fir_half + d.fir_block;
     if (d.fp64)
-        k_fir_mfma64<<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, d.wring_len,
-                                                       static_cast<const double *>(d.Afilt),
-                                                       static_cast<const double *>(d.wring), d.d_step,
-                                                       static_cast<double *>(d.U), force);
+        k_fir_mfma64<0><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, span,
+                                                          d.wring_len, static_cast<const double *>(d.Afilt),
+                                                          static_cast<const double *>(d.wring), d.d_step,
+                                                          static_cast<double *>(d.U), force);
     else
-        k_fir_mfma<<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, d.wring_len,
-                                                     static_cast<const float *>(d.Afilt),
-                                                     static_cast<const float *>(d.wring), d.d_step,
-                                                     static_cast<float *>(d.U), force);
+        k_fir_mfma<0><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, span,
+                                                        d.wring_len, static_cast<const float *>(d.Afilt),
+                                                        static_cast<const float *>(d.wring), d.d_step,
+                                                        static_cast<float *>(d.U), force);
     return hipGetLastError();
 }
 
@@ -863,6 +814,26 @@ hipError_t launch_take_window(const Dev &d, hipStream_t st)
     else
         k_take_window<float><<<blocks(len, 256), 256, 0, st>>>(len, static_cast<const float *>(d.FRw),
                                                                static_cast<float *>(d.FR), d.win, d.d_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_history_block(const Dev &d, int force, hipStream_t st)
+{
+    if (d.nslots == 0) return hipSuccess;
+    // the M - 1 ring slices before the block (t = n0 - (M - 1) .. n0 - 1)
+    // against the taps (K^s_m, g_m), m = M - 1 .. 1; HB steps of output
+    const int64_t M = 3 * d.S;
+    const unsigned grid = static_cast<unsigned>((M + kFirMfmaThreads - 1) / kFirMfmaThreads);
+    if (d.fp64)
+        k_fir_mfma64<1><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.hist_block, 2, d.nslots, d.nslots, d.nslots,
+                                                          static_cast<const double *>(d.hist_taps),
+                                                          static_cast<const double *>(d.ring), d.d_step,
+                                                          static_cast<double *>(d.Uh), force);
+    else
+        k_fir_mfma<1><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.hist_block, 2, d.nslots, d.nslots, d.nslots,
+                                                        static_cast<const float *>(d.hist_taps),
+                                                        static_cast<const float *>(d.ring), d.d_step,
+                                                        static_cast<float *>(d.Uh), force);
     return hipGetLastError();
 }
 

@@ -40,8 +40,9 @@ SOURCES = ["gld_kernels.hip", "gld_pairs.hip", "gld_internal.h"]
 # the work type T of the precision (F: suffix of the FP64 filter-bank kernel)
 CLASSES = {
     "noise_spmv": r"k_mv<{T}",
-    "history": r"k_history<{T}",
-    "noise_fir": r"k_fir_mfma{F}\(",
+    "history_step": r"k_history_step<{T}",
+    "history_block": r"k_fir_mfma{F}<1>",
+    "noise_fir": r"k_fir_mfma{F}<0>",
     "noise_white": r"k_white_ring<{T}",
     "neighbor_refresh": r"k_refresh<{T}",
     "neighbor_build": r"k_build<{T}",

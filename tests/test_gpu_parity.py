@@ -355,7 +355,7 @@ def test_kernel_timing_counts(pkg):
     log(f"    K={K} Kt={Kt} tight steps {nt} {kt}")
     pair = nt * (Kt - 1) + (3 - nt) * (K - 1)
     setup = 3 * (1 if Kt > 0 else 0) + nt * (K - Kt + 1) + (3 - nt)
-    assert kt["history"][1] == 3
+    assert kt["history"][1] == 6        # the block's product (at block starts) and the step's lags
     assert kt["noise_spmv"][1] == pair
     assert kt["noise_setup"][1] == setup
     assert kt["noise_fir"][1] == 6      # white ring and filter bank
