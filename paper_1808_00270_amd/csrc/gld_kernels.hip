@@ -316,15 +316,24 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t
     int sl = ring_slot(n0 - offset + hi, len);
     const float *src = W + static_cast<int64_t>(sl) * M + c0;
     const int64_t wrap = static_cast<int64_t>(len) * M;
-    int kw = hi;  // window step of the next load (steps past the span read as 0)
+    // window step of the next load.  The history's taps reach past the span
+    // (ROLE 1): its steps there count zero (the loads read other, finite
+    // ring slices and are multiplied by 0, which keeps them unconditional);
+    // the noise filters' taps are zero there already (ROLE 0)
+    [[maybe_unused]] int kw = hi;
     float xa[kFirUnroll][2], xn[kFirUnroll][2], xm[kFirUnroll][2];
     auto load_batch = [&](float (&dst)[kFirUnroll][2]) {
 #pragma unroll
         for (int u = 0; u < kFirUnroll; ++u) {
-            const bool in = kw < span;
-            dst[u][0] = in ? __builtin_nontemporal_load(src) : 0.f;
-            dst[u][1] = in ? __builtin_nontemporal_load(src + 32) : 0.f;
-            kw += 2;
+            if constexpr (ROLE == 1) {
+                const float in = kw < span ? 1.f : 0.f;
+                dst[u][0] = __builtin_nontemporal_load(src) * in;
+                dst[u][1] = __builtin_nontemporal_load(src + 32) * in;
+                kw += 2;
+            } else {
+                dst[u][0] = __builtin_nontemporal_load(src);
+                dst[u][1] = __builtin_nontemporal_load(src + 32);
+            }
             sl += 2;
             src += 2 * M;
             if (sl >= len) {
@@ -443,15 +452,22 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma64(int64_t n, int64
     int sl = ring_slot(n0 - offset + g, len);
     const double *src = W + static_cast<int64_t>(sl) * M + c0;
     const int64_t wrap = static_cast<int64_t>(len) * M;
-    int kw = g;  // window step of the next load (steps past the span read as 0)
+    // window step of the next load (ROLE 1, the history: past the span
+    // multiplied by 0, as in the FP32 kernel)
+    [[maybe_unused]] int kw = g;
     double xa[kFirUnroll64][4], xn[kFirUnroll64][4];
     auto load_batch = [&](double (&dst)[kFirUnroll64][4]) {
 #pragma unroll
         for (int u = 0; u < kFirUnroll64; ++u) {
-            const bool in = kw < span;
+            if constexpr (ROLE == 1) {
+                const double in = kw < span ? 1.0 : 0.0;
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) dst[u][ct] = in ? __builtin_nontemporal_load(src + 16 * ct) : 0.0;
-            kw += 4;
+                for (int ct = 0; ct < 4; ++ct) dst[u][ct] = __builtin_nontemporal_load(src + 16 * ct) * in;
+                kw += 4;
+            } else {
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) dst[u][ct] = __builtin_nontemporal_load(src + 16 * ct);
+            }
             sl += 4;
             src += 4 * M;
             if (sl >= len) {
