@@ -687,7 +687,9 @@ gld_status setup_noise(gld_system *s)
         return fail(GLD_ERR_INVALID_ARG, "noise_window " + std::to_string(d.win) + " exceeds the filter block " +
                                              std::to_string(d.fir_block) + " that this noise plan allows");
     d.fir_block -= d.fir_block % d.win;
-    d.wring_len = 2 * pl.half + d.fir_block;
+    // the filter bank steps through the ring 2 (FP32) or 4 (FP64) slices at a
+    // time and wraps once per step: at least 4 slots (the carve holds 16 more)
+    d.wring_len = std::max(4, 2 * pl.half + d.fir_block);
     // filter taps of the window, tap-major [2 half + 1][rcap] (columns beyond
     // r zero) with block - 1 zero rows before and kFirChunk + block - 1 after
     // (the matrix-core filter bank copies whole chunks of rows); and mixing

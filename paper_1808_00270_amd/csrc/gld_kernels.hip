@@ -336,7 +336,12 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t
             }
             sl += 2;
             src += 2 * M;
-            if (sl >= len) {
+            if constexpr (ROLE == 1) {
+                while (sl >= len) {  // the history ring (m_max - 1 slices) can be shorter than 2
+                    sl -= len;
+                    src -= wrap;
+                }
+            } else if (sl >= len) {  // the white-noise ring holds at least 4 slices
                 sl -= len;
                 src -= wrap;
             }
@@ -470,7 +475,12 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma64(int64_t n, int64
             }
             sl += 4;
             src += 4 * M;
-            if (sl >= len) {
+            if constexpr (ROLE == 1) {
+                while (sl >= len) {  // the history ring (m_max - 1 slices) can be shorter than 4
+                    sl -= len;
+                    src -= wrap;
+                }
+            } else if (sl >= len) {  // the white-noise ring holds at least 4 slices
                 sl -= len;
                 src -= wrap;
             }
