@@ -154,6 +154,9 @@ typedef struct {
                                  spectrum of P) is at most lam_hi_tight uses it; the
                                  noise interval chosen at create only               */
     double lam_hi_tight;
+    double lam_lo_tight;    /* lower end of the tight plan (closer to the spectrum
+                               than lam_lo); a spectrum check whose smallest Ritz
+                               value falls below it retires the tight plan       */
     int64_t tight_steps;    /* steps since create whose chain used the tight plan
                                (synchronises with the system's stream)               */
 } gld_noise_info;
@@ -185,7 +188,10 @@ gld_status gld_sync(gld_system *sys);
 gld_status gld_read_state(gld_system *sys, gld_state *out);
 
 /* Install a state (r, v, step, optional history); recomputes the neighbour
- * list and F^C, clears latched errors.  Synchronises. */
+ * list and F^C, clears latched errors and, with pair memory and noise, checks
+ * the spectrum of the pair-weight matrix against the noise interval as
+ * gld_create does (GLD_ERR_INTERVAL or GLD_ERR_NOT_PD if it fails).
+ * Synchronises. */
 gld_status gld_write_state(gld_system *sys, const gld_state *in);
 
 /* Noise-construction parameters of a system. */

@@ -93,6 +93,7 @@ class gld_noise_info(C.Structure):
         ("noise_window", C.c_int32),
         ("cheb_terms_tight", C.c_int32),
         ("lam_hi_tight", C.c_double),
+        ("lam_lo_tight", C.c_double),
         ("tight_steps", C.c_int64),
     ]
 

@@ -472,10 +472,12 @@ gld_status enqueue_step(gld_system *s, int slot)
         if (timing_on && d.cheb_kt > 0) {
             HIP_TRY(hipStreamSynchronize(st));
             unsigned bits = 0;
+            double theta_min = 0;
             HIP_TRY(hipMemcpy(&bits, d.d_rowmax, sizeof(bits), hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(&theta_min, d.lab + 2 * gld::kCheckIters, sizeof(double), hipMemcpyDeviceToHost));
             float g = 0;
             std::memcpy(&g, &bits, sizeof(g));
-            if (g <= d.lam_tight) Ka = pl.Kt;
+            if (g <= d.lam_tight && theta_min >= d.lam_lo_tight) Ka = pl.Kt;  // as k_cheb_select decides
         }
         size_t ix = 0;
         gld_status ts = ev_begin(s, ix);
@@ -620,7 +622,7 @@ gld_status setup_noise(gld_system *s)
     if (st != GLD_OK) return fail(st, err);
     const double tol = p.noise_tol > 0 ? p.noise_tol : (s->geo.fp64 ? 1e-12 : 1e-6);
     double lo = p.lam_lo, hi = p.lam_hi;
-    double hi_t = 0;  // tight plan (automatic interval only)
+    double hi_t = 0, lo_t = 0;  // tight plan (automatic interval only)
     const bool has_pair = d.has_pair;
     if (!(hi > lo)) {
         if (!has_pair) {
@@ -671,9 +673,13 @@ gld_status setup_noise(gld_system *s)
             // device picks the plan at every step, so the tight one is used
             // only where its interval provably holds the spectrum.
             if (observed < hi) hi_t = observed;
+            // its lower end an eighth of the way to the singular point (the
+            // wide plan's a quarter); the periodic spectrum check retires it
+            // if the smallest Ritz value ever drops below
+            lo_t = std::isfinite(s->plan.sing_lo) ? th[0] - 0.125 * (th[0] - s->plan.sing_lo) : lo;
         }
     }
-    st = gld::noise_build(p, lo, hi, tol, s->plan, err, hi_t);
+    st = gld::noise_build(p, lo, hi, tol, s->plan, err, hi_t, lo_t);
     if (st != GLD_OK) return fail(st, err);
     if (s->plan.K + s->plan.Kt > gld::kMaxCheb) s->plan.Kt = 0;  // the mixing table holds both plans' rows
     const NoisePlan &pl = s->plan;
@@ -712,6 +718,7 @@ gld_status setup_noise(gld_system *s)
     d.cheb_kt = pl.Kt;
     // a margin for the rounding of the row sums (float)
     d.lam_tight = pl.Kt > 0 ? static_cast<float>(pl.hi_t * (1.0 - 1e-5)) : 0.0f;
+    d.lam_lo_tight = pl.lo_t;
     d.cheb_ab[0] = pl.alpha;
     d.cheb_ab[1] = pl.beta;
     d.cheb_ab[2] = pl.alpha_t;
@@ -996,6 +1003,13 @@ gld_status gld_write_state(gld_system *s, const gld_state *in)
     if ((st = prime_noise(s)) != GLD_OK) return st;
     // the history sums over the lags before the block holding this step
     HIP_TRY(gld::launch_history_block(s->d, 1, s->st));
+    // the spectrum of the installed configuration against the noise interval
+    // (as at creation; the tight plan reads its smallest Ritz value)
+    if (s->noise_on && s->d.has_pair) {
+        double th[2];
+        if ((st = run_check_now(s, s->plan.lo, s->plan.hi, s->plan.sing_lo, s->plan.sing_hi, th, nullptr)) != GLD_OK)
+            return st;
+    }
     return read_flags(s);
 }
 
@@ -1013,6 +1027,7 @@ gld_status gld_noise_parameters(const gld_system *s, gld_noise_info *o)
     o->noise_window = s->d.win;
     o->cheb_terms_tight = s->noise_on ? s->plan.Kt : 0;
     o->lam_hi_tight = s->noise_on ? s->plan.hi_t : 0.0;
+    o->lam_lo_tight = s->noise_on ? s->plan.lo_t : 0.0;
     o->tight_steps = 0;
     if (s->noise_on && s->d.d_tight) {
         unsigned long long n = 0;
@@ -1101,6 +1116,7 @@ gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, doub
     info->noise_window = std::max(1, params->noise_window);
     info->cheb_terms_tight = 0;
     info->lam_hi_tight = 0.0;
+    info->lam_lo_tight = 0.0;
     info->tight_steps = 0;
     return GLD_OK;
 }

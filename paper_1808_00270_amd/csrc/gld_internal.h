@@ -46,17 +46,17 @@ struct NoisePlan {
     // Tight plan (Kt > 0): the expansion on [lo, hi_t], hi_t < hi, with the
     // same filters; a step whose row-sum bound of P stays below hi_t uses it
     int Kt = 0;
-    double hi_t = 0, alpha_t = 0, beta_t = 0, err_cheb_t = 0;
+    double lo_t = 0, hi_t = 0, alpha_t = 0, beta_t = 0, err_cheb_t = 0;
     std::vector<double> Bmix_t;  // [Kt][r]
 };
 
 // Spectra and singular points only (no expansion).  Returns GLD_OK.
 gld_status noise_spectra(const gld_params &p, NoisePlan &plan, std::string &err);
 // Full construction on [lo, hi] with relative rms tolerance tol; with
-// lo < hi_tight < hi also the tight plan on [lo, hi_tight] (one filter bank
-// for both).
+// lo < hi_tight < hi also the tight plan on [max(lo, lo_tight), hi_tight]
+// (one filter bank for both).
 gld_status noise_build(const gld_params &p, double lo, double hi, double tol, NoisePlan &plan,
-                       std::string &err, double hi_tight = 0.0);
+                       std::string &err, double hi_tight = 0.0, double lo_tight = -1e300);
 
 // ---------------------------------------------------------------------------
 // Device-side system description passed to the launchers.
@@ -93,6 +93,7 @@ struct Dev {
     // (alpha, beta) of the wide then the tight plan
     int cheb_kw = 0, cheb_kt = 0;
     float lam_tight = 0;
+    double lam_lo_tight = 0;  // the tight plan needs the last check's smallest Ritz value at least this
     double cheb_ab[4] = {0, 0, 0, 0};
 
     // state (double, [3][S])

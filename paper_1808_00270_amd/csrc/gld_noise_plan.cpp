@@ -193,7 +193,7 @@ gld_status cheb_rows(const NoisePlan &plan, double lo, double hi, double tol, do
 }  // namespace
 
 gld_status noise_build(const gld_params &p, double lo, double hi, double tol, NoisePlan &plan,
-                       std::string &err, double hi_tight)
+                       std::string &err, double hi_tight, double lo_tight)
 {
     gld_status st = noise_spectra(p, plan, err);
     if (st != GLD_OK) return st;
@@ -228,9 +228,10 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
     if ((st = cheb_rows(plan, lo, hi, tol, sig, K, err_cheb, X, err)) != GLD_OK) return st;
     int Kt = 0;
     double err_t = 0;
-    if (hi_tight > lo && hi_tight < hi) {
+    const double lo_t = std::max(lo, lo_tight);
+    if (hi_tight > lo_t && hi_tight < hi) {
         std::vector<double> Xt;
-        if ((st = cheb_rows(plan, lo, hi_tight, tol, sig, Kt, err_t, Xt, err)) != GLD_OK) return st;
+        if ((st = cheb_rows(plan, lo_t, hi_tight, tol, sig, Kt, err_t, Xt, err)) != GLD_OK) return st;
         if (Kt < K) X.insert(X.end(), Xt.begin(), Xt.end());
         else Kt = 0;  // no saving
     }
@@ -272,9 +273,10 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
     plan.err_cheb = err_cheb;
     plan.err_rank = std::sqrt(static_cast<double>(K) / c0) * dropped_max;
     plan.Kt = Kt;
+    plan.lo_t = Kt > 0 ? lo_t : 0.0;
     plan.hi_t = Kt > 0 ? hi_tight : 0.0;
-    plan.alpha_t = Kt > 0 ? 2.0 / (hi_tight - lo) : 0.0;
-    plan.beta_t = Kt > 0 ? -(hi_tight + lo) / (hi_tight - lo) : 0.0;
+    plan.alpha_t = Kt > 0 ? 2.0 / (hi_tight - lo_t) : 0.0;
+    plan.beta_t = Kt > 0 ? -(hi_tight + lo_t) / (hi_tight - lo_t) : 0.0;
     plan.err_cheb_t = err_t;
     plan.Bmix.assign(static_cast<size_t>(K) * r, 0.0);
     plan.Bmix_t.assign(static_cast<size_t>(Kt) * r, 0.0);

@@ -1631,17 +1631,22 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
 //   b_{Ka-1} = v_{Ka-1};  b_k = v_k + 2 P~ b_{k+1} - b_{k+2};  F = v_0 + P~ b_1 - b_2,
 // with b_{Ka} = b_{Ka+1} = 0, P~ = alpha P + beta and Ka the chosen plan's K;
 // the terms k >= Ka are skipped.
+// The tight plan's lower end lies closer to the spectrum than the wide
+// plan's: it also needs the smallest Ritz value of the last spectrum check
+// (theta_min) at least lo_t; once a check finds it below, every step takes
+// the wide plan, whose lower end the check guards as before.
 struct ChainSel {
     int Kw, Kt;           // terms of the wide and the tight plan
     float lam_t;          // largest row-sum bound for the tight plan
+    double lo_t;          // smallest Ritz value of the last check for the tight plan
     double aw, bw, at, bt;
 };
 
-__global__ void k_cheb_select(ChainSel c, const unsigned *__restrict__ rowmax, ChainStep *__restrict__ out,
-                              unsigned long long *__restrict__ tight_steps)
+__global__ void k_cheb_select(ChainSel c, const unsigned *__restrict__ rowmax, const double *__restrict__ theta,
+                              ChainStep *__restrict__ out, unsigned long long *__restrict__ tight_steps)
 {
     const float g = __uint_as_float(*rowmax);
-    const bool tight = c.Kt > 0 && g <= c.lam_t;
+    const bool tight = c.Kt > 0 && g <= c.lam_t && theta[0] >= c.lo_t;
     const int Ka = tight ? c.Kt : c.Kw;
     const double al = tight ? c.at : c.aw, be = tight ? c.bt : c.bw;
     for (int k = threadIdx.x; k < c.Kw; k += blockDim.x) {
@@ -1955,11 +1960,13 @@ hipError_t launch_cheb_select(const Dev &d, hipStream_t st)
     c.Kw = d.cheb_kw;
     c.Kt = d.cheb_kt;
     c.lam_t = d.lam_tight;
+    c.lo_t = d.lam_lo_tight;
     c.aw = d.cheb_ab[0];
     c.bw = d.cheb_ab[1];
     c.at = d.cheb_ab[2];
     c.bt = d.cheb_ab[3];
-    k_cheb_select<<<1, 64, 0, st>>>(c, d.d_rowmax, static_cast<ChainStep *>(d.chain), d.d_tight);
+    k_cheb_select<<<1, 64, 0, st>>>(c, d.d_rowmax, d.lab + 2 * kCheckIters, static_cast<ChainStep *>(d.chain),
+                                    d.d_tight);
     return hipGetLastError();
 }
 
