@@ -188,10 +188,10 @@ gld_status gld_sync(gld_system *sys);
 gld_status gld_read_state(gld_system *sys, gld_state *out);
 
 /* Install a state (r, v, step, optional history); recomputes the neighbour
- * list and F^C, clears latched errors and, with pair memory and noise, checks
- * the spectrum of the pair-weight matrix against the noise interval as
- * gld_create does (GLD_ERR_INTERVAL or GLD_ERR_NOT_PD if it fails).
- * Synchronises. */
+ * list and F^C, clears latched errors and, with pair memory and noise,
+ * measures the extreme Ritz values of the pair-weight matrix (the tight noise
+ * plan needs the smallest; nothing is latched: the periodic spectrum check
+ * judges the interval).  Synchronises. */
 gld_status gld_write_state(gld_system *sys, const gld_state *in);
 
 /* Noise-construction parameters of a system. */

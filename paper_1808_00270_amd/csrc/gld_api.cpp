@@ -1003,12 +1003,13 @@ gld_status gld_write_state(gld_system *s, const gld_state *in)
     if ((st = prime_noise(s)) != GLD_OK) return st;
     // the history sums over the lags before the block holding this step
     HIP_TRY(gld::launch_history_block(s->d, 1, s->st));
-    // the spectrum of the installed configuration against the noise interval
-    // (as at creation; the tight plan reads its smallest Ritz value)
+    // the extreme Ritz values of the installed configuration, which the tight
+    // plan reads (unbounded limits: this measurement latches nothing; the
+    // periodic check judges the interval as before)
     if (s->noise_on && s->d.has_pair) {
+        const double inf = std::numeric_limits<double>::infinity();
         double th[2];
-        if ((st = run_check_now(s, s->plan.lo, s->plan.hi, s->plan.sing_lo, s->plan.sing_hi, th, nullptr)) != GLD_OK)
-            return st;
+        if ((st = run_check_now(s, -inf, inf, -inf, inf, th, nullptr)) != GLD_OK) return st;
     }
     return read_flags(s);
 }
