@@ -491,3 +491,32 @@ def test_tight_and_wide_noise_plans_match_oracle(pkg, oracle_mod, fp64, W):
     assert s.noise_info()["tight_steps"] == t1
     assert_close("F^R (wide plan)", s.read_state()["f_r"], o.noise(9, Rs), tol)
     s.close()
+
+
+def test_tight_plan_lower_end_falls_back_to_wide(pkg, oracle_mod):
+    """One pair at distance 0.45 puts the smallest eigenvalue of P (about
+    -0.835) between the tight plan's lower end and the wide plan's, with the
+    row sums far below the tight bound: the Ritz value that gld_write_state
+    measures retires the tight plan for that state, and the noise (wide
+    plan) still matches the oracle.  WCA off, so that the close pair exerts
+    no force."""
+    w = wl.config(2, n=5000, rho=0.05, m_max=60, wca_eps=0.0)
+    s = pkg.System.from_workload(w)
+    info = s.noise_info()
+    log(f"    wide lower end {info['lam_lo']:.4f}, tight {info['lam_lo_tight']:.4f}")
+    hist = wl.random_history(np.random.default_rng(4), w.m_max, w.n, scale=0.01)
+    o = oracle_for(oracle_mod, w)
+    R, V = w.initial_state()
+    R2 = R.copy()
+    R2[1] = R2[0] + np.array([0.45, 0.0, 0.0])
+    s.write_state(R2, V, step=4, history=hist)
+    t0 = s.noise_info()["tight_steps"]
+    s.step(1)
+    assert s.noise_info()["tight_steps"] == t0
+    assert_close("F^R (wide plan, low eigenvalue)", s.read_state()["f_r"], o.noise(4, R2), TOL[False])
+    # the uniform state again: the tight plan is back
+    s.write_state(R, V, step=4, history=hist)
+    t1 = s.noise_info()["tight_steps"]
+    s.step(1)
+    assert s.noise_info()["tight_steps"] == t1 + 1
+    s.close()
