@@ -212,7 +212,8 @@ enum {
     GLD_K_UPDATE,       /* position and velocity updates                           */
     GLD_K_NEIGHBOR,     /* cell list, pair list and F^C                            */
     GLD_K_CHECK,        /* Lanczos spectrum check                                  */
-    GLD_K_NOISE_SETUP,  /* the chain's plan choice, skipped terms and first term
+    GLD_K_NOISE_SETUP,  /* the chain's plan choice, the premix of its terms'
+                           filter combinations, its skipped terms and first term
                            (with timing on, GLD_K_NOISE_SPMV counts the terms that
                            stream the pair lists only)                             */
     GLD_K_COUNT

@@ -219,6 +219,7 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.d_rowmax, 8);
     L.take(d.d_rebuild, 8);
     L.take(d.chain, static_cast<size_t>(gld::kMaxCheb) * 32);  // ChainStep
+    if (p->kT > 0) L.take(d.vk, static_cast<size_t>(gld::kMaxCheb) * v4);
     L.take(d.d_tight, 8);
     return L.off + 256;
 }
@@ -497,6 +498,8 @@ gld_status enqueue_step(gld_system *s, int slot)
                 LAUNCH(GLD_K_NOISE_SETUP, gld::launch_cheb_select(d, st));
                 ++setup;
             }
+            LAUNCH(GLD_K_NOISE_SETUP, gld::launch_cheb_mix(d, pl.r, pl.K, st));
+            ++setup;
             // term k of the chain passes its index: with a tight plan the
             // step's plan (k_cheb_select) sets its combination, and the terms
             // beyond the tight plan's K return at once
@@ -508,12 +511,12 @@ gld_status enqueue_step(gld_system *s, int slot)
                     if (c != prev1 && c != prev2) { out = c; break; }
                 if (!prev1) {
                     LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r,
-                                                              out, nullptr, nullptr, false, k));
+                                                              out, nullptr, nullptr, false, k, true));
                 } else {
                     rev = !rev;
                     LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, prev1,
                                                               prev2 ? -1.0 : 0.0, prev2, coef(k), pl.r, out, nullptr,
-                                                              nullptr, rev, k));
+                                                              nullptr, rev, k, true));
                 }
                 if (!in_pairs) ++setup;
                 prev2 = prev1;
@@ -522,10 +525,10 @@ gld_status enqueue_step(gld_system *s, int slot)
             if ((ts = to_pairs(0)) != GLD_OK) return ts;
             if (prev1) {
                 LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0, prev2,
-                                                          coef(0), pl.r, nullptr, d.FR, nullptr, !rev, 0));
+                                                          coef(0), pl.r, nullptr, d.FR, nullptr, !rev, 0, true));
             } else {
                 LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(0), pl.r,
-                                                          nullptr, d.FR, nullptr, false, 0));
+                                                          nullptr, d.FR, nullptr, false, 0, true));
             }
             if (!in_pairs) ++setup;
         }

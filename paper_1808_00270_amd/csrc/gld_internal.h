@@ -145,6 +145,7 @@ struct Dev {
     unsigned *d_rowmax = nullptr;  // max row sum of |w| (float bits)
     int *d_rebuild = nullptr;      // rebuild the cell order and candidate lists this step
     void *chain = nullptr;         // ChainStep [kMaxCheb]: the chain's terms as this step's plan sets them
+    void *vk = nullptr;            // T4 [kMaxCheb][S]: v_k = sum_q B[k][q] u_q of the step, sorted order
     unsigned long long *d_tight = nullptr;  // steps whose chain used the tight plan
 };
 
@@ -188,11 +189,15 @@ inline size_t hist_tap_rows(int nslots, int hb) { return static_cast<size_t>(hb 
 // before finished on, which are still in the caches.
 hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
                        const void *z, const void *coef, int r, void *out_sorted, void *out_orig,
-                       const void *add_orig, bool reverse = false, int cheb_k = -1);
+                       const void *add_orig, bool reverse = false, int cheb_k = -1, bool premixed = false);
 // the plan of this step's Chebyshev chain (tight or wide, from the row-sum
 // bound the refresh left): the combination of each term, for the terms of
 // launch_spmv that pass their index cheb_k
 hipError_t launch_cheb_select(const Dev &d, hipStream_t st);
+// v_k = sum_q B[k][q] u_q for the terms of the step's plan (the rows of the
+// mixing table that k_cheb_select chose, or row k without a tight plan):
+// the chain's terms then read one vector each instead of the r filter outputs
+hipError_t launch_cheb_mix(const Dev &d, int r, int K, hipStream_t st);
 // sorted copies of the dissipative input Y and of the r filter outputs of the step
 hipError_t launch_permute(const Dev &d, hipStream_t st, int r);
 // noise window: sorted copies of the r filter outputs of the W steps of the

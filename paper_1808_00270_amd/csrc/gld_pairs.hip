@@ -1038,6 +1038,7 @@ struct MvArgs {
     // rcap per row); null for every other mat-vec
     const ChainStep *chain;
     int cheb_k, rcap;
+    int premix;  // us holds the term's v_k (coefficient 1, r = 1)
 };
 
 // The staged input vector: for the isotropic mat-vec three planes x[], y[],
@@ -1351,7 +1352,7 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                             v = zv[s];
                         }
                     } else {
-                        cf = coef[tt - 2];
+                        cf = A.premix ? T(1) : coef[tt - 2];
                         v = us[static_cast<int64_t>(tt - 2) * A.S + s];
                     }
                     e0 += cf * v.x;
@@ -1671,6 +1672,48 @@ __global__ void k_cheb_select(ChainSel c, const unsigned *__restrict__ rowmax, c
     if (threadIdx.x == 0 && tight) atomicAdd(tight_steps, 1ull);
 }
 
+// v_k = sum_q B[row_k][q] u_q for every term k < K of the chain (row_k and
+// skip from the step's plan when there is a tight plan, else row k): one
+// read of the r filter outputs per step; particle s in cell order
+template <typename T, int RMAX>
+__global__ void k_cheb_mix(int64_t n, int64_t S, int r, int rcap, int K, const T *__restrict__ B,
+                           const ChainStep *__restrict__ chain, const typename V4<T>::t *__restrict__ us,
+                           typename V4<T>::t *__restrict__ vk)
+{
+    using T4 = typename V4<T>::t;
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    T ux[RMAX], uy[RMAX], uz[RMAX];  // the step's filter outputs of this particle (r <= RMAX)
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) {
+        ux[q] = uy[q] = uz[q] = T(0);
+        if (q < r) {
+            const T4 u = us[static_cast<int64_t>(q) * S + s];
+            ux[q] = u.x;
+            uy[q] = u.y;
+            uz[q] = u.z;
+        }
+    }
+    for (int k = 0; k < K; ++k) {
+        int row = k;
+        if (chain) {
+            if (chain[k].skip) continue;
+            row = chain[k].row;
+        }
+        const T *b = B + static_cast<int64_t>(row) * rcap;  // rows are zero-padded to rcap >= RMAX's r
+        T4 v;
+        v.x = v.y = v.z = v.w = T(0);
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) {
+            const T c = q < r ? b[q] : T(0);
+            v.x += c * ux[q];
+            v.y += c * uy[q];
+            v.z += c * uz[q];
+        }
+        vk[static_cast<int64_t>(k) * S + s] = v;
+    }
+}
+
 Geo make_geo(const Dev &d)
 {
     Geo g{};
@@ -1870,11 +1913,17 @@ MvArgs mv_args(const Dev &d, double a, double b, const void *x, double cz, const
 
 hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz, const void *z,
                        const void *coef, int r, void *out_sorted, void *out_orig, const void *add_orig, bool reverse,
-                       int cheb_k)
+                       int cheb_k, bool premixed)
 {
     MvArgs A = mv_args(d, a, b, x, cz, z, coef, r, d.us, out_sorted, out_orig, add_orig, reverse);
+    if (cheb_k >= 0 && premixed) {
+        // a term of the step's chain: its v_k is premixed (k_cheb_mix)
+        A.us = static_cast<const char *>(d.vk) + static_cast<size_t>(cheb_k) * d.S * 4 * (d.fp64 ? 8 : 4);
+        A.r = 1;
+        A.premix = 1;
+    }
     if (cheb_k >= 0 && d.cheb_kt > 0) {
-        // the step's plan decides (k_cheb_select): coef is the whole mixing table
+        // the step's plan decides (k_cheb_select)
         A.chain = static_cast<const ChainStep *>(d.chain);
         A.cheb_k = cheb_k;
         A.rcap = d.fir_rcap;
@@ -1968,6 +2017,29 @@ hipError_t launch_cheb_select(const Dev &d, hipStream_t st)
     k_cheb_select<<<1, 64, 0, st>>>(c, d.d_rowmax, d.lab + 2 * kCheckIters, static_cast<ChainStep *>(d.chain),
                                     d.d_tight);
     return hipGetLastError();
+}
+
+template <typename T, int RMAX>
+static hipError_t cheb_mix_t(const Dev &d, int r, int K, hipStream_t st)
+{
+    using T4 = typename V4<T>::t;
+    const ChainStep *chain = d.cheb_kt > 0 ? static_cast<const ChainStep *>(d.chain) : nullptr;
+    k_cheb_mix<T, RMAX><<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.S, r, d.fir_rcap, K, static_cast<const T *>(d.Bmix),
+                                                          chain, static_cast<const T4 *>(d.us),
+                                                          static_cast<T4 *>(d.vk));
+    return hipGetLastError();
+}
+
+hipError_t launch_cheb_mix(const Dev &d, int r, int K, hipStream_t st)
+{
+    if (d.fp64) {
+        if (r <= 8) return cheb_mix_t<double, 8>(d, r, K, st);
+        if (r <= 16) return cheb_mix_t<double, 16>(d, r, K, st);
+        return cheb_mix_t<double, kMaxRank>(d, r, K, st);
+    }
+    if (r <= 8) return cheb_mix_t<float, 8>(d, r, K, st);
+    if (r <= 16) return cheb_mix_t<float, 16>(d, r, K, st);
+    return cheb_mix_t<float, kMaxRank>(d, r, K, st);
 }
 
 hipError_t launch_permute_window(const Dev &d, hipStream_t st, int r)

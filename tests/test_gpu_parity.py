@@ -354,7 +354,9 @@ def test_kernel_timing_counts(pkg):
     s.close()
     log(f"    K={K} Kt={Kt} tight steps {nt} {kt}")
     pair = nt * (Kt - 1) + (3 - nt) * (K - 1)
-    setup = 3 * (1 if Kt > 0 else 0) + nt * (K - Kt + 1) + (3 - nt)
+    # per step: the premix of the terms' filter combinations, the plan
+    # choice, the skipped terms and the first term
+    setup = 3 * (1 + (1 if Kt > 0 else 0)) + nt * (K - Kt + 1) + (3 - nt)
     assert kt["history"][1] == 6        # the block's product (at block starts) and the step's lags
     assert kt["noise_spmv"][1] == pair
     assert kt["noise_setup"][1] == setup
