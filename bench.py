@@ -47,13 +47,12 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
         # once, the self-memory term added, the output
         return dict(bytes=pairs * (2 + sT) + 4 * n + vec * sT * 3)
     if kind == "noise_spmv":
-        r = info["rank"]
         # a term that streams the pair lists: index + weight per ordered pair,
-        # the input vector once, the combination inputs z and the r filter
-        # outputs, the output; the chain's first term has no pair term and
-        # reads only the r filter outputs and writes the output
-        full = pairs * (2 + sT) + 4 * n + vec * sT * (1 + 1 + r + 1)
-        first = vec * sT * (r + 1)
+        # the input vector once, the combination inputs z and the premixed
+        # v_k, the output (sorted T4 vectors: 4 components of sizeof(T));
+        # the chain's first term has no pair term and reads v_k only
+        full = pairs * (2 + sT) + 4 * n + 4 * n * sT * (1 + 1 + 1 + 1)
+        first = 4 * n * sT * 2
         return dict(full=full, first=first)
     if kind == "noise_fir":
         P = 2 * info["window_half"] + 1
