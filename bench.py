@@ -36,6 +36,7 @@ def log(*a):
 def algorithmic(info, n, m_max, pairs, fp64, kind):
     """Algorithmic bytes (or flops) of one launch of a kernel class."""
     sT = 8 if fp64 else 4
+    ib = info.get("list_index_bits", 16) / 8  # bytes per staged index in the lists
     vec = 3 * n
     if kind == "history":
         # what the convolution of the definition streams per step: the ring,
@@ -43,15 +44,16 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
         # block instead)
         return dict(bytes=(m_max - 1) * vec * sT + vec * 8 + 2 * vec * sT)
     if kind == "dissipative":
-        # 16-bit staged index + weight per ordered pair, the input vector
-        # once, the self-memory term added, the output
-        return dict(bytes=pairs * (2 + sT) + 4 * n + vec * sT * 3)
+        # staged index (12 or 16 bits) + weight per ordered pair, the pair
+        # counts, the input vector once, the self-memory term added, the output
+        return dict(bytes=pairs * (ib + sT) + 4 * n + vec * sT * 3)
     if kind == "noise_spmv":
-        # a term that streams the pair lists: index + weight per ordered pair,
-        # the input vector once, the combination inputs z and the premixed
-        # v_k, the output (sorted T4 vectors: 4 components of sizeof(T));
-        # the chain's first term has no pair term and reads v_k only
-        full = pairs * (2 + sT) + 4 * n + 4 * n * sT * (1 + 1 + 1 + 1)
+        # a term that streams the pair lists: index (12 or 16 bits) + weight
+        # per ordered pair, the pair counts, the input vector once, the
+        # combination inputs z and the premixed v_k, the output (sorted T4
+        # vectors: 4 components of sizeof(T)); the chain's first term has no
+        # pair term and reads v_k only
+        full = pairs * (ib + sT) + 4 * n + 4 * n * sT * (1 + 1 + 1 + 1)
         first = 4 * n * sT * 2
         return dict(full=full, first=first)
     if kind == "noise_fir":
@@ -103,7 +105,11 @@ def run_gpu(args, fp64, window=1):
     s.step(args.kernel_steps)
     kt = s.kernel_times()
     s.set_timing(False)
-    kt_tight = s.noise_info()["tight_steps"] - tight0
+    after = s.noise_info()
+    kt_tight = after["tight_steps"] - tight0
+    # the index width of the lists those steps streamed (12 bits while every
+    # cell's stencil holds at most 4096 particles)
+    info["list_index_bits"] = max(info["list_index_bits"], after["list_index_bits"])
     st = s.read_state()
     # mean neighbour count from the pair weights is not exported; estimate the
     # pair count from the density (checked against the oracle's pair list)
@@ -277,7 +283,7 @@ def main():
                    "precision": "fp32-mixed (f32 history/noise, f64 positions and update)"},
         "latency_ms": pct(r32["lat"]),
         "noise": {k: r32["info"][k] for k in ("cheb_terms", "cheb_terms_tight", "lam_hi", "lam_hi_tight", "rank",
-                                              "block", "window_half", "err_estimate")}
+                                              "block", "window_half", "err_estimate", "list_index_bits")}
                  | {"tight_fraction_kernel_steps": r32["kt_tight"] / args.kernel_steps},
         "kernels_ms_per_step": per_step,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | {"kernel": dom},
@@ -288,7 +294,7 @@ def main():
             "value": w.n * 1e3 / r64["ms_per_step"], "ms_per_step": r64["ms_per_step"],
             "latency_ms": pct(r64["lat"]),
             "noise": {k: r64["info"][k] for k in ("cheb_terms", "cheb_terms_tight", "rank", "block", "window_half",
-                                                  "err_estimate")}
+                                                  "err_estimate", "list_index_bits")}
                      | {"tight_fraction_kernel_steps": r64["kt_tight"] / args.kernel_steps},
             "kernels_ms_per_step": {k: ms / args.kernel_steps for k, (ms, c) in r64["kt"].items()},
             "roofline_history": roofline_entry(r64, "history", True, args.kernel_steps),

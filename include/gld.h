@@ -159,6 +159,10 @@ typedef struct {
                                value falls below it retires the tight plan       */
     int64_t tight_steps;    /* steps since create whose chain used the tight plan
                                (synchronises with the system's stream)               */
+    int32_t list_index_bits; /* bits per staged index in the pair lists the mat-vecs
+                               stream: 12 in a cell whose 27-cell stencil holds at
+                               most 4096 particles, else 16; the largest over the
+                               cells at the last list build (synchronises)          */
 } gld_noise_info;
 
 typedef struct gld_system gld_system;

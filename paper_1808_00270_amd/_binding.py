@@ -95,6 +95,7 @@ class gld_noise_info(C.Structure):
         ("lam_hi_tight", C.c_double),
         ("lam_lo_tight", C.c_double),
         ("tight_steps", C.c_int64),
+        ("list_index_bits", C.c_int32),
     ]
 
 

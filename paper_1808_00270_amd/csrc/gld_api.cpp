@@ -1039,6 +1039,14 @@ gld_status gld_noise_parameters(const gld_system *s, gld_noise_info *o)
         HIP_TRY(hipMemcpy(&n, s->d.d_tight, sizeof(n), hipMemcpyDeviceToHost));
         o->tight_steps = static_cast<int64_t>(n);
     }
+    // entry nst of each cell's stencil row holds (0, total)
+    std::vector<int2> stab(static_cast<size_t>(s->d.ncell) * 28);
+    HIP_TRY(hipStreamSynchronize(s->st));
+    HIP_TRY(hipMemcpy(stab.data(), s->d.stab, stab.size() * sizeof(int2), hipMemcpyDeviceToHost));
+    int most = 0;
+    const int nst = s->d.noff[0] * s->d.noff[1] * s->d.noff[2];
+    for (int c = 0; c < s->d.ncell; ++c) most = std::max(most, stab[static_cast<size_t>(c) * 28 + nst].y);
+    o->list_index_bits = most <= 4096 ? 12 : 16;
     return GLD_OK;
 }
 

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "gld_internal.h"
 
@@ -319,7 +320,11 @@ __device__ void make_stencil(const Geo &g, const int *__restrict__ cstart, int c
 //   nbw  T       entry (k, s) at ((2 h0 C + (k>>2) occ + j) 4 + (k&3)
 // so that one lane fetches 8 indices, or 4 weights, with one 16-byte load
 // (two for FP64 weights), a wave's consecutive particles read one
-// contiguous segment, and a cell's lists are one contiguous stretch.  The weight is w(R_ij) for the isotropic tensor and
+// contiguous segment, and a cell's lists are one contiguous stretch.  A cell
+// whose stencil holds at most kNarrowStencil candidates stores its indices
+// in 12 bits instead (narrow): chunk c of particle j is the 12-byte word
+// triple at c occ + j from the cell's start (the same start as the wide
+// form), entries 0..7 at bits 12 k of the 96.  The weight is w(R_ij) for the isotropic tensor and
 // w(R_ij) / R_ij^2 for the parallel one, whose mat-vec rebuilds the
 // separation d from staged positions (w e e^T x = (w / R^2) d (d . x)).
 // Lists are padded to a multiple of 8 with zero weights (index of the
@@ -328,6 +333,51 @@ __device__ void make_stencil(const Geo &g, const int *__restrict__ cstart, int c
 //                               each entry; entry nst holds (0, total)
 // ---------------------------------------------------------------------------
 constexpr int kStab = kMaxStencil + 1;
+constexpr int kNarrowStencil = 4096;
+
+// 8 staged indices (16-bit fields of a uint4) packed into 12-bit fields
+__device__ __forceinline__ uint3 ids_pack12(uint4 w)
+{
+    const unsigned e0 = w.x & 0xffffu, e1 = w.x >> 16, e2 = w.y & 0xffffu, e3 = w.y >> 16;
+    const unsigned e4 = w.z & 0xffffu, e5 = w.z >> 16, e6 = w.w & 0xffffu, e7 = w.w >> 16;
+    uint3 v;
+    v.x = e0 | (e1 << 12) | (e2 << 24);
+    v.y = (e2 >> 8) | (e3 << 4) | (e4 << 16) | (e5 << 28);
+    v.z = (e5 >> 4) | (e6 << 8) | (e7 << 20);
+    return v;
+}
+
+// chunk k of a cell's index list, as loaded (narrow: w unused)
+template <bool NARROW>
+__device__ __forceinline__ uint4 ids_load(const void *cell, int64_t k)
+{
+    if constexpr (NARROW) {
+        const uint3 v = static_cast<const uint3 *>(cell)[k];
+        return make_uint4(v.x, v.y, v.z, 0u);
+    } else {
+        return static_cast<const uint4 *>(cell)[k];
+    }
+}
+
+// staged index U (0..7, a compile-time constant) of a loaded chunk
+template <bool NARROW, int U>
+__device__ __forceinline__ unsigned id_at(uint4 id)
+{
+    static_assert(U >= 0 && U < 8, "eight entries per chunk");
+    if constexpr (NARROW) {
+        constexpr int b = 12 * U, wd = b / 32, sh = b % 32;
+        const unsigned lo = wd == 0 ? id.x : (wd == 1 ? id.y : id.z);
+        if constexpr (sh <= 20) {
+            return (lo >> sh) & 0xfffu;
+        } else {
+            const unsigned hi = wd == 0 ? id.y : id.z;
+            return ((lo >> sh) | (hi << (32 - sh))) & 0xfffu;
+        }
+    } else {
+        const unsigned wv = U < 2 ? id.x : (U < 4 ? id.y : (U < 6 ? id.z : id.w));
+        return (U & 1) ? (wv >> 16) : (wv & 0xffffu);
+    }
+}
 
 __device__ __forceinline__ int64_t nbl_at(int k, int64_t s, int64_t n) { return ((k >> 3) * n + s) * 8 + (k & 7); }
 __device__ __forceinline__ int64_t nbw_at(int k, int64_t s, int64_t n) { return ((k >> 2) * n + s) * 4 + (k & 3); }
@@ -802,6 +852,8 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
     // this cell's lists (cell-blocked: chunk c of the cell's particle j at
     // c occ + j, weight rows likewise)
     uint4 *nbl4 = reinterpret_cast<uint4 *>(a.nbl) + static_cast<int64_t>(h0) * capc;
+    uint3 *nbl3 = reinterpret_cast<uint3 *>(nbl4);  // the same cell start, narrow form
+    const bool narrow = total <= kNarrowStencil;
     const uint4 *cl = a.snl + static_cast<int64_t>(h0) * (a.capS >> 3);  // candidate lists, likewise
     T4 *nbw4 = static_cast<T4 *>(a.nbw) + static_cast<int64_t>(h0) * 2 * capc;
     for (int g0 = 0; g0 < occ; g0 += kRefreshGroup) {
@@ -916,7 +968,9 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
             const int fc = (cnt >> 3) + q;
             if (fc < (cnt1 >> 3) && fc < capc) {
                 const int base = (fc * 8) & (RING - 1);
-                nbl4[fc * occ + (g0 + pl)] = *reinterpret_cast<const uint4_ring *>(ri + base);
+                const uint4 idv = *reinterpret_cast<const uint4_ring *>(ri + base);
+                if (narrow) nbl3[fc * occ + (g0 + pl)] = ids_pack12(idv);
+                else nbl4[fc * occ + (g0 + pl)] = idv;
                 nbw4[(2 * fc) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base);
                 nbw4[(2 * fc + 1) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base + 4);
             }
@@ -939,7 +993,9 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
                     rw[p & (RING - 1)] = T(0);
                 }
                 const int fl = kept >> 3, base = (fl * 8) & (RING - 1);
-                nbl4[fl * occ + (g0 + pl)] = *reinterpret_cast<const uint4_ring *>(ri + base);
+                const uint4 idv = *reinterpret_cast<const uint4_ring *>(ri + base);
+                if (narrow) nbl3[fl * occ + (g0 + pl)] = ids_pack12(idv);
+                else nbl4[fl * occ + (g0 + pl)] = idv;
                 nbw4[(2 * fl) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base);
                 nbw4[(2 * fl + 1) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base + 4);
             }
@@ -1085,15 +1141,16 @@ constexpr size_t mv_lds_bytes(int maxc)
 }
 
 // one chunk of 8 entries; CHECK: only entries with staged index in [c0, c0 + cn)
-template <typename T, bool PAR, bool CHECK, bool MI, bool SOA>
+template <typename T, bool PAR, bool CHECK, bool MI, bool SOA, bool NARROW>
 __device__ __forceinline__ void mv_chunk(const StageView<T, SOA> &xs, const typename V2<T>::t *pyz, uint4 id,
                                          const typename V4<T>::t &wa, const typename V4<T>::t &wb, const T (&own)[3],
                                          const T (&Lb)[3], const bool (&mi)[3], unsigned c0, unsigned cn, T &p0, T &p1,
                                          T &p2)
 {
     using T4 = typename V4<T>::t;
-    const unsigned li[8] = {id.x & 0xffffu, id.x >> 16, id.y & 0xffffu, id.y >> 16,
-                            id.z & 0xffffu, id.z >> 16, id.w & 0xffffu, id.w >> 16};
+    const unsigned li[8] = {id_at<NARROW, 0>(id), id_at<NARROW, 1>(id), id_at<NARROW, 2>(id),
+                            id_at<NARROW, 3>(id), id_at<NARROW, 4>(id), id_at<NARROW, 5>(id),
+                            id_at<NARROW, 6>(id), id_at<NARROW, 7>(id)};
     const T w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
     if constexpr (!CHECK && SOA && !PAR) {
         // one plane at a time: eight staged values live instead of 24 (the
@@ -1234,12 +1291,13 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
     // this cell's lists (cell-blocked: chunk c of the cell's particle j at
     // c occ + j, weight rows likewise)
     const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw) + static_cast<int64_t>(h0) * 2 * A.cap8;
-    const uint4 *__restrict__ nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;
+    const void *nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;  // either index form
     const bool pair = ca != 0.0;
     const T Lb[3] = {static_cast<T>(A.g.L[0]), static_cast<T>(A.g.L[1]), static_cast<T>(A.g.L[2])};
     const bool mi[3] = {A.g.nc[0] < 3, A.g.nc[1] < 3, A.g.nc[2] < 3};
     __syncthreads();
-    const int total = sbase[nst];
+    const int total = __builtin_amdgcn_readfirstlane(sbase[nst]);
+    const bool narrow = total <= kNarrowStencil;
     bool staged_all = false;
     for (int g0 = 0; g0 < occ; g0 += PG) {
         const int m = min(PG, occ - g0);
@@ -1257,13 +1315,15 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
             own[2] = static_cast<T>(q.z);
         }
         T p0 = 0, p1 = 0, p2 = 0;
-        if (pair) {
+        // the pair sum, for either index form of the cell's lists
+        auto pair_sum = [&](auto narrow_form) __attribute__((always_inline)) {
+            constexpr bool NR = decltype(narrow_form)::value;
             // this lane's first chunk: its loads are in flight during the
             // staging below (a later staging round loads it again)
             uint4 id = make_uint4(0, 0, 0, 0);
             T4 wa{}, wb{};
             if (sub < nch) {
-                id = nbl[sub * occ + j];
+                id = ids_load<NR>(nbl, sub * occ + j);
                 wa = nbw4[(2 * sub) * occ + j];
                 wb = nbw4[(2 * sub + 1) * occ + j];
             }
@@ -1305,7 +1365,7 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                 }
                 // this lane's chunks, the next one's loads in flight
                 if (c0 > 0 && sub < nch) {
-                    id = nbl[sub * occ + j];
+                    id = ids_load<NR>(nbl, sub * occ + j);
                     wa = nbw4[(2 * sub) * occ + j];
                     wb = nbw4[(2 * sub + 1) * occ + j];
                 }
@@ -1314,16 +1374,23 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                     const T4 cwa = wa, cwb = wb;
                     if (ch + L < nch) {
                         const int nx = ch + L;
-                        id = nbl[nx * occ + j];
+                        id = ids_load<NR>(nbl, nx * occ + j);
                         wa = nbw4[(2 * nx) * occ + j];
                         wb = nbw4[(2 * nx + 1) * occ + j];
                     }
-                    if (single) mv_chunk<T, PAR, false, MI>(view, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1, p2);
+                    if (single)
+                        mv_chunk<T, PAR, false, MI, SOA, NR>(view, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1,
+                                                             p2);
                     else
-                        mv_chunk<T, PAR, true, MI>(view, pyz, cid8, cwa, cwb, own, Lb, mi, static_cast<unsigned>(c0),
-                                               static_cast<unsigned>(c1 - c0), p0, p1, p2);
+                        mv_chunk<T, PAR, true, MI, SOA, NR>(view, pyz, cid8, cwa, cwb, own, Lb, mi,
+                                                            static_cast<unsigned>(c0), static_cast<unsigned>(c1 - c0),
+                                                            p0, p1, p2);
                 }
             }
+        };
+        if (pair) {
+            if (narrow) pair_sum(std::true_type{});
+            else pair_sum(std::false_type{});
         }
         // the terms besides the pair sum, b x + cz z + sum_q c_q u_q, spread
         // over the L lanes of each particle (lane sub takes terms sub, sub + L,
@@ -1459,10 +1526,11 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
     const unsigned ss = static_cast<unsigned>(A.maxc);
     const T4 *__restrict__ x = static_cast<const T4 *>(A.x);
     const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw) + static_cast<int64_t>(h0) * 2 * A.cap8;
-    const uint4 *__restrict__ nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;
+    const void *nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;  // either index form
     const bool pair = ca != 0.0;
     __syncthreads();
-    const int total = sbase[nst];
+    const int total = __builtin_amdgcn_readfirstlane(sbase[nst]);
+    const bool narrow = total <= kNarrowStencil;
     bool staged_all = false;
     for (int g0 = 0; g0 < occ; g0 += PG) {
         const int m = min(PG, occ - g0);
@@ -1475,7 +1543,9 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
         T p[NV][3];
 #pragma unroll
         for (int v = 0; v < NV; ++v) p[v][0] = p[v][1] = p[v][2] = T(0);
-        if (pair) {
+        // the pair sums, for either index form of the cell's lists
+        auto pair_sum = [&](auto narrow_form) __attribute__((always_inline)) {
+            constexpr bool NR = decltype(narrow_form)::value;
             for (int c0 = 0; c0 < total; c0 += A.maxc) {
                 const int c1 = min(total, c0 + A.maxc);
                 const bool single = c0 == 0 && c1 == total;
@@ -1502,7 +1572,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                 uint4 id = make_uint4(0, 0, 0, 0);
                 T4 wa{}, wb{};
                 if (sub < nch) {
-                    id = nbl[sub * occ + j];
+                    id = ids_load<NR>(nbl, sub * occ + j);
                     wa = nbw4[(2 * sub) * occ + j];
                     wb = nbw4[(2 * sub + 1) * occ + j];
                 }
@@ -1512,12 +1582,13 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                     const T4 cwa = wa, cwb = wb;
                     if (ch + L < nch) {
                         const int nx = ch + L;
-                        id = nbl[nx * occ + j];
+                        id = ids_load<NR>(nbl, nx * occ + j);
                         wa = nbw4[(2 * nx) * occ + j];
                         wb = nbw4[(2 * nx + 1) * occ + j];
                     }
-                    const unsigned li[8] = {cid8.x & 0xffffu, cid8.x >> 16, cid8.y & 0xffffu, cid8.y >> 16,
-                                            cid8.z & 0xffffu, cid8.z >> 16, cid8.w & 0xffffu, cid8.w >> 16};
+                    const unsigned li[8] = {id_at<NR, 0>(cid8), id_at<NR, 1>(cid8), id_at<NR, 2>(cid8),
+                                            id_at<NR, 3>(cid8), id_at<NR, 4>(cid8), id_at<NR, 5>(cid8),
+                                            id_at<NR, 6>(cid8), id_at<NR, 7>(cid8)};
                     T w[8] = {cwa.x, cwa.y, cwa.z, cwa.w, cwb.x, cwb.y, cwb.z, cwb.w};
                     unsigned lo8[8];
 #pragma unroll
@@ -1544,6 +1615,10 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                     }
                 }
             }
+        };
+        if (pair) {
+            if (narrow) pair_sum(std::true_type{});
+            else pair_sum(std::false_type{});
         }
         // b x_v + cz z_v + sum_q c_q u_{v,q}, spread over the L lanes of each
         // particle as in k_mv

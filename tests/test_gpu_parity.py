@@ -186,6 +186,19 @@ def test_one_step_crowded_cells(pkg, oracle_mod, fp64, parallel):
 
 
 @pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("parallel", [False, True])
+def test_one_step_sixteen_bit_list_indices(pkg, oracle_mod, fp64, parallel):
+    # a Verlet skin of 10 makes the cells 15.5 wide, three per axis: every
+    # stencil holds all 5000 particles, more than 12-bit indices can address,
+    # so the lists keep 16-bit indices (the other tests use 12-bit ones)
+    w = wl.config(2, n=5000, rho=0.05, m_max=60, parallel=parallel)
+    info = one_step(pkg, oracle_mod, w, fp64, verlet_skin=10.0)
+    assert info["list_index_bits"] == 16
+    info = one_step(pkg, oracle_mod, w, fp64)
+    assert info["list_index_bits"] == 12
+
+
+@pytest.mark.parametrize("fp64", [True, False])
 def test_one_step_no_noise_no_pair(pkg, oracle_mod, fp64):
     w = wl.config(1, kT=0.0)
     one_step(pkg, oracle_mod, w, fp64)
@@ -375,25 +388,29 @@ def test_kernel_timing_counts(pkg):
 # positions
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("fp64,W,parallel,graph,crowded", [
-    (False, 2, False, True, False),
-    (False, 8, False, True, False),
-    (False, 4, False, False, False),   # eager launches, no graph
-    (False, 4, True, True, False),     # parallel tensor: one mat-vec per vector
-    (True, 2, False, True, False),
-    (False, 4, False, True, True),     # two staging rounds, two particle groups
-    (True, 2, False, True, True),
+@pytest.mark.parametrize("fp64,W,parallel,graph,crowded,wide", [
+    (False, 2, False, True, False, False),
+    (False, 8, False, True, False, False),
+    (False, 4, False, False, False, False),   # eager launches, no graph
+    (False, 4, True, True, False, False),     # parallel tensor: one mat-vec per vector
+    (True, 2, False, True, False, False),
+    (False, 4, False, True, True, False),     # two staging rounds, two particle groups
+    (True, 2, False, True, True, False),
+    (False, 4, False, True, False, True),     # 16-bit list indices (cells of 15.5)
 ])
-def test_noise_window_matches_oracle(pkg, oracle_mod, fp64, W, parallel, graph, crowded):
+def test_noise_window_matches_oracle(pkg, oracle_mod, fp64, W, parallel, graph, crowded, wide):
     w = wl.config(2, n=5000, rho=0.05, m_max=60, parallel=parallel)
     R, V = wl.slab_state(w, 0.5) if crowded else w.initial_state()
     kw = {"noise_tol": 1e-13} if fp64 else {}
     if crowded:
         kw.update(r=R, v=V)
-    log(f"  noise window W={W} fp64={fp64} parallel={parallel} graph={graph} crowded={crowded}")
+    if wide:
+        kw.update(verlet_skin=10.0)
+    log(f"  noise window W={W} fp64={fp64} parallel={parallel} graph={graph} crowded={crowded} wide={wide}")
     s = pkg.System.from_workload(w, fp64=fp64, noise_window=W, **kw)
     info = s.noise_info()
     assert info["noise_window"] == W and info["block"] % W == 0
+    assert info["list_index_bits"] == (16 if wide else 12)
     log(f"    filter block {info['block']}, rank {info['rank']}, Chebyshev terms {info['cheb_terms']}")
     if not graph:
         s.set_graph(False)
