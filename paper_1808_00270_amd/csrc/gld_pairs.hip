@@ -880,6 +880,44 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
         int cnt = 0;  // pairs so far (the same in the four lanes)
         T rowsum = 0;  // a bound checked with ample margin: work precision suffices
         double fx = 0, fy = 0, fz = 0;
+        // pairs within the WCA range wait in a queue of four (16-bit staged
+        // indices) and are evaluated together, in the order found, so that
+        // their position loads are in flight at once
+        uint32_t wq0 = 0, wq1 = 0;
+        int wn = 0;
+        const double4 xi = live ? a.pos_s[s] : make_double4(0, 0, 0, 0);
+        auto wca_flush = [&]() __attribute__((always_inline)) {
+            int sj[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int l = static_cast<int>(((k < 2 ? wq0 : wq1) >> ((k & 1) * 16)) & 0xffffu);
+                const int e = entry_of(sb, nst, l);
+                sj[k] = sst[e] + (l - sb[e]);
+            }
+            double4 xj[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < wn) xj[k] = a.pos_s[sj[k]];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k >= wn) break;
+                // conservative WCA force in FP64 from the wrapped positions
+                double gx = xi.x - xj[k].x, gy = xi.y - xj[k].y, gz = xi.z - xj[k].z;
+                gx -= a.g.L[0] * rint(gx / a.g.L[0]);
+                gy -= a.g.L[1] * rint(gy / a.g.L[1]);
+                gz -= a.g.L[2] * rint(gz / a.g.L[2]);
+                const double rd2 = gx * gx + gy * gy + gz * gz;
+                if (rd2 < a.wca_rc2) {
+                    const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
+                    const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
+                    fx += fr * gx;
+                    fy += fr * gy;
+                    fz += fr * gz;
+                }
+            }
+            wn = 0;
+            wq0 = wq1 = 0;
+        };
         uint32_t nxt[PL / 2];
         load_candidates<T>(cl, g0 + pl, occ, 0, q, nch, fill, nxt);
         for (int k = 0; k < nround; ++k) {
@@ -944,24 +982,13 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
                 wmask |= (h && r2v[u] < wca_pre) ? (1u << u) : 0u;
             }
             while (wmask) {
-                // conservative WCA force in FP64 from the wrapped positions
-                const int l = cand_at(cur, __ffs(wmask) - 1);
+                const uint32_t l = static_cast<uint32_t>(cand_at(cur, __ffs(wmask) - 1));
                 wmask &= wmask - 1;
-                const int e = entry_of(sb, nst, l);
-                const double4 xi = a.pos_s[s];
-                const double4 xj = a.pos_s[sst[e] + (l - sb[e])];
-                double gx = xi.x - xj.x, gy = xi.y - xj.y, gz = xi.z - xj.z;
-                gx -= a.g.L[0] * rint(gx / a.g.L[0]);
-                gy -= a.g.L[1] * rint(gy / a.g.L[1]);
-                gz -= a.g.L[2] * rint(gz / a.g.L[2]);
-                const double rd2 = gx * gx + gy * gy + gz * gz;
-                if (rd2 < a.wca_rc2) {
-                    const double s2 = a.wca_s2 / rd2, s6 = s2 * s2 * s2;
-                    const double fr = 24.0 * a.wca_eps * (2.0 * s6 * s6 - s6) / rd2;
-                    fx += fr * gx;
-                    fy += fr * gy;
-                    fz += fr * gz;
-                }
+                if (wn == 4) wca_flush();
+                const int sh = (wn & 1) * 16;
+                if (wn < 2) wq0 |= l << sh;
+                else wq1 |= l << sh;
+                ++wn;
             }
             // chunks completed this round, one per lane
             const int cnt1 = cnt + tot;
@@ -976,6 +1003,7 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
             }
             cnt = cnt1;
         }
+        if (wn > 0) wca_flush();
         // quad sums (WCA force components in the order of the lanes' entries)
         for (int o = 1; o < 4; o <<= 1) {
             rowsum += __shfl_xor(rowsum, o);
