@@ -198,6 +198,20 @@ def test_one_step_sixteen_bit_list_indices(pkg, oracle_mod, fp64, parallel):
     assert info["list_index_bits"] == 12
 
 
+@pytest.mark.parametrize("fp64,W", [(False, 1), (True, 1), (False, 2)])
+def test_one_step_mixed_list_index_widths(pkg, oracle_mod, fp64, W):
+    # 13000 particles in a slab of 0.6 L, cells of 12.8 (skin 7.5), five to
+    # an axis: the stencils of the slab's middle layer hold more than 4096
+    # particles (16-bit indices), those of its outer layers fewer (12-bit),
+    # so the refresh and the mat-vecs meet both forms in one system.  W = 2
+    # (written at step 4, a window's first step): the window's two chains
+    # share the lists, and its forces are those of the per-step method
+    w = wl.config(2, n=13000, rho=0.05, m_max=60)
+    info = one_step(pkg, oracle_mod, w, fp64, step=4, state=wl.slab_state(w, 0.6), verlet_skin=7.5,
+                    noise_window=W)
+    assert info["list_index_bits"] == 16 and info["noise_window"] == W
+
+
 @pytest.mark.parametrize("fp64", [True, False])
 def test_one_step_no_noise_no_pair(pkg, oracle_mod, fp64):
     w = wl.config(1, kT=0.0)
