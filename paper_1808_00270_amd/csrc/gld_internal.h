@@ -110,8 +110,9 @@ struct Dev {
     void *hist_taps = nullptr;          // [hist_tap_rows][2]: (K^s_m, g_m), m = M-1 .. 1, zero-padded
     void *Uh = nullptr;                 // [hist_block][2][3][S]: the block's sums over the lags before it
     double *wtab = nullptr;             // [n_r]
-    void *nbl = nullptr;                // uint16 chunks of 8 staged-stencil indices, cell-blocked: cell at h0 with occ
-                                        // particles holds [cap/8][occ][8] from chunk h0 cap/8
+    void *nbl = nullptr;                // chunks of 8 staged-stencil indices, cell-blocked: cell at h0 with occ
+                                        // particles holds [cap/8][occ] chunks from byte 16 h0 cap/8, each 8 x 16
+                                        // bits, or 8 x 12 bits in 12 bytes where the stencil holds <= 4096
     void *nbw = nullptr;                // T pair weights (w, or w / R^2 for the parallel tensor), cell-blocked
                                         // [cap/4][occ][4] from row h0 cap/4
     void *stab = nullptr;               // int2 [ncell][28] stencil of each cell (first index, base)

@@ -379,8 +379,6 @@ __device__ __forceinline__ unsigned id_at(uint4 id)
     }
 }
 
-__device__ __forceinline__ int64_t nbl_at(int k, int64_t s, int64_t n) { return ((k >> 3) * n + s) * 8 + (k & 7); }
-__device__ __forceinline__ int64_t nbw_at(int k, int64_t s, int64_t n) { return ((k >> 2) * n + s) * 4 + (k & 3); }
 
 struct BuildArgs {
     Geo g;
