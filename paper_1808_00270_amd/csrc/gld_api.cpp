@@ -654,7 +654,9 @@ gld_status setup_noise(gld_system *s)
             // room for it to grow as the configuration evolves: 8 standard
             // deviations above the mean row sum of an ideal gas at this density
             // (mean rho int w dV, variance rho int w^2 dV; a liquid fluctuates
-            // less), and at least 1.25 times the initial bound
+            // less), and at least 1.2 times the initial bound plus 0.5 (a
+            // lattice start at cfg3: 26.6, its liquid 29.2 - 30.3 over 1000
+            // steps)
             double mu = 0, var = 0;
             const double rho = static_cast<double>(p.n) / (p.box[0] * p.box[1] * p.box[2]);
             for (int b = 0; b + 1 < p.n_r; ++b) {
@@ -667,7 +669,7 @@ gld_status setup_noise(gld_system *s)
             }
             mu *= 4.0 * M_PI * rho;
             var *= 4.0 * M_PI * rho;
-            const double observed = 1.25 * std::max(static_cast<double>(gmax), th[1]) + 1.0;
+            const double observed = 1.2 * std::max(static_cast<double>(gmax), th[1]) + 0.5;
             hi = std::max(observed, mu + 8.0 * std::sqrt(var));
             if (std::isfinite(s->plan.sing_hi)) hi = std::min(hi, th[1] + 0.5 * (s->plan.sing_hi - th[1]));
             // A second, tight plan on [lo, observed] for the steps whose
