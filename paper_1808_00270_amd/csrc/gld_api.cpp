@@ -645,9 +645,9 @@ gld_status setup_noise(gld_system *s)
             // singular point: the expansion's cost grows as that gap closes,
             // while the smallest eigenvalue of P is set by the short-range
             // structure and moves by a few percent of the gap as a lattice
-            // start melts (cfg3: -0.810 -> -0.797 over 1000 steps, gap 1.05);
-            // the periodic Lanczos check latches GLD_ERR_INTERVAL if it ever
-            // crosses
+            // start melts (N = 2e5, rho = 0.5: -0.810 -> -0.797 over 1000
+            // steps, gap 1.05); the periodic Lanczos check latches
+            // GLD_ERR_INTERVAL if it ever crosses
             const double span = std::max(1.0, th[1] - th[0]);
             lo = std::isfinite(s->plan.sing_lo) ? th[0] - 0.25 * (th[0] - s->plan.sing_lo) : th[0] - 0.5 * span;
             // the largest row sum of |w| bounds lambda_max at every step; leave
@@ -655,8 +655,8 @@ gld_status setup_noise(gld_system *s)
             // deviations above the mean row sum of an ideal gas at this density
             // (mean rho int w dV, variance rho int w^2 dV; a liquid fluctuates
             // less), and at least 1.2 times the initial bound plus 0.5 (a
-            // lattice start at cfg3: 26.6, its liquid 29.2 - 30.3 over 1000
-            // steps)
+            // lattice start at N = 2e5, rho = 0.5: 26.6, its liquid 29.2 - 30.5
+            // over 1000 steps)
             double mu = 0, var = 0;
             const double rho = static_cast<double>(p.n) / (p.box[0] * p.box[1] * p.box[2]);
             for (int b = 0; b + 1 < p.n_r; ++b) {
@@ -674,9 +674,10 @@ gld_status setup_noise(gld_system *s)
             if (std::isfinite(s->plan.sing_hi)) hi = std::min(hi, th[1] + 0.5 * (s->plan.sing_hi - th[1]));
             // A second, tight plan on [lo, observed] for the steps whose
             // row-sum bound stays below it (the liquid's bound settles well
-            // below the ideal-gas margin: cfg3 near 30 against 48); the
-            // device picks the plan at every step, so the tight one is used
-            // only where its interval provably holds the spectrum.
+            // below the ideal-gas margin: near 30 against 48 at N = 2e5,
+            // rho = 0.5); the device picks the plan at every step, so the
+            // tight one is used only where its interval provably holds the
+            // spectrum.
             if (observed < hi) hi_t = observed;
             // its lower end an eighth of the way to the singular point (the
             // wide plan's a quarter); the periodic spectrum check retires it

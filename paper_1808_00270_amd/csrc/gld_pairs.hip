@@ -1124,7 +1124,7 @@ struct MvArgs {
 };
 
 // The staged input vector: for the isotropic mat-vec three planes x[], y[],
-// z[] of stride maxc (3 values per candidate instead of 4: at cfg3 four FP32
+// z[] of stride maxc (3 values per candidate instead of 4: at N = 2e5, rho = 0.5 four FP32
 // or two FP64 work-groups fit in a CU's LDS); for the parallel tensor
 // (x, y, z, own x) per candidate
 template <typename T, bool PAR>
@@ -1270,7 +1270,7 @@ __device__ __forceinline__ void mv_store(const MvArgs &A, int64_t so, T o0, T o1
 
 // FP32 isotropic: at most 80 registers, so that at least six waves per SIMD
 // are resident (the kernel needs about 62: eight waves, four work-groups of
-// 512, as the LDS of the planar staging allows at cfg3)
+// 512, as the LDS of the planar staging allows at N = 2e5, rho = 0.5)
 template <typename T, bool PAR>
 constexpr int mv_min_waves()
 {
@@ -1422,7 +1422,7 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
         // over the L lanes of each particle (lane sub takes terms sub, sub + L,
         // ...: 0 is x, 1 is z, 2 + q is u_q), loaded right after the pair
         // loop and added to the lane's partial sum, so that their loads are
-        // not left to the end of the work-group (measured at cfg3: FP64 138 ->
+        // not left to the end of the work-group (measured at N = 2e5, rho = 0.5: FP64 138 ->
         // 128 us per mat-vec, FP32 68 -> 64 us with the planar staging)
         {
             T e0 = 0, e1 = 0, e2 = 0;
