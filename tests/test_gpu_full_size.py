@@ -104,3 +104,21 @@ def test_cfg3_full_size_rows_update_and_noise_moments(pkg, oracle_mod, fp64):
     se = math.sqrt(3.0 * (c0 * c0 + cp0 * cp0) * sw2) / (3.0 * sw2) * 3.0
     log(f"    neighbour covariance / w: {est:.5f} vs {cp0:.5f} (+- {se:.5f}), {len(r)} pairs")
     assert abs(est - cp0) < 5 * se
+
+
+def test_cfg3_run_keeps_the_tight_noise_plan(pkg):
+    """Over 300 steps from the lattice start (the benchmark's run), the
+    largest row sum of |w| stays below the tight plan's upper end at every
+    step: each chain uses the shorter expansion (the wide one would be exact
+    too, only slower), and nothing is latched."""
+    w = wl.config(3)
+    s = pkg.System.from_workload(w)
+    info = s.noise_info()
+    log(f"  tight plan K {info['cheb_terms_tight']} up to {info['lam_hi_tight']:.3f} (wide K {info['cheb_terms']})")
+    assert 0 < info["cheb_terms_tight"] < info["cheb_terms"]
+    t0 = info["tight_steps"]
+    s.step(300)
+    st = s.read_state()
+    assert st["status"] == 0 and st["step"] == 300
+    assert s.noise_info()["tight_steps"] - t0 == 300
+    s.close()
