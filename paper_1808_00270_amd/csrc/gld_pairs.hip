@@ -655,6 +655,7 @@ __global__ __launch_bounds__(kPairThreads) void k_build(BuildArgs a)
 constexpr int kRefreshThreads = 256;
 constexpr int kRefreshGroup = kRefreshThreads / 4;  // particles per round of a work-group
 constexpr size_t kRefreshLds = 80 * 1024;           // per work-group: two per CU
+constexpr size_t kRefreshLds64 = 150 * 1024;        // FP64: one per CU
 
 template <typename T>
 struct RefreshShape;
@@ -1857,6 +1858,11 @@ template <typename T, bool EX, bool PAR, bool MI>
 hipError_t refresh_k(const Dev &d, const BuildArgs &a, hipStream_t st)
 {
     const size_t shm = static_cast<size_t>(a.stage_n + 1) * sizeof(typename V4<T>::t);
+    if (shm > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refresh<T, EX, PAR, MI>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
+        if (e != hipSuccess) return e;
+    }
     k_refresh<T, EX, PAR, MI><<<d.ncell, kRefreshThreads, shm, st>>>(a);
     return hipGetLastError();
 }
@@ -1865,9 +1871,13 @@ template <typename T, bool EX>
 hipError_t launch_refresh_t(const Dev &d, BuildArgs a, bool mi, hipStream_t st)
 {
     // stage the expected stencil (the mat-vec's estimate) as far as the LDS
-    // budget of two work-groups per CU allows
+    // budget allows: two work-groups per CU in FP32; in FP64 (32 bytes per
+    // position) one, which stages the whole stencil instead of half of it
+    // and spares the rest the global path (N = 2e5, rho = 0.5: 0.91 ->
+    // 0.83 ms of neighbour work per step)
     constexpr size_t per = sizeof(typename V4<T>::t);
-    const int room = static_cast<int>((kRefreshLds - refresh_fixed_lds<T>()) / per) - 1;
+    constexpr size_t budget = sizeof(T) == 8 ? kRefreshLds64 : kRefreshLds;
+    const int room = static_cast<int>((budget - refresh_fixed_lds<T>()) / per) - 1;
     a.stage_n = std::max(0, std::min(d.maxc, room));
     if (d.parallel) return mi ? refresh_k<T, EX, true, true>(d, a, st) : refresh_k<T, EX, true, false>(d, a, st);
     return mi ? refresh_k<T, EX, false, true>(d, a, st) : refresh_k<T, EX, false, false>(d, a, st);
