@@ -239,7 +239,7 @@ def main():
                          "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this GLD build runs one system on one GPU; multi-GPU runs are not supported "
+        print("bench.py: this library runs one system on one GPU; multi-GPU runs are not supported "
               "(each GPU would take its own systems with no communication).", file=sys.stderr)
         sys.exit(2)
     import torch
