@@ -23,10 +23,11 @@ ORC_OK, ORC_ERR_INVALID, ORC_ERR_NOT_PD, ORC_ERR_NO_CONV, ORC_ERR_OOM = 0, -1, -
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, IEEE semantics, OpenMP)."""
+    """Compile the oracle with gcc (-O3 without fast-math: IEEE semantics and
+    the source's order of every floating-point operation; OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c99", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-std=c99", "-shared", "-fPIC",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -81,6 +82,7 @@ def lib():
         _lib.orc_tridiag_eig.argtypes = [C.c_int, d, d, d]
         _lib.orc_last_iters.argtypes = [C.c_void_p]
         _lib.orc_num_threads.restype = C.c_int
+        _lib.orc_set_threads.argtypes = [C.c_int]
     return _lib
 
 
@@ -255,3 +257,8 @@ def tridiag_eig(d, e):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (1: single core)."""
+    lib().orc_set_threads(int(n))

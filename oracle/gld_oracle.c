@@ -1036,3 +1036,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* threads of the OpenMP loops (timing on one core); n <= 0 leaves them */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

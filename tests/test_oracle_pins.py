@@ -27,15 +27,16 @@ from paper_1808_00270_amd import workloads as wl
 
 
 def make_oracle(oracle_mod, *, n, box, m_max, dt=0.01, kT=1.0, mass=1.0, k_self=None, k_pair=None,
-                r_cut=5.0, n_r=51, parallel=False, wca_eps=0.0, seed=7, tol=1e-13, max_iter=300, r_cut_min=0.0):
+                r_cut=5.0, n_r=51, parallel=False, wca_eps=0.0, seed=7, tol=1e-13, max_iter=300, r_cut_min=0.0,
+                r0=0.0):
     if k_self is None:
         k_self = wl.discretize(wl.self_kernel, dt, m_max)
-    dr = r_cut / (n_r - 1)
+    dr = (r_cut - r0) / (n_r - 1)
     if k_pair is None:
-        w = wl.pair_weight(np.arange(n_r) * dr, r_cut)
+        w = wl.pair_weight(r0 + np.arange(n_r) * dr, r_cut)
         w[-1] = 0.0
         k_pair = np.outer(w, wl.discretize(wl.pair_time_kernel, dt, m_max))
-    return oracle_mod.Oracle(n=n, box=box, dt=dt, mass=mass, kT=kT, k_self=k_self, k_pair=k_pair, r0=0.0,
+    return oracle_mod.Oracle(n=n, box=box, dt=dt, mass=mass, kT=kT, k_self=k_self, k_pair=k_pair, r0=r0,
                              dr=dr, r_cut=r_cut, r_cut_min=r_cut_min, parallel=parallel, wca_sigma=1.0,
                              wca_eps=wca_eps, seed=seed, lanczos_tol=tol, lanczos_max_iter=max_iter)
 
@@ -211,32 +212,40 @@ def _gle_response_two_exp(t, A, a, B, b, M=1.0):
     return out.real
 
 
-@pytest.mark.parametrize("parallel", [False, True])
-def test_two_particle_dilute_limit_decouples(oracle_mod, parallel):
+@pytest.mark.parametrize("parallel,r_cut_min,r0", [(False, 0.0, 0.0), (True, 0.0, 0.0),
+                                                    (False, 0.0, 0.5), (False, 2.6, 0.5), (True, 2.6, 0.5),
+                                                    (False, 2.6, 0.0)])
+def test_two_particle_dilute_limit_decouples(oracle_mod, parallel, r_cut_min, r0):
     """Two particles at fixed distance R along x (Sec. III.A): V_+- obey
     single-particle GLEs with K_+- = K^s +- K^p(R).  Linear response with a
     tiny initial velocity keeps R fixed; the scheme converges to the closed
     form at second order.  Pins the sign and the j-index of the pair terms of
-    eq. (dissipative_force2), the m = 0 term included."""
+    eq. (dissipative_force2), the m = 0 term included.
+
+    The distance table starts at r0 (a grid offset) and w is linear in r, so
+    interpolation on the grid is exact.  With r_cut_min > R the kernel is
+    frozen at its value at r_c,min (Sec. III.B: the reconstruction stops at
+    r_c,min and the kernel below it is taken as the one there), so the
+    closed form must use K^p(r_c,min), not K^p(R)."""
     As, ts, Bp, tp, rc, Rd = 30.0, 0.25, 12.0, 0.15, 5.0, 2.0
     eps = 1e-7
     errs = []
     for dt in (0.02, 0.01):
         m_max = int(round(14 * ts / dt))
-        n_r = 51
-        dr = rc / (n_r - 1)
-        w = np.clip(1 - np.arange(n_r) * dr / rc, 0, None)
+        n_r = 46
+        dr = (rc - r0) / (n_r - 1)
+        w = np.clip(1 - (r0 + np.arange(n_r) * dr) / rc, 0, None)
         g = wl.discretize(lambda t: Bp * np.exp(-t / tp), dt, m_max)
         ks = wl.discretize(lambda t: As * np.exp(-t / ts), dt, m_max)
         o = make_oracle(oracle_mod, n=2, box=60.0, m_max=m_max, dt=dt, kT=0.0, k_self=ks,
-                        k_pair=np.outer(w, g), r_cut=rc, n_r=n_r, parallel=parallel)
+                        k_pair=np.outer(w, g), r_cut=rc, n_r=n_r, parallel=parallel, r_cut_min=r_cut_min, r0=r0)
         R = np.array([[10.0, 10.0, 10.0], [10.0 + Rd, 10.0, 10.0]])
         V = np.array([[eps, 0.0, 0.0], [0.0, 0.0, 0.0]])
         T = 1.5
         steps = int(round(T / dt))
         _, Vs = _run_free(o, R, V, steps)
         t = np.arange(steps + 1) * dt
-        wR = 1 - Rd / rc
+        wR = 1 - max(Rd, r_cut_min) / rc
         Gp = _gle_response_two_exp(t, As, 1 / ts, wR * Bp, 1 / tp)
         Gm = _gle_response_two_exp(t, As, 1 / ts, -wR * Bp, 1 / tp)
         v1 = Vs[:, 0, 0] / eps
