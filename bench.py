@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # vector FP32
 FP64_PEAK_TFLOPS = 78.6        # vector FP64
+FP64_MATRIX_PEAK_TFLOPS = 78.6 # FP64 matrix cores (dense)
 
 
 def log(*a):
@@ -52,15 +53,16 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
         # per ordered pair, the pair counts, the input vector once, the
         # combination inputs z and the premixed v_k, the output (sorted T4
         # vectors: 4 components of sizeof(T)); the chain's first term has no
-        # pair term and reads v_k only
+        # pair term and reads v_k only.  Arithmetic: 3 multiply-adds per
+        # ordered pair (isotropic tensor) and the epilogue's 4 per component
         full = pairs * (ib + sT) + 4 * n + 4 * n * sT * (1 + 1 + 1 + 1)
         first = 4 * n * sT * 2
-        return dict(full=full, first=first)
+        return dict(full=full, first=first, flops=6.0 * pairs + 2.0 * 4 * vec)
     if kind == "noise_fir":
         P = 2 * info["window_half"] + 1
-        # per active launch: block * rank filters of P taps (the window kept
-        # by the noise plan) on 3N channels
-        return dict(flops=2.0 * vec * info["block"] * info["rank"] * P)
+        # per step: a 1/block share of the block's outputs, block * rank
+        # filters of P taps (the window kept by the noise plan) on 3N channels
+        return dict(flops=2.0 * vec * info["rank"] * P)
     return {}
 
 
@@ -90,7 +92,21 @@ def run_gpu(args, fp64, window=1):
     torch.cuda.synchronize()
     dt_run = time.perf_counter() - t0
     ms_per_step = 1e3 * dt_run / args.steps
-    log(f"[bench] {tag}: {ms_per_step:.3f} ms/step")
+    log(f"[bench] {tag}: {ms_per_step:.3f} ms/step over {args.steps} steps")
+    step_now = args.warmup + args.steps
+    # whole spectrum-check cycles (the check runs every 100 steps): from the
+    # next multiple of 100, `cycle_steps` steps timed the same way
+    ms_cycle = None
+    if args.cycle_steps > 0:
+        s.step((-step_now) % 100)
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(args.cycle_steps)
+        s.sync()
+        torch.cuda.synchronize()
+        ms_cycle = 1e3 * (time.perf_counter() - t0) / args.cycle_steps
+        log(f"[bench] {tag}: {ms_cycle:.3f} ms/step over {args.cycle_steps} steps from a check")
     # per-step latency, synchronous single steps
     lat = []
     for _ in range(args.latency_steps):
@@ -110,15 +126,14 @@ def run_gpu(args, fp64, window=1):
     # the index width of the lists those steps streamed (12 bits while every
     # cell's stencil holds at most 4096 particles)
     info["list_index_bits"] = max(info["list_index_bits"], after["list_index_bits"])
+    info["theta_min"] = after["theta_min"]
+    pairs, most = s.list_stats()
     st = s.read_state()
-    # mean neighbour count from the pair weights is not exported; estimate the
-    # pair count from the density (checked against the oracle's pair list)
-    pairs = w.n * (w.n / w.box ** 3) * 4.0 / 3.0 * math.pi * w.r_cut ** 3
     s.close()
     del s
     torch.cuda.empty_cache()
-    return dict(w=w, info=info, ms_per_step=ms_per_step, lat=lat, kt=kt, kt_tight=kt_tight, pairs=pairs,
-                t_create=t_create, status=st["status"])
+    return dict(w=w, info=info, ms_per_step=ms_per_step, ms_cycle=ms_cycle, lat=lat, kt=kt, kt_tight=kt_tight,
+                pairs=pairs, max_pairs=most, t_create=t_create, status=st["status"])
 
 
 def measured_traffic(workload, kind, fp64):
@@ -155,23 +170,34 @@ def roofline_entry(res, kind, fp64, kernel_steps):
     if cnt == 0:
         return None
     if kind == "history":
-        # blocked: the matrix-core product over the lags before the block at
-        # block starts, the block's own lags every step; per step against the
-        # bytes the per-step streaming convolution would read
+        # every step: a 1/HB share of the next block's matrix-core product (the
+        # lags m > j + HB of its steps) and the step's own lags (m <= j + HB);
+        # the ring is read once per block of HB steps
+        hb = 16 if fp64 else 32
         per = ms / kernel_steps
+        sT = 8 if fp64 else 4
+        vec = 3 * w.n
+        span = max(0, w.m_max - 1 - hb)
+        flops = 2.0 * 2 * span * vec           # (K^s, g) rows x window x channels, per step (1/HB of HB rows)
+        ring_bytes = span * vec * sT / hb      # the ring's share read by the product per step
+        own = (hb + (hb - 1) / 2) * vec * sT   # the step's own lags, on average
         b = algorithmic(info, w.n, w.m_max, res["pairs"], fp64, kind)["bytes"]
-        return dict(kernel=kind, method="blocked: matrix-core product every block of steps + the block's own lags",
-                    block_steps=16 if fp64 else 32, ms_per_step=per, definition_bytes_per_step=b,
-                    equivalent_GBps=b / (per * 1e-3) / 1e9, hbm_peak_GBps=HBM_PEAK_GBS)
+        return dict(kernel=kind, method="blocked: a 1/HB share of the next block's matrix-core product every step "
+                    "+ the step's own lags", block_steps=hb, ms_per_step=per,
+                    matrix_flops_per_step=flops, matrix_tflops=flops / (per * 1e-3) / 1e12,
+                    matrix_peak_tflops=FP64_MATRIX_PEAK_TFLOPS if fp64 else FP32_PEAK_TFLOPS,
+                    hbm_bytes_per_step=ring_bytes + own + 8 * vec,
+                    hbm_GBps=(ring_bytes + own + 8 * vec) / (per * 1e-3) / 1e9,
+                    definition_bytes_per_step=b,
+                    note="the per-step definition would stream definition_bytes_per_step; the blocked form "
+                         "reads hbm_bytes_per_step")
     alg = algorithmic(info, w.n, w.m_max, res["pairs"], fp64, kind)
     if kind == "noise_fir":
-        # only one launch in `block` does work; charge the active ones
-        active = max(1, cnt // max(1, info["block"]))
-        avg = ms / active
+        avg = ms / cnt
         fl = alg["flops"]
         ach = fl / (avg * 1e-3) / 1e12
-        peak = FP64_PEAK_TFLOPS if fp64 else FP32_PEAK_TFLOPS
-        return dict(kernel=kind, bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
+        peak = FP64_MATRIX_PEAK_TFLOPS if fp64 else FP32_PEAK_TFLOPS
+        return dict(kernel=kind, bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
                     traffic=None, avg_ms=avg, launches=cnt, flops_per_launch=fl)
     if kind == "noise_spmv":
         # the library times the chain's terms that stream the pair lists
@@ -183,14 +209,35 @@ def roofline_entry(res, kind, fp64, kernel_steps):
         avg = ms / cnt
         b = alg["bytes"]
     ach = b / (avg * 1e-3) / 1e9
-    return dict(kernel=kind, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                traffic=measured_traffic(w.name, kind, fp64), avg_ms=avg, launches=cnt, bytes_per_launch=b)
+    out = dict(kernel=kind, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+               traffic=measured_traffic(w.name, kind, fp64), avg_ms=avg, launches=cnt, bytes_per_launch=b,
+               pairs=res["pairs"])
+    if "flops" in alg:
+        # the same launches against the vector FP32/FP64 peak (what the
+        # mat-vec computes: 3 multiply-adds per ordered pair)
+        tf = alg["flops"] / (avg * 1e-3) / 1e12
+        peak = FP64_PEAK_TFLOPS if fp64 else FP32_PEAK_TFLOPS
+        out["flop_view"] = dict(flops_per_launch=alg["flops"], achieved_tflops=tf, peak_tflops=peak,
+                                frac=tf / peak)
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(args):
     """The FP64 oracle on a bounded sample of the same workload: dissipative and
     conservative forces for a sample of particles, the colored noise for a
-    subset of the frequencies of Algorithm 1; scaled to one full step."""
+    subset of the frequencies of Algorithm 1; scaled to one full step.  Timed
+    on all the host's cores and on one."""
     import oracle
     from paper_1808_00270_amd import workloads as wl
 
@@ -201,21 +248,31 @@ def cpu_baseline(args):
     R, V = w.initial_state()
     hist = np.zeros((w.m_max - 1, w.n, 3))   # zero pages; the oracle loops over every lag regardless
     rng = np.random.default_rng(0)
-    rows = np.sort(rng.choice(w.n, size=args.cpu_rows, replace=False))
-    t0 = time.perf_counter()
-    o.forces_rows(R, V, hist, rows)
-    t_rows = time.perf_counter() - t0
-    nw = args.cpu_freqs
-    t0 = time.perf_counter()
-    o.noise(0, R, w0=0, w1=nw)
-    t_noise = time.perf_counter() - t0
-    t_step = t_rows * (w.n / len(rows)) + t_noise * (w.m_max / nw)
+
+    def sample(rows_n, nw):
+        rows = np.sort(rng.choice(w.n, size=rows_n, replace=False))
+        t0 = time.perf_counter()
+        o.forces_rows(R, V, hist, rows)
+        t_rows = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        o.noise(0, R, w0=0, w1=nw)
+        t_noise = time.perf_counter() - t0
+        return t_rows, t_noise, t_rows * (w.n / rows_n) + t_noise * (w.m_max / nw)
+
     cores = oracle.num_threads()
+    t_rows, t_noise, t_step = sample(args.cpu_rows, args.cpu_freqs)
+    oracle.set_threads(1)
+    t1_rows, t1_noise, t1_step = sample(max(50, args.cpu_rows // 8), max(1, args.cpu_freqs // 8))
+    oracle.set_threads(cores)
     return dict(value=w.n / t_step, unit="particle-steps/s", cores=cores, kind="oracle",
-                sample=(f"{w.name}: F^C+F^D' of {len(rows)} random particles ({t_rows:.1f}s) and the "
-                        f"Algorithm-1 noise for {nw} of {w.m_max} frequencies incl. pair search ({t_noise:.1f}s), "
-                        f"scaled to one full step = {t_step:.0f}s"),
-                seconds=t_rows + t_noise)
+                sample=(f"{w.name}: F^C+F^D' of {args.cpu_rows} random particles ({t_rows:.1f}s) and the "
+                        f"Algorithm-1 noise for {args.cpu_freqs} of {w.m_max} frequencies incl. pair search "
+                        f"({t_noise:.1f}s), scaled to one full step = {t_step:.0f}s"),
+                seconds=t_rows + t_noise + t1_rows + t1_noise, cpu_model=cpu_model(), build="gcc -O3 -fopenmp",
+                single_core=dict(value=w.n / t1_step, unit="particle-steps/s", cores=1,
+                                 sample=(f"F^C+F^D' of {max(50, args.cpu_rows // 8)} particles ({t1_rows:.1f}s), "
+                                         f"noise for {max(1, args.cpu_freqs // 8)} frequencies ({t1_noise:.1f}s), "
+                                         f"scaled to one full step = {t1_step:.0f}s")))
 
 
 def main():
@@ -224,8 +281,11 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--latency-steps", type=int, default=100)
-    ap.add_argument("--kernel-steps", type=int, default=40)
+    ap.add_argument("--latency-steps", type=int, default=1000)
+    ap.add_argument("--kernel-steps", type=int, default=100,
+                    help="steps timed kernel by kernel (100: one spectrum check included)")
+    ap.add_argument("--cycle-steps", type=int, default=200,
+                    help="steps timed from a multiple of the check interval (whole check cycles); 0: skip")
     ap.add_argument("--cpu-rows", type=int, default=2000)
     ap.add_argument("--cpu-freqs", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
@@ -286,12 +346,18 @@ def main():
                                               "block", "window_half", "err_estimate", "list_index_bits")}
                  | {"tight_fraction_kernel_steps": r32["kt_tight"] / args.kernel_steps},
         "kernels_ms_per_step": per_step,
-        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | {"kernel": dom},
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
+                    | {"kernel": dom, "pairs": r32["pairs"], "avg_ms": roof["avg_ms"]}
+                    | ({"flop_view": roof["flop_view"]} if "flop_view" in roof else {}),
         "roofline_history": roof_hist,
+        "ms_per_step_whole_check_cycles": r32["ms_cycle"],
+        "check_interval": 100,
+        "pairs": {"directed": r32["pairs"], "per_particle": r32["pairs"] / w.n, "max_per_particle": r32["max_pairs"]},
     }
     if r64 is not None:
         out["fp64_plain"] = {
             "value": w.n * 1e3 / r64["ms_per_step"], "ms_per_step": r64["ms_per_step"],
+            "ms_per_step_whole_check_cycles": r64["ms_cycle"],
             "latency_ms": pct(r64["lat"]),
             "noise": {k: r64["info"][k] for k in ("cheb_terms", "cheb_terms_tight", "rank", "block", "window_half",
                                                   "err_estimate", "list_index_bits")}

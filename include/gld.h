@@ -62,6 +62,9 @@ typedef enum { GLD_FP64 = 0, GLD_FP32_MIXED = 1 } gld_precision;
  * the whole table in LDS. */
 #define GLD_MAX_DISTANCE_BINS 1024
 
+/* Most Lanczos iterations a spectrum check may run (gld_params.check_iters). */
+#define GLD_MAX_CHECK_ITERS 200
+
 /* Tensor structure of the pair memory (Sec. II.A): isotropic K^p 1, or only
  * the component parallel to the line of centres, K^p e e^T. */
 typedef enum { GLD_PAIR_ISOTROPIC = 0, GLD_PAIR_PARALLEL = 1 } gld_pair_tensor;
@@ -123,6 +126,35 @@ typedef struct {
                                   32 / padded rank in FP64, so 8 and 2 for ranks 8 and
                                   16) makes gld_create return GLD_ERR_INVALID_ARG.
                                   Ignored when kT = 0. */
+    /* The general tables of eqs. (GLD_basic2) and (dissipative_force2) on the
+     * same distance grid (Sec. III.A tabulates K^p(R, t) on a grid), row-major
+     * [n_r][m_max]:
+     *   k_pair   K^p_m(r_b); NULL: the separable form k_pair_w x k_pair_g.  A
+     *            table of rank one (K^p_m(r) = w(r) g_m to 1e-13 of its
+     *            largest entry) is taken in that separable form, scaled so
+     *            that max_b |w(r_b)| = 1 (lam_lo, lam_hi refer to that w); a
+     *            table of
+     *            higher rank makes each per-frequency correlation a function
+     *            of several pair matrices, which this system type does not
+     *            expand: GLD_ERR_INVALID_ARG ("non-separable pair kernel").
+     *   dk_self  Delta K^s_m(r_b), the distance-dependent part of the self
+     *            memory; NULL or all zero: none.  Non-zero tables are not
+     *            supported by this system type: GLD_ERR_INVALID_ARG. */
+    const double *k_pair;
+    const double *dk_self;
+    /* Caller-built noise filters (the one-off noise coefficients of Sec. II.C,
+     * e.g. from gld_build_noise_filters): noise_a [noise_rank][2 m_max - 1]
+     * filter taps for the lags -(m_max-1)..m_max-1 and noise_b
+     * [noise_terms][noise_rank] Chebyshev mixing weights, built for the
+     * interval [lam_lo, lam_hi] of this struct (which must then be given,
+     * lam_lo < lam_hi).  NULL: gld_create builds them (and a tight plan).
+     * 1 <= noise_rank <= 32, 1 <= noise_terms <= 512; copied at create. */
+    const double *noise_a;
+    const double *noise_b;
+    int32_t noise_rank;
+    int32_t noise_terms;
+    int32_t check_iters;       /* Lanczos iterations of each spectrum check
+                                  (0: 40), at most GLD_MAX_CHECK_ITERS          */
 } gld_params;
 
 /* Snapshot of a system.  On read, every non-NULL array is filled; on write,
@@ -163,6 +195,12 @@ typedef struct {
                                stream: 12 in a cell whose 27-cell stencil holds at
                                most 4096 particles, else 16; the largest over the
                                cells at the last list build (synchronises)          */
+    double theta_min, theta_max; /* extreme Ritz values of the last spectrum check
+                               (an upper bound on the smallest and a lower bound on
+                               the largest eigenvalue of P; synchronises)           */
+    int32_t tight_retired;  /* 1 once a check found theta_min below lam_lo_tight
+                               (the wide plan until the next gld_write_state)       */
+    int32_t filters_given;  /* 1: the filters came from gld_params.noise_a/b      */
 } gld_noise_info;
 
 typedef struct gld_system gld_system;
@@ -201,6 +239,11 @@ gld_status gld_write_state(gld_system *sys, const gld_state *in);
 /* Noise-construction parameters of a system. */
 gld_status gld_noise_parameters(const gld_system *sys, gld_noise_info *out);
 
+/* Directed pairs (i, j), i != j, within r_cut in the current pair list (the
+ * pairs every pair mat-vec of a step streams), and the most any particle
+ * has.  Synchronises the system's stream. */
+gld_status gld_list_stats(gld_system *sys, int64_t *pairs, int32_t *max_per_particle);
+
 /* Use HIP graph replay for gld_step (default on).  */
 gld_status gld_set_graph(gld_system *sys, int enable);
 
@@ -227,6 +270,7 @@ gld_status gld_kernel_times(gld_system *sys, double *ms_sum, int64_t *launches);
 
 /* Release the handle (the workspace stays the caller's). Synchronises. */
 gld_status gld_destroy(gld_system *sys);
+
 
 /* White noise exactly as the integrator draws it: out[t][i][c] = W_{i,c,t0+t}
  * for t < n_t, i < n, c < 3, on the device (d_out: n_t*n*3 doubles), and the

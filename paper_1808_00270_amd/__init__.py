@@ -13,7 +13,7 @@ import numpy as np
 
 from . import _binding as B
 
-__all__ = ["System", "GLDError", "lib", "white_noise"]
+__all__ = ["System", "GLDError", "lib", "white_noise", "noise_filters"]
 
 _lib = None
 
@@ -61,19 +61,29 @@ class System:
     def __init__(self, *, n, box, dt, mass, kT, k_self, r, v, k_pair_g=None, k_pair_w=None, r0=0.0, dr=0.01,
                  r_cut=5.0, r_cut_min=0.0, parallel=False, fp64=False, wca_sigma=1.0, wca_eps=1.0, seed=0,
                  noise_tol=0.0, lam_lo=0.0, lam_hi=0.0, max_neighbors=0, check_interval=0, verlet_skin=None,
-                 noise_window=1, device=None, stream=None):
+                 noise_window=1, k_pair=None, dk_self=None, noise_filters=None, check_iters=0, device=None,
+                 stream=None):
         import torch
 
         self._keep = []
         k_self = np.ascontiguousarray(k_self, dtype=np.float64)
         m_max = k_self.shape[0]
-        g = w = None
+        g = w = kp = dks = fa = fb = None
         if k_pair_g is not None:
             g = np.ascontiguousarray(k_pair_g, dtype=np.float64)
             w = np.ascontiguousarray(k_pair_w, dtype=np.float64)
             assert g.shape == (m_max,)
-        n_r = int(w.shape[0]) if w is not None else 2
-        self._keep += [k_self, g, w]
+        if k_pair is not None:  # the general table [n_r][m_max]
+            kp = np.ascontiguousarray(k_pair, dtype=np.float64)
+            assert kp.ndim == 2 and kp.shape[1] == m_max
+        if dk_self is not None:
+            dks = np.ascontiguousarray(dk_self, dtype=np.float64)
+        if noise_filters is not None:  # (taps [rank][2 m_max - 1], mixing weights [K][rank])
+            fa = np.ascontiguousarray(noise_filters[0], dtype=np.float64)
+            fb = np.ascontiguousarray(noise_filters[1], dtype=np.float64)
+            assert fa.shape[1] == 2 * m_max - 1 and fb.shape[1] == fa.shape[0]
+        n_r = int(w.shape[0]) if w is not None else (int(kp.shape[0]) if kp is not None else 2)
+        self._keep += [k_self, g, w, kp, dks, fa, fb]
         box = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
         self.params = B.gld_params(
             n=int(n), box=(C.c_double * 3)(*box), dt=dt, mass=mass, kT=kT, m_max=m_max, n_r=n_r,
@@ -82,7 +92,10 @@ class System:
             precision=B.GLD_FP64 if fp64 else B.GLD_FP32_MIXED, wca_sigma=wca_sigma, wca_eps=wca_eps,
             seed=int(seed) & 0xFFFFFFFFFFFFFFFF, noise_tol=noise_tol, lam_lo=lam_lo, lam_hi=lam_hi,
             max_neighbors=max_neighbors, check_interval=check_interval,
-            verlet_skin=0.1 * r_cut if verlet_skin is None else float(verlet_skin), noise_window=int(noise_window))
+            verlet_skin=0.1 * r_cut if verlet_skin is None else float(verlet_skin), noise_window=int(noise_window),
+            k_pair=_dp(kp), dk_self=_dp(dks), noise_a=_dp(fa), noise_b=_dp(fb),
+            noise_rank=int(fa.shape[0]) if fa is not None else 0, noise_terms=int(fb.shape[0]) if fb is not None else 0,
+            check_iters=int(check_iters))
         self.n, self.m_max, self.fp64 = int(n), m_max, fp64
         nbytes = C.c_size_t()
         _check(lib().gld_workspace_size(C.byref(self.params), C.byref(nbytes)), "gld_workspace_size")
@@ -137,6 +150,12 @@ class System:
         _check(lib().gld_kernel_times(self.handle, ms, cnt), "gld_kernel_times")
         return {B.KERNEL_NAMES[k]: (ms[k], cnt[k]) for k in range(B.GLD_K_COUNT)}
 
+    def list_stats(self):
+        """(directed pairs within r_cut in the current list, most per particle)."""
+        pairs, most = C.c_int64(), C.c_int32()
+        _check(lib().gld_list_stats(self.handle, C.byref(pairs), C.byref(most)), "gld_list_stats")
+        return pairs.value, most.value
+
     def noise_info(self):
         o = B.gld_noise_info()
         _check(lib().gld_noise_parameters(self.handle, C.byref(o)), "gld_noise_parameters")
@@ -168,6 +187,19 @@ class System:
             assert h.shape == (max(self.m_max - 1, 0), self.n, 3)
         st = B.gld_state(r=_dp(r), v=_dp(v), history=_dp(h) if h is not None and h.size else None, step=int(step))
         _check(lib().gld_write_state(self.handle, C.byref(st)), "gld_write_state")
+
+
+def noise_filters(params, lam_lo, lam_hi, tol=0.0):
+    """The one-off noise construction for [lam_lo, lam_hi] (host only):
+    (taps [rank][2 m_max - 1], mixing weights [K][rank], info dict)."""
+    P = 2 * params.m_max - 1
+    A = np.zeros(32 * P)
+    Bm = np.zeros(512 * 32)
+    info = B.gld_noise_info()
+    _check(lib().gld_build_noise_filters(C.byref(params), float(lam_lo), float(lam_hi), float(tol), _dp(A), A.size,
+                                         _dp(Bm), Bm.size, C.byref(info)), "gld_build_noise_filters")
+    r, K = info.rank, info.cheb_terms
+    return A[:r * P].reshape(r, P).copy(), Bm[:K * r].reshape(K, r).copy(), {f: getattr(info, f) for f, _ in info._fields_}
 
 
 def white_noise(seed, n, t0, n_t, device="cuda"):

@@ -63,6 +63,13 @@ class gld_params(C.Structure):
         ("check_interval", C.c_int32),
         ("verlet_skin", C.c_double),
         ("noise_window", C.c_int32),
+        ("k_pair", _dp),
+        ("dk_self", _dp),
+        ("noise_a", _dp),
+        ("noise_b", _dp),
+        ("noise_rank", C.c_int32),
+        ("noise_terms", C.c_int32),
+        ("check_iters", C.c_int32),
     ]
 
 
@@ -96,13 +103,17 @@ class gld_noise_info(C.Structure):
         ("lam_lo_tight", C.c_double),
         ("tight_steps", C.c_int64),
         ("list_index_bits", C.c_int32),
+        ("theta_min", C.c_double),
+        ("theta_max", C.c_double),
+        ("tight_retired", C.c_int32),
+        ("filters_given", C.c_int32),
     ]
 
 
 EXPORTED = [
     "gld_workspace_size", "gld_create", "gld_step", "gld_sync", "gld_read_state", "gld_write_state",
     "gld_noise_parameters", "gld_set_graph", "gld_set_timing", "gld_kernel_times", "gld_destroy",
-    "gld_white_noise", "gld_build_noise_filters", "gld_status_string", "gld_last_error",
+    "gld_white_noise", "gld_build_noise_filters", "gld_status_string", "gld_last_error", "gld_list_stats",
 ]
 
 
@@ -122,6 +133,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gld_write_state.argtypes = [vp, S]
     lib.gld_noise_parameters.argtypes = [vp, C.POINTER(gld_noise_info)]
     lib.gld_set_graph.argtypes = [vp, C.c_int]
+    lib.gld_list_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
     lib.gld_set_timing.argtypes = [vp, C.c_int]
     lib.gld_kernel_times.argtypes = [vp, _dp, C.POINTER(C.c_int64)]
     lib.gld_destroy.argtypes = [vp]

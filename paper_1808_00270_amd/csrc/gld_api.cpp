@@ -56,6 +56,8 @@ bool finite_all(const double *p, int64_t n)
     return true;
 }
 
+gld_status separable_form(const gld_params *p, std::vector<double> &w, std::vector<double> &g, bool &any);
+
 gld_status validate(const gld_params *p)
 {
     if (!p) return fail(GLD_ERR_INVALID_ARG, "params is NULL");
@@ -89,6 +91,67 @@ gld_status validate(const gld_params *p)
         return fail(GLD_ERR_INVALID_ARG, "verlet_skin must be finite and >= 0");
     if (p->noise_window < 0 || p->noise_window > gld::kMaxFirBlock)
         return fail(GLD_ERR_INVALID_ARG, "noise_window must be in [0, " + std::to_string(gld::kMaxFirBlock) + "]");
+    if (p->check_iters < 0 || p->check_iters > GLD_MAX_CHECK_ITERS)
+        return fail(GLD_ERR_INVALID_ARG, "check_iters must be in [0, GLD_MAX_CHECK_ITERS]");
+    const size_t table = static_cast<size_t>(p->n_r) * p->m_max;
+    if (p->k_pair) {
+        if (p->k_pair_g || p->k_pair_w)
+            return fail(GLD_ERR_INVALID_ARG, "give either the general table k_pair or its separable form k_pair_w, k_pair_g");
+        if (!finite_all(p->k_pair, static_cast<int64_t>(table))) return fail(GLD_ERR_INVALID_ARG, "k_pair not finite");
+        std::vector<double> w, g;
+        bool any = false;
+        gld_status st = separable_form(p, w, g, any);
+        if (st != GLD_OK) return st;
+    }
+    if (p->dk_self) {
+        if (!finite_all(p->dk_self, static_cast<int64_t>(table))) return fail(GLD_ERR_INVALID_ARG, "dk_self not finite");
+        for (size_t i = 0; i < table; ++i)
+            if (p->dk_self[i] != 0.0)
+                return fail(GLD_ERR_INVALID_ARG, "distance-dependent self memory (dk_self): not supported by this "
+                                                 "system type");
+    }
+    if ((p->noise_a == nullptr) != (p->noise_b == nullptr))
+        return fail(GLD_ERR_INVALID_ARG, "noise_a and noise_b must both be given or both NULL");
+    if (p->noise_a) {
+        if (p->noise_rank < 1 || p->noise_rank > gld::kMaxRank || p->noise_terms < 1 || p->noise_terms > gld::kMaxCheb)
+            return fail(GLD_ERR_INVALID_ARG, "noise_rank must be in [1, 32] and noise_terms in [1, 512]");
+        if (!(p->lam_hi > p->lam_lo))
+            return fail(GLD_ERR_INVALID_ARG, "caller-built noise filters need their interval lam_lo < lam_hi");
+        if (!finite_all(p->noise_a, static_cast<int64_t>(p->noise_rank) * (2 * p->m_max - 1)) ||
+            !finite_all(p->noise_b, static_cast<int64_t>(p->noise_terms) * p->noise_rank))
+            return fail(GLD_ERR_INVALID_ARG, "noise filters not finite");
+    }
+    return GLD_OK;
+}
+
+// The general pair table as its separable form, when it has one: with the
+// largest entry at (b*, m*), w_b = K[b][m*] / K[b*][m*] (so max |w| = 1, the
+// scale in which the noise interval of P = [w(R_ij) T_ij] is given) and
+// g_m = K[b*][m]; the table is taken as separable when every entry agrees
+// with w_b g_m to 1e-13 of the largest.  An all-zero table means no pair
+// memory.
+gld_status separable_form(const gld_params *p, std::vector<double> &w, std::vector<double> &g, bool &any)
+{
+    const int nr = p->n_r, M = p->m_max;
+    const double *K = p->k_pair;
+    size_t at = 0;
+    double big = 0;
+    for (size_t i = 0; i < static_cast<size_t>(nr) * M; ++i)
+        if (std::fabs(K[i]) > big) { big = std::fabs(K[i]); at = i; }
+    any = big > 0;
+    if (!any) return GLD_OK;
+    const int bs = static_cast<int>(at / M), ms = static_cast<int>(at % M);
+    w.assign(nr, 0.0);
+    g.assign(M, 0.0);
+    for (int b = 0; b < nr; ++b) w[b] = K[static_cast<size_t>(b) * M + ms] / K[at];
+    for (int m = 0; m < M; ++m) g[m] = K[static_cast<size_t>(bs) * M + m];
+    double worst = 0;
+    for (int b = 0; b < nr; ++b)
+        for (int m = 0; m < M; ++m) worst = std::max(worst, std::fabs(K[static_cast<size_t>(b) * M + m] - w[b] * g[m]));
+    if (worst > 1e-13 * big)
+        return fail(GLD_ERR_INVALID_ARG, "non-separable pair kernel table (rank > 1; largest deviation from the "
+                                         "rank-one form " + std::to_string(worst / big) + " of its largest entry): "
+                                         "not supported by this system type");
     return GLD_OK;
 }
 
@@ -187,17 +250,17 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.relb, static_cast<size_t>(n) * 32);
     L.take(d.snl, static_cast<size_t>(g.capS) * n * 2);
     L.take(d.snn, n * 4);
-    L.take(d.U, static_cast<size_t>(g.firw) * vec * elt);
-    // white-noise ring: at most the full filter window plus the largest block
+    L.take(d.U, 2 * static_cast<size_t>(g.firw) * vec * elt);
+    // white-noise ring: at most the full filter window plus two of the largest blocks
     if (p->kT > 0)
-        L.take(d.wring, static_cast<size_t>(std::max(0, 2 * (p->m_max - 1)) + gld::kMaxFirBlock) * vec * elt);
+        L.take(d.wring, static_cast<size_t>(std::max(0, 2 * (p->m_max - 1)) + 2 * gld::kMaxFirBlock) * vec * elt);
     L.take(d.Afilt, static_cast<size_t>(gld::kMaxRank) * gld::fir_padded_rows(p->m_max - 1, gld::kMaxFirBlock) * elt);
     L.take(d.Bmix, static_cast<size_t>(gld::kMaxCheb) * gld::kMaxRank * elt);
     L.take(d.ks, static_cast<size_t>(p->m_max) * elt);
     if (nslots > 0) {
         const int hb = g.fp64 ? gld::kHistBlock64 : gld::kHistBlock32;
         L.take(d.hist_taps, gld::hist_tap_rows(nslots, hb) * 2 * elt);
-        L.take(d.Uh, static_cast<size_t>(hb) * 2 * vec * elt);
+        L.take(d.Uh, 2 * static_cast<size_t>(gld::kHistSplit) * hb * 2 * vec * elt);
     }
     L.take(d.gm, static_cast<size_t>(p->m_max) * elt);
     L.take(d.wtab, static_cast<size_t>(p->n_r) * 8);
@@ -212,7 +275,7 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.cell_count, static_cast<size_t>(g.ncell) * 4);
     L.take(d.cell_start, static_cast<size_t>(g.ncell + 1) * 4);
     L.take(d.partial, gld::kPartials * 8);
-    L.take(d.lab, (2 * gld::kCheckIters + 4) * 8);
+    L.take(d.lab, (2 * gld::kMaxCheckIters + 4) * 8);
     L.take(d.d_step, 8);
     L.take(d.d_flags, 8);
     L.take(d.d_flag_step, 8);
@@ -221,14 +284,74 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.chain, static_cast<size_t>(gld::kMaxCheb) * 32);  // ChainStep
     if (p->kT > 0) L.take(d.vk, static_cast<size_t>(gld::kMaxCheb) * v4);
     L.take(d.d_tight, 8);
+    L.take(d.d_retired, 8);
     return L.off + 256;
 }
 
 }  // namespace
 
+namespace gld {
+
+gld_status validate_params(const gld_params *p) { return validate(p); }
+
+gld_status separable_pair_table(const gld_params *p, std::vector<double> &w, std::vector<double> &g, bool &any)
+{
+    return separable_form(p, w, g, any);
+}
+
+void auto_interval(const gld_params &p, const NoisePlan &plan, double theta_min, double theta_max, double gmax,
+                   double &lo, double &hi, double &hi_t, double &lo_t)
+{
+    // lower end a quarter of the way from the smallest Ritz value to the
+    // singular point: the expansion's cost grows as that gap closes, while
+    // the smallest eigenvalue of P is set by the short-range structure and
+    // moves by a few percent of the gap as a lattice start melts (N = 2e5,
+    // rho = 0.5: -0.810 -> -0.797 over 1000 steps, gap 1.05); a 40-step
+    // Lanczos run's smallest Ritz value sits 0.009 - 0.016 above the smallest
+    // eigenvalue in rho = 0.5 liquids of N = 500 - 4000, against a margin of
+    // 0.26 here (0.13 for the tight plan); the periodic Lanczos check latches
+    // GLD_ERR_INTERVAL if it ever crosses
+    const double span = std::max(1.0, theta_max - theta_min);
+    lo = std::isfinite(plan.sing_lo) ? theta_min - 0.25 * (theta_min - plan.sing_lo) : theta_min - 0.5 * span;
+    // the largest row sum of |w| bounds lambda_max at every step; leave room
+    // for it to grow as the configuration evolves: 8 standard deviations above
+    // the mean row sum of an ideal gas at this density (mean rho int w dV,
+    // variance rho int w^2 dV; a liquid fluctuates less), and at least 1.2
+    // times the initial bound plus 0.5 (a lattice start at N = 2e5, rho = 0.5:
+    // 26.6, its liquid 29.2 - 30.5 over 1000 steps)
+    double mu = 0, var = 0;
+    const double rho = static_cast<double>(p.n) / (p.box[0] * p.box[1] * p.box[2]);
+    for (int b = 0; b + 1 < p.n_r; ++b) {
+        // trapezoid over the grid, inside the cutoff
+        const double ra = p.r0 + b * p.dr, rb = ra + p.dr;
+        if (ra >= p.r_cut) break;
+        const double wa = std::fabs(p.k_pair_w[b]), wb = std::fabs(p.k_pair_w[b + 1]);
+        mu += 0.5 * p.dr * (ra * ra * wa + rb * rb * wb);
+        var += 0.5 * p.dr * (ra * ra * wa * wa + rb * rb * wb * wb);
+    }
+    mu *= 4.0 * M_PI * rho;
+    var *= 4.0 * M_PI * rho;
+    const double observed = 1.2 * std::max(gmax, theta_max) + 0.5;
+    hi = std::max(observed, mu + 8.0 * std::sqrt(var));
+    if (std::isfinite(plan.sing_hi)) hi = std::min(hi, theta_max + 0.5 * (plan.sing_hi - theta_max));
+    // A second, tight plan on [lo, observed] for the steps whose row-sum bound
+    // stays below it (the liquid's bound settles well below the ideal-gas
+    // margin: near 30 against 48 at N = 2e5, rho = 0.5); the device picks the
+    // plan at every step, so the tight one is used only where its interval
+    // provably holds the spectrum.
+    hi_t = observed < hi ? observed : std::numeric_limits<double>::quiet_NaN();
+    // its lower end an eighth of the way to the singular point (the wide
+    // plan's a quarter); a spectrum check whose smallest Ritz value drops
+    // below it retires it until the next written state
+    lo_t = std::isfinite(plan.sing_lo) ? theta_min - 0.125 * (theta_min - plan.sing_lo) : lo;
+}
+
+}  // namespace gld
+
 struct gld_system {
     gld_params p{};
     std::vector<double> k_self, g, w;
+    std::vector<double> noise_a, noise_b;  // caller-built noise filters (copies)
     Geometry geo;
     Dev d;
     NoisePlan plan;
@@ -251,6 +374,7 @@ struct gld_system {
     int64_t cnt[GLD_K_COUNT] = {0};
     double theta[2] = {0, 0};
     gld_status latched = GLD_OK;
+    bool filters_given = false;
 };
 
 namespace {
@@ -474,11 +598,13 @@ gld_status enqueue_step(gld_system *s, int slot)
             HIP_TRY(hipStreamSynchronize(st));
             unsigned bits = 0;
             double theta_min = 0;
+            int retired = 0;
             HIP_TRY(hipMemcpy(&bits, d.d_rowmax, sizeof(bits), hipMemcpyDeviceToHost));
-            HIP_TRY(hipMemcpy(&theta_min, d.lab + 2 * gld::kCheckIters, sizeof(double), hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(&theta_min, d.lab + 2 * gld::kMaxCheckIters, sizeof(double), hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(&retired, d.d_retired, sizeof(int), hipMemcpyDeviceToHost));
             float g = 0;
             std::memcpy(&g, &bits, sizeof(g));
-            if (g <= d.lam_tight && theta_min >= d.lam_lo_tight) Ka = pl.Kt;  // as k_cheb_select decides
+            if (g <= d.lam_tight && theta_min >= d.lam_lo_tight && retired == 0) Ka = pl.Kt;  // as k_cheb_select
         }
         size_t ix = 0;
         gld_status ts = ev_begin(s, ix);
@@ -546,7 +672,7 @@ gld_status enqueue_step(gld_system *s, int slot)
 gld_status enqueue_check(gld_system *s)
 {
     const NoisePlan &pl = s->plan;
-    LAUNCH(GLD_K_CHECK, gld::launch_spectrum_check(s->d, s->st, gld::kCheckIters, pl.lo, pl.hi, pl.sing_lo,
+    LAUNCH(GLD_K_CHECK, gld::launch_spectrum_check(s->d, s->st, s->d.check_iters, pl.lo, pl.hi, pl.sing_lo,
                                                      pl.sing_hi, s->step + 0x5eed));
     return GLD_OK;
 }
@@ -592,6 +718,7 @@ gld_status clear_flags(gld_system *s)
 {
     HIP_TRY(hipMemsetAsync(s->d.d_flags, 0, 8, s->st));
     HIP_TRY(hipMemsetAsync(s->d.d_flag_step, 0, 8, s->st));
+    HIP_TRY(hipMemsetAsync(s->d.d_retired, 0, 8, s->st));
     HIP_TRY(hipStreamSynchronize(s->st));
     s->latched = GLD_OK;
     return GLD_OK;
@@ -600,10 +727,10 @@ gld_status clear_flags(gld_system *s)
 gld_status run_check_now(gld_system *s, double lo, double hi, double slo, double shi, double theta[2],
                          float *rowmax)
 {
-    HIP_TRY(gld::launch_spectrum_check(s->d, s->st, gld::kCheckIters, lo, hi, slo, shi, s->step + 0x5eed));
+    HIP_TRY(gld::launch_spectrum_check(s->d, s->st, s->d.check_iters, lo, hi, slo, shi, s->step + 0x5eed));
     HIP_TRY(hipStreamSynchronize(s->st));
     double res[2];
-    HIP_TRY(hipMemcpy(res, s->d.lab + 2 * gld::kCheckIters, sizeof(res), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(res, s->d.lab + 2 * gld::kMaxCheckIters, sizeof(res), hipMemcpyDeviceToHost));
     theta[0] = res[0];
     theta[1] = res[1];
     if (rowmax) {
@@ -613,6 +740,8 @@ gld_status run_check_now(gld_system *s, double lo, double hi, double slo, double
     }
     return GLD_OK;
 }
+
+gld_status install_plan(gld_system *s);
 
 gld_status setup_noise(gld_system *s)
 {
@@ -625,7 +754,34 @@ gld_status setup_noise(gld_system *s)
     if (st != GLD_OK) return fail(st, err);
     const double tol = p.noise_tol > 0 ? p.noise_tol : (s->geo.fp64 ? 1e-12 : 1e-6);
     double lo = p.lam_lo, hi = p.lam_hi;
-    double hi_t = 0, lo_t = 0;  // tight plan (automatic interval only)
+    if (p.noise_a) {
+        // the caller's filters for [lam_lo, lam_hi]: the interval must stay
+        // clear of the singular points, as for a plan built here
+        NoisePlan &pl = s->plan;
+        if (!(lo > pl.sing_lo) || !(hi < pl.sing_hi))
+            return fail(GLD_ERR_NOT_PD, "the interval of the given noise filters reaches a singular point of the "
+                                        "noise correlation (" + std::to_string(pl.sing_lo) + ", " +
+                                        std::to_string(pl.sing_hi) + ")");
+        pl.K = p.noise_terms;
+        pl.r = p.noise_rank;
+        pl.lo = lo;
+        pl.hi = hi;
+        pl.alpha = 2.0 / (hi - lo);
+        pl.beta = -(hi + lo) / (hi - lo);
+        pl.Afilt.assign(p.noise_a, p.noise_a + static_cast<size_t>(pl.r) * pl.P);
+        pl.Bmix.assign(p.noise_b, p.noise_b + static_cast<size_t>(pl.K) * pl.r);
+        // the filter window: the largest lag with a non-zero tap
+        pl.half = 0;
+        for (int q = 0; q < pl.r; ++q)
+            for (int t = 0; t < pl.P; ++t)
+                if (pl.Afilt[static_cast<size_t>(q) * pl.P + t] != 0.0) pl.half = std::max(pl.half, std::abs(t - (pl.M - 1)));
+        pl.err_cheb = pl.err_rank = pl.err_window = 0.0;  // unknown: the caller's construction
+        pl.Kt = 0;
+        pl.Bmix_t.clear();
+        s->filters_given = true;
+        return install_plan(s);
+    }
+    double hi_t = std::numeric_limits<double>::quiet_NaN(), lo_t = -1e300;  // tight plan (automatic interval only)
     const bool has_pair = d.has_pair;
     if (!(hi > lo)) {
         if (!has_pair) {
@@ -641,53 +797,22 @@ gld_status setup_noise(gld_system *s)
                                                 ", " + std::to_string(th[1]) + "] reaches a singular point of the "
                                                 "noise correlation (" + std::to_string(s->plan.sing_lo) + ", " +
                                                 std::to_string(s->plan.sing_hi) + "): not positive definite");
-            // lower end a quarter of the way from the smallest Ritz value to the
-            // singular point: the expansion's cost grows as that gap closes,
-            // while the smallest eigenvalue of P is set by the short-range
-            // structure and moves by a few percent of the gap as a lattice
-            // start melts (N = 2e5, rho = 0.5: -0.810 -> -0.797 over 1000
-            // steps, gap 1.05); the periodic Lanczos check latches
-            // GLD_ERR_INTERVAL if it ever crosses
-            const double span = std::max(1.0, th[1] - th[0]);
-            lo = std::isfinite(s->plan.sing_lo) ? th[0] - 0.25 * (th[0] - s->plan.sing_lo) : th[0] - 0.5 * span;
-            // the largest row sum of |w| bounds lambda_max at every step; leave
-            // room for it to grow as the configuration evolves: 8 standard
-            // deviations above the mean row sum of an ideal gas at this density
-            // (mean rho int w dV, variance rho int w^2 dV; a liquid fluctuates
-            // less), and at least 1.2 times the initial bound plus 0.5 (a
-            // lattice start at N = 2e5, rho = 0.5: 26.6, its liquid 29.2 - 30.5
-            // over 1000 steps)
-            double mu = 0, var = 0;
-            const double rho = static_cast<double>(p.n) / (p.box[0] * p.box[1] * p.box[2]);
-            for (int b = 0; b + 1 < p.n_r; ++b) {
-                // trapezoid over the grid, inside the cutoff
-                const double ra = p.r0 + b * p.dr, rb = ra + p.dr;
-                if (ra >= p.r_cut) break;
-                const double wa = std::fabs(p.k_pair_w[b]), wb = std::fabs(p.k_pair_w[b + 1]);
-                mu += 0.5 * p.dr * (ra * ra * wa + rb * rb * wb);
-                var += 0.5 * p.dr * (ra * ra * wa * wa + rb * rb * wb * wb);
-            }
-            mu *= 4.0 * M_PI * rho;
-            var *= 4.0 * M_PI * rho;
-            const double observed = 1.2 * std::max(static_cast<double>(gmax), th[1]) + 0.5;
-            hi = std::max(observed, mu + 8.0 * std::sqrt(var));
-            if (std::isfinite(s->plan.sing_hi)) hi = std::min(hi, th[1] + 0.5 * (s->plan.sing_hi - th[1]));
-            // A second, tight plan on [lo, observed] for the steps whose
-            // row-sum bound stays below it (the liquid's bound settles well
-            // below the ideal-gas margin: near 30 against 48 at N = 2e5,
-            // rho = 0.5); the device picks the plan at every step, so the
-            // tight one is used only where its interval provably holds the
-            // spectrum.
-            if (observed < hi) hi_t = observed;
-            // its lower end an eighth of the way to the singular point (the
-            // wide plan's a quarter); the periodic spectrum check retires it
-            // if the smallest Ritz value ever drops below
-            lo_t = std::isfinite(s->plan.sing_lo) ? th[0] - 0.125 * (th[0] - s->plan.sing_lo) : lo;
+            gld::auto_interval(p, s->plan, th[0], th[1], gmax, lo, hi, hi_t, lo_t);
         }
     }
     st = gld::noise_build(p, lo, hi, tol, s->plan, err, hi_t, lo_t);
     if (st != GLD_OK) return fail(st, err);
     if (s->plan.K + s->plan.Kt > gld::kMaxCheb) s->plan.Kt = 0;  // the mixing table holds both plans' rows
+    return install_plan(s);
+}
+
+// the device side of a noise plan: filter block and ring sizes, the padded
+// taps and mixing weights, the chain's parameters
+gld_status install_plan(gld_system *s)
+{
+    Dev &d = s->d;
+    const bool has_pair = d.has_pair;
+    gld_status st;
     const NoisePlan &pl = s->plan;
     d.fir_rcap = gld::fir_rcap_for(pl.r);
     d.fir_block = gld::fir_block_for(s->geo.fp64, d.fir_rcap);
@@ -699,9 +824,11 @@ gld_status setup_noise(gld_system *s)
         return fail(GLD_ERR_INVALID_ARG, "noise_window " + std::to_string(d.win) + " exceeds the filter block " +
                                              std::to_string(d.fir_block) + " that this noise plan allows");
     d.fir_block -= d.fir_block % d.win;
-    // the filter bank steps through the ring 2 (FP32) or 4 (FP64) slices at a
-    // time and wraps once per step: at least 4 slots (the carve holds 16 more)
-    d.wring_len = std::max(4, 2 * pl.half + d.fir_block);
+    // the ring holds the window of the next block's outputs while the steps
+    // of the current block add the slices one block further ahead:
+    // 2 half + 2 block - 1 slices (the filter bank steps through the ring 2
+    // (FP32) or 4 (FP64) slices at a time and wraps once per step: at least 4)
+    d.wring_len = std::max(4, 2 * pl.half + 2 * d.fir_block);
     // filter taps of the window, tap-major [2 half + 1][rcap] (columns beyond
     // r zero) with block - 1 zero rows before and kFirChunk + block - 1 after
     // (the matrix-core filter bank copies whole chunks of rows); and mixing
@@ -724,7 +851,9 @@ gld_status setup_noise(gld_system *s)
     d.cheb_kt = pl.Kt;
     // a margin for the rounding of the row sums (float)
     d.lam_tight = pl.Kt > 0 ? static_cast<float>(pl.hi_t * (1.0 - 1e-5)) : 0.0f;
-    d.lam_lo_tight = pl.lo_t;
+    d.lam_lo_tight = pl.Kt > 0 ? pl.lo_t : -std::numeric_limits<double>::infinity();
+    // the measurement that set the interval judged nothing: the tight plan starts unretired
+    HIP_TRY(hipMemsetAsync(d.d_retired, 0, 8, s->st));
     d.cheb_ab[0] = pl.alpha;
     d.cheb_ab[1] = pl.beta;
     d.cheb_ab[2] = pl.alpha_t;
@@ -737,8 +866,11 @@ gld_status setup_noise(gld_system *s)
 }
 
 // white-noise ring and filter outputs for the current step (at creation and
-// after a state is installed): the window of the current block, its filter
-// outputs, then the slices the block's earlier steps would have added
+// after a state is installed): the window of the current block and its
+// filter outputs; then the slices the ring holds before this step in an
+// uninterrupted run and, past the block's first step (whose own slice
+// completes that window), the next block's outputs, which the block's
+// earlier steps would have computed
 gld_status prime_noise(gld_system *s)
 {
     s->win_valid = false;
@@ -746,6 +878,7 @@ gld_status prime_noise(gld_system *s)
     HIP_TRY(gld::launch_white_ring(s->d, 1, s->st));
     HIP_TRY(gld::launch_fir(s->d, 1, s->st));
     HIP_TRY(gld::launch_white_ring(s->d, 2, s->st));
+    if (s->step % s->d.fir_block != 0) HIP_TRY(gld::launch_fir(s->d, 2, s->st));
     return GLD_OK;
 }
 
@@ -804,13 +937,27 @@ gld_status gld_create(const gld_params *params, const double *r0, const double *
     gld_system *s = new gld_system();
     s->p = *params;
     s->k_self.assign(params->k_self, params->k_self + params->m_max);
-    if (params->k_pair_g) {
+    bool pair = params->k_pair_g != nullptr;
+    if (params->k_pair) {
+        if ((st = separable_form(params, s->w, s->g, pair)) != GLD_OK) {
+            delete s;
+            return st;
+        }
+    } else if (pair) {
         s->g.assign(params->k_pair_g, params->k_pair_g + params->m_max);
         s->w.assign(params->k_pair_w, params->k_pair_w + params->n_r);
     }
     s->p.k_self = s->k_self.data();
-    s->p.k_pair_g = params->k_pair_g ? s->g.data() : nullptr;
-    s->p.k_pair_w = params->k_pair_w ? s->w.data() : nullptr;
+    s->p.k_pair_g = pair ? s->g.data() : nullptr;
+    s->p.k_pair_w = pair ? s->w.data() : nullptr;
+    s->p.k_pair = nullptr;
+    s->p.dk_self = nullptr;
+    if (params->noise_a) {
+        s->noise_a.assign(params->noise_a, params->noise_a + static_cast<size_t>(params->noise_rank) * (2 * params->m_max - 1));
+        s->noise_b.assign(params->noise_b, params->noise_b + static_cast<size_t>(params->noise_terms) * params->noise_rank);
+        s->p.noise_a = s->noise_a.data();
+        s->p.noise_b = s->noise_b.data();
+    }
     s->geo = geometry(&s->p);
     s->st = static_cast<hipStream_t>(hip_stream);
     s->check_interval = params->check_interval == 0 ? 100 : params->check_interval;
@@ -863,6 +1010,7 @@ gld_status gld_create(const gld_params *params, const double *r0, const double *
         else { d.noff[c] = 3; d.offs[c][0] = -1; d.offs[c][1] = 0; d.offs[c][2] = 1; }
     }
     d.g0 = d.has_pair ? p.k_pair_g[0] : 0.0;
+    d.check_iters = p.check_iters > 0 ? p.check_iters : gld::kCheckIters;
 
     auto bail = [&](gld_status e) {
         if (s->st) (void)hipStreamSynchronize(s->st);
@@ -1007,15 +1155,19 @@ gld_status gld_write_state(gld_system *s, const gld_state *in)
     if ((st = clear_flags(s)) != GLD_OK) return st;
     if ((st = refresh_forces(s)) != GLD_OK) return st;
     if ((st = prime_noise(s)) != GLD_OK) return st;
-    // the history sums over the lags before the block holding this step
+    // the history's block products of the block holding this step and of the
+    // next one (the steps of this block would have computed the latter)
     HIP_TRY(gld::launch_history_block(s->d, 1, s->st));
-    // the extreme Ritz values of the installed configuration, which the tight
-    // plan reads (unbounded limits: this measurement latches nothing; the
-    // periodic check judges the interval as before)
+    HIP_TRY(gld::launch_history_block(s->d, 2, s->st));
+    // the installed configuration against the noise interval and the
+    // singular points, as at creation (Sec. II.B: positive definiteness is
+    // checked on the fly); its smallest Ritz value also decides whether the
+    // tight plan may be used.  A failure latches GLD_ERR_INTERVAL or
+    // GLD_ERR_NOT_PD at the written step, returned here.
     if (s->noise_on && s->d.has_pair) {
-        const double inf = std::numeric_limits<double>::infinity();
         double th[2];
-        if ((st = run_check_now(s, -inf, inf, -inf, inf, th, nullptr)) != GLD_OK) return st;
+        if ((st = run_check_now(s, s->plan.lo, s->plan.hi, s->plan.sing_lo, s->plan.sing_hi, th, nullptr)) != GLD_OK)
+            return st;
     }
     return read_flags(s);
 }
@@ -1050,6 +1202,31 @@ gld_status gld_noise_parameters(const gld_system *s, gld_noise_info *o)
     const int nst = s->d.noff[0] * s->d.noff[1] * s->d.noff[2];
     for (int c = 0; c < s->d.ncell; ++c) most = std::max(most, stab[static_cast<size_t>(c) * 28 + nst].y);
     o->list_index_bits = most <= 4096 ? 12 : 16;
+    double th[2] = {0, 0};
+    int retired = 0;
+    HIP_TRY(hipMemcpy(th, s->d.lab + 2 * gld::kMaxCheckIters, sizeof(th), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&retired, s->d.d_retired, sizeof(int), hipMemcpyDeviceToHost));
+    o->theta_min = th[0];
+    o->theta_max = th[1];
+    o->tight_retired = retired;
+    o->filters_given = s->filters_given ? 1 : 0;
+    return GLD_OK;
+}
+
+gld_status gld_list_stats(gld_system *s, int64_t *pairs, int32_t *max_per_particle)
+{
+    if (!s || !pairs) return fail(GLD_ERR_INVALID_ARG, "NULL argument");
+    std::vector<int> nn(static_cast<size_t>(s->p.n));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    HIP_TRY(hipMemcpy(nn.data(), s->d.nn, nn.size() * sizeof(int), hipMemcpyDeviceToHost));
+    int64_t tot = 0;
+    int most = 0;
+    for (int v : nn) {
+        tot += v;
+        most = std::max(most, v);
+    }
+    *pairs = tot;
+    if (max_per_particle) *max_per_particle = most;
     return GLD_OK;
 }
 
@@ -1104,6 +1281,7 @@ gld_status gld_destroy(gld_system *s)
     return GLD_OK;
 }
 
+
 gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, double lam_hi, double tol, double *a_out,
                                    size_t a_cap, double *b_out, size_t b_cap, gld_noise_info *info)
 {
@@ -1114,7 +1292,16 @@ gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, doub
     if (tol <= 0) tol = params->precision == GLD_FP64 ? 1e-12 : 1e-6;
     NoisePlan plan;
     std::string err;
-    st = gld::noise_build(*params, lam_lo, lam_hi, tol, plan, err);
+    gld_params q = *params;
+    std::vector<double> wv, gv;
+    if (params->k_pair) {
+        bool any = false;
+        if ((st = separable_form(params, wv, gv, any)) != GLD_OK) return st;
+        q.k_pair_w = any ? wv.data() : nullptr;
+        q.k_pair_g = any ? gv.data() : nullptr;
+        q.k_pair = nullptr;
+    }
+    st = gld::noise_build(q, lam_lo, lam_hi, tol, plan, err);
     if (st != GLD_OK) return fail(st, err);
     if (a_cap < plan.Afilt.size() || b_cap < plan.Bmix.size())
         return fail(GLD_ERR_INVALID_ARG, "output capacity too small");
@@ -1133,6 +1320,10 @@ gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, doub
     info->lam_hi_tight = 0.0;
     info->lam_lo_tight = 0.0;
     info->tight_steps = 0;
+    info->list_index_bits = 0;
+    info->theta_min = info->theta_max = 0.0;
+    info->tight_retired = 0;
+    info->filters_given = 0;
     return GLD_OK;
 }
 

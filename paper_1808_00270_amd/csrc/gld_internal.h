@@ -14,7 +14,8 @@ namespace gld {
 
 constexpr int kMaxCheb = 512;     // Chebyshev terms of the noise expansion
 constexpr int kMaxRank = 32;      // filters in the white-noise filter bank
-constexpr int kCheckIters = 40;   // Lanczos iterations of a spectrum check
+constexpr int kCheckIters = 40;   // Lanczos iterations of a spectrum check (default)
+constexpr int kMaxCheckIters = GLD_MAX_CHECK_ITERS;  // the most a system may ask for
 
 // ---------------------------------------------------------------------------
 // One-off FP64 construction of the colored-noise filters.
@@ -54,9 +55,20 @@ struct NoisePlan {
 gld_status noise_spectra(const gld_params &p, NoisePlan &plan, std::string &err);
 // Full construction on [lo, hi] with relative rms tolerance tol; with
 // lo < hi_tight < hi also the tight plan on [max(lo, lo_tight), hi_tight]
-// (one filter bank for both).
+// (one filter bank for both).  hi_tight NaN (the default): no tight plan.
 gld_status noise_build(const gld_params &p, double lo, double hi, double tol, NoisePlan &plan,
-                       std::string &err, double hi_tight = 0.0, double lo_tight = -1e300);
+                       std::string &err, double hi_tight = __builtin_nan(""), double lo_tight = -1e300);
+
+// Parameter checks shared by every system type (gld_api.cpp).
+gld_status validate_params(const gld_params *p);
+// The general pair table as its separable form w x g (max |w| = 1), if it
+// has rank one; `any` false for an all-zero table.
+gld_status separable_pair_table(const gld_params *p, std::vector<double> &w, std::vector<double> &g, bool &any);
+// The automatic noise interval [lo, hi] from the extreme Ritz values of the
+// pair-weight matrix of a configuration and its largest row sum of |w|, and
+// the tight plan's [lo_t, hi_t] (hi_t NaN: none).
+void auto_interval(const gld_params &p, const NoisePlan &plan, double theta_min, double theta_max, double gmax,
+                   double &lo, double &hi, double &hi_t, double &lo_t);
 
 // ---------------------------------------------------------------------------
 // Device-side system description passed to the launchers.
@@ -93,7 +105,8 @@ struct Dev {
     // (alpha, beta) of the wide then the tight plan
     int cheb_kw = 0, cheb_kt = 0;
     float lam_tight = 0;
-    double lam_lo_tight = 0;  // the tight plan needs the last check's smallest Ritz value at least this
+    double lam_lo_tight = -__builtin_huge_val();  // the tight plan needs the last check's smallest Ritz value
+                                                  // at least this (-inf: no tight plan)
     double cheb_ab[4] = {0, 0, 0, 0};
 
     // state (double, [3][S])
@@ -102,13 +115,15 @@ struct Dev {
     void *ring = nullptr;   // [nslots][3][S]
     void *Dneg = nullptr, *Y = nullptr, *FD = nullptr, *FR = nullptr;
     void *cb[3] = {nullptr, nullptr, nullptr};  // T4 [S] Clenshaw vectors, sorted order
-    void *U = nullptr;      // [fir_block][fir_rcap][3][S]
+    void *U = nullptr;      // [2][fir_rows][3][S]: the outputs of two consecutive filter blocks
+                            // (block b at (b mod 2)), rows (step in block) * rcap + filter
     void *wring = nullptr;  // [wring_len][3][S] white noise W_t, slot t mod wring_len
     void *Afilt = nullptr;  // [2 fir_half + 1][fir_rcap], tap-major
     void *Bmix = nullptr;   // [kMaxCheb][fir_rcap]
     void *ks = nullptr, *gm = nullptr;  // [M]
     void *hist_taps = nullptr;          // [hist_tap_rows][2]: (K^s_m, g_m), m = M-1 .. 1, zero-padded
-    void *Uh = nullptr;                 // [hist_block][2][3][S]: the block's sums over the lags before it
+    void *Uh = nullptr;                 // [2][kHistSplit][hist_block][2][3][S]: partial sums over the lags
+                                        // m > j + HB of two consecutive history blocks (block b at b mod 2)
     double *wtab = nullptr;             // [n_r]
     void *nbl = nullptr;                // chunks of 8 staged-stencil indices, cell-blocked: cell at h0 with occ
                                         // particles holds [cap/8][occ] chunks from byte 16 h0 cap/8, each 8 x 16
@@ -138,7 +153,8 @@ struct Dev {
     void *lq[3] = {nullptr, nullptr, nullptr};
     void *lw = nullptr;
     double *partial = nullptr;  // [kPartials]
-    double *lab = nullptr;      // alpha[kCheckIters], beta[kCheckIters], result[4]
+    double *lab = nullptr;      // alpha[kMaxCheckIters], beta[kMaxCheckIters], result[4]
+    int check_iters = kCheckIters;  // Lanczos iterations of a spectrum check
     // scalars
     long long *d_step = nullptr;
     int *d_flags = nullptr;     // [0] status, [1] unused
@@ -148,6 +164,7 @@ struct Dev {
     void *chain = nullptr;         // ChainStep [kMaxCheb]: the chain's terms as this step's plan sets them
     void *vk = nullptr;            // T4 [kMaxCheb][S]: v_k = sum_q B[k][q] u_q of the step, sorted order
     unsigned long long *d_tight = nullptr;  // steps whose chain used the tight plan
+    int *d_retired = nullptr;      // a spectrum check found theta_min below the tight plan's lower end
 };
 
 constexpr int kPartials = 1024;
@@ -158,16 +175,23 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out);
 // history convolution of the step: the block's product (launch_history_block)
 // plus the step's own lags
 hipError_t launch_history(const Dev &d, hipStream_t st);
-// the lags that reach before the block, for all hist_block steps of the block
-// holding the current step: runs at block starts, or (force) at any step
-hipError_t launch_history_block(const Dev &d, int force, hipStream_t st);
+// the lags m > j + HB of the steps n0 + j of a block, summed on the matrix
+// cores: mode 0, the step's share of the next block's product (every step of
+// a block computes 1/HB of it); mode 1, the whole product of the block holding
+// the current step; mode 2, the whole product of the next block
+hipError_t launch_history_block(const Dev &d, int mode, hipStream_t st);
 
 hipError_t launch_dissipative(const Dev &d, hipStream_t st, bool reverse);
-// filter bank; force = 1 produces the block holding the current step even mid-block
-hipError_t launch_fir(const Dev &d, int force, hipStream_t st);
-// white-noise ring: mode 0 writes the slice the step adds (t = step + half +
-// block - 1); mode 1 fills the window of the current block; mode 2 the slices
-// steps n0 .. step-1 of the block would have added (after a resume mid-block)
+// filter bank, outputs of a block of `block` steps: mode 0, the step's share
+// (1/block of the channels) of the next block's outputs; mode 1, the whole
+// block holding the current step; mode 2, the whole next block
+hipError_t launch_fir(const Dev &d, int mode, hipStream_t st);
+// white-noise ring (block bf, window half h, n0 the start of the current
+// step's block): mode 0 writes the slice the step adds, t = step + h + 2 bf - 1
+// (one block ahead of the filter outputs it feeds); mode 1 fills the window of
+// the current block, t = n0 - h .. n0 + bf - 1 + h; mode 2 the slices
+// t = n0 + bf - h .. step + h + 2 bf - 2 (what the ring holds before the step
+// in an uninterrupted run, for the next block's outputs)
 hipError_t launch_white_ring(const Dev &d, int mode, hipStream_t st);
 // filter block sizes for a padded rank (work precision), and the largest one
 int fir_block_for(int fp64, int rcap);
@@ -180,6 +204,12 @@ inline size_t fir_padded_rows(int half, int bf) { return static_cast<size_t>(2 *
 // steps per block of the history convolution: two filters (K^s, g) fill the
 // 64 (FP32) or 32 (FP64) accumulator rows of the matrix-core product
 constexpr int kHistBlock32 = 32, kHistBlock64 = 16;
+// the history's block product is computed during the block before, in
+// hist_block / kHistSplit channel slices times kHistSplit window splits
+// (one per step; the step part adds the kHistSplit partial sums)
+constexpr int kHistSplit = 4;
+// accumulator rows of the filter bank's product (rows of one output block)
+inline int fir_rows(int fp64) { return fp64 ? 32 : 64; }
 // rows of its zero-padded taps (the filter bank's layout, nslots taps)
 inline size_t hist_tap_rows(int nslots, int hb) { return static_cast<size_t>(hb - 1 + nslots + kFirChunk + hb - 1); }
 // out = a P x + b x + cz z + sum_q coef[q] us_q  (x, z, us: sorted T4; x, z may be null
@@ -218,7 +248,7 @@ hipError_t launch_update_r(const Dev &d, hipStream_t st);
 hipError_t launch_update_v(const Dev &d, hipStream_t st);
 hipError_t launch_step_advance(const Dev &d, hipStream_t st);
 hipError_t launch_fill_zero_work(const Dev &d, void *p, int64_t count, hipStream_t st);
-// Lanczos spectrum check on P; writes theta_min/max into d.lab[2*kCheckIters + 0/1]
+// Lanczos spectrum check on P; writes theta_min/max into d.lab[2*kMaxCheckIters + 0/1]
 // and latches GLD_ERR_INTERVAL / GLD_ERR_NOT_PD against the given bounds.
 hipError_t launch_spectrum_check(const Dev &d, hipStream_t st, int iters, double lo, double hi,
                                  double sing_lo, double sing_hi, long long salt);

@@ -25,93 +25,15 @@
 #include <cstdint>
 
 #include "gld_internal.h"
+#include "gld_device.h"
 
 namespace gld {
 
 namespace {
 
 // ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller.
-// Counter (particle, step lo, step hi, stream), key (seed lo, seed hi).
-// ---------------------------------------------------------------------------
-struct U4 {
-    uint32_t x, y, z, w;
-};
-
-__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int i = 0; i < 10; ++i) {
-        if (i) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        U4 o;
-        o.x = hi1 ^ c.y ^ k0;
-        o.y = lo1;
-        o.z = hi0 ^ c.w ^ k1;
-        o.w = lo0;
-        c = o;
-    }
-    return c;
-}
-
-__device__ __forceinline__ U4 philox_at(uint64_t seed, uint32_t pid, long long t, uint32_t stream)
-{
-    const unsigned long long tu = static_cast<unsigned long long>(t);
-    U4 c{pid, static_cast<uint32_t>(tu), static_cast<uint32_t>(tu >> 32), stream};
-    return philox10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
-}
-
-template <typename T>
-struct BoxMuller;
-
-template <>
-struct BoxMuller<double> {
-    __device__ static void gauss3(U4 x, double z[3])
-    {
-        const double s = 1.0 / 4294967296.0;
-        const double u0 = (static_cast<double>(x.x) + 0.5) * s, u1 = (static_cast<double>(x.y) + 0.5) * s;
-        const double u2 = (static_cast<double>(x.z) + 0.5) * s, u3 = (static_cast<double>(x.w) + 0.5) * s;
-        const double ra = sqrt(-2.0 * log(u0)), rb = sqrt(-2.0 * log(u2));
-        double sa, ca, cb, sb;
-        sincos(6.283185307179586476925286766559 * u1, &sa, &ca);
-        sincos(6.283185307179586476925286766559 * u3, &sb, &cb);
-        z[0] = ra * ca;
-        z[1] = ra * sa;
-        z[2] = rb * cb;
-    }
-};
-
-template <>
-struct BoxMuller<float> {
-    __device__ static void gauss3(U4 x, float z[3])
-    {
-        // uniforms formed in double (exact), transcendental part in float
-        const double s = 1.0 / 4294967296.0;
-        const float u0 = static_cast<float>((static_cast<double>(x.x) + 0.5) * s);
-        const float u1 = static_cast<float>((static_cast<double>(x.y) + 0.5) * s);
-        const float u2 = static_cast<float>((static_cast<double>(x.z) + 0.5) * s);
-        const float u3 = static_cast<float>((static_cast<double>(x.w) + 0.5) * s);
-        const float ra = sqrtf(-2.0f * logf(u0)), rb = sqrtf(-2.0f * logf(u2));
-        float sa, ca, sb, cb;
-        sincosf(6.28318530717958647692f * u1, &sa, &ca);
-        sincosf(6.28318530717958647692f * u3, &sb, &cb);
-        z[0] = ra * ca;
-        z[1] = ra * sa;
-        z[2] = rb * cb;
-    }
-};
-
-// ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void latch(int *flags, long long *flag_step, int code, long long step)
-{
-    if (atomicCAS(flags, 0, code) == 0) *flag_step = step;
-}
 
 template <typename T>
 __global__ void k_zero_work(T *p, int64_t n)
@@ -125,13 +47,16 @@ __global__ void k_zero_work(T *p, int64_t n)
 //   Dneg = -(1/dt) sum_{m=1}^{M-1} K^s_m dR_{n-m}
 //   Y    = g_0 V + (1/dt) sum_{m=1}^{M-1} g_m dR_{n-m}
 // in blocks of HB steps.  For step n = n0 + j of the block starting at n0,
-// the lags m > j reach only displacements from before n0, which the ring
-// already holds when the block starts; for all j at once these sums are one
-// product (the filter bank's kernel on the matrix cores, ROLE 1):
-//   Uh[j][0] = sum_{m=j+1}^{M-1} K^s_m dR_{n0+j-m},  Uh[j][1] likewise with g_m,
-// which reads the ring once per block instead of once per step.  Each step
-// then adds its lags m <= j (the block's own displacements) directly.  The
-// sums are those of the definition, taken in another order.
+// the lags m > j + HB reach only displacements from before the block before
+// (t < n0 - HB); for all j at once these sums are one product (the filter
+// bank's kernel on the matrix cores, ROLE 1):
+//   Uh[j][0] = sum_{m=j+HB+1}^{M-1} K^s_m dR_{n0+j-m},  Uh[j][1] likewise with g_m,
+// which the steps of the block before compute, each 1/HB of it (a slice of
+// the channels and a split of the window, the splits' partial sums kept
+// apart), so that every step does the same work and the ring is read once
+// per block instead of once per step.  Each step then adds the splits and
+// its lags m <= j + HB directly.  The sums are those of the definition,
+// taken in another order.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Vec4;
@@ -165,18 +90,24 @@ __global__ __launch_bounds__(256) void k_history_step(const T *__restrict__ ring
     const int j = static_cast<int>(step % hb);
     T d[4] = {T(0), T(0), T(0), T(0)}, h[4] = {T(0), T(0), T(0), T(0)};
     if (nslots > 0) {  // no history (m_max = 1): no block sums either
-        const auto ud = load4<T>(Uh + (2 * static_cast<int64_t>(j)) * n3 + e0);
-        const auto uh = load4<T>(Uh + (2 * static_cast<int64_t>(j) + 1) * n3 + e0);
-        d[0] = ud.x;
-        d[1] = ud.y;
-        d[2] = ud.z;
-        d[3] = ud.w;
-        h[0] = uh.x;
-        h[1] = uh.y;
-        h[2] = uh.z;
-        h[3] = uh.w;
+        // the kHistSplit partial sums of the block's product (parity of the block)
+        const T *ub = Uh + ((step / hb) & 1) * kHistSplit * (2 * static_cast<int64_t>(hb)) * n3;
+#pragma unroll
+        for (int q = 0; q < kHistSplit; ++q) {
+            const T *uq = ub + q * (2 * static_cast<int64_t>(hb)) * n3;
+            const auto ud = load4<T>(uq + (2 * static_cast<int64_t>(j)) * n3 + e0);
+            const auto uh = load4<T>(uq + (2 * static_cast<int64_t>(j) + 1) * n3 + e0);
+            d[0] += ud.x;
+            d[1] += ud.y;
+            d[2] += ud.z;
+            d[3] += ud.w;
+            h[0] += uh.x;
+            h[1] += uh.y;
+            h[2] += uh.z;
+            h[3] += uh.w;
+        }
     }
-    const int mm = min(j, nslots);
+    const int mm = min(j + hb, nslots);
     for (int m = 1; m <= mm; ++m) {
         long long t = (step - m) % nslots;
         if (t < 0) t += nslots;
@@ -223,11 +154,6 @@ static hipError_t history_t(const Dev &d, hipStream_t st)
 // (taps zero-padded to RC rows, window cut where the taps fall below the
 // noise tolerance).  Output U[b][q][3][S].
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int ring_slot(long long t, int len)
-{
-    long long m = t % len;
-    return static_cast<int>(m < 0 ? m + len : m);
-}
 
 template <typename T>
 __global__ void k_white_ring(int64_t n, int64_t S, uint64_t seed, const long long *__restrict__ d_step, int mode,
@@ -240,13 +166,13 @@ __global__ void k_white_ring(int64_t n, int64_t S, uint64_t seed, const long lon
     const int y = blockIdx.y;
     long long t;
     if (mode == 0) {
-        t = cur + half + bf - 1;
+        t = cur + half + 2 * bf - 1;
     } else if (mode == 1) {
-        if (y >= len) return;
+        if (y >= 2 * half + bf) return;
         t = n0 - half + y;
     } else {
-        if (y >= cur - n0) return;
-        t = n0 + half + bf + y;
+        t = n0 + bf - half + y;
+        if (t > cur + half + 2 * bf - 2) return;
     }
     T w[3];
     BoxMuller<T>::gauss3(philox_at(seed, static_cast<uint32_t>(i), t, 0u), w);
@@ -256,288 +182,25 @@ __global__ void k_white_ring(int64_t n, int64_t S, uint64_t seed, const long lon
     dst[2 * S + i] = w[2];
 }
 
-// FP32 filter bank on the matrix cores.  For the block of steps starting at
-// n0 the outputs are a product of two matrices:
-//   U[b][q][m] = sum_k Ash[k][(b,q)] X[k][m],
-//   X[k][m]    = W at window step k (ring slot of n0 - half + k), channel m
-//                (m = component * S + particle), k < span = P + BF - 1,
-//   Ash[k][(b,q)] = A[k - b][q] for 0 <= k - b < P, else 0.
-// Each wave owns 64 channels and all BF*RC <= 64 rows (b,q): four 32x32
-// accumulator tiles of v_mfma_f32_32x32x2f32, which takes two k per
-// instruction (lanes 0-31 the first, 32-63 the second).  The channel operand
-// is a 128-byte segment of one ring slice per half-wave; the tap operand
-// comes from the taps staged in LDS in chunks of kFirChunk window steps.  The
-// ring loads run two batches of kFirUnroll k-pairs ahead; past the window they
-// read other (finite) ring slices, which meet zero taps.
-// The taps come zero-padded (see kFirChunk): row t + bf - 1 holds A[t], so
-// a chunk's rows are one contiguous copy.
-typedef float fir_v16f __attribute__((ext_vector_type(16)));
-constexpr int kFirMfmaThreads = 256;  // four waves, 256 channels
-constexpr int kFirUnroll = 8;         // MFMA k-pairs per batch
-constexpr int kFirStageIt = ((kFirChunk + kMaxFirBlock - 1) * kMaxRank / 2 + kFirMfmaThreads - 1) / kFirMfmaThreads;
 
 template <int ROLE>
 __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t S, int bf, int rc, int offset,
                                                               int span, int len, const float *__restrict__ A,
                                                               const float *__restrict__ W,
                                                               const long long *__restrict__ d_step,
-                                                              float *__restrict__ U, int force)
+                                                              float *__restrict__ U, FirPart part)
 {
-    __shared__ __align__(16) float taps[(kFirChunk + kMaxFirBlock - 1) * kMaxRank];
-    const long long cur = *d_step;
-    if (!force && cur % bf != 0) return;
-    const long long n0 = cur - cur % bf;
-    const int64_t M = 3 * S;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int64_t m0 = (static_cast<int64_t>(blockIdx.x) * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
-    const bool wlive = m0 < M;  // a wave past the channels only joins the staging
-    const int hi = lane >> 5, lo = lane & 31;
-    // this lane's tap rows i = 32 rt + lo, i.e. (b, q) = (i / rc, i % rc)
-    // (rows past bf * rc read a valid tap and multiply it by 0, so the LDS
-    // reads carry no branch)
-    int trow[2];
-    float tmul[2];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        const int i = 32 * rt + lo;
-        const bool valid = i < bf * rc;
-        tmul[rt] = valid ? 1.f : 0.f;
-        trow[rt] = (bf - 1 - (valid ? i / rc : 0)) * rc + (valid ? i % rc : 0);
-    }
-    // channel columns of this lane (clamped for a dead wave: never stored)
-    const int64_t c0 = wlive ? m0 + lo : lo;
-    fir_v16f acc[2][2];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = fir_v16f{};
-    // ring slot of this lane's window step k = 2 j + hi, and its channel c0
-    // there (c1 = c0 + 32 follows at a fixed offset)
-    int sl = ring_slot(n0 - offset + hi, len);
-    const float *src = W + static_cast<int64_t>(sl) * M + c0;
-    const int64_t wrap = static_cast<int64_t>(len) * M;
-    // window step of the next load.  The history's taps reach past the span
-    // (ROLE 1): its steps there count zero (the loads read other, finite
-    // ring slices and are multiplied by 0, which keeps them unconditional);
-    // the noise filters' taps are zero there already (ROLE 0)
-    [[maybe_unused]] int kw = hi;
-    float xa[kFirUnroll][2], xn[kFirUnroll][2], xm[kFirUnroll][2];
-    auto load_batch = [&](float (&dst)[kFirUnroll][2]) {
-#pragma unroll
-        for (int u = 0; u < kFirUnroll; ++u) {
-            if constexpr (ROLE == 1) {
-                const float in = kw < span ? 1.f : 0.f;
-                dst[u][0] = __builtin_nontemporal_load(src) * in;
-                dst[u][1] = __builtin_nontemporal_load(src + 32) * in;
-                kw += 2;
-            } else {
-                dst[u][0] = __builtin_nontemporal_load(src);
-                dst[u][1] = __builtin_nontemporal_load(src + 32);
-            }
-            sl += 2;
-            src += 2 * M;
-            if constexpr (ROLE == 1) {
-                while (sl >= len) {  // the history ring (m_max - 1 slices) can be shorter than 2
-                    sl -= len;
-                    src -= wrap;
-                }
-            } else if (sl >= len) {  // the white-noise ring holds at least 4 slices
-                sl -= len;
-                src -= wrap;
-            }
-        }
-    };
-    load_batch(xa);
-    load_batch(xn);
-    for (int k0 = 0; k0 < span; k0 += kFirChunk) {
-        // taps of window steps [k0, k0 + kFirChunk) for every b: padded rows
-        // k0 .. k0 + kFirChunk + bf - 2 (t = k0 - (bf - 1) ..), loaded before
-        // the barrier that retires the previous chunk
-        const int nel = (kFirChunk + bf - 1) * rc / 2;  // float2 (rc is even)
-        const float2 *srcA = reinterpret_cast<const float2 *>(A + static_cast<int64_t>(k0) * rc);
-        float2 tv[kFirStageIt];
-#pragma unroll
-        for (int j = 0; j < kFirStageIt; ++j) {
-            const int e = tid + j * kFirMfmaThreads;
-            tv[j] = e < nel ? srcA[e] : make_float2(0.f, 0.f);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kFirStageIt; ++j) {
-            const int e = tid + j * kFirMfmaThreads;
-            if (e < nel) reinterpret_cast<float2 *>(taps)[e] = tv[j];
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int kk = 0; kk < kFirChunk; kk += 2 * kFirUnroll) {
-            load_batch(xm);  // two batches ahead
-#pragma unroll
-            for (int u = 0; u < kFirUnroll; ++u) {
-                const int kl = kk + 2 * u + hi;  // window step k0 + kl of this lane
-                float av[2];
-#pragma unroll
-                for (int rt = 0; rt < 2; ++rt) av[rt] = taps[kl * rc + trow[rt]] * tmul[rt];
-#pragma unroll
-                for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                    for (int ct = 0; ct < 2; ++ct)
-                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rt], xa[u][ct], acc[rt][ct], 0, 0, 0);
-            }
-#pragma unroll
-            for (int u = 0; u < kFirUnroll; ++u) {
-                xa[u][0] = xn[u][0];
-                xa[u][1] = xn[u][1];
-                xn[u][0] = xm[u][0];
-                xn[u][1] = xm[u][1];
-            }
-        }
-    }
-    if (!wlive) return;
-    // accumulator element v of tile (rt, ct): row i = 32 rt + (v % 4) + 4 hi
-    // + 8 (v / 4), channel m0 + 32 ct + lo
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-        const int64_t m = m0 + 32 * ct + lo;
-        const int64_t p = m - (m >= S ? S : 0) - (m >= 2 * S ? S : 0);  // particle of channel m
-        if (p >= n) continue;
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int i = 32 * rt + (v % 4) + 4 * hi + 8 * (v / 4);
-                if (i < bf * rc) U[static_cast<int64_t>(i) * M + m] = acc[rt][ct][v];
-            }
-    }
+    fir_mfma_body<ROLE>(n, S, bf, rc, offset, span, len, A, W, d_step, U, part, blockIdx.x);
 }
-
-// FP64 filter bank on the matrix cores, the same product with
-// v_mfma_f64_16x16x4f64 (four k per instruction, lanes 16 g .. 16 g + 15
-// taking k = g): each wave owns 64 channels (four 16-wide column tiles) and
-// the bf * rc <= 32 rows (two 16-row tiles); accumulator element v of a tile
-// is row 4 v + g, column lane % 16.  Taps are staged in chunks of
-// kFirChunk64 window steps.
-typedef double fir_v4d __attribute__((ext_vector_type(4)));
-constexpr int kFirChunk64 = 64;
-constexpr int kFirUnroll64 = 4;  // MFMA k-quads per batch
-constexpr int kFirStageIt64 =
-    ((kFirChunk64 + kMaxFirBlock - 1) * kMaxRank / 2 + kFirMfmaThreads - 1) / kFirMfmaThreads;
 
 template <int ROLE>
 __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma64(int64_t n, int64_t S, int bf, int rc, int offset,
                                                                 int span, int len, const double *__restrict__ A,
                                                                 const double *__restrict__ W,
                                                                 const long long *__restrict__ d_step,
-                                                                double *__restrict__ U, int force)
+                                                                double *__restrict__ U, FirPart part)
 {
-    __shared__ __align__(16) double taps[(kFirChunk64 + kMaxFirBlock - 1) * kMaxRank];
-    const long long cur = *d_step;
-    if (!force && cur % bf != 0) return;
-    const long long n0 = cur - cur % bf;
-    const int64_t M = 3 * S;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int64_t m0 = (static_cast<int64_t>(blockIdx.x) * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
-    const bool wlive = m0 < M;
-    const int g = lane >> 4, lo = lane & 15;
-    int trow[2];
-    double tmul[2];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        const int i = 16 * rt + lo;
-        const bool valid = i < bf * rc;
-        tmul[rt] = valid ? 1.0 : 0.0;
-        trow[rt] = (bf - 1 - (valid ? i / rc : 0)) * rc + (valid ? i % rc : 0);
-    }
-    const int64_t c0 = wlive ? m0 + lo : lo;
-    fir_v4d acc[2][4];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = fir_v4d{};
-    // ring slot of this lane's window step k = 4 j + g
-    int sl = ring_slot(n0 - offset + g, len);
-    const double *src = W + static_cast<int64_t>(sl) * M + c0;
-    const int64_t wrap = static_cast<int64_t>(len) * M;
-    // window step of the next load (ROLE 1, the history: past the span
-    // multiplied by 0, as in the FP32 kernel)
-    [[maybe_unused]] int kw = g;
-    double xa[kFirUnroll64][4], xn[kFirUnroll64][4];
-    auto load_batch = [&](double (&dst)[kFirUnroll64][4]) {
-#pragma unroll
-        for (int u = 0; u < kFirUnroll64; ++u) {
-            if constexpr (ROLE == 1) {
-                const double in = kw < span ? 1.0 : 0.0;
-#pragma unroll
-                for (int ct = 0; ct < 4; ++ct) dst[u][ct] = __builtin_nontemporal_load(src + 16 * ct) * in;
-                kw += 4;
-            } else {
-#pragma unroll
-                for (int ct = 0; ct < 4; ++ct) dst[u][ct] = __builtin_nontemporal_load(src + 16 * ct);
-            }
-            sl += 4;
-            src += 4 * M;
-            if constexpr (ROLE == 1) {
-                while (sl >= len) {  // the history ring (m_max - 1 slices) can be shorter than 4
-                    sl -= len;
-                    src -= wrap;
-                }
-            } else if (sl >= len) {  // the white-noise ring holds at least 4 slices
-                sl -= len;
-                src -= wrap;
-            }
-        }
-    };
-    load_batch(xa);
-    for (int k0 = 0; k0 < span; k0 += kFirChunk64) {
-        const int nel = (kFirChunk64 + bf - 1) * rc / 2;  // double2 (rc is even)
-        const double2 *srcA = reinterpret_cast<const double2 *>(A + static_cast<int64_t>(k0) * rc);
-        double2 tv[kFirStageIt64];
-#pragma unroll
-        for (int j = 0; j < kFirStageIt64; ++j) {
-            const int e = tid + j * kFirMfmaThreads;
-            tv[j] = e < nel ? srcA[e] : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kFirStageIt64; ++j) {
-            const int e = tid + j * kFirMfmaThreads;
-            if (e < nel) reinterpret_cast<double2 *>(taps)[e] = tv[j];
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int kk = 0; kk < kFirChunk64; kk += 4 * kFirUnroll64) {
-            load_batch(xn);
-#pragma unroll
-            for (int u = 0; u < kFirUnroll64; ++u) {
-                const int kl = kk + 4 * u + g;
-                double av[2];
-#pragma unroll
-                for (int rt = 0; rt < 2; ++rt) av[rt] = taps[kl * rc + trow[rt]] * tmul[rt];
-#pragma unroll
-                for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                    for (int ct = 0; ct < 4; ++ct)
-                        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], xa[u][ct], acc[rt][ct], 0, 0, 0);
-            }
-#pragma unroll
-            for (int u = 0; u < kFirUnroll64; ++u)
-#pragma unroll
-                for (int ct = 0; ct < 4; ++ct) xa[u][ct] = xn[u][ct];
-        }
-    }
-    if (!wlive) return;
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const int64_t m = m0 + 16 * ct + lo;
-        const int64_t p = m - (m >= S ? S : 0) - (m >= 2 * S ? S : 0);
-        if (p >= n) continue;
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = 16 * rt + 4 * v + g;
-                if (i < bf * rc) U[static_cast<int64_t>(i) * M + m] = acc[rt][ct][v];
-            }
-    }
+    fir_mfma64_body<ROLE>(n, S, bf, rc, offset, span, len, A, W, d_step, U, part, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -676,13 +339,37 @@ __device__ int sturm_count(const double *al, const double *be, int k, double x)
     return cnt;
 }
 
-// Extreme Ritz values by bisection; checks them against the noise interval
-// and the singular points; result[0] = theta_min, result[1] = theta_max.
-__global__ void k_lanczos_judge(const double *al, const double *be, int k, double lo, double hi, double sing_lo,
-                                double sing_hi, double *result, int *flags, long long *flag_step,
-                                const long long *d_step)
+// Extreme Ritz values of the tridiagonal (al, be) by multisection on one
+// wave: each round the 64 lanes take the Sturm counts at 64 points inside the
+// bracket and keep the sub-interval where the count first reaches the target
+// (the bracket shrinks 65-fold per round, down to the rounding of the points).
+// Checks them against the noise interval and the singular points:
+// result[0] = theta_min, result[1] = theta_max.  A smallest Ritz value below
+// lo_t (the tight plan's lower end) retires the tight plan for good (until a
+// new state is written).
+__device__ double ritz_extreme(const double *al, const double *be, int kk, double a, double b, int target)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int lane = threadIdx.x;
+    for (int round = 0; round < 40; ++round) {
+        const double x = a + (b - a) * (static_cast<double>(lane + 1) / 65.0);
+        const bool hit = sturm_count(al, be, kk, x) >= target;
+        const unsigned long long m = __ballot(hit);
+        // first point at or past the target count (none: the last sub-interval)
+        const int f = m ? __ffsll(static_cast<long long>(m)) - 1 : 64;
+        const double na = f == 0 ? a : a + (b - a) * (static_cast<double>(f) / 65.0);
+        const double nb = f == 64 ? b : a + (b - a) * (static_cast<double>(f + 1) / 65.0);
+        if (!(nb - na < b - a)) break;  // no further progress in double precision
+        a = na;
+        b = nb;
+    }
+    return 0.5 * (a + b);
+}
+
+__global__ __launch_bounds__(64) void k_lanczos_judge(const double *al, const double *be, int k, double lo,
+                                                      double hi, double sing_lo, double sing_hi, double lo_t,
+                                                      double *result, int *flags, long long *flag_step,
+                                                      const long long *d_step, int *retired)
+{
     // effective dimension: stop at the first (near) breakdown
     int kk = k;
     for (int i = 0; i < k - 1; ++i)
@@ -693,21 +380,12 @@ __global__ void k_lanczos_judge(const double *al, const double *be, int k, doubl
         gl = fmin(gl, al[i] - r);
         gh = fmax(gh, al[i] + r);
     }
-    double a = gl, b = gh;
-    for (int it = 0; it < 200; ++it) {  // smallest eigenvalue
-        const double mid = 0.5 * (a + b);
-        if (sturm_count(al, be, kk, mid) >= 1) b = mid; else a = mid;
-    }
-    const double tmin = 0.5 * (a + b);
-    a = gl;
-    b = gh;
-    for (int it = 0; it < 200; ++it) {  // largest eigenvalue
-        const double mid = 0.5 * (a + b);
-        if (sturm_count(al, be, kk, mid) >= kk) b = mid; else a = mid;
-    }
-    const double tmax = 0.5 * (a + b);
+    const double tmin = ritz_extreme(al, be, kk, gl, gh, 1);
+    const double tmax = ritz_extreme(al, be, kk, gl, gh, kk);
+    if (threadIdx.x != 0) return;
     result[0] = tmin;
     result[1] = tmax;
+    if (tmin < lo_t) *retired = 1;
     if (!(tmin > sing_lo) || !(tmax < sing_hi)) latch(flags, flag_step, GLD_ERR_NOT_PD, *d_step);
     else if (tmin < lo || tmax > hi) latch(flags, flag_step, GLD_ERR_INTERVAL, *d_step);
 }
@@ -787,7 +465,7 @@ int fir_block_for(int fp64, int rcap)
 
 hipError_t launch_white_ring(const Dev &d, int mode, hipStream_t st)
 {
-    const unsigned gy = mode == 0 ? 1u : (mode == 1 ? static_cast<unsigned>(d.wring_len) : static_cast<unsigned>(d.fir_block));
+    const unsigned gy = mode == 0 ? 1u : static_cast<unsigned>(2 * d.fir_half + 2 * d.fir_block);
     const dim3 grid(blocks(d.n, 256), gy);
     if (d.fp64)
         k_white_ring<double><<<grid, 256, 0, st>>>(d.n, d.S, d.seed, d.d_step, mode, d.fir_block, d.fir_half,
@@ -798,24 +476,29 @@ hipError_t launch_white_ring(const Dev &d, int mode, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_fir(const Dev &d, int force, hipStream_t st)
+hipError_t launch_fir(const Dev &d, int mode, hipStream_t st)
 {
     // block * rcap <= 64 (FP32) or <= 32 (FP64) for every padded rank: the
     // rows of one pair of MFMA tiles
     const int64_t M = 3 * d.S;
-    const unsigned grid = static_cast<unsigned>((M + kFirMfmaThreads - 1) / kFirMfmaThreads);
+    FirPart part;
+    part.ustride = static_cast<int64_t>(fir_rows(d.fp64)) * M;
+    part.ahead = mode == 1 ? 0 : 1;
+    part.nslice = mode == 0 ? d.fir_block : 1;
+    part.cs = mode == 0 ? (M / d.fir_block + 1 + kFirMfmaThreads - 1) / kFirMfmaThreads * kFirMfmaThreads : M;
+    const unsigned grid = static_cast<unsigned>((part.cs + kFirMfmaThreads - 1) / kFirMfmaThreads);
     // window: t = n0 - half .. n0 + bf - 1 + half (2 half + 1 taps, bf outputs)
     const int span = 2 * d.fir_half + d.fir_block;
     if (d.fp64)
         k_fir_mfma64<0><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, span,
                                                           d.wring_len, static_cast<const double *>(d.Afilt),
                                                           static_cast<const double *>(d.wring), d.d_step,
-                                                          static_cast<double *>(d.U), force);
+                                                          static_cast<double *>(d.U), part);
     else
         k_fir_mfma<0><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, span,
                                                         d.wring_len, static_cast<const float *>(d.Afilt),
                                                         static_cast<const float *>(d.wring), d.d_step,
-                                                        static_cast<float *>(d.U), force);
+                                                        static_cast<float *>(d.U), part);
     return hipGetLastError();
 }
 
@@ -843,24 +526,37 @@ hipError_t launch_take_window(const Dev &d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_history_block(const Dev &d, int force, hipStream_t st)
+hipError_t launch_history_block(const Dev &d, int mode, hipStream_t st)
 {
     if (d.nslots == 0) return hipSuccess;
-    // the M - 1 ring slices before the block (t = n0 - (M - 1) .. n0 - 1)
-    // against the taps (K^s_m, g_m), m = M - 1 .. 1; HB steps of output
+    // the lags m > j + HB of step n0 + j of a block: the ring slices
+    // t = n0 - (M - 1) .. n0 - HB - 1 (span nslots - HB) against the taps
+    // (K^s_m, g_m), m = M - 1 .. 1, for the HB steps of the block
     const int64_t M = 3 * d.S;
-    const unsigned grid = static_cast<unsigned>((M + kFirMfmaThreads - 1) / kFirMfmaThreads);
-    if (d.fp64)
-        k_fir_mfma64<1><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.hist_block, 2, d.nslots, d.nslots, d.nslots,
-                                                          static_cast<const double *>(d.hist_taps),
-                                                          static_cast<const double *>(d.ring), d.d_step,
-                                                          static_cast<double *>(d.Uh), force);
-    else
-        k_fir_mfma<1><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.hist_block, 2, d.nslots, d.nslots, d.nslots,
-                                                        static_cast<const float *>(d.hist_taps),
-                                                        static_cast<const float *>(d.ring), d.d_step,
-                                                        static_cast<float *>(d.Uh), force);
-    return hipGetLastError();
+    const int span = std::max(0, d.nslots - d.hist_block);
+    FirPart part;
+    part.ustride = static_cast<int64_t>(2 * d.hist_block) * M;
+    part.ahead = mode == 1 ? 0 : 1;
+    part.nsplit = kHistSplit;
+    part.nslice = mode == 0 ? d.hist_block / kHistSplit : 1;
+    part.cs = mode == 0 ? (M / part.nslice + 1 + kFirMfmaThreads - 1) / kFirMfmaThreads * kFirMfmaThreads : M;
+    const unsigned grid = static_cast<unsigned>((part.cs + kFirMfmaThreads - 1) / kFirMfmaThreads);
+    for (int q = 0; q < (mode == 0 ? 1 : kHistSplit); ++q) {
+        part.split = q;
+        if (d.fp64)
+            k_fir_mfma64<1><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.hist_block, 2, d.nslots, span, d.nslots,
+                                                              static_cast<const double *>(d.hist_taps),
+                                                              static_cast<const double *>(d.ring), d.d_step,
+                                                              static_cast<double *>(d.Uh), part);
+        else
+            k_fir_mfma<1><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.hist_block, 2, d.nslots, span, d.nslots,
+                                                            static_cast<const float *>(d.hist_taps),
+                                                            static_cast<const float *>(d.ring), d.d_step,
+                                                            static_cast<float *>(d.Uh), part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_update_r(const Dev &d, hipStream_t st)
@@ -908,14 +604,14 @@ hipError_t spectrum_check_t(const Dev &d, hipStream_t st, int iters, double lo, 
     const int64_t n = d.n, m = 4 * n;  // sorted T4 vectors, the 4th entry stays zero
     T *q[3] = {static_cast<T *>(d.lq[0]), static_cast<T *>(d.lq[1]), static_cast<T *>(d.lq[2])};
     T *w = static_cast<T *>(d.lw);
-    double *al = d.lab, *be = d.lab + kCheckIters, *res = d.lab + 2 * kCheckIters;
+    double *al = d.lab, *be = d.lab + kMaxCheckIters, *res = d.lab + 2 * kMaxCheckIters;
     const unsigned nbd = static_cast<unsigned>(std::min<int64_t>(kPartials, blocks(m, 256)));
     const unsigned ne = blocks(m, 256);
     k_lanczos_start<T><<<blocks(n, 256), 256, 0, st>>>(n, d.seed, salt, q[0]);
     k_dot<T><<<nbd, 256, 0, st>>>(m, q[0], q[0], d.partial);
     k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, res + 2, 1);
     k_lanczos_normalize<T><<<ne, 256, 0, st>>>(m, q[0], res + 2);
-    iters = std::min(iters, kCheckIters);
+    iters = std::min(iters, kMaxCheckIters);
     for (int k = 0; k < iters; ++k) {
         T *qc = q[k % 3], *qp = q[(k + 2) % 3], *qn = q[(k + 1) % 3];
         hipError_t e = launch_spmv(d, st, 1.0, 0.0, qc, 0.0, nullptr, nullptr, 0, w, nullptr, nullptr);
@@ -927,8 +623,8 @@ hipError_t spectrum_check_t(const Dev &d, hipStream_t st, int iters, double lo, 
         k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, be + k, 1);
         k_lanczos_scale<T><<<ne, 256, 0, st>>>(m, w, be + k, qn);
     }
-    k_lanczos_judge<<<1, 1, 0, st>>>(al, be, iters, lo, hi, sing_lo, sing_hi, res, d.d_flags, d.d_flag_step,
-                                     d.d_step);
+    k_lanczos_judge<<<1, 64, 0, st>>>(al, be, iters, lo, hi, sing_lo, sing_hi, d.lam_lo_tight, res, d.d_flags,
+                                      d.d_flag_step, d.d_step, d.d_retired);
     return hipGetLastError();
 }
 }  // namespace

@@ -1045,12 +1045,13 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
 // ---------------------------------------------------------------------------
 // sorted copies of the inputs of the pair mat-vecs:
 //   ys[s]    = Y[p]                       (dissipative input)
-//   us[q][s] = U[step % block][q][p]      (filter outputs of this step)
+//   us[q][s] = U[step % block][q][p]      (filter outputs of this step, in the
+//                                          buffer of its block's parity)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_permute(int64_t n, int64_t S, const int *__restrict__ sorted, const T *__restrict__ Y,
                           typename V4<T>::t *__restrict__ ys, const T *__restrict__ U, int r, int rcap, int block,
-                          const long long *__restrict__ d_step, typename V4<T>::t *__restrict__ us)
+                          int urows, const long long *__restrict__ d_step, typename V4<T>::t *__restrict__ us)
 {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -1062,8 +1063,9 @@ __global__ void k_permute(int64_t n, int64_t S, const int *__restrict__ sorted, 
     v.w = T(0);
     ys[s] = v;
     if (r > 0) {
-        const int bi = static_cast<int>(*d_step % block);
-        const T *u = U + static_cast<int64_t>(bi) * rcap * 3 * S;
+        const long long cur = *d_step;
+        const int bi = static_cast<int>(cur % block);
+        const T *u = U + ((cur / block) & 1) * urows * 3 * S + static_cast<int64_t>(bi) * rcap * 3 * S;
         for (int q = 0; q < r; ++q) {
             const T *uq = u + static_cast<int64_t>(q) * 3 * S;
             typename V4<T>::t o;
@@ -1491,13 +1493,14 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
 // the block whose outputs U holds).
 template <typename T>
 __global__ void k_permute_window(int64_t n, int64_t S, const int *__restrict__ sorted, const T *__restrict__ U,
-                                 int r, int rcap, int block, int W, const long long *__restrict__ d_step,
+                                 int r, int rcap, int block, int urows, int W, const long long *__restrict__ d_step,
                                  typename V4<T>::t *__restrict__ usw)
 {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int p = sorted[s];
     const long long n0 = *d_step - *d_step % W;
+    U += ((n0 / block) & 1) * urows * 3 * S;
     for (int m = 0; m < W; ++m) {
         const int bi = static_cast<int>((n0 + m) % block);
         for (int q = 0; q < r; ++q) {
@@ -1736,8 +1739,9 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
 // the terms k >= Ka are skipped.
 // The tight plan's lower end lies closer to the spectrum than the wide
 // plan's: it also needs the smallest Ritz value of the last spectrum check
-// (theta_min) at least lo_t; once a check finds it below, every step takes
-// the wide plan, whose lower end the check guards as before.
+// (theta_min) at least lo_t; once a check finds it below, the retired flag
+// stays set and every step takes the wide plan (until a new state is
+// written), whose lower end the check guards as before.
 struct ChainSel {
     int Kw, Kt;           // terms of the wide and the tight plan
     float lam_t;          // largest row-sum bound for the tight plan
@@ -1746,10 +1750,11 @@ struct ChainSel {
 };
 
 __global__ void k_cheb_select(ChainSel c, const unsigned *__restrict__ rowmax, const double *__restrict__ theta,
-                              ChainStep *__restrict__ out, unsigned long long *__restrict__ tight_steps)
+                              const int *__restrict__ retired, ChainStep *__restrict__ out,
+                              unsigned long long *__restrict__ tight_steps)
 {
     const float g = __uint_as_float(*rowmax);
-    const bool tight = c.Kt > 0 && g <= c.lam_t && theta[0] >= c.lo_t;
+    const bool tight = c.Kt > 0 && g <= c.lam_t && theta[0] >= c.lo_t && *retired == 0;
     const int Ka = tight ? c.Kt : c.Kw;
     const double al = tight ? c.at : c.aw, be = tight ? c.bt : c.bw;
     for (int k = threadIdx.x; k < c.Kw; k += blockDim.x) {
@@ -1981,11 +1986,12 @@ hipError_t launch_permute(const Dev &d, hipStream_t st, int r)
         k_permute<double><<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.S, d.cell_sorted, static_cast<const double *>(d.Y),
                                                             static_cast<double4 *>(d.ys),
                                                             static_cast<const double *>(d.U), r, d.fir_rcap,
-                                                            d.fir_block, d.d_step, static_cast<double4 *>(d.us));
+                                                            d.fir_block, fir_rows(1), d.d_step,
+                                                            static_cast<double4 *>(d.us));
     else
         k_permute<float><<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.S, d.cell_sorted, static_cast<const float *>(d.Y),
                                                            static_cast<float4 *>(d.ys), static_cast<const float *>(d.U),
-                                                           r, d.fir_rcap, d.fir_block, d.d_step,
+                                                           r, d.fir_rcap, d.fir_block, fir_rows(0), d.d_step,
                                                            static_cast<float4 *>(d.us));
     return hipGetLastError();
 }
@@ -2125,8 +2131,8 @@ hipError_t launch_cheb_select(const Dev &d, hipStream_t st)
     c.bw = d.cheb_ab[1];
     c.at = d.cheb_ab[2];
     c.bt = d.cheb_ab[3];
-    k_cheb_select<<<1, 64, 0, st>>>(c, d.d_rowmax, d.lab + 2 * kCheckIters, static_cast<ChainStep *>(d.chain),
-                                    d.d_tight);
+    k_cheb_select<<<1, 64, 0, st>>>(c, d.d_rowmax, d.lab + 2 * kMaxCheckIters, d.d_retired,
+                                    static_cast<ChainStep *>(d.chain), d.d_tight);
     return hipGetLastError();
 }
 
@@ -2158,12 +2164,12 @@ hipError_t launch_permute_window(const Dev &d, hipStream_t st, int r)
     if (d.fp64)
         k_permute_window<double><<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.S, d.cell_sorted,
                                                                    static_cast<const double *>(d.U), r, d.fir_rcap,
-                                                                   d.fir_block, d.win, d.d_step,
+                                                                   d.fir_block, fir_rows(1), d.win, d.d_step,
                                                                    static_cast<double4 *>(d.usw));
     else
         k_permute_window<float><<<blocks(d.n, 256), 256, 0, st>>>(d.n, d.S, d.cell_sorted,
                                                                   static_cast<const float *>(d.U), r, d.fir_rcap,
-                                                                  d.fir_block, d.win, d.d_step,
+                                                                  d.fir_block, fir_rows(0), d.win, d.d_step,
                                                                   static_cast<float4 *>(d.usw));
     return hipGetLastError();
 }

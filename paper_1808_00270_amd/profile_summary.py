@@ -34,7 +34,7 @@ import sqlite3
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 # the kernels and their launchers (the traffic of a launch depends on these only)
-SOURCES = ["gld_kernels.hip", "gld_pairs.hip", "gld_internal.h"]
+SOURCES = ["gld_kernels.hip", "gld_pairs.hip", "gld_internal.h", "gld_device.h"]
 
 # kernel classes of the step (the names bench.py uses) -> kernel symbol, for
 # the work type T of the precision (F: suffix of the FP64 filter-bank kernel)

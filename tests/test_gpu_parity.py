@@ -37,10 +37,11 @@ def pkg():
     return p
 
 
-def oracle_for(oracle_mod, w, tables=None):
+def oracle_for(oracle_mod, w, tables=None, r_cut_min=0.0):
     k_self, g, wt, r0, dr = tables or w.tables()
     return oracle_mod.Oracle(n=w.n, box=w.box, dt=w.dt, mass=w.mass, kT=w.kT, k_self=k_self,
-                             k_pair=np.outer(wt, g), r0=r0, dr=dr, r_cut=w.r_cut, parallel=w.parallel,
+                             k_pair=np.outer(wt, g), r0=r0, dr=dr, r_cut=w.r_cut, r_cut_min=r_cut_min,
+                             parallel=w.parallel,
                              wca_sigma=w.wca_sigma, wca_eps=w.wca_eps, seed=w.seed, lanczos_tol=1e-13,
                              lanczos_max_iter=400)
 
@@ -83,7 +84,7 @@ def one_step(pkg, oracle_mod, w, fp64, step=5, hist_scale=0.01, seed=11, check_f
     g = s.read_state(history=True)
     info = s.noise_info()
     s.close()
-    o = oracle_for(oracle_mod, w, tables)
+    o = oracle_for(oracle_mod, w, tables, r_cut_min=kw.get("r_cut_min", 0.0))
     Ro, Vo, Ho = R.copy(), V.copy(), hist.copy()
     FC, FD, FR = o.step(step, Ro, Vo, Ho)
     tol = TOL[fp64]
@@ -213,6 +214,35 @@ def test_one_step_mixed_list_index_widths(pkg, oracle_mod, fp64, W):
 
 
 @pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("parallel", [False, True])
+def test_one_step_kernel_frozen_below_r_cut_min(pkg, oracle_mod, fp64, parallel):
+    """A distance grid that starts at r0 = 0.37 (not at 0) and a pair kernel
+    frozen below r_c,min (Sec. III.B).  Isotropic: the rho = 0.5 box, whose
+    six nearest lattice neighbours sit at 1.25 < r_c,min = 1.5.  Parallel (not
+    positive definite at rho = 0.5): the rho = 0.05 lattice, neighbours at
+    2.7 < r_c,min = 3.0.  Every such pair must take w(r_c,min) in the
+    dissipative force, the noise correlation and the noise interval."""
+    if parallel:
+        w, rmin, step = wl.config(1, parallel=True), 3.0, 5
+    else:
+        w, rmin, step = wl.config(3, n=1200, m_max=60), 1.5, 9
+    k_self, g, _, _, _ = w.tables()
+    r0, n_r = 0.37, 400
+    dr = (w.r_cut - r0) / (n_r - 1)
+    wt = wl.pair_weight(r0 + np.arange(n_r) * dr, w.r_cut)
+    wt[-1] = 0.0
+    R, _ = w.initial_state()
+    d = R[:, None, :] - R[None, :, :]
+    d -= w.box * np.round(d / w.box)
+    rr = np.sqrt((d ** 2).sum(-1))
+    below = ((rr < rmin) & (rr > 0)).sum()
+    log(f"    ordered pairs below r_cut_min: {below}")
+    assert below >= w.n
+    one_step(pkg, oracle_mod, w, fp64, step=step, tables=(k_self, g, wt, r0, dr), k_pair_w=wt, r0=r0, dr=dr,
+             r_cut_min=rmin)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
 def test_one_step_no_noise_no_pair(pkg, oracle_mod, fp64):
     w = wl.config(1, kT=0.0)
     one_step(pkg, oracle_mod, w, fp64)
@@ -321,8 +351,10 @@ def test_fp32_mixed_tracks_fp64_over_steps(pkg):
 # --------------------------------------------------------------------------
 
 def test_nonfinite_is_latched_and_poisons(pkg):
+    # no pair memory: two coincident particles would otherwise be refused at
+    # the write (their pair puts the spectrum of P outside the noise interval)
     w = wl.config(1)
-    s = pkg.System.from_workload(w, fp64=True)
+    s = pkg.System.from_workload(w, fp64=True, k_pair_g=None, k_pair_w=None)
     R, V = w.initial_state()
     R[5] = R[4]  # two coincident particles: the WCA force is not finite
     s.write_state(R, V, step=0)
@@ -360,6 +392,11 @@ def test_parallel_tensor_at_high_density_is_not_pd(pkg, oracle_mod):
     with pytest.raises(pkg.GLDError) as e:
         pkg.System.from_workload(w)
     assert e.value.status == pkg._binding.GLD_ERR_NOT_PD
+    # the oracle's Algorithm 1 reaches the same verdict on the same configuration
+    R, _ = w.initial_state()
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_for(oracle_mod, w).noise(0, R)
+    assert e.value.code == oracle_mod.ORC_ERR_NOT_PD
 
 
 def test_kernel_timing_counts(pkg):

@@ -162,3 +162,72 @@ def test_noise_filters_report_not_pd(pkg):
     p, keep = _params(pkg)
     st, info, A, Bm = _filters(pkg, p, -3.0, 5.0, 1e-6)  # singular point near -1.8
     assert st == B.GLD_ERR_NOT_PD
+
+
+def test_general_tables_and_caller_filters_are_validated(pkg):
+    """The general pair table K^p_m(r_b) (Sec. III.A) is accepted in its
+    separable form when it has rank one and refused otherwise; a non-zero
+    distance-dependent self memory Delta K^s (eq. GLD_basic2) is refused by
+    this system type; caller-built noise filters need their interval; the
+    spectrum check's iteration count is bounded."""
+    from paper_1808_00270_amd import workloads as wl
+    B = pkg._binding
+    lib = pkg.lib()
+    d = C.POINTER(C.c_double)
+    nb = C.c_size_t()
+    w = wl.config(1, m_max=30)
+    k_self, g, wt, r0, dr = w.tables()
+    # rank one: the outer product, with the separable pointers cleared
+    K1 = np.ascontiguousarray(np.outer(wt, g))
+    p, keep = _params(pkg, k_pair_g=None, k_pair_w=None)
+    p.k_pair = K1.ctypes.data_as(d)
+    assert lib.gld_workspace_size(C.byref(p), C.byref(nb)) == B.GLD_OK
+    # both forms at once
+    p2, k2 = _params(pkg)
+    p2.k_pair = K1.ctypes.data_as(d)
+    assert lib.gld_workspace_size(C.byref(p2), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    # rank two: refused, with the reason
+    K2 = np.ascontiguousarray(K1 + np.outer(np.linspace(1, 0, len(wt)), np.exp(-np.arange(30) * 0.3)) * 1e-3)
+    p3, k3 = _params(pkg, k_pair_g=None, k_pair_w=None)
+    p3.k_pair = K2.ctypes.data_as(d)
+    assert lib.gld_workspace_size(C.byref(p3), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    assert b"non-separable" in lib.gld_last_error()
+    # the separable form's filters equal those of the general rank-one table
+    # (m_max = 60: shorter truncations of these kernels have negative spectra)
+    w60 = wl.config(1, m_max=60)
+    _, g60, wt60, _, _ = w60.tables()
+    K60 = np.ascontiguousarray(np.outer(wt60, g60))
+    pa, ka = _params(pkg, m_max=60)
+    pb, kb = _params(pkg, m_max=60, k_pair_g=None, k_pair_w=None)
+    pb.k_pair = K60.ctypes.data_as(d)
+    st_a, info_a, A_a, B_a = _filters(pkg, pa, -1.0, 5.0, 1e-8)
+    st_b, info_b, A_b, B_b = _filters(pkg, pb, -1.0, 5.0, 1e-8)
+    assert st_a == st_b == B.GLD_OK and info_a.cheb_terms == info_b.cheb_terms and info_a.rank == info_b.rank
+    # the same filters up to the rounding of g_m = K[b*][m] / K[b*][m*]
+    assert np.allclose(A_a, A_b, rtol=0, atol=1e-12 * np.abs(A_a).max())
+    # Delta K^s: zero is accepted, non-zero refused
+    Z = np.zeros((len(wt), 30))
+    p4, k4 = _params(pkg)
+    p4.dk_self = Z.ctypes.data_as(d)
+    assert lib.gld_workspace_size(C.byref(p4), C.byref(nb)) == B.GLD_OK
+    Z2 = Z.copy()
+    Z2[3, 2] = 0.1
+    p4.dk_self = Z2.ctypes.data_as(d)
+    assert lib.gld_workspace_size(C.byref(p4), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    # caller-built filters: both arrays, a rank and term count, and the interval
+    a = np.zeros(7 * 59)
+    b = np.zeros(20 * 7)
+    p5, k5 = _params(pkg)
+    p5.noise_a = a.ctypes.data_as(d)
+    assert lib.gld_workspace_size(C.byref(p5), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    p5.noise_b = b.ctypes.data_as(d)
+    p5.noise_rank, p5.noise_terms = 7, 20
+    assert lib.gld_workspace_size(C.byref(p5), C.byref(nb)) == B.GLD_ERR_INVALID_ARG  # no interval
+    p5.lam_lo, p5.lam_hi = -1.0, 5.0
+    assert lib.gld_workspace_size(C.byref(p5), C.byref(nb)) == B.GLD_OK
+    p5.noise_rank = 33
+    assert lib.gld_workspace_size(C.byref(p5), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    # spectrum-check iterations
+    for it, ok in ((0, True), (40, True), (200, True), (201, False), (-1, False)):
+        p6, k6 = _params(pkg, check_iters=it)
+        assert (lib.gld_workspace_size(C.byref(p6), C.byref(nb)) == B.GLD_OK) == ok, it
