@@ -271,6 +271,25 @@ gld_status gld_kernel_times(gld_system *sys, double *ms_sum, int64_t *launches);
 /* Release the handle (the workspace stays the caller's). Synchronises. */
 gld_status gld_destroy(gld_system *sys);
 
+/* Bytes of the library's own static workspace (one per device). */
+#define GLD_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: serving loops, harnesses that forbid it): gld_create with the
+ * workspace taken from a static device array of GLD_STATIC_WORKSPACE_BYTES
+ * that the library holds on each device it runs on until the process ends,
+ * instead of a caller-provided one.  Same arguments, checks and result as
+ * gld_create otherwise; allocates no device memory.  The current device
+ * (hipGetDevice) owns the system, and hip_stream must belong to it.
+ * Errors: GLD_ERR_OOM when gld_workspace_size() of these parameters exceeds
+ * GLD_STATIC_WORKSPACE_BYTES; GLD_ERR_INVALID_ARG while another system created
+ * by this call lives on the same device (one static workspace per device;
+ * gld_destroy frees it for the next).  The array keeps the last system's
+ * contents; creation clears what must start at zero.  Work of a static
+ * system and of a later one on the same device must not overlap: gld_destroy
+ * synchronises the stream before the array is reused. */
+gld_status gld_create_static(const gld_params *params, const double *r0, const double *v0, void *hip_stream,
+                             gld_system **out);
 
 /* White noise exactly as the integrator draws it: out[t][i][c] = W_{i,c,t0+t}
  * for t < n_t, i < n, c < 3, on the device (d_out: n_t*n*3 doubles), and the

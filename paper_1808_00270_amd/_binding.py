@@ -113,8 +113,11 @@ class gld_noise_info(C.Structure):
 EXPORTED = [
     "gld_workspace_size", "gld_create", "gld_step", "gld_sync", "gld_read_state", "gld_write_state",
     "gld_noise_parameters", "gld_set_graph", "gld_set_timing", "gld_kernel_times", "gld_destroy",
-    "gld_white_noise", "gld_build_noise_filters", "gld_status_string", "gld_last_error", "gld_list_stats",
+    "gld_white_noise", "gld_build_noise_filters", "gld_status_string", "gld_last_error", "gld_create_static",
+    "gld_list_stats",
 ]
+
+GLD_STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:
@@ -127,6 +130,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     S = C.POINTER(gld_state)
     lib.gld_workspace_size.argtypes = [P, C.POINTER(C.c_size_t)]
     lib.gld_create.argtypes = [P, _dp, _dp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.gld_create_static.argtypes = [P, _dp, _dp, vp, C.POINTER(vp)]
     lib.gld_step.argtypes = [vp, C.c_int64]
     lib.gld_sync.argtypes = [vp]
     lib.gld_read_state.argtypes = [vp, S]

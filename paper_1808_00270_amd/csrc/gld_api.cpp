@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -375,6 +376,7 @@ struct gld_system {
     double theta[2] = {0, 0};
     gld_status latched = GLD_OK;
     bool filters_given = false;
+    int static_device = -1;  // >= 0: the workspace is that device's static array
 };
 
 namespace {
@@ -892,6 +894,49 @@ gld_status refresh_forces(gld_system *s)
     return GLD_OK;
 }
 
+// The workspace of gld_create_static: one file-scope device array per GPU,
+// which each device holds until the process ends.  Host code never uses the
+// array's name as an address (on the host it is a stand-in): the device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+// One system at a time may live in a device's array.
+static __device__ __align__(256) unsigned char scratch[GLD_STATIC_WORKSPACE_BYTES];
+
+struct StaticSlot {
+    bool resolved = false;
+    void *ptr = nullptr;  // device address of this device's copy of scratch
+    bool in_use = false;
+};
+std::mutex g_static_mu;
+std::vector<StaticSlot> g_static;
+
+gld_status acquire_static(int &dev, void *&base)
+{
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (static_cast<int>(g_static.size()) <= dev) g_static.resize(dev + 1);
+    StaticSlot &sl = g_static[dev];
+    if (!sl.resolved) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return fail(GLD_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        sl.ptr = ptr;
+        sl.resolved = true;
+    }
+    if (sl.in_use)
+        return fail(GLD_ERR_INVALID_ARG, "the static workspace of device " + std::to_string(dev) +
+                                             " holds a live system (gld_destroy it first)");
+    sl.in_use = true;
+    base = sl.ptr;
+    return GLD_OK;
+}
+
+void release_static(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (dev >= 0 && dev < static_cast<int>(g_static.size())) g_static[dev].in_use = false;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1277,10 +1322,37 @@ gld_status gld_destroy(gld_system *s)
     else (void)hipDeviceSynchronize();
     drop_graph(s);
     for (auto e : s->pool) (void)hipEventDestroy(e);
+    if (s->static_device >= 0) release_static(s->static_device);
     delete s;
     return GLD_OK;
 }
 
+gld_status gld_create_static(const gld_params *params, const double *r0, const double *v0, void *hip_stream,
+                             gld_system **out)
+{
+    gld_status st = validate(params);
+    if (st != GLD_OK) return st;
+    if (!out) return fail(GLD_ERR_INVALID_ARG, "NULL pointer argument");
+    *out = nullptr;
+    size_t need = 0;
+    {
+        Dev d;
+        need = carve(params, geometry(params), nullptr, d);
+    }
+    if (need > GLD_STATIC_WORKSPACE_BYTES)
+        return fail(GLD_ERR_OOM, "system needs " + std::to_string(need) + " workspace bytes; the static workspace "
+                                 "holds GLD_STATIC_WORKSPACE_BYTES = " + std::to_string(GLD_STATIC_WORKSPACE_BYTES));
+    int dev = 0;
+    void *base = nullptr;
+    if ((st = acquire_static(dev, base)) != GLD_OK) return st;
+    st = gld_create(params, r0, v0, base, GLD_STATIC_WORKSPACE_BYTES, hip_stream, out);
+    if (st != GLD_OK) {
+        release_static(dev);
+        return st;
+    }
+    (*out)->static_device = dev;
+    return GLD_OK;
+}
 
 gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, double lam_hi, double tol, double *a_out,
                                    size_t a_cap, double *b_out, size_t b_cap, gld_noise_info *info)
