@@ -275,6 +275,83 @@ def cpu_baseline(args):
                                          f"scaled to one full step = {t1_step:.0f}s")))
 
 
+def run_batch(args):
+    """The batched workload: 256 independent systems (N log-uniform in
+    [100, 2e4], density in [0.005, 0.5], m_max in {200, 500, 1000}, kernels
+    scaled by factors in [0.5, 2]) in one batch, FP32-mixed, one graph replay
+    per step for all of them, mat-vec schedule from the autotuner."""
+    import torch
+    from paper_1808_00270_amd import batch as bm
+    from paper_1808_00270_amd import workloads as wl
+
+    t0 = time.perf_counter()
+    b = bm.Batch(args.batch_systems, args.batch_gib << 30, fp64=False)
+    attempts = [0] * args.batch_systems
+    pending = list(range(args.batch_systems))
+    slot_of = {}
+    redrawn = 0
+    for _ in range(12):
+        if not pending:
+            break
+        ws = [wl.batch_system(i, attempts[i]) for i in pending]
+        systems = []
+        for w in ws:
+            p, keep = bm.workload_params(w)
+            R, V = w.initial_state()
+            systems.append((p, keep, R, V))
+        slots, stat = b.add(systems, strict=False)
+        nxt = []
+        for i, w, s, st in zip(pending, ws, slots, stat):
+            if s >= 0:
+                slot_of[i] = (s, w)
+            else:
+                if st == -5:
+                    raise RuntimeError("batched workload does not fit the workspace")
+                attempts[i] = w.attempt + 1   # not positive definite / outside the interval: draw again
+                redrawn += 1
+                nxt.append(i)
+        pending = nxt
+    t_setup = time.perf_counter() - t0
+    n_tot = sum(w.n for s, w in slot_of.values())
+    log(f"[bench] batch: {len(slot_of)} systems, {n_tot} particles, set up in {t_setup:.1f}s ({redrawn} redrawn)")
+    thr, cand_ms = b.autotune(3)
+    log(f"[bench] batch autotune: thresholds {thr}, ms per pass {[round(x, 3) for x in cand_ms]}")
+    b.step(args.warmup)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    b.sync()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    log(f"[bench] batch: {ms:.3f} ms/step")
+    b.set_timing(True)
+    b.step(args.batch_kernel_steps)
+    kt = b.kernel_times()
+    b.set_timing(False)
+    nsys, npart, pairs = b.stats()
+    bad = sum(1 for s, w in slot_of.values() if b.read_state(s)["flags"] != 0)
+    ring_bytes = sum(4 * 3 * w.n * (w.m_max - 1) for s, w in slot_of.values())
+    per = {k: v / args.batch_kernel_steps for k, (v, c) in kt.items()}
+    hist_ms = per["history"]
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return {
+        "workload": "batch256_n100-2e4_rho0.005-0.5_m200-1000",
+        "systems": nsys, "particles": npart, "pairs": pairs, "redrawn": redrawn, "flagged_systems": bad,
+        "value": npart * 1e3 / ms, "unit": "particle-steps/s", "ms_per_step": ms,
+        "schedule_lane_thresholds": thr, "autotune_ms_per_candidate": cand_ms,
+        "kernels_ms_per_step": per,
+        "roofline_history": {"kernel": "history (streamed every step)", "bound": "hbm",
+                             "bytes_per_step": ring_bytes + npart * 3 * (8 + 4 * 3),
+                             "achieved": (ring_bytes + npart * 3 * (8 + 4 * 3)) / (hist_ms * 1e-3) / 1e9,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": (ring_bytes + npart * 3 * (8 + 4 * 3)) / (hist_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "setup_s": t_setup,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +366,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=2000)
     ap.add_argument("--cpu-freqs", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-systems", type=int, default=256, help="systems of the batched leg (0: skip)")
+    ap.add_argument("--batch-gib", type=int, default=48, help="workspace of the batched leg, GiB")
+    ap.add_argument("--batch-kernel-steps", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly (counter runs)")
     ap.add_argument("--window", type=int, default=8,
@@ -377,6 +457,10 @@ def main():
             "note": "random forces of W consecutive steps computed together at the positions of the window's "
                     "first step (the variant proposed for time-scale separation); not the per-step method",
         }
+    if args.batch_systems > 0:
+        rb = run_batch(args)
+        rb["fp32_batched_over_fp64_single"] = rb["value"] / out["fp64_plain"]["value"] if r64 is not None else None
+        out["batched"] = rb
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(args)

@@ -119,6 +119,39 @@ EXPORTED = [
 
 GLD_STATIC_WORKSPACE_BYTES = 64 << 20
 
+# include/gld_batch.h
+EXPORTED_BATCH = [
+    "gld_batch_base_size", "gld_batch_create", "gld_batch_footprint", "gld_batch_add", "gld_batch_remove",
+    "gld_batch_step", "gld_batch_sync", "gld_batch_read_state", "gld_batch_write_state",
+    "gld_batch_noise_parameters", "gld_batch_autotune", "gld_batch_set_schedule", "gld_batch_stats",
+    "gld_batch_destroy", "gld_batch_set_timing", "gld_batch_kernel_times",
+]
+GLD_BATCH_CANDIDATES = 8
+
+# include/gld_serve.h
+EXPORTED_SERVE = [
+    "gld_server_create", "gld_server_submit", "gld_server_run", "gld_server_request", "gld_server_stats",
+    "gld_server_destroy",
+]
+
+
+class gld_request_info(C.Structure):
+    _fields_ = [
+        ("id", C.c_int64),
+        ("n", C.c_int64),
+        ("m_max", C.c_int32),
+        ("status", C.c_int32),
+        ("steps", C.c_int64),
+        ("footprint", C.c_size_t),
+        ("arrival_s", C.c_double),
+        ("admitted_s", C.c_double),
+        ("done_s", C.c_double),
+    ]
+
+
+class gld_batch_schedule(C.Structure):
+    _fields_ = [("lanes_threshold", C.c_int32 * 3)]
+
 
 def load(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
@@ -144,6 +177,36 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gld_white_noise.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, vp, vp, vp]
     lib.gld_build_noise_filters.argtypes = [P, C.c_double, C.c_double, C.c_double, _dp, C.c_size_t, _dp,
                                             C.c_size_t, C.POINTER(gld_noise_info)]
+    PP = C.POINTER(P)
+    dpp = C.POINTER(_dp)
+    lib.gld_batch_base_size.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    lib.gld_batch_create.argtypes = [C.c_int32, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.gld_batch_footprint.argtypes = [vp, P, _dp, C.POINTER(C.c_size_t)]
+    lib.gld_batch_add.argtypes = [vp, C.c_int32, PP, dpp, dpp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.gld_batch_remove.argtypes = [vp, C.c_int32]
+    lib.gld_batch_step.argtypes = [vp, C.c_int64]
+    lib.gld_batch_sync.argtypes = [vp]
+    lib.gld_batch_read_state.argtypes = [vp, C.c_int32, S]
+    lib.gld_batch_write_state.argtypes = [vp, C.c_int32, S]
+    lib.gld_batch_noise_parameters.argtypes = [vp, C.c_int32, C.POINTER(gld_noise_info)]
+    lib.gld_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(gld_batch_schedule), _dp]
+    lib.gld_batch_set_schedule.argtypes = [vp, C.POINTER(gld_batch_schedule)]
+    lib.gld_batch_stats.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.gld_batch_destroy.argtypes = [vp]
+    lib.gld_batch_set_timing.argtypes = [vp, C.c_int]
+    lib.gld_batch_kernel_times.argtypes = [vp, _dp, C.POINTER(C.c_int64)]
+    for name in EXPORTED_BATCH:
+        getattr(lib, name).restype = C.c_int
+    lib.gld_server_create.argtypes = [C.c_int32, C.c_int32, vp, C.c_size_t, vp, C.c_int32,
+                                      C.POINTER(gld_batch_schedule), C.POINTER(vp)]
+    lib.gld_server_submit.argtypes = [vp, P, _dp, _dp, C.c_int64, C.c_double, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_size_t)]
+    lib.gld_server_run.argtypes = [vp]
+    lib.gld_server_request.argtypes = [vp, C.c_int64, C.POINTER(gld_request_info), S]
+    lib.gld_server_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.gld_server_destroy.argtypes = [vp]
+    for name in EXPORTED_SERVE:
+        getattr(lib, name).restype = C.c_int
     lib.gld_status_string.restype = C.c_char_p
     lib.gld_status_string.argtypes = [C.c_int]
     lib.gld_last_error.restype = C.c_char_p

@@ -295,6 +295,8 @@ namespace gld {
 
 gld_status validate_params(const gld_params *p) { return validate(p); }
 
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
 gld_status separable_pair_table(const gld_params *p, std::vector<double> &w, std::vector<double> &g, bool &any)
 {
     return separable_form(p, w, g, any);

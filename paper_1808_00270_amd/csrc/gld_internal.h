@@ -59,6 +59,8 @@ gld_status noise_spectra(const gld_params &p, NoisePlan &plan, std::string &err)
 gld_status noise_build(const gld_params &p, double lo, double hi, double tol, NoisePlan &plan,
                        std::string &err, double hi_tight = __builtin_nan(""), double lo_tight = -1e300);
 
+// The thread-local message gld_last_error() returns.
+void set_last_error(const std::string &msg);
 // Parameter checks shared by every system type (gld_api.cpp).
 gld_status validate_params(const gld_params *p);
 // The general pair table as its separable form w x g (max |w| = 1), if it
@@ -209,7 +211,7 @@ constexpr int kHistBlock32 = 32, kHistBlock64 = 16;
 // (one per step; the step part adds the kHistSplit partial sums)
 constexpr int kHistSplit = 4;
 // accumulator rows of the filter bank's product (rows of one output block)
-inline int fir_rows(int fp64) { return fp64 ? 32 : 64; }
+__host__ __device__ inline int fir_rows(int fp64) { return fp64 ? 32 : 64; }
 // rows of its zero-padded taps (the filter bank's layout, nslots taps)
 inline size_t hist_tap_rows(int nslots, int hb) { return static_cast<size_t>(hb - 1 + nslots + kFirChunk + hb - 1); }
 // out = a P x + b x + cz z + sum_q coef[q] us_q  (x, z, us: sorted T4; x, z may be null

@@ -131,3 +131,60 @@ def config(k: int, **over) -> Workload:
 def random_history(rng, m_max, n, scale=0.01):
     """A seeded displacement history dR_{n-m}, m = 1..m_max-1, shape [m_max-1, n, 3]."""
     return rng.normal(0.0, scale, size=(max(m_max - 1, 0), n, 3))
+
+
+def batch_system(i: int, attempt: int = 0) -> "Workload":
+    """System i of the batched benchmark (256 independent systems): N
+    log-uniform in [100, 2e4], density uniform in [0.005, 0.5], m_max from
+    {200, 500, 1000}, the self and pair kernels scaled by independent factors
+    uniform in [0.5, 2]; seeded by (2000 + i, attempt).  A draw whose box is
+    below 10 (r_c = 5 needs L > 2 r_c) is drawn again with the next attempt;
+    so is one that the library reports not positive definite (the caller
+    passes the attempt)."""
+    while True:
+        rng = np.random.default_rng([2000 + i, attempt])
+        n = int(round(math.exp(rng.uniform(math.log(100.0), math.log(2e4)))))
+        rho = float(rng.uniform(0.005, 0.5))
+        m_max = int(rng.choice([200, 500, 1000]))
+        fs, fp = (float(x) for x in rng.uniform(0.5, 2.0, size=2))
+        w = ScaledWorkload(name=f"batch{i}", n=n, rho=rho, m_max=m_max, steps=1000, seed=2000 + i,
+                           f_self=fs, f_pair=fp)
+        if w.box > 10.0:
+            w.attempt = attempt
+            return w
+        attempt += 1
+
+
+@dataclasses.dataclass
+class ScaledWorkload(Workload):
+    """A workload whose self and pair kernels are scaled by f_self and f_pair."""
+    f_self: float = 1.0
+    f_pair: float = 1.0
+    attempt: int = 0
+
+    def tables(self):
+        k_self, g, w, r0, dr = super().tables()
+        return self.f_self * k_self, self.f_pair * g, w, r0, dr
+
+
+def serve_requests(count: int, steps_scale: float = 1.0, seed: int = 5000):
+    """The first `count` requests of the serving workload: Poisson arrivals at
+    20 per second, N log-uniform in [64, 5e4], steps log-uniform in
+    [1e3, 1e5] (times steps_scale, at least 1), m_max from {200, 500, 1000},
+    density uniform in [0.005, 0.5] (a box below 10 is drawn again).
+    Returns [(arrival_s, steps, Workload)]."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += float(rng.exponential(1.0 / 20.0))
+        steps = int(round(math.exp(rng.uniform(math.log(1e3), math.log(1e5))) * steps_scale))
+        while True:
+            n = int(round(math.exp(rng.uniform(math.log(64.0), math.log(5e4)))))
+            rho = float(rng.uniform(0.005, 0.5))
+            m_max = int(rng.choice([200, 500, 1000]))
+            w = Workload(name=f"req{i}", n=n, rho=rho, m_max=m_max, steps=steps, seed=seed + 1 + i)
+            if w.box > 10.0:
+                break
+        out.append((t, max(1, steps), w))
+    return out

@@ -1,0 +1,189 @@
+"""The batched engine (include/gld_batch.h) against the FP64 oracle and
+against itself.
+
+* every system of a mixed batch (different N, density, memory length and
+  kernel scales) advanced one step from a written state with history matches
+  one oracle step of that system: 1e-12 (FP64) / 1e-5 (FP32-mixed),
+  normwise and element-wise, as the single-system parity tests;
+* one system's trajectory is the same, bit for bit, alone in a batch and in
+  a mixed batch (with the same mat-vec schedule);
+* a 40-step FP64 trajectory of one system matches the oracle's;
+* admission statuses, removal and re-use of the workspace, and the
+  autotuner's choice (the fastest candidate it measured).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1808_00270_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = {True: 1e-12, False: 1e-5}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bmod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1808_00270_amd as p
+    p.lib()
+    from paper_1808_00270_amd import batch
+    return batch
+
+
+def mixed(n_sys=4):
+    """Small systems of the batched workload's kinds (oracle-sized)."""
+    ws = [
+        wl.ScaledWorkload(name="b0", n=64, rho=0.05, m_max=200, steps=10, seed=3001, f_self=1.0, f_pair=1.0),
+        wl.ScaledWorkload(name="b1", n=300, rho=0.2, m_max=60, steps=10, seed=3002, f_self=1.7, f_pair=0.6),
+        wl.ScaledWorkload(name="b2", n=900, rho=0.5, m_max=120, steps=10, seed=3003, f_self=1.3, f_pair=1.2),
+        wl.ScaledWorkload(name="b3", n=250, rho=0.01, m_max=500, steps=10, seed=3004, f_self=0.6, f_pair=1.9),
+        wl.ScaledWorkload(name="b4", n=1500, rho=0.35, m_max=200, steps=10, seed=3005, f_self=1.0, f_pair=0.8),
+    ]
+    return ws[:n_sys]
+
+
+def oracle_for(oracle_mod, w):
+    k_self, g, wt, r0, dr = w.tables()
+    return oracle_mod.Oracle(n=w.n, box=w.box, dt=w.dt, mass=w.mass, kT=w.kT, k_self=k_self,
+                             k_pair=np.outer(wt, g), r0=r0, dr=dr, r_cut=w.r_cut, wca_sigma=w.wca_sigma,
+                             wca_eps=w.wca_eps, seed=w.seed, lanczos_tol=1e-13, lanczos_max_iter=400)
+
+
+def assert_close(name, a, b, tol, atol=0.0):
+    d = np.abs(a - b)
+    nb = np.linalg.norm(b)
+    r = np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+    rms = math.sqrt(np.mean(b ** 2)) if b.size else 0.0
+    emax = d.max() / rms if rms > 0 else d.max()
+    log(f"    {name}: rel {r:.2e}  max/rms {emax:.2e}")
+    assert np.linalg.norm(a - b) <= tol * nb + atol * math.sqrt(b.size), f"{name}: rel {r:.3e} > {tol:.1e}"
+    assert np.all(d <= 10 * tol * rms + atol), f"{name}: element error {emax:.3e}"
+
+
+def make_batch(bmod, ws, fp64, capacity=8, gib=2.0, **kw):
+    b = bmod.Batch(capacity, int(gib * (1 << 30)), fp64=fp64)
+    systems = []
+    for w in ws:
+        p, keep = bmod.workload_params(w, fp64=fp64, **({"noise_tol": 1e-13} if fp64 else {}), **kw)
+        R, V = w.initial_state()
+        systems.append((p, keep, R, V))
+    slots = b.add(systems)
+    return b, slots
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_every_system_of_a_mixed_batch_matches_the_oracle(bmod, oracle_mod, fp64):
+    ws = mixed(5)
+    b, slots = make_batch(bmod, ws, fp64)
+    b.set_schedule([24, 64, 160])
+    rng = np.random.default_rng(41)
+    hists, steps = [], []
+    for k, (w, s) in enumerate(zip(ws, slots)):
+        R, V = w.initial_state()
+        h = wl.random_history(rng, w.m_max, w.n, scale=0.01)
+        st = 5 + 13 * k  # different phases of the filter and history blocks
+        b.write_state(s, R, V, step=st, history=h)
+        hists.append(h)
+        steps.append(st)
+    b.step(1)
+    for w, s, h, st in zip(ws, slots, hists, steps):
+        info = b.noise_info(s)
+        log(f"  {w.name}: n={w.n} rho={w.rho} m_max={w.m_max} K={info['cheb_terms']} rank={info['rank']} "
+            f"step {st}")
+        g = b.read_state(s, history=True)
+        R, V = w.initial_state()
+        o = oracle_for(oracle_mod, w)
+        Ro, Vo, Ho = R.copy(), V.copy(), h.copy()
+        FC, FD, FR = o.step(st, Ro, Vo, Ho)
+        tol = TOL[fp64]
+        atol = 4 * np.finfo(np.float64).eps * max(np.abs(R).max(), 1.0)
+        assert g["step"] == st + 1 and g["flags"] == 0
+        assert_close("F^D'", g["f_d"], FD, tol)
+        assert_close("F^R", g["f_r"], FR, tol)
+        assert_close("dR", g["r"] - R, Ro - R, tol, atol)
+        assert_close("dV", g["v"] - V, Vo - V, tol, atol)
+        assert_close("history lag 1", g["history"][0], Ho[0], tol, atol)
+    b.close()
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_a_system_is_the_same_alone_and_in_the_mix(bmod, fp64):
+    ws = mixed(5)
+    alone, sa = make_batch(bmod, [ws[2]], fp64, capacity=2)
+    mix, sm = make_batch(bmod, ws, fp64)
+    for bb in (alone, mix):
+        bb.set_schedule([24, 64, 160])
+        bb.step(25)
+    a = alone.read_state(sa[0], history=True)
+    m = mix.read_state(sm[2], history=True)
+    for k in ("r", "v", "f_c", "f_d", "f_r", "history"):
+        assert np.array_equal(a[k], m[k]), k
+    assert a["step"] == m["step"] == 25
+    alone.close()
+    mix.close()
+
+
+def test_fp64_trajectory_matches_the_oracle(bmod, oracle_mod):
+    w = mixed(1)[0]
+    b, slots = make_batch(bmod, [w], True, capacity=1)
+    o = oracle_for(oracle_mod, w)
+    R, V = w.initial_state()
+    H = o.empty_history()
+    for n in range(40):
+        o.step(n, R, V, H)
+    b.step(40)
+    g = b.read_state(slots[0])
+    R0, _ = w.initial_state()
+    assert_close("R - R0 after 40 steps", g["r"] - R0, R - R0, 1e-9)
+    assert_close("V after 40 steps", g["v"], V, 1e-9)
+    b.close()
+
+
+def test_admission_removal_and_autotune(bmod):
+    ws = mixed(5)
+    systems = []
+    for w in ws:
+        p, keep = bmod.workload_params(w)
+        R, V = w.initial_state()
+        systems.append((p, keep, R, V))
+    probe = bmod.Batch(8, 1 << 30, fp64=False)
+    foot = [probe.footprint(s[0], s[2]) for s in systems]
+    probe.close()
+    log(f"  footprints (MB): {[round(f / 2**20, 2) for f in foot]}")
+    order = sorted(range(len(systems)), key=lambda i: -foot[i])
+    systems = [systems[i] for i in order]
+    foot = [foot[i] for i in order]
+    # room for the two largest and the batch's own tables: the rest is refused
+    b = bmod.Batch(8, bmod.base_size(8) + 4096 + foot[0] + foot[1], fp64=False)
+    slots, stat = b.add(systems, strict=False)
+    log(f"  slots {slots} statuses {stat}")
+    assert slots[0] >= 0 and slots[1] >= 0 and any(s < 0 for s in slots)
+    assert all((s >= 0) == (st == 0) for s, st in zip(slots, stat))
+    assert all(st in (0, -5) for st in stat)
+    b.step(3)
+    kept = [s for s in slots if s >= 0]
+    before = {s: b.read_state(s) for s in kept}
+    # removing the largest frees room for any refused one
+    b.remove(slots[0])
+    refused = [i for i, s in enumerate(slots) if s < 0]
+    s2 = b.add([systems[refused[0]]])
+    log(f"  re-admitted into slot {s2}")
+    b.step(2)
+    for s in kept[1:]:
+        assert b.read_state(s)["step"] == before[s]["step"] + 2
+    assert b.read_state(s2[0])["step"] == 2
+    thr, ms = b.autotune(2)
+    log(f"  autotune: thresholds {thr}, ms per pass {[round(x, 3) for x in ms]}")
+    assert min(ms) > 0
+    b.step(2)
+    b.sync()
+    b.close()

@@ -23,13 +23,17 @@ def pkg():
 
 
 def test_every_declared_symbol_is_exported(pkg):
-    header = open(os.path.join(ROOT, "include", "gld.h")).read()
-    declared = set(re.findall(r"^\s*(?:gld_status|const char \*)\s*(gld_\w+)\s*\(", header, re.M))
-    assert len(declared) >= 14
+    import glob
+    declared = set()
+    for path in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        header = open(path).read()
+        declared |= set(re.findall(r"^\s*(?:gld_status|const char \*)\s*(gld_\w+)\s*\(", header, re.M))
+    assert len(declared) >= 28
     lib = C.CDLL(pkg._binding.LIB_PATH)
     for name in declared:
         assert hasattr(lib, name), name
-    assert declared == set(pkg._binding.EXPORTED)
+    assert declared == (set(pkg._binding.EXPORTED) | set(pkg._binding.EXPORTED_BATCH)
+                        | set(pkg._binding.EXPORTED_SERVE))
 
 
 def _params(pkg, **over):
