@@ -47,6 +47,7 @@ class OrcParams(C.Structure):
         ("wca_sigma", C.c_double), ("wca_eps", C.c_double),
         ("seed", C.c_uint64),
         ("lanczos_tol", C.c_double),
+        ("dk_self", C.POINTER(C.c_double)),
     ]
 
 
@@ -111,19 +112,22 @@ class Oracle:
 
     def __init__(self, *, n, box, dt, mass, kT, k_self, k_pair, r0, dr, r_cut,
                  r_cut_min=0.0, parallel=False, wca_sigma=1.0, wca_eps=1.0, seed=0,
-                 lanczos_tol=1e-13, lanczos_max_iter=300):
+                 lanczos_tol=1e-13, lanczos_max_iter=300, dk_self=None):
         box = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
         self.k_self = np.ascontiguousarray(k_self, dtype=np.float64)
         self.k_pair = np.ascontiguousarray(k_pair, dtype=np.float64)
+        self.dk_self = None if dk_self is None else np.ascontiguousarray(dk_self, dtype=np.float64)
         m_max = self.k_self.shape[0]
         assert self.k_pair.ndim == 2 and self.k_pair.shape[1] == m_max
+        assert self.dk_self is None or self.dk_self.shape == self.k_pair.shape
         self.n, self.m_max, self.n_r = int(n), int(m_max), int(self.k_pair.shape[0])
         self.p = OrcParams(
             n=self.n, box=(C.c_double * 3)(*box), dt=dt, mass=mass, kT=kT,
             m_max=self.m_max, n_r=self.n_r, k_self=_dp(self.k_self), k_pair=_dp(self.k_pair),
             r0=r0, dr=dr, r_cut=r_cut, r_cut_min=r_cut_min, parallel=int(bool(parallel)),
             lanczos_max_iter=int(lanczos_max_iter), wca_sigma=wca_sigma, wca_eps=wca_eps,
-            seed=int(seed) & 0xFFFFFFFFFFFFFFFF, lanczos_tol=lanczos_tol)
+            seed=int(seed) & 0xFFFFFFFFFFFFFFFF, lanczos_tol=lanczos_tol,
+            dk_self=_dp(self.dk_self) if self.dk_self is not None else None)
         self.box = np.array(box)
         self.ctx = lib().orc_create(C.byref(self.p))
         if not self.ctx:

@@ -44,7 +44,10 @@
  *     t (also negative), so the colored noise is stationary from step 0;
  *   - white noise is Philox4x32-10 (Salmon et al., SC'11) with Box-Muller;
  *     key = seed, counter = (particle id, step lo, step hi, 0);
- *   - Delta K^s (distance dependent self memory) is not modelled.
+ *   - the distance dependent self memory Delta K^s of eq. (GLD_basic2) has
+ *     the pair memory's tensor form (1 or e e^T) and enters F^D' and the
+ *     noise correlation as eqs. (dissipative_force2), (stochastic_force2)
+ *     write it; a and b use the isotropic K^s_0 alone.
  */
 #include <math.h>
 #include <stdint.h>
@@ -75,6 +78,7 @@ typedef struct {
     double wca_sigma, wca_eps;
     uint64_t seed;
     double lanczos_tol;      /* relative stopping tolerance of Algorithm 1  */
+    const double *dk_self;   /* [n_r*m_max] Delta K^s_m(r_b), or NULL: none */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -298,6 +302,18 @@ static double kpair_at(const orc_params *p, double r, int m)
     return t0[m] * (1.0 - f) + t1[m] * f;
 }
 
+/* Delta K^s_m(r) for one lag m (0 without a table) */
+static double dks_at(const orc_params *p, double r, int m)
+{
+    if (!p->dk_self) return 0.0;
+    int b;
+    double f;
+    grid_locate(p, r, &b, &f);
+    const double *t0 = p->dk_self + (size_t)b * p->m_max;
+    const double *t1 = t0 + p->m_max;
+    return t0[m] * (1.0 - f) + t1[m] * f;
+}
+
 /* y += k * T_ij x, with T = 1 or e e^T */
 static void apply_tensor(const orc_params *p, const orc_pair *q, double k, const double *x, double *y)
 {
@@ -375,10 +391,10 @@ void orc_ab(const orc_params *p, double *a, double *b)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Dissipative force, eq. (dissipative_force2), Delta K^s = 0:               */
-/*   F_i = - sum_{j!=i} K^p_0(R_ij) T V_j                                    */
+/* Dissipative force, eq. (dissipative_force2):                             */
+/*   F_i = - sum_{j!=i} [ K^p_0(R_ij) T V_j + Delta K^s_0(R_ij) T V_i ]      */
 /*         - 1/dt sum_{m=1}^{m_max-1} [ sum_{j!=i} K^p_m(R_ij) T dR_{j,n-m}  */
-/*                                      + K^s_m dR_{i,n-m} ]                 */
+/*              + (K^s_m + sum_{k!=i} Delta K^s_m(R_ik) T) dR_{i,n-m} ]      */
 /* hist[(m-1)][i][c] = dR_{i,n-m}.                                           */
 /* ------------------------------------------------------------------------ */
 
@@ -393,6 +409,12 @@ static void dissipative_row(const orc_params *p, int64_t i, const orc_pair *nb, 
         apply_tensor(p, q, kpair_at(p, q->r, 0), V + 3 * q->j, acc);
         for (int m = 1; m < p->m_max; ++m)
             apply_tensor(p, q, kpair_at(p, q->r, m), hist + ((size_t)(m - 1) * N + q->j) * 3, hsum);
+        if (p->dk_self) {
+            /* the two-particle part of the self memory acts on particle i's own velocity and history */
+            apply_tensor(p, q, dks_at(p, q->r, 0), V + 3 * i, acc);
+            for (int m = 1; m < p->m_max; ++m)
+                apply_tensor(p, q, dks_at(p, q->r, m), hist + ((size_t)(m - 1) * N + i) * 3, hsum);
+        }
     }
     for (int m = 1; m < p->m_max; ++m)
         for (int c = 0; c < 3; ++c)
@@ -425,6 +447,7 @@ typedef struct {
     double *cosw;     /* [M*M] cos(2 pi w m / P)                 */
     double *S_hat;    /* [M]   self spectrum                      */
     double *Kp_hat;   /* [n_r*M] pair spectrum per distance bin   */
+    double *DKs_hat;  /* [n_r*M] spectrum of Delta K^s per bin, or NULL */
     int last_iters;   /* largest Lanczos iteration count, last call */
 } orc_ctx;
 
@@ -433,6 +456,8 @@ static double corr_coef(const orc_params *p, double Km, int m)
     const double am = (m == 0) ? 2.0 : 1.0;
     return p->kT * am * Km / p->dt;
 }
+
+void orc_destroy(orc_ctx *c);
 
 orc_ctx *orc_create(const orc_params *p)
 {
@@ -467,13 +492,25 @@ orc_ctx *orc_create(const orc_params *p)
             c->Kp_hat[(size_t)b * M + w] = s;
         }
     }
+    if (p->dk_self) {
+        c->DKs_hat = (double *)malloc((size_t)p->n_r * M * sizeof(double));
+        if (!c->DKs_hat) { orc_destroy(c); return NULL; }
+        for (int b = 0; b < p->n_r; ++b) {
+            const double *kb = p->dk_self + (size_t)b * M;
+            for (int w = 0; w < M; ++w) {
+                double s = corr_coef(p, kb[0], 0);
+                for (int m = 1; m < M; ++m) s += 2.0 * corr_coef(p, kb[m], m) * c->cosw[(size_t)w * M + m];
+                c->DKs_hat[(size_t)b * M + w] = s;
+            }
+        }
+    }
     return c;
 }
 
 void orc_destroy(orc_ctx *c)
 {
     if (!c) return;
-    free(c->cosw); free(c->S_hat); free(c->Kp_hat); free(c);
+    free(c->cosw); free(c->S_hat); free(c->Kp_hat); free(c->DKs_hat); free(c);
 }
 
 int orc_last_iters(const orc_ctx *c) { return c->last_iters; }
@@ -492,9 +529,19 @@ static double kp_hat_at(const orc_ctx *c, double r, int w)
     return c->Kp_hat[(size_t)b * c->M + w] * (1.0 - f) + c->Kp_hat[(size_t)(b + 1) * c->M + w] * f;
 }
 
+static double dks_hat_at(const orc_ctx *c, double r, int w)
+{
+    if (!c->DKs_hat) return 0.0;
+    int b;
+    double f;
+    grid_locate(&c->p, r, &b, &f);
+    return c->DKs_hat[(size_t)b * c->M + w] * (1.0 - f) + c->DKs_hat[(size_t)(b + 1) * c->M + w] * f;
+}
+
 /* y = K_hat_w x, matrix free over the pair list (Sec. II.C: iterate over the
- * neighbours instead of storing the sparse matrix). */
-static void khat_apply(const orc_ctx *c, int w, const pair_list *L, const double *khp,
+ * neighbours instead of storing the sparse matrix); khp[k], dkh[k]: the pair
+ * and the self-memory spectra of pair k at this frequency (dkh NULL: none) */
+static void khat_apply(const orc_ctx *c, int w, const pair_list *L, const double *khp, const double *dkh,
                        const double *x, double *y)
 {
     const int64_t n3 = 3 * c->p.n;
@@ -502,6 +549,7 @@ static void khat_apply(const orc_ctx *c, int w, const pair_list *L, const double
     for (int64_t k = 0; k < L->n; ++k) {
         const orc_pair *q = &L->v[k];
         apply_tensor(&c->p, q, khp[k], x + 3 * q->j, y + 3 * q->i);
+        if (dkh) apply_tensor(&c->p, q, dkh[k], x + 3 * q->i, y + 3 * q->i);
     }
 }
 
@@ -600,7 +648,7 @@ static double dotv(int64_t n, const double *a, const double *b)
 }
 
 /* x = sqrt(K_hat_w) b by Lanczos (Algorithm 1, one frequency). */
-static int lanczos_sqrt(const orc_ctx *c, int w, const pair_list *L, const double *khp,
+static int lanczos_sqrt(const orc_ctx *c, int w, const pair_list *L, const double *khp, const double *dkh,
                         const double *bvec, double *x, int *iters)
 {
     const int64_t n3 = 3 * c->p.n;
@@ -625,7 +673,7 @@ static int lanczos_sqrt(const orc_ctx *c, int w, const pair_list *L, const doubl
 
     /* v^1 = b / |b|, alpha^1 = v^1 K v^1 */
     for (int64_t I = 0; I < n3; ++I) Vb[I] = bvec[I] / nb;
-    khat_apply(c, w, L, khp, Vb, Kv);
+    khat_apply(c, w, L, khp, dkh, Vb, Kv);
     alpha[0] = dotv(n3, Vb, Kv);
     if (alpha[0] <= 0.0) { rc = ORC_ERR_NOT_PD; goto done; }
     {
@@ -649,7 +697,7 @@ static int lanczos_sqrt(const orc_ctx *c, int w, const pair_list *L, const doubl
         }
         double *vn = Vb + (size_t)k * n3;
         for (int64_t I = 0; I < n3; ++I) vn[I] = r[I] / beta[k - 1];
-        khat_apply(c, w, L, khp, vn, Kv);
+        khat_apply(c, w, L, khp, dkh, vn, Kv);
         alpha[k] = dotv(n3, vn, Kv);
         const int kk = k + 1;
         for (int q = 0; q < kk; ++q) dd[q] = alpha[q];
@@ -704,10 +752,14 @@ static int noise_on_pairs(orc_ctx *c, int64_t step, const pair_list *L, const ui
 #pragma omp parallel for schedule(dynamic, 1)
     for (int w = 0; w < nw; ++w) {
         double *khp = (double *)malloc((size_t)(L->n ? L->n : 1) * sizeof(double));
+        double *dkh = c->DKs_hat ? (double *)malloc((size_t)(L->n ? L->n : 1) * sizeof(double)) : NULL;
         for (int64_t k = 0; k < L->n; ++k) khp[k] = kp_hat_at(c, L->v[k].r, w0 + w);
+        if (dkh)
+            for (int64_t k = 0; k < L->n; ++k) dkh[k] = dks_hat_at(c, L->v[k].r, w0 + w);
         int it = 0;
-        int r1 = lanczos_sqrt(c, w0 + w, L, khp, What + (size_t)w * n3, X + (size_t)w * n3, &it);
+        int r1 = lanczos_sqrt(c, w0 + w, L, khp, dkh, What + (size_t)w * n3, X + (size_t)w * n3, &it);
         free(khp);
+        free(dkh);
 #pragma omp critical
         {
             if (r1 && !rc) rc = r1;
@@ -795,11 +847,16 @@ int orc_corr_matrix(const orc_ctx *c, const double *R, int m, double *K)
     for (int64_t k = 0; k < L.n; ++k) {
         const orc_pair *q = &L.v[k];
         const double cp = corr_coef(p, kpair_at(p, q->r, m), m);
+        const double cs = corr_coef(p, dks_at(p, q->r, m), m);
         for (int b = 0; b < 3; ++b) {
-            double e[3] = {0, 0, 0}, col[3] = {0, 0, 0};
+            double e[3] = {0, 0, 0}, col[3] = {0, 0, 0}, dcol[3] = {0, 0, 0};
             e[b] = 1.0;
             apply_tensor(p, q, cp, e, col);
-            for (int a = 0; a < 3; ++a) K[(3 * q->i + a) * n3 + 3 * q->j + b] = col[a];
+            apply_tensor(p, q, cs, e, dcol);
+            for (int a = 0; a < 3; ++a) {
+                K[(3 * q->i + a) * n3 + 3 * q->j + b] = col[a];
+                K[(3 * q->i + a) * n3 + 3 * q->i + b] += dcol[a];
+            }
         }
     }
     free(L.v);
@@ -814,12 +871,16 @@ static int dense_khat(const orc_ctx *c, const pair_list *L, int w, double *K)
     for (int64_t I = 0; I < n3; ++I) K[I * n3 + I] = c->S_hat[w];
     for (int64_t k = 0; k < L->n; ++k) {
         const orc_pair *q = &L->v[k];
-        const double kp = kp_hat_at(c, q->r, w);
+        const double kp = kp_hat_at(c, q->r, w), ds = dks_hat_at(c, q->r, w);
         for (int b = 0; b < 3; ++b) {
-            double e[3] = {0, 0, 0}, col[3] = {0, 0, 0};
+            double e[3] = {0, 0, 0}, col[3] = {0, 0, 0}, dcol[3] = {0, 0, 0};
             e[b] = 1.0;
             apply_tensor(&c->p, q, kp, e, col);
-            for (int a = 0; a < 3; ++a) K[(3 * q->i + a) * n3 + 3 * q->j + b] = col[a];
+            apply_tensor(&c->p, q, ds, e, dcol);
+            for (int a = 0; a < 3; ++a) {
+                K[(3 * q->i + a) * n3 + 3 * q->j + b] = col[a];
+                K[(3 * q->i + a) * n3 + 3 * q->i + b] += dcol[a];
+            }
         }
     }
     return ORC_OK;

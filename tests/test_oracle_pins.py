@@ -28,7 +28,7 @@ from paper_1808_00270_amd import workloads as wl
 
 def make_oracle(oracle_mod, *, n, box, m_max, dt=0.01, kT=1.0, mass=1.0, k_self=None, k_pair=None,
                 r_cut=5.0, n_r=51, parallel=False, wca_eps=0.0, seed=7, tol=1e-13, max_iter=300, r_cut_min=0.0,
-                r0=0.0):
+                r0=0.0, dk_self=None):
     if k_self is None:
         k_self = wl.discretize(wl.self_kernel, dt, m_max)
     dr = (r_cut - r0) / (n_r - 1)
@@ -37,6 +37,7 @@ def make_oracle(oracle_mod, *, n, box, m_max, dt=0.01, kT=1.0, mass=1.0, k_self=
         w[-1] = 0.0
         k_pair = np.outer(w, wl.discretize(wl.pair_time_kernel, dt, m_max))
     return oracle_mod.Oracle(n=n, box=box, dt=dt, mass=mass, kT=kT, k_self=k_self, k_pair=k_pair, r0=r0,
+                             dk_self=dk_self,
                              dr=dr, r_cut=r_cut, r_cut_min=r_cut_min, parallel=parallel, wca_sigma=1.0,
                              wca_eps=wca_eps, seed=seed, lanczos_tol=tol, lanczos_max_iter=max_iter)
 
@@ -212,10 +213,11 @@ def _gle_response_two_exp(t, A, a, B, b, M=1.0):
     return out.real
 
 
-@pytest.mark.parametrize("parallel,r_cut_min,r0", [(False, 0.0, 0.0), (True, 0.0, 0.0),
-                                                    (False, 0.0, 0.5), (False, 2.6, 0.5), (True, 2.6, 0.5),
-                                                    (False, 2.6, 0.0)])
-def test_two_particle_dilute_limit_decouples(oracle_mod, parallel, r_cut_min, r0):
+@pytest.mark.parametrize("parallel,r_cut_min,r0,dks", [(False, 0.0, 0.0, 0.0), (True, 0.0, 0.0, 0.0),
+                                                        (False, 0.0, 0.5, 0.0), (False, 2.6, 0.5, 0.0),
+                                                        (True, 2.6, 0.5, 0.0), (False, 2.6, 0.0, 0.0),
+                                                        (False, 0.0, 0.0, 9.0), (True, 2.6, 0.5, 9.0)])
+def test_two_particle_dilute_limit_decouples(oracle_mod, parallel, r_cut_min, r0, dks):
     """Two particles at fixed distance R along x (Sec. III.A): V_+- obey
     single-particle GLEs with K_+- = K^s +- K^p(R).  Linear response with a
     tiny initial velocity keeps R fixed; the scheme converges to the closed
@@ -226,7 +228,12 @@ def test_two_particle_dilute_limit_decouples(oracle_mod, parallel, r_cut_min, r0
     interpolation on the grid is exact.  With r_cut_min > R the kernel is
     frozen at its value at r_c,min (Sec. III.B: the reconstruction stops at
     r_c,min and the kernel below it is taken as the one there), so the
-    closed form must use K^p(r_c,min), not K^p(R)."""
+    closed form must use K^p(r_c,min), not K^p(R).
+
+    dks > 0 adds a distance-dependent self memory Delta K^s(r, t) =
+    w(r) dks exp(-t/ts) (eq. GLD_basic2): then K_+- = K^s + Delta K^s(R)
+    +- K^p(R) (Sec. III.A), the self part acting on each particle's own
+    velocity and history in eq. (dissipative_force2)."""
     As, ts, Bp, tp, rc, Rd = 30.0, 0.25, 12.0, 0.15, 5.0, 2.0
     eps = 1e-7
     errs = []
@@ -237,8 +244,10 @@ def test_two_particle_dilute_limit_decouples(oracle_mod, parallel, r_cut_min, r0
         w = np.clip(1 - (r0 + np.arange(n_r) * dr) / rc, 0, None)
         g = wl.discretize(lambda t: Bp * np.exp(-t / tp), dt, m_max)
         ks = wl.discretize(lambda t: As * np.exp(-t / ts), dt, m_max)
+        dk = np.outer(w, wl.discretize(lambda t: dks * np.exp(-t / ts), dt, m_max)) if dks else None
         o = make_oracle(oracle_mod, n=2, box=60.0, m_max=m_max, dt=dt, kT=0.0, k_self=ks,
-                        k_pair=np.outer(w, g), r_cut=rc, n_r=n_r, parallel=parallel, r_cut_min=r_cut_min, r0=r0)
+                        k_pair=np.outer(w, g), r_cut=rc, n_r=n_r, parallel=parallel, r_cut_min=r_cut_min, r0=r0,
+                        dk_self=dk)
         R = np.array([[10.0, 10.0, 10.0], [10.0 + Rd, 10.0, 10.0]])
         V = np.array([[eps, 0.0, 0.0], [0.0, 0.0, 0.0]])
         T = 1.5
@@ -246,8 +255,8 @@ def test_two_particle_dilute_limit_decouples(oracle_mod, parallel, r_cut_min, r0
         _, Vs = _run_free(o, R, V, steps)
         t = np.arange(steps + 1) * dt
         wR = 1 - max(Rd, r_cut_min) / rc
-        Gp = _gle_response_two_exp(t, As, 1 / ts, wR * Bp, 1 / tp)
-        Gm = _gle_response_two_exp(t, As, 1 / ts, -wR * Bp, 1 / tp)
+        Gp = _gle_response_two_exp(t, As + wR * dks, 1 / ts, wR * Bp, 1 / tp)
+        Gm = _gle_response_two_exp(t, As + wR * dks, 1 / ts, -wR * Bp, 1 / tp)
         v1 = Vs[:, 0, 0] / eps
         v2 = Vs[:, 1, 0] / eps
         errs.append(max(np.abs(v1 - (Gp + Gm) / 2).max(), np.abs(v2 - (Gp - Gm) / 2).max()))
@@ -285,21 +294,29 @@ def test_velocity_verlet_limit_conserves_energy(oracle_mod):
 # colored noise: Algorithm 1 against its definition
 # --------------------------------------------------------------------------
 
-def _tiny_system(oracle_mod, parallel, n=6, m_max=12, seed=3):
+def _tiny_system(oracle_mod, parallel, n=6, m_max=12, seed=3, dk=False):
     L = 6.0
     rng = np.random.default_rng(seed)
     R = rng.uniform(0, L, size=(n, 3))
+    dk_self = None
+    if dk:
+        # a distance-dependent self memory: w(r) times a damped oscillation
+        n_r, r_cut, dt = 30, 2.9, 0.05
+        w = wl.pair_weight(np.arange(n_r) * (r_cut / (n_r - 1)), r_cut)
+        dk_self = np.outer(w, wl.discretize(lambda t: 2.0 * np.exp(-t / 0.2) * np.cos(3 * t), dt, m_max))
     o = make_oracle(oracle_mod, n=n, box=L, m_max=m_max, dt=0.05, r_cut=2.9, n_r=30,
-                    parallel=parallel, seed=seed)
+                    parallel=parallel, seed=seed, dk_self=dk_self)
     return o, R
 
 
-@pytest.mark.parametrize("parallel", [False, True])
-def test_circular_ansatz_reproduces_correlation_matrices(oracle_mod, parallel):
+@pytest.mark.parametrize("parallel,dk", [(False, False), (True, False), (False, True), (True, True)])
+def test_circular_ansatz_reproduces_correlation_matrices(oracle_mod, parallel, dk):
     """eq. (noise_ansatz): K_m = sum_s A_s A_{s+m} with periodic continuation
     of A (period 2 m_max - 1), A_s from the per-frequency square roots.  Pins
-    the DFT convention and the 1/(2 m_max - 1) normalisation."""
-    o, R = _tiny_system(oracle_mod, parallel)
+    the DFT convention and the 1/(2 m_max - 1) normalisation; with a
+    distance-dependent self memory (dk), its place in the diagonal blocks of
+    eq. (stochastic_force2)."""
+    o, R = _tiny_system(oracle_mod, parallel, dk=dk)
     M = o.m_max
     P = 2 * M - 1
     A = o.dense_filters(R)
@@ -312,12 +329,12 @@ def test_circular_ansatz_reproduces_correlation_matrices(oracle_mod, parallel):
         assert np.abs(acc - K).max() <= 1e-11 * np.abs(K).max()
 
 
-@pytest.mark.parametrize("parallel", [False, True])
-def test_lanczos_noise_matches_dense_definitions(oracle_mod, parallel):
+@pytest.mark.parametrize("parallel,dk", [(False, False), (True, False), (False, True), (True, True)])
+def test_lanczos_noise_matches_dense_definitions(oracle_mod, parallel, dk):
     """Algorithm 1 (Lanczos per frequency) reaches the vector defined by the
     dense per-frequency square roots and by the time-domain filter sum of
     eq. (noise_production)."""
-    o, R = _tiny_system(oracle_mod, parallel)
+    o, R = _tiny_system(oracle_mod, parallel, dk=dk)
     for step in (0, 3, 40):
         F_l = o.noise(step, R)
         F_f = o.noise_dense_freq(step, R)
