@@ -42,6 +42,12 @@ gld_status bfail(gld_status st, const std::string &msg)
             return bfail(GLD_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));           \
     } while (0)
 
+#define BLAUNCH0(expr)                                                                                 \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return bfail(GLD_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
 size_t up256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 constexpr size_t kMapArena = size_t(16) << 20;  // launch maps of a batch (a few hundred KB at 256 systems)
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -601,7 +607,8 @@ void fir_tiles(const gld_batch *b, const std::vector<int> &which, int mode, std:
         const Sys &y = b->sys[s];
         if (!y.noise_on) continue;
         const int64_t M = 3 * y.S;
-        const int64_t cs = mode == 0 ? (M / y.bf + 1 + 255) / 256 * 256 : M;
+        const int nslice = y.bf / gld::fir_period(y.bf);
+        const int64_t cs = mode == 0 ? (M / nslice + 1 + 255) / 256 * 256 : M;
         const int nt = static_cast<int>((cs + 255) / 256);
         for (int t = 0; t < nt; ++t) out.push_back(int2{s, t});
     }
@@ -611,6 +618,34 @@ struct HostMaps {
     std::vector<BMap> p, c, sl[4];
     std::vector<int2> t;
 };
+
+// The blocks of the pair mat-vecs and list builds of one lane class, in an
+// XCD-aware order: the GPU hands work-group b to XCD b mod 8, so each system
+// is given to one XCD (largest pair work first, to the least loaded XCD) and
+// its blocks are placed at indices of that residue; the input vectors its
+// mat-vecs gather then stay in that XCD's L2.  Shorter XCD lists are padded
+// with empty blocks (sys -1).
+void xcd_map(const gld_batch *b, const std::vector<int> &cls, int per, std::vector<BMap> &out)
+{
+    constexpr int kXcd = 8;
+    std::vector<int> order(cls);
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        const double wx = b->sys[x].n * (1.0 + b->sys[x].mean_nbrs), wy = b->sys[y].n * (1.0 + b->sys[y].mean_nbrs);
+        return wx > wy || (wx == wy && x < y);
+    });
+    std::vector<std::vector<BMap>> bins(kXcd);
+    std::vector<double> load(kXcd, 0.0);
+    for (int s : order) {
+        const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+        const int64_t n = b->sys[s].n;
+        for (int64_t f = 0; f < n; f += per) bins[x].push_back(BMap{s, static_cast<int>(f)});
+        load[x] += b->sys[s].n * (1.0 + b->sys[s].mean_nbrs);
+    }
+    size_t longest = 0;
+    for (auto &v : bins) longest = std::max(longest, v.size());
+    for (size_t j = 0; j < longest; ++j)
+        for (int x = 0; x < kXcd; ++x) out.push_back(j < bins[x].size() ? bins[x][j] : BMap{-1, 0});
+}
 
 void make_maps(const gld_batch *b, const std::vector<int> &which, HostMaps &h, int fir_mode)
 {
@@ -623,7 +658,7 @@ void make_maps(const gld_batch *b, const std::vector<int> &which, HostMaps &h, i
         std::vector<int> cls;
         for (int s : which)
             if (lane_class(lanes_for(b->sched, b->sys[s].mean_nbrs)) == k) cls.push_back(s);
-        part_map(b, cls, gld::batch::kThreads / gld::batch::kLaneChoices[k], h.sl[k]);
+        xcd_map(b, cls, gld::batch::kThreads / gld::batch::kLaneChoices[k], h.sl[k]);
     }
     fir_tiles(b, which, fir_mode, h.t);
 }
@@ -687,12 +722,27 @@ gld_status rebuild(gld_batch *b)
     b->kmax = 0;
     b->rmax = 1;
     b->any_noise = 0;
+    bool relayout = false;
     for (int s2 : a) {
-        const Sys &y = b->sys[s2];
+        Sys &y = b->sys[s2];
+        const int lanes = lanes_for(b->sched, y.mean_nbrs);
+        if (lanes != y.d.lanes) {
+            y.d.lanes = lanes;
+            BHIP(hipMemcpyAsync(b->d_sys + s2, &y.d, sizeof(BSys), hipMemcpyHostToDevice, b->st));
+            relayout = true;
+        }
         if (!y.noise_on) continue;
         b->any_noise = 1;
         b->kmax = std::max(b->kmax, y.plan.K);
         b->rmax = std::max(b->rmax, y.plan.r);
+    }
+    if (relayout) {
+        // the pair lists of the current positions again, in the new lane
+        // layout (F^C into the scratch FCn, as in a step)
+        const BMap *sm[4] = {b->smap[0], b->smap[1], b->smap[2], b->smap[3]};
+        BLAUNCH0(gld::batch::b_neighbors(b->fp64, b->d_sys, b->pmap, b->np, b->cmap, b->nc, sm, b->ns, b->capacity, 0,
+                                         b->st));
+        BHIP(hipStreamSynchronize(b->st));
     }
     b->dirty = false;
     return GLD_OK;
@@ -782,7 +832,8 @@ gld_status enqueue_step(gld_batch *b)
     }
     {
         Timed t(b, GLD_K_NEIGHBOR);
-        BLAUNCH(b_neighbors(f, b->d_sys, b->pmap, b->np, b->cmap, b->nc, b->capacity, 0, st));
+        const BMap *sm[4] = {b->smap[0], b->smap[1], b->smap[2], b->smap[3]};
+        BLAUNCH(b_neighbors(f, b->d_sys, b->pmap, b->np, b->cmap, b->nc, sm, b->ns, b->capacity, 0, st));
     }
     Timed t(b, GLD_K_UPDATE);
     BLAUNCH(b_update_v(f, b->d_sys, b->pmap, b->np, st));
@@ -809,7 +860,10 @@ gld_status prime(gld_batch *b, const std::vector<int> &which)
     int gy = 1;
     for (int w : which)
         if (b->sys[w].noise_on) gy = std::max(gy, 2 * b->sys[w].plan.half + 2 * b->sys[w].bf);
-    BLAUNCH(b_neighbors(f, b->d_sys, pm, np, cm, static_cast<int>(h.c.size()), b->capacity, 1, st));
+    const BMap *smp[4] = {sm[0], sm[1], sm[2], sm[3]};
+    int nsp[4];
+    for (int k = 0; k < 4; ++k) nsp[k] = static_cast<int>(h.sl[k].size());
+    BLAUNCH(b_neighbors(f, b->d_sys, pm, np, cm, static_cast<int>(h.c.size()), smp, nsp, b->capacity, 1, st));
     BLAUNCH(b_white(f, b->d_sys, pm, np, 1, gy, st));
     BLAUNCH(b_fir(f, b->d_sys, tl, nt, 1, st));
     BLAUNCH(b_white(f, b->d_sys, pm, np, 2, gy, st));
@@ -857,6 +911,7 @@ gld_status place(gld_batch *b, Sys &&src, size_t off, int s, const double *r0, c
     char *base = b->base + y.off;
     BHIP(hipMemsetAsync(base, 0, y.bytes, b->st));
     carve_system(b->fp64, y, base);
+    y.d.lanes = lanes_for(b->sched, y.mean_nbrs);
     if ((st = b->fp64 ? upload_tables<double>(b, y) : upload_tables<float>(b, y)) != GLD_OK) return st;
     std::vector<double> dstage;
     if ((st = put_vec<double>(b->st, y.n, y.S, y.d.R, r0, dstage)) != GLD_OK) return st;

@@ -133,16 +133,18 @@ __global__ __launch_bounds__(kThreads) void kb_white(const BSys *__restrict__ sy
 
 // ---------------------------------------------------------------------------
 // H5a: the filter bank on the matrix cores, one tile of 256 channels per
-// block: tiles[b] = (system, tile within the system's share).  mode 0: the
-// step's 1/bf share of the next block; 1: the whole current block; 2: the
-// whole next block.
+// block: tiles[b] = (system, tile within the system's share).  mode 0: every
+// fir_period(bf) steps a share of the next block; 1: the whole current block;
+// 2: the whole next block.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ FirPart fir_part(const BSys &d, int mode, int64_t M)
 {
     FirPart part;
     part.ahead = mode == 1 ? 0 : 1;
-    part.nslice = mode == 0 ? d.bf : 1;
-    part.cs = mode == 0 ? (M / d.bf + 1 + kThreads - 1) / kThreads * kThreads : M;
+    part.spread = mode == 0;
+    part.period = fir_period(d.bf);
+    part.nslice = mode == 0 ? d.bf / part.period : 1;
+    part.cs = mode == 0 ? (M / part.nslice + 1 + kThreads - 1) / kThreads * kThreads : M;
     return part;
 }
 
@@ -233,6 +235,7 @@ __global__ __launch_bounds__(kThreads) void kb_spmv(const BSys *__restrict__ sys
 {
     using T4 = typename V4t<T>::t;
     const BMap mp = map[blockIdx.x];
+    if (mp.sys < 0) return;  // padding of the XCD-ordered map
     const BSys &d = sys[mp.sys];
     if (k >= d.K && k >= 0) return;  // beyond this system's chain
     if (k >= 0 && !d.noise_on) return;
@@ -244,12 +247,17 @@ __global__ __launch_bounds__(kThreads) void kb_spmv(const BSys *__restrict__ sys
     const BTerm tm = k >= 0 ? d.terms[k] : BTerm{-1.0, 0.0, 0.0};
     T ax = T(0), ay = T(0), az = T(0);
     if (live && tm.a != 0.0) {
+        // lane sub reads entries sub, sub + LANES, ... of particle i: in the
+        // lane-interleaved lists a lane group's reads are LANES consecutive
+        // entries, and a wave's 64 consecutive ones
         const int nn = d.nn[i];
-        const uint16_t *li = d.nbl + i;
-        const T *lw = static_cast<const T *>(d.nbw) + i;
-        for (int q = sub; q < nn; q += LANES) {
-            const int j = li[static_cast<int64_t>(q) * S];
-            const T w = lw[static_cast<int64_t>(q) * S];
+        const uint16_t *li = d.nbl + i * LANES + sub;
+        const T *lw = static_cast<const T *>(d.nbw) + i * LANES + sub;
+        const int64_t row = S * LANES;
+        int64_t o = 0;
+        for (int q = sub; q < nn; q += LANES, o += row) {
+            const int j = li[o];
+            const T w = lw[o];
             const T4 xj = x[j];
             ax += w * xj.x;
             ay += w * xj.y;
@@ -464,20 +472,31 @@ __device__ __forceinline__ double batch_weight(const BSys &d, double r)
     return d.wtab[b] * (1.0 - f) + d.wtab[b + 1] * f;
 }
 
-template <typename T>
+// LANES lanes per particle take the candidates of each stencil cell in
+// turns of LANES; the hits of a turn get consecutive list positions in
+// candidate order (a ballot over the lane group), so the list is the same
+// for any LANES and its order is fixed by the configuration
+template <typename T, int LANES>
 __global__ __launch_bounds__(kThreads) void kb_build(const BSys *__restrict__ sys, const BMap *__restrict__ map,
                                                      int into_fc)
 {
     const BMap mp = map[blockIdx.x];
+    if (mp.sys < 0) return;
     const BSys &d = sys[mp.sys];
-    const int64_t i = mp.first + threadIdx.x;
-    if (i >= d.n) return;
+    const int sub = threadIdx.x % LANES;
+    const int64_t i = mp.first + threadIdx.x / LANES;
+    const bool live = i < d.n;
     const int64_t S = d.S;
-    const double4 pi = d.Rw[i];
-    const int ci = d.cell_id[i];
+    const double4 pi = live ? d.Rw[i] : make_double4(0, 0, 0, 0);
+    const int ci = live ? d.cell_id[i] : 0;
     const int cx = ci % d.nc[0], cy = (ci / d.nc[0]) % d.nc[1], cz = ci / (d.nc[0] * d.nc[1]);
     const double rc2 = d.r_cut * d.r_cut;
-    T *lw = static_cast<T *>(d.nbw);
+    T *lw = static_cast<T *>(d.nbw) + i * LANES;
+    uint16_t *li = d.nbl + i * LANES;
+    const int64_t row = S * LANES;
+    // lanes of this particle within the wave: bits [gbase, gbase + LANES)
+    const int gbase = (threadIdx.x % 64) & ~(LANES - 1);
+    const unsigned long long gmask = (LANES == 64 ? ~0ull : ((1ull << LANES) - 1)) << gbase;
     int cnt = 0;
     bool over = false;
     double fx = 0, fy = 0, fz = 0, rowsum = 0;
@@ -490,44 +509,71 @@ __global__ __launch_bounds__(kThreads) void kb_build(const BSys *__restrict__ sy
                 const int nx = (cx + dxo + d.nc[0]) % d.nc[0], ny = (cy + dyo + d.nc[1]) % d.nc[1];
                 const int nz = (cz + dzo + d.nc[2]) % d.nc[2];
                 const int cj = (nz * d.nc[1] + ny) * d.nc[0] + nx;
-                const int b = d.cell_start[cj], e = d.cell_start[cj + 1];
-                for (int q = b; q < e; ++q) {
-                    const int j = d.cell_sorted[q];
-                    if (j == i) continue;
-                    const double4 pj = d.Rw[j];
-                    double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-                    dx -= d.box[0] * rint(dx / d.box[0]);
-                    dy -= d.box[1] * rint(dy / d.box[1]);
-                    dz -= d.box[2] * rint(dz / d.box[2]);
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 >= rc2) continue;
-                    if (r2 < d.wca_rc2) {
-                        // WCA force on i: -dU/dr along (R_i - R_j) = -(dx, dy, dz)
-                        const double s2 = d.wca_s2 / r2, s6 = s2 * s2 * s2;
-                        const double fr = 24.0 * d.wca_eps * (2.0 * s6 * s6 - s6) / r2;
-                        fx -= fr * dx;
-                        fy -= fr * dy;
-                        fz -= fr * dz;
+                const int b = live ? d.cell_start[cj] : 0, e = live ? d.cell_start[cj + 1] : 0;
+                // the lanes of a group run the same number of turns
+                for (int q0 = b; q0 < e; q0 += LANES) {
+                    const int q = q0 + sub;
+                    bool hit = false;
+                    int j = 0;
+                    double w = 0;
+                    if (q < e) {
+                        j = d.cell_sorted[q];
+                        if (j != i) {
+                            const double4 pj = d.Rw[j];
+                            double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+                            dx -= d.box[0] * rint(dx / d.box[0]);
+                            dy -= d.box[1] * rint(dy / d.box[1]);
+                            dz -= d.box[2] * rint(dz / d.box[2]);
+                            const double r2 = dx * dx + dy * dy + dz * dz;
+                            if (r2 < rc2) {
+                                if (r2 < d.wca_rc2) {
+                                    // WCA force on i: -dU/dr along (R_i - R_j) = -(dx, dy, dz)
+                                    const double s2 = d.wca_s2 / r2, s6 = s2 * s2 * s2;
+                                    const double fr = 24.0 * d.wca_eps * (2.0 * s6 * s6 - s6) / r2;
+                                    fx -= fr * dx;
+                                    fy -= fr * dy;
+                                    fz -= fr * dz;
+                                }
+                                if (d.has_pair) {
+                                    w = batch_weight(d, sqrt(r2));
+                                    rowsum += fabs(w);
+                                    hit = true;
+                                }
+                            }
+                        }
                     }
-                    if (!d.has_pair) continue;
-                    const double w = batch_weight(d, sqrt(r2));
-                    rowsum += fabs(w);
-                    if (cnt < d.cap) {
-                        d.nbl[static_cast<int64_t>(cnt) * S + i] = static_cast<uint16_t>(j);
-                        lw[static_cast<int64_t>(cnt) * S + i] = static_cast<T>(w);
-                        ++cnt;
-                    } else {
-                        over = true;
+                    const unsigned long long m = __ballot(hit) & gmask;
+                    if (hit) {
+                        const int pos = cnt + __popcll(m & ((1ull << (threadIdx.x % 64)) - 1) & gmask);
+                        if (pos < d.cap) {
+                            const int64_t o = static_cast<int64_t>(pos / LANES) * row + pos % LANES;
+                            li[o] = static_cast<uint16_t>(j);
+                            lw[o] = static_cast<T>(w);
+                        } else {
+                            over = true;
+                        }
                     }
+                    cnt += __popcll(m);
                 }
             }
-    d.nn[i] = cnt;
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) {
+        fx += __shfl_xor(fx, o, LANES);
+        fy += __shfl_xor(fy, o, LANES);
+        fz += __shfl_xor(fz, o, LANES);
+        rowsum += __shfl_xor(rowsum, o, LANES);
+    }
+    if (!live || sub != 0) {
+        if (live && over) latch(d.flags, d.flag_step, GLD_ERR_CAPACITY, *d.step);
+        return;
+    }
+    d.nn[i] = min(cnt, d.cap);
     double *fc = into_fc ? d.FC : d.FCn;
     fc[i] = fx;
     fc[S + i] = fy;
     fc[2 * S + i] = fz;
     const long long step = *d.step;
-    if (over) latch(d.flags, d.flag_step, GLD_ERR_CAPACITY, step);
+    if (over || cnt > d.cap) latch(d.flags, d.flag_step, GLD_ERR_CAPACITY, step);
     if (rowsum > d.lam_hi) latch(d.flags, d.flag_step, GLD_ERR_INTERVAL, step);
     atomicMax(d.rowmax, __float_as_uint(static_cast<float>(rowsum)));
 }
@@ -620,8 +666,17 @@ hipError_t b_advance(const BSys *sys, int nsys_total, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename T>
+static void build_t(const BMap *const *smap, const int *ns, const BSys *sys, int into_fc, hipStream_t st)
+{
+    if (ns[0] > 0) kb_build<T, 1><<<nb(ns[0]), kThreads, 0, st>>>(sys, smap[0], into_fc);
+    if (ns[1] > 0) kb_build<T, 2><<<nb(ns[1]), kThreads, 0, st>>>(sys, smap[1], into_fc);
+    if (ns[2] > 0) kb_build<T, 4><<<nb(ns[2]), kThreads, 0, st>>>(sys, smap[2], into_fc);
+    if (ns[3] > 0) kb_build<T, 8><<<nb(ns[3]), kThreads, 0, st>>>(sys, smap[3], into_fc);
+}
+
 hipError_t b_neighbors(int fp64, const BSys *sys, const BMap *pmap, int npblocks, const BMap *cmap, int ncblocks,
-                       int nsys_total, int into_fc, hipStream_t st)
+                       const BMap *const *smap, const int *nsblocks, int nsys_total, int into_fc, hipStream_t st)
 {
     if (npblocks <= 0) return hipSuccess;
     kb_cell_clear<<<nb(ncblocks), kThreads, 0, st>>>(sys, cmap);
@@ -629,8 +684,8 @@ hipError_t b_neighbors(int fp64, const BSys *sys, const BMap *pmap, int npblocks
     kb_cell_scan<<<nb(nsys_total), 1024, 0, st>>>(sys);
     kb_cell_scatter<<<nb(npblocks), kThreads, 0, st>>>(sys, pmap);
     kb_cell_rank<<<nb(npblocks), kThreads, 0, st>>>(sys, pmap);
-    if (fp64) kb_build<double><<<nb(npblocks), kThreads, 0, st>>>(sys, pmap, into_fc);
-    else kb_build<float><<<nb(npblocks), kThreads, 0, st>>>(sys, pmap, into_fc);
+    if (fp64) build_t<double>(smap, nsblocks, sys, into_fc, st);
+    else build_t<float>(smap, nsblocks, sys, into_fc, st);
     return hipGetLastError();
 }
 

@@ -26,6 +26,9 @@ struct BSys {
     int bf, wlen, cap, n_r;     // filter block, white-noise ring slots, pair capacity, distance grid
     int nc[3], noff[3], ncell;  // cell grid (cells of edge >= r_cut), stencil offsets per axis
     int noise_on, has_pair;
+    int lanes;                  // lanes per particle of the pair mat-vecs and the list build (1, 2, 4, 8);
+                                // the pair lists are lane-interleaved: entry q of particle i at
+                                // ((q / lanes) S + i) lanes + q % lanes
     double box[3];
     double dt, mass, kT, a, b, g0;
     double r_cut, r_cut_min, r0, dr, lam_hi;
@@ -46,8 +49,8 @@ struct BSys {
     void *cb[3];                // T4 [S]: Clenshaw vectors
     void *vk;                   // T4 [K][S]: premixed chain inputs
     double *wtab;               // [n_r]
-    uint16_t *nbl;              // [cap][S] neighbour indices (ELL, column = particle)
-    void *nbw;                  // T [cap][S] pair weights w(R_ij)
+    uint16_t *nbl;              // [cap / lanes][S][lanes] neighbour indices (cap a multiple of 8)
+    void *nbw;                  // T, the same layout: pair weights w(R_ij)
     int *nn;                    // [S] neighbour counts
     int *cell_id, *cell_slot, *cell_count, *cell_start, *cell_list, *cell_sorted;
     BTerm *terms;               // [K]
@@ -81,10 +84,11 @@ hipError_t b_spmv(int fp64, int lanes, const BSys *sys, const BMap *map, int nbl
 hipError_t b_update_r(int fp64, const BSys *sys, const BMap *map, int nblocks, hipStream_t st);
 hipError_t b_update_v(int fp64, const BSys *sys, const BMap *map, int nblocks, hipStream_t st);
 hipError_t b_advance(const BSys *sys, int nsys_total, hipStream_t st);
-// neighbour list at the current positions (cells, ELL pair list, F^C into
-// `fcn` = FCn (step) or FC (set-up), row-sum check against lam_hi)
+// neighbour list at the current positions (cells, pair lists, F^C into FCn
+// (step) or FC (into_fc, set-up), row-sum check against lam_hi); the lists
+// are built per lane class with the mat-vecs' maps smap[c] / nsblocks[c]
 hipError_t b_neighbors(int fp64, const BSys *sys, const BMap *pmap, int npblocks, const BMap *cmap, int ncblocks,
-                       int nsys_total, int into_fc, hipStream_t st);
+                       const BMap *const *smap, const int *nsblocks, int nsys_total, int into_fc, hipStream_t st);
 
 }  // namespace batch
 }  // namespace gld

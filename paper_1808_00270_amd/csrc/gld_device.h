@@ -116,16 +116,19 @@ __device__ __forceinline__ int ring_slot(long long t, int len)
 // a chunk's rows are one contiguous copy.
 // Which part of a block's product one launch computes.  The block starts at
 // n0 + ahead * bf (n0 the start of the block holding the current step).
-// nslice == 1: all channels, the window chunks of split `split`.
-// nslice > 1 (spread over the bf steps of the block before, step i of it):
-// channels [c cs, (c + 1) cs) with c = i % nslice, and the window chunks of
-// split q = i / nslice of nsplit (nslice nsplit = bf), so that every step of
-// a block computes the same share of the next block's product.  Outputs go
+// Not spread: all channels, the window chunks of split `split`.
+// Spread over the block before (launched every step, working at the steps
+// that are multiples of `period`, share i = (step mod bf) / period of
+// bf / period): channels [c cs, (c + 1) cs) with c = i % nslice, and the
+// window chunks of split q = i / nslice of nsplit, so that every `period`
+// steps of a block compute the same share of the next block's product.  Outputs go
 // to U + ((block parity) nsplit + q) ustride: two blocks' outputs alternate,
 // and the nsplit partial sums over the window are added by the consumer.
 struct FirPart {
     int ahead = 0, nslice = 1, nsplit = 1;
-    int split = 0;  // with nslice == 1: the split this launch computes
+    int split = 0;   // not spread: the split this launch computes
+    int spread = 0;  // spread: every `period` steps the share (i % nslice, i / nslice),
+    int period = 1;  // i = (step mod bf) / period, with nslice nsplit = bf / period
     int64_t cs = 0, ustride = 0;
 };
 
@@ -147,12 +150,17 @@ __device__ __forceinline__ void fir_mfma_body(int64_t n, int64_t S, int bf, int 
     // the block of steps computed, this launch's channels and window chunks,
     // and where its outputs go (see FirPart)
     const long long n0 = cur - cur % bf + part.ahead * bf;
-    const int i = static_cast<int>(cur % bf);
-    const int cslice = part.nslice > 1 ? i % part.nslice : 0, ksplit = part.nslice > 1 ? i / part.nslice : part.split;
+    int cslice = 0, ksplit = part.split;
+    if (part.spread) {
+        if (cur % part.period != 0) return;  // the whole grid, before any barrier
+        const int i = static_cast<int>(cur % bf) / part.period;
+        cslice = i % part.nslice;
+        ksplit = i / part.nslice;
+    }
     const int nch = (span + kFirChunk - 1) / kFirChunk;
     const int kbeg = (ksplit * nch / part.nsplit) * kFirChunk, kend = ((ksplit + 1) * nch / part.nsplit) * kFirChunk;
     U += (((n0 / bf) & 1) * part.nsplit + ksplit) * part.ustride;
-    const int64_t climit = part.nslice > 1 ? min(M, (cslice + 1) * part.cs) : M;
+    const int64_t climit = min(M, (cslice + 1) * part.cs);
     const int64_t m0 = cslice * part.cs + (tile * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
     const bool wlive = m0 < climit;  // a wave past the channels only joins the staging
     const int hi = lane >> 5, lo = lane & 31;
@@ -297,13 +305,18 @@ __device__ __forceinline__ void fir_mfma64_body(int64_t n, int64_t S, int bf, in
     const int64_t M = 3 * S;
     const int tid = threadIdx.x, lane = tid & 63;
     const long long n0 = cur - cur % bf + part.ahead * bf;
-    const int i = static_cast<int>(cur % bf);
-    const int cslice = part.nslice > 1 ? i % part.nslice : 0, ksplit = part.nslice > 1 ? i / part.nslice : part.split;
+    int cslice = 0, ksplit = part.split;
+    if (part.spread) {
+        if (cur % part.period != 0) return;  // the whole grid, before any barrier
+        const int i = static_cast<int>(cur % bf) / part.period;
+        cslice = i % part.nslice;
+        ksplit = i / part.nslice;
+    }
     const int nch = (span + kFirChunk64 - 1) / kFirChunk64;
     const int kbeg = (ksplit * nch / part.nsplit) * kFirChunk64;
     const int kend = ((ksplit + 1) * nch / part.nsplit) * kFirChunk64;
     U += (((n0 / bf) & 1) * part.nsplit + ksplit) * part.ustride;
-    const int64_t climit = part.nslice > 1 ? min(M, (cslice + 1) * part.cs) : M;
+    const int64_t climit = min(M, (cslice + 1) * part.cs);
     const int64_t m0 = cslice * part.cs + (tile * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
     const bool wlive = m0 < climit;
     const int g = lane >> 4, lo = lane & 15;

@@ -484,8 +484,10 @@ hipError_t launch_fir(const Dev &d, int mode, hipStream_t st)
     FirPart part;
     part.ustride = static_cast<int64_t>(fir_rows(d.fp64)) * M;
     part.ahead = mode == 1 ? 0 : 1;
-    part.nslice = mode == 0 ? d.fir_block : 1;
-    part.cs = mode == 0 ? (M / d.fir_block + 1 + kFirMfmaThreads - 1) / kFirMfmaThreads * kFirMfmaThreads : M;
+    part.spread = mode == 0;
+    part.period = fir_period(d.fir_block);
+    part.nslice = mode == 0 ? d.fir_block / part.period : 1;
+    part.cs = mode == 0 ? (M / part.nslice + 1 + kFirMfmaThreads - 1) / kFirMfmaThreads * kFirMfmaThreads : M;
     const unsigned grid = static_cast<unsigned>((part.cs + kFirMfmaThreads - 1) / kFirMfmaThreads);
     // window: t = n0 - half .. n0 + bf - 1 + half (2 half + 1 taps, bf outputs)
     const int span = 2 * d.fir_half + d.fir_block;
@@ -538,7 +540,9 @@ hipError_t launch_history_block(const Dev &d, int mode, hipStream_t st)
     part.ustride = static_cast<int64_t>(2 * d.hist_block) * M;
     part.ahead = mode == 1 ? 0 : 1;
     part.nsplit = kHistSplit;
-    part.nslice = mode == 0 ? d.hist_block / kHistSplit : 1;
+    part.spread = mode == 0;
+    part.period = kHistPeriod;
+    part.nslice = mode == 0 ? d.hist_block / (kHistPeriod * kHistSplit) : 1;
     part.cs = mode == 0 ? (M / part.nslice + 1 + kFirMfmaThreads - 1) / kFirMfmaThreads * kFirMfmaThreads : M;
     const unsigned grid = static_cast<unsigned>((part.cs + kFirMfmaThreads - 1) / kFirMfmaThreads);
     for (int q = 0; q < (mode == 0 ? 1 : kHistSplit); ++q) {
