@@ -63,6 +63,9 @@ gld_status noise_build(const gld_params &p, double lo, double hi, double tol, No
 void set_last_error(const std::string &msg);
 // Parameter checks shared by every system type (gld_api.cpp).
 gld_status validate_params(const gld_params *p);
+// The same checks for the general system type: pair tables of any rank and
+// a distance-dependent self memory are accepted.
+gld_status validate_params_general(const gld_params *p);
 // The general pair table as its separable form w x g (max |w| = 1), if it
 // has rank one; `any` false for an all-zero table.
 gld_status separable_pair_table(const gld_params *p, std::vector<double> &w, std::vector<double> &g, bool &any);
@@ -212,6 +215,12 @@ constexpr int kHistBlock32 = 32, kHistBlock64 = 16;
 constexpr int kHistSplit = 4;
 // accumulator rows of the filter bank's product (rows of one output block)
 __host__ __device__ inline int fir_rows(int fp64) { return fp64 ? 32 : 64; }
+// steps between the launches that compute a share of the next filter block
+// (a divisor of the block of at most 5: 1, 2, 4 or 5, each a divisor of 20;
+// the block's product is split into block / period shares)
+__host__ __device__ inline int fir_period(int bf) { return bf <= 5 ? bf : (bf / 2 <= 5 ? bf / 2 : bf / 4); }
+// the same for the history's block product (blocks of 32 or 16 steps)
+constexpr int kHistPeriod = 4;
 // rows of its zero-padded taps (the filter bank's layout, nslots taps)
 inline size_t hist_tap_rows(int nslots, int hb) { return static_cast<size_t>(hb - 1 + nslots + kFirChunk + hb - 1); }
 // out = a P x + b x + cz z + sum_q coef[q] us_q  (x, z, us: sorted T4; x, z may be null

@@ -13,6 +13,14 @@ open (it refers to earlier work for it); here h is a fixed window, 1 up to a
 correction time t_cor and decaying as exp(-(t - t_cor) / t_cor) after it
 (t_cor = infinity: h = 1), the same at every iteration.
 
+A kernel is only usable if its noise exists, i.e. if the spectrum of the
+discrete correlation sequence (Sec. II.C, eq. FT) is positive.  The
+correction of a measured (noisy) correlation function can push that
+spectrum below zero at some frequencies; the paper does not say what to do
+then.  :func:`reconstruct` projects each corrected kernel onto positive
+spectra by default (:func:`project_positive`: the spectrum clipped from
+below at a small fraction of its largest value, transformed back).
+
 The driver is host logic around GLD runs: `simulate(k_of_t)` is any callable
 that runs the GLD engine with the continuous kernel samples K(m dt),
 m = 0..m_max-1, and returns the velocity correlation Y(m dt) it measured
@@ -53,6 +61,32 @@ def window(m_max: int, dt: float, t_cor: float = math.inf) -> np.ndarray:
     return np.where(t <= t_cor, 1.0, np.exp(-(t - t_cor) / t_cor))
 
 
+def spectrum(k_of_t: np.ndarray) -> np.ndarray:
+    """S_w = K(0) + 2 sum_{m>=1} K(m dt) cos(2 pi w m / P), w = 0..M-1,
+    P = 2M - 1: the DFT of the even continuation of the samples, which is
+    kT / dt times the library's per-frequency self spectrum of to_table(K)."""
+    k = np.asarray(k_of_t, dtype=np.float64)
+    M = len(k)
+    P = 2 * M - 1
+    c = np.concatenate([k, k[:0:-1]])  # K_0..K_{M-1}, K_{M-1}..K_1: period P
+    return np.fft.rfft(c, n=P).real[:M]
+
+
+def project_positive(k_of_t: np.ndarray, floor: float = 1e-3) -> np.ndarray:
+    """The kernel whose spectrum is max(S_w, floor max_w |S_w|): unchanged
+    when the spectrum already clears the floor."""
+    k = np.asarray(k_of_t, dtype=np.float64)
+    M = len(k)
+    P = 2 * M - 1
+    S = spectrum(k)
+    lo = floor * float(np.max(np.abs(S)))
+    if np.all(S >= lo):
+        return k.copy()
+    S = np.maximum(S, lo)
+    full = np.concatenate([S, S[:0:-1]])  # even spectrum of period P
+    return np.fft.ifft(full).real[:M] * 1.0
+
+
 @dataclasses.dataclass
 class IMRVResult:
     kernels: List[np.ndarray]      # K_n(t_m), n = 0..iterations
@@ -62,12 +96,13 @@ class IMRVResult:
 
 def reconstruct(target: np.ndarray, k0: np.ndarray, simulate: Callable[[np.ndarray], np.ndarray], *, dt: float,
                 mass: float = 1.0, kT: float = 1.0, alpha: float = 6.0, iterations: int = 20,
-                t_cor: float = math.inf, callback: Optional[Callable[[int, np.ndarray, float], None]] = None
-                ) -> IMRVResult:
+                t_cor: float = math.inf, callback: Optional[Callable[[int, np.ndarray, float], None]] = None,
+                positive: bool = True) -> IMRVResult:
     """Run `iterations` IMRV corrections from the kernel samples k0 towards
     the target correlation function (target[m] = Y(m dt), at least
     len(k0) + 1 points).  Returns every kernel, its correlation function and
-    its error."""
+    its error.  positive: project every corrected kernel onto positive
+    spectra (project_positive)."""
     m_max = len(k0)
     target = np.asarray(target, dtype=np.float64)
     assert len(target) >= m_max + 1, "the target needs m_max + 1 points"
@@ -87,6 +122,8 @@ def reconstruct(target: np.ndarray, k0: np.ndarray, simulate: Callable[[np.ndarr
         if it == iterations:
             break
         k = k + h * (phi_t - phi(y, dt, mass, kT, alpha))
+        if positive:
+            k = project_positive(k)
     return res
 
 

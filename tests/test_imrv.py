@@ -86,3 +86,26 @@ def test_decoupled_kernels_recombine_exactly():
     a, b = np.array([3.0, 1.0, -0.5]), np.array([1.0, 0.5, 0.25])
     ks, kp = imrv.pair_kernels_from_decoupled(a + b, a - b)
     assert np.allclose(ks, a) and np.allclose(kp, b)
+
+
+def test_positive_projection():
+    """The spectrum convention: S_w of K(t) = exp(-t/tau) samples equals the
+    direct cosine sum; a kernel with a positive spectrum is left alone; one
+    with negative values is mapped to one whose spectrum is the clipped one
+    (inverse transform of an even real spectrum of period 2M - 1)."""
+    t = np.arange(M) * DT
+    k = np.exp(-t / 0.05)   # spectrum ratio min/max = ((1-q)/(1+q))^2 ~ 1e-2, q = exp(-DT/0.05)
+    P = 2 * M - 1
+    S = imrv.spectrum(k)
+    w = np.arange(M)[:, None]
+    direct = k[0] + 2 * (k[None, 1:] * np.cos(2 * np.pi * w * np.arange(1, M)[None, :] / P)).sum(axis=1)
+    np.testing.assert_allclose(S, direct, rtol=1e-12, atol=1e-12)
+    assert np.all(S > 0)
+    np.testing.assert_array_equal(imrv.project_positive(k), k)
+    bad = k - 0.3 * np.cos(2 * np.pi * 3 * np.arange(M) / P)  # dents the spectrum at w = 3
+    Sb = imrv.spectrum(bad)
+    assert Sb.min() < 0
+    fixed = imrv.project_positive(bad, floor=1e-3)
+    Sf = imrv.spectrum(fixed)
+    lo = 1e-3 * np.abs(Sb).max()
+    np.testing.assert_allclose(Sf, np.maximum(Sb, lo), rtol=1e-10, atol=1e-10)
