@@ -352,6 +352,110 @@ def run_batch(args):
     }
 
 
+def run_general(args):
+    """The general memory model (rank-two pair table, Delta K^s, noise by
+    Algorithm 1 per frequency on the GPU), FP64."""
+    import torch
+    from paper_1808_00270_amd import general
+    from paper_1808_00270_amd import workloads as wl
+
+    n, rho, M = args.general_n, args.general_rho, args.general_m
+    w = wl.Workload(name=f"general_n{n}_rho{rho}_m{M}", n=n, rho=rho, m_max=M, steps=0, seed=3100)
+    ks, kp, dks, r0, dr = wl.general_tables(M, 101, w.r_cut, w.dt)
+    R, V = w.initial_state()
+    log(f"[bench] general: create {w.name}")
+    t0 = time.perf_counter()
+    s = general.GeneralSystem(n=n, box=w.box, dt=w.dt, mass=w.mass, kT=w.kT, k_self=ks, k_pair=kp, dk_self=dks,
+                              r0=r0, dr=dr, r_cut=w.r_cut, wca_sigma=w.wca_sigma, wca_eps=w.wca_eps, seed=w.seed,
+                              r=R, v=V)
+    t_create = time.perf_counter() - t0
+    s.step(args.general_warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.general_steps)
+    s.sync()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.general_steps
+    log(f"[bench] general: {ms:.3f} ms/step over {args.general_steps} steps")
+    s.set_timing(True)
+    s.step(args.general_kernel_steps)
+    kt = s.kernel_times()
+    s.set_timing(False)
+    info = s.info()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    per = {k: v / args.general_kernel_steps for k, (v, c) in kt.items()}
+    lz = kt["lanczos"]
+    lz_ms = lz[0] / max(lz[1], 1)
+    # per frequency and Lanczos iteration the mat-vec streams the pair list
+    # (j, bin, fraction: 16 bytes a pair) and touches the Krylov vectors:
+    # reads v and writes K v (mat-vec), reads K v, v_k, v_{k-1} and writes
+    # v_{k+1} (recurrence and scaling, 2 passes), then reads the basis once
+    # for x = |b| V y: (6 + 1) * 3n doubles; iterations counted at the last
+    # step's largest dimension (an upper bound)
+    k = info["last_iters"]
+    lz_bytes = M * (k * (16 * info["pairs"] + 7 * 3 * n * 8) + 2 * 3 * n * 8)
+    return {
+        "workload": w.name, "n": n, "rho": rho, "m_max": M, "n_r": 101, "dtype": "f64",
+        "value": n * 1e3 / ms, "unit": "particle-steps/s", "ms_per_step": ms, "create_s": t_create,
+        "lanczos_max_dim_last_step": k, "pairs": info["pairs"], "max_per_particle": info["max_per_particle"],
+        "kernels_ms_per_step": per,
+        "roofline_lanczos": {"kernel": "lanczos (one work-group per frequency)", "bound": "hbm",
+                             "bytes_per_launch_upper": lz_bytes, "avg_ms": lz_ms,
+                             "achieved": lz_bytes / (lz_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": lz_bytes / (lz_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "note": "pair list and Krylov vectors mostly served from L2/MALL; the byte count "
+                                     "takes every iteration at the largest dimension"},
+    }
+
+
+def run_serve(args):
+    """Continuous-batching server on the first requests of the serving
+    workload (Poisson arrivals, uneven N, m_max and step counts scaled by
+    --serve-steps-scale)."""
+    import torch
+    from paper_1808_00270_amd import batch
+    from paper_1808_00270_amd import workloads as wl
+
+    reqs = wl.serve_requests(args.serve_requests, steps_scale=args.serve_steps_scale)
+    sv = batch.Server(args.serve_slots, args.serve_gib << 30, chunk_steps=args.serve_chunk)
+    keep, ids = [], []
+    for t, steps, w in reqs:
+        p, k = batch.workload_params(w, fp64=False)
+        R, V = w.initial_state()
+        rid, foot = sv.submit(p, R, V, steps, t)
+        ids.append((rid, w, steps))
+        keep.append(k)
+    log(f"[bench] serve: {len(reqs)} requests submitted")
+    torch.cuda.synchronize()
+    sv.run()
+    makespan, bsteps = sv.stats()
+    lat, queue, service, work, failed = [], [], [], 0, 0
+    for rid, w, steps in ids:
+        rec, _ = sv.request(rid, state=False)
+        if rec["status"] != 0:
+            failed += 1
+            continue
+        lat.append(1e3 * (rec["done_s"] - rec["arrival_s"]))
+        queue.append(1e3 * (rec["admitted_s"] - rec["arrival_s"]))
+        service.append(1e3 * (rec["done_s"] - rec["admitted_s"]))
+        work += w.n * steps
+    sv.close()
+    del sv
+    torch.cuda.empty_cache()
+    log(f"[bench] serve: makespan {makespan:.2f}s, {bsteps} batch steps, {failed} refused")
+    return {
+        "workload": f"serve_poisson20_first{args.serve_requests}_steps_x{args.serve_steps_scale}",
+        "requests": len(reqs), "served": len(lat), "refused": failed, "slots": args.serve_slots,
+        "chunk_steps": args.serve_chunk, "makespan_s": makespan, "batch_steps": bsteps,
+        "value": work / makespan, "unit": "particle-steps/s",
+        "latency_ms": pct(lat), "queueing_ms": pct(queue), "service_ms": pct(service),
+        "note": "arrivals at 20/s; each request's steps log-uniform in [1e3, 1e5] times the scale",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +473,17 @@ def main():
     ap.add_argument("--batch-systems", type=int, default=256, help="systems of the batched leg (0: skip)")
     ap.add_argument("--batch-gib", type=int, default=48, help="workspace of the batched leg, GiB")
     ap.add_argument("--batch-kernel-steps", type=int, default=10)
+    ap.add_argument("--general-n", type=int, default=10000, help="particles of the general-model leg (0: skip)")
+    ap.add_argument("--general-rho", type=float, default=0.05)
+    ap.add_argument("--general-m", type=int, default=500)
+    ap.add_argument("--general-steps", type=int, default=10)
+    ap.add_argument("--general-warmup", type=int, default=2)
+    ap.add_argument("--general-kernel-steps", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=64, help="requests of the serving leg (0: skip)")
+    ap.add_argument("--serve-steps-scale", type=float, default=0.01)
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-gib", type=int, default=32)
+    ap.add_argument("--serve-chunk", type=int, default=50)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly (counter runs)")
     ap.add_argument("--window", type=int, default=8,
@@ -461,6 +576,10 @@ def main():
         rb = run_batch(args)
         rb["fp32_batched_over_fp64_single"] = rb["value"] / out["fp64_plain"]["value"] if r64 is not None else None
         out["batched"] = rb
+    if args.general_n > 0:
+        out["general"] = run_general(args)
+    if args.serve_requests > 0:
+        out["serving"] = run_serve(args)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(args)

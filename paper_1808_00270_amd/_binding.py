@@ -135,6 +135,29 @@ EXPORTED_SERVE = [
 ]
 
 
+# include/gld_general.h
+EXPORTED_GENERAL = [
+    "gld_general_workspace_size", "gld_general_create", "gld_general_step", "gld_general_sync",
+    "gld_general_read_state", "gld_general_write_state", "gld_general_frequency_vectors", "gld_general_get_info",
+    "gld_general_set_timing", "gld_general_kernel_times", "gld_general_destroy",
+]
+GLD_GENERAL_MAX_N = 32768
+GLD_GENERAL_MAX_ITERS = 128
+GENERAL_KERNEL_NAMES = ["dissipative", "dft", "lanczos", "combine", "pairs", "update"]
+GLD_G_COUNT = len(GENERAL_KERNEL_NAMES)
+
+
+class gld_general_info(C.Structure):
+    _fields_ = [
+        ("max_iters", C.c_int32),
+        ("last_iters", C.c_int32),
+        ("pairs", C.c_int64),
+        ("max_per_particle", C.c_int32),
+        ("capacity", C.c_int32),
+        ("tol", C.c_double),
+    ]
+
+
 class gld_request_info(C.Structure):
     _fields_ = [
         ("id", C.c_int64),
@@ -206,6 +229,19 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gld_server_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.gld_server_destroy.argtypes = [vp]
     for name in EXPORTED_SERVE:
+        getattr(lib, name).restype = C.c_int
+    lib.gld_general_workspace_size.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+    lib.gld_general_create.argtypes = [P, C.c_int32, _dp, _dp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.gld_general_step.argtypes = [vp, C.c_int64]
+    lib.gld_general_sync.argtypes = [vp]
+    lib.gld_general_read_state.argtypes = [vp, S]
+    lib.gld_general_write_state.argtypes = [vp, S]
+    lib.gld_general_frequency_vectors.argtypes = [vp, C.c_int32, C.c_int32, _dp]
+    lib.gld_general_get_info.argtypes = [vp, C.POINTER(gld_general_info)]
+    lib.gld_general_set_timing.argtypes = [vp, C.c_int]
+    lib.gld_general_kernel_times.argtypes = [vp, _dp, C.POINTER(C.c_int64)]
+    lib.gld_general_destroy.argtypes = [vp]
+    for name in EXPORTED_GENERAL:
         getattr(lib, name).restype = C.c_int
     lib.gld_status_string.restype = C.c_char_p
     lib.gld_status_string.argtypes = [C.c_int]

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgld.so")
-SOURCES = ["gld_api.cpp", "gld_noise_plan.cpp", "gld_kernels.hip", "gld_pairs.hip", "gld_batch.cpp", "gld_batch.hip"]
+SOURCES = ["gld_api.cpp", "gld_noise_plan.cpp", "gld_kernels.hip", "gld_pairs.hip", "gld_batch.cpp", "gld_batch.hip",
+           "gld_general.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -59,7 +59,9 @@ bool finite_all(const double *p, int64_t n)
 
 gld_status separable_form(const gld_params *p, std::vector<double> &w, std::vector<double> &g, bool &any);
 
-gld_status validate(const gld_params *p)
+// general: the checks of the general system type (gld_general.h), which
+// takes pair tables of any rank and a distance-dependent self memory
+gld_status validate(const gld_params *p, bool general = false)
 {
     if (!p) return fail(GLD_ERR_INVALID_ARG, "params is NULL");
     if (p->n < 1 || p->n > (int64_t(1) << 30)) return fail(GLD_ERR_INVALID_ARG, "n must be in [1, 2^30]");
@@ -99,17 +101,19 @@ gld_status validate(const gld_params *p)
         if (p->k_pair_g || p->k_pair_w)
             return fail(GLD_ERR_INVALID_ARG, "give either the general table k_pair or its separable form k_pair_w, k_pair_g");
         if (!finite_all(p->k_pair, static_cast<int64_t>(table))) return fail(GLD_ERR_INVALID_ARG, "k_pair not finite");
-        std::vector<double> w, g;
-        bool any = false;
-        gld_status st = separable_form(p, w, g, any);
-        if (st != GLD_OK) return st;
+        if (!general) {
+            std::vector<double> w, g;
+            bool any = false;
+            gld_status st = separable_form(p, w, g, any);
+            if (st != GLD_OK) return st;
+        }
     }
     if (p->dk_self) {
         if (!finite_all(p->dk_self, static_cast<int64_t>(table))) return fail(GLD_ERR_INVALID_ARG, "dk_self not finite");
-        for (size_t i = 0; i < table; ++i)
+        for (size_t i = 0; i < table && !general; ++i)
             if (p->dk_self[i] != 0.0)
                 return fail(GLD_ERR_INVALID_ARG, "distance-dependent self memory (dk_self): not supported by this "
-                                                 "system type");
+                                                 "system type (the general system of gld_general.h takes it)");
     }
     if ((p->noise_a == nullptr) != (p->noise_b == nullptr))
         return fail(GLD_ERR_INVALID_ARG, "noise_a and noise_b must both be given or both NULL");
@@ -152,7 +156,8 @@ gld_status separable_form(const gld_params *p, std::vector<double> &w, std::vect
     if (worst > 1e-13 * big)
         return fail(GLD_ERR_INVALID_ARG, "non-separable pair kernel table (rank > 1; largest deviation from the "
                                          "rank-one form " + std::to_string(worst / big) + " of its largest entry): "
-                                         "not supported by this system type");
+                                         "not supported by this system type (the general system of gld_general.h "
+                                         "takes it)");
     return GLD_OK;
 }
 
@@ -294,6 +299,7 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
 namespace gld {
 
 gld_status validate_params(const gld_params *p) { return validate(p); }
+gld_status validate_params_general(const gld_params *p) { return validate(p, true); }
 
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 

@@ -188,3 +188,36 @@ def serve_requests(count: int, steps_scale: float = 1.0, seed: int = 5000):
                 break
         out.append((t, max(1, steps), w))
     return out
+
+
+def general_tables(m_max: int, n_r: int, r_cut: float, dt: float, pair2: float = 0.3, dk: float = 2.0,
+                   f_pair: float = 1.0, t_scale: float = 1.0):
+    """Tables of the general memory model (a pair kernel of rank two and a
+    distance-dependent self memory) on the grid r_b = b r_cut / (n_r - 1):
+
+    * K^s(t)      = self_kernel(t)
+    * K^p(r, t)   = f_pair [w(r) g(t) + pair2 w2(r) g2(t)],  w, g as above,
+                    w2(r) = 4 (r/r_c)(1 - r/r_c) (largest at r_c/2),
+                    g2(t) = exp(-t/0.15)
+    * dK^s(r, t)  = (dk / 10) w(r) K^s(t)
+
+    t_scale < 1 compresses every kernel in time, K(t) -> K(t / t_scale)
+    (for short memories: a kernel cut off well before it has decayed can
+    have a non-positive spectrum).
+
+    Returns (k_self[m_max], k_pair[n_r][m_max], dk_self[n_r][m_max] or None,
+    r0 = 0, dr); the last grid point is zeroed like the separable tables."""
+    dr = r_cut / (n_r - 1)
+    r = np.arange(n_r) * dr
+    x = np.clip(r / r_cut, 0.0, 1.0)
+    w = (1.0 - x) ** 2
+    w2 = 4.0 * x * (1.0 - x)
+    w[-1] = 0.0
+    w2[-1] = 0.0
+    ts = float(t_scale)
+    k_self = discretize(lambda t: self_kernel(t / ts), dt, m_max)
+    g = discretize(lambda t: pair_time_kernel(t / ts), dt, m_max)
+    g2 = discretize(lambda t: np.exp(-t / (0.15 * ts)), dt, m_max)
+    k_pair = f_pair * (np.outer(w, g) + pair2 * np.outer(w2, g2))
+    dks = np.outer(w, (dk / 10.0) * k_self) if dk else None
+    return k_self, k_pair, dks, 0.0, dr

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(pkg):
     for name in declared:
         assert hasattr(lib, name), name
     assert declared == (set(pkg._binding.EXPORTED) | set(pkg._binding.EXPORTED_BATCH)
-                        | set(pkg._binding.EXPORTED_SERVE))
+                        | set(pkg._binding.EXPORTED_SERVE) | set(pkg._binding.EXPORTED_GENERAL))
 
 
 def _params(pkg, **over):
@@ -235,3 +235,49 @@ def test_general_tables_and_caller_filters_are_validated(pkg):
     for it, ok in ((0, True), (40, True), (200, True), (201, False), (-1, False)):
         p6, k6 = _params(pkg, check_iters=it)
         assert (lib.gld_workspace_size(C.byref(p6), C.byref(nb)) == B.GLD_OK) == ok, it
+
+
+def test_general_system_validation_and_workspace(pkg):
+    """The general system type (gld_general.h) takes pair tables of any rank
+    and Delta K^s, computes in FP64 only, and sizes its workspace by the
+    per-frequency Lanczos bases m_max * max_iters * 3n doubles."""
+    from paper_1808_00270_amd import workloads as wl
+    B = pkg._binding
+    lib = pkg.lib()
+    d = C.POINTER(C.c_double)
+    nb = C.c_size_t()
+    w = wl.config(1, m_max=30)
+    k_self, kp, dks, r0, dr = wl.general_tables(30, 51, 5.0, w.dt)
+    kp, dks = np.ascontiguousarray(kp), np.ascontiguousarray(dks)
+    p, keep = _params(pkg, k_pair_g=None, k_pair_w=None, precision=B.GLD_FP64, n_r=51, dr=dr)
+    p.k_pair = kp.ctypes.data_as(d)
+    p.dk_self = dks.ctypes.data_as(d)
+    # the single-system type refuses both, the general one takes them
+    assert lib.gld_workspace_size(C.byref(p), C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    assert lib.gld_general_workspace_size(C.byref(p), 0, C.byref(nb)) == B.GLD_OK
+    n, M = w.n, 30
+    assert nb.value >= M * 96 * 3 * n * 8
+    base = nb.value
+    assert lib.gld_general_workspace_size(C.byref(p), 40, C.byref(nb)) == B.GLD_OK
+    assert base - nb.value >= M * 56 * 3 * n * 8 - 256 * 4
+    for it, ok in ((0, True), (2, True), (128, True), (1, False), (129, False), (-1, False)):
+        assert (lib.gld_general_workspace_size(C.byref(p), it, C.byref(nb)) == B.GLD_OK) == ok, it
+    # FP64 only, noise window 0/1, particle bound
+    p.precision = B.GLD_FP32_MIXED
+    assert lib.gld_general_workspace_size(C.byref(p), 0, C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    p.precision = B.GLD_FP64
+    p.noise_window = 4
+    assert lib.gld_general_workspace_size(C.byref(p), 0, C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    p.noise_window = 1
+    p.n = B.GLD_GENERAL_MAX_N + 1
+    p.box = (C.c_double * 3)(100.0, 100.0, 100.0)
+    assert lib.gld_general_workspace_size(C.byref(p), 0, C.byref(nb)) == B.GLD_ERR_INVALID_ARG
+    p.n = n
+    # no noise: no Lanczos bases
+    p.kT = 0.0
+    assert lib.gld_general_workspace_size(C.byref(p), 0, C.byref(nb)) == B.GLD_OK
+    assert nb.value < M * 3 * n * 8 * 4
+    # the shared checks still apply (minimum image)
+    p.kT = 1.0
+    p.box = (C.c_double * 3)(9.0, 9.0, 9.0)
+    assert lib.gld_general_workspace_size(C.byref(p), 0, C.byref(nb)) == B.GLD_ERR_BOX
