@@ -75,12 +75,17 @@ def run_gpu(args, fp64, window=1):
     tag = ("fp64" if fp64 else "fp32-mixed") + (f", noise window {window}" if window > 1 else "")
     log(f"[bench] create {w.name} {tag}")
     t0 = time.perf_counter()
-    s = pkg.System.from_workload(w, fp64=fp64, noise_window=window)
+    s = pkg.System.from_workload(w, fp64=fp64, noise_window=window, verlet_skin=args.skin,
+                                 rebuild_period=args.rebuild_period)
     t_create = time.perf_counter() - t0
     info = s.noise_info()
     log(f"[bench] created in {t_create:.1f}s, noise {info}")
     if args.no_graph:
         s.set_graph(False)
+    # the lattice start melts over the first ~100 steps (list lengths and
+    # the noise plan's choice settle); run it in untimed before the warmup
+    s.step(args.equilibrate)
+    s.sync()
     # warmup
     s.step(args.warmup)
     s.sync()
@@ -93,7 +98,7 @@ def run_gpu(args, fp64, window=1):
     dt_run = time.perf_counter() - t0
     ms_per_step = 1e3 * dt_run / args.steps
     log(f"[bench] {tag}: {ms_per_step:.3f} ms/step over {args.steps} steps")
-    step_now = args.warmup + args.steps
+    step_now = args.equilibrate + args.warmup + args.steps
     # whole spectrum-check cycles (the check runs every 100 steps): from the
     # next multiple of 100, `cycle_steps` steps timed the same way
     ms_cycle = None
@@ -331,6 +336,14 @@ def run_batch(args):
     b.set_timing(False)
     nsys, npart, pairs = b.stats()
     bad = sum(1 for s, w in slot_of.values() if b.read_state(s)["flags"] != 0)
+    # the chain's list streams: per system K - 1 Clenshaw mat-vecs plus the
+    # dissipative one, each over its pairs (16-bit index + 32-bit weight)
+    term_pairs, lanes_hist = 0, {}
+    for s, w in slot_of.values():
+        pr, ln = b.system_stats(s)
+        K = b.noise_info(s)["cheb_terms"]
+        term_pairs += pr * K
+        lanes_hist[ln] = lanes_hist.get(ln, 0) + 1
     ring_bytes = sum(4 * 3 * w.n * (w.m_max - 1) for s, w in slot_of.values())
     per = {k: v / args.batch_kernel_steps for k, (v, c) in kt.items()}
     hist_ms = per["history"]
@@ -343,6 +356,12 @@ def run_batch(args):
         "value": npart * 1e3 / ms, "unit": "particle-steps/s", "ms_per_step": ms,
         "schedule_lane_thresholds": thr, "autotune_ms_per_candidate": cand_ms,
         "kernels_ms_per_step": per,
+        "lanes_per_particle_systems": {str(k): v for k, v in sorted(lanes_hist.items())},
+        "roofline_spmv": {"kernel": "noise_spmv (dissipative + Clenshaw mat-vecs of every system)", "bound": "hbm",
+                          "pair_terms_per_step": term_pairs, "bytes_per_step": 6 * term_pairs,
+                          "achieved": 6 * term_pairs / (per["noise_spmv"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": 6 * term_pairs / (per["noise_spmv"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "note": "list bytes only (index and weight per pair term); the vectors come from L2"},
         "roofline_history": {"kernel": "history (streamed every step)", "bound": "hbm",
                              "bytes_per_step": ring_bytes + npart * 3 * (8 + 4 * 3),
                              "achieved": (ring_bytes + npart * 3 * (8 + 4 * 3)) / (hist_ms * 1e-3) / 1e9,
@@ -387,20 +406,42 @@ def run_general(args):
     del s
     torch.cuda.empty_cache()
     per = {k: v / args.general_kernel_steps for k, (v, c) in kt.items()}
+    cpu = None
+    if not args.no_cpu:
+        # the oracle on a sample of the same workload: F^C + F^D' of 500
+        # particles and Algorithm 1 for 4 of the frequencies, scaled to a step
+        import oracle
+        o = oracle.Oracle(n=n, box=w.box, dt=w.dt, mass=w.mass, kT=w.kT, k_self=ks, k_pair=kp, dk_self=dks, r0=r0,
+                          dr=dr, r_cut=w.r_cut, wca_sigma=w.wca_sigma, wca_eps=w.wca_eps, seed=w.seed,
+                          lanczos_tol=1e-12)
+        rows = np.sort(np.random.default_rng(0).choice(n, size=500, replace=False))
+        hist = np.zeros((M - 1, n, 3))
+        t0 = time.perf_counter()
+        o.forces_rows(R, V, hist, rows)
+        t_rows = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        o.noise(0, R, w0=0, w1=4)
+        t_noise = time.perf_counter() - t0
+        t_step = t_rows * n / 500 + t_noise * M / 4
+        cpu = {"value": n / t_step, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"F^C+F^D' of 500 particles ({t_rows:.1f}s) and Algorithm 1 for 4 of {M} frequencies "
+                         f"({t_noise:.1f}s), scaled to one step = {t_step:.0f}s"}
+        log(f"[bench] general: oracle sample {t_rows + t_noise:.1f}s, {t_step:.0f}s per step")
     lz = kt["lanczos"]
     lz_ms = lz[0] / max(lz[1], 1)
     # per frequency and Lanczos iteration the mat-vec streams the pair list
-    # (j, bin, fraction: 16 bytes a pair) and touches the Krylov vectors:
+    # (j and the grid coordinate: 12 bytes a pair) and touches the Krylov vectors:
     # reads v and writes K v (mat-vec), reads K v, v_k, v_{k-1} and writes
     # v_{k+1} (recurrence and scaling, 2 passes), then reads the basis once
     # for x = |b| V y: (6 + 1) * 3n doubles; iterations counted at the last
     # step's largest dimension (an upper bound)
     k = info["last_iters"]
-    lz_bytes = M * (k * (16 * info["pairs"] + 7 * 3 * n * 8) + 2 * 3 * n * 8)
+    lz_bytes = M * (k * (12 * info["pairs"] + 7 * 3 * n * 8) + 2 * 3 * n * 8)
     return {
         "workload": w.name, "n": n, "rho": rho, "m_max": M, "n_r": 101, "dtype": "f64",
         "value": n * 1e3 / ms, "unit": "particle-steps/s", "ms_per_step": ms, "create_s": t_create,
         "lanczos_max_dim_last_step": k, "pairs": info["pairs"], "max_per_particle": info["max_per_particle"],
+        "cpu_baseline": cpu,
         "kernels_ms_per_step": per,
         "roofline_lanczos": {"kernel": "lanczos (one work-group per frequency)", "bound": "hbm",
                              "bytes_per_launch_upper": lz_bytes, "avg_ms": lz_ms,
@@ -484,6 +525,12 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-gib", type=int, default=32)
     ap.add_argument("--serve-chunk", type=int, default=50)
+    ap.add_argument("--skin", type=float, default=0.6, help="Verlet skin of the single-system runs")
+    ap.add_argument("--equilibrate", type=int, default=200,
+                    help="untimed steps from the lattice start before the warmup (single-system runs)")
+    ap.add_argument("--rebuild-period", type=int, default=20,
+                    help="candidate-list rebuild cadence in steps (the displacement test stays as the safety "
+                         "net; 0: the displacement test alone)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly (counter runs)")
     ap.add_argument("--window", type=int, default=8,
@@ -535,7 +582,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "rho": w.rho, "m_max": w.m_max, "r_cut": w.r_cut, "dt": w.dt,
-                   "precision": "fp32-mixed (f32 history/noise, f64 positions and update)"},
+                   "precision": "fp32-mixed (f32 history/noise, f64 positions and update)",
+                   "verlet_skin": args.skin, "rebuild_period": args.rebuild_period},
         "latency_ms": pct(r32["lat"]),
         "noise": {k: r32["info"][k] for k in ("cheb_terms", "cheb_terms_tight", "lam_hi", "lam_hi_tight", "rank",
                                               "block", "window_half", "err_estimate", "list_index_bits")}

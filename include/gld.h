@@ -155,6 +155,11 @@ typedef struct {
     int32_t noise_terms;
     int32_t check_iters;       /* Lanczos iterations of each spectrum check
                                   (0: 40), at most GLD_MAX_CHECK_ITERS          */
+    int32_t rebuild_period;    /* > 0 (with verlet_skin > 0): the candidate lists
+                                  are also rebuilt at the positions of every step
+                                  that is a multiple of it, so that the rebuilds
+                                  keep a fixed cadence when the skin outlasts the
+                                  period; 0: only the displacement test          */
 } gld_params;
 
 /* Snapshot of a system.  On read, every non-NULL array is filled; on write,

@@ -115,6 +115,10 @@ gld_status gld_batch_kernel_times(gld_batch *b, double *ms_sum, int64_t *launche
 /* Systems, particles and total directed pairs of the batch (synchronises). */
 gld_status gld_batch_stats(gld_batch *b, int32_t *systems, int64_t *particles, int64_t *pairs);
 
+/* One system of the batch: its directed pairs in the current list and the
+ * lanes per particle of its mat-vecs (1, 2, 4 or 8).  Synchronises. */
+gld_status gld_batch_system_stats(gld_batch *b, int32_t slot, int64_t *pairs, int32_t *lanes);
+
 /* Release the batch (the workspace stays the caller's).  Synchronises. */
 gld_status gld_batch_destroy(gld_batch *b);
 

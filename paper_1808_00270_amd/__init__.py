@@ -61,8 +61,8 @@ class System:
     def __init__(self, *, n, box, dt, mass, kT, k_self, r, v, k_pair_g=None, k_pair_w=None, r0=0.0, dr=0.01,
                  r_cut=5.0, r_cut_min=0.0, parallel=False, fp64=False, wca_sigma=1.0, wca_eps=1.0, seed=0,
                  noise_tol=0.0, lam_lo=0.0, lam_hi=0.0, max_neighbors=0, check_interval=0, verlet_skin=None,
-                 noise_window=1, k_pair=None, dk_self=None, noise_filters=None, check_iters=0, device=None,
-                 stream=None):
+                 noise_window=1, k_pair=None, dk_self=None, noise_filters=None, check_iters=0, rebuild_period=0,
+                 device=None, stream=None):
         import torch
 
         self._keep = []
@@ -95,7 +95,7 @@ class System:
             verlet_skin=0.1 * r_cut if verlet_skin is None else float(verlet_skin), noise_window=int(noise_window),
             k_pair=_dp(kp), dk_self=_dp(dks), noise_a=_dp(fa), noise_b=_dp(fb),
             noise_rank=int(fa.shape[0]) if fa is not None else 0, noise_terms=int(fb.shape[0]) if fb is not None else 0,
-            check_iters=int(check_iters))
+            check_iters=int(check_iters), rebuild_period=int(rebuild_period))
         self.n, self.m_max, self.fp64 = int(n), m_max, fp64
         nbytes = C.c_size_t()
         _check(lib().gld_workspace_size(C.byref(self.params), C.byref(nbytes)), "gld_workspace_size")

@@ -70,6 +70,7 @@ class gld_params(C.Structure):
         ("noise_rank", C.c_int32),
         ("noise_terms", C.c_int32),
         ("check_iters", C.c_int32),
+        ("rebuild_period", C.c_int32),
     ]
 
 
@@ -124,7 +125,7 @@ EXPORTED_BATCH = [
     "gld_batch_base_size", "gld_batch_create", "gld_batch_footprint", "gld_batch_add", "gld_batch_remove",
     "gld_batch_step", "gld_batch_sync", "gld_batch_read_state", "gld_batch_write_state",
     "gld_batch_noise_parameters", "gld_batch_autotune", "gld_batch_set_schedule", "gld_batch_stats",
-    "gld_batch_destroy", "gld_batch_set_timing", "gld_batch_kernel_times",
+    "gld_batch_destroy", "gld_batch_set_timing", "gld_batch_kernel_times", "gld_batch_system_stats",
 ]
 GLD_BATCH_CANDIDATES = 8
 
@@ -216,6 +217,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gld_batch_set_schedule.argtypes = [vp, C.POINTER(gld_batch_schedule)]
     lib.gld_batch_stats.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.gld_batch_destroy.argtypes = [vp]
+    lib.gld_batch_system_stats.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
     lib.gld_batch_set_timing.argtypes = [vp, C.c_int]
     lib.gld_batch_kernel_times.argtypes = [vp, _dp, C.POINTER(C.c_int64)]
     for name in EXPORTED_BATCH:

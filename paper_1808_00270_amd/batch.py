@@ -172,6 +172,13 @@ class Batch:
         _check(lib().gld_batch_stats(self.handle, C.byref(ns), C.byref(npart), C.byref(pairs)), "gld_batch_stats")
         return ns.value, npart.value, pairs.value
 
+    def system_stats(self, slot):
+        """(directed pairs, lanes per particle) of one system."""
+        pairs, lanes = C.c_int64(), C.c_int32()
+        _check(lib().gld_batch_system_stats(self.handle, int(slot), C.byref(pairs), C.byref(lanes)),
+               "gld_batch_system_stats")
+        return pairs.value, lanes.value
+
 
 class Server:
     """Continuous-batching server (include/gld_serve.h): requests are queued

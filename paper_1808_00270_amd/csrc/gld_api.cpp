@@ -94,6 +94,7 @@ gld_status validate(const gld_params *p, bool general = false)
         return fail(GLD_ERR_INVALID_ARG, "verlet_skin must be finite and >= 0");
     if (p->noise_window < 0 || p->noise_window > gld::kMaxFirBlock)
         return fail(GLD_ERR_INVALID_ARG, "noise_window must be in [0, " + std::to_string(gld::kMaxFirBlock) + "]");
+    if (p->rebuild_period < 0) return fail(GLD_ERR_INVALID_ARG, "rebuild_period must be >= 0");
     if (p->check_iters < 0 || p->check_iters > GLD_MAX_CHECK_ITERS)
         return fail(GLD_ERR_INVALID_ARG, "check_iters must be in [0, GLD_MAX_CHECK_ITERS]");
     const size_t table = static_cast<size_t>(p->n_r) * p->m_max;
@@ -280,7 +281,7 @@ size_t carve(const gld_params *p, const Geometry &g, char *base, Dev &d)
     L.take(d.cell_sorted, n * 4);
     L.take(d.cell_count, static_cast<size_t>(g.ncell) * 4);
     L.take(d.cell_start, static_cast<size_t>(g.ncell + 1) * 4);
-    L.take(d.partial, gld::kPartials * 8);
+    L.take(d.partial, 2 * gld::kPartials * 8);  // two stages of the check's dot products
     L.take(d.lab, (2 * gld::kMaxCheckIters + 4) * 8);
     L.take(d.d_step, 8);
     L.take(d.d_flags, 8);
@@ -1055,6 +1056,7 @@ gld_status gld_create(const gld_params *params, const double *r0, const double *
     d.maxc = s->geo.maxc;
     d.capS = s->geo.capS;
     d.skin = p.verlet_skin;
+    d.rebuild_period = p.rebuild_period;
     d.ncell = s->geo.ncell;
     for (int c = 0; c < 3; ++c) {
         d.nc[c] = s->geo.nc[c];

@@ -398,7 +398,7 @@ Built build_system(int fp64, const gld_params *params, const double *r0, Sys &y)
     take(static_cast<size_t>(y.cap) * S * 2);
     take(static_cast<size_t>(y.cap) * S * elt);
     take(S * 4);                        // nn
-    for (int k = 0; k < 4; ++k) take(S * 4);  // cell id, slot, list, sorted
+    for (int k = 0; k < 5; ++k) take(S * 4);  // cell id, slot, list, sorted, cpos
     take(static_cast<size_t>(y.ncell) * 4);
     take(static_cast<size_t>(y.ncell + 1) * 4);
     for (int k = 0; k < 4; ++k) take(8);  // step flags flag_step rowmax
@@ -451,6 +451,7 @@ void carve_system(int fp64, Sys &y, char *base)
     d.cell_slot = reinterpret_cast<int *>(take(S * 4));
     d.cell_list = reinterpret_cast<int *>(take(S * 4));
     d.cell_sorted = reinterpret_cast<int *>(take(S * 4));
+    d.cpos = reinterpret_cast<int *>(take(S * 4));
     d.cell_count = reinterpret_cast<int *>(take(static_cast<size_t>(y.ncell) * 4));
     d.cell_start = reinterpret_cast<int *>(take(static_cast<size_t>(y.ncell + 1) * 4));
     d.step = reinterpret_cast<long long *>(take(8));
@@ -1352,6 +1353,23 @@ gld_status gld_batch_stats(gld_batch *b, int32_t *systems, int64_t *particles, i
     if (systems) *systems = ns;
     if (particles) *particles = np;
     if (pairs) *pairs = pr;
+    return GLD_OK;
+}
+
+gld_status gld_batch_system_stats(gld_batch *b, int32_t slot, int64_t *pairs, int32_t *lanes)
+{
+    if (!b || slot < 0 || slot >= b->capacity || !b->sys[slot].used)
+        return bfail(GLD_ERR_INVALID_ARG, "no such system");
+    BHIP(hipStreamSynchronize(b->st));
+    const Sys &y = b->sys[slot];
+    if (pairs) {
+        std::vector<int> nn(static_cast<size_t>(y.n));
+        BHIP(hipMemcpy(nn.data(), y.d.nn, nn.size() * sizeof(int), hipMemcpyDeviceToHost));
+        int64_t pr = 0;
+        for (int v : nn) pr += v;
+        *pairs = pr;
+    }
+    if (lanes) *lanes = y.d.lanes;
     return GLD_OK;
 }
 

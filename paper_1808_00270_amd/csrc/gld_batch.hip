@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void kb_history(const BSys *__restrict__ 
     y.y = g0 * static_cast<T>(d.V[S + i]) + hy * inv_dt;
     y.z = g0 * static_cast<T>(d.V[2 * S + i]) + hz * inv_dt;
     y.w = T(0);
-    static_cast<typename V4t<T>::t *>(d.y4)[i] = y;
+    static_cast<typename V4t<T>::t *>(d.y4)[d.cpos[i]] = y;
 }
 
 // ---------------------------------------------------------------------------
@@ -203,6 +203,7 @@ __global__ __launch_bounds__(kThreads) void kb_premix(const BSys *__restrict__ s
     }
     const T *B = static_cast<const T *>(d.Bmix);
     T4 *vk = static_cast<T4 *>(d.vk);
+    const int64_t p = d.cpos[i];  // the chain runs in cell order
     for (int k = 0; k < d.K; ++k) {
         const T *bk = B + static_cast<int64_t>(k) * d.rcap;
         T sx = T(0), sy = T(0), sz = T(0);
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(kThreads) void kb_premix(const BSys *__restrict__ s
         v.y = sy;
         v.z = sz;
         v.w = T(0);
-        vk[static_cast<int64_t>(k) * S + i] = v;
+        vk[static_cast<int64_t>(k) * S + p] = v;
     }
 }
 
@@ -240,22 +241,44 @@ __global__ __launch_bounds__(kThreads) void kb_spmv(const BSys *__restrict__ sys
     if (k >= d.K && k >= 0) return;  // beyond this system's chain
     if (k >= 0 && !d.noise_on) return;
     const int sub = threadIdx.x % LANES;
-    const int64_t i = mp.first + threadIdx.x / LANES;
-    const bool live = i < d.n;
+    // p: a cell-order position (the vectors and lists are in cell order)
+    const int64_t p = mp.first + threadIdx.x / LANES;
+    const bool live = p < d.n;
     const int64_t S = d.S;
     const T4 *x = static_cast<const T4 *>(k < 0 ? d.y4 : d.cb[ix]);
     const BTerm tm = k >= 0 ? d.terms[k] : BTerm{-1.0, 0.0, 0.0};
     T ax = T(0), ay = T(0), az = T(0);
     if (live && tm.a != 0.0) {
-        // lane sub reads entries sub, sub + LANES, ... of particle i: in the
+        // lane sub reads entries sub, sub + LANES, ... of row p: in the
         // lane-interleaved lists a lane group's reads are LANES consecutive
         // entries, and a wave's 64 consecutive ones
-        const int nn = d.nn[i];
-        const uint16_t *li = d.nbl + i * LANES + sub;
-        const T *lw = static_cast<const T *>(d.nbw) + i * LANES + sub;
+        const int nn = d.nn[p];
+        const uint16_t *li = d.nbl + p * LANES + sub;
+        const T *lw = static_cast<const T *>(d.nbw) + p * LANES + sub;
         const int64_t row = S * LANES;
         int64_t o = 0;
-        for (int q = sub; q < nn; q += LANES, o += row) {
+        int q = sub;
+        // four of the lane's entries at a time: their index and weight
+        // loads, then their gathers, then the sums in entry order (several
+        // loads in flight per lane; the same sums as one entry at a time)
+        for (; q + 3 * LANES < nn; q += 4 * LANES, o += 4 * row) {
+            const int j0 = li[o], j1 = li[o + row], j2 = li[o + 2 * row], j3 = li[o + 3 * row];
+            const T w0 = lw[o], w1 = lw[o + row], w2 = lw[o + 2 * row], w3 = lw[o + 3 * row];
+            const T4 x0 = x[j0], x1 = x[j1], x2 = x[j2], x3 = x[j3];
+            ax += w0 * x0.x;
+            ay += w0 * x0.y;
+            az += w0 * x0.z;
+            ax += w1 * x1.x;
+            ay += w1 * x1.y;
+            az += w1 * x1.z;
+            ax += w2 * x2.x;
+            ay += w2 * x2.y;
+            az += w2 * x2.z;
+            ax += w3 * x3.x;
+            ay += w3 * x3.y;
+            az += w3 * x3.z;
+        }
+        for (; q < nn; q += LANES, o += row) {
             const int j = li[o];
             const T w = lw[o];
             const T4 xj = x[j];
@@ -272,6 +295,7 @@ __global__ __launch_bounds__(kThreads) void kb_spmv(const BSys *__restrict__ sys
     }
     if (!live || sub != 0) return;
     if (k < 0) {
+        const int64_t i = d.cell_sorted[p];  // the particle, for the outputs in particle order
         const T *Dn = static_cast<const T *>(d.Dneg);
         T *FD = static_cast<T *>(d.FD);
         FD[i] = -ax + Dn[i];
@@ -280,21 +304,22 @@ __global__ __launch_bounds__(kThreads) void kb_spmv(const BSys *__restrict__ sys
         return;
     }
     const T a = static_cast<T>(tm.a), b = static_cast<T>(tm.b), cz = static_cast<T>(tm.cz);
-    const T4 vk = static_cast<const T4 *>(d.vk)[static_cast<int64_t>(k) * S + i];
+    const T4 vk = static_cast<const T4 *>(d.vk)[static_cast<int64_t>(k) * S + p];
     T ox = a * ax + vk.x, oy = a * ay + vk.y, oz = a * az + vk.z;
     if (b != T(0)) {
-        const T4 xi = x[i];
+        const T4 xi = x[p];
         ox += b * xi.x;
         oy += b * xi.y;
         oz += b * xi.z;
     }
     if (cz != T(0)) {
-        const T4 zi = static_cast<const T4 *>(d.cb[iz])[i];
+        const T4 zi = static_cast<const T4 *>(d.cb[iz])[p];
         ox += cz * zi.x;
         oy += cz * zi.y;
         oz += cz * zi.z;
     }
     if (k == 0) {
+        const int64_t i = d.cell_sorted[p];
         T *FR = static_cast<T *>(d.FR);
         FR[i] = ox;
         FR[S + i] = oy;
@@ -305,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void kb_spmv(const BSys *__restrict__ sys
         o.y = oy;
         o.z = oz;
         o.w = T(0);
-        static_cast<T4 *>(d.cb[io])[i] = o;
+        static_cast<T4 *>(d.cb[io])[p] = o;
     }
 }
 
@@ -460,6 +485,7 @@ __global__ __launch_bounds__(kThreads) void kb_cell_rank(const BSys *__restrict_
     int r = 0;
     for (int q = b; q < e; ++q) r += d.cell_list[q] < i ? 1 : 0;
     d.cell_sorted[b + r] = static_cast<int>(i);
+    d.cpos[i] = b + r;
 }
 
 __device__ __forceinline__ double batch_weight(const BSys &d, double r)
@@ -491,8 +517,10 @@ __global__ __launch_bounds__(kThreads) void kb_build(const BSys *__restrict__ sy
     const int ci = live ? d.cell_id[i] : 0;
     const int cx = ci % d.nc[0], cy = (ci / d.nc[0]) % d.nc[1], cz = ci / (d.nc[0] * d.nc[1]);
     const double rc2 = d.r_cut * d.r_cut;
-    T *lw = static_cast<T *>(d.nbw) + i * LANES;
-    uint16_t *li = d.nbl + i * LANES;
+    // the particle's row and its neighbours' entries are cell-order positions
+    const int64_t prow = live ? d.cpos[i] : 0;
+    T *lw = static_cast<T *>(d.nbw) + prow * LANES;
+    uint16_t *li = d.nbl + prow * LANES;
     const int64_t row = S * LANES;
     // lanes of this particle within the wave: bits [gbase, gbase + LANES)
     const int gbase = (threadIdx.x % 64) & ~(LANES - 1);
@@ -547,7 +575,7 @@ __global__ __launch_bounds__(kThreads) void kb_build(const BSys *__restrict__ sy
                         const int pos = cnt + __popcll(m & ((1ull << (threadIdx.x % 64)) - 1) & gmask);
                         if (pos < d.cap) {
                             const int64_t o = static_cast<int64_t>(pos / LANES) * row + pos % LANES;
-                            li[o] = static_cast<uint16_t>(j);
+                            li[o] = static_cast<uint16_t>(q);
                             lw[o] = static_cast<T>(w);
                         } else {
                             over = true;
@@ -567,7 +595,7 @@ __global__ __launch_bounds__(kThreads) void kb_build(const BSys *__restrict__ sy
         if (live && over) latch(d.flags, d.flag_step, GLD_ERR_CAPACITY, *d.step);
         return;
     }
-    d.nn[i] = min(cnt, d.cap);
+    d.nn[prow] = min(cnt, d.cap);
     double *fc = into_fc ? d.FC : d.FCn;
     fc[i] = fx;
     fc[S + i] = fy;

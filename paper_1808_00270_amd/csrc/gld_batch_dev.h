@@ -45,14 +45,19 @@ struct BSys {
     void *Afilt;                // padded taps [fir_padded_rows][rcap]
     void *Bmix;                 // [K][rcap]
     void *ks, *gm;              // [M]
-    void *y4;                   // T4 [S]: dissipative input
-    void *cb[3];                // T4 [S]: Clenshaw vectors
-    void *vk;                   // T4 [K][S]: premixed chain inputs
+    // the mat-vec vectors are in the cell order of the last list build
+    // (entry p holds particle cell_sorted[p]; particle i sits at cpos[i]),
+    // so that the neighbours a particle gathers lie close together
+    void *y4;                   // T4 [S]: dissipative input (cell order)
+    void *cb[3];                // T4 [S]: Clenshaw vectors (cell order)
+    void *vk;                   // T4 [K][S]: premixed chain inputs (cell order)
     double *wtab;               // [n_r]
-    uint16_t *nbl;              // [cap / lanes][S][lanes] neighbour indices (cap a multiple of 8)
+    uint16_t *nbl;              // [cap / lanes][S][lanes] neighbours' cell-order positions, rows in
+                                // cell order (cap a multiple of 8)
     void *nbw;                  // T, the same layout: pair weights w(R_ij)
-    int *nn;                    // [S] neighbour counts
+    int *nn;                    // [S] neighbour counts, cell order
     int *cell_id, *cell_slot, *cell_count, *cell_start, *cell_list, *cell_sorted;
+    int *cpos;                  // [S] cell-order position of each particle
     BTerm *terms;               // [K]
     long long *step;
     int *flags;

@@ -8,9 +8,11 @@
 //   displacement ring       [n][Hs][3], dR_t at slot t mod Hs, Hs = m_max - 1
 //                           (a particle's lags are contiguous, so the lanes of
 //                           a wave that split the lags read one segment)
-//   pair list               capacity C per particle: j, distance bin b and
-//                           fraction f (Sec. III.A grid, frozen below
-//                           r_cut_min), unit vector e = (R_i - R_j) / r
+//   pair list               capacity C per particle: j, the grid coordinate
+//                           t = (max(r, r_cut_min) - r0) / dr clamped at 0
+//                           (Sec. III.A grid, frozen below r_cut_min; bin
+//                           b = min(floor t, n_r - 2), fraction t - b) and the
+//                           unit vector e = (R_i - R_j) / r
 //   kernel tables           K^p [n_r][m_max], Delta K^s [n_r][m_max], K^s [m_max]
 //   spectra                 S_w [m_max], K^p_hat and Delta K^s_hat [m_max][n_r]
 //                           (frequency-major: one Lanczos work-group reads one row)
@@ -42,6 +44,9 @@ namespace gen {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kLzThreads = 1024;    // threads of a Lanczos work-group
+constexpr int kLzLanes = 4;         // lanes per particle in its mat-vec
+constexpr int kLzUnroll = 2;        // pair entries a lane has in flight
 constexpr int kAnchor = 256;        // steps between full window transforms
 constexpr int kDftOmega = 8;        // frequencies per thread of the full transform
 constexpr int kDefaultIters = 96;
@@ -57,8 +62,8 @@ struct GDev {
     uint64_t seed = 0;
     double *R = nullptr, *V = nullptr, *FD = nullptr, *FR = nullptr, *FC0 = nullptr, *FC1 = nullptr;
     double *hist = nullptr;
-    int *pj = nullptr, *pb = nullptr, *cnt = nullptr;
-    double *pf = nullptr, *pe = nullptr;
+    int *pj = nullptr, *cnt = nullptr;
+    double *pt = nullptr, *pe = nullptr;  // grid coordinate of the distance, unit vector
     double *kp = nullptr, *dk = nullptr, *ks = nullptr;
     double *shat = nullptr, *khT = nullptr, *dkhT = nullptr;
     double *cosP = nullptr, *tw = nullptr;  // tw: [4][M] cos, sin of theta w and of theta w (M-1)
@@ -76,8 +81,8 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum over the work-group (kThreads lanes) in a fixed order; every thread
-// gets the total.  red: kThreads / 64 doubles of LDS.
+// Sum over a Lanczos work-group (kLzThreads lanes) in a fixed order; every
+// thread gets the total.  red: kLzThreads / 64 doubles of LDS.
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
     v = wave_sum(v);
@@ -87,17 +92,21 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     __syncthreads();
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < kThreads / 64; ++k) s += red[k];
+    for (int k = 0; k < kLzThreads / 64; ++k) s += red[k];
     return s;
 }
 
-// grid position of a distance, as the tables are read: r clamped to
-// [r_cut_min, ...), bin b in [0, n_r - 2], fraction f = t - b
-__device__ __forceinline__ void locate(const GDev &d, double r, int &b, double &f)
+// grid coordinate of a distance: r clamped to [r_cut_min, ...), t >= 0
+__device__ __forceinline__ double grid_coord(const GDev &d, double r)
 {
     if (r < d.r_cut_min) r = d.r_cut_min;
-    double t = (r - d.r0) / d.dr;
-    if (t < 0.0) t = 0.0;
+    const double t = (r - d.r0) / d.dr;
+    return t < 0.0 ? 0.0 : t;
+}
+
+// bin b in [0, n_r - 2] and fraction f = t - b of a grid coordinate t >= 0
+__device__ __forceinline__ void bin_of(const GDev &d, double t, int &b, double &f)
+{
     int k = static_cast<int>(floor(t));
     if (k > d.NR - 2) k = d.NR - 2;
     if (k < 0) k = 0;
@@ -121,51 +130,68 @@ __device__ __forceinline__ void tensor_add(bool par, const double e[3], double k
 }
 
 // ---------------------------------------------------------------------------
-// All-pairs search at positions R: pair list, F^C (WCA), capacity latch.
+// All-pairs search at positions R: pair list (in ascending j), F^C (WCA),
+// capacity latch.  One wave per particle; its lanes test 64 candidates j at
+// a time and the hits take consecutive list entries in j order (ballot and
+// prefix count).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_pairs(GDev d, double *FC, long long step)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-    if (i >= d.n) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6);
+    if (i >= d.n) return;  // whole waves
     const double xi = d.R[3 * i], yi = d.R[3 * i + 1], zi = d.R[3 * i + 2];
     double f[3] = {0.0, 0.0, 0.0};
-    int c = 0;
+    int c = 0;  // hits so far (uniform over the wave)
     const int64_t base = i * d.C;
-    for (int64_t j = 0; j < d.n; ++j) {
-        if (j == i) continue;
-        double dx = xi - d.R[3 * j], dy = yi - d.R[3 * j + 1], dz = zi - d.R[3 * j + 2];
-        dx -= d.box[0] * rint(dx / d.box[0]);
-        dy -= d.box[1] * rint(dy / d.box[1]);
-        dz -= d.box[2] * rint(dz / d.box[2]);
-        const double r = sqrt(dx * dx + dy * dy + dz * dz);
-        if (!(r < d.r_cut)) continue;
-        if (d.wca_eps != 0.0 && r < d.wca_rc) {
-            const double s2 = (d.wca_sigma / r) * (d.wca_sigma / r);
-            const double s6 = s2 * s2 * s2;
-            const double fr = 24.0 * d.wca_eps * (2.0 * s6 * s6 - s6) / (r * r);
-            f[0] += fr * dx;
-            f[1] += fr * dy;
-            f[2] += fr * dz;
+    for (int64_t j0 = 0; j0 < d.n; j0 += 64) {
+        const int64_t j = j0 + lane;
+        bool hit = false;
+        double dx = 0.0, dy = 0.0, dz = 0.0, r = 0.0;
+        if (j < d.n && j != i) {
+            dx = xi - d.R[3 * j];
+            dy = yi - d.R[3 * j + 1];
+            dz = zi - d.R[3 * j + 2];
+            dx -= d.box[0] * rint(dx / d.box[0]);
+            dy -= d.box[1] * rint(dy / d.box[1]);
+            dz -= d.box[2] * rint(dz / d.box[2]);
+            r = sqrt(dx * dx + dy * dy + dz * dz);
+            hit = r < d.r_cut;
         }
-        if (c < d.C) {
-            int b;
-            double fr;
-            locate(d, r, b, fr);
-            d.pj[base + c] = static_cast<int>(j);
-            d.pb[base + c] = b;
-            d.pf[base + c] = fr;
-            double *e = d.pe + 3 * (base + c);
-            e[0] = dx / r;
-            e[1] = dy / r;
-            e[2] = dz / r;
+        const unsigned long long m = __ballot(hit);
+        if (hit) {
+            if (d.wca_eps != 0.0 && r < d.wca_rc) {
+                const double s2 = (d.wca_sigma / r) * (d.wca_sigma / r);
+                const double s6 = s2 * s2 * s2;
+                const double fr = 24.0 * d.wca_eps * (2.0 * s6 * s6 - s6) / (r * r);
+                f[0] += fr * dx;
+                f[1] += fr * dy;
+                f[2] += fr * dz;
+            }
+            const int k = c + __popcll(m & ((1ull << lane) - 1ull));
+            if (k < d.C) {
+                d.pj[base + k] = static_cast<int>(j);
+                d.pt[base + k] = grid_coord(d, r);
+                if (d.parallel) {
+                    double *e = d.pe + 3 * (base + k);
+                    e[0] = dx / r;
+                    e[1] = dy / r;
+                    e[2] = dz / r;
+                }
+            }
         }
-        ++c;
+        c += __popcll(m);
     }
-    FC[3 * i] = f[0];
-    FC[3 * i + 1] = f[1];
-    FC[3 * i + 2] = f[2];
-    d.cnt[i] = c < d.C ? c : d.C;
-    if (c > d.C) latch(d.flags, d.flag_step, GLD_ERR_CAPACITY, step);
+    f[0] = wave_sum(f[0]);
+    f[1] = wave_sum(f[1]);
+    f[2] = wave_sum(f[2]);
+    if (lane == 0) {
+        FC[3 * i] = f[0];
+        FC[3 * i + 1] = f[1];
+        FC[3 * i + 2] = f[2];
+        d.cnt[i] = c < d.C ? c : d.C;
+        if (c > d.C) latch(d.flags, d.flag_step, GLD_ERR_CAPACITY, step);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -188,9 +214,15 @@ __global__ __launch_bounds__(kThreads) void k_dissipative(GDev d, long long n)
     const double *hi_ = d.hist + static_cast<int64_t>(i) * Hs * 3;
     for (int q = 0; q < np; ++q) {
         const int j = d.pj[base + q];
-        const int b = d.pb[base + q];
-        const double f = d.pf[base + q];
-        const double e[3] = {d.pe[3 * (base + q)], d.pe[3 * (base + q) + 1], d.pe[3 * (base + q) + 2]};
+        int b;
+        double f;
+        bin_of(d, d.pt[base + q], b, f);
+        double e[3] = {0.0, 0.0, 0.0};
+        if (par) {
+            e[0] = d.pe[3 * (base + q)];
+            e[1] = d.pe[3 * (base + q) + 1];
+            e[2] = d.pe[3 * (base + q) + 2];
+        }
         const double *k0 = d.kp + static_cast<int64_t>(b) * M, *k1 = k0 + M;
         const double *q0 = d.has_dk ? d.dk + static_cast<int64_t>(b) * M : nullptr, *q1 = q0 ? q0 + M : nullptr;
         if (lane == 0) {
@@ -371,7 +403,7 @@ __device__ __forceinline__ LanczosLds carve_lds(double *base, int NR, int has_dk
     L.yo = p;
     p += kmax;
     L.red = p;
-    p += kThreads / 64;
+    p += kLzThreads / 64;
     L.flag = reinterpret_cast<int *>(p);
     p += 1;
     L.Q = p;
@@ -380,33 +412,72 @@ __device__ __forceinline__ LanczosLds carve_lds(double *base, int NR, int has_dk
 
 size_t lanczos_lds_bytes(int NR, int has_dk, int kmax)
 {
-    return sizeof(double) * (static_cast<size_t>(NR) * (has_dk ? 2 : 1) + 6 * static_cast<size_t>(kmax) + kThreads / 64 +
+    return sizeof(double) * (static_cast<size_t>(NR) * (has_dk ? 2 : 1) + 6 * static_cast<size_t>(kmax) + kLzThreads / 64 +
                              1 + static_cast<size_t>(kmax) * kmax);
 }
 
-// y = K_hat_w x over this work-group's rows; returns this thread's part of x.y
+// y = K_hat_w x over this work-group's rows; returns this thread's part of
+// x.y.  kLzLanes lanes per particle split its pairs (entries q = lane,
+// lane + kLzLanes, ...) and sum them by a butterfly; the first adds S_w x_i.
 __device__ double spmv(const GDev &d, const LanczosLds &L, double S, const double *x, double *y)
 {
     const bool par = d.parallel != 0;
+    const int sub = threadIdx.x % kLzLanes;
     double dot = 0.0;
-    for (int64_t i = threadIdx.x; i < d.n; i += kThreads) {
+    for (int64_t i = threadIdx.x / kLzLanes; i < d.n; i += kLzThreads / kLzLanes) {
         const double xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
-        double acc[3] = {S * xi[0], S * xi[1], S * xi[2]};
+        double acc[3] = {0.0, 0.0, 0.0};
         const int np = d.cnt[i];
         const int64_t base = i * d.C;
-        for (int q = 0; q < np; ++q) {
-            const int j = d.pj[base + q];
-            const int b = d.pb[base + q];
-            const double f = d.pf[base + q];
-            const double e[3] = {d.pe[3 * (base + q)], d.pe[3 * (base + q) + 1], d.pe[3 * (base + q) + 2]};
-            const double xj[3] = {x[3 * j], x[3 * j + 1], x[3 * j + 2]};
-            tensor_add(par, e, L.kh[b] * (1.0 - f) + L.kh[b + 1] * f, xj, acc);
-            if (d.has_dk) tensor_add(par, e, L.dkh[b] * (1.0 - f) + L.dkh[b + 1] * f, xi, acc);
+        // kLzUnroll of the lane's entries at a time: their list loads, then
+        // their gathers, then their sums (several loads in flight per lane)
+        for (int q0 = sub; q0 < np; q0 += kLzLanes * kLzUnroll) {
+            int jj[kLzUnroll];
+            double tt[kLzUnroll];
+#pragma unroll
+            for (int u = 0; u < kLzUnroll; ++u) {
+                const int q = q0 + u * kLzLanes;
+                jj[u] = q < np ? d.pj[base + q] : -1;
+                tt[u] = q < np ? d.pt[base + q] : 0.0;
+            }
+            double xj[kLzUnroll][3];
+#pragma unroll
+            for (int u = 0; u < kLzUnroll; ++u) {
+                const int j = jj[u] >= 0 ? jj[u] : 0;
+                xj[u][0] = x[3 * j];
+                xj[u][1] = x[3 * j + 1];
+                xj[u][2] = x[3 * j + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < kLzUnroll; ++u) {
+                if (jj[u] < 0) break;
+                const int q = q0 + u * kLzLanes;
+                int b;
+                double f;
+                bin_of(d, tt[u], b, f);
+                double e[3] = {0.0, 0.0, 0.0};
+                if (par) {
+                    e[0] = d.pe[3 * (base + q)];
+                    e[1] = d.pe[3 * (base + q) + 1];
+                    e[2] = d.pe[3 * (base + q) + 2];
+                }
+                tensor_add(par, e, L.kh[b] * (1.0 - f) + L.kh[b + 1] * f, xj[u], acc);
+                if (d.has_dk) tensor_add(par, e, L.dkh[b] * (1.0 - f) + L.dkh[b + 1] * f, xi, acc);
+            }
         }
-        y[3 * i] = acc[0];
-        y[3 * i + 1] = acc[1];
-        y[3 * i + 2] = acc[2];
-        dot += xi[0] * acc[0] + xi[1] * acc[1] + xi[2] * acc[2];
+#pragma unroll
+        for (int o = 1; o < kLzLanes; o <<= 1) {
+            acc[0] += __shfl_xor(acc[0], o, kLzLanes);
+            acc[1] += __shfl_xor(acc[1], o, kLzLanes);
+            acc[2] += __shfl_xor(acc[2], o, kLzLanes);
+        }
+        if (sub == 0) {
+            const double y0 = S * xi[0] + acc[0], y1 = S * xi[1] + acc[1], y2 = S * xi[2] + acc[2];
+            y[3 * i] = y0;
+            y[3 * i + 1] = y1;
+            y[3 * i + 2] = y2;
+            dot += xi[0] * y0 + xi[1] * y1 + xi[2] * y2;
+        }
     }
     return dot;
 }
@@ -484,14 +555,14 @@ __device__ int tridiag_sqrt_e1(const LanczosLds &L, int kk, int ld)
     return 0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_lanczos(GDev d, long long step)
+__global__ __launch_bounds__(kLzThreads) void k_lanczos(GDev d, long long step)
 {
     extern __shared__ __align__(16) double glds[];
     const int w = blockIdx.x;
     const LanczosLds L = carve_lds(glds, d.NR, d.has_dk, d.kmax);
     const int ld = d.kmax;
     const int64_t n3 = d.n3;
-    for (int b = threadIdx.x; b < d.NR; b += kThreads) {
+    for (int b = threadIdx.x; b < d.NR; b += kLzThreads) {
         L.kh[b] = d.khT[static_cast<int64_t>(w) * d.NR + b];
         if (d.has_dk) L.dkh[b] = d.dkhT[static_cast<int64_t>(w) * d.NR + b];
     }
@@ -501,14 +572,14 @@ __global__ __launch_bounds__(kThreads) void k_lanczos(GDev d, long long step)
     double *Kv = d.KV + static_cast<int64_t>(w) * n3;
     double *X = d.X + static_cast<int64_t>(w) * n3;
     double s = 0.0;
-    for (int64_t I = threadIdx.x; I < n3; I += kThreads) s += bv[I] * bv[I];
+    for (int64_t I = threadIdx.x; I < n3; I += kLzThreads) s += bv[I] * bv[I];
     const double nb = sqrt(block_sum(s, L.red));
     if (nb == 0.0) {
-        for (int64_t I = threadIdx.x; I < n3; I += kThreads) X[I] = 0.0;
+        for (int64_t I = threadIdx.x; I < n3; I += kLzThreads) X[I] = 0.0;
         if (threadIdx.x == 0) d.kprev[w] = 1;
         return;
     }
-    for (int64_t I = threadIdx.x; I < n3; I += kThreads) Vb[I] = bv[I] / nb;
+    for (int64_t I = threadIdx.x; I < n3; I += kLzThreads) Vb[I] = bv[I] / nb;
     __syncthreads();
     const double a0 = block_sum(spmv(d, L, S, Vb, Kv), L.red);
     int status = 0;
@@ -533,7 +604,7 @@ __global__ __launch_bounds__(kThreads) void k_lanczos(GDev d, long long step)
             const double *vm = k >= 2 ? Vb + static_cast<int64_t>(k - 2) * n3 : nullptr;
             double *vn = Vb + static_cast<int64_t>(k) * n3;
             double rr = 0.0;
-            for (int64_t I = threadIdx.x; I < n3; I += kThreads) {
+            for (int64_t I = threadIdx.x; I < n3; I += kLzThreads) {
                 double t = Kv[I] - ak * vk[I];
                 if (vm) t -= bk * vm[I];
                 vn[I] = t;
@@ -562,7 +633,7 @@ __global__ __launch_bounds__(kThreads) void k_lanczos(GDev d, long long step)
             }
             if (threadIdx.x == 0) L.be[k - 1] = beta;
             const double ib = 1.0 / beta;
-            for (int64_t I = threadIdx.x; I < n3; I += kThreads) vn[I] = vn[I] * ib;
+            for (int64_t I = threadIdx.x; I < n3; I += kLzThreads) vn[I] = vn[I] * ib;
             __syncthreads();
             const double ak1 = block_sum(spmv(d, L, S, vn, Kv), L.red);
             if (threadIdx.x == 0) L.al[k] = ak1;
@@ -605,11 +676,11 @@ __global__ __launch_bounds__(kThreads) void k_lanczos(GDev d, long long step)
     __syncthreads();
     if (status) {
         if (threadIdx.x == 0) latch(d.flags, d.flag_step, status, step);
-        for (int64_t I = threadIdx.x; I < n3; I += kThreads) X[I] = 0.0;
+        for (int64_t I = threadIdx.x; I < n3; I += kLzThreads) X[I] = 0.0;
         if (threadIdx.x == 0) d.kprev[w] = 0;
         return;
     }
-    for (int64_t I = threadIdx.x; I < n3; I += kThreads) {
+    for (int64_t I = threadIdx.x; I < n3; I += kLzThreads) {
         double acc = 0.0;
         for (int a = 0; a < ko; ++a) acc += Vb[static_cast<int64_t>(a) * n3 + I] * L.yo[a];
         X[I] = nb * acc;
@@ -740,9 +811,8 @@ void plan(GDev &d, const gld_params *p, int kmax, bool has_dk, Layout &L)
     L.take(d.FC1, n3);
     L.take(d.hist, N * d.Hs * 3);
     L.take(d.pj, N * C);
-    L.take(d.pb, N * C);
     L.take(d.cnt, N);
-    L.take(d.pf, N * C);
+    L.take(d.pt, N * C);
     L.take(d.pe, N * C * 3);
     L.take(d.kp, NR * M);
     if (has_dk) L.take(d.dk, NR * M);
@@ -827,7 +897,7 @@ gld_status enqueue_pairs(gld_general *g, int into, int64_t step)
 {
     GDev &d = g->d;
     double *fc = into ? d.FC1 : d.FC0;
-    return launch(g, GLD_G_PAIRS, [&] { k_pairs<<<blocks(d.n), kThreads, 0, g->st>>>(d, fc, step); });
+    return launch(g, GLD_G_PAIRS, [&] { k_pairs<<<blocks(d.n * 64), kThreads, 0, g->st>>>(d, fc, step); });
 }
 
 // the white-noise window of step n and its transform
@@ -855,7 +925,7 @@ gld_status enqueue_step(gld_general *g)
         return st;
     if (d.noise_on) {
         if ((st = launch(g, GLD_G_LANCZOS, [&] {
-                 k_lanczos<<<d.M, kThreads, g->lds, g->st>>>(d, n);
+                 k_lanczos<<<d.M, kLzThreads, g->lds, g->st>>>(d, n);
              })) != GLD_OK)
             return st;
         if ((st = launch(g, GLD_G_COMBINE, [&] { k_combine<<<blocks(d.n3), kThreads, 0, g->st>>>(d); })) != GLD_OK)

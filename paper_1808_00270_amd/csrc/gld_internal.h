@@ -95,6 +95,7 @@ struct Dev {
     int cap = 0;            // neighbours per particle
     int capS = 0;           // candidates per particle (within r_cut + skin)
     double skin = 0;        // Verlet skin (0: rebuild every step)
+    int rebuild_period = 0; // > 0: also rebuild at the positions of every multiple of it
     int nc[3] = {1, 1, 1};  // cell grid
     int noff[3] = {1, 1, 1};
     int offs[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -157,7 +158,7 @@ struct Dev {
     // Lanczos check (T4 [S], sorted order)
     void *lq[3] = {nullptr, nullptr, nullptr};
     void *lw = nullptr;
-    double *partial = nullptr;  // [kPartials]
+    double *partial = nullptr;  // [2][kPartials]
     double *lab = nullptr;      // alpha[kMaxCheckIters], beta[kMaxCheckIters], result[4]
     int check_iters = kCheckIters;  // Lanczos iterations of a spectrum check
     // scalars

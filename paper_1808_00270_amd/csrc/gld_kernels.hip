@@ -293,27 +293,70 @@ __global__ __launch_bounds__(256) void k_dot_finish(const double *__restrict__ p
     if (threadIdx.x == 0) *out = mode ? sqrt(sh[0]) : sh[0];
 }
 
-// w <- w - alpha q - beta_prev q_prev   (beta_prev = 0 for the first step)
-template <typename T>
-__global__ void k_lanczos_orth(int64_t m, T *__restrict__ w, const T *__restrict__ q, const T *__restrict__ qp,
-                               const double *__restrict__ alpha, const double *__restrict__ beta_prev)
+// The sum of nb partials in a fixed order (thread k takes k, k + 256, ...,
+// then a tree), identical in every block that calls it.  sh: 256 doubles.
+__device__ double sum_partials(const double *__restrict__ partial, int nb, double *sh)
 {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    T v = w[e] - static_cast<T>(*alpha) * q[e];
-    if (beta_prev) v -= static_cast<T>(*beta_prev) * qp[e];
-    w[e] = v;
+    double s = 0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) s += partial[k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
 }
 
-// q_next = w / beta
+// One Lanczos step after the mat-vec w = P q, in two launches of nb blocks
+// (the dot products' second stage folded into the next kernel):
+//   orth_norm:  alpha = sum(partial_a) (q.w), w <- w - alpha q - beta_prev q_prev,
+//               partial_b[block] = this block's part of |w|^2
+//   scale_norm: beta = sqrt(sum(partial_b)), q_next = w / beta
+// Block 0 stores alpha and beta.  Each partial sum is k_dot's (same grid,
+// same stride, same tree) and each total k_dot_finish's, so the recurrence
+// is the one the separate launches computed, bit for bit.
 template <typename T>
-__global__ void k_lanczos_scale(int64_t m, const T *__restrict__ w, const double *__restrict__ beta,
-                                T *__restrict__ qn)
+__global__ __launch_bounds__(256) void k_lanczos_orth_norm(int64_t m, T *__restrict__ w, const T *__restrict__ q,
+                                                          const T *__restrict__ qp, const double *__restrict__ partial_a,
+                                                          int nb, double *alpha_out, const double *beta_prev,
+                                                          double *__restrict__ partial_b)
 {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    const double b = *beta;
-    qn[e] = b > 0 ? static_cast<T>(static_cast<double>(w[e]) / b) : T(0);
+    __shared__ double sh[256];
+    const double alpha = sum_partials(partial_a, nb, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = alpha;
+    const T a = static_cast<T>(alpha);
+    const T bp = beta_prev ? static_cast<T>(*beta_prev) : T(0);
+    double s = 0;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        T v = w[e] - a * q[e];
+        if (beta_prev) v -= bp * qp[e];
+        w[e] = v;
+        s += static_cast<double>(v) * static_cast<double>(v);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial_b[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lanczos_scale_norm(int64_t m, const T *__restrict__ w,
+                                                           const double *__restrict__ partial_b, int nb,
+                                                           double *beta_out, T *__restrict__ qn)
+{
+    __shared__ double sh[256];
+    const double b = sqrt(sum_partials(partial_b, nb, sh));
+    if (blockIdx.x == 0 && threadIdx.x == 0) *beta_out = b;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        qn[e] = b > 0 ? static_cast<T>(static_cast<double>(w[e]) / b) : T(0);
 }
 
 // q <- q / |q| using a precomputed norm
@@ -370,6 +413,15 @@ __global__ __launch_bounds__(64) void k_lanczos_judge(const double *al, const do
                                                       double *result, int *flags, long long *flag_step,
                                                       const long long *d_step, int *retired)
 {
+    // the tridiagonal in LDS: every Sturm count of the multisection walks it
+    __shared__ double sal[kMaxCheckIters], sbe[kMaxCheckIters];
+    for (int i = threadIdx.x; i < k; i += 64) {
+        sal[i] = al[i];
+        sbe[i] = be[i];
+    }
+    __syncthreads();
+    al = sal;
+    be = sbe;
     // effective dimension: stop at the first (near) breakdown
     int kk = k;
     for (int i = 0; i < k - 1; ++i)
@@ -621,11 +673,9 @@ hipError_t spectrum_check_t(const Dev &d, hipStream_t st, int iters, double lo, 
         hipError_t e = launch_spmv(d, st, 1.0, 0.0, qc, 0.0, nullptr, nullptr, 0, w, nullptr, nullptr);
         if (e != hipSuccess) return e;
         k_dot<T><<<nbd, 256, 0, st>>>(m, qc, w, d.partial);
-        k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, al + k, 0);
-        k_lanczos_orth<T><<<ne, 256, 0, st>>>(m, w, qc, qp, al + k, k > 0 ? be + k - 1 : nullptr);
-        k_dot<T><<<nbd, 256, 0, st>>>(m, w, w, d.partial);
-        k_dot_finish<<<1, 256, 0, st>>>(d.partial, nbd, be + k, 1);
-        k_lanczos_scale<T><<<ne, 256, 0, st>>>(m, w, be + k, qn);
+        k_lanczos_orth_norm<T><<<nbd, 256, 0, st>>>(m, w, qc, qp, d.partial, nbd, al + k,
+                                                    k > 0 ? be + k - 1 : nullptr, d.partial + kPartials);
+        k_lanczos_scale_norm<T><<<nbd, 256, 0, st>>>(m, w, d.partial + kPartials, nbd, be + k, qn);
     }
     k_lanczos_judge<<<1, 64, 0, st>>>(al, be, iters, lo, hi, sing_lo, sing_hi, d.lam_lo_tight, res, d.d_flags,
                                       d.d_flag_step, d.d_step, d.d_retired);

@@ -215,9 +215,12 @@ __global__ void k_cell_order(int64_t n, int64_t S, Geo g, const int *__restrict_
 // skin/2 from where it was at the last build?  Then the pairs within r_c may
 // include one missing from the candidate list, and the lists are rebuilt.
 __global__ void k_disp_check(int64_t n, int64_t S, const int *__restrict__ sorted, const double *__restrict__ R,
-                             const double4 *__restrict__ rb, double thr2, int *gate)
+                             const double4 *__restrict__ rb, double thr2, int *gate, const long long *d_step,
+                             int period)
 {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    // a fixed cadence as well: the positions of every step that is a multiple of `period`
+    if (period > 0 && s == 0 && (*d_step + 1) % period == 0) atomicOr(gate, 1);
     bool far = false;
     if (s < n) {
         const int p = sorted[s];
@@ -1918,7 +1921,7 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     // more than skin/2 since the last build (or the host asked for it)
     const double half = 0.5 * d.skin;
     k_disp_check<<<nb, 256, 0, st>>>(d.n, d.S, d.cell_sorted, d.R, static_cast<const double4 *>(d.rb_s), half * half,
-                                     d.d_rebuild);
+                                     d.d_rebuild, d.d_step, d.rebuild_period);
     k_zero<<<blocks(d.ncell, 256), 256, 0, st>>>(d.cell_count, d.ncell, d.d_rebuild);
     k_cell_assign<<<nb, 256, 0, st>>>(d.R, d.S, d.n, g, d.Rw, d.cell_id, d.cell_slot, d.cell_count, d.d_rebuild);
     k_cell_scan<<<1, 1024, 0, st>>>(d.cell_count, d.cell_start, d.ncell, d.d_rebuild);

@@ -35,6 +35,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 # the kernels and their launchers (the traffic of a launch depends on these only)
 SOURCES = ["gld_kernels.hip", "gld_pairs.hip", "gld_internal.h", "gld_device.h"]
+SOURCES_KIND = {
+    "single": SOURCES,
+    "batch": ["gld_batch.hip", "gld_batch_dev.h", "gld_batch.cpp", "gld_device.h", "gld_internal.h"],
+    "general": ["gld_general.hip", "gld_device.h"],
+}
 
 # kernel classes of the step (the names bench.py uses) -> kernel symbol, for
 # the work type T of the precision (F: suffix of the FP64 filter-bank kernel)
@@ -48,12 +53,30 @@ CLASSES = {
     "neighbor_build": r"k_build<{T}",
     "update": r"k_update_[rv]\b",  # FP64 in both paths
 }
+# the batched engine's and the general engine's kernel classes
+CLASSES_BATCH = {
+    "noise_spmv": r"kb_spmv<{T}",
+    "history": r"kb_history<{T}",
+    "noise_fir": r"kb_fir",
+    "noise_premix": r"kb_premix<{T}",
+    "noise_white": r"kb_white<{T}",
+    "neighbor_build": r"kb_build<{T}",
+    "update": r"kb_update_[rv]<{T}",
+}
+CLASSES_GENERAL = {
+    "lanczos": r"gen::.*k_lanczos\(",
+    "dissipative": r"gen::.*k_dissipative\(",
+    "dft": r"gen::.*k_dft_(slide|full)\(",
+    "pairs": r"gen::.*k_pairs\(",
+    "combine": r"gen::.*k_combine\(",
+    "update": r"gen::.*k_(update_[rv]|white_step)\(",
+}
 CALIB = r"neg"
 
 
-def source_hash() -> str:
+def source_hash(kind: str = "single") -> str:
     h = hashlib.sha256()
-    for s in SOURCES:
+    for s in SOURCES_KIND[kind]:
         with open(os.path.join(HERE, "csrc", s), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -133,10 +156,13 @@ def main():
     ap.add_argument("--note", default="")
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
                     help="kernel classes of this path (work type float or double)")
+    ap.add_argument("--kind", choices=("single", "batch", "general"), default="single",
+                    help="which engine's kernel classes to report")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
+    table = {"single": CLASSES, "batch": CLASSES_BATCH, "general": CLASSES_GENERAL}[a.kind]
     classes = {k: v.format(T="float" if a.precision == "fp32" else "double", F="" if a.precision == "fp32" else "64")
-               for k, v in CLASSES.items()}
+               for k, v in table.items()}
 
     lines = [f"# {a.name}", ""]
     if a.note:
@@ -147,8 +173,9 @@ def main():
     for name, calls, total, avg, pctg in kt[:16]:
         lines.append(f"| `{short(name)}` | {calls} | {avg:.1f} | {total / 1e3:.2f} | {pctg:.1f} |")
     lines += ["", "Average duration per launch by kernel class (" + a.precision + " path; launches below a "
-              "quarter of the class median did next to nothing and are counted apart: the chain's first term "
-              "and the terms beyond the K of the step's noise plan):", ""]
+              "quarter of the class median did next to nothing and are counted apart"
+              + (": the chain's first term and the terms beyond the K of the step's noise plan" if a.kind == "single"
+                 else "") + "):", ""]
     avg_by_class = {}
     durs = kernel_durations(a.kt)
     for cls, pat in classes.items():
@@ -157,8 +184,8 @@ def main():
             avg_by_class[cls] = d[0]
             extra = f" (+ {d[2]} that did next to nothing)" if d[2] else ""
             lines.append(f"- {cls} (`{pat}`): {d[0]:.1f} us over {d[1]} launches{extra}")
-    out = {"name": a.name, "precision": a.precision, "source_sha256": source_hash(), "avg_us": avg_by_class,
-           "kernels": {}}
+    out = {"name": a.name, "precision": a.precision, "kind": a.kind, "source_sha256": source_hash(a.kind),
+           "avg_us": avg_by_class, "kernels": {}}
 
     if a.fetch and a.write and a.calib_bytes > 0:
         fe = counter_values(a.fetch, "FETCH_SIZE")
