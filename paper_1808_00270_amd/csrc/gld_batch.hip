@@ -230,6 +230,8 @@ __global__ __launch_bounds__(kThreads) void kb_premix(const BSys *__restrict__ s
 //            x = cb[ix], z = cb[iz], out = cb[io] (T4), or F^R for k = 0
 //   k = -1:  F^D' = -P y + Dneg  (y the history's Y)
 // ---------------------------------------------------------------------------
+constexpr int kSpmvUnroll = 8;  // list entries a lane of the mat-vec has in flight
+
 template <typename T, int LANES>
 __global__ __launch_bounds__(kThreads) void kb_spmv(const BSys *__restrict__ sys, const BMap *__restrict__ map, int k,
                                                     int ix, int iz, int io)
@@ -258,25 +260,26 @@ __global__ __launch_bounds__(kThreads) void kb_spmv(const BSys *__restrict__ sys
         const int64_t row = S * LANES;
         int64_t o = 0;
         int q = sub;
-        // four of the lane's entries at a time: their index and weight
+        // kUnroll of the lane's entries at a time: their index and weight
         // loads, then their gathers, then the sums in entry order (several
         // loads in flight per lane; the same sums as one entry at a time)
-        for (; q + 3 * LANES < nn; q += 4 * LANES, o += 4 * row) {
-            const int j0 = li[o], j1 = li[o + row], j2 = li[o + 2 * row], j3 = li[o + 3 * row];
-            const T w0 = lw[o], w1 = lw[o + row], w2 = lw[o + 2 * row], w3 = lw[o + 3 * row];
-            const T4 x0 = x[j0], x1 = x[j1], x2 = x[j2], x3 = x[j3];
-            ax += w0 * x0.x;
-            ay += w0 * x0.y;
-            az += w0 * x0.z;
-            ax += w1 * x1.x;
-            ay += w1 * x1.y;
-            az += w1 * x1.z;
-            ax += w2 * x2.x;
-            ay += w2 * x2.y;
-            az += w2 * x2.z;
-            ax += w3 * x3.x;
-            ay += w3 * x3.y;
-            az += w3 * x3.z;
+        for (; q + (kSpmvUnroll - 1) * LANES < nn; q += kSpmvUnroll * LANES, o += kSpmvUnroll * row) {
+            int jj[kSpmvUnroll];
+            T ww[kSpmvUnroll];
+#pragma unroll
+            for (int u = 0; u < kSpmvUnroll; ++u) {
+                jj[u] = li[o + u * row];
+                ww[u] = lw[o + u * row];
+            }
+            T4 xx[kSpmvUnroll];
+#pragma unroll
+            for (int u = 0; u < kSpmvUnroll; ++u) xx[u] = x[jj[u]];
+#pragma unroll
+            for (int u = 0; u < kSpmvUnroll; ++u) {
+                ax += ww[u] * xx[u].x;
+                ay += ww[u] * xx[u].y;
+                az += ww[u] * xx[u].z;
+            }
         }
         for (; q < nn; q += LANES, o += row) {
             const int j = li[o];
