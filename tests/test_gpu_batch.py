@@ -186,4 +186,10 @@ def test_admission_removal_and_autotune(bmod):
     assert min(ms) > 0
     b.step(2)
     b.sync()
+    # per-system statistics add up to the batch's
+    ns, npart, pairs = b.stats()
+    live = [s for s in kept[1:]] + [s2[0]]
+    per = [b.system_stats(s) for s in live]
+    assert ns == len(live) and sum(p for p, _ in per) == pairs
+    assert all(l in (1, 2, 4, 8) for _, l in per)
     b.close()

@@ -317,19 +317,22 @@ def test_verlet_skin_matches_rebuild_every_step(pkg):
     # 27 cells, particles moving several skins: the candidate lists must hold
     # every pair within r_c at every step (a missed pair would change the
     # forces at the percent level); only the order of the sums differs
+    # (also with the fixed rebuild cadence the benchmark uses: skin 0.6,
+    # a rebuild at every multiple of 20 as well as on the displacement test)
     w = wl.config(2, n=3000, m_max=60)
     out = {}
-    for skin in (0.0, 0.5):
-        s = pkg.System.from_workload(w, fp64=True, verlet_skin=skin)
+    for skin, period in ((0.0, 0), (0.5, 0), (0.6, 20)):
+        s = pkg.System.from_workload(w, fp64=True, verlet_skin=skin, rebuild_period=period)
         s.step(150)
-        out[skin] = s.read_state()
+        out[(skin, period)] = s.read_state()
         s.close()
     R0 = wl.config(2, n=3000, m_max=60).initial_state()[0]
-    moved = np.abs(out[0.0]["r"] - R0).max()
+    moved = np.abs(out[(0.0, 0)]["r"] - R0).max()
     log(f"    largest displacement over the run {moved:.3f} (skin 0.5)")
     assert moved > 0.5
-    for k in ("r", "v", "f_c", "f_d", "f_r"):
-        assert_close(k, out[0.5][k], out[0.0][k], 1e-9, 1e-12)
+    for key in ((0.5, 0), (0.6, 20)):
+        for k in ("r", "v", "f_c", "f_d", "f_r"):
+            assert_close(f"{k} skin {key}", out[key][k], out[(0.0, 0)][k], 1e-9, 1e-12)
 
 
 def test_fp32_mixed_tracks_fp64_over_steps(pkg):
