@@ -381,6 +381,7 @@ Built build_system(int fp64, const gld_params *params, const double *r0, Sys &y)
     auto take = [&](size_t b) { sz = up256(sz) + b; };
     for (int k = 0; k < 4; ++k) take(vec * 8);  // R V FC FCn
     take(S * 32);                                // Rw
+    take(S * 32);                                // Rs
     take(static_cast<size_t>(nslots) * vec * elt);
     for (int k = 0; k < 3; ++k) take(vec * elt);  // Dneg FD FR
     if (y.noise_on) {
@@ -427,6 +428,7 @@ void carve_system(int fp64, Sys &y, char *base)
     d.FC = reinterpret_cast<double *>(take(vec * 8));
     d.FCn = reinterpret_cast<double *>(take(vec * 8));
     d.Rw = reinterpret_cast<double4 *>(take(S * 32));
+    d.Rs = reinterpret_cast<double4 *>(take(S * 32));
     d.ring = take(static_cast<size_t>(nslots) * vec * elt);
     d.Dneg = take(vec * elt);
     d.FD = take(vec * elt);

@@ -489,6 +489,7 @@ __global__ __launch_bounds__(kThreads) void kb_cell_rank(const BSys *__restrict_
     for (int q = b; q < e; ++q) r += d.cell_list[q] < i ? 1 : 0;
     d.cell_sorted[b + r] = static_cast<int>(i);
     d.cpos[i] = b + r;
+    d.Rs[b + r] = d.Rw[i];
 }
 
 __device__ __forceinline__ double batch_weight(const BSys &d, double r)
@@ -545,12 +546,11 @@ __global__ __launch_bounds__(kThreads) void kb_build(const BSys *__restrict__ sy
                 for (int q0 = b; q0 < e; q0 += LANES) {
                     const int q = q0 + sub;
                     bool hit = false;
-                    int j = 0;
                     double w = 0;
                     if (q < e) {
-                        j = d.cell_sorted[q];
-                        if (j != i) {
-                            const double4 pj = d.Rw[j];
+                        // q: the candidate's cell-order position, the index the list stores
+                        if (q != prow) {
+                            const double4 pj = d.Rs[q];  // consecutive for the lanes of a group
                             double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
                             dx -= d.box[0] * rint(dx / d.box[0]);
                             dy -= d.box[1] * rint(dy / d.box[1]);

@@ -37,6 +37,7 @@ struct BSys {
     // state, double [3][S]
     double *R, *V, *FC, *FCn;
     double4 *Rw;                // wrapped positions [n]
+    double4 *Rs;                // the same in cell order [n] (the list build reads candidates in order)
     // work precision T (float or double) buffers
     void *ring;                 // [nslots][3][S]
     void *Dneg, *FD, *FR;       // [3][S]
