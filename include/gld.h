@@ -122,9 +122,9 @@ typedef struct {
                                   written positions.  The filter block of the noise
                                   plan (gld_noise_info.block) becomes the largest
                                   multiple of W it allows; W larger than the block the
-                                  plan allows (64 / padded rank steps in FP32_MIXED,
-                                  32 / padded rank in FP64, so 8 and 2 for ranks 8 and
-                                  16) makes gld_create return GLD_ERR_INVALID_ARG.
+                                  plan allows (64 / padded rank steps, so 8 and 4 for
+                                  ranks 8 and 16) makes gld_create return
+                                  GLD_ERR_INVALID_ARG.
                                   Ignored when kT = 0. */
     /* The general tables of eqs. (GLD_basic2) and (dissipative_force2) on the
      * same distance grid (Sec. III.A tabulates K^p(R, t) on a grid), row-major

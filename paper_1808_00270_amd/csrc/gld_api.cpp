@@ -180,7 +180,7 @@ Geometry geometry(const gld_params *p)
     g.S = round_up(p->n, 64);
     g.fp64 = p->precision == GLD_FP64;
     g.parallel = p->pair_tensor == GLD_PAIR_PARALLEL;
-    g.firw = g.fp64 ? 32 : 64;
+    g.firw = gld::fir_rows(g.fp64);  // the rows of a filter block's outputs
     g.win = p->kT > 0 ? std::max(1, p->noise_window) : 1;
     const double vol = p->box[0] * p->box[1] * p->box[2];
     if (p->max_neighbors > 0) {

@@ -168,7 +168,8 @@ __global__ __launch_bounds__(kFirMfmaThreads) void kb_fir64(const BSys *__restri
     const int64_t M = 3 * d.S;
     FirPart part = fir_part(d, mode, M);
     part.ustride = static_cast<int64_t>(fir_rows(1)) * M;
-    fir_mfma64_body<0>(d.n, d.S, d.bf, d.rcap, d.half, 2 * d.half + d.bf, d.wlen,
+    // four row tiles: a launch covers every system, whose bf * rcap reach 64
+    fir_mfma64_body<0, 4>(d.n, d.S, d.bf, d.rcap, d.half, 2 * d.half + d.bf, d.wlen,
                        static_cast<const double *>(d.Afilt), static_cast<const double *>(d.wring), d.step,
                        static_cast<double *>(d.U), part, tl.y);
 }

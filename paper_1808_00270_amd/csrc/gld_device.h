@@ -285,16 +285,16 @@ __device__ __forceinline__ void fir_mfma_body(int64_t n, int64_t S, int bf, int 
 // FP64 filter bank on the matrix cores, the same product with
 // v_mfma_f64_16x16x4f64 (four k per instruction, lanes 16 g .. 16 g + 15
 // taking k = g): each wave owns 64 channels (four 16-wide column tiles) and
-// the bf * rc <= 32 rows (two 16-row tiles); accumulator element v of a tile
-// is row 4 v + g, column lane % 16.  Taps are staged in chunks of
-// kFirChunk64 window steps.
+// the bf * rc <= 16 RT rows (RT = 2 or 4 16-row tiles); accumulator element
+// v of a tile is row 4 v + g, column lane % 16.  Taps are staged in chunks
+// of kFirChunk64 window steps.
 typedef double fir_v4d __attribute__((ext_vector_type(4)));
 constexpr int kFirChunk64 = 64;
 constexpr int kFirUnroll64 = 4;  // MFMA k-quads per batch
 constexpr int kFirStageIt64 =
     ((kFirChunk64 + kMaxFirBlock - 1) * kMaxRank / 2 + kFirMfmaThreads - 1) / kFirMfmaThreads;
 
-template <int ROLE>
+template <int ROLE, int RT>
 __device__ __forceinline__ void fir_mfma64_body(int64_t n, int64_t S, int bf, int rc, int offset, int span, int len,
                                                 const double *__restrict__ A, const double *__restrict__ W,
                                                 const long long *__restrict__ d_step, double *__restrict__ U,
@@ -320,19 +320,19 @@ __device__ __forceinline__ void fir_mfma64_body(int64_t n, int64_t S, int bf, in
     const int64_t m0 = cslice * part.cs + (tile * (kFirMfmaThreads / 64) + (tid >> 6)) * 64;
     const bool wlive = m0 < climit;
     const int g = lane >> 4, lo = lane & 15;
-    int trow[2];
-    double tmul[2];
+    int trow[RT];
+    double tmul[RT];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
         const int i = 16 * rt + lo;
         const bool valid = i < bf * rc;
         tmul[rt] = valid ? 1.0 : 0.0;
         trow[rt] = (bf - 1 - (valid ? i / rc : 0)) * rc + (valid ? i % rc : 0);
     }
     const int64_t c0 = wlive ? m0 + lo : lo;
-    fir_v4d acc[2][4];
+    fir_v4d acc[RT][4];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = fir_v4d{};
     // ring slot of this lane's window step k = 4 j + g
@@ -391,11 +391,11 @@ __device__ __forceinline__ void fir_mfma64_body(int64_t n, int64_t S, int bf, in
 #pragma unroll
             for (int u = 0; u < kFirUnroll64; ++u) {
                 const int kl = kk + 4 * u + g;
-                double av[2];
+                double av[RT];
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt) av[rt] = taps[kl * rc + trow[rt]] * tmul[rt];
+                for (int rt = 0; rt < RT; ++rt) av[rt] = taps[kl * rc + trow[rt]] * tmul[rt];
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt)
+                for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                     for (int ct = 0; ct < 4; ++ct)
                         acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], xa[u][ct], acc[rt][ct], 0, 0, 0);
@@ -413,7 +413,7 @@ __device__ __forceinline__ void fir_mfma64_body(int64_t n, int64_t S, int bf, in
         const int64_t p = m - (m >= S ? S : 0) - (m >= 2 * S ? S : 0);
         if (p >= n) continue;
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * rt + 4 * v + g;

@@ -215,7 +215,7 @@ constexpr int kHistBlock32 = 32, kHistBlock64 = 16;
 // (one per step; the step part adds the kHistSplit partial sums)
 constexpr int kHistSplit = 4;
 // accumulator rows of the filter bank's product (rows of one output block)
-__host__ __device__ inline int fir_rows(int fp64) { return fp64 ? 32 : 64; }
+__host__ __device__ inline int fir_rows(int fp64) { return (void)fp64, 64; }
 // steps between the launches that compute a share of the next filter block
 // (a divisor of the block of at most 5: 1, 2, 4 or 5, each a divisor of 20;
 // the block's product is split into block / period shares)

@@ -193,14 +193,14 @@ __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma(int64_t n, int64_t
     fir_mfma_body<ROLE>(n, S, bf, rc, offset, span, len, A, W, d_step, U, part, blockIdx.x);
 }
 
-template <int ROLE>
+template <int ROLE, int RT>
 __global__ __launch_bounds__(kFirMfmaThreads) void k_fir_mfma64(int64_t n, int64_t S, int bf, int rc, int offset,
                                                                 int span, int len, const double *__restrict__ A,
                                                                 const double *__restrict__ W,
                                                                 const long long *__restrict__ d_step,
                                                                 double *__restrict__ U, FirPart part)
 {
-    fir_mfma64_body<ROLE>(n, S, bf, rc, offset, span, len, A, W, d_step, U, part, blockIdx.x);
+    fir_mfma64_body<ROLE, RT>(n, S, bf, rc, offset, span, len, A, W, d_step, U, part, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,14 +504,17 @@ int fir_rcap_for(int rank)
 
 int fir_block_for(int fp64, int rcap)
 {
+    // block * rcap <= 64 rows in both precisions (FP32: two 32-row MFMA
+    // tiles; FP64: up to four 16-row tiles)
+    (void)fp64;
     switch (rcap) {
-    case 4: return fp64 ? 8 : 16;
-    case 6: return fp64 ? 5 : 10;
-    case 8: return fp64 ? 4 : 8;
-    case 12: return fp64 ? 2 : 5;
-    case 16: return fp64 ? 2 : 4;
-    case 24: return fp64 ? 1 : 2;
-    default: return fp64 ? 1 : 2;
+    case 4: return 16;
+    case 6: return 10;
+    case 8: return 8;
+    case 12: return 5;
+    case 16: return 4;
+    case 24: return 2;
+    default: return 2;
     }
 }
 
@@ -530,8 +533,8 @@ hipError_t launch_white_ring(const Dev &d, int mode, hipStream_t st)
 
 hipError_t launch_fir(const Dev &d, int mode, hipStream_t st)
 {
-    // block * rcap <= 64 (FP32) or <= 32 (FP64) for every padded rank: the
-    // rows of one pair of MFMA tiles
+    // block * rcap <= 64 for every padded rank: the rows of the MFMA tiles
+    // (FP64: four 16-row tiles above 32 rows, else two)
     const int64_t M = 3 * d.S;
     FirPart part;
     part.ustride = static_cast<int64_t>(fir_rows(d.fp64)) * M;
@@ -543,11 +546,16 @@ hipError_t launch_fir(const Dev &d, int mode, hipStream_t st)
     const unsigned grid = static_cast<unsigned>((part.cs + kFirMfmaThreads - 1) / kFirMfmaThreads);
     // window: t = n0 - half .. n0 + bf - 1 + half (2 half + 1 taps, bf outputs)
     const int span = 2 * d.fir_half + d.fir_block;
-    if (d.fp64)
-        k_fir_mfma64<0><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, span,
-                                                          d.wring_len, static_cast<const double *>(d.Afilt),
-                                                          static_cast<const double *>(d.wring), d.d_step,
-                                                          static_cast<double *>(d.U), part);
+    if (d.fp64 && d.fir_block * d.fir_rcap > 32)
+        k_fir_mfma64<0, 4><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, span,
+                                                             d.wring_len, static_cast<const double *>(d.Afilt),
+                                                             static_cast<const double *>(d.wring), d.d_step,
+                                                             static_cast<double *>(d.U), part);
+    else if (d.fp64)
+        k_fir_mfma64<0, 2><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, span,
+                                                             d.wring_len, static_cast<const double *>(d.Afilt),
+                                                             static_cast<const double *>(d.wring), d.d_step,
+                                                             static_cast<double *>(d.U), part);
     else
         k_fir_mfma<0><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.fir_block, d.fir_rcap, d.fir_half, span,
                                                         d.wring_len, static_cast<const float *>(d.Afilt),
@@ -600,7 +608,7 @@ hipError_t launch_history_block(const Dev &d, int mode, hipStream_t st)
     for (int q = 0; q < (mode == 0 ? 1 : kHistSplit); ++q) {
         part.split = q;
         if (d.fp64)
-            k_fir_mfma64<1><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.hist_block, 2, d.nslots, span, d.nslots,
+            k_fir_mfma64<1, 2><<<grid, kFirMfmaThreads, 0, st>>>(d.n, d.S, d.hist_block, 2, d.nslots, span, d.nslots,
                                                               static_cast<const double *>(d.hist_taps),
                                                               static_cast<const double *>(d.ring), d.d_step,
                                                               static_cast<double *>(d.Uh), part);

@@ -14,7 +14,7 @@ noise construction the benchmark times:
   ends), in both precisions at their default noise tolerances;
 * a run written at step 30 and stepped through step 32, where both the
   history's block product (blocks of 32 steps in FP32, 16 in FP64) and the
-  filter bank (blocks of 8 and 2 steps) start a new block by themselves,
+  filter bank (blocks of 8 and 4 steps) start a new block by themselves,
   without the forced products that gld_write_state runs; every step is
   compared with one oracle step from the GPU's own state.
 
