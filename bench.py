@@ -138,7 +138,7 @@ def run_gpu(args, fp64, window=1):
     del s
     torch.cuda.empty_cache()
     return dict(w=w, info=info, ms_per_step=ms_per_step, ms_cycle=ms_cycle, lat=lat, kt=kt, kt_tight=kt_tight,
-                pairs=pairs, max_pairs=most, t_create=t_create, status=st["status"])
+                pairs=pairs, max_pairs=most, t_create=t_create, status=st["status"], window=window)
 
 
 def measured_traffic(workload, kind, fp64):
@@ -207,9 +207,14 @@ def roofline_entry(res, kind, fp64, kernel_steps):
     if kind == "noise_spmv":
         # the library times the chain's terms that stream the pair lists
         # between one event pair and counts them (the plan choice, skipped
-        # terms and first term go to noise_setup)
+        # terms and first term go to noise_setup).  With the per-step chain
+        # and the isotropic tensor the first of them also computes P Y: its
+        # extra vectors (Y and Dneg read, F^D' written: 10 n sizeof(T) per
+        # step) are spread over the step's launches
         avg = ms / cnt
         b = alg["full"]
+        if res.get("window", 1) == 1 and not w.parallel:
+            b += 10 * w.n * (8 if fp64 else 4) * kernel_steps / cnt
     else:
         avg = ms / cnt
         b = alg["bytes"]

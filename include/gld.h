@@ -93,8 +93,8 @@ typedef struct {
     double wca_sigma;          /* WCA conservative pair force; wca_eps = 0 disables  */
     double wca_eps;
     uint64_t seed;             /* Philox4x32-10 key of the white noise W             */
-    double noise_tol;          /* relative rms accuracy of F^R (0: 1e-6 FP32_MIXED,
-                                  1e-12 FP64)                                        */
+    double noise_tol;          /* relative rms accuracy of F^R (0: 4e-6 FP32_MIXED,
+                                  whose forces are held to 1e-5; 1e-12 FP64)         */
     double lam_lo, lam_hi;     /* interval holding the spectrum of the pair-weight
                                   matrix P = [w(R_ij) T_ij]; both 0: chosen at
                                   create from the initial configuration              */

@@ -579,10 +579,19 @@ gld_status enqueue_step(gld_system *s, int slot)
         LAUNCH(GLD_K_NOISE_FIR, gld::launch_fir(d, 0, st));
     }
     LAUNCH(GLD_K_DISSIPATIVE, gld::launch_permute(d, st, (s->noise_on && d.win == 1) ? pl.r : 0));
+    // With the per-step chain (isotropic pair tensor), the dissipative
+    // product P Y rides on the chain's first pair term (one stream of the
+    // lists for both); otherwise it streams the lists alone, here.
+    const bool fuse = s->noise_on && d.win == 1 && !d.parallel && d.has_pair && pl.K >= 2 &&
+                      (d.cheb_kt == 0 || d.cheb_kt >= 2);
     // the refresh of the step before wrote the pair lists in ascending cell
-    // order; the mat-vecs that stream them alternate the order from here on
-    bool rev = true;
-    LAUNCH(GLD_K_DISSIPATIVE, gld::launch_dissipative(d, st, rev));
+    // order; the mat-vecs that stream them alternate the order from here on,
+    // the first one descending
+    bool rev = !fuse;
+    if (!fuse) LAUNCH(GLD_K_DISSIPATIVE, gld::launch_dissipative(d, st, rev));
+    // the chain terms that may be the step's first pair term (k = K - 2 of
+    // the wide and of the tight plan): with fusion they carry P Y
+    auto first_pair = [&](int k) { return fuse && (k == pl.K - 2 || (d.cheb_kt > 0 && k == d.cheb_kt - 2)); };
     if (s->noise_on && d.win > 1) {
         if (slot == 0) {
             gld_status ws = enqueue_window(s);
@@ -649,6 +658,10 @@ gld_status enqueue_step(gld_system *s, int slot)
                 if (!prev1) {
                     LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 0.0, 0.0, nullptr, 0.0, nullptr, coef(k), pl.r,
                                                               out, nullptr, nullptr, false, k, true));
+                } else if (first_pair(k)) {
+                    rev = !rev;
+                    LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_dual(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, prev1,
+                                                                   prev2 ? -1.0 : 0.0, prev2, out, nullptr, rev, k));
                 } else {
                     rev = !rev;
                     LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, 2.0 * pl.alpha, 2.0 * pl.beta, prev1,
@@ -660,7 +673,10 @@ gld_status enqueue_step(gld_system *s, int slot)
                 prev1 = out;
             }
             if ((ts = to_pairs(0)) != GLD_OK) return ts;
-            if (prev1) {
+            if (prev1 && first_pair(0)) {
+                LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv_dual(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0,
+                                                               prev2, nullptr, d.FR, !rev, 0));
+            } else if (prev1) {
                 LAUNCH(GLD_K_NOISE_SPMV, gld::launch_spmv(d, st, pl.alpha, pl.beta, prev1, prev2 ? -1.0 : 0.0, prev2,
                                                           coef(0), pl.r, nullptr, d.FR, nullptr, !rev, 0, true));
             } else {
@@ -763,7 +779,7 @@ gld_status setup_noise(gld_system *s)
     std::string err;
     gld_status st = gld::noise_spectra(p, s->plan, err);
     if (st != GLD_OK) return fail(st, err);
-    const double tol = p.noise_tol > 0 ? p.noise_tol : (s->geo.fp64 ? 1e-12 : 1e-6);
+    const double tol = p.noise_tol > 0 ? p.noise_tol : (s->geo.fp64 ? gld::kNoiseTolFp64 : gld::kNoiseTolMixed);
     double lo = p.lam_lo, hi = p.lam_hi;
     if (p.noise_a) {
         // the caller's filters for [lam_lo, lam_hi]: the interval must stay
@@ -1371,7 +1387,7 @@ gld_status gld_build_noise_filters(const gld_params *params, double lam_lo, doub
     if (st != GLD_OK) return st;
     if (!a_out || !b_out || !info) return fail(GLD_ERR_INVALID_ARG, "NULL argument");
     if (!(params->kT > 0)) return fail(GLD_ERR_INVALID_ARG, "kT must be > 0 for a noise construction");
-    if (tol <= 0) tol = params->precision == GLD_FP64 ? 1e-12 : 1e-6;
+    if (tol <= 0) tol = params->precision == GLD_FP64 ? gld::kNoiseTolFp64 : gld::kNoiseTolMixed;
     NoisePlan plan;
     std::string err;
     gld_params q = *params;

@@ -337,7 +337,7 @@ Built build_system(int fp64, const gld_params *params, const double *r0, Sys &y)
     if (y.noise_on) {
         std::string e;
         if ((st = gld::noise_spectra(p, y.plan, e)) != GLD_OK) return err(st, e);
-        const double tol = p.noise_tol > 0 ? p.noise_tol : (fp64 ? 1e-12 : 1e-6);
+        const double tol = p.noise_tol > 0 ? p.noise_tol : (fp64 ? gld::kNoiseTolFp64 : gld::kNoiseTolMixed);
         double lo = p.lam_lo, hi = p.lam_hi;
         if (!(hi > lo)) {
             if (!pair) {

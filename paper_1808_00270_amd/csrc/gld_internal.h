@@ -14,6 +14,10 @@ namespace gld {
 
 constexpr int kMaxCheb = 512;     // Chebyshev terms of the noise expansion
 constexpr int kMaxRank = 32;      // filters in the white-noise filter bank
+// default noise accuracy (relative rms of F^R): FP32-mixed forces are held to
+// 1e-5, and the noise construction takes 4e-6 of it (the FP32 arithmetic of
+// the chain, the history and the weights adds well under 1e-6); FP64 1e-12
+constexpr double kNoiseTolMixed = 4e-6, kNoiseTolFp64 = 1e-12;
 constexpr int kCheckIters = 40;   // Lanczos iterations of a spectrum check (default)
 constexpr int kMaxCheckIters = GLD_MAX_CHECK_ITERS;  // the most a system may ask for
 
@@ -252,6 +256,14 @@ hipError_t launch_permute_window(const Dev &d, hipStream_t st, int r);
 hipError_t launch_spmv_window(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
                               const void *z, const void *coef, int r, const void *us, void *out_sorted,
                               void *out_orig, int nv, bool reverse, int cheb_k = -1);
+// the chain's first pair term and the dissipative product through one stream
+// of the pair lists (isotropic tensor): out = a P x + b x + cz z + v_k (the
+// term cheb_k, premixed; to out_sorted, or to out_orig for k = 0) and
+// F^D' = -P Y + Dneg (Y the sorted ys).  With a plan chosen on the device the
+// launch takes the second product only where the plan makes cheb_k its first
+// pair term; the host launches it for k = K - 2 of both plans.
+hipError_t launch_spmv_dual(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
+                            const void *z, void *out_sorted, void *out_orig, bool reverse, int cheb_k);
 // noise window: FR = FRw[step mod W]
 hipError_t launch_take_window(const Dev &d, hipStream_t st);
 // largest mat-vec staging capacity (candidates) that fits the LDS of one work-group

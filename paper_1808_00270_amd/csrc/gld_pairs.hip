@@ -1100,9 +1100,11 @@ __global__ void k_permute(int64_t n, int64_t S, const int *__restrict__ sorted, 
 // (skip) for the terms beyond the chosen plan's K
 struct ChainStep {
     double a, b, cz;
-    int row;   // row of the mixing table (the tight plan's rows follow the wide plan's)
-    int skip;
+    int row;             // row of the mixing table (the tight plan's rows follow the wide plan's)
+    unsigned char skip;  // a term beyond the plan's K
+    unsigned char dual;  // the plan's first term that streams the pair lists (k = K - 2)
 };
+static_assert(sizeof(ChainStep) == 32, "the chain's device table holds 32 bytes per term");
 
 struct MvArgs {
     int64_t n, S;
@@ -1127,6 +1129,10 @@ struct MvArgs {
     const ChainStep *chain;
     int cheb_k, rcap;
     int premix;  // us holds the term's v_k (coefficient 1, r = 1)
+    // k_mvw's dual form: the second product -P y2 + dneg2 (y2 sorted T4),
+    // scattered to fd2 ([3][S], original order)
+    const void *y2, *dneg2;
+    void *fd2;
 };
 
 // The staged input vector: for the isotropic mat-vec three planes x[], y[],
@@ -1526,15 +1532,23 @@ __global__ void k_permute_window(int64_t n, int64_t S, const int *__restrict__ s
 // order).  The staging holds NV x 3 planes of maxc values; rounds, lanes and
 // the spread epilogue are those of k_mv.  Each list chunk is read once for
 // the NV vectors, so the list traffic per vector falls by NV.
-template <typename T, int BS, int L, int NV>
+// DUAL (NV = 2): vector 0 is a term of the step's chain (as k_mv computes
+// it, premixed v_k included) and vector 1 the dissipative product
+// F^D' = -P Y + Dneg (y2, dneg2, fd2), so that the chain's first pair term
+// and P Y share one stream of the lists.  With a plan chosen on the device,
+// the term takes the second product only where the plan marks it as its
+// first pair term (ChainStep::dual), else it is the plain term.
+template <typename T, int BS, int L, int NV, bool DUAL = false>
 __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
 {
+    static_assert(!DUAL || NV == 2, "the dual form carries two vectors");
     using T4 = typename V4<T>::t;
     constexpr int PG = BS / L;
     extern __shared__ __align__(32) unsigned char mv_lds[];
     __shared__ int sst[kStab], sbase[kStab];
     double ca = A.a, cb = A.b, ccz = A.cz;
     const T *coefp = static_cast<const T *>(A.coef);
+    bool dual = DUAL;
     if (A.chain) {
         // a term of the Chebyshev chains: its coefficients follow this step's plan
         const ChainStep cs = A.chain[A.cheb_k];
@@ -1543,7 +1557,10 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
         cb = cs.b;
         ccz = cs.cz;
         coefp += static_cast<int64_t>(cs.row) * A.rcap;
+        dual = DUAL && cs.dual != 0;
     }
+    // vectors this launch carries; vector v's input
+    const int nvl = DUAL ? (dual ? 2 : 1) : NV;
     const int cid = A.rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
     const int h0 = A.cstart[cid], occ = A.cstart[cid + 1] - h0;
     if (occ <= 0) return;
@@ -1558,6 +1575,9 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
     T4 *part = reinterpret_cast<T4 *>(mv_lds);  // [NV][BS], once the gathers of a round are done
     const unsigned ss = static_cast<unsigned>(A.maxc);
     const T4 *__restrict__ x = static_cast<const T4 *>(A.x);
+    auto vin = [&](int v) -> const T4 * {
+        return (DUAL && v == 1) ? static_cast<const T4 *>(A.y2) : x + static_cast<int64_t>(v) * A.S;
+    };
     const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw) + static_cast<int64_t>(h0) * 2 * A.cap8;
     const void *nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;  // either index form
     const bool pair = ca != 0.0;
@@ -1593,7 +1613,8 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                         const int t = sst[lo] + (l - sbase[lo]);
 #pragma unroll
                         for (int v = 0; v < NV; ++v) {
-                            const T4 q = x[static_cast<int64_t>(v) * A.S + t];
+                            if (v >= nvl) break;
+                            const T4 q = vin(v)[t];
                             xsoa[(3 * v + 0) * ss + (l - c0)] = q.x;
                             xsoa[(3 * v + 1) * ss + (l - c0)] = q.y;
                             xsoa[(3 * v + 2) * ss + (l - c0)] = q.z;
@@ -1635,6 +1656,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                     }
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
+                        if (v >= nvl) break;
 #pragma unroll
                         for (int q = 0; q < 3; ++q) {
                             T val[8];
@@ -1665,6 +1687,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
             const T4 *zv = static_cast<const T4 *>(A.z);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
+                if (DUAL && v == 1) break;  // the dissipative product has no other terms
                 for (int tt = sub; tt < nterm; tt += L) {
                     T cf = T(0);
                     T4 q{};
@@ -1679,7 +1702,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                             q = zv[static_cast<int64_t>(v) * A.S + s];
                         }
                     } else {
-                        cf = coef[tt - 2];
+                        cf = A.premix ? T(1) : coef[tt - 2];
                         q = us[(static_cast<int64_t>(v) * A.r + (tt - 2)) * A.S + s];
                     }
                     e[v][0] += cf * q.x;
@@ -1690,9 +1713,10 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
         }
         __syncthreads();
         if (active) {
-            const T a = static_cast<T>(ca);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
+                if (v >= nvl) break;
+                const T a = (DUAL && v == 1) ? T(-1) : static_cast<T>(ca);
                 T4 q;
                 q.x = a * p[v][0] + e[v][0];
                 q.y = a * p[v][1] + e[v][1];
@@ -1703,7 +1727,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
         }
         __syncthreads();
         staged_all = false;
-        for (int k = tid; k < NV * m; k += BS) {
+        for (int k = tid; k < nvl * m; k += BS) {
             const int v = k / m, i = k - v * m;
             T o0 = 0, o1 = 0, o2 = 0;
 #pragma unroll
@@ -1714,7 +1738,14 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                 o2 += q.z;
             }
             const int64_t so = h0 + g0 + i;
-            if (A.out_sorted) {
+            if (DUAL && v == 1) {
+                const int pp = A.sorted[so];
+                const T *ad = static_cast<const T *>(A.dneg2);
+                T *out = static_cast<T *>(A.fd2);
+                out[pp] = o0 + ad[pp];
+                out[A.S + pp] = o1 + ad[A.S + pp];
+                out[2 * A.S + pp] = o2 + ad[2 * A.S + pp];
+            } else if (A.out_sorted) {
                 T4 o;
                 o.x = o0;
                 o.y = o1;
@@ -1764,6 +1795,7 @@ __global__ void k_cheb_select(ChainSel c, const unsigned *__restrict__ rowmax, c
         ChainStep e;
         e.row = (tight ? c.Kw : 0) + k;
         e.skip = k >= Ka ? 1 : 0;
+        e.dual = k == Ka - 2 ? 1 : 0;
         if (k >= Ka - 1) {
             e.a = 0.0;
             e.b = 0.0;
@@ -2073,7 +2105,7 @@ int mvw_staging(const Dev &d)
     return static_cast<int>(std::min<size_t>(static_cast<size_t>(d.maxc), budget / (NV * 3 * sizeof(T))));
 }
 
-template <typename T, int NV>
+template <typename T, int NV, bool DUAL = false>
 hipError_t launch_mvw_t(const Dev &d, MvArgs A, hipStream_t st)
 {
     constexpr int BS = sizeof(T) == 8 ? kMvThreads64 : kMvThreads32;
@@ -2083,12 +2115,33 @@ hipError_t launch_mvw_t(const Dev &d, MvArgs A, hipStream_t st)
     const size_t part = static_cast<size_t>(NV) * BS * sizeof(typename V4<T>::t);
     const size_t shm = stage > part ? stage : part;
     if (shm > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mvw<T, BS, L, NV>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mvw<T, BS, L, NV, DUAL>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
         if (e != hipSuccess) return e;
     }
-    k_mvw<T, BS, L, NV><<<d.ncell, BS, shm, st>>>(A);
+    k_mvw<T, BS, L, NV, DUAL><<<d.ncell, BS, shm, st>>>(A);
     return hipGetLastError();
+}
+
+hipError_t launch_spmv_dual(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,
+                            const void *z, void *out_sorted, void *out_orig, bool reverse, int cheb_k)
+{
+    if (d.parallel || !d.has_pair || !d.ys || !d.FD || !d.Dneg || !d.vk) return hipErrorInvalidValue;
+    MvArgs A = mv_args(d, a, b, x, cz, z, nullptr, 1, d.us, out_sorted, out_orig, nullptr, reverse);
+    // the term's premixed v_k (k_cheb_mix)
+    A.us = static_cast<const char *>(d.vk) + static_cast<size_t>(cheb_k) * d.S * 4 * (d.fp64 ? 8 : 4);
+    A.r = 1;
+    A.premix = 1;
+    if (d.cheb_kt > 0) {
+        A.chain = static_cast<const ChainStep *>(d.chain);
+        A.cheb_k = cheb_k;
+        A.rcap = d.fir_rcap;
+        A.coef = d.Bmix;
+    }
+    A.y2 = d.ys;
+    A.dneg2 = d.Dneg;
+    A.fd2 = d.FD;
+    return d.fp64 ? launch_mvw_t<double, 2, true>(d, A, st) : launch_mvw_t<float, 2, true>(d, A, st);
 }
 
 hipError_t launch_spmv_window(const Dev &d, hipStream_t st, double a, double b, const void *x, double cz,

@@ -44,7 +44,7 @@ SOURCES_KIND = {
 # kernel classes of the step (the names bench.py uses) -> kernel symbol, for
 # the work type T of the precision (F: suffix of the FP64 filter-bank kernel)
 CLASSES = {
-    "noise_spmv": r"k_mv<{T}",
+    "noise_spmv": r"k_mvw?<{T}",  # k_mvw: the first pair term with P Y
     "history_step": r"k_history_step<{T}",
     "history_block": r"k_fir_mfma{F}<1>",
     "noise_fir": r"k_fir_mfma{F}<0>",

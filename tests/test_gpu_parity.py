@@ -6,7 +6,7 @@ bound of 10x that relative to the rms of the reference):
   FP32-mixed path   1e-5  for every force and for the state increments
 The colored noise is the vector sum_s A_s W_{n+s} of eq. (noise_production);
 the oracle reaches it by Algorithm 1 (Lanczos, tol 1e-13), the GPU by a
-Chebyshev expansion with tolerance 1e-13 (FP64) or 1e-6 (FP32); both are
+Chebyshev expansion with tolerance 1e-13 (FP64) or, by default, 4e-6 (FP32); both are
 approximations of one defined vector, well inside the bounds above.
 """
 import math
@@ -405,8 +405,9 @@ def test_parallel_tensor_at_high_density_is_not_pd(pkg, oracle_mod):
 def test_kernel_timing_counts(pkg):
     """Per-kernel timing: an event pair per launch, except the Chebyshev chain:
     its terms that stream the pair lists (Ka - 1 of them, Ka the K of the
-    step's noise plan) count under noise_spmv, its plan choice, skipped terms
-    and first term under noise_setup."""
+    step's noise plan; the first of them also computes P Y) count under
+    noise_spmv, its plan choice, skipped terms and first term under
+    noise_setup."""
     w = wl.config(1)
     s = pkg.System.from_workload(w)
     info = s.noise_info()
@@ -428,7 +429,9 @@ def test_kernel_timing_counts(pkg):
     assert kt["noise_spmv"][1] == pair
     assert kt["noise_setup"][1] == setup
     assert kt["noise_fir"][1] == 6      # white ring and filter bank
-    assert kt["dissipative"][1] == 6    # permute and the pair contraction
+    # the permute; the pair contraction P Y rides on the chain's first pair
+    # term (noise_spmv) for the isotropic tensor
+    assert kt["dissipative"][1] == 3
     assert kt["update"][1] == 6
     assert kt["neighbor"][1] == 3
     for k in ("history", "noise_spmv", "noise_setup", "noise_fir", "dissipative", "update", "neighbor"):
@@ -547,7 +550,10 @@ def test_tight_and_wide_noise_plans_match_oracle(pkg, oracle_mod, fp64, W):
     t0 = s.noise_info()["tight_steps"]
     s.step(1)
     assert s.noise_info()["tight_steps"] == t0 + 1
-    assert_close("F^R (tight plan)", s.read_state()["f_r"], o.noise(4, R), tol)
+    g = s.read_state()
+    assert_close("F^R (tight plan)", g["f_r"], o.noise(4, R), tol)
+    # F^D' streams the lists with the plan's first pair term (isotropic, W = 1)
+    assert_close("F^D' (tight plan)", g["f_d"], o.forces_rows(R, V, hist, np.arange(w.n))[1], tol)
     # a denser arrangement whose bound lies between the two: the wide plan
     # (its smallest eigenvalue hardly moves: -0.672 against -0.670 at 0.55)
     for frac in (0.6, 0.55, 0.5):
@@ -562,7 +568,9 @@ def test_tight_and_wide_noise_plans_match_oracle(pkg, oracle_mod, fp64, W):
     t1 = s.noise_info()["tight_steps"]
     s.step(1)
     assert s.noise_info()["tight_steps"] == t1
-    assert_close("F^R (wide plan)", s.read_state()["f_r"], o.noise(9, Rs), tol)
+    g = s.read_state()
+    assert_close("F^R (wide plan)", g["f_r"], o.noise(9, Rs), tol)
+    assert_close("F^D' (wide plan)", g["f_d"], o.forces_rows(Rs, Vs, hist, np.arange(w.n))[1], tol)
     s.close()
 
 
