@@ -46,8 +46,8 @@ SOURCES_KIND = {
 CLASSES = {
     "noise_spmv": r"k_mvw?<{T}",  # k_mvw: the first pair term with P Y
     "history_step": r"k_history_step<{T}",
-    "history_block": r"k_fir_mfma{F}<1>",
-    "noise_fir": r"k_fir_mfma{F}<0>",
+    "history_block": r"k_fir_mfma{F}<1[,>]",  # FP64: k_fir_mfma64<ROLE, row tiles>
+    "noise_fir": r"k_fir_mfma{F}<0[,>]",
     "noise_white": r"k_white_ring<{T}",
     "neighbor_refresh": r"k_refresh<{T}",
     "neighbor_build": r"k_build<{T}",
