@@ -38,6 +38,9 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
     """Algorithmic bytes (or flops) of one launch of a kernel class."""
     sT = 8 if fp64 else 4
     ib = info.get("list_index_bits", 16) / 8  # bytes per staged index in the lists
+    # bytes per weight: 20-bit fixed point in the packed lists, which only the
+    # cells with 12-bit indices hold (with some 16-bit cells, the full width)
+    wb = info.get("list_weight_bits", 8 * sT) / 8 if ib == 1.5 else sT
     vec = 3 * n
     if kind == "history":
         # what the convolution of the definition streams per step: the ring,
@@ -47,7 +50,7 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
     if kind == "dissipative":
         # staged index (12 or 16 bits) + weight per ordered pair, the pair
         # counts, the input vector once, the self-memory term added, the output
-        return dict(bytes=pairs * (ib + sT) + 4 * n + vec * sT * 3)
+        return dict(bytes=pairs * (ib + wb) + 4 * n + vec * sT * 3)
     if kind == "noise_spmv":
         # a term that streams the pair lists: index (12 or 16 bits) + weight
         # per ordered pair, the pair counts, the input vector once, the
@@ -55,7 +58,7 @@ def algorithmic(info, n, m_max, pairs, fp64, kind):
         # vectors: 4 components of sizeof(T)); the chain's first term has no
         # pair term and reads v_k only.  Arithmetic: 3 multiply-adds per
         # ordered pair (isotropic tensor) and the epilogue's 4 per component
-        full = pairs * (ib + sT) + 4 * n + 4 * n * sT * (1 + 1 + 1 + 1)
+        full = pairs * (ib + wb) + 4 * n + 4 * n * sT * (1 + 1 + 1 + 1)
         first = 4 * n * sT * 2
         return dict(full=full, first=first, flops=6.0 * pairs + 2.0 * 4 * vec)
     if kind == "noise_fir":
@@ -591,7 +594,8 @@ def main():
                    "verlet_skin": args.skin, "rebuild_period": args.rebuild_period},
         "latency_ms": pct(r32["lat"]),
         "noise": {k: r32["info"][k] for k in ("cheb_terms", "cheb_terms_tight", "lam_hi", "lam_hi_tight", "rank",
-                                              "block", "window_half", "err_estimate", "list_index_bits")}
+                                              "block", "window_half", "err_estimate", "list_index_bits",
+                                              "list_weight_bits")}
                  | {"tight_fraction_kernel_steps": r32["kt_tight"] / args.kernel_steps},
         "kernels_ms_per_step": per_step,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
@@ -608,7 +612,7 @@ def main():
             "ms_per_step_whole_check_cycles": r64["ms_cycle"],
             "latency_ms": pct(r64["lat"]),
             "noise": {k: r64["info"][k] for k in ("cheb_terms", "cheb_terms_tight", "rank", "block", "window_half",
-                                                  "err_estimate", "list_index_bits")}
+                                                  "err_estimate", "list_index_bits", "list_weight_bits")}
                      | {"tight_fraction_kernel_steps": r64["kt_tight"] / args.kernel_steps},
             "kernels_ms_per_step": {k: ms / args.kernel_steps for k, (ms, c) in r64["kt"].items()},
             "roofline_history": roofline_entry(r64, "history", True, args.kernel_steps),

@@ -108,6 +108,7 @@ class gld_noise_info(C.Structure):
         ("theta_max", C.c_double),
         ("tight_retired", C.c_int32),
         ("filters_given", C.c_int32),
+        ("list_weight_bits", C.c_int32),
     ]
 
 

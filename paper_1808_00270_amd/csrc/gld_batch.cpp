@@ -1249,6 +1249,7 @@ gld_status gld_batch_noise_parameters(const gld_batch *b, int32_t slot, gld_nois
     o->window_half = y.noise_on ? y.plan.half : 0;
     o->noise_window = 1;
     o->list_index_bits = 16;
+    o->list_weight_bits = b->fp64 ? 64 : 32;
     o->theta_min = y.theta[0];
     o->theta_max = y.theta[1];
     return GLD_OK;

@@ -362,6 +362,38 @@ __device__ __forceinline__ uint4 ids_load(const void *cell, int64_t k)
     }
 }
 
+// Packed chunk (narrow cells of FP32 isotropic lists): 8 words, each the
+// 12-bit staged index with the weight in 20-bit fixed point above it.
+__device__ __forceinline__ uint32_t pack_entry(unsigned idx, float w, float scale, int sgn)
+{
+    int q = __float2int_rn(w * scale);
+    q = sgn ? min(max(q, -kWeightQMaxSigned), kWeightQMaxSigned) : min(max(q, 0), kWeightQMax);
+    return (idx & 0xfffu) | (static_cast<uint32_t>(q) << 12);
+}
+
+__device__ __forceinline__ float entry_weight(uint32_t e, float inv, int sgn)
+{
+    const int q = sgn ? (static_cast<int>(e) >> 12) : static_cast<int>(e >> 12);
+    return static_cast<float>(q) * inv;
+}
+
+// a packed chunk (words pa: entries 0-3, pb: 4-7) as 16-bit indices and
+// weights (W4: the mat-vec's four-vector; packed lists are FP32 only)
+template <typename W4>
+__device__ __forceinline__ void unpack_chunk(uint4 pa, uint4 pb, float inv, int sgn, uint4 &id, W4 &wa, W4 &wb)
+{
+    id = make_uint4((pa.x & 0xfffu) | ((pa.y & 0xfffu) << 16), (pa.z & 0xfffu) | ((pa.w & 0xfffu) << 16),
+                    (pb.x & 0xfffu) | ((pb.y & 0xfffu) << 16), (pb.z & 0xfffu) | ((pb.w & 0xfffu) << 16));
+    wa.x = entry_weight(pa.x, inv, sgn);
+    wa.y = entry_weight(pa.y, inv, sgn);
+    wa.z = entry_weight(pa.z, inv, sgn);
+    wa.w = entry_weight(pa.w, inv, sgn);
+    wb.x = entry_weight(pb.x, inv, sgn);
+    wb.y = entry_weight(pb.y, inv, sgn);
+    wb.z = entry_weight(pb.z, inv, sgn);
+    wb.w = entry_weight(pb.w, inv, sgn);
+}
+
 // staged index U (0..7, a compile-time constant) of a loaded chunk
 template <bool NARROW, int U>
 __device__ __forceinline__ unsigned id_at(uint4 id)
@@ -407,6 +439,8 @@ struct BuildArgs {
     double wca_rc2, wca_s2, wca_eps;
     uint16_t *nbl;
     void *nbw;
+    int wpack, wq_signed;     // packed lists (narrow cells, FP32 isotropic) and the weight's form
+    float wq_scale;           // weight -> 20-bit fixed point
     int *nn;
     int2 *stab;
     const int2 *stab_c;
@@ -858,6 +892,33 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
     const bool narrow = total <= kNarrowStencil;
     const uint4 *cl = a.snl + static_cast<int64_t>(h0) * (a.capS >> 3);  // candidate lists, likewise
     T4 *nbw4 = static_cast<T4 *>(a.nbw) + static_cast<int64_t>(h0) * 2 * capc;
+    uint4 *nbp4 = reinterpret_cast<uint4 *>(nbw4);  // packed chunks: two words of four entries
+    const bool packed = sizeof(T) == 4 && !PAR && a.wpack && narrow;
+    // chunk c of the cell's particle jj from the ring at base: indices and
+    // weights, or the packed words
+    auto put_chunk = [&](int c, int jj, int base) __attribute__((always_inline)) {
+        const uint4 idv = *reinterpret_cast<const uint4_ring *>(ri + base);
+        const RV4 w0 = *reinterpret_cast<const RV4 *>(rw + base), w1 = *reinterpret_cast<const RV4 *>(rw + base + 4);
+        if (packed) {
+            const float sc = a.wq_scale;
+            const int sg = a.wq_signed;
+            nbp4[(2 * c) * occ + jj] = make_uint4(
+                pack_entry(idv.x & 0xffffu, static_cast<float>(w0.x), sc, sg),
+                pack_entry(idv.x >> 16, static_cast<float>(w0.y), sc, sg),
+                pack_entry(idv.y & 0xffffu, static_cast<float>(w0.z), sc, sg),
+                pack_entry(idv.y >> 16, static_cast<float>(w0.w), sc, sg));
+            nbp4[(2 * c + 1) * occ + jj] = make_uint4(
+                pack_entry(idv.z & 0xffffu, static_cast<float>(w1.x), sc, sg),
+                pack_entry(idv.z >> 16, static_cast<float>(w1.y), sc, sg),
+                pack_entry(idv.w & 0xffffu, static_cast<float>(w1.z), sc, sg),
+                pack_entry(idv.w >> 16, static_cast<float>(w1.w), sc, sg));
+            return;
+        }
+        if (narrow) nbl3[c * occ + jj] = ids_pack12(idv);
+        else nbl4[c * occ + jj] = idv;
+        nbw4[(2 * c) * occ + jj] = w0;
+        nbw4[(2 * c + 1) * occ + jj] = w1;
+    };
     for (int g0 = 0; g0 < occ; g0 += kRefreshGroup) {
         const bool live = g0 + pl < occ;
         const int64_t s = h0 + g0 + pl;
@@ -995,14 +1056,7 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
             // chunks completed this round, one per lane
             const int cnt1 = cnt + tot;
             const int fc = (cnt >> 3) + q;
-            if (fc < (cnt1 >> 3) && fc < capc) {
-                const int base = (fc * 8) & (RING - 1);
-                const uint4 idv = *reinterpret_cast<const uint4_ring *>(ri + base);
-                if (narrow) nbl3[fc * occ + (g0 + pl)] = ids_pack12(idv);
-                else nbl4[fc * occ + (g0 + pl)] = idv;
-                nbw4[(2 * fc) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base);
-                nbw4[(2 * fc + 1) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base + 4);
-            }
+            if (fc < (cnt1 >> 3) && fc < capc) put_chunk(fc, g0 + pl, (fc * 8) & (RING - 1));
             cnt = cnt1;
         }
         if (wn > 0) wca_flush();
@@ -1022,12 +1076,8 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
                     ri[p & (RING - 1)] = self_l;
                     rw[p & (RING - 1)] = T(0);
                 }
-                const int fl = kept >> 3, base = (fl * 8) & (RING - 1);
-                const uint4 idv = *reinterpret_cast<const uint4_ring *>(ri + base);
-                if (narrow) nbl3[fl * occ + (g0 + pl)] = ids_pack12(idv);
-                else nbl4[fl * occ + (g0 + pl)] = idv;
-                nbw4[(2 * fl) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base);
-                nbw4[(2 * fl + 1) * occ + (g0 + pl)] = *reinterpret_cast<const RV4 *>(rw + base + 4);
+                const int fl = kept >> 3;
+                put_chunk(fl, g0 + pl, (fl * 8) & (RING - 1));
             }
             if (cnt > a.cap) latch(a.flags, a.flag_step, GLD_ERR_CAPACITY, *a.d_step);
             a.nn[s] = kept;
@@ -1115,6 +1165,8 @@ struct MvArgs {
     int cap8;   // list chunks per particle (cap / 8)
     const uint4 *nbl;
     const void *nbw;
+    int wpack, wq_signed;  // packed lists in the narrow cells (FP32 isotropic); signed weights
+    float wq_inv;          // 20-bit fixed point -> weight
     const int *nn;
     const double4 *reld;  // parallel tensor: positions relative to their own cell
     Geo g;
@@ -1329,6 +1381,7 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
     // this cell's lists (cell-blocked: chunk c of the cell's particle j at
     // c occ + j, weight rows likewise)
     const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw) + static_cast<int64_t>(h0) * 2 * A.cap8;
+    const uint4 *__restrict__ nbp4 = reinterpret_cast<const uint4 *>(nbw4);  // packed chunks
     const void *nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;  // either index form
     const bool pair = ca != 0.0;
     const T Lb[3] = {static_cast<T>(A.g.L[0]), static_cast<T>(A.g.L[1]), static_cast<T>(A.g.L[2])};
@@ -1354,17 +1407,27 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
         }
         T p0 = 0, p1 = 0, p2 = 0;
         // the pair sum, for either index form of the cell's lists
-        auto pair_sum = [&](auto narrow_form) __attribute__((always_inline)) {
-            constexpr bool NR = decltype(narrow_form)::value;
+        // FM: the cell's list form, 0 wide (16-bit indices), 1 narrow (12-bit),
+        // 2 packed (12-bit index and 20-bit weight per word; its chunk's two
+        // words wait in id and id2 until the chunk is used)
+        auto pair_sum = [&](auto form) __attribute__((always_inline)) {
+            constexpr int FM = decltype(form)::value;
+            constexpr bool NR = FM == 1;
+            auto load = [&](int c, uint4 &i1, uint4 &i2, T4 &w1, T4 &w2) __attribute__((always_inline)) {
+                if constexpr (FM == 2) {
+                    i1 = nbp4[(2 * c) * occ + j];
+                    i2 = nbp4[(2 * c + 1) * occ + j];
+                } else {
+                    i1 = ids_load<NR>(nbl, c * occ + j);
+                    w1 = nbw4[(2 * c) * occ + j];
+                    w2 = nbw4[(2 * c + 1) * occ + j];
+                }
+            };
             // this lane's first chunk: its loads are in flight during the
             // staging below (a later staging round loads it again)
-            uint4 id = make_uint4(0, 0, 0, 0);
+            uint4 id = make_uint4(0, 0, 0, 0), id2 = make_uint4(0, 0, 0, 0);
             T4 wa{}, wb{};
-            if (sub < nch) {
-                id = ids_load<NR>(nbl, sub * occ + j);
-                wa = nbw4[(2 * sub) * occ + j];
-                wb = nbw4[(2 * sub + 1) * occ + j];
-            }
+            if (sub < nch) load(sub, id, id2, wa, wb);
             for (int c0 = 0; c0 < total; c0 += A.maxc) {
                 const int c1 = min(total, c0 + A.maxc);
                 const bool single = c0 == 0 && c1 == total;
@@ -1402,20 +1465,13 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                     staged_all = single;
                 }
                 // this lane's chunks, the next one's loads in flight
-                if (c0 > 0 && sub < nch) {
-                    id = ids_load<NR>(nbl, sub * occ + j);
-                    wa = nbw4[(2 * sub) * occ + j];
-                    wb = nbw4[(2 * sub + 1) * occ + j];
-                }
+                if (c0 > 0 && sub < nch) load(sub, id, id2, wa, wb);
                 for (int ch = sub; ch < nch; ch += L) {
-                    const uint4 cid8 = id;
-                    const T4 cwa = wa, cwb = wb;
-                    if (ch + L < nch) {
-                        const int nx = ch + L;
-                        id = ids_load<NR>(nbl, nx * occ + j);
-                        wa = nbw4[(2 * nx) * occ + j];
-                        wb = nbw4[(2 * nx + 1) * occ + j];
-                    }
+                    uint4 cid8 = id;
+                    const uint4 cid8b = id2;
+                    T4 cwa = wa, cwb = wb;
+                    if (ch + L < nch) load(ch + L, id, id2, wa, wb);
+                    if constexpr (FM == 2) unpack_chunk(cid8, cid8b, A.wq_inv, A.wq_signed, cid8, cwa, cwb);
                     if (single)
                         mv_chunk<T, PAR, false, MI, SOA, NR>(view, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1,
                                                              p2);
@@ -1427,8 +1483,14 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
             }
         };
         if (pair) {
-            if (narrow) pair_sum(std::true_type{});
-            else pair_sum(std::false_type{});
+            if constexpr (sizeof(T) == 4 && !PAR) {
+                if (narrow && A.wpack) pair_sum(std::integral_constant<int, 2>{});
+                else if (narrow) pair_sum(std::integral_constant<int, 1>{});
+                else pair_sum(std::integral_constant<int, 0>{});
+            } else {
+                if (narrow) pair_sum(std::integral_constant<int, 1>{});
+                else pair_sum(std::integral_constant<int, 0>{});
+            }
         }
         // the terms besides the pair sum, b x + cz z + sum_q c_q u_q, spread
         // over the L lanes of each particle (lane sub takes terms sub, sub + L,
@@ -1579,6 +1641,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
         return (DUAL && v == 1) ? static_cast<const T4 *>(A.y2) : x + static_cast<int64_t>(v) * A.S;
     };
     const T4 *__restrict__ nbw4 = static_cast<const T4 *>(A.nbw) + static_cast<int64_t>(h0) * 2 * A.cap8;
+    const uint4 *__restrict__ nbp4 = reinterpret_cast<const uint4 *>(nbw4);  // packed chunks
     const void *nbl = A.nbl + static_cast<int64_t>(h0) * A.cap8;  // either index form
     const bool pair = ca != 0.0;
     __syncthreads();
@@ -1597,8 +1660,20 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
 #pragma unroll
         for (int v = 0; v < NV; ++v) p[v][0] = p[v][1] = p[v][2] = T(0);
         // the pair sums, for either index form of the cell's lists
-        auto pair_sum = [&](auto narrow_form) __attribute__((always_inline)) {
-            constexpr bool NR = decltype(narrow_form)::value;
+        // FM: the cell's list form, as in k_mv (2: packed words in id, id2)
+        auto pair_sum = [&](auto form) __attribute__((always_inline)) {
+            constexpr int FM = decltype(form)::value;
+            constexpr bool NR = FM == 1;
+            auto load = [&](int c, uint4 &i1, uint4 &i2, T4 &w1, T4 &w2) __attribute__((always_inline)) {
+                if constexpr (FM == 2) {
+                    i1 = nbp4[(2 * c) * occ + j];
+                    i2 = nbp4[(2 * c + 1) * occ + j];
+                } else {
+                    i1 = ids_load<NR>(nbl, c * occ + j);
+                    w1 = nbw4[(2 * c) * occ + j];
+                    w2 = nbw4[(2 * c + 1) * occ + j];
+                }
+            };
             for (int c0 = 0; c0 < total; c0 += A.maxc) {
                 const int c1 = min(total, c0 + A.maxc);
                 const bool single = c0 == 0 && c1 == total;
@@ -1623,23 +1698,16 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                     __syncthreads();
                     staged_all = single;
                 }
-                uint4 id = make_uint4(0, 0, 0, 0);
+                uint4 id = make_uint4(0, 0, 0, 0), id2 = make_uint4(0, 0, 0, 0);
                 T4 wa{}, wb{};
-                if (sub < nch) {
-                    id = ids_load<NR>(nbl, sub * occ + j);
-                    wa = nbw4[(2 * sub) * occ + j];
-                    wb = nbw4[(2 * sub + 1) * occ + j];
-                }
+                if (sub < nch) load(sub, id, id2, wa, wb);
                 const unsigned cn = static_cast<unsigned>(c1 - c0);
                 for (int ch = sub; ch < nch; ch += L) {
-                    const uint4 cid8 = id;
-                    const T4 cwa = wa, cwb = wb;
-                    if (ch + L < nch) {
-                        const int nx = ch + L;
-                        id = ids_load<NR>(nbl, nx * occ + j);
-                        wa = nbw4[(2 * nx) * occ + j];
-                        wb = nbw4[(2 * nx + 1) * occ + j];
-                    }
+                    uint4 cid8 = id;
+                    const uint4 cid8b = id2;
+                    T4 cwa = wa, cwb = wb;
+                    if (ch + L < nch) load(ch + L, id, id2, wa, wb);
+                    if constexpr (FM == 2) unpack_chunk(cid8, cid8b, A.wq_inv, A.wq_signed, cid8, cwa, cwb);
                     const unsigned li[8] = {id_at<NR, 0>(cid8), id_at<NR, 1>(cid8), id_at<NR, 2>(cid8),
                                             id_at<NR, 3>(cid8), id_at<NR, 4>(cid8), id_at<NR, 5>(cid8),
                                             id_at<NR, 6>(cid8), id_at<NR, 7>(cid8)};
@@ -1672,8 +1740,14 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
             }
         };
         if (pair) {
-            if (narrow) pair_sum(std::true_type{});
-            else pair_sum(std::false_type{});
+            if constexpr (sizeof(T) == 4) {
+                if (narrow && A.wpack) pair_sum(std::integral_constant<int, 2>{});
+                else if (narrow) pair_sum(std::integral_constant<int, 1>{});
+                else pair_sum(std::integral_constant<int, 0>{});
+            } else {
+                if (narrow) pair_sum(std::integral_constant<int, 1>{});
+                else pair_sum(std::integral_constant<int, 0>{});
+            }
         }
         // b x_v + cz z_v + sum_q c_q u_{v,q}, spread over the L lanes of each
         // particle as in k_mv
@@ -1991,6 +2065,9 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     a.wca_eps = d.wca_eps;
     a.nbl = static_cast<uint16_t *>(d.nbl);
     a.nbw = d.nbw;
+    a.wpack = d.wpack;
+    a.wq_signed = d.wq_signed;
+    a.wq_scale = d.wq_scale;
     a.nn = d.nn;
     a.stab = static_cast<int2 *>(d.stab);
     a.stab_c = static_cast<const int2 *>(d.stab);
@@ -2046,6 +2123,9 @@ MvArgs mv_args(const Dev &d, double a, double b, const void *x, double cz, const
     A.cap8 = d.cap >> 3;
     A.nbl = static_cast<const uint4 *>(d.nbl);
     A.nbw = d.nbw;
+    A.wpack = d.wpack;
+    A.wq_signed = d.wq_signed;
+    A.wq_inv = d.wq_inv;
     A.nn = d.nn;
     A.reld = static_cast<const double4 *>(d.reld);
     A.g = make_geo(d);
