@@ -1197,6 +1197,15 @@ constexpr bool mv_soa()
     return !PAR;
 }
 
+// FP32: x and y interleaved as (x, y) pairs in the first two planes' space
+// (one 8-byte LDS read per staged entry instead of two; measured at N = 2e5,
+// rho = 0.5: 52.5 -> 50.1 us per mat-vec; FP64 gained nothing from it)
+template <typename T>
+constexpr bool mv_xy()
+{
+    return sizeof(T) == 4;
+}
+
 template <typename T, bool SOA>
 struct StageView {
     const typename V4<T>::t *aos;
@@ -1206,8 +1215,14 @@ struct StageView {
     {
         if constexpr (SOA) {
             typename V4<T>::t v;
-            v.x = soa[l];
-            v.y = soa[stride + l];
+            if constexpr (mv_xy<T>()) {
+                const typename V2<T>::t xy = reinterpret_cast<const typename V2<T>::t *>(soa)[l];
+                v.x = xy.x;
+                v.y = xy.y;
+            } else {
+                v.x = soa[l];
+                v.y = soa[stride + l];
+            }
             v.z = soa[2 * stride + l];
             v.w = T(0);
             return v;
@@ -1242,9 +1257,8 @@ __device__ __forceinline__ void mv_chunk(const StageView<T, SOA> &xs, const type
                             id_at<NARROW, 3>(id), id_at<NARROW, 4>(id), id_at<NARROW, 5>(id),
                             id_at<NARROW, 6>(id), id_at<NARROW, 7>(id)};
     const T w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-    if constexpr (!CHECK && SOA && !PAR) {
-        // one plane at a time: eight staged values live instead of 24 (the
-        // FP32 kernel then needs about 62 registers: eight waves per SIMD)
+    if constexpr (!CHECK && SOA && !PAR && !mv_xy<T>()) {
+        // one plane at a time: eight staged values live instead of 24
         T acc[3] = {p0, p1, p2};
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -1257,6 +1271,29 @@ __device__ __forceinline__ void mv_chunk(const StageView<T, SOA> &xs, const type
         p0 = acc[0];
         p1 = acc[1];
         p2 = acc[2];
+    } else if constexpr (!CHECK && SOA && !PAR) {
+        // (x, y) pairs four entries at a time, then the z plane: eight
+        // staged values live (the FP32 kernel then needs 64 registers:
+        // eight waves per SIMD), two LDS reads per entry instead of three;
+        // each component's sum takes the entries in order
+        using T2 = typename V2<T>::t;
+        const T2 *xy = reinterpret_cast<const T2 *>(xs.soa);
+#pragma unroll
+        for (int h = 0; h < 8; h += 4) {
+            T2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = xy[li[h + u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                p0 += w[h + u] * v[u].x;
+                p1 += w[h + u] * v[u].y;
+            }
+        }
+        T vz[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vz[u] = xs.soa[2 * xs.stride + li[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p2 += w[u] * vz[u];
     } else if (!CHECK) {
         T4 v[8];
 #pragma unroll
@@ -1453,7 +1490,13 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                             yz.y = static_cast<T>(q.z) + static_cast<T>(A.g.offs[2][e2] * A.g.edge[2]);
                             pyz[l - c0] = yz;
                         }
-                        if constexpr (SOA) {
+                        if constexpr (SOA && mv_xy<T>()) {
+                            T2 xyv;
+                            xyv.x = v.x;
+                            xyv.y = v.y;
+                            reinterpret_cast<T2 *>(xsoa)[l - c0] = xyv;
+                            xsoa[2 * sstride + (l - c0)] = v.z;
+                        } else if constexpr (SOA) {
                             xsoa[l - c0] = v.x;
                             xsoa[sstride + (l - c0)] = v.y;
                             xsoa[2 * sstride + (l - c0)] = v.z;
