@@ -189,7 +189,6 @@ struct Dev {
 constexpr int kPartials = 1024;
 
 // Launchers (gld_kernels.hip).  All enqueue on `st` and return hipError_t.
-hipError_t launch_zero_int(int *p, int64_t n, hipStream_t st);
 hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out);
 // history convolution of the step: the block's product (launch_history_block)
 // plus the step's own lags

@@ -126,14 +126,8 @@ struct Geo {
 
 // The cell list and the candidate lists are rebuilt only when the device
 // flag *gate is set (see k_disp_check); every kernel of the rebuild checks it
-// first, so the same launch sequence serves every step of a graph.
-__global__ void k_zero(int *p, int64_t n, const int *gate)
-{
-    if (gate && *gate == 0) return;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
+// first, so the same launch sequence serves every step of a graph.  The cell
+// counts start at zero (the scan of the previous rebuild cleared them).
 __global__ void k_cell_assign(const double *__restrict__ R, int64_t S, int64_t n, Geo g, double *__restrict__ Rw,
                               int *__restrict__ cell_id, int *__restrict__ cell_slot, int *__restrict__ cell_count,
                               const int *gate)
@@ -153,8 +147,10 @@ __global__ void k_cell_assign(const double *__restrict__ R, int64_t S, int64_t n
     cell_slot[i] = atomicAdd(&cell_count[cid], 1);
 }
 
-// exclusive scan of the cell counts by one work-group (chunked)
-__global__ void k_cell_scan(const int *__restrict__ count, int *__restrict__ start, int ncell, const int *gate)
+// exclusive scan of the cell counts by one work-group (chunked); the counts
+// are cleared behind it, so they start at zero at the next rebuild (the
+// workspace starts zeroed)
+__global__ void k_cell_scan(int *__restrict__ count, int *__restrict__ start, int ncell, const int *gate)
 {
     if (*gate == 0) return;
     __shared__ int part[1024];
@@ -175,6 +171,7 @@ __global__ void k_cell_scan(const int *__restrict__ count, int *__restrict__ sta
     for (int k = b; k < e; ++k) {
         start[k] = run;
         run += count[k];
+        count[k] = 0;
     }
     if (tid == nt - 1) start[ncell] = part[tid];
 }
@@ -234,14 +231,18 @@ __global__ void k_disp_check(int64_t n, int64_t S, const int *__restrict__ sorte
 // Every step, after the rebuild kernels: current positions in the cell order
 // of the last build, relative to the build-time cell (relb + R - rb, from the
 // unwrapped displacement, so crossing the box edge needs no care), as double
-// and float, and wrapped absolute (WCA).  Clears the rebuild flag.
+// and float, and wrapped absolute (WCA).  Clears the rebuild flag and the
+// row-sum maximum that the refresh then takes.
 __global__ void k_rel_update(int64_t n, int64_t S, Geo g, const int *__restrict__ sorted,
                              const double *__restrict__ R, const double4 *__restrict__ rb,
                              const double4 *__restrict__ relb, double4 *__restrict__ reld, float4 *__restrict__ relf,
-                             double4 *__restrict__ pos_s, int *gate)
+                             double4 *__restrict__ pos_s, int *gate, unsigned *rowmax)
 {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s == 0) *gate = 0;
+    if (s == 0) {
+        *gate = 0;
+        *rowmax = 0u;
+    }
     if (s >= n) return;
     const int p = sorted[s];
     const double x = R[p], y = R[S + p], z = R[2 * S + p];
@@ -2055,13 +2056,6 @@ int mv_max_staging(int fp64, int parallel)
 // ===========================================================================
 // launchers
 // ===========================================================================
-hipError_t launch_zero_int(int *p, int64_t n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    k_zero<<<blocks(n, 256), 256, 0, st>>>(p, n, nullptr);
-    return hipGetLastError();
-}
-
 hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
 {
     const Geo g = make_geo(d);
@@ -2071,7 +2065,6 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     const double half = 0.5 * d.skin;
     k_disp_check<<<nb, 256, 0, st>>>(d.n, d.S, d.cell_sorted, d.R, static_cast<const double4 *>(d.rb_s), half * half,
                                      d.d_rebuild, d.d_step, d.rebuild_period);
-    k_zero<<<blocks(d.ncell, 256), 256, 0, st>>>(d.cell_count, d.ncell, d.d_rebuild);
     k_cell_assign<<<nb, 256, 0, st>>>(d.R, d.S, d.n, g, d.Rw, d.cell_id, d.cell_slot, d.cell_count, d.d_rebuild);
     k_cell_scan<<<1, 1024, 0, st>>>(d.cell_count, d.cell_start, d.ncell, d.d_rebuild);
     k_cell_scatter<<<nb, 256, 0, st>>>(d.n, d.cell_id, d.cell_slot, d.cell_start, d.cell_tmp, d.d_rebuild);
@@ -2130,8 +2123,8 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     // current positions in the build's cell order; clears the rebuild flag
     k_rel_update<<<nb, 256, 0, st>>>(d.n, d.S, g, d.cell_sorted, d.R, static_cast<const double4 *>(d.rb_s),
                                      static_cast<const double4 *>(d.relb), static_cast<double4 *>(d.reld),
-                                     static_cast<float4 *>(d.relf), static_cast<double4 *>(d.pos_s), d.d_rebuild);
-    if ((e = launch_zero_int(reinterpret_cast<int *>(d.d_rowmax), 1, st)) != hipSuccess) return e;
+                                     static_cast<float4 *>(d.relf), static_cast<double4 *>(d.pos_s), d.d_rebuild,
+                                     d.d_rowmax);
     return d.fp64 ? launch_refresh_t<double, true>(d, a, mi, st) : launch_refresh_t<float, false>(d, a, mi, st);
 }
 
