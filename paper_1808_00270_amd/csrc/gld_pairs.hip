@@ -869,8 +869,22 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
     const int nstage = min(total, a.stage_n);
     // (one slot past the staged ones is read for candidates that are not
     // staged, and for the end marker)
-    for (int l = tid; l < nstage; l += kRefreshThreads)
-        pos[l] = stencil_pos<T, EXACT64>(a, sst, sb, off, l, entry_of(sb, nst, l));
+    {
+        // four positions per thread at a time: their searches and loads in
+        // flight together, then the stores
+        int l = tid;
+        for (; l + 3 * kRefreshThreads < nstage; l += 4 * kRefreshThreads) {
+            int e[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) e[u] = entry_of(sb, nst, l + u * kRefreshThreads);
+            T4 p[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[u] = stencil_pos<T, EXACT64>(a, sst, sb, off, l + u * kRefreshThreads, e[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pos[l + u * kRefreshThreads] = p[u];
+        }
+        for (; l < nstage; l += kRefreshThreads) pos[l] = stencil_pos<T, EXACT64>(a, sst, sb, off, l, entry_of(sb, nst, l));
+    }
     if (tid == 0) pos[nstage] = T4{};
     __syncthreads();
 
@@ -1207,6 +1221,8 @@ constexpr bool mv_xy()
     return sizeof(T) == 4;
 }
 
+constexpr int kStageDepth = 4;  // staged entries a thread of the mat-vec has in flight
+
 template <typename T, bool SOA>
 struct StageView {
     const typename V4<T>::t *aos;
@@ -1495,6 +1511,22 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
         }
         T p0 = 0, p1 = 0, p2 = 0;
         // the pair sum, for either index form of the cell's lists
+        // a staged input entry into the LDS layout of the view
+        auto stage_put = [&](int at, const T4 &v) __attribute__((always_inline)) {
+            if constexpr (SOA && mv_xy<T>()) {
+                T2 xyv;
+                xyv.x = v.x;
+                xyv.y = v.y;
+                reinterpret_cast<T2 *>(xsoa)[at] = xyv;
+                xsoa[2 * sstride + at] = v.z;
+            } else if constexpr (SOA) {
+                xsoa[at] = v.x;
+                xsoa[sstride + at] = v.y;
+                xsoa[2 * sstride + at] = v.z;
+            } else {
+                xs[at] = v;
+            }
+        };
         // FM: the cell's list form, 0 wide (16-bit indices), 1 narrow (12-bit),
         // 2 and 3 packed (12-bit index and 20-bit weight per word, unsigned or
         // signed; its chunk's two words wait in id and id2 until the chunk is
@@ -1522,15 +1554,42 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                 const bool single = c0 == 0 && c1 == total;
                 if (!(single && staged_all)) {
                     __syncthreads();
-                    for (int l = c0 + tid; l < c1; l += BS) {
+                    // the stencil entry holding staged index l
+                    auto source = [&](int l) __attribute__((always_inline)) {
                         int lo = 0, hi = nst - 1;
                         while (lo < hi) {
                             const int mid = (lo + hi + 1) >> 1;
                             if (sbase[mid] <= l) lo = mid; else hi = mid - 1;
                         }
-                        const int t = sst[lo] + (l - sbase[lo]);
-                        T4 v = x[t];
-                        if (PAR) {
+                        return lo;
+                    };
+                    if constexpr (!PAR) {
+                        // kStageDepth entries per thread at a time: their
+                        // searches and loads in flight together, then the
+                        // stores
+                        int l = c0 + tid;
+                        for (; l + (kStageDepth - 1) * BS < c1; l += kStageDepth * BS) {
+                            int t[kStageDepth];
+#pragma unroll
+                            for (int u = 0; u < kStageDepth; ++u) {
+                                const int e = source(l + u * BS);
+                                t[u] = sst[e] + (l + u * BS - sbase[e]);
+                            }
+                            T4 v[kStageDepth];
+#pragma unroll
+                            for (int u = 0; u < kStageDepth; ++u) v[u] = x[t[u]];
+#pragma unroll
+                            for (int u = 0; u < kStageDepth; ++u) stage_put(l + u * BS - c0, v[u]);
+                        }
+                        for (; l < c1; l += BS) {
+                            const int e = source(l);
+                            stage_put(l - c0, x[sst[e] + (l - sbase[e])]);
+                        }
+                    } else {
+                        for (int l = c0 + tid; l < c1; l += BS) {
+                            const int lo = source(l);
+                            const int t = sst[lo] + (l - sbase[lo]);
+                            T4 v = x[t];
                             const int e0 = lo % A.g.noff[0], e1 = (lo / A.g.noff[0]) % A.g.noff[1];
                             const int e2 = lo / (A.g.noff[0] * A.g.noff[1]);
                             const double4 q = A.reld[t];
@@ -1541,19 +1600,7 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                             yz.x = static_cast<T>(q.y) + static_cast<T>(A.g.offs[1][e1] * A.g.edge[1]);
                             yz.y = static_cast<T>(q.z) + static_cast<T>(A.g.offs[2][e2] * A.g.edge[2]);
                             pyz[l - c0] = yz;
-                        }
-                        if constexpr (SOA && mv_xy<T>()) {
-                            T2 xyv;
-                            xyv.x = v.x;
-                            xyv.y = v.y;
-                            reinterpret_cast<T2 *>(xsoa)[l - c0] = xyv;
-                            xsoa[2 * sstride + (l - c0)] = v.z;
-                        } else if constexpr (SOA) {
-                            xsoa[l - c0] = v.x;
-                            xsoa[sstride + (l - c0)] = v.y;
-                            xsoa[2 * sstride + (l - c0)] = v.z;
-                        } else {
-                            xs[l - c0] = v;
+                            stage_put(l - c0, v);
                         }
                     }
                     __syncthreads();
@@ -1786,22 +1833,34 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                 const bool single = c0 == 0 && c1 == total;
                 if (!(single && staged_all)) {
                     __syncthreads();
-                    for (int l = c0 + tid; l < c1; l += BS) {
-                        int lo = 0, hi = nst - 1;
-                        while (lo < hi) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (sbase[mid] <= l) lo = mid; else hi = mid - 1;
+                    // entries l + u BS (u < D) of the stage, their searches
+                    // and loads in flight together, then the stores
+                    auto stage = [&](int l, auto depth) __attribute__((always_inline)) {
+                        constexpr int D = decltype(depth)::value;
+                        int t[D];
+#pragma unroll
+                        for (int u = 0; u < D; ++u) {
+                            const int e = entry_of(sbase, nst, l + u * BS);
+                            t[u] = sst[e] + (l + u * BS - sbase[e]);
                         }
-                        const int t = sst[lo] + (l - sbase[lo]);
 #pragma unroll
                         for (int v = 0; v < NV; ++v) {
                             if (v >= nvl) break;
-                            const T4 q = vin(v)[t];
-                            xsoa[(3 * v + 0) * ss + (l - c0)] = q.x;
-                            xsoa[(3 * v + 1) * ss + (l - c0)] = q.y;
-                            xsoa[(3 * v + 2) * ss + (l - c0)] = q.z;
+                            T4 q[D];
+#pragma unroll
+                            for (int u = 0; u < D; ++u) q[u] = vin(v)[t[u]];
+#pragma unroll
+                            for (int u = 0; u < D; ++u) {
+                                xsoa[(3 * v + 0) * ss + (l + u * BS - c0)] = q[u].x;
+                                xsoa[(3 * v + 1) * ss + (l + u * BS - c0)] = q[u].y;
+                                xsoa[(3 * v + 2) * ss + (l + u * BS - c0)] = q[u].z;
+                            }
                         }
-                    }
+                    };
+                    int l = c0 + tid;
+                    for (; l + (kStageDepth - 1) * BS < c1; l += kStageDepth * BS)
+                        stage(l, std::integral_constant<int, kStageDepth>{});
+                    for (; l < c1; l += BS) stage(l, std::integral_constant<int, 1>{});
                     __syncthreads();
                     staged_all = single;
                 }
