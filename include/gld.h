@@ -207,12 +207,13 @@ typedef struct {
                                (the wide plan until the next gld_write_state)       */
     int32_t filters_given;  /* 1: the filters came from gld_params.noise_a/b      */
     int32_t list_weight_bits; /* bits per pair weight in the lists of the cells with
-                               12-bit indices: 20 (fixed point relative to the
-                               largest |w| of the table, index and weight in one
-                               32-bit word) in FP32_MIXED with the isotropic tensor
-                               and a library-built noise plan of tolerance at
-                               least 4e-6, which moves F^R by about 1e-6 of its
-                               rms; else 32 (FP32) or 64 (FP64)                   */
+                               12-bit indices, isotropic tensor: fixed point
+                               relative to the largest |w| of the table, index
+                               and weight in one word; 52 of 64 bits in FP64
+                               (about 1e-16 of the largest weight); 20 of 32
+                               bits in FP32_MIXED with a library-built noise
+                               plan of tolerance at least 4e-6 (moves F^R by
+                               about 1e-6 of its rms), else 32                    */
 } gld_noise_info;
 
 typedef struct gld_system gld_system;

@@ -1083,22 +1083,25 @@ gld_status gld_create(const gld_params *params, const double *r0, const double *
     d.g0 = d.has_pair ? p.k_pair_g[0] : 0.0;
     d.check_iters = p.check_iters > 0 ? p.check_iters : gld::kCheckIters;
     {
-        // packed pair lists where the noise tolerance leaves room for 20-bit
-        // weights (their rounding moves F^R by about 1e-6 of its rms); not
-        // with caller-built filters, whose accuracy the library does not know
+        // packed pair lists (isotropic tensor): in FP64 always (52 bits:
+        // about 1e-16 of the largest weight); in FP32-mixed where a noise plan
+        // built here leaves room for 20-bit weights (their rounding moves F^R
+        // by about 1e-6 of its rms), not with caller-built filters, whose
+        // accuracy the library does not know
         const double tol = p.noise_tol > 0 ? p.noise_tol : (d.fp64 ? gld::kNoiseTolFp64 : gld::kNoiseTolMixed);
         double wmax = 0.0, wmin = 0.0;
         for (int b = 0; d.has_pair && b < p.n_r; ++b) {
             wmax = std::max(wmax, std::fabs(p.k_pair_w[b]));
             wmin = std::min(wmin, p.k_pair_w[b]);
         }
-        d.wpack = (!d.fp64 && !d.parallel && d.has_pair && p.kT > 0 && !p.noise_a && tol >= gld::kNoiseTolMixed &&
-                   wmax > 0) ? 1 : 0;
+        d.wpack = (!d.parallel && d.has_pair && wmax > 0 &&
+                   (d.fp64 || (p.kT > 0 && !p.noise_a && tol >= gld::kNoiseTolMixed))) ? 1 : 0;
         if (d.wpack) {
             d.wq_signed = wmin < 0 ? 1 : 0;
-            const double qmax = d.wq_signed ? gld::kWeightQMaxSigned : gld::kWeightQMax;
-            d.wq_scale = static_cast<float>(qmax / wmax);
-            d.wq_inv = static_cast<float>(wmax / qmax);
+            const double qmax = d.fp64 ? static_cast<double>(d.wq_signed ? gld::kWeightQMaxSigned64 : gld::kWeightQMax64)
+                                       : (d.wq_signed ? gld::kWeightQMaxSigned : gld::kWeightQMax);
+            d.wq_scale = qmax / wmax;
+            d.wq_inv = wmax / qmax;
         }
     }
 
@@ -1300,7 +1303,7 @@ gld_status gld_noise_parameters(const gld_system *s, gld_noise_info *o)
     o->theta_max = th[1];
     o->tight_retired = retired;
     o->filters_given = s->filters_given ? 1 : 0;
-    o->list_weight_bits = s->d.wpack ? 20 : (s->d.fp64 ? 64 : 32);
+    o->list_weight_bits = s->d.wpack ? (s->d.fp64 ? 52 : 20) : (s->d.fp64 ? 64 : 32);
     return GLD_OK;
 }
 

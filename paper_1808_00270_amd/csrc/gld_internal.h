@@ -18,8 +18,10 @@ constexpr int kMaxRank = 32;      // filters in the white-noise filter bank
 // 1e-5, and the noise construction takes 4e-6 of it (the FP32 arithmetic of
 // the chain, the history and the weights adds well under 1e-6); FP64 1e-12
 constexpr double kNoiseTolMixed = 4e-6, kNoiseTolFp64 = 1e-12;
-// largest magnitude of a 20-bit fixed-point pair weight (unsigned, signed)
+// largest magnitude of a fixed-point pair weight, 20 bits (FP32 lists) or
+// 52 bits (FP64 lists), unsigned and signed
 constexpr int kWeightQMax = (1 << 20) - 1, kWeightQMaxSigned = (1 << 19) - 1;
+constexpr long long kWeightQMax64 = (1LL << 52) - 1, kWeightQMaxSigned64 = (1LL << 51) - 1;
 constexpr int kCheckIters = 40;   // Lanczos iterations of a spectrum check (default)
 constexpr int kMaxCheckIters = GLD_MAX_CHECK_ITERS;  // the most a system may ask for
 
@@ -142,13 +144,14 @@ struct Dev {
                                         // bits, or 8 x 12 bits in 12 bytes where the stencil holds <= 4096
     void *nbw = nullptr;                // T pair weights (w, or w / R^2 for the parallel tensor), cell-blocked
                                         // [cap/4][occ][4] from row h0 cap/4
-    // packed lists (FP32-mixed, isotropic tensor, noise tolerance >= the
-    // default): a narrow cell's entry is one 32-bit word in nbw, the 12-bit
-    // staged index in bits 0-11 and the weight in 20-bit fixed point above
-    // it (q = round(w wq_scale), unsigned, or signed when the table has
-    // negative values; w = q wq_inv); nbl is then unused for that cell
+    // packed lists (isotropic tensor, library-built noise plan; FP32-mixed at
+    // a noise tolerance >= the default): a narrow cell's entry is one word in
+    // nbw, the 12-bit staged index in bits 0-11 and the weight in fixed point
+    // above it, 20 bits of a 32-bit word (FP32) or 52 of a 64-bit one (FP64)
+    // (q = round(w wq_scale), unsigned, or signed when the table has negative
+    // values; w = q wq_inv); nbl is then unused for that cell
     int wpack = 0, wq_signed = 0;
-    float wq_scale = 0.f, wq_inv = 0.f;
+    double wq_scale = 0.0, wq_inv = 0.0;
     void *stab = nullptr;               // int2 [ncell][28] stencil of each cell (first index, base)
     int maxc = 0;                       // candidates staged per round by the mat-vec
     void *snl = nullptr;                // uint16 [capS/8][n][8] candidate lists (staged indices, within r_cut + skin)

@@ -372,6 +372,19 @@ __device__ __forceinline__ uint32_t pack_entry(unsigned idx, float w, float scal
     return (idx & 0xfffu) | (static_cast<uint32_t>(q) << 12);
 }
 
+// FP64 lists: a 64-bit word, the index in bits 0-11, 52-bit weight above
+__device__ __forceinline__ uint64_t pack_entry64(unsigned idx, double w, double scale, int sgn)
+{
+    long long q = llrint(w * scale);
+    q = sgn ? min(max(q, -kWeightQMaxSigned64), kWeightQMaxSigned64) : min(max(q, 0LL), kWeightQMax64);
+    return static_cast<uint64_t>(idx & 0xfffu) | (static_cast<uint64_t>(q) << 12);
+}
+
+__device__ __forceinline__ double entry_q64(uint64_t e, int sgn)
+{
+    return sgn ? static_cast<double>(static_cast<long long>(e) >> 12) : static_cast<double>(e >> 12);
+}
+
 __device__ __forceinline__ float entry_weight(uint32_t e, float inv, int sgn)
 {
     const int q = sgn ? (static_cast<int>(e) >> 12) : static_cast<int>(e >> 12);
@@ -393,6 +406,35 @@ __device__ __forceinline__ void unpack_chunk(uint4 pa, uint4 pb, float inv, int 
     wb.y = entry_weight(pb.y, inv, sgn);
     wb.z = entry_weight(pb.z, inv, sgn);
     wb.w = entry_weight(pb.w, inv, sgn);
+}
+
+// a packed FP64 chunk, its eight words held as the bits of two double4
+// (entries 0-3, 4-7), as 16-bit indices and weights
+template <typename W4>
+__device__ __forceinline__ void unpack_chunk64(const W4 &ra, const W4 &rb, double inv, int sgn, uint4 &id, W4 &wa,
+                                               W4 &wb)
+{
+    const uint64_t e[8] = {static_cast<uint64_t>(__double_as_longlong(ra.x)),
+                           static_cast<uint64_t>(__double_as_longlong(ra.y)),
+                           static_cast<uint64_t>(__double_as_longlong(ra.z)),
+                           static_cast<uint64_t>(__double_as_longlong(ra.w)),
+                           static_cast<uint64_t>(__double_as_longlong(rb.x)),
+                           static_cast<uint64_t>(__double_as_longlong(rb.y)),
+                           static_cast<uint64_t>(__double_as_longlong(rb.z)),
+                           static_cast<uint64_t>(__double_as_longlong(rb.w))};
+    const unsigned i[8] = {static_cast<unsigned>(e[0]) & 0xfffu, static_cast<unsigned>(e[1]) & 0xfffu,
+                           static_cast<unsigned>(e[2]) & 0xfffu, static_cast<unsigned>(e[3]) & 0xfffu,
+                           static_cast<unsigned>(e[4]) & 0xfffu, static_cast<unsigned>(e[5]) & 0xfffu,
+                           static_cast<unsigned>(e[6]) & 0xfffu, static_cast<unsigned>(e[7]) & 0xfffu};
+    id = make_uint4(i[0] | (i[1] << 16), i[2] | (i[3] << 16), i[4] | (i[5] << 16), i[6] | (i[7] << 16));
+    wa.x = entry_q64(e[0], sgn) * inv;
+    wa.y = entry_q64(e[1], sgn) * inv;
+    wa.z = entry_q64(e[2], sgn) * inv;
+    wa.w = entry_q64(e[3], sgn) * inv;
+    wb.x = entry_q64(e[4], sgn) * inv;
+    wb.y = entry_q64(e[5], sgn) * inv;
+    wb.z = entry_q64(e[6], sgn) * inv;
+    wb.w = entry_q64(e[7], sgn) * inv;
 }
 
 // staged index U (0..7, a compile-time constant) of a loaded chunk
@@ -440,8 +482,9 @@ struct BuildArgs {
     double wca_rc2, wca_s2, wca_eps;
     uint16_t *nbl;
     void *nbw;
-    int wpack, wq_signed;     // packed lists (narrow cells, FP32 isotropic) and the weight's form
-    float wq_scale;           // weight -> 20-bit fixed point
+    int wpack, wq_signed;     // packed lists (narrow cells, isotropic) and the weight's form
+    double wq_scale;          // weight -> fixed point (FP64 lists)
+    float wq_scale32;         // the same for FP32 lists
     int *nn;
     int2 *stab;
     const int2 *stab_c;
@@ -908,14 +951,37 @@ __global__ __launch_bounds__(kRefreshThreads) void k_refresh(BuildArgs a)
     const uint4 *cl = a.snl + static_cast<int64_t>(h0) * (a.capS >> 3);  // candidate lists, likewise
     T4 *nbw4 = static_cast<T4 *>(a.nbw) + static_cast<int64_t>(h0) * 2 * capc;
     uint4 *nbp4 = reinterpret_cast<uint4 *>(nbw4);  // packed chunks: two words of four entries
-    const bool packed = sizeof(T) == 4 && !PAR && a.wpack && narrow;
+    const bool packed = !PAR && a.wpack && narrow;
     // chunk c of the cell's particle jj from the ring at base: indices and
     // weights, or the packed words
     auto put_chunk = [&](int c, int jj, int base) __attribute__((always_inline)) {
         const uint4 idv = *reinterpret_cast<const uint4_ring *>(ri + base);
         const RV4 w0 = *reinterpret_cast<const RV4 *>(rw + base), w1 = *reinterpret_cast<const RV4 *>(rw + base + 4);
-        if (packed) {
-            const float sc = a.wq_scale;
+        if constexpr (sizeof(T) == 8) {
+            if (packed) {
+                // eight 64-bit words in the weights' two double4 slots
+                const double sc = a.wq_scale;
+                const int sg = a.wq_signed;
+                const unsigned ix[8] = {idv.x & 0xffffu, idv.x >> 16, idv.y & 0xffffu, idv.y >> 16,
+                                        idv.z & 0xffffu, idv.z >> 16, idv.w & 0xffffu, idv.w >> 16};
+                const double wv8[8] = {static_cast<double>(w0.x), static_cast<double>(w0.y), static_cast<double>(w0.z),
+                                       static_cast<double>(w0.w), static_cast<double>(w1.x), static_cast<double>(w1.y),
+                                       static_cast<double>(w1.z), static_cast<double>(w1.w)};
+                T4 o0, o1;
+                o0.x = __longlong_as_double(pack_entry64(ix[0], wv8[0], sc, sg));
+                o0.y = __longlong_as_double(pack_entry64(ix[1], wv8[1], sc, sg));
+                o0.z = __longlong_as_double(pack_entry64(ix[2], wv8[2], sc, sg));
+                o0.w = __longlong_as_double(pack_entry64(ix[3], wv8[3], sc, sg));
+                o1.x = __longlong_as_double(pack_entry64(ix[4], wv8[4], sc, sg));
+                o1.y = __longlong_as_double(pack_entry64(ix[5], wv8[5], sc, sg));
+                o1.z = __longlong_as_double(pack_entry64(ix[6], wv8[6], sc, sg));
+                o1.w = __longlong_as_double(pack_entry64(ix[7], wv8[7], sc, sg));
+                nbw4[(2 * c) * occ + jj] = o0;
+                nbw4[(2 * c + 1) * occ + jj] = o1;
+                return;
+            }
+        } else if (packed) {
+            const float sc = a.wq_scale32;
             const int sg = a.wq_signed;
             nbp4[(2 * c) * occ + jj] = make_uint4(
                 pack_entry(idv.x & 0xffffu, static_cast<float>(w0.x), sc, sg),
@@ -1180,8 +1246,9 @@ struct MvArgs {
     int cap8;   // list chunks per particle (cap / 8)
     const uint4 *nbl;
     const void *nbw;
-    int wpack, wq_signed;  // packed lists in the narrow cells (FP32 isotropic); signed weights
-    float wq_inv;          // 20-bit fixed point -> weight
+    int wpack, wq_signed;  // packed lists in the narrow cells (isotropic); signed weights
+    double wq_inv;         // fixed point -> weight (FP64 lists)
+    float wq_inv32;        // the same for FP32 lists
     const int *nn;
     const double4 *reld;  // parallel tensor: positions relative to their own cell
     Geo g;
@@ -1408,6 +1475,55 @@ __device__ __forceinline__ void mv_chunk_packed(const StageView<float, true> &xs
     }
 }
 
+// One packed FP64 chunk (isotropic, three planes): the eight 64-bit words
+// held as the bits of ra (entries 0-3) and rb (4-7), index e & 0xfff and
+// weight q = e >> 12 in units of the dequantisation step, as above.
+template <bool SGN, bool CHECK>
+__device__ __forceinline__ void mv_chunk_packed64(const StageView<double, true> &xs, const double4 &ra,
+                                                  const double4 &rb, unsigned c0, unsigned cn, double &p0, double &p1,
+                                                  double &p2)
+{
+    const uint64_t e[8] = {static_cast<uint64_t>(__double_as_longlong(ra.x)),
+                           static_cast<uint64_t>(__double_as_longlong(ra.y)),
+                           static_cast<uint64_t>(__double_as_longlong(ra.z)),
+                           static_cast<uint64_t>(__double_as_longlong(ra.w)),
+                           static_cast<uint64_t>(__double_as_longlong(rb.x)),
+                           static_cast<uint64_t>(__double_as_longlong(rb.y)),
+                           static_cast<uint64_t>(__double_as_longlong(rb.z)),
+                           static_cast<uint64_t>(__double_as_longlong(rb.w))};
+    unsigned li[8];
+    double q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        li[u] = static_cast<unsigned>(e[u]) & 0xfffu;
+        q[u] = entry_q64(e[u], SGN);
+    }
+    if constexpr (!CHECK) {
+        double acc[3] = {p0, p1, p2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = xs.soa[d * xs.stride + li[u]];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[d] += q[u] * v[u];
+        }
+        p0 = acc[0];
+        p1 = acc[1];
+        p2 = acc[2];
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const unsigned l = li[u] - c0;
+            if (l >= cn) continue;
+            const double4 v = xs.get(l);
+            p0 += q[u] * v.x;
+            p1 += q[u] * v.y;
+            p2 += q[u] * v.z;
+        }
+    }
+}
+
 // output of particle so (cell order): to the sorted vector, or to the
 // original order with an optional addend
 template <typename T>
@@ -1535,9 +1651,13 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
             constexpr int FM = decltype(form)::value;
             constexpr bool NR = FM == 1, PK = FM >= 2;
             auto load = [&](int c, uint4 &i1, uint4 &i2, T4 &w1, T4 &w2) __attribute__((always_inline)) {
-                if constexpr (PK) {
+                if constexpr (PK && sizeof(T) == 4) {
                     i1 = nbp4[(2 * c) * occ + j];
                     i2 = nbp4[(2 * c + 1) * occ + j];
+                } else if constexpr (PK) {
+                    // FP64: the chunk's eight words in the weights' slots
+                    w1 = nbw4[(2 * c) * occ + j];
+                    w2 = nbw4[(2 * c + 1) * occ + j];
                 } else {
                     i1 = ids_load<NR>(nbl, c * occ + j);
                     w1 = nbw4[(2 * c) * occ + j];
@@ -1612,12 +1732,18 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
                     const uint4 cid8 = id, cid8b = id2;
                     const T4 cwa = wa, cwb = wb;
                     if (ch + L < nch) load(ch + L, id, id2, wa, wb);
-                    if constexpr (PK) {
+                    if constexpr (PK && sizeof(T) == 4) {
                         if (single)
                             mv_chunk_packed<FM == 3, false>(view, cid8, cid8b, 0u, 0u, p0, p1, p2);
                         else
                             mv_chunk_packed<FM == 3, true>(view, cid8, cid8b, static_cast<unsigned>(c0),
                                                            static_cast<unsigned>(c1 - c0), p0, p1, p2);
+                    } else if constexpr (PK) {
+                        if (single)
+                            mv_chunk_packed64<FM == 3, false>(view, cwa, cwb, 0u, 0u, p0, p1, p2);
+                        else
+                            mv_chunk_packed64<FM == 3, true>(view, cwa, cwb, static_cast<unsigned>(c0),
+                                                             static_cast<unsigned>(c1 - c0), p0, p1, p2);
                     } else if (single) {
                         mv_chunk<T, PAR, false, MI, SOA, NR>(view, pyz, cid8, cwa, cwb, own, Lb, mi, 0u, 0u, p0, p1,
                                                              p2);
@@ -1630,13 +1756,14 @@ __global__ __launch_bounds__(BS, (mv_min_waves<T, PAR>())) void k_mv(MvArgs A)
             }
             if constexpr (PK) {
                 // the sums took the weights in units of their step
-                p0 *= A.wq_inv;
-                p1 *= A.wq_inv;
-                p2 *= A.wq_inv;
+                const T inv = sizeof(T) == 4 ? static_cast<T>(A.wq_inv32) : static_cast<T>(A.wq_inv);
+                p0 *= inv;
+                p1 *= inv;
+                p2 *= inv;
             }
         };
         if (pair) {
-            if constexpr (sizeof(T) == 4 && !PAR) {
+            if constexpr (!PAR) {
                 if (narrow && A.wpack && A.wq_signed) pair_sum(std::integral_constant<int, 3>{});
                 else if (narrow && A.wpack) pair_sum(std::integral_constant<int, 2>{});
                 else if (narrow) pair_sum(std::integral_constant<int, 1>{});
@@ -1814,14 +1941,18 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
 #pragma unroll
         for (int v = 0; v < NV; ++v) p[v][0] = p[v][1] = p[v][2] = T(0);
         // the pair sums, for either index form of the cell's lists
-        // FM: the cell's list form, as in k_mv (2: packed words in id, id2)
+        // FM: the cell's list form, as in k_mv (2: packed words in id, id2,
+        // or in FP64 in wa, wb)
         auto pair_sum = [&](auto form) __attribute__((always_inline)) {
             constexpr int FM = decltype(form)::value;
             constexpr bool NR = FM == 1;
             auto load = [&](int c, uint4 &i1, uint4 &i2, T4 &w1, T4 &w2) __attribute__((always_inline)) {
-                if constexpr (FM == 2) {
+                if constexpr (FM == 2 && sizeof(T) == 4) {
                     i1 = nbp4[(2 * c) * occ + j];
                     i2 = nbp4[(2 * c + 1) * occ + j];
+                } else if constexpr (FM == 2) {
+                    w1 = nbw4[(2 * c) * occ + j];
+                    w2 = nbw4[(2 * c + 1) * occ + j];
                 } else {
                     i1 = ids_load<NR>(nbl, c * occ + j);
                     w1 = nbw4[(2 * c) * occ + j];
@@ -1873,7 +2004,12 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                     const uint4 cid8b = id2;
                     T4 cwa = wa, cwb = wb;
                     if (ch + L < nch) load(ch + L, id, id2, wa, wb);
-                    if constexpr (FM == 2) unpack_chunk(cid8, cid8b, A.wq_inv, A.wq_signed, cid8, cwa, cwb);
+                    if constexpr (FM == 2 && sizeof(T) == 4) {
+                        unpack_chunk(cid8, cid8b, A.wq_inv32, A.wq_signed, cid8, cwa, cwb);
+                    } else if constexpr (FM == 2) {
+                        const T4 ra = cwa, rb = cwb;
+                        unpack_chunk64(ra, rb, A.wq_inv, A.wq_signed, cid8, cwa, cwb);
+                    }
                     const unsigned li[8] = {id_at<NR, 0>(cid8), id_at<NR, 1>(cid8), id_at<NR, 2>(cid8),
                                             id_at<NR, 3>(cid8), id_at<NR, 4>(cid8), id_at<NR, 5>(cid8),
                                             id_at<NR, 6>(cid8), id_at<NR, 7>(cid8)};
@@ -1906,14 +2042,9 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
             }
         };
         if (pair) {
-            if constexpr (sizeof(T) == 4) {
-                if (narrow && A.wpack) pair_sum(std::integral_constant<int, 2>{});
-                else if (narrow) pair_sum(std::integral_constant<int, 1>{});
-                else pair_sum(std::integral_constant<int, 0>{});
-            } else {
-                if (narrow) pair_sum(std::integral_constant<int, 1>{});
-                else pair_sum(std::integral_constant<int, 0>{});
-            }
+            if (narrow && A.wpack) pair_sum(std::integral_constant<int, 2>{});
+            else if (narrow) pair_sum(std::integral_constant<int, 1>{});
+            else pair_sum(std::integral_constant<int, 0>{});
         }
         // b x_v + cz z_v + sum_q c_q u_{v,q}, spread over the L lanes of each
         // particle as in k_mv
@@ -2226,6 +2357,7 @@ hipError_t launch_neighbors(const Dev &d, hipStream_t st, double *fc_out)
     a.wpack = d.wpack;
     a.wq_signed = d.wq_signed;
     a.wq_scale = d.wq_scale;
+    a.wq_scale32 = static_cast<float>(d.wq_scale);
     a.nn = d.nn;
     a.stab = static_cast<int2 *>(d.stab);
     a.stab_c = static_cast<const int2 *>(d.stab);
@@ -2284,6 +2416,7 @@ MvArgs mv_args(const Dev &d, double a, double b, const void *x, double cz, const
     A.wpack = d.wpack;
     A.wq_signed = d.wq_signed;
     A.wq_inv = d.wq_inv;
+    A.wq_inv32 = static_cast<float>(d.wq_inv);
     A.nn = d.nn;
     A.reld = static_cast<const double4 *>(d.reld);
     A.g = make_geo(d);

@@ -243,19 +243,19 @@ def test_one_step_kernel_frozen_below_r_cut_min(pkg, oracle_mod, fp64, parallel)
 
 
 def test_one_step_packed_list_weights(pkg, oracle_mod):
-    """FP32-mixed at the default noise tolerance keeps each pair of a cell
-    with 12-bit indices in one 32-bit word: the index and the weight in
-    20-bit fixed point relative to the table's largest |w| (unsigned for a
-    table without negative values, signed otherwise).  Both forms against
-    the oracle at 1e-5; a tighter noise tolerance keeps FP32 weights, FP64
-    keeps FP64 ones."""
+    """A pair of a cell with 12-bit indices is one word: the index and the
+    weight in fixed point relative to the table's largest |w| (unsigned for
+    a table without negative values, signed otherwise), 20 bits of a 32-bit
+    word in FP32-mixed at the default noise tolerance, 52 bits of a 64-bit
+    word in FP64.  Both forms of both against the oracle (1e-5, 1e-12); a
+    tighter FP32 noise tolerance keeps FP32 weights."""
     w = wl.config(3, n=1200, m_max=60)
     info = one_step(pkg, oracle_mod, w, False, step=9)
     assert (info["list_index_bits"], info["list_weight_bits"]) == (12, 20)
     info = one_step(pkg, oracle_mod, w, False, step=9, noise_tol=1e-6)
     assert info["list_weight_bits"] == 32
     info = one_step(pkg, oracle_mod, w, True, step=9)
-    assert info["list_weight_bits"] == 64
+    assert info["list_weight_bits"] == 52
     # a weight table that turns negative past r = 4 (the signed form)
     w = wl.config(1)
     k_self, g, wt0, r0, dr = w.tables()
@@ -265,6 +265,8 @@ def test_one_step_packed_list_weights(pkg, oracle_mod):
     log(f"    signed table: min {wt.min():.3f}, max {wt.max():.3f}")
     info = one_step(pkg, oracle_mod, w, False, step=5, tables=(k_self, g, wt, r0, dr), k_pair_w=wt)
     assert info["list_weight_bits"] == 20
+    info = one_step(pkg, oracle_mod, w, True, step=5, tables=(k_self, g, wt, r0, dr), k_pair_w=wt)
+    assert info["list_weight_bits"] == 52
 
 
 @pytest.mark.parametrize("fp64", [True, False])
