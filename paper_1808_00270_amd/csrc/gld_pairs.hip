@@ -372,17 +372,26 @@ __device__ __forceinline__ uint32_t pack_entry(unsigned idx, float w, float scal
     return (idx & 0xfffu) | (static_cast<uint32_t>(q) << 12);
 }
 
-// FP64 lists: a 64-bit word, the index in bits 0-11, 52-bit weight above
+// FP64 lists: a 64-bit word, the index in bits 0-11, 52-bit weight above.
+// q = qh 2^20 + ql (ql in [0, 2^20), all exact in double) gives the high
+// word qh and the low word ql << 12 | idx without 64-bit integer steps
 __device__ __forceinline__ uint64_t pack_entry64(unsigned idx, double w, double scale, int sgn)
 {
-    long long q = llrint(w * scale);
-    q = sgn ? min(max(q, -kWeightQMaxSigned64), kWeightQMaxSigned64) : min(max(q, 0LL), kWeightQMax64);
-    return static_cast<uint64_t>(idx & 0xfffu) | (static_cast<uint64_t>(q) << 12);
+    const double lim = sgn ? static_cast<double>(kWeightQMaxSigned64) : static_cast<double>(kWeightQMax64);
+    const double q = fmin(fmax(rint(w * scale), sgn ? -lim : 0.0), lim);
+    const double qh = floor(q * 0x1p-20);
+    const unsigned ql = static_cast<unsigned>(fma(qh, -0x1p20, q));
+    const unsigned hi = sgn ? static_cast<unsigned>(static_cast<int>(qh)) : static_cast<unsigned>(qh);
+    return (static_cast<uint64_t>(hi) << 32) | ((ql << 12) | (idx & 0xfffu));
 }
 
+// the weight field of a 64-bit word: high word times 2^20 plus the low
+// word's upper 20 bits (exact in double)
 __device__ __forceinline__ double entry_q64(uint64_t e, int sgn)
 {
-    return sgn ? static_cast<double>(static_cast<long long>(e) >> 12) : static_cast<double>(e >> 12);
+    const unsigned hi = static_cast<unsigned>(e >> 32), lo = static_cast<unsigned>(e);
+    const double h = sgn ? static_cast<double>(static_cast<int>(hi)) : static_cast<double>(hi);
+    return fma(h, 0x1p20, static_cast<double>(lo >> 12));
 }
 
 __device__ __forceinline__ float entry_weight(uint32_t e, float inv, int sgn)
