@@ -400,8 +400,9 @@ __device__ __forceinline__ float entry_weight(uint32_t e, float inv, int sgn)
     return static_cast<float>(q) * inv;
 }
 
-// a packed chunk (words pa: entries 0-3, pb: 4-7) as 16-bit indices and
-// weights (W4: the mat-vec's four-vector; packed lists are FP32 only)
+// a packed FP32 chunk (words pa: entries 0-3, pb: 4-7) as 16-bit indices
+// and weights (W4, the mat-vec's four-vector type, is a template parameter
+// so that the FP64 instantiations, which never call it, still compile)
 template <typename W4>
 __device__ __forceinline__ void unpack_chunk(uint4 pa, uint4 pb, float inv, int sgn, uint4 &id, W4 &wa, W4 &wb)
 {
