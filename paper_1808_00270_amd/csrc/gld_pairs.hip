@@ -1924,7 +1924,7 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
         sst[tid] = e.x;
         sbase[tid] = e.y;
     }
-    T *xsoa = reinterpret_cast<T *>(mv_lds);   // [NV][3][maxc]
+    T *xsoa = reinterpret_cast<T *>(mv_lds);   // [NV][3 maxc]: FP32 (x, y) pairs then z; FP64 three planes
     T4 *part = reinterpret_cast<T4 *>(mv_lds);  // [NV][BS], once the gathers of a round are done
     const unsigned ss = static_cast<unsigned>(A.maxc);
     const T4 *__restrict__ x = static_cast<const T4 *>(A.x);
@@ -1951,16 +1951,18 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
 #pragma unroll
         for (int v = 0; v < NV; ++v) p[v][0] = p[v][1] = p[v][2] = T(0);
         // the pair sums, for either index form of the cell's lists
-        // FM: the cell's list form, as in k_mv (2: packed words in id, id2,
-        // or in FP64 in wa, wb)
+        // FM: the cell's list form, as in k_mv (2 and 3: packed words,
+        // unsigned and signed weights, in id, id2 or in FP64 in wa, wb; the
+        // sums take the weights in units of their step and are scaled at the
+        // end).  FP32 stages each vector as (x, y) pairs and a z plane.
         auto pair_sum = [&](auto form) __attribute__((always_inline)) {
             constexpr int FM = decltype(form)::value;
-            constexpr bool NR = FM == 1;
+            constexpr bool NR = FM == 1, PK = FM >= 2;
             auto load = [&](int c, uint4 &i1, uint4 &i2, T4 &w1, T4 &w2) __attribute__((always_inline)) {
-                if constexpr (FM == 2 && sizeof(T) == 4) {
+                if constexpr (PK && sizeof(T) == 4) {
                     i1 = nbp4[(2 * c) * occ + j];
                     i2 = nbp4[(2 * c + 1) * occ + j];
-                } else if constexpr (FM == 2) {
+                } else if constexpr (PK) {
                     w1 = nbw4[(2 * c) * occ + j];
                     w2 = nbw4[(2 * c + 1) * occ + j];
                 } else {
@@ -1992,9 +1994,18 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                             for (int u = 0; u < D; ++u) q[u] = vin(v)[t[u]];
 #pragma unroll
                             for (int u = 0; u < D; ++u) {
-                                xsoa[(3 * v + 0) * ss + (l + u * BS - c0)] = q[u].x;
-                                xsoa[(3 * v + 1) * ss + (l + u * BS - c0)] = q[u].y;
-                                xsoa[(3 * v + 2) * ss + (l + u * BS - c0)] = q[u].z;
+                                const int at = l + u * BS - c0;
+                                if constexpr (sizeof(T) == 4) {
+                                    float2 xyv;
+                                    xyv.x = q[u].x;
+                                    xyv.y = q[u].y;
+                                    reinterpret_cast<float2 *>(xsoa + 3 * v * ss)[at] = xyv;
+                                    xsoa[(3 * v + 2) * ss + at] = q[u].z;
+                                } else {
+                                    xsoa[(3 * v + 0) * ss + at] = q[u].x;
+                                    xsoa[(3 * v + 1) * ss + at] = q[u].y;
+                                    xsoa[(3 * v + 2) * ss + at] = q[u].z;
+                                }
                             }
                         }
                     };
@@ -2010,20 +2021,38 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
                 if (sub < nch) load(sub, id, id2, wa, wb);
                 const unsigned cn = static_cast<unsigned>(c1 - c0);
                 for (int ch = sub; ch < nch; ch += L) {
-                    uint4 cid8 = id;
-                    const uint4 cid8b = id2;
-                    T4 cwa = wa, cwb = wb;
+                    const uint4 cid8 = id, cid8b = id2;
+                    const T4 cwa = wa, cwb = wb;
                     if (ch + L < nch) load(ch + L, id, id2, wa, wb);
-                    if constexpr (FM == 2 && sizeof(T) == 4) {
-                        unpack_chunk(cid8, cid8b, A.wq_inv32, A.wq_signed, cid8, cwa, cwb);
-                    } else if constexpr (FM == 2) {
-                        const T4 ra = cwa, rb = cwb;
-                        unpack_chunk64(ra, rb, A.wq_inv, A.wq_signed, cid8, cwa, cwb);
+                    unsigned li[8];
+                    T w[8];
+                    if constexpr (PK && sizeof(T) == 4) {
+                        const uint32_t ew[8] = {cid8.x, cid8.y, cid8.z, cid8.w, cid8b.x, cid8b.y, cid8b.z, cid8b.w};
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            li[u] = ew[u] & 0xfffu;
+                            w[u] = FM == 3 ? static_cast<T>(static_cast<int>(ew[u]) >> 12)
+                                           : static_cast<T>(ew[u] >> 12);
+                        }
+                    } else if constexpr (PK) {
+                        const T ww[8] = {cwa.x, cwa.y, cwa.z, cwa.w, cwb.x, cwb.y, cwb.z, cwb.w};
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const uint64_t e = static_cast<uint64_t>(__double_as_longlong(static_cast<double>(ww[u])));
+                            li[u] = static_cast<unsigned>(e) & 0xfffu;
+                            w[u] = static_cast<T>(entry_q64(e, FM == 3));
+                        }
+                    } else {
+                        const unsigned l8[8] = {id_at<NR, 0>(cid8), id_at<NR, 1>(cid8), id_at<NR, 2>(cid8),
+                                                id_at<NR, 3>(cid8), id_at<NR, 4>(cid8), id_at<NR, 5>(cid8),
+                                                id_at<NR, 6>(cid8), id_at<NR, 7>(cid8)};
+                        const T w8[8] = {cwa.x, cwa.y, cwa.z, cwa.w, cwb.x, cwb.y, cwb.z, cwb.w};
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            li[u] = l8[u];
+                            w[u] = w8[u];
+                        }
                     }
-                    const unsigned li[8] = {id_at<NR, 0>(cid8), id_at<NR, 1>(cid8), id_at<NR, 2>(cid8),
-                                            id_at<NR, 3>(cid8), id_at<NR, 4>(cid8), id_at<NR, 5>(cid8),
-                                            id_at<NR, 6>(cid8), id_at<NR, 7>(cid8)};
-                    T w[8] = {cwa.x, cwa.y, cwa.z, cwa.w, cwb.x, cwb.y, cwb.z, cwb.w};
                     unsigned lo8[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
@@ -2037,22 +2066,54 @@ __global__ __launch_bounds__(BS) void k_mvw(MvArgs A)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         if (v >= nvl) break;
+                        if constexpr (sizeof(T) == 4) {
+                            const float2 *xy = reinterpret_cast<const float2 *>(xsoa + 3 * v * ss);
 #pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            T val[8];
+                            for (int h = 0; h < 8; h += 4) {
+                                float2 vv[4];
 #pragma unroll
-                            for (int u = 0; u < 8; ++u) val[u] = xsoa[(3 * v + q) * ss + lo8[u]];
-                            T acc = p[v][q];
+                                for (int u = 0; u < 4; ++u) vv[u] = xy[lo8[h + u]];
 #pragma unroll
-                            for (int u = 0; u < 8; ++u) acc += w[u] * val[u];
-                            p[v][q] = acc;
+                                for (int u = 0; u < 4; ++u) {
+                                    p[v][0] += w[h + u] * vv[u].x;
+                                    p[v][1] += w[h + u] * vv[u].y;
+                                }
+                            }
+                            T vz[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) vz[u] = xsoa[(3 * v + 2) * ss + lo8[u]];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) p[v][2] += w[u] * vz[u];
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 3; ++q) {
+                                T val[8];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) val[u] = xsoa[(3 * v + q) * ss + lo8[u]];
+                                T acc = p[v][q];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) acc += w[u] * val[u];
+                                p[v][q] = acc;
+                            }
                         }
                     }
                 }
             }
+            if constexpr (PK) {
+                // the sums took the weights in units of their step
+                const T inv = sizeof(T) == 4 ? static_cast<T>(A.wq_inv32) : static_cast<T>(A.wq_inv);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if (v >= nvl) break;
+                    p[v][0] *= inv;
+                    p[v][1] *= inv;
+                    p[v][2] *= inv;
+                }
+            }
         };
         if (pair) {
-            if (narrow && A.wpack) pair_sum(std::integral_constant<int, 2>{});
+            if (narrow && A.wpack && A.wq_signed) pair_sum(std::integral_constant<int, 3>{});
+            else if (narrow && A.wpack) pair_sum(std::integral_constant<int, 2>{});
             else if (narrow) pair_sum(std::integral_constant<int, 1>{});
             else pair_sum(std::integral_constant<int, 0>{});
         }
@@ -2482,8 +2543,12 @@ hipError_t launch_spmv(const Dev &d, hipStream_t st, double a, double b, const v
 template <typename T, int NV>
 int mvw_staging(const Dev &d)
 {
+    // even, so that each vector's (x, y) pairs start 8-byte aligned: d.maxc
+    // rounded up (at least 2), the LDS budget rounded down
     const size_t budget = 160 * 1024 - 1024;
-    return static_cast<int>(std::min<size_t>(static_cast<size_t>(d.maxc), budget / (NV * 3 * sizeof(T))));
+    const size_t want = (static_cast<size_t>(std::max(d.maxc, 1)) + 1) & ~static_cast<size_t>(1);
+    const size_t room = (budget / (NV * 3 * sizeof(T))) & ~static_cast<size_t>(1);
+    return static_cast<int>(std::min(want, room));
 }
 
 template <typename T, int NV, bool DUAL = false>
@@ -2492,6 +2557,7 @@ hipError_t launch_mvw_t(const Dev &d, MvArgs A, hipStream_t st)
     constexpr int BS = sizeof(T) == 8 ? kMvThreads64 : kMvThreads32;
     constexpr int L = sizeof(T) == 8 ? kMvLanes64 : kMvLanes32;
     A.maxc = mvw_staging<T, NV>(d);
+    if (A.maxc < 2) return hipErrorInvalidValue;  // the staging rounds advance by maxc
     const size_t stage = static_cast<size_t>(NV) * 3 * A.maxc * sizeof(T);
     const size_t part = static_cast<size_t>(NV) * BS * sizeof(typename V4<T>::t);
     const size_t shm = stage > part ? stage : part;
