@@ -231,10 +231,17 @@ constexpr int kHistBlock32 = 32, kHistBlock64 = 16;
 constexpr int kHistSplit = 4;
 // accumulator rows of the filter bank's product (rows of one output block)
 __host__ __device__ inline int fir_rows(int fp64) { return (void)fp64, 64; }
-// steps between the launches that compute a share of the next filter block
-// (a divisor of the block of at most 5: 1, 2, 4 or 5, each a divisor of 20;
-// the block's product is split into block / period shares)
-__host__ __device__ inline int fir_period(int bf) { return bf <= 5 ? bf : (bf / 2 <= 5 ? bf / 2 : bf / 4); }
+// steps between the launches that compute a share of the next filter block:
+// the largest divisor of the block up to 5, so that the shares tile the
+// block (a noise window makes the block any multiple of the window up to the
+// largest block: 9, 14, 18 ...); the block's product is split into
+// block / period shares
+__host__ __device__ inline int fir_period(int bf)
+{
+    for (int p = 5; p > 1; --p)
+        if (bf % p == 0) return p;
+    return 1;
+}
 // the same for the history's block product (blocks of 32 or 16 steps)
 constexpr int kHistPeriod = 4;
 // rows of its zero-padded taps (the filter bank's layout, nslots taps)
