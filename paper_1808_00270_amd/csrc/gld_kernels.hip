@@ -76,6 +76,7 @@ __device__ __forceinline__ typename Vec4<T>::type load4(const T *p)
 }
 
 // the step's part: 4 consecutive elements of the [3][S] vectors per thread
+constexpr int kLagBatch = 4;  // ring loads in flight per thread
 template <typename T>
 __global__ __launch_bounds__(256) void k_history_step(const T *__restrict__ ring, const T *__restrict__ Uh,
                                                       int64_t n3, int nslots, int hb, const T *__restrict__ ks,
@@ -108,19 +109,39 @@ __global__ __launch_bounds__(256) void k_history_step(const T *__restrict__ ring
         }
     }
     const int mm = min(j + hb, nslots);
-    for (int m = 1; m <= mm; ++m) {
-        long long t = (step - m) % nslots;
+    if (mm > 0) {
+        // ring slot of step - m, walked down with a wrap from one remainder;
+        // kLagBatch lags' loads in flight, their sums in the order of m
+        int t = static_cast<int>((step - 1) % nslots);
         if (t < 0) t += nslots;
-        const auto x = load4<T>(ring + t * n3 + e0);
-        const T k = ks[m], q = gm[m];
-        d[0] += k * x.x;
-        d[1] += k * x.y;
-        d[2] += k * x.z;
-        d[3] += k * x.w;
-        h[0] += q * x.x;
-        h[1] += q * x.y;
-        h[2] += q * x.z;
-        h[3] += q * x.w;
+        auto lag = [&](const typename Vec4<T>::type &x, int m) __attribute__((always_inline)) {
+            const T k = ks[m], q = gm[m];
+            d[0] += k * x.x;
+            d[1] += k * x.y;
+            d[2] += k * x.z;
+            d[3] += k * x.w;
+            h[0] += q * x.x;
+            h[1] += q * x.y;
+            h[2] += q * x.z;
+            h[3] += q * x.w;
+        };
+        int m = 1;
+        for (; m + kLagBatch - 1 <= mm; m += kLagBatch) {
+            int tt[kLagBatch];
+            tt[0] = t;
+#pragma unroll
+            for (int u = 1; u < kLagBatch; ++u) tt[u] = tt[u - 1] == 0 ? nslots - 1 : tt[u - 1] - 1;
+            typename Vec4<T>::type x[kLagBatch];
+#pragma unroll
+            for (int u = 0; u < kLagBatch; ++u) x[u] = load4<T>(ring + static_cast<int64_t>(tt[u]) * n3 + e0);
+#pragma unroll
+            for (int u = 0; u < kLagBatch; ++u) lag(x[u], m + u);
+            t = tt[kLagBatch - 1] == 0 ? nslots - 1 : tt[kLagBatch - 1] - 1;
+        }
+        for (; m <= mm; ++m) {
+            lag(load4<T>(ring + static_cast<int64_t>(t) * n3 + e0), m);
+            t = t == 0 ? nslots - 1 : t - 1;
+        }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
