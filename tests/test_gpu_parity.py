@@ -483,6 +483,7 @@ def test_kernel_timing_counts(pkg):
     (False, 4, False, True, False, True),     # 16-bit list indices (cells of 15.5)
     (False, 3, False, True, False, False),    # block 9: the bank's shares every 3 steps
     (False, 7, False, True, False, False),    # block 7: a share at every step
+    (True, 3, False, True, False, False),
 ])
 def test_noise_window_matches_oracle(pkg, oracle_mod, fp64, W, parallel, graph, crowded, wide):
     w = wl.config(2, n=5000, rho=0.05, m_max=60, parallel=parallel)
